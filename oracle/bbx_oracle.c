@@ -1,0 +1,721 @@
+/*
+ * bbx_oracle.c -- plain, slow, single-threaded CPU oracle of the bit-box
+ * particle compressor (arXiv 2404.02826), FP64 arithmetic throughout.
+ *
+ * TEST INFRASTRUCTURE ONLY: loaded by the test-suite, the smoke check and the
+ * benchmark's CPU-baseline leg; never by the product path.  It shares no code
+ * with the HIP library.  Build: -O2 -ffp-contract=off, no fast-math.
+ *
+ * Each step follows the paper's method in its order, with the readings chosen
+ * where the paper is silent:
+ *   1. range and bound      Sec. 3 (absolute / value-range relative bound)
+ *   2. quantize             Sec. 3 (linear-scale quantization, bins of 2*eb)
+ *   3. k-d median partition Sec. 4.1 (median split, median on the larger side,
+ *                           stop at <= r particles), round-robin split axis,
+ *                           ties by original particle index
+ *   4. bit box per leaf     Sec. 4.1 (AABB, reference = particle nearest the
+ *                           AABB centre, Eq. 2 bit widths)
+ *   5. offsets + packing    Sec. 4.2 (sequence layout, 5/6-bit width fields;
+ *                           storage-cost model) in a structure-of-arrays form
+ *   6. unpack + dequantize  Sec. 3 (reconstruction at the bin centre)
+ *
+ * Parity pins live in tests/: a worked example of Sec. 4.1, a pure-Python
+ * brute-force re-derivation on tiny inputs, closed forms (Eq. 1-3), the error
+ * bound, and mutation tests that build this file with -DBBXO_MUTANT=k to
+ * plant one plausible mistake k and check that some pin catches it.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "bbx_oracle.h"
+
+#ifndef BBXO_MUTANT
+#define BBXO_MUTANT 0 /* 0: faithful; k > 0: plant mistake k (mutation tests only) */
+#endif
+#define MUT(k) (BBXO_MUTANT == (k))
+
+#define MAGIC 0x31584242u /* bytes 'B','B','X','1' */
+#define HEADER_BYTES 128u
+
+/* ------------------------------------------------------------------ helpers */
+
+static uint32_t bitlen64(uint64_t v) {
+  uint32_t b = 0;
+  while (v) {
+    b++;
+    v >>= 1;
+  }
+  return b;
+}
+
+/* Eq. 2: m = ceil(log2(D + 1/2) + 1), D = largest |offset| from the reference
+ * in bins of width 2*eb.  For 2^(k-1) <= D < 2^k, D + 1/2 lies strictly between
+ * 2^(k-1) and 2^k, so the ceiling is k + 1 = bitlen(D) + 1.  For D = 0 the
+ * expression is exactly 0. */
+uint32_t bbxo_bits_for_offset(uint64_t D) {
+  if (D == 0) return 0;
+#if MUT(6)
+  return bitlen64(D);
+#else
+  return bitlen64(D) + 1;
+#endif
+}
+
+static void put_u16le(uint8_t* b, uint32_t v) { b[0] = (uint8_t)v; b[1] = (uint8_t)(v >> 8); }
+static void put_u32le(uint8_t* b, uint32_t v) {
+  for (int k = 0; k < 4; k++) b[k] = (uint8_t)(v >> (8 * k));
+}
+static void put_u64le(uint8_t* b, uint64_t v) {
+  for (int k = 0; k < 8; k++) b[k] = (uint8_t)(v >> (8 * k));
+}
+static void put_f64le(uint8_t* b, double v) {
+  uint64_t u;
+  memcpy(&u, &v, 8);
+  put_u64le(b, u);
+}
+static uint32_t get_u16le(const uint8_t* b) { return (uint32_t)b[0] | ((uint32_t)b[1] << 8); }
+static uint32_t get_u32le(const uint8_t* b) {
+  uint32_t v = 0;
+  for (int k = 0; k < 4; k++) v |= (uint32_t)b[k] << (8 * k);
+  return v;
+}
+static uint64_t get_u64le(const uint8_t* b) {
+  uint64_t v = 0;
+  for (int k = 0; k < 8; k++) v |= (uint64_t)b[k] << (8 * k);
+  return v;
+}
+static double get_f64le(const uint8_t* b) {
+  uint64_t u = get_u64le(b);
+  double v;
+  memcpy(&v, &u, 8);
+  return v;
+}
+
+/* One bit at a time: bit i of a section is bit (i mod 8) of byte i/8, which is
+ * bit (i mod 64) of the little-endian 64-bit word i/64. */
+static void put_bits(uint8_t* sec, uint64_t pos, uint64_t v, uint32_t nb) {
+  for (uint32_t k = 0; k < nb; k++)
+    if ((v >> k) & 1u) sec[(pos + k) >> 3] |= (uint8_t)(1u << ((pos + k) & 7u));
+}
+static uint64_t get_bits(const uint8_t* sec, uint64_t pos, uint32_t nb) {
+  uint64_t v = 0;
+  for (uint32_t k = 0; k < nb; k++)
+    if ((sec[(pos + k) >> 3] >> ((pos + k) & 7u)) & 1u) v |= (uint64_t)1 << k;
+  return v;
+}
+
+/* ------------------------------------------------------------------ params */
+
+typedef struct {
+  uint64_t n;
+  uint32_t dims;
+  int dtype, eb_mode;
+  uint32_t r, mbits;
+  double eb_user, eb_abs, eb_eff, w, inv_w;
+  double lo[3], hi[3];
+  uint32_t G[3];
+} params_t;
+
+static double coord(const void* pos, const params_t* p, int layout, uint64_t i, uint32_t d) {
+  uint64_t k = (layout == 0) ? i * p->dims + d : (uint64_t)d * p->n + i;
+  return p->dtype == 0 ? (double)((const float*)pos)[k] : ((const double*)pos)[k];
+}
+
+/* Sec. 3 quantization: index of the bin of width w (= 2*eb_eff) holding x,
+ * bins centred on lo + k*w; round-half-up, three separately rounded FP64
+ * operations. */
+static double quantize_real(double x, double lo, double inv_w) {
+  double t = (x - lo) * inv_w + 0.5;
+  return floor(t);
+}
+
+/* Steps 1-2: per-axis range, error bound, bin width, code widths G_d. */
+static int range_and_bound(const void* pos, int layout, params_t* p) {
+  uint32_t dims = p->dims;
+  for (uint32_t d = 0; d < 3; d++) p->lo[d] = p->hi[d] = 0.0, p->G[d] = 0;
+  p->eb_abs = p->eb_eff = p->w = p->inv_w = 0.0;
+  if (p->n == 0) {
+    p->eb_abs = (p->eb_mode == 1) ? p->eb_user : 0.0;
+    return BBXO_OK;
+  }
+  for (uint32_t d = 0; d < dims; d++) p->lo[d] = p->hi[d] = coord(pos, p, layout, 0, d);
+  for (uint64_t i = 0; i < p->n; i++)
+    for (uint32_t d = 0; d < dims; d++) {
+      double v = coord(pos, p, layout, i, d);
+      if (!isfinite(v)) return BBXO_EINVAL;
+      if (v < p->lo[d]) p->lo[d] = v;
+      if (v > p->hi[d]) p->hi[d] = v;
+    }
+  /* -0.0 and +0.0 compare equal; make the stored origin +0.0 either way */
+  for (uint32_t d = 0; d < dims; d++) {
+    p->lo[d] = p->lo[d] + 0.0;
+    p->hi[d] = p->hi[d] + 0.0;
+  }
+  /* Delta_max: the largest coordinate range over all axes (Sec. 3) */
+  double delta = 0.0;
+  for (uint32_t d = 0; d < dims; d++) {
+    double rg = p->hi[d] - p->lo[d];
+#if MUT(15)
+    if (d == 0 || rg < delta) delta = rg;
+#else
+    if (rg > delta) delta = rg;
+#endif
+  }
+  p->eb_abs = (p->eb_mode == 0) ? p->eb_user * delta : p->eb_user;
+  if (!isfinite(delta) || !isfinite(p->eb_abs)) return BBXO_EBOUND;
+  if (delta == 0.0) return BBXO_OK; /* all particles identical: exact, w = 0 */
+
+  /* Guard: the bound must survive FP64 rounding of quantize/dequantize and the
+   * final rounding to the input type.  guard = ulp_T(A)/2 (T = f32 only) +
+   * A * 2^-48, A = largest magnitude of any coordinate or reconstruction. */
+  double amax = 0.0;
+  for (uint32_t d = 0; d < dims; d++) {
+    double a = fabs(p->lo[d]) > fabs(p->hi[d]) ? fabs(p->lo[d]) : fabs(p->hi[d]);
+    if (a > amax) amax = a;
+  }
+  amax = amax + p->eb_abs;
+  double guard = ldexp(amax, -48);
+  if (p->dtype == 0) {
+    int e = 0;
+    (void)frexp(amax, &e); /* amax = f * 2^e, f in [1/2, 1): f32 ulp is 2^(e-24) */
+    double half_ulp = ldexp(1.0, e - 25);
+    if (half_ulp < ldexp(1.0, -150)) half_ulp = ldexp(1.0, -150);
+    guard = guard + half_ulp;
+  }
+  p->eb_eff = p->eb_abs - guard;
+  if (!(p->eb_eff > 0.0)) return BBXO_EBOUND;
+#if MUT(9)
+  p->w = p->eb_eff;
+#else
+  p->w = 2.0 * p->eb_eff;
+#endif
+  p->inv_w = 1.0 / p->w;
+  if (!isfinite(p->w) || !isfinite(p->inv_w) || !(p->inv_w > 0.0)) return BBXO_EBOUND;
+  /* the largest code of axis d is the code of hi_d (quantization is monotone) */
+  for (uint32_t d = 0; d < dims; d++) {
+    double qm = quantize_real(p->hi[d], p->lo[d], p->inv_w);
+    if (!(qm < 1073741824.0)) return BBXO_EBOUND; /* codes must stay below 2^30 */
+    p->G[d] = bitlen64((uint64_t)qm);
+#if MUT(14)
+    if (p->G[d] > 0) p->G[d] -= 1;
+#endif
+  }
+  return BBXO_OK;
+}
+
+/* ------------------------------------------------------------------ tree */
+
+typedef struct {
+  const uint32_t* q; /* [dims][n] */
+  uint64_t n;
+  uint32_t dims, r;
+  uint32_t* order;  /* tree order being built, [n] */
+  uint64_t* keys;   /* scratch, [n] */
+  uint32_t* tmp;    /* scratch, [n] */
+  uint32_t* leaf_start;
+  uint32_t* leaf_size;
+  uint64_t nleaves, cap;
+  int fail;
+} tree_t;
+
+static int cmp_u64(const void* a, const void* b) {
+  uint64_t x = *(const uint64_t*)a, y = *(const uint64_t*)b;
+  return (x > y) - (x < y);
+}
+
+/* (q_d, original index) as one ordered 64-bit key: codes < 2^30, index < 2^32 */
+static uint64_t split_key(const tree_t* t, uint32_t i, uint32_t d) {
+#if MUT(2)
+  return ((uint64_t)t->q[(uint64_t)d * t->n + i] << 32) | (uint64_t)(0xffffffffu - i);
+#else
+  return ((uint64_t)t->q[(uint64_t)d * t->n + i] << 32) | (uint64_t)i;
+#endif
+}
+
+/* Sec. 4.1: split the node order[start, start+s) at the median along one axis.
+ * The element of rank floor(s/2) in (q_d, index) order and everything after
+ * it form the right child ("median on the side with larger coordinates"); the
+ * split is stable, so both children keep ascending original index. */
+static void kd_split(tree_t* t, uint64_t start, uint64_t s, uint32_t depth) {
+  uint32_t* S = t->order + start;
+#if MUT(12)
+  int leaf = (s < t->r) || s <= 1;
+#else
+  int leaf = (s <= t->r);
+#endif
+  if (leaf) {
+    if (t->nleaves >= t->cap) {
+      t->fail = 1;
+      return;
+    }
+    t->leaf_start[t->nleaves] = (uint32_t)start;
+    t->leaf_size[t->nleaves] = (uint32_t)s;
+    t->nleaves++;
+    return;
+  }
+#if MUT(3)
+  uint32_t d = 0;
+#else
+  uint32_t d = depth % t->dims; /* round-robin split axis */
+#endif
+  for (uint64_t j = 0; j < s; j++) t->keys[j] = split_key(t, S[j], d);
+  qsort(t->keys, (size_t)s, sizeof(uint64_t), cmp_u64);
+#if MUT(1)
+  uint64_t med = t->keys[(s - 1) / 2] + 1; /* median joins the left side */
+#else
+  uint64_t med = t->keys[s / 2];
+#endif
+  uint64_t nl = 0;
+  for (uint64_t j = 0; j < s; j++)
+    if (split_key(t, S[j], d) < med) t->tmp[nl++] = S[j];
+  uint64_t k = nl;
+  for (uint64_t j = 0; j < s; j++)
+    if (!(split_key(t, S[j], d) < med)) t->tmp[k++] = S[j];
+  memcpy(S, t->tmp, (size_t)s * sizeof(uint32_t));
+  kd_split(t, start, nl, depth + 1);
+  kd_split(t, start + nl, s - nl, depth + 1);
+}
+
+/* The same recursion on sizes only (children floor(s/2), ceil(s/2)): the leaf
+ * sizes depend on (n, r) alone. */
+static void size_leaves(uint64_t s, uint32_t r, uint32_t* out, uint64_t* k, uint64_t cap) {
+  if (s <= r) {
+    if (*k < cap) out[*k] = (uint32_t)s;
+    (*k)++;
+    return;
+  }
+  size_leaves(s / 2, r, out, k, cap);
+  size_leaves(s - s / 2, r, out, k, cap);
+}
+
+static uint64_t count_leaves(uint64_t s, uint32_t r) {
+  if (s <= r) return 1;
+  return count_leaves(s / 2, r) + count_leaves(s - s / 2, r);
+}
+
+uint64_t bbxo_leaf_count(uint64_t n, uint32_t r) {
+  if (n == 0 || r == 0) return 0;
+  return count_leaves(n, r);
+}
+
+/* ------------------------------------------------------------------ bit box */
+
+/* Sec. 4.1 bit box of one leaf: AABB, reference = member nearest the AABB
+ * centre (squared Euclidean distance in code space, doubled to stay integral;
+ * ties to the first member), then Eq. 2 per axis. */
+static void bit_box(const uint32_t* q, uint64_t n, uint32_t dims, const uint32_t* mem,
+                    uint64_t s, uint32_t* ref_out, uint32_t m_out[3]) {
+  uint64_t qmin[3] = {0, 0, 0}, qmax[3] = {0, 0, 0};
+  for (uint32_t d = 0; d < dims; d++) {
+    qmin[d] = qmax[d] = q[(uint64_t)d * n + mem[0]];
+    for (uint64_t j = 1; j < s; j++) {
+      uint64_t v = q[(uint64_t)d * n + mem[j]];
+      if (v < qmin[d]) qmin[d] = v;
+      if (v > qmax[d]) qmax[d] = v;
+    }
+  }
+  uint64_t best = UINT64_MAX, ref = 0;
+  for (uint64_t j = 0; j < s; j++) {
+    uint64_t dist = 0;
+    for (uint32_t d = 0; d < dims; d++) {
+      int64_t t = 2 * (int64_t)q[(uint64_t)d * n + mem[j]] - (int64_t)(qmin[d] + qmax[d]);
+      dist += (uint64_t)(t * t);
+    }
+#if MUT(5)
+    if (dist <= best) {
+#else
+    if (dist < best) {
+#endif
+      best = dist;
+      ref = j;
+    }
+  }
+#if MUT(4)
+  ref = 0;
+#endif
+  *ref_out = (uint32_t)ref;
+  for (uint32_t d = 0; d < 3; d++) m_out[d] = 0;
+  for (uint32_t d = 0; d < dims; d++) {
+    uint64_t c = q[(uint64_t)d * n + mem[ref]];
+    uint64_t D = (c - qmin[d] > qmax[d] - c) ? c - qmin[d] : qmax[d] - c;
+#if MUT(7)
+    D = qmax[d] - qmin[d];
+#endif
+    m_out[d] = bbxo_bits_for_offset(D);
+  }
+}
+
+/* ------------------------------------------------------------------ compress */
+
+typedef struct {
+  params_t p;
+  uint32_t* q;     /* [dims][n] */
+  uint32_t* order; /* [n] */
+  uint64_t nleaves;
+  uint32_t *leaf_start, *leaf_size, *leaf_ref;
+  uint32_t* leaf_m; /* [nleaves][3] */
+  uint64_t* leaf_bits;
+  uint64_t meta_bits, payload_bits;
+} core_t;
+
+static void core_free(core_t* c) {
+  free(c->q);
+  free(c->order);
+  free(c->leaf_start);
+  free(c->leaf_size);
+  free(c->leaf_ref);
+  free(c->leaf_m);
+  free(c->leaf_bits);
+  memset(c, 0, sizeof(*c));
+}
+
+static int check_args(uint64_t n, uint32_t dims, int dtype, int layout, double eb, int eb_mode,
+                      uint32_t r) {
+  if (dtype != 0 && dtype != 1) return BBXO_EINVAL;
+  if (layout != 0 && layout != 1) return BBXO_EINVAL;
+  if (eb_mode != 0 && eb_mode != 1) return BBXO_EINVAL;
+  if (r == 0) return BBXO_EINVAL;
+  if (!isfinite(eb) || !(eb > 0.0)) return BBXO_EINVAL;
+  if (dims != 2 && dims != 3) return BBXO_EUNSUPPORTED;
+  if (n >= ((uint64_t)1 << 32)) return BBXO_EUNSUPPORTED;
+  return BBXO_OK;
+}
+
+static int core_run(core_t* c, const void* pos, uint64_t n, uint32_t dims, int dtype, int layout,
+                    double eb, int eb_mode, uint32_t r) {
+  memset(c, 0, sizeof(*c));
+  int st = check_args(n, dims, dtype, layout, eb, eb_mode, r);
+  if (st) return st;
+  params_t* p = &c->p;
+  p->n = n;
+  p->dims = dims;
+  p->dtype = dtype;
+  p->eb_mode = eb_mode;
+  p->r = r;
+  p->eb_user = eb;
+  p->mbits = dtype == 0 ? 5u : 6u; /* Sec. 4.2: 5 bits for M = 32, 6 for M = 64 */
+  st = range_and_bound(pos, layout, p);
+  if (st) return st;
+  if (n == 0) return BBXO_OK;
+
+  uint64_t nl = bbxo_leaf_count(n, r);
+  c->q = (uint32_t*)malloc((size_t)(n * dims) * sizeof(uint32_t));
+  c->order = (uint32_t*)malloc((size_t)n * sizeof(uint32_t));
+  c->leaf_start = (uint32_t*)malloc((size_t)nl * sizeof(uint32_t));
+  c->leaf_size = (uint32_t*)malloc((size_t)nl * sizeof(uint32_t));
+  c->leaf_ref = (uint32_t*)malloc((size_t)nl * sizeof(uint32_t));
+  c->leaf_m = (uint32_t*)malloc((size_t)nl * 3 * sizeof(uint32_t));
+  c->leaf_bits = (uint64_t*)malloc((size_t)nl * sizeof(uint64_t));
+  uint64_t* keys = (uint64_t*)malloc((size_t)n * sizeof(uint64_t));
+  uint32_t* tmp = (uint32_t*)malloc((size_t)n * sizeof(uint32_t));
+  uint32_t* sz = (uint32_t*)malloc((size_t)nl * sizeof(uint32_t));
+  if (!c->q || !c->order || !c->leaf_start || !c->leaf_size || !c->leaf_ref || !c->leaf_m ||
+      !c->leaf_bits || !keys || !tmp || !sz) {
+    free(keys);
+    free(tmp);
+    free(sz);
+    return BBXO_ENOMEM;
+  }
+
+  /* Step 2: quantize every coordinate (codes of the whole set first). */
+  for (uint32_t d = 0; d < dims; d++)
+    for (uint64_t i = 0; i < n; i++)
+      c->q[(uint64_t)d * n + i] =
+          (uint32_t)quantize_real(coord(pos, p, layout, i, d), p->lo[d], p->inv_w);
+
+  /* Step 3: k-d median partition. */
+  for (uint64_t i = 0; i < n; i++) c->order[i] = (uint32_t)i;
+  tree_t t;
+  memset(&t, 0, sizeof(t));
+  t.q = c->q;
+  t.n = n;
+  t.dims = dims;
+  t.r = r;
+  t.order = c->order;
+  t.keys = keys;
+  t.tmp = tmp;
+  t.leaf_start = c->leaf_start;
+  t.leaf_size = c->leaf_size;
+  t.cap = nl;
+  kd_split(&t, 0, n, 0);
+  c->nleaves = t.nleaves;
+  /* the partition must reproduce the size-only recursion exactly */
+  uint64_t k = 0;
+  size_leaves(n, r, sz, &k, nl);
+  int same = !t.fail && k == nl && t.nleaves == nl;
+  for (uint64_t i = 0; same && i < nl; i++) same = (sz[i] == c->leaf_size[i]);
+  free(keys);
+  free(tmp);
+  free(sz);
+  if (!same) return BBXO_ENOMEM; /* internal inconsistency: never expected */
+
+  /* Step 4: bit box of every leaf; Step 5: section sizes. */
+  uint32_t sumG = 0;
+  for (uint32_t d = 0; d < dims; d++) sumG += p->G[d];
+  c->meta_bits = nl * (uint64_t)(dims * p->mbits + sumG);
+  c->payload_bits = 0;
+  for (uint64_t i = 0; i < nl; i++) {
+    uint32_t m[3];
+    bit_box(c->q, n, dims, c->order + c->leaf_start[i], c->leaf_size[i], &c->leaf_ref[i], m);
+    uint32_t sm = 0;
+    for (uint32_t d = 0; d < 3; d++) {
+      c->leaf_m[i * 3 + d] = m[d];
+      sm += m[d];
+    }
+    c->leaf_bits[i] = (uint64_t)(c->leaf_size[i] - 1) * sm;
+    c->payload_bits += c->leaf_bits[i];
+  }
+  return BBXO_OK;
+}
+
+static uint64_t words_bytes(uint64_t bits) { return ((bits + 63) / 64) * 8; }
+
+uint64_t bbxo_compress_bound(uint64_t n, uint32_t dims, int dtype) {
+  uint64_t mbits = dtype == 1 ? 6 : 5;
+  /* every particle is either a reference (dims*(mbits + G) <= dims*(mbits+30)
+   * meta bits) or a member (dims*31 payload bits at most) */
+  return HEADER_BYTES + 16 + words_bytes(n * dims * (mbits + 30));
+}
+
+static void write_header(uint8_t* h, const core_t* c) {
+  const params_t* p = &c->p;
+  memset(h, 0, HEADER_BYTES);
+  put_u32le(h + 0, MAGIC);
+  put_u16le(h + 4, 1);
+  h[6] = (uint8_t)p->dtype;
+  h[7] = (uint8_t)p->dims;
+  put_u64le(h + 8, p->n);
+  put_u32le(h + 16, p->r);
+  h[20] = (uint8_t)p->eb_mode;
+  h[21] = 0; /* split rule: median, round-robin axis */
+  h[22] = 0; /* reference stored as its code */
+  h[23] = (uint8_t)p->mbits;
+  put_f64le(h + 24, p->eb_user);
+  put_f64le(h + 32, p->eb_abs);
+  put_f64le(h + 40, p->eb_eff);
+  put_f64le(h + 48, p->w);
+  put_f64le(h + 56, p->inv_w);
+  for (uint32_t d = 0; d < 3; d++) put_f64le(h + 64 + 8 * d, d < p->dims ? p->lo[d] : 0.0);
+  for (uint32_t d = 0; d < 3; d++) h[88 + d] = (uint8_t)(d < p->dims ? p->G[d] : 0);
+  put_u64le(h + 96, c->nleaves);
+  put_u64le(h + 104, c->meta_bits);
+  put_u64le(h + 112, c->payload_bits);
+  put_u64le(h + 120, 0);
+}
+
+int bbxo_compress(const void* pos, uint64_t n, uint32_t dims, int dtype, int layout, double eb,
+                  int eb_mode, uint32_t r, uint8_t* out, uint64_t out_cap, uint64_t* out_size,
+                  uint32_t* perm) {
+  core_t c;
+  int st = core_run(&c, pos, n, dims, dtype, layout, eb, eb_mode, r);
+  if (st) {
+    core_free(&c);
+    return st;
+  }
+  const params_t* p = &c.p;
+  uint64_t mb = words_bytes(c.meta_bits), pb = words_bytes(c.payload_bits);
+  uint64_t total = HEADER_BYTES + mb + pb;
+  if (out_size) *out_size = total;
+  if (total > out_cap) {
+    core_free(&c);
+    return BBXO_ENOSPC;
+  }
+  memset(out, 0, (size_t)total);
+  write_header(out, &c);
+  uint8_t* meta = out + HEADER_BYTES;
+  uint8_t* pay = meta + mb;
+  uint64_t mpos = 0, ppos = 0;
+  for (uint64_t i = 0; i < c.nleaves; i++) {
+    const uint32_t* mem = c.order + c.leaf_start[i];
+    uint32_t s = c.leaf_size[i], ref = c.leaf_ref[i];
+    const uint32_t* m = c.leaf_m + 3 * i;
+    /* meta record: widths m_d (mbits each), then the reference's codes */
+    for (uint32_t d = 0; d < p->dims; d++) put_bits(meta, mpos, m[d], p->mbits), mpos += p->mbits;
+    for (uint32_t d = 0; d < p->dims; d++) {
+      put_bits(meta, mpos, c.q[(uint64_t)d * n + mem[ref]], p->G[d]);
+      mpos += p->G[d];
+    }
+    /* payload: every other member in leaf order, codes o + 2^(m-1) per axis */
+    for (uint32_t jj = 0; jj < s; jj++) {
+#if MUT(13)
+      uint32_t j = s - 1 - jj;
+#else
+      uint32_t j = jj;
+#endif
+      if (j == ref) continue;
+      for (uint32_t dd = 0; dd < p->dims; dd++) {
+#if MUT(8)
+        uint32_t d = p->dims - 1 - dd;
+#else
+        uint32_t d = dd;
+#endif
+        if (m[d] == 0) continue;
+        int64_t o = (int64_t)c.q[(uint64_t)d * n + mem[j]] - (int64_t)c.q[(uint64_t)d * n + mem[ref]];
+        uint64_t u = (uint64_t)(o + ((int64_t)1 << (m[d] - 1)));
+        put_bits(pay, ppos, u, m[d]);
+        ppos += m[d];
+      }
+    }
+    if (perm) {
+      uint64_t slot = c.leaf_start[i];
+      perm[slot++] = mem[ref];
+      for (uint32_t j = 0; j < s; j++)
+        if (j != ref) perm[slot++] = mem[j];
+    }
+  }
+  core_free(&c);
+  return BBXO_OK;
+}
+
+int bbxo_stages(const void* pos, uint64_t n, uint32_t dims, int dtype, int layout, double eb,
+                int eb_mode, uint32_t r, uint32_t* q, uint32_t* order, uint64_t max_leaves,
+                uint32_t* leaf_start, uint32_t* leaf_size, uint32_t* leaf_ref, uint8_t* leaf_m,
+                uint64_t* leaf_bits, double* scal) {
+  core_t c;
+  int st = core_run(&c, pos, n, dims, dtype, layout, eb, eb_mode, r);
+  if (st) {
+    core_free(&c);
+    return st;
+  }
+  if (scal) {
+    scal[0] = c.p.eb_abs;
+    scal[1] = c.p.eb_eff;
+    scal[2] = c.p.w;
+    scal[3] = c.p.inv_w;
+    for (int d = 0; d < 3; d++) {
+      scal[4 + d] = c.p.lo[d];
+      scal[7 + d] = c.p.hi[d];
+      scal[10 + d] = (double)c.p.G[d];
+    }
+    scal[13] = (double)c.nleaves;
+    scal[14] = (double)c.meta_bits;
+    scal[15] = (double)c.payload_bits;
+  }
+  if (n > 0) {
+    if (q) memcpy(q, c.q, (size_t)(n * dims) * sizeof(uint32_t));
+    if (order) memcpy(order, c.order, (size_t)n * sizeof(uint32_t));
+  }
+  uint64_t L = c.nleaves < max_leaves ? c.nleaves : max_leaves;
+  for (uint64_t i = 0; i < L; i++) {
+    if (leaf_start) leaf_start[i] = c.leaf_start[i];
+    if (leaf_size) leaf_size[i] = c.leaf_size[i];
+    if (leaf_ref) leaf_ref[i] = c.leaf_ref[i];
+    if (leaf_m)
+      for (int d = 0; d < 3; d++) leaf_m[i * 3 + d] = (uint8_t)c.leaf_m[i * 3 + d];
+    if (leaf_bits) leaf_bits[i] = c.leaf_bits[i];
+  }
+  core_free(&c);
+  return BBXO_OK;
+}
+
+/* ------------------------------------------------------------------ decompress */
+
+int bbxo_decompress(const uint8_t* s, uint64_t size, void* pos, uint64_t pos_cap_bytes,
+                    int layout) {
+  if (layout != 0 && layout != 1) return BBXO_EINVAL;
+  if (!s || size < HEADER_BYTES) return BBXO_ECORRUPT;
+  if (get_u32le(s) != MAGIC || get_u16le(s + 4) != 1) return BBXO_ECORRUPT;
+  int dtype = s[6];
+  uint32_t dims = s[7];
+  uint64_t n = get_u64le(s + 8);
+  uint32_t r = get_u32le(s + 16);
+  uint32_t eb_mode = s[20], mbits = s[23];
+  if (dtype > 1 || (dims != 2 && dims != 3) || eb_mode > 1 || s[21] != 0 || s[22] != 0)
+    return BBXO_ECORRUPT;
+  if (mbits != (dtype == 0 ? 5u : 6u) || r == 0 || n >= ((uint64_t)1 << 32)) return BBXO_ECORRUPT;
+  double w = get_f64le(s + 48);
+  double origin[3];
+  uint32_t G[3], sumG = 0;
+  for (uint32_t d = 0; d < 3; d++) {
+    origin[d] = get_f64le(s + 64 + 8 * d);
+    G[d] = s[88 + d];
+    if (d >= dims && (G[d] != 0 || origin[d] != 0.0)) return BBXO_ECORRUPT;
+    if (G[d] > 30 || !isfinite(origin[d])) return BBXO_ECORRUPT;
+    sumG += G[d];
+  }
+  if (!isfinite(w) || w < 0.0) return BBXO_ECORRUPT;
+  for (int k = 91; k < 96; k++)
+    if (s[k] != 0) return BBXO_ECORRUPT;
+  uint64_t nl = get_u64le(s + 96), meta_bits = get_u64le(s + 104), payload_bits = get_u64le(s + 112);
+  if (get_u64le(s + 120) != 0) return BBXO_ECORRUPT;
+  if (nl != bbxo_leaf_count(n, r)) return BBXO_ECORRUPT;
+  if (meta_bits != nl * (uint64_t)(dims * mbits + sumG)) return BBXO_ECORRUPT;
+  if (payload_bits > n * (uint64_t)dims * 31u) return BBXO_ECORRUPT;
+  uint64_t mb = words_bytes(meta_bits), pb = words_bytes(payload_bits);
+  if (size < HEADER_BYTES + mb + pb) return BBXO_ECORRUPT;
+  uint64_t esz = dtype == 0 ? 4 : 8;
+  if (pos_cap_bytes < n * dims * esz) return BBXO_ENOSPC;
+  if (n == 0) return BBXO_OK;
+
+  const uint8_t* meta = s + HEADER_BYTES;
+  const uint8_t* pay = meta + mb;
+  uint32_t* sizes = (uint32_t*)malloc((size_t)nl * sizeof(uint32_t));
+  uint32_t* codes = (uint32_t*)malloc((size_t)(n * dims) * sizeof(uint32_t)); /* [slot][d] */
+  if (!sizes || !codes) {
+    free(sizes);
+    free(codes);
+    return BBXO_ENOMEM;
+  }
+  uint64_t k = 0;
+  size_leaves(n, r, sizes, &k, nl);
+  int st = BBXO_OK;
+  uint64_t mpos = 0, ppos = 0, slot = 0;
+  for (uint64_t i = 0; i < nl && st == BBXO_OK; i++) {
+    uint32_t m[3] = {0, 0, 0};
+    uint64_t qref[3] = {0, 0, 0};
+    for (uint32_t d = 0; d < dims; d++) {
+      m[d] = (uint32_t)get_bits(meta, mpos, mbits);
+      mpos += mbits;
+      if (m[d] == 1 || m[d] > 31 || m[d] > G[d] + 1) st = BBXO_ECORRUPT;
+    }
+    for (uint32_t d = 0; d < dims; d++) {
+      qref[d] = get_bits(meta, mpos, G[d]);
+      mpos += G[d];
+    }
+    if (st) break;
+    uint32_t sm = 0;
+    for (uint32_t d = 0; d < dims; d++) sm += m[d];
+    if (ppos + (uint64_t)(sizes[i] - 1) * sm > payload_bits) {
+      st = BBXO_ECORRUPT;
+      break;
+    }
+    for (uint32_t d = 0; d < dims; d++) codes[slot * dims + d] = (uint32_t)qref[d];
+    slot++;
+    for (uint32_t j = 1; j < sizes[i] && st == BBXO_OK; j++, slot++) {
+      for (uint32_t d = 0; d < dims; d++) {
+        int64_t qv = (int64_t)qref[d];
+        if (m[d] > 0) {
+          uint64_t u = get_bits(pay, ppos, m[d]);
+          ppos += m[d];
+          if (u == 0) st = BBXO_ECORRUPT; /* code 0 is never emitted */
+          qv = (int64_t)qref[d] + (int64_t)u - ((int64_t)1 << (m[d] - 1));
+        }
+        if (qv < 0 || qv >= ((int64_t)1 << G[d])) st = BBXO_ECORRUPT;
+        codes[slot * dims + d] = (uint32_t)qv;
+      }
+    }
+  }
+  if (st == BBXO_OK && ppos != payload_bits) st = BBXO_ECORRUPT;
+  if (st == BBXO_OK) {
+    /* Sec. 3 dequantization: the bin centre origin + q*w (multiply, then add,
+     * each rounded), then rounded to the stream's type. */
+    for (uint64_t i = 0; i < n; i++)
+      for (uint32_t d = 0; d < dims; d++) {
+        double qw = (double)codes[i * dims + d] * w;
+#if MUT(11)
+        double v = origin[d] + qw + 0.5 * w;
+#else
+        double v = origin[d] + qw;
+#endif
+        uint64_t kk = (layout == 0) ? i * dims + d : (uint64_t)d * n + i;
+        if (dtype == 0)
+          ((float*)pos)[kk] = (float)v;
+        else
+          ((double*)pos)[kk] = v;
+      }
+  }
+  free(sizes);
+  free(codes);
+  return st;
+}

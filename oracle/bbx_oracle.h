@@ -1,0 +1,75 @@
+/*
+ * bbx_oracle.h -- plain, single-threaded CPU oracle of the bit-box particle
+ * compressor's data-parallel path (quantize -> k-d median partition -> per-leaf
+ * bit box -> leaf offsets -> bit packing, and the inverse unpack/dequantize).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * benchmark's CPU-baseline leg load this library.  It shares no code, header,
+ * table or helper with the HIP library; the stream format and status values
+ * are the same interface, written out independently here.
+ *
+ * Paper: Ren, Di, Zhang, Zhao, Guo, "An Error-Bounded Lossy Compression
+ * Method with Bit-Adaptive Quantization for Particle Data" (arXiv 2404.02826).
+ */
+#ifndef BBX_ORACLE_H
+#define BBX_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status values (same numbering as the product library's ABI) */
+enum {
+  BBXO_OK = 0,
+  BBXO_EINVAL = 1,       /* bad argument or non-finite coordinate */
+  BBXO_ENOSPC = 2,       /* output buffer too small */
+  BBXO_ECORRUPT = 3,     /* stream fails validation */
+  BBXO_EBOUND = 4,       /* error bound too small for the input type / 30-bit codes */
+  BBXO_EUNSUPPORTED = 5, /* dims not in {2,3}, n >= 2^32 */
+  BBXO_ENOMEM = 7
+};
+
+/* Worst-case stream size in bytes for n particles. */
+uint64_t bbxo_compress_bound(uint64_t n, uint32_t dims, int dtype);
+
+/*
+ * Compress n particles.  pos: dtype 0 = float32, 1 = float64; layout 0 =
+ * [n][dims] (AoS), 1 = [dims][n] (SoA).  eb_mode 0 = value-range relative
+ * (xi), 1 = absolute (epsilon).  r = leaf capacity (>= 1).  perm (optional,
+ * may be NULL, n entries): source index of each decompressed output slot.
+ * On success *out_size holds the stream length in bytes.
+ */
+int bbxo_compress(const void* pos, uint64_t n, uint32_t dims, int dtype, int layout,
+                  double eb, int eb_mode, uint32_t r,
+                  uint8_t* out, uint64_t out_cap, uint64_t* out_size, uint32_t* perm);
+
+/* Decompress a stream into pos (n*dims values of the stream's dtype). */
+int bbxo_decompress(const uint8_t* stream, uint64_t size, void* pos, uint64_t pos_cap_bytes,
+                    int layout);
+
+/*
+ * Stage dump for stage-by-stage parity.  Any output pointer may be NULL.
+ *   q        [dims][n]  quantized codes in input order
+ *   order    [n]        source index of each particle in tree (leaf) order
+ *   leaf_start, leaf_size, leaf_ref (position of the reference within the leaf),
+ *   leaf_m   [n_leaves][3] bit widths, leaf_bits [n_leaves] payload bits
+ *   scal     [16]: eb_abs, eb_eff, w, inv_w, lo[3], hi[3], G[3] (as doubles), n_leaves
+ * max_leaves bounds the leaf arrays.
+ */
+int bbxo_stages(const void* pos, uint64_t n, uint32_t dims, int dtype, int layout,
+                double eb, int eb_mode, uint32_t r,
+                uint32_t* q, uint32_t* order, uint64_t max_leaves,
+                uint32_t* leaf_start, uint32_t* leaf_size, uint32_t* leaf_ref,
+                uint8_t* leaf_m, uint64_t* leaf_bits, double* scal);
+
+/* Number of leaves of the size-only recursion for n particles, capacity r. */
+uint64_t bbxo_leaf_count(uint64_t n, uint32_t r);
+
+/* Eq. 2 of the paper in its integer form: bits for a largest offset D. */
+uint32_t bbxo_bits_for_offset(uint64_t D);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,205 @@
+"""Pure-Python brute-force re-derivation of the compressor for tiny inputs.
+
+TEST INFRASTRUCTURE ONLY.  A third, independently formulated implementation
+used to pin the C oracle: where the C oracle uses closed forms this module
+searches exhaustively, and it builds the stream with Python big integers
+instead of a bit-at-a-time byte writer.
+
+  * bin widths: smallest m whose Eq. 1 predictable range holds every member
+    (searched m = 0, 1, 2, ...), instead of the bitlen(D) + 1 closed form;
+  * reference: exact rational distance to the AABB centre (Sec. 4.1);
+  * tree: the median definition applied with ``sorted`` at every node.
+"""
+from __future__ import annotations
+
+import math
+import struct
+from fractions import Fraction
+
+import numpy as np
+
+
+def _coords(points: np.ndarray):
+    return [[float(v) for v in row] for row in points]
+
+
+def bound_params(points: np.ndarray, eb: float, eb_mode: str):
+    """Range, error bound, guard and bin width (Sec. 3 + the rounding guard)."""
+    pts = _coords(points)
+    n = len(pts)
+    dims = points.shape[1]
+    f32 = points.dtype == np.float32
+    if n == 0:
+        return dict(lo=[0.0] * dims, hi=[0.0] * dims, eb_abs=(eb if eb_mode == "abs" else 0.0),
+                    eb_eff=0.0, w=0.0, inv_w=0.0, G=[0] * dims)
+    lo = [min(p[d] for p in pts) + 0.0 for d in range(dims)]
+    hi = [max(p[d] for p in pts) + 0.0 for d in range(dims)]
+    delta = max(hi[d] - lo[d] for d in range(dims))
+    eb_abs = eb * delta if eb_mode == "rel" else eb
+    if delta == 0.0:
+        return dict(lo=lo, hi=hi, eb_abs=eb_abs, eb_eff=0.0, w=0.0, inv_w=0.0, G=[0] * dims)
+    amax = max(max(abs(lo[d]), abs(hi[d])) for d in range(dims)) + eb_abs
+    guard = math.ldexp(amax, -48)
+    if f32:
+        _, e = math.frexp(amax)
+        guard += max(math.ldexp(1.0, e - 25), math.ldexp(1.0, -150))
+    eb_eff = eb_abs - guard
+    if not eb_eff > 0:
+        raise ValueError("EBOUND")
+    w = 2.0 * eb_eff
+    inv_w = 1.0 / w
+    codes = [[math.floor((p[d] - lo[d]) * inv_w + 0.5) for d in range(dims)] for p in pts]
+    qmax = [max(c[d] for c in codes) for d in range(dims)]
+    if max(qmax) >= (1 << 30):
+        raise ValueError("EBOUND")
+    G = [int(v).bit_length() for v in qmax]
+    return dict(lo=lo, hi=hi, eb_abs=eb_abs, eb_eff=eb_eff, w=w, inv_w=inv_w, G=G, codes=codes)
+
+
+def quantize(points: np.ndarray, prm: dict):
+    if "codes" in prm:
+        return prm["codes"]
+    return [[0] * points.shape[1] for _ in range(points.shape[0])]
+
+
+def kd_leaves(codes, r: int, dims: int):
+    """Leaves (lists of original indices, ascending) in depth-first order."""
+    leaves = []
+
+    def split(members, depth):
+        if len(members) <= r:
+            leaves.append(members)
+            return
+        d = depth % dims
+        ranked = sorted(members, key=lambda i: (codes[i][d], i))
+        half = len(members) // 2
+        left = set(ranked[:half])
+        split([i for i in members if i in left], depth + 1)
+        split([i for i in members if i not in left], depth + 1)
+
+    n = len(codes)
+    if n:
+        split(list(range(n)), 0)
+    return leaves
+
+
+def minimal_bits(offsets) -> int:
+    """Smallest m whose 2^m - 1 intervals centred on the reference hold every
+    offset (Eq. 1 in code units: |o| <= 2^(m-1) - 1; m = 0 holds only 0)."""
+    m = 0
+    while True:
+        reach = 0 if m == 0 else (1 << (m - 1)) - 1
+        if all(abs(o) <= reach for o in offsets):
+            return m
+        m += 1
+
+
+def bit_box(codes, members, dims):
+    lo = [min(codes[i][d] for i in members) for d in range(dims)]
+    hi = [max(codes[i][d] for i in members) for d in range(dims)]
+    centre = [Fraction(lo[d] + hi[d], 2) for d in range(dims)]
+    best = min(range(len(members)),
+               key=lambda j: (sum((codes[members[j]][d] - centre[d]) ** 2 for d in range(dims)), j))
+    ref = members[best]
+    m = [minimal_bits([codes[i][d] - codes[ref][d] for i in members]) for d in range(dims)]
+    return best, m
+
+
+def compress(points: np.ndarray, eb: float, eb_mode: str = "rel", r: int = 32):
+    """Returns (stream bytes, perm, details) for an (n, dims) float array."""
+    n, dims = points.shape
+    f32 = points.dtype == np.float32
+    mbits = 5 if f32 else 6
+    prm = bound_params(points, eb, eb_mode)
+    codes = quantize(points, prm)
+    leaves = kd_leaves(codes, r, dims)
+    G = prm["G"]
+    meta = 0
+    mpos = 0
+    pay = 0
+    ppos = 0
+    perm = []
+    boxes = []
+    for members in leaves:
+        j, m = bit_box(codes, members, dims)
+        ref = members[j]
+        boxes.append((j, m))
+        for d in range(dims):
+            meta |= m[d] << mpos
+            mpos += mbits
+        for d in range(dims):
+            meta |= codes[ref][d] << mpos
+            mpos += G[d]
+        perm.append(ref)
+        for i in members:
+            if i == ref:
+                continue
+            perm.append(i)
+            for d in range(dims):
+                if m[d]:
+                    pay |= (codes[i][d] - codes[ref][d] + (1 << (m[d] - 1))) << ppos
+                    ppos += m[d]
+    mbytes = 8 * ((mpos + 63) // 64)
+    pbytes = 8 * ((ppos + 63) // 64)
+    lo3 = list(prm["lo"]) + [0.0] * (3 - dims)
+    G3 = list(G) + [0] * (3 - dims)
+    header = struct.pack(
+        "<4sHBBQIBBBBddddd3d3B5xQQQQ", b"BBX1", 1, 0 if f32 else 1, dims, n, r,
+        0 if eb_mode == "rel" else 1, 0, 0, mbits, eb, prm["eb_abs"], prm["eb_eff"], prm["w"],
+        prm["inv_w"], *lo3, *G3, len(leaves), mpos, ppos, 0)
+    assert len(header) == 128
+    stream = header + meta.to_bytes(mbytes, "little") + pay.to_bytes(pbytes, "little")
+    details = dict(prm=prm, codes=codes, leaves=leaves, boxes=boxes)
+    return stream, np.array(perm, dtype=np.uint32), details
+
+
+def decompress(stream: bytes) -> np.ndarray:
+    """Independent decoder for tiny streams (big-integer bit extraction)."""
+    (magic, ver, dt, dims, n, r, mode, _s, _rm, mbits, _eu, _ea, _ee, w, _iw, o0, o1, o2, g0, g1,
+     g2, nl, meta_bits, pay_bits, _res) = struct.unpack("<4sHBBQIBBBBddddd3d3B5xQQQQ", stream[:128])
+    assert magic == b"BBX1" and ver == 1
+    origin = [o0, o1, o2][:dims]
+    G = [g0, g1, g2][:dims]
+    mbytes = 8 * ((meta_bits + 63) // 64)
+    meta = int.from_bytes(stream[128:128 + mbytes], "little")
+    pay = int.from_bytes(stream[128 + mbytes:], "little")
+    sizes = []
+
+    def rec(s):
+        if s <= r:
+            sizes.append(s)
+        else:
+            rec(s // 2)
+            rec(s - s // 2)
+
+    if n:
+        rec(n)
+    assert len(sizes) == nl
+    T = np.float32 if dt == 0 else np.float64
+    out = np.zeros((n, dims), dtype=T)
+    mpos = ppos = slot = 0
+    for s in sizes:
+        m = []
+        for d in range(dims):
+            m.append((meta >> mpos) & ((1 << mbits) - 1))
+            mpos += mbits
+        ref = []
+        for d in range(dims):
+            ref.append((meta >> mpos) & ((1 << G[d]) - 1))
+            mpos += G[d]
+        rows = [ref]
+        for _ in range(s - 1):
+            q = []
+            for d in range(dims):
+                if m[d]:
+                    u = (pay >> ppos) & ((1 << m[d]) - 1)
+                    ppos += m[d]
+                    q.append(ref[d] + u - (1 << (m[d] - 1)))
+                else:
+                    q.append(ref[d])
+            rows.append(q)
+        for q in rows:
+            out[slot] = [T(origin[d] + float(q[d]) * w) for d in range(dims)]
+            slot += 1
+    assert ppos == pay_bits
+    return out

@@ -1,0 +1,153 @@
+"""ctypes wrapper of the C oracle (test infrastructure only).
+
+Only the test-suite, the smoke check and the benchmark's CPU-baseline leg use
+this module.  It never touches the HIP library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+STATUS = {0: "OK", 1: "EINVAL", 2: "ENOSPC", 3: "ECORRUPT", 4: "EBOUND", 5: "EUNSUPPORTED",
+          6: "EHIP", 7: "ENOMEM"}
+
+
+class OracleError(RuntimeError):
+    def __init__(self, status: int):
+        self.status = status
+        self.name = STATUS.get(status, f"status {status}")
+        super().__init__(self.name)
+
+
+def _dt(arr: np.ndarray) -> int:
+    if arr.dtype == np.float32:
+        return 0
+    if arr.dtype == np.float64:
+        return 1
+    raise TypeError("positions must be float32 or float64")
+
+
+class Oracle:
+    """Loads libbbx_oracle.so (building it first if nothing is built)."""
+
+    def __init__(self, path: str | None = None):
+        path = path or _build.LIB
+        if not os.path.exists(path):
+            _build.build_oracle(path)
+        self.path = path
+        lib = C.CDLL(path)
+        u64, u32, i32, dbl, vp = C.c_uint64, C.c_uint32, C.c_int, C.c_double, C.c_void_p
+        lib.bbxo_compress_bound.restype = u64
+        lib.bbxo_compress_bound.argtypes = [u64, u32, i32]
+        lib.bbxo_compress.restype = i32
+        lib.bbxo_compress.argtypes = [vp, u64, u32, i32, i32, dbl, i32, u32, vp, u64,
+                                      C.POINTER(u64), vp]
+        lib.bbxo_decompress.restype = i32
+        lib.bbxo_decompress.argtypes = [vp, u64, vp, u64, i32]
+        lib.bbxo_stages.restype = i32
+        lib.bbxo_stages.argtypes = [vp, u64, u32, i32, i32, dbl, i32, u32, vp, vp, u64, vp, vp,
+                                    vp, vp, vp, vp]
+        lib.bbxo_leaf_count.restype = u64
+        lib.bbxo_leaf_count.argtypes = [u64, u32]
+        lib.bbxo_bits_for_offset.restype = u32
+        lib.bbxo_bits_for_offset.argtypes = [u64]
+        self.lib = lib
+
+    # -- helpers ---------------------------------------------------------
+    @staticmethod
+    def _shape(pos: np.ndarray, layout: str):
+        if pos.ndim != 2:
+            raise ValueError("positions must be 2-D")
+        if layout == "aos":
+            return pos.shape[0], pos.shape[1], 0
+        if layout == "soa":
+            return pos.shape[1], pos.shape[0], 1
+        raise ValueError(layout)
+
+    def compress_bound(self, n: int, dims: int, dtype) -> int:
+        return int(self.lib.bbxo_compress_bound(n, dims, 0 if np.dtype(dtype) == np.float32 else 1))
+
+    def leaf_count(self, n: int, r: int) -> int:
+        return int(self.lib.bbxo_leaf_count(n, r))
+
+    def bits_for_offset(self, D: int) -> int:
+        return int(self.lib.bbxo_bits_for_offset(D))
+
+    # -- API ---------------------------------------------------------------
+    def compress(self, pos: np.ndarray, eb: float, eb_mode: str = "rel", r: int = 32,
+                 layout: str = "aos", want_perm: bool = False, out_cap: int | None = None):
+        pos = np.ascontiguousarray(pos)
+        n, dims, lay = self._shape(pos, layout)
+        dt = _dt(pos)
+        cap = self.compress_bound(n, dims, pos.dtype) if out_cap is None else out_cap
+        out = np.zeros(max(cap, 1), dtype=np.uint8)
+        size = C.c_uint64(0)
+        perm = np.zeros(max(n, 1), dtype=np.uint32) if want_perm else None
+        st = self.lib.bbxo_compress(pos.ctypes.data, n, dims, dt, lay, float(eb),
+                                    0 if eb_mode == "rel" else 1, r, out.ctypes.data, cap,
+                                    C.byref(size), None if perm is None else perm.ctypes.data)
+        if st:
+            raise OracleError(st)
+        stream = out[: size.value].tobytes()
+        if want_perm:
+            return stream, perm[:n].copy()
+        return stream
+
+    def decompress(self, stream: bytes, layout: str = "aos", pos_cap_bytes: int | None = None):
+        buf = np.frombuffer(stream, dtype=np.uint8) if len(stream) else np.zeros(1, np.uint8)
+        if len(stream) >= 16:
+            n = int.from_bytes(stream[8:16], "little")
+            dims = stream[7] if stream[7] in (2, 3) else 3
+            dt = np.float64 if stream[6] == 1 else np.float32
+        else:
+            n, dims, dt = 0, 3, np.float32
+        nalloc = max(n, 0) if n < (1 << 31) else 0
+        out = np.zeros((nalloc, dims) if layout == "aos" else (dims, nalloc), dtype=dt)
+        cap = out.nbytes if pos_cap_bytes is None else pos_cap_bytes
+        st = self.lib.bbxo_decompress(buf.ctypes.data, len(stream), out.ctypes.data if out.size else None,
+                                      cap, 0 if layout == "aos" else 1)
+        if st:
+            raise OracleError(st)
+        return out
+
+    def stages(self, pos: np.ndarray, eb: float, eb_mode: str = "rel", r: int = 32,
+               layout: str = "aos") -> dict:
+        pos = np.ascontiguousarray(pos)
+        n, dims, lay = self._shape(pos, layout)
+        nl = self.leaf_count(n, r)
+        q = np.zeros((dims, max(n, 1)), dtype=np.uint32)
+        order = np.zeros(max(n, 1), dtype=np.uint32)
+        ls = np.zeros(max(nl, 1), dtype=np.uint32)
+        lz = np.zeros(max(nl, 1), dtype=np.uint32)
+        lr = np.zeros(max(nl, 1), dtype=np.uint32)
+        lm = np.zeros((max(nl, 1), 3), dtype=np.uint8)
+        lb = np.zeros(max(nl, 1), dtype=np.uint64)
+        sc = np.zeros(16, dtype=np.float64)
+        st = self.lib.bbxo_stages(pos.ctypes.data, n, dims, _dt(pos), lay, float(eb),
+                                  0 if eb_mode == "rel" else 1, r, q.ctypes.data,
+                                  order.ctypes.data, nl, ls.ctypes.data, lz.ctypes.data,
+                                  lr.ctypes.data, lm.ctypes.data, lb.ctypes.data, sc.ctypes.data)
+        if st:
+            raise OracleError(st)
+        return {
+            "q": q[:, :n], "order": order[:n], "leaf_start": ls[:nl], "leaf_size": lz[:nl],
+            "leaf_ref": lr[:nl], "leaf_m": lm[:nl, :dims], "leaf_bits": lb[:nl],
+            "eb_abs": sc[0], "eb_eff": sc[1], "w": sc[2], "inv_w": sc[3],
+            "lo": sc[4:4 + dims].copy(), "hi": sc[7:7 + dims].copy(),
+            "G": sc[10:10 + dims].astype(int), "n_leaves": int(sc[13]),
+            "meta_bits": int(sc[14]), "payload_bits": int(sc[15]),
+        }
+
+
+_default = None
+
+
+def default() -> Oracle:
+    global _default
+    if _default is None:
+        _default = Oracle()
+    return _default

@@ -1,0 +1,16 @@
+"""Seeded synthetic particle generators shared by the tests and the benchmark.
+
+This package holds no compressor arithmetic: it only draws particle
+positions with the shapes and value distributions of the paper's workloads
+(cosmology- and fluid-shaped sets, Table 2 of the paper), since the paper's
+datasets are not available.
+"""
+from .generators import (  # noqa: F401
+    uniform_cube,
+    cosmology,
+    fluid,
+    fluid_lattice_dims,
+    batch_sets,
+    served_requests,
+    sha256_of,
+)

@@ -1,0 +1,101 @@
+"""A quick battery of oracle pins, callable against any oracle build.
+
+Used by test_oracle_pins (faithful build must pass every pin) and by
+test_oracle_mutations (every planted mistake must fail at least one pin).
+Each pin checks the oracle against something other than itself: the
+paper's worked example, the brute-force re-derivation, or a property that
+follows from the paper's definitions.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+import numpy as np
+
+from oracle import brute
+import props
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def w1_case():
+    with open(os.path.join(GOLDEN, "w1_worked_example.json")) as f:
+        return json.load(f)
+
+
+def pin_worked_example(orc):
+    """Sec. 4.1 worked example: m = (12, 2, 8), reference = the particle
+    nearest the AABB centre, 22 bits per non-reference particle."""
+    g = w1_case()
+    for dt in (np.float64, np.float32):
+        pts = np.array(g["points"], dtype=dt)
+        st = orc.stages(pts, g["eps_abs"], "abs", r=len(pts))
+        assert st["n_leaves"] == 1
+        assert list(st["leaf_m"][0]) == g["m"], (dt, st["leaf_m"])
+        assert int(st["order"][st["leaf_ref"][0]]) == g["reference_index"]
+        assert int(sum(st["leaf_m"][0])) == g["bits_per_particle"]
+        assert int(st["leaf_bits"][0]) == (len(pts) - 1) * g["bits_per_particle"]
+        assert 3 * max(g["m"]) == g["bits_per_particle_shared_width"]
+
+
+def tiny_cases(seed: int, count: int):
+    """Tiny random inputs with duplicates, odd sizes, 2-D/3-D, both types."""
+    rng = np.random.default_rng(seed)
+    for _ in range(count):
+        n = int(rng.integers(1, 36))
+        dims = int(rng.integers(2, 4))
+        dt = np.float32 if rng.random() < 0.5 else np.float64
+        scale = float(rng.choice([1.0, 7.0, 1000.0]))
+        pts = rng.random((n, dims)) * scale
+        if rng.random() < 0.5:
+            pts = np.round(pts * 4 / scale) * scale / 4  # many exact ties
+        pts = pts.astype(dt)
+        r = int(rng.integers(1, max(2, n // 2 + 2)))
+        eb = float(rng.choice([0.2, 0.05, 1e-2, 1e-3]))
+        mode = "rel" if rng.random() < 0.7 else "abs"
+        if mode == "abs":
+            eb = eb * scale
+        yield pts, eb, mode, r
+
+
+def pin_brute_force(orc, seed=11, count=60):
+    """Stream bytes, perm and decoded positions equal the brute-force
+    re-derivation (Python, big-integer packing, exhaustive bit search)."""
+    for pts, eb, mode, r in tiny_cases(seed, count):
+        s1, p1 = orc.compress(pts, eb, mode, r, want_perm=True)
+        s2, p2, _ = brute.compress(pts, eb, mode, r)
+        assert s1 == s2, ("stream differs from brute force", pts.shape, r, eb, mode)
+        assert np.array_equal(p1, p2), "perm differs from brute force"
+        d1 = orc.decompress(s1)
+        d2 = brute.decompress(s2)
+        assert np.array_equal(d1, d2), "decoded positions differ from brute force"
+
+
+def pin_properties(orc, seed=12, count=30):
+    """P1-P6 on the oracle's own output, judged by definitions only."""
+    for pts, eb, mode, r in tiny_cases(seed, count):
+        n, dims = pts.shape
+        s, perm = orc.compress(pts, eb, mode, r, want_perm=True)
+        h = props.parse_header(s)
+        dec = orc.decompress(s)
+        props.check_permutation(perm, n)
+        ea = eb * max(float(pts[:, d].max()) - float(pts[:, d].min()) for d in range(dims)) \
+            if mode == "rel" else eb
+        assert h["eb_abs"] == ea
+        props.check_bound(pts, dec, perm, ea)
+        sizes = props.leaf_sizes(n, r)
+        assert h["n_leaves"] == len(sizes)
+        assert len(s) == props.stream_size(h["meta_bits"], h["payload_bits"])
+
+
+def run_battery(orc):
+    """Returns the names of the pins that fail."""
+    failed = []
+    for name, fn in (("worked_example", pin_worked_example), ("brute_force", pin_brute_force),
+                     ("properties", pin_properties)):
+        try:
+            fn(orc)
+        except Exception as e:  # noqa: BLE001 -- any failure counts as caught
+            failed.append(f"{name}: {type(e).__name__}: {e}"[:200])
+    return failed
