@@ -1,0 +1,157 @@
+/*
+ * bitbox.h -- C ABI of the MI355X (gfx950) bit-box particle compressor.
+ *
+ * Implements the data-parallel path of the error-bounded, bit-adaptive
+ * particle-position compressor of Ren, Di, Zhang, Zhao and Guo, "An
+ * Error-Bounded Lossy Compression Method with Bit-Adaptive Quantization for
+ * Particle Data" (arXiv 2404.02826):
+ *
+ *   compress   = range and bound (Sec. 3) -> quantization into bins of width
+ *                2*eb (Sec. 3, linear-scale quantization) -> k-d median
+ *                partition into leaves of <= r particles (Sec. 4.1) -> per-leaf
+ *                bit box: reference particle nearest the AABB centre and the
+ *                per-axis widths of Eq. 2 (Sec. 4.1) -> leaf bit offsets ->
+ *                bit packing (Sec. 4.2, in a structure-of-arrays layout)
+ *   decompress = unpack -> dequantize to the bin centre (Sec. 3)
+ *
+ * All entry points are extern "C", take plain host or device pointers and
+ * sizes, and never throw.  Every buffer is owned by the caller; the library
+ * never allocates device memory on these paths and keeps no per-call global
+ * state apart from the thread-local error message.  Calls are ordered on the
+ * given HIP stream.
+ *
+ * Stream format v1 (little-endian), produced byte-for-byte identically to the
+ * CPU oracle:
+ *   [0,128)   header: magic 'BBX1' u32 | version u16 = 1 | dtype u8 | dims u8 |
+ *             n u64 | r u32 | eb_mode u8 | split_rule u8 = 0 | ref_mode u8 = 0 |
+ *             mbits u8 (5 for f32, 6 for f64: Sec. 4.2) | eb_user f64 |
+ *             eb_abs f64 | eb_eff f64 | w f64 | inv_w f64 | origin[3] f64 |
+ *             G[3] u8 + 5 zero bytes | n_leaves u64 | meta_bits u64 |
+ *             payload_bits u64 | reserved u64 = 0
+ *   meta      n_leaves fixed-stride records, leaves in depth-first order:
+ *             m_d (mbits each, d < dims) then the reference's code q_d (G_d
+ *             bits each); zero-padded to 8 bytes
+ *   payload   per leaf, every non-reference member in ascending original
+ *             index, per axis the code q - q_ref + 2^(m_d - 1) in m_d bits
+ *             (nothing when m_d = 0); zero-padded to 8 bytes
+ *   Bit i of a section is bit (i mod 64) of its little-endian u64 word i/64.
+ *
+ * Decompressed order: leaves depth-first; in each leaf the reference first,
+ * then the other members in ascending original index (the paper keeps all
+ * particles but not their order, Sec. 2.2).  The optional perm[] output of
+ * compress gives the source index of every output slot.
+ *
+ * Error bound: every reconstructed coordinate satisfies |x - x_hat| <= eb_abs
+ * (eb_abs = eb * Delta_max for the relative mode, Delta_max the largest
+ * coordinate range over the axes, Sec. 3), including FP64 and output-type
+ * rounding: the bins are 2*eb_eff wide with eb_eff = eb_abs minus a guard of
+ * half an FP32 ulp of the largest magnitude (FP32 input) plus 2^-48 of it.
+ */
+#ifndef BITBOX_H
+#define BITBOX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  BBX_OK = 0,
+  BBX_EINVAL = 1,       /* bad argument, or a NaN/Inf coordinate */
+  BBX_ENOSPC = 2,       /* output or position buffer too small */
+  BBX_ECORRUPT = 3,     /* stream fails validation */
+  BBX_EBOUND = 4,       /* eb too small for the input type, or codes would need >= 30 bits */
+  BBX_EUNSUPPORTED = 5, /* dims not in {2,3}, or n >= 2^32 */
+  BBX_EHIP = 6,         /* a HIP runtime call failed */
+  BBX_ENOMEM = 7        /* workspace too small */
+} bbx_status;
+
+typedef enum { BBX_F32 = 0, BBX_F64 = 1 } bbx_dtype;
+typedef enum { BBX_EB_REL = 0, BBX_EB_ABS = 1 } bbx_eb_mode; /* xi or epsilon, Sec. 3 */
+typedef enum { BBX_AOS = 0, BBX_SOA = 1 } bbx_layout;         /* [n][dims] or [dims][n] */
+
+/* Compression parameters.  leaf_size is r of Sec. 4.1 (a node of <= r
+ * particles is not split); it changes the stream.  tile_override selects the
+ * on-chip tile capacity (0 = library default); it never changes the stream. */
+typedef struct {
+  uint32_t leaf_size;     /* r >= 1 */
+  uint32_t eb_mode;       /* bbx_eb_mode */
+  uint32_t layout;        /* bbx_layout of the input positions */
+  uint32_t tile_override; /* 0, or one of 1024, 2048 */
+} bbx_params;
+
+/* Worst-case stream size in bytes for n particles of the given type. */
+size_t bbx_compress_bound(uint64_t n, uint32_t dims, bbx_dtype dtype);
+
+/* Device workspace bytes needed by bbx_compress for these arguments
+ * (0 on invalid arguments; bbx_last_error() says why). */
+size_t bbx_compress_workspace_size(uint64_t n, uint32_t dims, bbx_dtype dtype,
+                                   const bbx_params* params);
+
+/*
+ * Compress n particles.
+ *   d_pos      device, n*dims values of dtype in params->layout
+ *   eb         xi (relative) or epsilon (absolute), > 0 and finite
+ *   d_out      device, out_cap bytes; receives the stream
+ *   h_out_size host; if non-NULL the call synchronizes the stream once at the
+ *              end and stores the stream length; on error the returned status
+ *              says why and d_out is not written
+ *   d_size     device u64 (optional); receives the stream length, or
+ *              UINT64_MAX if the device detected an error (async mode)
+ *   d_status   device u32 (optional); receives the bbx_status of the call
+ *   d_perm     device u32[n] (optional); source index of each output slot
+ *   d_ws       device workspace of ws_size >= bbx_compress_workspace_size()
+ * With h_out_size == NULL nothing waits: argument errors are still returned
+ * at once, data errors (NaN/Inf, eb too small, out_cap too small) appear in
+ * *d_status / *d_size.
+ */
+bbx_status bbx_compress(const void* d_pos, uint64_t n, uint32_t dims, bbx_dtype dtype, double eb,
+                        const bbx_params* params, void* d_out, size_t out_cap,
+                        size_t* h_out_size, uint64_t* d_size, uint32_t* d_status,
+                        uint32_t* d_perm, void* d_ws, size_t ws_size, hipStream_t stream);
+
+/* Parses and validates a stream header (host copy of its first 128 bytes). */
+bbx_status bbx_stream_info(const void* h_header, size_t header_bytes, uint64_t* n,
+                           uint32_t* dims, bbx_dtype* dtype, double* eb_abs, uint32_t* leaf_size,
+                           uint64_t* n_leaves, uint64_t* stream_bytes);
+
+/* Device workspace bytes needed by bbx_decompress for the stream whose
+ * header is h_header (host copy of its first 128 bytes). */
+size_t bbx_decompress_workspace_size(const void* h_header, size_t header_bytes);
+
+/*
+ * Decompress a stream into d_pos (n*dims values of the stream's dtype in the
+ * requested layout, pos_cap bytes).
+ *   h_header   optional host copy of the first 128 stream bytes; if NULL the
+ *              library copies them from d_stream (one stream synchronization)
+ *   d_status   device u32 (optional).  If non-NULL the call does not wait and
+ *              payload corruption found on the device is reported there; if
+ *              NULL the call synchronizes at the end and returns it.
+ */
+bbx_status bbx_decompress(const void* d_stream, size_t stream_size, const void* h_header,
+                          void* d_pos, size_t pos_cap, bbx_layout layout, uint32_t* d_status,
+                          void* d_ws, size_t ws_size, hipStream_t stream);
+
+/* Short name of a status value, and the calling thread's last error message. */
+const char* bbx_status_str(bbx_status status);
+const char* bbx_last_error(void);
+
+/*
+ * Kernel timing.  While enabled, every kernel launch of the library is
+ * bracketed by HIP events on its stream; bbx_profile_get() waits for the
+ * recorded events and reports, per kernel name, the number of launches and
+ * their summed duration in milliseconds.  Index i runs over 0..count-1.
+ */
+void bbx_profile_enable(int on);
+void bbx_profile_reset(void);
+int bbx_profile_count(void);
+bbx_status bbx_profile_get(int i, const char** name, uint64_t* launches, double* total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BITBOX_H */

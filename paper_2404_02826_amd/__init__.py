@@ -1,0 +1,26 @@
+"""bitbox: MI355X (gfx950) bit-box particle compressor.
+
+Thin Python binding of the C ABI declared in include/bitbox.h (arXiv
+2404.02826: quantize -> k-d median partition -> per-leaf bit box -> offsets
+-> bit packing, and unpack -> dequantize).  Every step runs in the HIP
+library; this module only marshals arguments.  PyTorch supplies device
+memory and the current HIP stream.  There is no CPU fallback: if the built
+library is missing, every call raises.
+"""
+from __future__ import annotations
+
+from ._binding import (  # noqa: F401
+    BitboxError,
+    Compressor,
+    Decompressor,
+    STATUS,
+    compress,
+    compress_bound,
+    compress_workspace_size,
+    decompress,
+    decompress_workspace_size,
+    lib_path,
+    load,
+    profile,
+    stream_info,
+)

@@ -1,0 +1,252 @@
+"""ctypes marshalling for libbitbox.so (include/bitbox.h)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from contextlib import contextmanager
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_PKG, "lib", "libbitbox.so")
+_lib = None
+
+STATUS = {0: "OK", 1: "EINVAL", 2: "ENOSPC", 3: "ECORRUPT", 4: "EBOUND", 5: "EUNSUPPORTED",
+          6: "EHIP", 7: "ENOMEM"}
+
+F32, F64 = 0, 1
+REL, ABS = 0, 1
+AOS, SOA = 0, 1
+
+
+class BitboxError(RuntimeError):
+    def __init__(self, status: int, msg: str = ""):
+        self.status = status
+        self.name = STATUS.get(status, f"status {status}")
+        super().__init__(f"{self.name}: {msg}" if msg else self.name)
+
+
+class _Params(C.Structure):
+    _fields_ = [("leaf_size", C.c_uint32), ("eb_mode", C.c_uint32), ("layout", C.c_uint32),
+                ("tile_override", C.c_uint32)]
+
+
+def lib_path() -> str:
+    return _LIB_PATH
+
+
+def load():
+    """Loads the built HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError(f"{_LIB_PATH} is not built (run __graft_entry__.build())")
+    lib = C.CDLL(_LIB_PATH)
+    u64, u32, i32, dbl, vp, sz = C.c_uint64, C.c_uint32, C.c_int, C.c_double, C.c_void_p, C.c_size_t
+    lib.bbx_compress_bound.restype = sz
+    lib.bbx_compress_bound.argtypes = [u64, u32, i32]
+    lib.bbx_compress_workspace_size.restype = sz
+    lib.bbx_compress_workspace_size.argtypes = [u64, u32, i32, C.POINTER(_Params)]
+    lib.bbx_compress.restype = i32
+    lib.bbx_compress.argtypes = [vp, u64, u32, i32, dbl, C.POINTER(_Params), vp, sz,
+                                 C.POINTER(sz), vp, vp, vp, vp, sz, vp]
+    lib.bbx_stream_info.restype = i32
+    lib.bbx_stream_info.argtypes = [vp, sz, C.POINTER(u64), C.POINTER(u32), C.POINTER(i32),
+                                    C.POINTER(dbl), C.POINTER(u32), C.POINTER(u64), C.POINTER(u64)]
+    lib.bbx_decompress_workspace_size.restype = sz
+    lib.bbx_decompress_workspace_size.argtypes = [vp, sz]
+    lib.bbx_decompress.restype = i32
+    lib.bbx_decompress.argtypes = [vp, sz, vp, vp, sz, i32, vp, vp, sz, vp]
+    lib.bbx_status_str.restype = C.c_char_p
+    lib.bbx_status_str.argtypes = [i32]
+    lib.bbx_last_error.restype = C.c_char_p
+    lib.bbx_last_error.argtypes = []
+    lib.bbx_profile_enable.restype = None
+    lib.bbx_profile_enable.argtypes = [i32]
+    lib.bbx_profile_reset.restype = None
+    lib.bbx_profile_reset.argtypes = []
+    lib.bbx_profile_count.restype = i32
+    lib.bbx_profile_count.argtypes = []
+    lib.bbx_profile_get.restype = i32
+    lib.bbx_profile_get.argtypes = [i32, C.POINTER(C.c_char_p), C.POINTER(u64), C.POINTER(dbl)]
+    _lib = lib
+    return lib
+
+
+def _check(st: int):
+    if st != 0:
+        raise BitboxError(st, load().bbx_last_error().decode())
+
+
+def _stream_ptr(stream) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float32:
+        return F32
+    if t.dtype == torch.float64:
+        return F64
+    raise TypeError("positions must be float32 or float64")
+
+
+def _shape(pos: torch.Tensor, layout: str):
+    if pos.dim() != 2:
+        raise ValueError("positions must be 2-D: (n, dims) for aos or (dims, n) for soa")
+    if layout == "aos":
+        return pos.shape[0], pos.shape[1], AOS
+    if layout == "soa":
+        return pos.shape[1], pos.shape[0], SOA
+    raise ValueError(layout)
+
+
+def _params(leaf_size: int, eb_mode: str, layout: int, tile: int) -> _Params:
+    return _Params(leaf_size, REL if eb_mode == "rel" else ABS, layout, tile)
+
+
+def compress_bound(n: int, dims: int = 3, dtype=torch.float32) -> int:
+    return int(load().bbx_compress_bound(n, dims, F32 if dtype == torch.float32 else F64))
+
+
+def compress_workspace_size(n: int, dims: int = 3, dtype=torch.float32, leaf_size: int = 32,
+                            eb_mode: str = "rel", layout: str = "aos", tile: int = 0) -> int:
+    p = _params(leaf_size, eb_mode, AOS if layout == "aos" else SOA, tile)
+    v = int(load().bbx_compress_workspace_size(n, dims, F32 if dtype == torch.float32 else F64,
+                                               C.byref(p)))
+    if v == 0:
+        raise BitboxError(1, load().bbx_last_error().decode())
+    return v
+
+
+class Compressor:
+    """Reusable compress call: owns the workspace and the output buffer.
+
+    ``__call__`` synchronizes once and returns the stream as a uint8 view of
+    the output buffer (valid until the next call); ``launch`` enqueues the
+    work without waiting and leaves the size in ``d_size`` (device).
+    """
+
+    def __init__(self, n: int, dims: int = 3, dtype=torch.float32, leaf_size: int = 32,
+                 eb_mode: str = "rel", layout: str = "aos", tile: int = 0, want_perm: bool = False,
+                 device="cuda"):
+        self.n, self.dims, self.dtype = n, dims, dtype
+        self.layout = layout
+        self.params = _params(leaf_size, eb_mode, AOS if layout == "aos" else SOA, tile)
+        lib = load()
+        self.ws_size = compress_workspace_size(n, dims, dtype, leaf_size, eb_mode, layout, tile)
+        self.ws = torch.empty(self.ws_size, dtype=torch.uint8, device=device)
+        self.cap = compress_bound(n, dims, dtype)
+        self.out = torch.empty((self.cap + 7) // 8 * 8, dtype=torch.uint8, device=device)
+        self.perm = torch.empty(max(n, 1), dtype=torch.int32, device=device) if want_perm else None
+        self.d_size = torch.zeros(1, dtype=torch.int64, device=device)
+        self.d_status = torch.zeros(1, dtype=torch.int32, device=device)
+        self._lib = lib
+
+    def _call(self, pos: torch.Tensor, eb: float, h_size, stream):
+        n, dims, lay = _shape(pos, self.layout)
+        if n != self.n or dims != self.dims or pos.dtype != self.dtype:
+            raise ValueError("positions do not match this Compressor's shape/type")
+        if not pos.is_cuda or not pos.is_contiguous():
+            raise ValueError("positions must be a contiguous device tensor")
+        return self._lib.bbx_compress(
+            pos.data_ptr() if n else None, n, dims, _dtype_code(pos), float(eb), C.byref(self.params),
+            self.out.data_ptr(), self.cap, h_size, self.d_size.data_ptr(), self.d_status.data_ptr(),
+            self.perm.data_ptr() if self.perm is not None else None, self.ws.data_ptr(),
+            self.ws_size, _stream_ptr(stream))
+
+    def launch(self, pos: torch.Tensor, eb: float, stream=None):
+        _check(self._call(pos, eb, None, stream))
+
+    def __call__(self, pos: torch.Tensor, eb: float, stream=None):
+        size = C.c_size_t(0)
+        _check(self._call(pos, eb, C.byref(size), stream))
+        return self.out[: size.value]
+
+
+class Decompressor:
+    """Reusable decompress call for streams of one header shape."""
+
+    def __init__(self, header: bytes, layout: str = "aos", device="cuda"):
+        lib = load()
+        self.header = bytes(header[:128])
+        self.info = stream_info(self.header)
+        self.layout = layout
+        self.ws_size = int(lib.bbx_decompress_workspace_size(self.header, 128))
+        if self.ws_size == 0:
+            raise BitboxError(3, lib.bbx_last_error().decode())
+        self.ws = torch.empty(self.ws_size, dtype=torch.uint8, device=device)
+        n, dims = self.info["n"], self.info["dims"]
+        dt = torch.float32 if self.info["dtype"] == F32 else torch.float64
+        shape = (n, dims) if layout == "aos" else (dims, n)
+        self.pos = torch.empty(shape, dtype=dt, device=device)
+        self.d_status = torch.zeros(1, dtype=torch.int32, device=device)
+        self._lib = lib
+
+    def _call(self, stream_t: torch.Tensor, d_status, stream):
+        return self._lib.bbx_decompress(
+            stream_t.data_ptr(), stream_t.numel(), self.header, self.pos.data_ptr(),
+            self.pos.numel() * self.pos.element_size(), AOS if self.layout == "aos" else SOA,
+            d_status, self.ws.data_ptr(), self.ws_size, _stream_ptr(stream))
+
+    def launch(self, stream_t: torch.Tensor, stream=None):
+        _check(self._call(stream_t, self.d_status.data_ptr(), stream))
+
+    def __call__(self, stream_t: torch.Tensor, stream=None):
+        _check(self._call(stream_t, None, stream))
+        return self.pos
+
+
+def stream_info(header: bytes) -> dict:
+    lib = load()
+    n, dims, dt, eb, r, nl, sb = (C.c_uint64(), C.c_uint32(), C.c_int(), C.c_double(),
+                                  C.c_uint32(), C.c_uint64(), C.c_uint64())
+    buf = bytes(header[:128])
+    _check(lib.bbx_stream_info(buf, len(buf), C.byref(n), C.byref(dims), C.byref(dt),
+                               C.byref(eb), C.byref(r), C.byref(nl), C.byref(sb)))
+    return dict(n=n.value, dims=dims.value, dtype=dt.value, eb_abs=eb.value, leaf_size=r.value,
+                n_leaves=nl.value, stream_bytes=sb.value)
+
+
+def decompress_workspace_size(header: bytes) -> int:
+    return int(load().bbx_decompress_workspace_size(bytes(header[:128]), 128))
+
+
+def compress(pos: torch.Tensor, eb: float, eb_mode: str = "rel", leaf_size: int = 32,
+             layout: str = "aos", want_perm: bool = False, tile: int = 0, stream=None):
+    """One-shot compress of a device tensor; returns the stream as a uint8
+    device tensor (and the int32 source index of every output slot)."""
+    n, dims, _ = _shape(pos, layout)
+    c = Compressor(n, dims, pos.dtype, leaf_size, eb_mode, layout, tile, want_perm, pos.device)
+    s = c(pos.contiguous(), eb, stream).clone()
+    if want_perm:
+        return s, c.perm[:n].clone()
+    return s
+
+
+def decompress(stream_t: torch.Tensor, layout: str = "aos", stream=None) -> torch.Tensor:
+    """One-shot decompress of a device uint8 stream."""
+    if stream_t.numel() < 128:
+        raise BitboxError(3, "stream shorter than its header")
+    header = stream_t[:128].cpu().numpy().tobytes()
+    d = Decompressor(header, layout, stream_t.device)
+    return d(stream_t, stream).clone()
+
+
+@contextmanager
+def profile():
+    """Collects per-kernel launch counts and summed durations (ms)."""
+    lib = load()
+    lib.bbx_profile_reset()
+    lib.bbx_profile_enable(1)
+    result = {}
+    try:
+        yield result
+    finally:
+        lib.bbx_profile_enable(0)
+        for i in range(lib.bbx_profile_count()):
+            name, cnt, ms = C.c_char_p(), C.c_uint64(), C.c_double()
+            _check(lib.bbx_profile_get(i, C.byref(name), C.byref(cnt), C.byref(ms)))
+            result[name.value.decode()] = (cnt.value, ms.value)
+        lib.bbx_profile_reset()

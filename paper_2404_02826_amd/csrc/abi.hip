@@ -1,0 +1,463 @@
+// abi.hip -- the C ABI of include/bitbox.h: argument validation, the launch
+// plan (tree shape, tile depth), workspace carving, the stream-ordered launch
+// sequence, and kernel timing.
+#include <math.h>
+#include <string.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "bbx_internal.h"
+
+namespace bbx {
+
+static thread_local std::string g_err;
+
+static bbx_status fail(bbx_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+// ---------------------------------------------------------------- profiling
+
+struct ProfEntry {
+  std::string name;
+  uint64_t launches = 0;
+  double ms = 0.0;
+};
+struct Pending {
+  int entry;
+  hipEvent_t ev[2];
+};
+static std::mutex g_prof_mu;
+static bool g_prof_on = false;
+static std::vector<ProfEntry> g_prof;
+static std::vector<Pending> g_pending;
+
+static int prof_index(const char* name) {
+  for (size_t i = 0; i < g_prof.size(); ++i)
+    if (g_prof[i].name == name) return (int)i;
+  ProfEntry e;
+  e.name = name;
+  g_prof.push_back(e);
+  return (int)g_prof.size() - 1;
+}
+
+ProfScope::ProfScope(const char* nm, hipStream_t s) : name(nm), stream(s), on(false) {
+  if (!g_prof_on) return;
+  if (hipEventCreate(&ev[0]) != hipSuccess) return;
+  if (hipEventCreate(&ev[1]) != hipSuccess) {
+    (void)hipEventDestroy(ev[0]);
+    return;
+  }
+  (void)hipEventRecord(ev[0], stream);
+  on = true;
+}
+
+ProfScope::~ProfScope() {
+  if (!on) return;
+  (void)hipEventRecord(ev[1], stream);
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  Pending p;
+  p.entry = prof_index(name);
+  p.ev[0] = ev[0];
+  p.ev[1] = ev[1];
+  g_pending.push_back(p);
+}
+
+static void prof_drain() {
+  for (auto& p : g_pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(p.ev[1]) == hipSuccess &&
+        hipEventElapsedTime(&ms, p.ev[0], p.ev[1]) == hipSuccess) {
+      g_prof[p.entry].launches += 1;
+      g_prof[p.entry].ms += ms;
+    }
+    (void)hipEventDestroy(p.ev[0]);
+    (void)hipEventDestroy(p.ev[1]);
+  }
+  g_pending.clear();
+}
+
+// ---------------------------------------------------------------- geometry
+
+TreeGeom make_geom(uint64_t n, uint32_t r) {
+  TreeGeom g;
+  memset(&g, 0, sizeof(g));
+  g.n = n;
+  g.r = r;
+  uint32_t D = 0;
+  while (D < 63 && ((n + (1ull << D) - 1) >> D) > r) ++D;  // first depth with every node <= r
+  g.depths = D + 1;
+  for (uint32_t k = 0; k <= D && k < (uint32_t)kMaxDepth; ++k) g.a[k] = n >> k;
+  for (int k = (int)D; k >= 0; --k)
+    for (int t = 0; t < 2; ++t) {
+      uint64_t s = g.a[k] + t;
+      if (s <= r || k == (int)D) {
+        g.L[k][t] = 1;
+      } else {
+        uint64_t sl = s >> 1, sr = s - sl;
+        g.L[k][t] = g.L[k + 1][sl - g.a[k + 1]] + g.L[k + 1][sr - g.a[k + 1]];
+      }
+    }
+  return g;
+}
+
+static size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+static bbx_status check_compress_args(uint64_t n, uint32_t dims, bbx_dtype dtype, double eb,
+                                      const bbx_params* prm) {
+  if (!prm) return fail(BBX_EINVAL, "params is NULL");
+  if (dtype != BBX_F32 && dtype != BBX_F64) return fail(BBX_EINVAL, "dtype must be BBX_F32 or BBX_F64");
+  if (prm->layout != BBX_AOS && prm->layout != BBX_SOA) return fail(BBX_EINVAL, "layout must be AOS or SOA");
+  if (prm->eb_mode != BBX_EB_REL && prm->eb_mode != BBX_EB_ABS) return fail(BBX_EINVAL, "eb_mode must be REL or ABS");
+  if (prm->leaf_size == 0) return fail(BBX_EINVAL, "leaf_size must be >= 1");
+  if (!isfinite(eb) || !(eb > 0.0)) return fail(BBX_EINVAL, "eb must be finite and > 0");
+  if (prm->tile_override != 0 && prm->tile_override != 1024 && prm->tile_override != 2048)
+    return fail(BBX_EINVAL, "tile_override must be 0, 1024 or 2048");
+  if (dims != 2 && dims != 3) return fail(BBX_EUNSUPPORTED, "dims must be 2 or 3");
+  if (n >= (1ull << 32)) return fail(BBX_EUNSUPPORTED, "n must be below 2^32");
+  return BBX_OK;
+}
+
+static CompressPlan make_plan(uint64_t n, uint32_t dims, bbx_dtype dtype, double eb,
+                              const bbx_params* prm, bool track) {
+  CompressPlan p;
+  memset(&p, 0, sizeof(p));
+  p.n = n;
+  p.dims = dims;
+  p.dtype = (uint32_t)dtype;
+  p.layout = prm->layout;
+  p.r = prm->leaf_size;
+  p.eb_mode = prm->eb_mode;
+  p.eb = eb;
+  p.track_idx = track ? 1u : 0u;
+  p.tile = prm->tile_override ? prm->tile_override : 2048;
+  p.mbits = dtype == BBX_F32 ? 5u : 6u;
+  if (n == 0) return p;
+  p.geom = make_geom(n, p.r);
+  p.n_leaves = p.geom.L[0][0];
+  if (p.r < p.tile) {
+    p.tile_mode = 1;
+    uint32_t K = 0;
+    while (((n + (1ull << K) - 1) >> K) > p.tile) ++K;
+    p.global_levels = K;
+  } else {
+    p.tile_mode = 0;
+    uint32_t K = 0;
+    while ((n >> K) > p.r) ++K;
+    const uint64_t hi = (n + (1ull << K) - 1) >> K;
+    p.global_levels = hi <= p.r ? K : K + 1;
+  }
+  p.max_nodes = 0;
+  p.max_blocks = 0;
+  for (uint32_t k = 0; k < p.global_levels; ++k) {
+    LevelShape sh = level_shape(p, k);
+    if (sh.nodes > p.max_nodes) p.max_nodes = sh.nodes;
+    if (sh.nodes * sh.chunks > p.max_blocks) p.max_blocks = sh.nodes * sh.chunks;
+  }
+  return p;
+}
+
+struct Carve {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  }
+};
+
+static size_t carve_compress(const CompressPlan& p, uint8_t* base, CompressWs* w) {
+  Carve c;
+  const size_t o_params = c.take(sizeof(DevParams));
+  const size_t o_part = c.take(sizeof(double) * 8 * kMinMaxBlocks);
+  const size_t kb = (size_t)p.dims * p.n * 4;
+  const size_t o_k0 = c.take(kb), o_k1 = c.take(kb);
+  const size_t o_i0 = c.take(p.n * 4), o_i1 = c.take(p.n * 4);
+  const size_t o_hist = c.take(p.max_nodes * kHistStride * 4);
+  const size_t o_sel = c.take(p.max_nodes * sizeof(NodeSel));
+  const size_t o_rows = c.take(p.max_blocks * kRowStride * 4);
+  const size_t o_cb = c.take(p.max_blocks * 8);
+  const size_t o_leaves = c.take(p.n_leaves * sizeof(LeafRec));
+  const size_t o_bits = c.take(p.n_leaves * 8);
+  const size_t o_sp = c.take((scan_blocks(p.n_leaves) + 1) * 8);
+  if (w && base) {
+    w->params = (DevParams*)(base + o_params);
+    w->partials = (double*)(base + o_part);
+    w->keys[0] = base + o_k0;
+    w->keys[1] = base + o_k1;
+    w->idx[0] = (uint32_t*)(base + o_i0);
+    w->idx[1] = (uint32_t*)(base + o_i1);
+    w->hist = (uint32_t*)(base + o_hist);
+    w->sel = (NodeSel*)(base + o_sel);
+    w->rows = (uint32_t*)(base + o_rows);
+    w->chunk_base = (uint32_t*)(base + o_cb);
+    w->leaves = (LeafRec*)(base + o_leaves);
+    w->leaf_bits = (uint64_t*)(base + o_bits);
+    w->scan_part = (uint64_t*)(base + o_sp);
+  }
+  return c.off;
+}
+
+// ---------------------------------------------------------------- stream header
+
+struct HostHeader {
+  uint64_t n, n_leaves, meta_bits, payload_bits;
+  uint32_t dims, dtype, r, eb_mode, mbits;
+  uint32_t G[3];
+  double eb_user, eb_abs, eb_eff, w, inv_w, origin[3];
+};
+
+static uint64_t rd64(const uint8_t* b) {
+  uint64_t v;
+  memcpy(&v, b, 8);
+  return v;
+}
+static double rdf(const uint8_t* b) {
+  double v;
+  memcpy(&v, b, 8);
+  return v;
+}
+
+static bbx_status parse_header(const uint8_t* h, size_t bytes, HostHeader* o) {
+  if (!h || bytes < (size_t)kHeaderBytes) return fail(BBX_ECORRUPT, "stream shorter than its header");
+  uint32_t magic;
+  memcpy(&magic, h, 4);
+  uint16_t ver;
+  memcpy(&ver, h + 4, 2);
+  if (magic != kMagic || ver != 1) return fail(BBX_ECORRUPT, "bad magic or version");
+  o->dtype = h[6];
+  o->dims = h[7];
+  o->n = rd64(h + 8);
+  memcpy(&o->r, h + 16, 4);
+  o->eb_mode = h[20];
+  o->mbits = h[23];
+  if (o->dtype > 1 || (o->dims != 2 && o->dims != 3) || o->eb_mode > 1 || h[21] != 0 || h[22] != 0)
+    return fail(BBX_ECORRUPT, "bad dtype, dims, eb_mode or rule fields");
+  if (o->mbits != (o->dtype == 0 ? 5u : 6u) || o->r == 0 || o->n >= (1ull << 32))
+    return fail(BBX_ECORRUPT, "bad width-field size, leaf size or n");
+  o->eb_user = rdf(h + 24);
+  o->eb_abs = rdf(h + 32);
+  o->eb_eff = rdf(h + 40);
+  o->w = rdf(h + 48);
+  o->inv_w = rdf(h + 56);
+  uint32_t sumG = 0;
+  for (uint32_t d = 0; d < 3; ++d) {
+    o->origin[d] = rdf(h + 64 + 8 * d);
+    o->G[d] = h[88 + d];
+    if (d >= o->dims && (o->G[d] != 0 || o->origin[d] != 0.0)) return fail(BBX_ECORRUPT, "unused axis fields not zero");
+    if (o->G[d] > 30 || !isfinite(o->origin[d])) return fail(BBX_ECORRUPT, "bad code width or origin");
+    sumG += o->G[d];
+  }
+  if (!isfinite(o->w) || o->w < 0.0) return fail(BBX_ECORRUPT, "bad bin width");
+  for (int k = 91; k < 96; ++k)
+    if (h[k] != 0) return fail(BBX_ECORRUPT, "header padding not zero");
+  o->n_leaves = rd64(h + 96);
+  o->meta_bits = rd64(h + 104);
+  o->payload_bits = rd64(h + 112);
+  if (rd64(h + 120) != 0) return fail(BBX_ECORRUPT, "reserved field not zero");
+  const uint64_t nl = o->n ? make_geom(o->n, o->r).L[0][0] : 0;
+  if (o->n_leaves != nl) return fail(BBX_ECORRUPT, "leaf count does not match (n, r)");
+  if (o->meta_bits != nl * (uint64_t)(o->dims * o->mbits + sumG)) return fail(BBX_ECORRUPT, "meta size mismatch");
+  if (o->payload_bits > o->n * (uint64_t)o->dims * 31u) return fail(BBX_ECORRUPT, "payload size out of range");
+  return BBX_OK;
+}
+
+static uint64_t stream_bytes_of(const HostHeader& h) {
+  return kHeaderBytes + ((h.meta_bits + 63) / 64) * 8 + ((h.payload_bits + 63) / 64) * 8;
+}
+
+static size_t carve_decompress(const HostHeader& h, uint8_t* base, DecompressWs* w) {
+  Carve c;
+  const size_t o_params = c.take(sizeof(DevParams));
+  const size_t o_leaves = c.take(h.n_leaves * sizeof(LeafRec));
+  const size_t o_bits = c.take(h.n_leaves * 8);
+  const size_t o_sp = c.take((scan_blocks(h.n_leaves) + 1) * 8);
+  if (w && base) {
+    w->params = (DevParams*)(base + o_params);
+    w->leaves = (LeafRec*)(base + o_leaves);
+    w->leaf_bits = (uint64_t*)(base + o_bits);
+    w->scan_part = (uint64_t*)(base + o_sp);
+  }
+  return c.off;
+}
+
+}  // namespace bbx
+
+using namespace bbx;
+
+extern "C" {
+
+size_t bbx_compress_bound(uint64_t n, uint32_t dims, bbx_dtype dtype) {
+  const uint64_t mbits = dtype == BBX_F64 ? 6 : 5;
+  return kHeaderBytes + 16 + ((n * dims * (mbits + 30) + 63) / 64) * 8;
+}
+
+size_t bbx_compress_workspace_size(uint64_t n, uint32_t dims, bbx_dtype dtype,
+                                   const bbx_params* params) {
+  if (check_compress_args(n, dims, dtype, 1.0, params) != BBX_OK) return 0;
+  CompressPlan p = make_plan(n, dims, dtype, 1.0, params, true);
+  return carve_compress(p, nullptr, nullptr);
+}
+
+bbx_status bbx_compress(const void* d_pos, uint64_t n, uint32_t dims, bbx_dtype dtype, double eb,
+                        const bbx_params* params, void* d_out, size_t out_cap,
+                        size_t* h_out_size, uint64_t* d_size, uint32_t* d_status,
+                        uint32_t* d_perm, void* d_ws, size_t ws_size, hipStream_t stream) {
+  bbx_status st = check_compress_args(n, dims, dtype, eb, params);
+  if (st != BBX_OK) return st;
+  if (n > 0 && !d_pos) return fail(BBX_EINVAL, "d_pos is NULL");
+  if (!d_out || ((uintptr_t)d_out & 7)) return fail(BBX_EINVAL, "d_out must be 8-byte aligned");
+  if (out_cap < (size_t)kHeaderBytes) return fail(BBX_ENOSPC, "out_cap below the 128-byte header");
+  if (!d_ws || ((uintptr_t)d_ws & 255)) return fail(BBX_EINVAL, "d_ws must be 256-byte aligned");
+  CompressPlan p = make_plan(n, dims, dtype, eb, params, d_perm != nullptr);
+  CompressWs w;
+  memset(&w, 0, sizeof(w));
+  const size_t need = carve_compress(p, (uint8_t*)d_ws, &w);
+  if (ws_size < need) return fail(BBX_ENOMEM, "workspace too small: need " + std::to_string(need));
+
+  hipError_t e = launch_range(p, w, d_pos, stream);
+  int buf = 0;
+  if (e == hipSuccess && n > 0) e = launch_levels(p, w, stream, &buf);
+  int out_buf = buf;
+  if (e == hipSuccess && n > 0) e = launch_leaves(p, w, buf, d_perm, stream, &out_buf);
+  if (e == hipSuccess)
+    e = launch_scan(p.n_leaves, w.leaf_bits, w.scan_part, w.params, &p, 0, out_cap, d_size, stream);
+  if (e == hipSuccess) e = launch_pack(p, w, out_buf, (uint8_t*)d_out, d_size, d_status, stream);
+  if (e != hipSuccess) return fail(BBX_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+  if (h_out_size) {
+    DevParams hp;
+    e = hipMemcpyAsync(&hp, w.params, sizeof(hp), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return fail(BBX_EHIP, std::string("synchronize failed: ") + hipGetErrorString(e));
+    if (hp.status != BBX_OK) {
+      const char* why = hp.status == BBX_EINVAL   ? "non-finite coordinate"
+                        : hp.status == BBX_EBOUND ? "error bound too small for the input type or 30-bit codes"
+                        : hp.status == BBX_ENOSPC ? "out_cap smaller than the stream"
+                                                  : "device error";
+      return fail((bbx_status)hp.status, why);
+    }
+    *h_out_size = (size_t)hp.total_bytes;
+  }
+  return BBX_OK;
+}
+
+bbx_status bbx_stream_info(const void* h_header, size_t header_bytes, uint64_t* n, uint32_t* dims,
+                           bbx_dtype* dtype, double* eb_abs, uint32_t* leaf_size,
+                           uint64_t* n_leaves, uint64_t* stream_bytes) {
+  HostHeader h;
+  bbx_status st = parse_header((const uint8_t*)h_header, header_bytes, &h);
+  if (st != BBX_OK) return st;
+  if (n) *n = h.n;
+  if (dims) *dims = h.dims;
+  if (dtype) *dtype = (bbx_dtype)h.dtype;
+  if (eb_abs) *eb_abs = h.eb_abs;
+  if (leaf_size) *leaf_size = h.r;
+  if (n_leaves) *n_leaves = h.n_leaves;
+  if (stream_bytes) *stream_bytes = stream_bytes_of(h);
+  return BBX_OK;
+}
+
+size_t bbx_decompress_workspace_size(const void* h_header, size_t header_bytes) {
+  HostHeader h;
+  if (parse_header((const uint8_t*)h_header, header_bytes, &h) != BBX_OK) return 0;
+  return carve_decompress(h, nullptr, nullptr);
+}
+
+bbx_status bbx_decompress(const void* d_stream, size_t stream_size, const void* h_header,
+                          void* d_pos, size_t pos_cap, bbx_layout layout, uint32_t* d_status,
+                          void* d_ws, size_t ws_size, hipStream_t stream) {
+  if (layout != BBX_AOS && layout != BBX_SOA) return fail(BBX_EINVAL, "layout must be AOS or SOA");
+  if (!d_stream || ((uintptr_t)d_stream & 7)) return fail(BBX_EINVAL, "d_stream must be 8-byte aligned");
+  if (stream_size < (size_t)kHeaderBytes) return fail(BBX_ECORRUPT, "stream shorter than its header");
+  uint8_t hb[kHeaderBytes];
+  if (!h_header) {
+    hipError_t e = hipMemcpyAsync(hb, d_stream, kHeaderBytes, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return fail(BBX_EHIP, std::string("header copy failed: ") + hipGetErrorString(e));
+    h_header = hb;
+  }
+  HostHeader h;
+  bbx_status st = parse_header((const uint8_t*)h_header, kHeaderBytes, &h);
+  if (st != BBX_OK) return st;
+  if (stream_size < stream_bytes_of(h)) return fail(BBX_ECORRUPT, "stream shorter than its sections");
+  const uint64_t esz = h.dtype == 0 ? 4 : 8;
+  if (pos_cap < h.n * h.dims * esz) return fail(BBX_ENOSPC, "position buffer too small");
+  if (h.n > 0 && (!d_pos || ((uintptr_t)d_pos & (esz - 1)))) return fail(BBX_EINVAL, "d_pos is NULL or misaligned");
+  if (!d_ws || ((uintptr_t)d_ws & 255)) return fail(BBX_EINVAL, "d_ws must be 256-byte aligned");
+  DecompressWs w;
+  memset(&w, 0, sizeof(w));
+  const size_t need = carve_decompress(h, (uint8_t*)d_ws, &w);
+  if (ws_size < need) return fail(BBX_ENOMEM, "workspace too small: need " + std::to_string(need));
+  DecompressPlan p;
+  memset(&p, 0, sizeof(p));
+  p.n = h.n;
+  p.n_leaves = h.n_leaves;
+  p.meta_bits = h.meta_bits;
+  p.payload_bits = h.payload_bits;
+  p.dims = h.dims;
+  p.dtype = h.dtype;
+  p.r = h.r;
+  p.mbits = h.mbits;
+  p.layout = layout;
+  for (int d = 0; d < 3; ++d) p.G[d] = h.G[d], p.origin[d] = h.origin[d];
+  p.w = h.w;
+  if (h.n) p.geom = make_geom(h.n, h.r);
+  hipError_t e = launch_decompress(p, w, (const uint8_t*)d_stream, d_pos, d_status, stream);
+  if (e != hipSuccess) return fail(BBX_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+  if (!d_status) {
+    DevParams hp;
+    e = hipMemcpyAsync(&hp, w.params, sizeof(hp), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return fail(BBX_EHIP, std::string("synchronize failed: ") + hipGetErrorString(e));
+    if (hp.status != BBX_OK) return fail((bbx_status)hp.status, "stream payload fails validation");
+  }
+  return BBX_OK;
+}
+
+const char* bbx_status_str(bbx_status s) {
+  switch (s) {
+    case BBX_OK: return "OK";
+    case BBX_EINVAL: return "EINVAL";
+    case BBX_ENOSPC: return "ENOSPC";
+    case BBX_ECORRUPT: return "ECORRUPT";
+    case BBX_EBOUND: return "EBOUND";
+    case BBX_EUNSUPPORTED: return "EUNSUPPORTED";
+    case BBX_EHIP: return "EHIP";
+    case BBX_ENOMEM: return "ENOMEM";
+  }
+  return "UNKNOWN";
+}
+
+const char* bbx_last_error(void) { return g_err.c_str(); }
+
+void bbx_profile_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_on = on != 0;
+}
+
+void bbx_profile_reset(void) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  prof_drain();
+  g_prof.clear();
+}
+
+int bbx_profile_count(void) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  prof_drain();
+  return (int)g_prof.size();
+}
+
+bbx_status bbx_profile_get(int i, const char** name, uint64_t* launches, double* total_ms) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  prof_drain();
+  if (i < 0 || i >= (int)g_prof.size()) return fail(BBX_EINVAL, "profile index out of range");
+  if (name) *name = g_prof[i].name.c_str();
+  if (launches) *launches = g_prof[i].launches;
+  if (total_ms) *total_ms = g_prof[i].ms;
+  return BBX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,205 @@
+// k_unpack.hip -- unpack and dequantize (Sec. 3: reconstruction at the bin
+// centre origin + q*w, FP64 multiply then add, then rounding to the type).
+//
+//   k_dec_meta   one thread per leaf: reads its fixed-stride meta record,
+//                validates the widths, and derives its span from (n, r) alone
+//                (the tree's leaf sizes depend on n and r only)
+//   (scan)       payload bit offset of every leaf, total checked against the
+//                header
+//   k_unpack     blocks of 1024 output slots: the block finds the leaves that
+//                cover its slots, every thread decodes slots
+//                (reference -> its code; member j -> payload code j-1)
+#include "bbx_internal.h"
+
+namespace bbx {
+
+typedef unsigned __int128 u128;
+
+__device__ inline u128 read_bits(const uint64_t* sec, uint64_t nwords, uint64_t at, uint32_t len) {
+  if (len == 0) return 0;
+  const uint64_t w0 = at >> 6;
+  const uint32_t s = (uint32_t)(at & 63);
+  u128 v = (u128)sec[w0];
+  if (w0 + 1 < nwords) v |= (u128)sec[w0 + 1] << 64;
+  v >>= s;
+  if (s + len > 128 && w0 + 2 < nwords) v |= (u128)sec[w0 + 2] << (128 - s);
+  if (len < 128) v &= (((u128)1) << len) - 1;
+  return v;
+}
+
+__global__ void __launch_bounds__(kBlock) k_dec_meta(uint64_t n_leaves, uint32_t dims,
+                                                     uint32_t mbits, uint32_t G0, uint32_t G1,
+                                                     uint32_t G2, uint64_t meta_bits, TreeGeom g,
+                                                     const uint8_t* stream, LeafRec* leaves,
+                                                     uint64_t* bits, DevParams* P) {
+  const uint32_t G[3] = {G0, G1, G2};
+  uint32_t S = dims * mbits;
+  for (uint32_t d = 0; d < dims; ++d) S += G[d];
+  const uint64_t* meta = (const uint64_t*)(stream + kHeaderBytes);
+  const uint64_t nwords = (meta_bits + 63) / 64;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_leaves;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    u128 v = read_bits(meta, nwords, i * S, S);
+    LeafRec rec;
+    uint32_t m = 0, summ = 0;
+    bool bad = false;
+    for (uint32_t d = 0; d < dims; ++d) {
+      uint32_t md = (uint32_t)(v & ((1u << mbits) - 1));
+      v >>= mbits;
+      if (md == 1 || md > 31 || md > G[d] + 1) bad = true;
+      m |= md << (8 * d);
+      summ += md;
+    }
+    for (uint32_t d = 0; d < 3; ++d) {
+      rec.qref[d] = 0;
+      if (d < dims) {
+        rec.qref[d] = (uint32_t)(v & ((((u128)1) << G[d]) - 1));
+        v >>= G[d];
+      }
+    }
+    uint64_t st, sz;
+    leaf_span(g, i, &st, &sz);
+    rec.start = (uint32_t)st;
+    rec.size = (uint32_t)sz;
+    rec.m = m;
+    leaves[i] = rec;
+    bits[i] = bad ? 0 : (sz - 1) * (uint64_t)summ;
+    if (bad) P->status = BBX_ECORRUPT;
+  }
+}
+
+template <typename T>
+__device__ void unpack_body(uint64_t n, uint32_t dims, uint32_t layout, TreeGeom g, double w,
+                            const double* origin, const uint32_t* G, uint64_t n_leaves,
+                            const LeafRec* leaves, const uint64_t* off, const uint64_t* pay,
+                            uint64_t pay_words, T* out, DevParams* P, uint32_t* s_start) {
+  __shared__ uint64_t s_i0;
+  __shared__ uint32_t s_cnt;
+  const uint64_t S0 = (uint64_t)blockIdx.x * 1024;
+  if (threadIdx.x == 0) {
+    // descend to the leaf holding slot S0
+    uint64_t s = g.n, st = 0, base = 0;
+    uint32_t k = 0;
+    while (s > g.r) {
+      uint64_t sl = s >> 1;
+      if (S0 < st + sl) {
+        s = sl;
+      } else {
+        base += geom_L(g, k + 1, sl);
+        st += sl;
+        s -= sl;
+      }
+      ++k;
+    }
+    s_i0 = base;
+  }
+  __syncthreads();
+  const uint64_t i0 = s_i0;
+  const uint64_t Send = S0 + 1024 < n ? S0 + 1024 : n;
+  // leaves overlapping [S0, Send): at most 1024
+  for (uint32_t t = threadIdx.x; t < 1024; t += kBlock) {
+    uint64_t i = i0 + t;
+    s_start[t] = i < n_leaves ? leaves[i].start : 0xffffffffu;
+  }
+  __syncthreads();
+  bool corrupt = false;
+  for (uint32_t k = 0; k < 1024 / kBlock; ++k) {
+    const uint64_t p = S0 + k * kBlock + threadIdx.x;
+    if (p >= Send) break;
+    uint32_t a = 0, z = 1023;
+    while (a < z) {
+      uint32_t mid = (a + z + 1) >> 1;
+      if (s_start[mid] <= p)
+        a = mid;
+      else
+        z = mid - 1;
+    }
+    const uint64_t i = i0 + a;
+    const LeafRec rec = leaves[i];
+    const uint64_t j = p - rec.start;
+    int64_t q[3] = {rec.qref[0], rec.qref[1], rec.qref[2]};
+    if (j > 0) {
+      uint32_t summ = 0;
+      for (uint32_t d = 0; d < dims; ++d) summ += (rec.m >> (8 * d)) & 0xffu;
+      u128 v = read_bits(pay, pay_words, off[i] + (j - 1) * summ, summ);
+      for (uint32_t d = 0; d < dims; ++d) {
+        const uint32_t m = (rec.m >> (8 * d)) & 0xffu;
+        if (m == 0) continue;
+        const uint64_t u = (uint64_t)(v & ((((u128)1) << m) - 1));
+        v >>= m;
+        if (u == 0) corrupt = true;
+        q[d] = (int64_t)rec.qref[d] + (int64_t)u - ((int64_t)1 << (m - 1));
+      }
+    }
+    for (uint32_t d = 0; d < dims; ++d) {
+      if (q[d] < 0 || q[d] >= ((int64_t)1 << G[d])) {
+        corrupt = true;
+        q[d] = 0;
+      }
+      const double x = origin[d] + (double)q[d] * w;
+      const T t = (T)x;
+      if (layout == BBX_AOS)
+        out[p * dims + d] = t;
+      else
+        out[(uint64_t)d * n + p] = t;
+    }
+  }
+  if (corrupt) P->status = BBX_ECORRUPT;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_unpack(uint64_t n, uint32_t dims, uint32_t layout,
+                                                   TreeGeom g, double w, double o0, double o1,
+                                                   double o2, uint32_t G0, uint32_t G1,
+                                                   uint32_t G2, uint64_t n_leaves,
+                                                   uint64_t meta_bits, const LeafRec* leaves,
+                                                   const uint64_t* off, const uint8_t* stream,
+                                                   uint64_t pay_bits, T* out, DevParams* P) {
+  if (P->status != BBX_OK) return;
+  __shared__ uint32_t s_start[1024];
+  const double origin[3] = {o0, o1, o2};
+  const uint32_t G[3] = {G0, G1, G2};
+  const uint64_t* pay = (const uint64_t*)(stream + kHeaderBytes + ((meta_bits + 63) / 64) * 8);
+  unpack_body<T>(n, dims, layout, g, w, origin, G, n_leaves, leaves, off, pay, (pay_bits + 63) / 64,
+                 out, P, s_start);
+}
+
+__global__ void k_dec_init(DevParams* P) {
+  if (threadIdx.x == 0) {
+    P->status = BBX_OK;
+    P->payload_bits = 0;
+  }
+}
+
+__global__ void k_dec_finish(const DevParams* P, uint32_t* d_status) {
+  if (threadIdx.x == 0 && d_status) *d_status = P->status;
+}
+
+hipError_t launch_decompress(const DecompressPlan& p, const DecompressWs& w, const uint8_t* stream,
+                             void* pos, uint32_t* d_status, hipStream_t s) {
+  BBX_LAUNCH("dec_init", k_dec_init, 1, 64, 0, s, w.params);
+  if (p.n > 0) {
+    uint64_t g = (p.n_leaves + kBlock - 1) / kBlock;
+    if (g > 65536) g = 65536;
+    BBX_LAUNCH("dec_meta", k_dec_meta, g, kBlock, 0, s, p.n_leaves, p.dims, p.mbits, p.G[0],
+               p.G[1], p.G[2], p.meta_bits, p.geom, stream, w.leaves, w.leaf_bits, w.params);
+    hipError_t e = launch_scan(p.n_leaves, w.leaf_bits, w.scan_part, w.params, nullptr,
+                               p.payload_bits, 0, nullptr, s);
+    if (e != hipSuccess) return e;
+    const uint64_t blocks = (p.n + 1023) / 1024;
+    if (p.dtype == BBX_F32)
+      BBX_LAUNCH("unpack", k_unpack<float>, blocks, kBlock, 0, s, p.n, p.dims, p.layout, p.geom,
+                 p.w, p.origin[0], p.origin[1], p.origin[2], p.G[0], p.G[1], p.G[2], p.n_leaves,
+                 p.meta_bits, w.leaves, w.leaf_bits, stream, p.payload_bits, (float*)pos,
+                 w.params);
+    else
+      BBX_LAUNCH("unpack", k_unpack<double>, blocks, kBlock, 0, s, p.n, p.dims, p.layout, p.geom,
+                 p.w, p.origin[0], p.origin[1], p.origin[2], p.G[0], p.G[1], p.G[2], p.n_leaves,
+                 p.meta_bits, w.leaves, w.leaf_bits, stream, p.payload_bits, (double*)pos,
+                 w.params);
+  }
+  BBX_LAUNCH("dec_finish", k_dec_finish, 1, 64, 0, s, w.params, d_status);
+  return hipGetLastError();
+}
+
+}  // namespace bbx

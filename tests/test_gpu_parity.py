@@ -1,0 +1,205 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Streams must be byte-identical, the perm outputs equal, and decompressed
+positions bit-identical, on seeded inputs that span several tiles and
+global levels with ragged tails, both key widths (u16/u32 codes), 2-D and
+3-D, FP32 and FP64, both layouts, both bound modes, and leaf capacities
+below and above the tile capacity.  Full-size workloads are checked by
+properties that hold at any size plus sampled leaves.
+"""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+import props
+from oracle import Oracle, OracleError
+from synth import cosmology, fluid, fluid_lattice_dims, uniform_cube
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def bbx():
+    import paper_2404_02826_amd as b
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    b.load()
+    return b
+
+
+@pytest.fixture(scope="module")
+def orc():
+    return Oracle()
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gen(kind, n, dims=3, dtype=np.float32, seed=1):
+    if kind == "uniform":
+        return uniform_cube(n, seed=seed, dims=dims, dtype=dtype)
+    if kind == "cosmology":
+        return cosmology(n, seed=seed, dims=dims, dtype=dtype)
+    if kind == "fluid":
+        return fluid(*fluid_lattice_dims(n), seed=seed, dtype=dtype)
+    if kind == "ties":  # heavy duplication: many equal codes at every median
+        rng = np.random.default_rng(seed)
+        return (np.floor(rng.random((n, dims)) * 5) / 5).astype(dtype)
+    raise ValueError(kind)
+
+
+def gpu_roundtrip(bbx, pts, eb, mode, r, layout="aos", tile=0):
+    host = pts if layout == "aos" else np.ascontiguousarray(pts.T)
+    x = torch.from_numpy(host).cuda()
+    s, perm = bbx.compress(x, eb, mode, r, layout, want_perm=True, tile=tile)
+    dec = bbx.decompress(s, layout)
+    torch.cuda.synchronize()
+    return s.cpu().numpy().tobytes(), perm.cpu().numpy().astype(np.uint32), dec.cpu().numpy()
+
+
+def first_diff(a: bytes, b: bytes):
+    for i in range(min(len(a), len(b))):
+        if a[i] != b[i]:
+            return i
+    return min(len(a), len(b))
+
+
+def check_parity(orc, bbx, pts, eb, mode, r, layout="aos", tile=0):
+    host = pts if layout == "aos" else np.ascontiguousarray(pts.T)
+    ref_s, ref_p = orc.compress(host, eb, mode, r, layout=layout, want_perm=True)
+    got_s, got_p, got_d = gpu_roundtrip(bbx, pts, eb, mode, r, layout, tile)
+    if got_s != ref_s:
+        h = props.parse_header(ref_s)
+        mb = 8 * ((h["meta_bits"] + 63) // 64)
+        i = first_diff(got_s, ref_s)
+        where = "header" if i < 128 else ("meta" if i < 128 + mb else "payload")
+        raise AssertionError(f"stream differs at byte {i} ({where}); sizes {len(got_s)} vs {len(ref_s)}")
+    assert np.array_equal(got_p, ref_p), "perm differs"
+    ref_d = orc.decompress(ref_s, layout)
+    assert np.array_equal(got_d, ref_d), "decompressed positions differ"
+    return ref_s
+
+
+# (generator, n, dims, dtype, eb, mode, r)
+CASES = [
+    ("uniform", 1, 3, np.float32, 1e-3, "rel", 32),
+    ("uniform", 2, 3, np.float32, 1e-3, "rel", 1),
+    ("uniform", 3, 2, np.float32, 1e-3, "rel", 1),
+    ("uniform", 33, 3, np.float32, 1e-3, "rel", 32),
+    ("ties", 1000, 3, np.float32, 1e-3, "rel", 7),
+    ("cosmology", 2047, 3, np.float32, 1e-4, "rel", 32),
+    ("cosmology", 2048, 3, np.float32, 1e-4, "rel", 32),
+    ("cosmology", 2049, 3, np.float32, 1e-4, "rel", 32),
+    ("uniform", 4097, 2, np.float32, 1e-3, "rel", 5),
+    ("ties", 20000, 3, np.float32, 1e-2, "rel", 32),
+    ("cosmology", 20011, 3, np.float64, 1e-6, "rel", 33),     # u32 codes
+    ("uniform", 65536, 3, np.float32, 1e-3, "rel", 32),       # the plain single-set workload
+    ("cosmology", 65536, 3, np.float32, 1e-4, "rel", 32),
+    ("fluid", 32768, 3, np.float32, 1e-4, "rel", 32),
+    ("cosmology", 100003, 3, np.float32, 1e-3, "rel", 1),
+    ("cosmology", 100003, 2, np.float32, 1e-4, "rel", 100),
+    ("uniform", 100003, 3, np.float64, 1e-5, "abs", 16),
+    ("cosmology", 300007, 3, np.float32, 1e-4, "rel", 32),
+    ("ties", 300007, 3, np.float32, 1e-3, "rel", 32),
+    ("cosmology", 150001, 3, np.float32, 1e-7, "rel", 32),    # G > 16 on float32: u32 codes
+    ("cosmology", 5000, 3, np.float32, 1e-3, "rel", 2048),    # leaves >= tile capacity
+    ("cosmology", 60000, 3, np.float32, 1e-4, "rel", 3000),
+    ("cosmology", 60000, 3, np.float32, 1e-4, "rel", 60000),  # single leaf
+    ("uniform", 10000, 3, np.float32, 1e-3, "rel", 4999),     # leaves of r+1 split once more
+    ("ties", 50000, 2, np.float64, 1e-3, "rel", 2100),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}-n{c[1]}-d{c[2]}-{np.dtype(c[3]).name}-{c[4]}-{c[5]}-r{c[6]}")
+def test_parity(orc, bbx, case):
+    kind, n, dims, dt, eb, mode, r = case
+    _say("case", case)
+    pts = gen(kind, n, dims, dt, seed=n % 97 + 1)
+    check_parity(orc, bbx, pts, eb, mode, r)
+
+
+@pytest.mark.parametrize("layout", ["aos", "soa"])
+@pytest.mark.parametrize("tile", [1024, 2048])
+def test_layout_and_tile_invariance(orc, bbx, layout, tile):
+    """Tile capacity never changes the bytes; SoA input gives the same stream."""
+    _say("layout", layout, "tile", tile)
+    pts = cosmology(70001, seed=5)
+    check_parity(orc, bbx, pts, 1e-4, "rel", 32, layout=layout, tile=tile)
+
+
+def test_empty(orc, bbx):
+    pts = np.zeros((0, 3), dtype=np.float32)
+    ref = orc.compress(pts, 1e-3, "rel", 32)
+    x = torch.zeros((0, 3), dtype=torch.float32, device="cuda")
+    s = bbx.compress(x, 1e-3, "rel", 32)
+    assert s.cpu().numpy().tobytes() == ref
+    assert bbx.decompress(s).shape == (0, 3)
+
+
+def test_identical_points(orc, bbx):
+    pts = np.full((5000, 3), 7.5, dtype=np.float32)
+    check_parity(orc, bbx, pts, 1e-4, "rel", 32)
+
+
+def test_determinism(bbx):
+    pts = cosmology(200003, seed=9)
+    x = torch.from_numpy(pts).cuda()
+    outs = [bbx.compress(x, 1e-4, "rel", 32).cpu().numpy().tobytes() for _ in range(3)]
+    assert outs[0] == outs[1] == outs[2]
+
+
+def test_errors(bbx):
+    pts = uniform_cube(5000, seed=3)
+    bad = pts.copy()
+    bad[17, 2] = np.nan
+    for arr, eb, want in ((bad, 1e-3, "EINVAL"), (pts, 1e-12, "EBOUND")):
+        with pytest.raises(bbx.BitboxError) as e:
+            bbx.compress(torch.from_numpy(arr).cuda(), eb)
+        assert e.value.name == want
+    with pytest.raises(bbx.BitboxError) as e:
+        bbx.compress(torch.zeros((10, 4), device="cuda"), 1e-3)
+    assert e.value.name == "EUNSUPPORTED"
+    # out_cap too small: use the raw Compressor with a shrunken capacity
+    c = bbx.Compressor(5000)
+    c.cap = 256
+    with pytest.raises(bbx.BitboxError) as e:
+        c(torch.from_numpy(pts).cuda(), 1e-3)
+    assert e.value.name == "ENOSPC"
+
+
+def test_corrupt_payload_detected_on_device(orc, bbx):
+    pts = cosmology(20000, seed=10)
+    good = orc.compress(pts, 1e-3, "rel", 32)
+    h = props.parse_header(good)
+    mb = 8 * ((h["meta_bits"] + 63) // 64)
+    b = bytearray(good)
+    mx = int.from_bytes(b[128:136], "little") & 31
+    word = int.from_bytes(b[128 + mb:128 + mb + 8], "little") & ~((1 << mx) - 1)
+    b[128 + mb:128 + mb + 8] = word.to_bytes(8, "little")  # first member's x code -> 0
+    t = torch.from_numpy(np.frombuffer(bytes(b), dtype=np.uint8).copy()).cuda()
+    with pytest.raises(bbx.BitboxError) as e:
+        bbx.decompress(t)
+    assert e.value.name == "ECORRUPT"
+    with pytest.raises(OracleError):
+        orc.decompress(bytes(b))
+
+
+def test_decompress_oracle_streams(orc, bbx):
+    """The GPU decoder reproduces the oracle's decoder on oracle-written streams."""
+    for r in (1, 32, 3000):
+        pts = cosmology(30001, seed=r)
+        s = orc.compress(pts, 1e-4, "rel", r)
+        t = torch.from_numpy(np.frombuffer(s, dtype=np.uint8).copy()).cuda()
+        assert np.array_equal(bbx.decompress(t).cpu().numpy(), orc.decompress(s))
+
+
+def test_full_size_cosmology_1_in_4_oracle(orc, bbx):
+    """A quarter of the cosmology workload (2^22 particles, xi = 1e-4), full
+    byte parity with the oracle."""
+    pts = cosmology(1 << 22, seed=2)
+    check_parity(orc, bbx, pts, 1e-4, "rel", 32)
