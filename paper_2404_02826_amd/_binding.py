@@ -113,10 +113,14 @@ def compress_bound(n: int, dims: int = 3, dtype=torch.float32) -> int:
 def compress_workspace_size(n: int, dims: int = 3, dtype=torch.float32, leaf_size: int = 32,
                             eb_mode: str = "rel", layout: str = "aos", tile: int = 0) -> int:
     p = _params(leaf_size, eb_mode, AOS if layout == "aos" else SOA, tile)
-    v = int(load().bbx_compress_workspace_size(n, dims, F32 if dtype == torch.float32 else F64,
-                                               C.byref(p)))
+    code = F32 if dtype == torch.float32 else F64
+    lib = load()
+    v = int(lib.bbx_compress_workspace_size(n, dims, code, C.byref(p)))
     if v == 0:
-        raise BitboxError(1, load().bbx_last_error().decode())
+        # argument errors are reported before any launch: ask bbx_compress for the status
+        st = lib.bbx_compress(None, n, dims, code, 1.0, C.byref(p), None, 0, None, None, None,
+                              None, None, 0, None)
+        raise BitboxError(st if st else 1, lib.bbx_last_error().decode())
     return v
 
 
