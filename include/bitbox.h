@@ -81,7 +81,7 @@ typedef struct {
   uint32_t leaf_size;     /* r >= 1 */
   uint32_t eb_mode;       /* bbx_eb_mode */
   uint32_t layout;        /* bbx_layout of the input positions */
-  uint32_t tile_override; /* 0, or one of 1024, 2048 */
+  uint32_t tile_override; /* 0 (= 512), 256 or 512 */
 } bbx_params;
 
 /* Worst-case stream size in bytes for n particles of the given type. */
@@ -113,6 +113,49 @@ bbx_status bbx_compress(const void* d_pos, uint64_t n, uint32_t dims, bbx_dtype 
                         const bbx_params* params, void* d_out, size_t out_cap,
                         size_t* h_out_size, uint64_t* d_size, uint32_t* d_status,
                         uint32_t* d_perm, void* d_ws, size_t ws_size, hipStream_t stream);
+
+/*
+ * Batched compression: many independent particle sets in one launch sequence
+ * (every set is compressed exactly as bbx_compress would compress it alone,
+ * byte for byte).  Each set carries its own positions, size, type, bound,
+ * leaf size, layout and output; all sets of one batch share tile_override.
+ */
+typedef struct {
+  const void* d_pos;  /* device positions of this set */
+  uint64_t n;
+  uint32_t dims;
+  uint32_t dtype;     /* bbx_dtype */
+  double eb;
+  bbx_params params;
+  void* d_out;        /* device, out_cap bytes, 8-byte aligned */
+  size_t out_cap;
+  uint64_t* d_size;   /* device u64 (optional): stream length or UINT64_MAX */
+  uint32_t* d_status; /* device u32 (optional): bbx_status of this set */
+  uint32_t* d_perm;   /* device u32[n] (optional): source index per output slot */
+} bbx_set;
+
+/* Device workspace bytes for a batch (0 on invalid arguments). */
+size_t bbx_batch_workspace_size(const bbx_set* sets, uint32_t nsets);
+
+/*
+ * Two-part form for callers that record the launch once and replay it (HIP
+ * graph capture): bbx_batch_upload copies the batch's descriptors and launch
+ * tables from host memory into the workspace (one host-to-device copy on
+ * `stream`; the call returns once the host data has been consumed);
+ * bbx_batch_launch enqueues the kernels only (no allocation, copy or
+ * synchronization), reading those descriptors.  A replay of recorded
+ * launches is valid while the same workspace holds the same upload.
+ * Errors of a single set (NaN/Inf, bound, capacity) go to its d_status /
+ * d_size and do not affect the other sets.
+ */
+bbx_status bbx_batch_upload(const bbx_set* sets, uint32_t nsets, void* d_ws, size_t ws_size,
+                            hipStream_t stream);
+bbx_status bbx_batch_launch(const bbx_set* sets, uint32_t nsets, void* d_ws, size_t ws_size,
+                            hipStream_t stream);
+
+/* bbx_batch_upload followed by bbx_batch_launch; never waits. */
+bbx_status bbx_compress_batch(const bbx_set* sets, uint32_t nsets, void* d_ws, size_t ws_size,
+                              hipStream_t stream);
 
 /* Parses and validates a stream header (host copy of its first 128 bytes). */
 bbx_status bbx_stream_info(const void* h_header, size_t header_bytes, uint64_t* n,

@@ -10,6 +10,7 @@ library is missing, every call raises.
 from __future__ import annotations
 
 from ._binding import (  # noqa: F401
+    BatchCompressor,
     BitboxError,
     Compressor,
     Decompressor,

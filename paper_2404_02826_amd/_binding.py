@@ -31,6 +31,13 @@ class _Params(C.Structure):
                 ("tile_override", C.c_uint32)]
 
 
+class _Set(C.Structure):
+    _fields_ = [("d_pos", C.c_void_p), ("n", C.c_uint64), ("dims", C.c_uint32),
+                ("dtype", C.c_uint32), ("eb", C.c_double), ("params", _Params),
+                ("d_out", C.c_void_p), ("out_cap", C.c_size_t), ("d_size", C.c_void_p),
+                ("d_status", C.c_void_p), ("d_perm", C.c_void_p)]
+
+
 def lib_path() -> str:
     return _LIB_PATH
 
@@ -51,6 +58,12 @@ def load():
     lib.bbx_compress.restype = i32
     lib.bbx_compress.argtypes = [vp, u64, u32, i32, dbl, C.POINTER(_Params), vp, sz,
                                  C.POINTER(sz), vp, vp, vp, vp, sz, vp]
+    lib.bbx_batch_workspace_size.restype = sz
+    lib.bbx_batch_workspace_size.argtypes = [C.POINTER(_Set), u32]
+    for nm in ("bbx_batch_upload", "bbx_batch_launch", "bbx_compress_batch"):
+        f = getattr(lib, nm)
+        f.restype = i32
+        f.argtypes = [C.POINTER(_Set), u32, vp, sz, vp]
     lib.bbx_stream_info.restype = i32
     lib.bbx_stream_info.argtypes = [vp, sz, C.POINTER(u64), C.POINTER(u32), C.POINTER(i32),
                                     C.POINTER(dbl), C.POINTER(u32), C.POINTER(u64), C.POINTER(u64)]
@@ -200,6 +213,93 @@ class Decompressor:
     def __call__(self, stream_t: torch.Tensor, stream=None):
         _check(self._call(stream_t, None, stream))
         return self.pos
+
+
+class BatchCompressor:
+    """Compresses many independent particle sets with one launch sequence.
+
+    ``sets`` is a list of dicts with keys ``pos`` (contiguous device tensor),
+    ``eb`` and optionally ``eb_mode``, ``leaf_size``, ``layout``,
+    ``want_perm``, ``out_cap``.  The outputs of all sets live in one device buffer
+    (set i at byte ``offsets[i]``, capacity ``caps[i]``); ``d_size`` and
+    ``d_status`` hold one entry per set.  ``upload`` copies the descriptors
+    into the workspace, ``launch`` enqueues the kernels only (so it can be
+    recorded in a HIP graph and replayed while the upload stays valid).
+    """
+
+    def __init__(self, sets, tile: int = 0, device="cuda"):
+        lib = load()
+        self._lib = lib
+        self.nsets = len(sets)
+        self.tile = tile
+        arr = (_Set * max(self.nsets, 1))()
+        caps, offs, perms, total = [], [], [], 0
+        for spec in sets:
+            pos = spec["pos"]
+            layout = spec.get("layout", "aos")
+            n, dims, _ = _shape(pos, layout)
+            cap = (compress_bound(n, dims, pos.dtype) + 7) // 8 * 8
+            if "out_cap" in spec:  # a smaller capacity, reported per set as ENOSPC
+                cap = int(spec["out_cap"])
+            caps.append(cap)
+            offs.append(total)
+            total += (cap + 7) // 8 * 8
+        self.out = torch.empty(max(total, 8), dtype=torch.uint8, device=device)
+        self.d_size = torch.zeros(max(self.nsets, 1), dtype=torch.int64, device=device)
+        self.d_status = torch.zeros(max(self.nsets, 1), dtype=torch.int32, device=device)
+        self.offsets, self.caps, self.perms, self.inputs = offs, caps, [], []
+        base = self.out.data_ptr()
+        for i, spec in enumerate(sets):
+            pos = spec["pos"]
+            layout = spec.get("layout", "aos")
+            if not pos.is_cuda or not pos.is_contiguous():
+                raise ValueError("positions must be contiguous device tensors")
+            n, dims, lay = _shape(pos, layout)
+            perm = (torch.empty(max(n, 1), dtype=torch.int32, device=device)
+                    if spec.get("want_perm") else None)
+            self.perms.append(perm)
+            self.inputs.append(pos)
+            S = arr[i]
+            S.d_pos = pos.data_ptr() if n else None
+            S.n, S.dims, S.dtype, S.eb = n, dims, _dtype_code(pos), float(spec["eb"])
+            S.params = _params(spec.get("leaf_size", 32), spec.get("eb_mode", "rel"), lay, tile)
+            S.d_out = base + offs[i]
+            S.out_cap = caps[i]
+            S.d_size = self.d_size.data_ptr() + 8 * i
+            S.d_status = self.d_status.data_ptr() + 4 * i
+            S.d_perm = perm.data_ptr() if perm is not None else None
+        self._arr = arr
+        self.ws_size = int(lib.bbx_batch_workspace_size(arr, self.nsets))
+        if self.ws_size == 0:
+            _check(lib.bbx_batch_upload(arr, self.nsets, None, 0, None) or 1)
+        self.ws = torch.empty(self.ws_size, dtype=torch.uint8, device=device)
+
+    def upload(self, stream=None):
+        _check(self._lib.bbx_batch_upload(self._arr, self.nsets, self.ws.data_ptr(), self.ws_size,
+                                          _stream_ptr(stream)))
+
+    def launch(self, stream=None):
+        _check(self._lib.bbx_batch_launch(self._arr, self.nsets, self.ws.data_ptr(), self.ws_size,
+                                          _stream_ptr(stream)))
+
+    def results(self):
+        """Waits for the stream's work and returns, per set, the stream bytes
+        (uint8 device view) or a BitboxError."""
+        torch.cuda.synchronize()
+        sizes = self.d_size.cpu().tolist()
+        stats = self.d_status.cpu().tolist()
+        res = []
+        for i in range(self.nsets):
+            if stats[i] != 0:
+                res.append(BitboxError(stats[i], f"set {i}"))
+            else:
+                res.append(self.out[self.offsets[i]: self.offsets[i] + sizes[i]])
+        return res
+
+    def __call__(self, stream=None):
+        self.upload(stream)
+        self.launch(stream)
+        return self.results()
 
 
 def stream_info(header: bytes) -> dict:

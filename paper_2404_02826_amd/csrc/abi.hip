@@ -4,6 +4,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -106,6 +107,21 @@ TreeGeom make_geom(uint64_t n, uint32_t r) {
 
 static size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
+// One set of a compress request, as the ABI receives it.
+struct SetIn {
+  const void* pos;
+  uint64_t n;
+  uint32_t dims;
+  bbx_dtype dtype;
+  double eb;
+  bbx_params prm;
+  void* out;
+  size_t out_cap;
+  uint64_t* d_size;
+  uint32_t* d_status;
+  uint32_t* d_perm;
+};
+
 static bbx_status check_compress_args(uint64_t n, uint32_t dims, bbx_dtype dtype, double eb,
                                       const bbx_params* prm) {
   if (!prm) return fail(BBX_EINVAL, "params is NULL");
@@ -114,51 +130,27 @@ static bbx_status check_compress_args(uint64_t n, uint32_t dims, bbx_dtype dtype
   if (prm->eb_mode != BBX_EB_REL && prm->eb_mode != BBX_EB_ABS) return fail(BBX_EINVAL, "eb_mode must be REL or ABS");
   if (prm->leaf_size == 0) return fail(BBX_EINVAL, "leaf_size must be >= 1");
   if (!isfinite(eb) || !(eb > 0.0)) return fail(BBX_EINVAL, "eb must be finite and > 0");
-  if (prm->tile_override != 0 && prm->tile_override != 1024 && prm->tile_override != 2048)
-    return fail(BBX_EINVAL, "tile_override must be 0, 1024 or 2048");
+  if (prm->tile_override != 0 && prm->tile_override != 256 && prm->tile_override != 512)
+    return fail(BBX_EINVAL, "tile_override must be 0, 256 or 512");
   if (dims != 2 && dims != 3) return fail(BBX_EUNSUPPORTED, "dims must be 2 or 3");
   if (n >= (1ull << 32)) return fail(BBX_EUNSUPPORTED, "n must be below 2^32");
   return BBX_OK;
 }
 
-static CompressPlan make_plan(uint64_t n, uint32_t dims, bbx_dtype dtype, double eb,
-                              const bbx_params* prm, bool track) {
-  CompressPlan p;
-  memset(&p, 0, sizeof(p));
-  p.n = n;
-  p.dims = dims;
-  p.dtype = (uint32_t)dtype;
-  p.layout = prm->layout;
-  p.r = prm->leaf_size;
-  p.eb_mode = prm->eb_mode;
-  p.eb = eb;
-  p.track_idx = track ? 1u : 0u;
-  p.tile = prm->tile_override ? prm->tile_override : 2048;
-  p.mbits = dtype == BBX_F32 ? 5u : 6u;
-  if (n == 0) return p;
-  p.geom = make_geom(n, p.r);
-  p.n_leaves = p.geom.L[0][0];
-  if (p.r < p.tile) {
-    p.tile_mode = 1;
-    uint32_t K = 0;
-    while (((n + (1ull << K) - 1) >> K) > p.tile) ++K;
-    p.global_levels = K;
-  } else {
-    p.tile_mode = 0;
-    uint32_t K = 0;
-    while ((n >> K) > p.r) ++K;
-    const uint64_t hi = (n + (1ull << K) - 1) >> K;
-    p.global_levels = hi <= p.r ? K : K + 1;
-  }
-  p.max_nodes = 0;
-  p.max_blocks = 0;
-  for (uint32_t k = 0; k < p.global_levels; ++k) {
-    LevelShape sh = level_shape(p, k);
-    if (sh.nodes > p.max_nodes) p.max_nodes = sh.nodes;
-    if (sh.nodes * sh.chunks > p.max_blocks) p.max_blocks = sh.nodes * sh.chunks;
-  }
-  return p;
+static bbx_status check_set(const SetIn& in) {
+  bbx_status st = check_compress_args(in.n, in.dims, in.dtype, in.eb, &in.prm);
+  if (st != BBX_OK) return st;
+  if (in.n > 0 && !in.pos) return fail(BBX_EINVAL, "positions pointer is NULL");
+  if (!in.out || ((uintptr_t)in.out & 7)) return fail(BBX_EINVAL, "output must be 8-byte aligned");
+  if (in.out_cap < (size_t)kHeaderBytes) return fail(BBX_ENOSPC, "output capacity below the 128-byte header");
+  return BBX_OK;
 }
+
+// Byte offsets of the batch workspace regions.
+struct WsLayout {
+  size_t params, sets, pre, partials, keys[2], idx[2], hist, sel, rows, cb, leaves, bits, spart,
+      stotal, total;
+};
 
 struct Carve {
   size_t off = 0;
@@ -169,36 +161,206 @@ struct Carve {
   }
 };
 
-static size_t carve_compress(const CompressPlan& p, uint8_t* base, CompressWs* w) {
-  Carve c;
-  const size_t o_params = c.take(sizeof(DevParams));
-  const size_t o_part = c.take(sizeof(double) * 8 * kMinMaxBlocks);
-  const size_t kb = (size_t)p.dims * p.n * 4;
-  const size_t o_k0 = c.take(kb), o_k1 = c.take(kb);
-  const size_t o_i0 = c.take(p.n * 4), o_i1 = c.take(p.n * 4);
-  const size_t o_hist = c.take(p.max_nodes * kHistStride * 4);
-  const size_t o_sel = c.take(p.max_nodes * sizeof(NodeSel));
-  const size_t o_rows = c.take(p.max_blocks * kRowStride * 4);
-  const size_t o_cb = c.take(p.max_blocks * 8);
-  const size_t o_leaves = c.take(p.n_leaves * sizeof(LeafRec));
-  const size_t o_bits = c.take(p.n_leaves * 8);
-  const size_t o_sp = c.take((scan_blocks(p.n_leaves) + 1) * 8);
-  if (w && base) {
-    w->params = (DevParams*)(base + o_params);
-    w->partials = (double*)(base + o_part);
-    w->keys[0] = base + o_k0;
-    w->keys[1] = base + o_k1;
-    w->idx[0] = (uint32_t*)(base + o_i0);
-    w->idx[1] = (uint32_t*)(base + o_i1);
-    w->hist = (uint32_t*)(base + o_hist);
-    w->sel = (NodeSel*)(base + o_sel);
-    w->rows = (uint32_t*)(base + o_rows);
-    w->chunk_base = (uint32_t*)(base + o_cb);
-    w->leaves = (LeafRec*)(base + o_leaves);
-    w->leaf_bits = (uint64_t*)(base + o_bits);
-    w->scan_part = (uint64_t*)(base + o_sp);
+// Builds the per-set descriptors (without caller pointers when `in` lacks
+// them), the launch plan and the workspace layout of a batch.
+static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vector<SetDesc>* descs,
+                       std::vector<uint64_t>* pre, WsLayout* lay) {
+  memset(bp, 0, sizeof(*bp));
+  bp->nsets = nsets;
+  bp->tile = in[0].prm.tile_override ? in[0].prm.tile_override : 512;
+  descs->assign(nsets, SetDesc());
+  uint64_t key_bytes = 0, idx_n = 0, hist_n = 0, sel_n = 0, rows_n = 0, leaves_n = 0, parts = 0;
+  std::vector<uint64_t> mm(nsets), qz(nsets), tl(nsets), bg(nsets), pm(nsets), pp(nsets);
+  std::vector<std::vector<uint64_t>> lv(nsets), nd(nsets);
+  for (uint32_t s = 0; s < nsets; ++s) {
+    const SetIn& I = in[s];
+    SetDesc& D = (*descs)[s];
+    memset(&D, 0, sizeof(D));
+    D.pos = I.pos;
+    D.out = (uint8_t*)I.out;
+    D.perm = I.d_perm;
+    D.d_size = I.d_size;
+    D.d_status = I.d_status;
+    D.n = I.n;
+    D.out_cap = I.out_cap;
+    D.eb = I.eb;
+    D.dims = I.dims;
+    D.dtype = (uint32_t)I.dtype;
+    D.layout = I.prm.layout;
+    D.r = I.prm.leaf_size;
+    D.eb_mode = I.prm.eb_mode;
+    D.mbits = I.dtype == BBX_F32 ? 5u : 6u;
+    const uint64_t n = I.n;
+    if (n > 0) {
+      D.geom = make_geom(n, D.r);
+      D.n_leaves = D.geom.L[0][0];
+      if (D.r < bp->tile) {
+        D.tile_mode = 1;
+        uint32_t K = 0;
+        while (((n + (1ull << K) - 1) >> K) > bp->tile) ++K;
+        D.gl = K;
+      } else {
+        D.tile_mode = 0;
+        uint32_t K = 0;
+        while ((n >> K) > D.r) ++K;
+        D.gl = ((n + (1ull << K) - 1) >> K) <= D.r ? K : K + 1;
+      }
+      D.final_buf = D.tile_mode ? (D.gl & 1) : ((D.gl & 1) ^ 1);
+      mm[s] = std::min<uint64_t>((n + 2047) / 2048, kMaxMinMaxBlocks);
+      qz[s] = std::min<uint64_t>((n + 1023) / 1024, 16384);
+      tl[s] = D.tile_mode ? (1ull << D.gl) : 0;
+      bg[s] = D.tile_mode ? 0 : D.n_leaves;
+      const uint64_t mw = (D.n_leaves * (uint64_t)(D.dims * (D.mbits + 30)) + 63) / 64;
+      pm[s] = std::max<uint64_t>(1, std::min<uint64_t>((mw + kBlock - 1) / kBlock, 1024));
+      const uint64_t pw = (n * (uint64_t)D.dims * 31 + 63) / 64;
+      pp[s] = std::max<uint64_t>(1, std::min<uint64_t>((pw + kBlock - 1) / kBlock, 4096));
+      uint64_t max_nodes = 0, max_blocks = 0;
+      for (uint32_t k = 0; k < D.gl; ++k) {
+        const LevelShape sh = level_shape(n, k);
+        lv[s].push_back(sh.nodes * sh.chunks);
+        nd[s].push_back(sh.nodes);
+        max_nodes = std::max(max_nodes, sh.nodes);
+        max_blocks = std::max(max_blocks, sh.nodes * sh.chunks);
+      }
+      bp->max_gl = std::max(bp->max_gl, D.gl);
+      D.mm_blocks = (uint32_t)mm[s];
+      D.key_off = key_bytes;
+      D.idx_off = idx_n;
+      D.hist_off = hist_n;
+      D.sel_off = sel_n;
+      D.rows_off = rows_n * kRowStride;
+      D.cb_off = rows_n * 2;
+      D.leaf_off = leaves_n;
+      D.part_off = parts;
+      key_bytes += align_up((uint64_t)D.dims * n * 4);
+      idx_n += (n + 63) & ~63ull;
+      hist_n += max_nodes * kHistBins;
+      sel_n += max_nodes;
+      rows_n += max_blocks;
+      leaves_n += D.n_leaves;
+      parts += mm[s];
+    }
+    if (D.perm) bp->track = 1;
   }
-  return c.off;
+  bp->total_leaves = leaves_n;
+  bp->hist_entries = hist_n;
+  // prefix arrays
+  pre->clear();
+  auto add = [&](const std::vector<uint64_t>& blocks, uint64_t* grid) -> uint64_t {
+    const uint64_t off = pre->size();
+    uint64_t run = 0;
+    for (uint32_t s = 0; s < nsets; ++s) {
+      pre->push_back(run);
+      run += blocks[s];
+    }
+    pre->push_back(run);
+    *grid = run;
+    return off;
+  };
+  bp->o_mm = add(mm, &bp->g_mm);
+  bp->o_qz = add(qz, &bp->g_qz);
+  bp->o_tile = add(tl, &bp->g_tile);
+  bp->o_big = add(bg, &bp->g_big);
+  bp->o_pm = add(pm, &bp->g_pm);
+  bp->o_pp = add(pp, &bp->g_pp);
+  for (uint32_t k = 0; k < bp->max_gl; ++k) {
+    std::vector<uint64_t> a(nsets), b(nsets);
+    for (uint32_t s = 0; s < nsets; ++s) {
+      a[s] = k < lv[s].size() ? lv[s][k] : 0;
+      b[s] = k < nd[s].size() ? nd[s][k] : 0;
+    }
+    bp->o_lv[k] = add(a, &bp->g_lv[k]);
+    bp->o_nd[k] = add(b, &bp->g_nd[k]);
+  }
+  bp->pre_entries = pre->size();
+  Carve c;
+  lay->params = c.take(sizeof(DevParams) * nsets);
+  lay->sets = c.take(sizeof(SetDesc) * nsets);
+  lay->pre = c.take(8 * bp->pre_entries);
+  lay->partials = c.take(64 * (parts + 1));
+  lay->keys[0] = c.take(key_bytes);
+  lay->keys[1] = c.take(key_bytes);
+  lay->idx[0] = c.take(4 * idx_n);
+  lay->idx[1] = c.take(4 * idx_n);
+  lay->hist = c.take(4 * hist_n);
+  lay->sel = c.take(sizeof(NodeSel) * sel_n);
+  lay->rows = c.take(4 * kRowStride * rows_n);
+  lay->cb = c.take(8 * rows_n);
+  lay->leaves = c.take(sizeof(LeafRec) * leaves_n);
+  lay->bits = c.take(8 * leaves_n);
+  lay->spart = c.take(8 * (scan_blocks(leaves_n) + 1));
+  lay->stotal = c.take(8);
+  lay->total = c.off;
+}
+
+static Ws carve_ws(const WsLayout& L, uint8_t* base) {
+  Ws w;
+  w.params = (DevParams*)(base + L.params);
+  w.sets = (const SetDesc*)(base + L.sets);
+  w.pre = (const uint64_t*)(base + L.pre);
+  w.partials = (double*)(base + L.partials);
+  w.keys[0] = base + L.keys[0];
+  w.keys[1] = base + L.keys[1];
+  w.idx[0] = (uint32_t*)(base + L.idx[0]);
+  w.idx[1] = (uint32_t*)(base + L.idx[1]);
+  w.hist = (uint32_t*)(base + L.hist);
+  w.sel = (NodeSel*)(base + L.sel);
+  w.rows = (uint32_t*)(base + L.rows);
+  w.chunk_base = (uint32_t*)(base + L.cb);
+  w.leaves = (LeafRec*)(base + L.leaves);
+  w.leaf_bits = (uint64_t*)(base + L.bits);
+  w.scan_part = (uint64_t*)(base + L.spart);
+  w.scan_total = (uint64_t*)(base + L.stotal);
+  return w;
+}
+
+static bbx_status check_batch(const SetIn* in, uint32_t nsets) {
+  if (nsets == 0) return fail(BBX_EINVAL, "empty batch");
+  const uint32_t tile = in[0].prm.tile_override;
+  for (uint32_t s = 0; s < nsets; ++s) {
+    bbx_status st = check_set(in[s]);
+    if (st != BBX_OK) return fail(st, "set " + std::to_string(s) + ": " + g_err);
+    if (in[s].prm.tile_override != tile) return fail(BBX_EINVAL, "all sets of a batch share one tile_override");
+  }
+  return BBX_OK;
+}
+
+// Uploads descriptors and prefix arrays (stream-ordered copy from host memory).
+static bbx_status batch_upload(const SetIn* in, uint32_t nsets, void* d_ws, size_t ws_size,
+                               hipStream_t stream) {
+  BatchPlan bp;
+  std::vector<SetDesc> descs;
+  std::vector<uint64_t> pre;
+  WsLayout lay;
+  plan_batch(in, nsets, &bp, &descs, &pre, &lay);
+  if (!d_ws || ((uintptr_t)d_ws & 255)) return fail(BBX_EINVAL, "workspace must be 256-byte aligned");
+  if (ws_size < lay.total) return fail(BBX_ENOMEM, "workspace too small: need " + std::to_string(lay.total));
+  std::vector<uint8_t> blob(lay.pre + 8 * pre.size() - lay.sets);
+  memcpy(blob.data(), descs.data(), sizeof(SetDesc) * nsets);
+  memcpy(blob.data() + (lay.pre - lay.sets), pre.data(), 8 * pre.size());
+  hipError_t e = hipMemcpyAsync((uint8_t*)d_ws + lay.sets, blob.data(), blob.size(),
+                                hipMemcpyHostToDevice, stream);
+  if (e != hipSuccess) return fail(BBX_EHIP, std::string("descriptor upload failed: ") + hipGetErrorString(e));
+  return BBX_OK;
+}
+
+// Enqueues every kernel of the batch; no host synchronization, no copies.
+static bbx_status batch_launch(const SetIn* in, uint32_t nsets, void* d_ws, size_t ws_size,
+                               hipStream_t stream) {
+  BatchPlan bp;
+  std::vector<SetDesc> descs;
+  std::vector<uint64_t> pre;
+  WsLayout lay;
+  plan_batch(in, nsets, &bp, &descs, &pre, &lay);
+  if (!d_ws || ((uintptr_t)d_ws & 255)) return fail(BBX_EINVAL, "workspace must be 256-byte aligned");
+  if (ws_size < lay.total) return fail(BBX_ENOMEM, "workspace too small: need " + std::to_string(lay.total));
+  const Ws w = carve_ws(lay, (uint8_t*)d_ws);
+  hipError_t e = launch_range(bp, w, stream);
+  if (e == hipSuccess) e = launch_levels(bp, w, stream);
+  if (e == hipSuccess) e = launch_leaves(bp, w, stream);
+  if (e == hipSuccess) e = launch_pack(bp, w, stream);
+  if (e != hipSuccess) return fail(BBX_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+  return BBX_OK;
 }
 
 // ---------------------------------------------------------------- stream header
@@ -298,8 +460,19 @@ size_t bbx_compress_bound(uint64_t n, uint32_t dims, bbx_dtype dtype) {
 size_t bbx_compress_workspace_size(uint64_t n, uint32_t dims, bbx_dtype dtype,
                                    const bbx_params* params) {
   if (check_compress_args(n, dims, dtype, 1.0, params) != BBX_OK) return 0;
-  CompressPlan p = make_plan(n, dims, dtype, 1.0, params, true);
-  return carve_compress(p, nullptr, nullptr);
+  SetIn in;
+  memset(&in, 0, sizeof(in));
+  in.n = n;
+  in.dims = dims;
+  in.dtype = dtype;
+  in.eb = 1.0;
+  in.prm = *params;
+  BatchPlan bp;
+  std::vector<SetDesc> descs;
+  std::vector<uint64_t> pre;
+  WsLayout lay;
+  plan_batch(&in, 1, &bp, &descs, &pre, &lay);
+  return lay.total;
 }
 
 bbx_status bbx_compress(const void* d_pos, uint64_t n, uint32_t dims, bbx_dtype dtype, double eb,
@@ -308,28 +481,27 @@ bbx_status bbx_compress(const void* d_pos, uint64_t n, uint32_t dims, bbx_dtype 
                         uint32_t* d_perm, void* d_ws, size_t ws_size, hipStream_t stream) {
   bbx_status st = check_compress_args(n, dims, dtype, eb, params);
   if (st != BBX_OK) return st;
-  if (n > 0 && !d_pos) return fail(BBX_EINVAL, "d_pos is NULL");
-  if (!d_out || ((uintptr_t)d_out & 7)) return fail(BBX_EINVAL, "d_out must be 8-byte aligned");
-  if (out_cap < (size_t)kHeaderBytes) return fail(BBX_ENOSPC, "out_cap below the 128-byte header");
-  if (!d_ws || ((uintptr_t)d_ws & 255)) return fail(BBX_EINVAL, "d_ws must be 256-byte aligned");
-  CompressPlan p = make_plan(n, dims, dtype, eb, params, d_perm != nullptr);
-  CompressWs w;
-  memset(&w, 0, sizeof(w));
-  const size_t need = carve_compress(p, (uint8_t*)d_ws, &w);
-  if (ws_size < need) return fail(BBX_ENOMEM, "workspace too small: need " + std::to_string(need));
-
-  hipError_t e = launch_range(p, w, d_pos, stream);
-  int buf = 0;
-  if (e == hipSuccess && n > 0) e = launch_levels(p, w, stream, &buf);
-  int out_buf = buf;
-  if (e == hipSuccess && n > 0) e = launch_leaves(p, w, buf, d_perm, stream, &out_buf);
-  if (e == hipSuccess)
-    e = launch_scan(p.n_leaves, w.leaf_bits, w.scan_part, w.params, &p, 0, out_cap, d_size, stream);
-  if (e == hipSuccess) e = launch_pack(p, w, out_buf, (uint8_t*)d_out, d_size, d_status, stream);
-  if (e != hipSuccess) return fail(BBX_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+  SetIn in;
+  in.pos = d_pos;
+  in.n = n;
+  in.dims = dims;
+  in.dtype = dtype;
+  in.eb = eb;
+  in.prm = *params;
+  in.out = d_out;
+  in.out_cap = out_cap;
+  in.d_size = d_size;
+  in.d_status = d_status;
+  in.d_perm = d_perm;
+  st = check_set(in);
+  if (st != BBX_OK) return st;
+  st = batch_upload(&in, 1, d_ws, ws_size, stream);
+  if (st != BBX_OK) return st;
+  st = batch_launch(&in, 1, d_ws, ws_size, stream);
+  if (st != BBX_OK) return st;
   if (h_out_size) {
     DevParams hp;
-    e = hipMemcpyAsync(&hp, w.params, sizeof(hp), hipMemcpyDeviceToHost, stream);
+    hipError_t e = hipMemcpyAsync(&hp, d_ws, sizeof(hp), hipMemcpyDeviceToHost, stream);  // params[0]
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return fail(BBX_EHIP, std::string("synchronize failed: ") + hipGetErrorString(e));
     if (hp.status != BBX_OK) {
@@ -342,6 +514,64 @@ bbx_status bbx_compress(const void* d_pos, uint64_t n, uint32_t dims, bbx_dtype 
     *h_out_size = (size_t)hp.total_bytes;
   }
   return BBX_OK;
+}
+
+static bool sets_from_abi(const bbx_set* sets, uint32_t nsets, std::vector<SetIn>* v) {
+  if (!sets) return false;
+  v->resize(nsets);
+  for (uint32_t s = 0; s < nsets; ++s) {
+    SetIn& I = (*v)[s];
+    I.pos = sets[s].d_pos;
+    I.n = sets[s].n;
+    I.dims = sets[s].dims;
+    I.dtype = (bbx_dtype)sets[s].dtype;
+    I.eb = sets[s].eb;
+    I.prm = sets[s].params;
+    I.out = sets[s].d_out;
+    I.out_cap = sets[s].out_cap;
+    I.d_size = sets[s].d_size;
+    I.d_status = sets[s].d_status;
+    I.d_perm = sets[s].d_perm;
+  }
+  return true;
+}
+
+size_t bbx_batch_workspace_size(const bbx_set* sets, uint32_t nsets) {
+  std::vector<SetIn> v;
+  if (!sets_from_abi(sets, nsets, &v) || nsets == 0) return 0;
+  for (uint32_t s = 0; s < nsets; ++s)
+    if (check_compress_args(v[s].n, v[s].dims, v[s].dtype, v[s].eb, &v[s].prm) != BBX_OK) return 0;
+  BatchPlan bp;
+  std::vector<SetDesc> descs;
+  std::vector<uint64_t> pre;
+  WsLayout lay;
+  plan_batch(v.data(), nsets, &bp, &descs, &pre, &lay);
+  return lay.total;
+}
+
+bbx_status bbx_batch_upload(const bbx_set* sets, uint32_t nsets, void* d_ws, size_t ws_size,
+                            hipStream_t stream) {
+  std::vector<SetIn> v;
+  if (!sets_from_abi(sets, nsets, &v)) return fail(BBX_EINVAL, "sets is NULL");
+  bbx_status st = check_batch(v.data(), nsets);
+  if (st != BBX_OK) return st;
+  return batch_upload(v.data(), nsets, d_ws, ws_size, stream);
+}
+
+bbx_status bbx_batch_launch(const bbx_set* sets, uint32_t nsets, void* d_ws, size_t ws_size,
+                            hipStream_t stream) {
+  std::vector<SetIn> v;
+  if (!sets_from_abi(sets, nsets, &v)) return fail(BBX_EINVAL, "sets is NULL");
+  bbx_status st = check_batch(v.data(), nsets);
+  if (st != BBX_OK) return st;
+  return batch_launch(v.data(), nsets, d_ws, ws_size, stream);
+}
+
+bbx_status bbx_compress_batch(const bbx_set* sets, uint32_t nsets, void* d_ws, size_t ws_size,
+                              hipStream_t stream) {
+  bbx_status st = bbx_batch_upload(sets, nsets, d_ws, ws_size, stream);
+  if (st != BBX_OK) return st;
+  return bbx_batch_launch(sets, nsets, d_ws, ws_size, stream);
 }
 
 bbx_status bbx_stream_info(const void* h_header, size_t header_bytes, uint64_t* n, uint32_t* dims,

@@ -1,5 +1,9 @@
 // bbx_internal.h -- definitions shared by the HIP library's translation units.
 // Not part of the public ABI (include/bitbox.h is).
+//
+// Every compress launch works on a batch of independent particle sets; a
+// single compress is a batch of one.  Each kernel finds its set from the
+// block index through a per-launch prefix array of block counts.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -12,22 +16,25 @@ namespace bbx {
 constexpr uint32_t kMagic = 0x31584242u;  // bytes 'B','B','X','1'
 constexpr int kHeaderBytes = 128;
 constexpr int kBlock = 256;               // threads per block for streaming kernels
-constexpr int kMinMaxBlocks = 1024;       // partial-reduction blocks of the range pass
+constexpr int kMaxMinMaxBlocks = 1024;    // partial-reduction blocks of the range pass per set
 constexpr int kMaxDepth = 40;             // depth table size (n < 2^32 needs <= 33)
-constexpr int kHistStride = 2048;         // per-node bins of the global radix select
+constexpr int kHistBins = 256;            // per-node bins of the global radix select (digits <= 8 bits)
 constexpr int kRowStride = 258;           // per-chunk row: 257 prefix counts + below count
+constexpr int kRows = 8;                  // rows of kBlock elements per streaming group
+constexpr int kGroup = kRows * kBlock;    // elements per streaming group
 
 // Scalars of the range-and-bound step (Sec. 3), computed on the device by the
-// range epilogue and read by every later compress kernel.
+// range epilogue and read by every later compress kernel of the set.
 struct DevParams {
   double lo[3], hi[3];
   double eb_user, eb_abs, eb_eff, w, inv_w;
   uint32_t G[3];        // bits of the largest code per axis
   uint32_t key16;       // 1 when every code fits 16 bits
-  uint32_t status;      // bbx_status of the call so far
+  uint32_t status;      // bbx_status of the set so far
   uint32_t pad0;
   uint64_t meta_bits, payload_bits, total_bytes;
-  uint64_t pad1[4];
+  uint64_t payload_base;  // global payload-bit offset of the set's first leaf
+  uint64_t pad1[3];
 };
 
 // Shape of the k-d tree, which depends on (n, r) only: at depth k every node
@@ -57,6 +64,50 @@ struct NodeSel {
   uint32_t rank;    // rank of the median among the remaining candidates
   uint32_t v;       // median code (after the last pass)
   uint32_t jeq;     // members equal to v that go to the left child
+};
+
+// One set of a compress batch (device-resident).
+struct SetDesc {
+  const void* pos;        // caller's positions
+  uint8_t* out;           // caller's stream buffer
+  uint32_t* perm;         // optional source index per output slot
+  uint64_t* d_size;       // optional stream length (UINT64_MAX on error)
+  uint32_t* d_status;     // optional status
+  uint64_t n, out_cap;
+  double eb;
+  uint32_t dims, dtype, layout, r, eb_mode, mbits;
+  uint32_t gl;            // global levels
+  uint32_t tile_mode;     // 1: tile stage at depth gl; 0: big-leaf stage
+  uint32_t final_buf;     // key buffer that ends in output-slot order
+  uint32_t mm_blocks;     // blocks of the range pass
+  uint64_t n_leaves;
+  uint64_t key_off;       // byte offset into each key buffer (capacity dims*n*4)
+  uint64_t idx_off;       // u32 offset into each index buffer
+  uint64_t hist_off;      // u32 offset into the histogram bins
+  uint64_t sel_off;       // NodeSel offset
+  uint64_t rows_off;      // u32 offset into the chunk rows
+  uint64_t cb_off;        // u32 offset into the chunk bases
+  uint64_t leaf_off;      // first leaf of the set in the batch's leaf arrays
+  uint64_t part_off;      // first block of the set's range partials
+  TreeGeom geom;
+};
+
+// Shared scratch of a batch.
+struct Ws {
+  DevParams* params;   // [nsets]
+  const SetDesc* sets; // [nsets]
+  double* partials;    // range partials, 8 doubles per block
+  uint8_t* keys[2];
+  uint32_t* idx[2];
+  uint32_t* hist;
+  NodeSel* sel;
+  uint32_t* rows;
+  uint32_t* chunk_base;
+  LeafRec* leaves;
+  uint64_t* leaf_bits;
+  uint64_t* scan_part;
+  uint64_t* scan_total;
+  const uint64_t* pre;  // block-count prefix arrays (see BatchPlan)
 };
 
 // ---------------------------------------------------------------- device helpers
@@ -113,37 +164,76 @@ __host__ __device__ inline uint64_t leaves_before_node(const TreeGeom& g, uint32
 }
 
 // Radix-select digit plan for a code of G bits: the last pass takes the low
-// min(G, 8) bits; the bits above are split into one or two passes of <= 11.
+// min(G, 8) bits; the bits above are split evenly into passes of <= 8 bits.
 struct DigitPlan {
   uint32_t npass;
-  uint32_t width[3];
-  uint32_t shift[3];
+  uint32_t width[4];
+  uint32_t shift[4];
 };
 
 __host__ __device__ inline DigitPlan digit_plan(uint32_t G) {
   DigitPlan p;
-  uint32_t wl = G < 8 ? G : 8;
-  uint32_t rest = G - wl;
-  if (rest == 0) {
-    p.npass = 1;
-    p.width[0] = wl;
-  } else if (rest <= 11) {
-    p.npass = 2;
-    p.width[0] = rest;
-    p.width[1] = wl;
-  } else {
-    p.npass = 3;
-    p.width[0] = (rest + 1) / 2;
-    p.width[1] = rest / 2;
-    p.width[2] = wl;
-  }
-  uint32_t used = 0;
-  for (uint32_t i = 0; i < p.npass; ++i) {
-    used += p.width[i];
-    p.shift[i] = G - used;
-  }
-  for (uint32_t i = p.npass; i < 3; ++i) p.width[i] = p.shift[i] = 0;
+  const uint32_t wl = G < 8 ? G : 8;
+  const uint32_t rest = G - wl;
+  const uint32_t nmid = (rest + 7) / 8;  // 0..3 for G <= 30
+  p.npass = nmid + 1;
+  const uint32_t base = nmid ? rest / nmid : 0, extra = nmid ? rest % nmid : 0;
+  // mid passes (the first `extra` get one more bit), then the last digit
+  p.width[0] = nmid >= 1 ? base + (extra > 0 ? 1u : 0u) : wl;
+  p.width[1] = nmid >= 2 ? base + (extra > 1 ? 1u : 0u) : (nmid == 1 ? wl : 0u);
+  p.width[2] = nmid >= 3 ? base : (nmid == 2 ? wl : 0u);
+  p.width[3] = nmid == 3 ? wl : 0u;
+  p.shift[0] = G - p.width[0];
+  p.shift[1] = p.shift[0] - p.width[1];
+  p.shift[2] = p.shift[1] - p.width[2];
+  p.shift[3] = p.shift[2] - p.width[3];
   return p;
+}
+
+// width / shift of pass i without dynamic indexing (keeps the plan in registers)
+__host__ __device__ inline uint32_t dp_width(const DigitPlan& p, uint32_t i) {
+  return i == 0 ? p.width[0] : (i == 1 ? p.width[1] : (i == 2 ? p.width[2] : p.width[3]));
+}
+__host__ __device__ inline uint32_t dp_shift(const DigitPlan& p, uint32_t i) {
+  return i == 0 ? p.shift[0] : (i == 1 ? p.shift[1] : (i == 2 ? p.shift[2] : p.shift[3]));
+}
+
+// Blocks of one global level of one set: nodes x chunks, each chunk a whole
+// number of streaming groups.
+struct LevelShape {
+  uint64_t nodes;
+  uint32_t chunk_elems;
+  uint64_t chunks;
+};
+
+__host__ __device__ inline LevelShape level_shape(uint64_t n, uint32_t depth) {
+  LevelShape sh;
+  sh.nodes = 1ull << depth;
+  const uint64_t maxsz = (n + sh.nodes - 1) >> depth;  // ceil(n / 2^depth)
+  const uint64_t target_blocks = 4096;
+  uint64_t cpn = (target_blocks + sh.nodes - 1) / sh.nodes;
+  if (cpn == 0) cpn = 1;
+  const uint64_t elems = (maxsz + cpn - 1) / cpn;
+  uint64_t groups = (elems + kGroup - 1) / kGroup;
+  if (groups < 1) groups = 1;
+  sh.chunk_elems = (uint32_t)(groups * kGroup);
+  sh.chunks = (maxsz + sh.chunk_elems - 1) / sh.chunk_elems;
+  if (sh.chunks == 0) sh.chunks = 1;
+  return sh;
+}
+
+// set owning global block b: largest s with pre[s] <= b (pre non-decreasing,
+// pre[0] = 0, b < pre[nsets])
+__device__ inline uint32_t find_set(const uint64_t* pre, uint32_t nsets, uint64_t b) {
+  uint32_t lo = 0, hi = nsets - 1;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1) >> 1;
+    if (pre[mid] <= b)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
 }
 
 // ---------------------------------------------------------------- launch plumbing
@@ -164,55 +254,21 @@ struct ProfScope {
     hipLaunchKernelGGL(kern, dim3(grid), dim3(block), shm, stream, __VA_ARGS__); \
   } while (0)
 
-// ---------------------------------------------------------------- launchers
-
-struct CompressPlan {
-  uint64_t n;
-  uint32_t dims, dtype, layout, r, eb_mode, track_idx;
-  double eb;
-  uint32_t tile;          // tile capacity of the on-chip stage
-  uint32_t global_levels; // depths handled by the global level kernels
-  uint32_t tile_mode;     // 1: tile stage at depth global_levels, 0: big-leaf stage
-  uint64_t n_leaves;
-  uint64_t max_nodes;     // nodes of the deepest global level
-  uint64_t max_blocks;    // blocks of the largest global level launch
-  uint32_t mbits;
-  TreeGeom geom;
+// Host-side launch plan of a batch: grid sizes and the offsets (in u64
+// entries) of each prefix array inside the uploaded plan buffer.
+struct BatchPlan {
+  uint32_t nsets;
+  uint32_t max_gl;            // deepest global level count over the sets
+  uint32_t tile;              // tile capacity (256 or 512)
+  uint32_t track;             // source indices are carried (some set wants perm)
+  uint64_t total_leaves;
+  uint64_t hist_entries;      // u32 bins zeroed once per call
+  uint64_t g_mm, g_qz, g_tile, g_big, g_pm, g_pp;
+  uint64_t o_mm, o_qz, o_tile, o_big, o_pm, o_pp;
+  uint64_t g_lv[kMaxDepth], g_nd[kMaxDepth];
+  uint64_t o_lv[kMaxDepth], o_nd[kMaxDepth];
+  uint64_t pre_entries;       // total u64 entries of the prefix buffer
 };
-
-struct CompressWs {
-  DevParams* params;
-  double* partials;
-  void* keys[2];
-  uint32_t* idx[2];
-  uint32_t* hist;
-  NodeSel* sel;
-  uint32_t* rows;
-  uint32_t* chunk_base;
-  LeafRec* leaves;
-  uint64_t* leaf_bits;
-  uint64_t* scan_part;
-};
-
-struct LevelShape {
-  uint32_t depth;
-  uint64_t nodes;
-  uint32_t iters;     // 256-element iterations per block
-  uint64_t chunks;    // chunks per node
-};
-
-LevelShape level_shape(const CompressPlan& p, uint32_t depth);
-
-hipError_t launch_range(const CompressPlan& p, const CompressWs& w, const void* pos,
-                        hipStream_t s);
-hipError_t launch_levels(const CompressPlan& p, const CompressWs& w, hipStream_t s, int* final_buf);
-hipError_t launch_leaves(const CompressPlan& p, const CompressWs& w, int buf, uint32_t* perm,
-                         hipStream_t s, int* out_buf);
-hipError_t launch_scan(uint64_t count, uint64_t* bits, uint64_t* part, DevParams* params,
-                       const CompressPlan* cp, uint64_t expect_payload, size_t out_cap,
-                       uint64_t* d_size, hipStream_t s);
-hipError_t launch_pack(const CompressPlan& p, const CompressWs& w, int buf, uint8_t* out,
-                       uint64_t* d_size, uint32_t* d_status, hipStream_t s);
 
 struct DecompressPlan {
   uint64_t n, n_leaves, meta_bits, payload_bits;
@@ -230,9 +286,16 @@ struct DecompressWs {
   uint64_t* scan_part;
 };
 
+uint64_t scan_blocks(uint64_t count);
+
+// launchers (one group per translation unit)
+hipError_t launch_range(const BatchPlan& bp, const Ws& w, hipStream_t s);
+hipError_t launch_levels(const BatchPlan& bp, const Ws& w, hipStream_t s);
+hipError_t launch_leaves(const BatchPlan& bp, const Ws& w, hipStream_t s);
+hipError_t launch_pack(const BatchPlan& bp, const Ws& w, hipStream_t s);
 hipError_t launch_decompress(const DecompressPlan& p, const DecompressWs& w, const uint8_t* stream,
                              void* pos, uint32_t* d_status, hipStream_t s);
-
-uint64_t scan_blocks(uint64_t count);
+hipError_t launch_dec_scan(uint64_t count, uint64_t* bits, uint64_t* part, DevParams* params,
+                           uint64_t expect_payload, hipStream_t s);
 
 }  // namespace bbx

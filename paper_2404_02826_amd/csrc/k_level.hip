@@ -1,33 +1,40 @@
-// k_level.hip -- the global levels of the k-d median partition (Sec. 4.1).
+// k_level.hip -- the global levels of the k-d median partition (Sec. 4.1),
+// for every set of a batch that still has nodes above the tile capacity.
 //
-// At depth k every node is a contiguous range of the key arrays whose members
-// are in ascending original index.  The node splits at the member of rank
-// floor(s/2) in (q_d, index) order, d = k mod dims; that member and everything
-// after it form the right child.  Because the members are stored in index
-// order, "index order" is "storage order", so the split is an exact radix
-// select on q_d followed by a stable partition.
+// At depth k every node is a contiguous range of the set's code arrays whose
+// members are in ascending original index.  The node splits at the member of
+// rank floor(s/2) in (q_d, index) order, d = k mod dims; that member and
+// everything after it form the right child.  Because the members are stored
+// in index order, "index order" is "storage order", so the split is an exact
+// radix select on q_d followed by a stable partition.
 //
-//   k_fill_hist       zero the per-node histogram bins used by one pass
-//   k_hist_mid        histogram of a high digit of q_d over the candidates
-//                     (members matching the digits found so far)
-//   k_select_mid      per node: pick the digit holding the median's rank
-//   k_hist_last       last digit: per-chunk prefix counts + node totals
-//   k_select_last     per node: the median code v, how many members equal to
-//                     v go left (jeq), and each chunk's (lt, eq) base
-//   k_scatter         stable partition of the keys (and source indices)
+//   k_hist_zero    zero the histogram bins once per call (every select kernel
+//                  re-zeroes the bins it reads)
+//   k_hist_root    first-digit histogram of depth 0
+//   k_hist_mid     histogram of a further high digit over the candidates
+//                  (members matching the digits found so far)
+//   k_select_mid   per node: the digit holding the median's rank
+//   k_hist_last    last digit: per-chunk prefix counts + node totals
+//   k_select_last  per node: the median code v, how many members equal to v
+//                  go left (jeq), and each chunk's (lt, eq) base
+//   k_scatter      stable partition of the codes (and source indices); also
+//                  builds the next level's first-digit histogram, so that
+//                  level needs no separate pass over its codes for it
 //
+// Streaming kernels keep 8 loads in flight per thread (rows of 256 elements,
+// 8 rows per group) and synchronize once per 2048 elements.
 // Nodes of <= r particles (possible only when r exceeds the tile capacity)
 // are leaves: they skip selection and are copied through.
 #include "bbx_internal.h"
 
 namespace bbx {
 
-template <typename KT>
-__device__ inline const KT* kp(const void* keys, uint64_t n, uint32_t d) {
-  return (const KT*)keys + (uint64_t)d * n;
-}
-
 __device__ inline uint32_t popc64(uint64_t v) { return (uint32_t)__popcll(v); }
+
+// element d of a 3-array held in registers (d is wave-uniform; no dynamic indexing)
+__device__ inline uint32_t pick3(const uint32_t* k, uint32_t d) {
+  return d == 0 ? k[0] : (d == 1 ? k[1] : k[2]);
+}
 
 // Block-wide exclusive scan of one u64 per thread (256 threads); returns the
 // exclusive prefix and writes the block total to *total.
@@ -51,176 +58,252 @@ __device__ inline uint64_t block_exscan_u64(uint64_t v, uint64_t* total) {
   return off + x - v;
 }
 
-__global__ void __launch_bounds__(kBlock) k_fill_hist(uint32_t depth, uint32_t pass, uint32_t last,
-                                                      uint32_t dims, uint64_t nodes,
-                                                      const DevParams* P, uint32_t* hist) {
-  if (P->status != BBX_OK) return;
-  const DigitPlan pl = digit_plan(P->G[depth % dims]);
-  if (last ? false : pass + 1 >= pl.npass) return;
-  const uint32_t w = last ? pl.width[pl.npass - 1] : pl.width[pass];
-  const uint64_t total = nodes << w;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+__global__ void __launch_bounds__(kBlock) k_hist_zero(uint64_t entries, uint32_t* hist) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < entries;
        i += (uint64_t)gridDim.x * blockDim.x)
     hist[i] = 0;
 }
 
+// The block's set, local block index and level shape.
+struct LevelCtx {
+  uint32_t s;
+  uint64_t lb;
+  LevelShape sh;
+};
+
+__device__ inline LevelCtx level_ctx(uint32_t nsets, const uint64_t* pre, const SetDesc* sets,
+                                     uint32_t depth) {
+  LevelCtx c;
+  c.s = find_set(pre, nsets, blockIdx.x);
+  c.lb = blockIdx.x - pre[c.s];
+  c.sh = level_shape(sets[c.s].n, depth);
+  return c;
+}
+
 template <typename KT>
-__device__ void hist_mid_body(uint32_t depth, uint32_t pass, uint64_t n, uint32_t dims, uint32_t r,
-                              uint64_t chunks, uint32_t chunk_elems, const DevParams* P,
-                              const void* keys, const NodeSel* sel, uint32_t* hist,
-                              uint32_t* lh) {
-  const uint32_t d = depth % dims;
+__device__ void hist_mid_body(uint32_t depth, uint32_t pass, const SetDesc& S, const DevParams* P,
+                              const LevelCtx& c, const uint8_t* keys, const NodeSel* sel,
+                              uint32_t* hist, uint32_t* lh) {
+  const uint64_t n = S.n;
+  const uint32_t d = depth % S.dims;
   const DigitPlan pl = digit_plan(P->G[d]);
-  const uint64_t j = blockIdx.x / chunks, ch = blockIdx.x % chunks;
+  const uint64_t j = c.lb / c.sh.chunks, ch = c.lb % c.sh.chunks;
   uint64_t st, sz;
   node_span(n, depth, j, &st, &sz);
-  if (sz <= r) return;
-  const uint32_t w = pl.width[pass], sh = pl.shift[pass], hs = sh + w;
-  const uint32_t prefix = pass == 0 ? 0u : sel[j].prefix;
+  if (sz <= S.r) return;
+  const uint32_t w = dp_width(pl, pass), sh = dp_shift(pl, pass), hs = sh + w;
+  const uint32_t prefix = sel[j].prefix;
   const uint32_t nb = 1u << w, mask = nb - 1;
-  for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) lh[b] = 0;
+  lh[threadIdx.x] = 0;
   __syncthreads();
-  const KT* q = kp<KT>(keys, n, d) + st;
-  const uint64_t beg = ch * (uint64_t)chunk_elems;
-  const uint64_t end = beg + chunk_elems < sz ? beg + chunk_elems : sz;
-  for (uint64_t p = beg + threadIdx.x; p < end; p += blockDim.x) {
-    uint32_t v = q[p];
-    if ((v >> hs) == prefix) atomicAdd(&lh[(v >> sh) & mask], 1u);
+  const KT* q = (const KT*)keys + (uint64_t)d * n + st;
+  const uint64_t beg = ch * (uint64_t)c.sh.chunk_elems;
+  const uint64_t end = beg + c.sh.chunk_elems < sz ? beg + c.sh.chunk_elems : sz;
+  for (uint64_t g = beg; g < end; g += kGroup) {
+    uint32_t v[kRows];
+#pragma unroll
+    for (int i = 0; i < kRows; ++i) {
+      const uint64_t p = g + (uint64_t)i * kBlock + threadIdx.x;
+      v[i] = p < end ? (uint32_t)q[p] : 0xffffffffu;
+    }
+#pragma unroll
+    for (int i = 0; i < kRows; ++i)
+      if (v[i] != 0xffffffffu && (v[i] >> hs) == prefix) atomicAdd(&lh[(v[i] >> sh) & mask], 1u);
   }
   __syncthreads();
-  for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x)
-    if (lh[b]) atomicAdd(&hist[(j << w) + b], lh[b]);
+  if (threadIdx.x < nb && lh[threadIdx.x]) atomicAdd(&hist[(j << 8) + threadIdx.x], lh[threadIdx.x]);
 }
 
-__global__ void __launch_bounds__(kBlock) k_hist_mid(uint32_t depth, uint32_t pass, uint64_t n,
-                                                     uint32_t dims, uint32_t r, uint64_t chunks,
-                                                     uint32_t chunk_elems, const DevParams* P,
-                                                     const void* keys, const NodeSel* sel,
-                                                     uint32_t* hist) {
+// passes >= 1 of a code with more than two digits (pass 0 is built by the
+// previous scatter, or by k_hist_root at depth 0)
+__global__ void __launch_bounds__(kBlock) k_hist_mid(uint32_t depth, uint32_t pass, uint32_t nsets,
+                                                     const uint64_t* pre, const SetDesc* sets,
+                                                     const DevParams* params, uint8_t* keys0,
+                                                     const NodeSel* sel0, uint32_t* hist0) {
+  const LevelCtx c = level_ctx(nsets, pre, sets, depth);
+  const SetDesc& S = sets[c.s];
+  const DevParams* P = params + c.s;
   if (P->status != BBX_OK) return;
-  if (pass + 1 >= digit_plan(P->G[depth % dims]).npass) return;
-  __shared__ uint32_t lh[kHistStride];
+  if (pass + 1 >= digit_plan(P->G[depth % S.dims]).npass) return;
+  __shared__ uint32_t lh[kHistBins];
+  const uint8_t* keys = keys0 + S.key_off;
   if (P->key16)
-    hist_mid_body<uint16_t>(depth, pass, n, dims, r, chunks, chunk_elems, P, keys, sel, hist, lh);
+    hist_mid_body<uint16_t>(depth, pass, S, P, c, keys, sel0 + S.sel_off, hist0 + S.hist_off, lh);
   else
-    hist_mid_body<uint32_t>(depth, pass, n, dims, r, chunks, chunk_elems, P, keys, sel, hist, lh);
+    hist_mid_body<uint32_t>(depth, pass, S, P, c, keys, sel0 + S.sel_off, hist0 + S.hist_off, lh);
 }
 
-// Per node: find the bin that holds the median's rank among nb bins.
-__global__ void __launch_bounds__(kBlock) k_select_mid(uint32_t depth, uint32_t pass, uint64_t n,
-                                                       uint32_t dims, uint32_t r,
-                                                       const DevParams* P, NodeSel* sel,
-                                                       const uint32_t* hist) {
+// Per node: find the bin that holds the median's rank, then clear the bins.
+__global__ void __launch_bounds__(kBlock) k_select_mid(uint32_t depth, uint32_t pass,
+                                                       uint32_t nsets, const uint64_t* pre,
+                                                       const SetDesc* sets,
+                                                       const DevParams* params, NodeSel* sel0,
+                                                       uint32_t* hist0) {
+  const uint32_t s = find_set(pre, nsets, blockIdx.x);
+  const SetDesc& S = sets[s];
+  const DevParams* P = params + s;
   if (P->status != BBX_OK) return;
-  const DigitPlan pl = digit_plan(P->G[depth % dims]);
+  const DigitPlan pl = digit_plan(P->G[depth % S.dims]);
   if (pass + 1 >= pl.npass) return;
-  const uint64_t j = blockIdx.x;
+  const uint64_t j = blockIdx.x - pre[s];
   uint64_t st, sz;
-  node_span(n, depth, j, &st, &sz);
-  if (sz <= r) return;
-  const uint32_t w = pl.width[pass];
+  node_span(S.n, depth, j, &st, &sz);
+  if (sz <= S.r) return;
+  NodeSel* sel = sel0 + S.sel_off;
+  uint32_t* hist = hist0 + S.hist_off + (j << 8);
+  const uint32_t w = dp_width(pl, pass);
   const uint32_t nb = 1u << w;
   const uint32_t rank = pass == 0 ? (uint32_t)(sz >> 1) : sel[j].rank;
   const uint32_t prefix = pass == 0 ? 0u : sel[j].prefix;
-  // each thread owns 8 consecutive bins (nb <= 2048)
-  uint32_t c[8];
-  uint64_t mine = 0;
-  for (int k = 0; k < 8; ++k) {
-    uint32_t b = threadIdx.x * 8 + k;
-    c[k] = b < nb ? hist[(j << w) + b] : 0u;
-    mine += c[k];
-  }
+  const uint32_t c = threadIdx.x < nb ? hist[threadIdx.x] : 0u;
+  if (c) hist[threadIdx.x] = 0;
   uint64_t tot;
-  uint64_t cum = block_exscan_u64(mine, &tot);
-  for (int k = 0; k < 8; ++k) {
-    if (cum <= rank && rank < cum + c[k]) {
-      NodeSel s;
-      s.prefix = (prefix << w) | (threadIdx.x * 8 + k);
-      s.rank = rank - (uint32_t)cum;
-      s.v = 0;
-      s.jeq = 0;
-      sel[j] = s;
-    }
-    cum += c[k];
+  const uint64_t cum = block_exscan_u64(c, &tot);
+  if (threadIdx.x < nb && cum <= rank && rank < cum + c) {
+    NodeSel ns;
+    ns.prefix = (prefix << w) | threadIdx.x;
+    ns.rank = rank - (uint32_t)cum;
+    ns.v = 0;
+    ns.jeq = 0;
+    sel[j] = ns;
   }
 }
 
+// depth 0 builds its first digit here (deeper levels get it from the scatter)
+__global__ void __launch_bounds__(kBlock) k_hist_root(uint32_t nsets, const uint64_t* pre,
+                                                      const SetDesc* sets, const DevParams* params,
+                                                      uint8_t* keys0, uint32_t* hist0) {
+  const LevelCtx c = level_ctx(nsets, pre, sets, 0);
+  const SetDesc& S = sets[c.s];
+  const DevParams* P = params + c.s;
+  if (P->status != BBX_OK) return;
+  const DigitPlan pl = digit_plan(P->G[0]);
+  if (pl.npass < 2) return;
+  if (S.n <= S.r) return;
+  __shared__ uint32_t lh[kHistBins];
+  const uint32_t w = pl.width[0], sh = pl.shift[0], mask = (1u << w) - 1;
+  lh[threadIdx.x] = 0;
+  __syncthreads();
+  const uint64_t beg = c.lb * (uint64_t)c.sh.chunk_elems;
+  const uint64_t end = beg + c.sh.chunk_elems < S.n ? beg + c.sh.chunk_elems : S.n;
+  const uint8_t* keys = keys0 + S.key_off;
+  for (uint64_t g = beg; g < end; g += kGroup) {
+    uint32_t v[kRows];
+#pragma unroll
+    for (int i = 0; i < kRows; ++i) {
+      const uint64_t p = g + (uint64_t)i * kBlock + threadIdx.x;
+      v[i] = p < end ? (P->key16 ? (uint32_t)((const uint16_t*)keys)[p] : ((const uint32_t*)keys)[p])
+                     : 0xffffffffu;
+    }
+#pragma unroll
+    for (int i = 0; i < kRows; ++i)
+      if (v[i] != 0xffffffffu) atomicAdd(&lh[(v[i] >> sh) & mask], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x <= mask && lh[threadIdx.x])
+    atomicAdd(&hist0[S.hist_off + threadIdx.x], lh[threadIdx.x]);
+}
+
 template <typename KT>
-__device__ void hist_last_body(uint32_t depth, uint64_t n, uint32_t dims, uint32_t r,
-                               uint64_t chunks, uint32_t chunk_elems, const DevParams* P,
-                               const void* keys, const NodeSel* sel, uint32_t* hist,
-                               uint32_t* rows, uint32_t* lh) {
-  const uint32_t d = depth % dims;
+__device__ void hist_last_body(uint32_t depth, const SetDesc& S, const DevParams* P,
+                               const LevelCtx& c, const uint8_t* keys, const NodeSel* sel,
+                               uint32_t* hist, uint32_t* rows, uint32_t* lh) {
+  const uint64_t n = S.n;
+  const uint32_t d = depth % S.dims;
   const DigitPlan pl = digit_plan(P->G[d]);
   const uint32_t pass = pl.npass - 1;
-  const uint64_t j = blockIdx.x / chunks, ch = blockIdx.x % chunks;
+  const uint64_t j = c.lb / c.sh.chunks, ch = c.lb % c.sh.chunks;
   uint64_t st, sz;
   node_span(n, depth, j, &st, &sz);
-  if (sz <= r) return;
-  const uint32_t w = pl.width[pass], sh = pl.shift[pass], hs = sh + w;
+  if (sz <= S.r) return;
+  const uint32_t w = dp_width(pl, pass), sh = dp_shift(pl, pass), hs = sh + w;
   const uint32_t prefix = pass == 0 ? 0u : sel[j].prefix;
   const uint32_t nb = 1u << w, mask = nb - 1;
   lh[threadIdx.x] = 0;
   __syncthreads();
-  const KT* q = kp<KT>(keys, n, d) + st;
-  const uint64_t beg = ch * (uint64_t)chunk_elems;
-  const uint64_t end = beg + chunk_elems < sz ? beg + chunk_elems : sz;
+  const KT* q = (const KT*)keys + (uint64_t)d * n + st;
+  const uint64_t beg = ch * (uint64_t)c.sh.chunk_elems;
+  const uint64_t end = beg + c.sh.chunk_elems < sz ? beg + c.sh.chunk_elems : sz;
   uint32_t below = 0;
-  for (uint64_t p = beg + threadIdx.x; p < end; p += blockDim.x) {
-    uint32_t v = q[p];
-    uint32_t hi = v >> hs;
-    if (hi == prefix)
-      atomicAdd(&lh[(v >> sh) & mask], 1u);
-    else if (hi < prefix)
-      ++below;
+  for (uint64_t g = beg; g < end; g += kGroup) {
+    uint32_t v[kRows];
+#pragma unroll
+    for (int i = 0; i < kRows; ++i) {
+      const uint64_t p = g + (uint64_t)i * kBlock + threadIdx.x;
+      v[i] = p < end ? (uint32_t)q[p] : 0xffffffffu;
+    }
+#pragma unroll
+    for (int i = 0; i < kRows; ++i) {
+      if (v[i] == 0xffffffffu) continue;
+      const uint32_t hi = v[i] >> hs;
+      if (hi == prefix)
+        atomicAdd(&lh[(v[i] >> sh) & mask], 1u);
+      else if (hi < prefix)
+        ++below;
+    }
   }
   __syncthreads();
-  uint32_t cnt = threadIdx.x < nb ? lh[threadIdx.x] : 0u;
+  const uint32_t cnt = threadIdx.x < nb ? lh[threadIdx.x] : 0u;
   uint64_t tot;
-  uint64_t ex = block_exscan_u64(((uint64_t)below << 32) | cnt, &tot);
-  uint32_t* row = rows + (uint64_t)blockIdx.x * kRowStride;
+  const uint64_t ex = block_exscan_u64(((uint64_t)below << 32) | cnt, &tot);
+  uint32_t* row = rows + c.lb * kRowStride;
   row[threadIdx.x] = (uint32_t)ex;  // candidates with a smaller last digit
   if (threadIdx.x == 0) {
     row[256] = (uint32_t)tot;          // all candidates of the chunk
     row[257] = (uint32_t)(tot >> 32);  // members below the prefix
   }
-  if (threadIdx.x < nb && cnt) atomicAdd(&hist[(j << w) + threadIdx.x], cnt);
+  if (threadIdx.x < nb && cnt) atomicAdd(&hist[(j << 8) + threadIdx.x], cnt);
 }
 
-__global__ void __launch_bounds__(kBlock) k_hist_last(uint32_t depth, uint64_t n, uint32_t dims,
-                                                      uint32_t r, uint64_t chunks,
-                                                      uint32_t chunk_elems, const DevParams* P,
-                                                      const void* keys, const NodeSel* sel,
-                                                      uint32_t* hist, uint32_t* rows) {
+__global__ void __launch_bounds__(kBlock) k_hist_last(uint32_t depth, uint32_t nsets,
+                                                      const uint64_t* pre, const SetDesc* sets,
+                                                      const DevParams* params, uint8_t* keys0,
+                                                      const NodeSel* sel0, uint32_t* hist0,
+                                                      uint32_t* rows0) {
+  const LevelCtx c = level_ctx(nsets, pre, sets, depth);
+  const SetDesc& S = sets[c.s];
+  const DevParams* P = params + c.s;
   if (P->status != BBX_OK) return;
   __shared__ uint32_t lh[kBlock];
+  const uint8_t* keys = keys0 + S.key_off;
   if (P->key16)
-    hist_last_body<uint16_t>(depth, n, dims, r, chunks, chunk_elems, P, keys, sel, hist, rows, lh);
+    hist_last_body<uint16_t>(depth, S, P, c, keys, sel0 + S.sel_off, hist0 + S.hist_off,
+                             rows0 + S.rows_off, lh);
   else
-    hist_last_body<uint32_t>(depth, n, dims, r, chunks, chunk_elems, P, keys, sel, hist, rows, lh);
+    hist_last_body<uint32_t>(depth, S, P, c, keys, sel0 + S.sel_off, hist0 + S.hist_off,
+                             rows0 + S.rows_off, lh);
 }
 
-__global__ void __launch_bounds__(kBlock) k_select_last(uint32_t depth, uint64_t n, uint32_t dims,
-                                                        uint32_t r, uint64_t chunks,
-                                                        const DevParams* P, NodeSel* sel,
-                                                        const uint32_t* hist, const uint32_t* rows,
-                                                        uint32_t* chunk_base) {
+__global__ void __launch_bounds__(kBlock) k_select_last(uint32_t depth, uint32_t nsets,
+                                                        const uint64_t* pre, const SetDesc* sets,
+                                                        const DevParams* params, NodeSel* sel0,
+                                                        uint32_t* hist0, const uint32_t* rows0,
+                                                        uint32_t* cb0) {
+  const uint32_t s = find_set(pre, nsets, blockIdx.x);
+  const SetDesc& S = sets[s];
+  const DevParams* P = params + s;
   if (P->status != BBX_OK) return;
-  const DigitPlan pl = digit_plan(P->G[depth % dims]);
+  const DigitPlan pl = digit_plan(P->G[depth % S.dims]);
   const uint32_t pass = pl.npass - 1;
-  const uint64_t j = blockIdx.x;
+  const uint64_t j = blockIdx.x - pre[s];
   uint64_t st, sz;
-  node_span(n, depth, j, &st, &sz);
-  if (sz <= r) return;
-  const uint32_t w = pl.width[pass];
+  node_span(S.n, depth, j, &st, &sz);
+  if (sz <= S.r) return;
+  const uint64_t chunks = level_shape(S.n, depth).chunks;
+  NodeSel* sel = sel0 + S.sel_off;
+  uint32_t* hist = hist0 + S.hist_off + (j << 8);
+  const uint32_t* rows = rows0 + S.rows_off;
+  uint32_t* chunk_base = cb0 + S.cb_off;
+  const uint32_t w = dp_width(pl, pass);
   const uint32_t nb = 1u << w;
   const uint32_t rank = pass == 0 ? (uint32_t)(sz >> 1) : sel[j].rank;
   const uint32_t prefix = pass == 0 ? 0u : sel[j].prefix;
   __shared__ uint32_t s_b, s_jeq;
   if (threadIdx.x == 0) s_b = 0, s_jeq = 0;  // ordered before the finder by the scan's barriers
-  uint32_t c = threadIdx.x < nb ? hist[(j << w) + threadIdx.x] : 0u;
+  const uint32_t c = threadIdx.x < nb ? hist[threadIdx.x] : 0u;
+  if (c) hist[threadIdx.x] = 0;
   uint64_t tot;
-  uint64_t cum = block_exscan_u64(c, &tot);
+  const uint64_t cum = block_exscan_u64(c, &tot);
   if (threadIdx.x < nb && cum <= rank && rank < cum + c) {
     s_b = threadIdx.x;
     s_jeq = rank - (uint32_t)cum;
@@ -228,12 +311,12 @@ __global__ void __launch_bounds__(kBlock) k_select_last(uint32_t depth, uint64_t
   __syncthreads();
   const uint32_t b = s_b, jeq = s_jeq;
   if (threadIdx.x == 0) {
-    NodeSel s;
-    s.prefix = prefix;
-    s.rank = rank;
-    s.v = (prefix << w) | b;
-    s.jeq = jeq;
-    sel[j] = s;
+    NodeSel ns;
+    ns.prefix = prefix;
+    ns.rank = rank;
+    ns.v = (prefix << w) | b;
+    ns.jeq = jeq;
+    sel[j] = ns;
   }
   // per-chunk counts of members below v (lt) and equal to v (eq), then an
   // exclusive scan over the node's chunks (both packed in one u64)
@@ -241,20 +324,20 @@ __global__ void __launch_bounds__(kBlock) k_select_last(uint32_t depth, uint64_t
   const uint64_t c0 = threadIdx.x * per;
   uint64_t mine = 0;
   for (uint64_t k = 0; k < per; ++k) {
-    uint64_t ch = c0 + k;
+    const uint64_t ch = c0 + k;
     if (ch >= chunks) break;
     const uint32_t* row = rows + (j * chunks + ch) * kRowStride;
-    uint64_t lt = (uint64_t)row[257] + row[b];
-    uint64_t eq = (uint64_t)row[b + 1] - row[b];
+    const uint64_t lt = (uint64_t)row[257] + row[b];
+    const uint64_t eq = (uint64_t)row[b + 1] - row[b];
     mine += (eq << 32) | lt;
   }
   uint64_t run = block_exscan_u64(mine, &tot);
   for (uint64_t k = 0; k < per; ++k) {
-    uint64_t ch = c0 + k;
+    const uint64_t ch = c0 + k;
     if (ch >= chunks) break;
     const uint32_t* row = rows + (j * chunks + ch) * kRowStride;
-    uint64_t lt = (uint64_t)row[257] + row[b];
-    uint64_t eq = (uint64_t)row[b + 1] - row[b];
+    const uint64_t lt = (uint64_t)row[257] + row[b];
+    const uint64_t eq = (uint64_t)row[b + 1] - row[b];
     chunk_base[(j * chunks + ch) * 2 + 0] = (uint32_t)run;
     chunk_base[(j * chunks + ch) * 2 + 1] = (uint32_t)(run >> 32);
     run += (eq << 32) | lt;
@@ -262,17 +345,19 @@ __global__ void __launch_bounds__(kBlock) k_select_last(uint32_t depth, uint64_t
 }
 
 template <typename KT>
-__device__ void scatter_body(uint32_t depth, uint64_t n, uint32_t dims, uint32_t r,
-                             uint64_t chunks, uint32_t chunk_elems, DevParams* P,
-                             const NodeSel* sel, const uint32_t* chunk_base, const void* src,
-                             void* dst, const uint32_t* isrc, uint32_t* idst) {
+__device__ void scatter_body(uint32_t depth, const SetDesc& S, DevParams* P, const LevelCtx& c,
+                             const NodeSel* sel, const uint32_t* chunk_base, const uint8_t* src,
+                             uint8_t* dst, const uint32_t* isrc, uint32_t* idst, uint32_t* hist,
+                             uint32_t* lhist) {
+  const uint64_t n = S.n;
+  const uint32_t dims = S.dims, r = S.r;
   const uint32_t d = depth % dims;
-  const uint64_t j = blockIdx.x / chunks, ch = blockIdx.x % chunks;
+  const uint64_t j = c.lb / c.sh.chunks, ch = c.lb % c.sh.chunks;
   uint64_t st, sz;
   node_span(n, depth, j, &st, &sz);
-  const uint64_t beg = ch * (uint64_t)chunk_elems;
+  const uint64_t beg = ch * (uint64_t)c.sh.chunk_elems;
   if (beg >= sz) return;
-  const uint64_t end = beg + chunk_elems < sz ? beg + chunk_elems : sz;
+  const uint64_t end = beg + c.sh.chunk_elems < sz ? beg + c.sh.chunk_elems : sz;
   const KT* s0 = (const KT*)src;
   KT* d0 = (KT*)dst;
   if (sz <= r) {  // leaf: copy through
@@ -282,116 +367,138 @@ __device__ void scatter_body(uint32_t depth, uint64_t n, uint32_t dims, uint32_t
     }
     return;
   }
-  const NodeSel s = sel[j];
-  const uint32_t v = s.v, jeq = s.jeq;
+  // next level's first digit, built here when that level runs a mid pass
   const uint64_t half = sz >> 1;
-  uint64_t lt_run = chunk_base[blockIdx.x * 2 + 0];
-  uint64_t eq_run = chunk_base[blockIdx.x * 2 + 1];
-  __shared__ uint32_t wl[2][kBlock / 64], we[2][kBlock / 64];
+  const uint32_t dn = (depth + 1) % dims;
+  const DigitPlan pn = digit_plan(P->G[dn]);
+  const bool fuse = depth + 1 < S.gl && pn.npass >= 2;
+  const uint32_t wn = pn.width[0], shn = pn.shift[0], maskn = (1u << wn) - 1;
+  const bool cl = fuse && half > r, cr = fuse && (sz - half) > r;  // children that split again
+  if (fuse) lhist[threadIdx.x] = lhist[kBlock + threadIdx.x] = 0;
+  const NodeSel ns = sel[j];
+  const uint32_t v = ns.v, jeq = ns.jeq;
+  uint64_t lt_run = chunk_base[c.lb * 2 + 0];
+  uint64_t eq_run = chunk_base[c.lb * 2 + 1];
+  __shared__ uint32_t cnt[2][kBlock / 64][kRows][2];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const uint64_t below_me = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const KT* q = s0 + (uint64_t)d * n + st;
-  int it = 0;
-  for (uint64_t base = beg; base < end; base += blockDim.x, ++it) {
-    const uint64_t p = base + threadIdx.x;
-    const bool active = p < end;
-    const uint32_t key = active ? (uint32_t)q[p] : 0u;
-    const bool lt = active && key < v;
-    const bool eq = active && key == v;
-    const uint64_t mlt = __ballot(lt), meq = __ballot(eq);
-    const int buf = it & 1;
-    if (lane == 0) {
-      wl[buf][wv] = popc64(mlt);
-      we[buf][wv] = popc64(meq);
+  int buf = 0;
+  for (uint64_t g = beg; g < end; g += kGroup, buf ^= 1) {
+    uint32_t key[kRows][3];
+    uint64_t mlt[kRows], meq[kRows];
+#pragma unroll
+    for (int i = 0; i < kRows; ++i) {
+      const uint64_t p = g + (uint64_t)i * kBlock + threadIdx.x;
+      const bool active = p < end;
+#pragma unroll
+      for (uint32_t dd = 0; dd < 3; ++dd)
+        key[i][dd] = (active && dd < dims) ? (uint32_t)s0[(uint64_t)dd * n + st + p] : 0u;
+    }
+#pragma unroll
+    for (int i = 0; i < kRows; ++i) {
+      const uint64_t p = g + (uint64_t)i * kBlock + threadIdx.x;
+      const bool active = p < end;
+      const uint32_t kd = pick3(key[i], d);
+      mlt[i] = __ballot(active && kd < v);
+      meq[i] = __ballot(active && kd == v);
+      if (lane == 0) {
+        cnt[buf][wv][i][0] = popc64(mlt[i]);
+        cnt[buf][wv][i][1] = popc64(meq[i]);
+      }
     }
     __syncthreads();
-    uint64_t ol = 0, oe = 0, tl = 0, te = 0;
-    for (int k = 0; k < kBlock / 64; ++k) {
-      if (k < wv) ol += wl[buf][k], oe += we[buf][k];
-      tl += wl[buf][k];
-      te += we[buf][k];
-    }
-    if (active) {
-      const uint64_t L = lt_run + ol + popc64(mlt & below_me);
-      const uint64_t E = eq_run + oe + popc64(meq & below_me);
-      const uint64_t lb = L + (E < jeq ? E : (uint64_t)jeq);
-      const bool left = lt || (eq && E < jeq);
-      const uint64_t dest = left ? lb : half + (p - lb);
-      if (dest >= sz) {  // inconsistent counts: never expected; refuse to write out of the node
-        P->status = BBX_EHIP;
-        continue;
+    uint64_t off_l = 0, off_e = 0;  // elements of this group before row i
+#pragma unroll
+    for (int i = 0; i < kRows; ++i) {
+      uint64_t rl = 0, re = 0, bl = 0, be = 0;
+      for (int w = 0; w < kBlock / 64; ++w) {
+        const uint32_t a = cnt[buf][w][i][0], b = cnt[buf][w][i][1];
+        if (w < wv) bl += a, be += b;
+        rl += a;
+        re += b;
       }
-      for (uint32_t dd = 0; dd < dims; ++dd)
-        d0[(uint64_t)dd * n + st + dest] = dd == d ? (KT)key : s0[(uint64_t)dd * n + st + p];
-      if (isrc) idst[st + dest] = isrc[st + p];
+      const uint64_t p = g + (uint64_t)i * kBlock + threadIdx.x;
+      if (p < end) {
+        const uint32_t kd = pick3(key[i], d);
+        const bool lt = kd < v, eq = kd == v;
+        const uint64_t L = lt_run + off_l + bl + popc64(mlt[i] & below_me);
+        const uint64_t E = eq_run + off_e + be + popc64(meq[i] & below_me);
+        const uint64_t lb = L + (E < jeq ? E : (uint64_t)jeq);
+        const bool left = lt || (eq && E < jeq);
+        const uint64_t dest = left ? lb : half + (p - lb);
+        if (dest < sz) {
+#pragma unroll
+          for (uint32_t dd = 0; dd < 3; ++dd)
+            if (dd < dims) d0[(uint64_t)dd * n + st + dest] = (KT)key[i][dd];
+          if (isrc) idst[st + dest] = isrc[st + p];
+          if (left ? cl : cr)
+            atomicAdd(&lhist[(left ? 0u : (uint32_t)kBlock) + ((pick3(key[i], dn) >> shn) & maskn)], 1u);
+        } else {
+          P->status = BBX_EHIP;  // inconsistent counts: never expected
+        }
+      }
+      off_l += rl;
+      off_e += re;
     }
-    lt_run += tl;
-    eq_run += te;
+    lt_run += off_l;
+    eq_run += off_e;
+  }
+  if (fuse) {
+    __syncthreads();
+    for (uint32_t child = 0; child < 2; ++child) {
+      const uint32_t cnum = lhist[child * kBlock + threadIdx.x];
+      if (cnum) atomicAdd(&hist[((2 * j + child) << 8) + threadIdx.x], cnum);
+    }
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_scatter(uint32_t depth, uint64_t n, uint32_t dims,
-                                                    uint32_t r, uint64_t chunks,
-                                                    uint32_t chunk_elems, DevParams* P,
-                                                    const NodeSel* sel,
-                                                    const uint32_t* chunk_base, const void* src,
-                                                    void* dst, const uint32_t* isrc,
-                                                    uint32_t* idst) {
+__global__ void __launch_bounds__(kBlock) k_scatter(uint32_t depth, uint32_t nsets,
+                                                    const uint64_t* pre, const SetDesc* sets,
+                                                    DevParams* params, const NodeSel* sel0,
+                                                    const uint32_t* cb0, uint8_t* src0,
+                                                    uint8_t* dst0, uint32_t* isrc0,
+                                                    uint32_t* idst0, uint32_t* hist0) {
+  const LevelCtx c = level_ctx(nsets, pre, sets, depth);
+  const SetDesc& S = sets[c.s];
+  DevParams* P = params + c.s;
   if (P->status != BBX_OK) return;
+  __shared__ uint32_t lhist[2 * kBlock];
+  const uint32_t* isrc = S.perm ? isrc0 + S.idx_off : nullptr;
+  uint32_t* idst = S.perm ? idst0 + S.idx_off : nullptr;
   if (P->key16)
-    scatter_body<uint16_t>(depth, n, dims, r, chunks, chunk_elems, P, sel, chunk_base, src, dst,
-                           isrc, idst);
+    scatter_body<uint16_t>(depth, S, P, c, sel0 + S.sel_off, cb0 + S.cb_off, src0 + S.key_off,
+                           dst0 + S.key_off, isrc, idst, hist0 + S.hist_off, lhist);
   else
-    scatter_body<uint32_t>(depth, n, dims, r, chunks, chunk_elems, P, sel, chunk_base, src, dst,
-                           isrc, idst);
+    scatter_body<uint32_t>(depth, S, P, c, sel0 + S.sel_off, cb0 + S.cb_off, src0 + S.key_off,
+                           dst0 + S.key_off, isrc, idst, hist0 + S.hist_off, lhist);
 }
 
-LevelShape level_shape(const CompressPlan& p, uint32_t depth) {
-  LevelShape sh;
-  sh.depth = depth;
-  sh.nodes = 1ull << depth;
-  const uint64_t maxsz = (p.n + sh.nodes - 1) >> depth;  // ceil(n / 2^depth)
-  const uint64_t target_blocks = 4096;
-  uint64_t cpn = (target_blocks + sh.nodes - 1) / sh.nodes;
-  if (cpn == 0) cpn = 1;
-  uint64_t elems = (maxsz + cpn - 1) / cpn;
-  uint64_t iters = (elems + kBlock - 1) / kBlock;
-  if (iters < 16) iters = 16;
-  sh.iters = (uint32_t)iters;
-  const uint64_t ce = iters * kBlock;
-  sh.chunks = (maxsz + ce - 1) / ce;
-  if (sh.chunks == 0) sh.chunks = 1;
-  return sh;
-}
-
-hipError_t launch_levels(const CompressPlan& p, const CompressWs& w, hipStream_t s,
-                         int* final_buf) {
-  int cur = 0;
-  for (uint32_t k = 0; k < p.global_levels; ++k) {
-    const LevelShape sh = level_shape(p, k);
-    const uint64_t grid = sh.nodes * sh.chunks;
-    const uint32_t ce = sh.iters * kBlock;
-    const uint32_t fill_grid = 1024;
-    for (uint32_t pass = 0; pass < 2; ++pass) {
-      BBX_LAUNCH("level_fill", k_fill_hist, fill_grid, kBlock, 0, s, k, pass, 0u, p.dims,
-                 sh.nodes, w.params, w.hist);
-      BBX_LAUNCH("level_hist_mid", k_hist_mid, grid, kBlock, 0, s, k, pass, p.n, p.dims, p.r,
-                 sh.chunks, ce, w.params, w.keys[cur], w.sel, w.hist);
-      BBX_LAUNCH("level_select_mid", k_select_mid, sh.nodes, kBlock, 0, s, k, pass, p.n, p.dims,
-                 p.r, w.params, w.sel, w.hist);
+hipError_t launch_levels(const BatchPlan& bp, const Ws& w, hipStream_t s) {
+  if (bp.max_gl == 0) return hipGetLastError();
+  BBX_LAUNCH("level_hist_zero", k_hist_zero, 1024, kBlock, 0, s, bp.hist_entries, w.hist);
+  for (uint32_t k = 0; k < bp.max_gl; ++k) {
+    const uint64_t* plv = w.pre + bp.o_lv[k];
+    const uint64_t* pnd = w.pre + bp.o_nd[k];
+    const int cur = k & 1;
+    if (k == 0)
+      BBX_LAUNCH("level_hist_mid", k_hist_root, bp.g_lv[0], kBlock, 0, s, bp.nsets, plv, w.sets,
+                 w.params, w.keys[0], w.hist);
+    // mid passes: pass 0 was built above or by the previous scatter
+    for (uint32_t pass = 0; pass < 3; ++pass) {
+      if (pass > 0)
+        BBX_LAUNCH("level_hist_mid", k_hist_mid, bp.g_lv[k], kBlock, 0, s, k, pass, bp.nsets, plv,
+                   w.sets, w.params, w.keys[cur], w.sel, w.hist);
+      BBX_LAUNCH("level_select_mid", k_select_mid, bp.g_nd[k], kBlock, 0, s, k, pass, bp.nsets, pnd,
+                 w.sets, w.params, w.sel, w.hist);
     }
-    BBX_LAUNCH("level_fill", k_fill_hist, fill_grid, kBlock, 0, s, k, 0u, 1u, p.dims, sh.nodes,
-               w.params, w.hist);
-    BBX_LAUNCH("level_hist_last", k_hist_last, grid, kBlock, 0, s, k, p.n, p.dims, p.r, sh.chunks,
-               ce, w.params, w.keys[cur], w.sel, w.hist, w.rows);
-    BBX_LAUNCH("level_select_last", k_select_last, sh.nodes, kBlock, 0, s, k, p.n, p.dims, p.r,
-               sh.chunks, w.params, w.sel, w.hist, w.rows, w.chunk_base);
-    BBX_LAUNCH("level_scatter", k_scatter, grid, kBlock, 0, s, k, p.n, p.dims, p.r, sh.chunks, ce,
-               w.params, w.sel, w.chunk_base, w.keys[cur], w.keys[cur ^ 1],
-               p.track_idx ? w.idx[cur] : nullptr, p.track_idx ? w.idx[cur ^ 1] : nullptr);
-    cur ^= 1;
+    BBX_LAUNCH("level_hist_last", k_hist_last, bp.g_lv[k], kBlock, 0, s, k, bp.nsets, plv, w.sets,
+               w.params, w.keys[cur], w.sel, w.hist, w.rows);
+    BBX_LAUNCH("level_select_last", k_select_last, bp.g_nd[k], kBlock, 0, s, k, bp.nsets, pnd,
+               w.sets, w.params, w.sel, w.hist, w.rows, w.chunk_base);
+    BBX_LAUNCH("level_scatter", k_scatter, bp.g_lv[k], kBlock, 0, s, k, bp.nsets, plv, w.sets,
+               w.params, w.sel, w.chunk_base, w.keys[cur], w.keys[cur ^ 1], w.idx[cur],
+               w.idx[cur ^ 1], w.hist);
   }
-  *final_buf = cur;
   return hipGetLastError();
 }
 

@@ -1,9 +1,11 @@
-// k_pack.hip -- leaf bit offsets and bit packing (Sec. 4.2, storage layout).
+// k_pack.hip -- leaf bit offsets and bit packing (Sec. 4.2, storage layout),
+// for every set of a batch.
 //
 //   k_scan_reduce / k_scan_top / k_scan_down
-//        exclusive prefix sum of the per-leaf payload bits (depth-first
-//        order), in place; the top pass also fixes the section sizes:
-//        meta = n_leaves * (dims*mbits + sum G_d) bits, payload = the total
+//        exclusive prefix sum of the per-leaf payload bits over the whole
+//        batch (depth-first leaf order inside each set); a set's offsets are
+//        differences against its first leaf's offset
+//   k_set_sizes     per set: payload and meta bits, stream size, capacity check
 //   k_pack_meta     one thread per 64-bit meta word: gathers the fixed-stride
 //                   leaf records (widths, reference codes) that overlap it
 //   k_pack_payload  one thread per 64-bit payload word: finds the leaf holding
@@ -43,9 +45,10 @@ __device__ inline uint64_t bexscan(uint64_t v, uint64_t* total) {
   return off + x - v;
 }
 
+// P (optional): skip when its status is not OK
 __global__ void __launch_bounds__(kBlock) k_scan_reduce(uint64_t count, const uint64_t* bits,
                                                         uint64_t* part, const DevParams* P) {
-  if (P->status != BBX_OK) return;
+  if (P && P->status != BBX_OK) return;
   const uint64_t base = blockIdx.x * kScanChunk + (uint64_t)threadIdx.x * kScanPer;
   uint64_t s = 0;
   for (int k = 0; k < kScanPer; ++k)
@@ -55,14 +58,12 @@ __global__ void __launch_bounds__(kBlock) k_scan_reduce(uint64_t count, const ui
   if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
-// mode 0 (compress): record the section sizes, check out_cap.
-// mode 1 (decompress): the total must equal the header's payload bits.
+// Exclusive scan of the block partials; the grand total goes to *total.
+// With P: the total must equal expect (decoding) or the status turns ECORRUPT.
 __global__ void __launch_bounds__(kBlock) k_scan_top(uint64_t nparts, uint64_t* part,
-                                                     DevParams* P, uint32_t mode,
-                                                     uint64_t n_leaves, uint32_t dims,
-                                                     uint32_t mbits, uint64_t out_cap,
-                                                     uint64_t expect_payload) {
-  if (P->status != BBX_OK) return;
+                                                     uint64_t* total, DevParams* P,
+                                                     uint64_t expect) {
+  if (P && P->status != BBX_OK) return;
   const uint64_t per = (nparts + kBlock - 1) / kBlock;
   const uint64_t b0 = threadIdx.x * per;
   uint64_t s = 0;
@@ -72,21 +73,14 @@ __global__ void __launch_bounds__(kBlock) k_scan_top(uint64_t nparts, uint64_t* 
   uint64_t run = bexscan(s, &tot);
   for (uint64_t k = 0; k < per; ++k)
     if (b0 + k < nparts) {
-      uint64_t v = part[b0 + k];
+      const uint64_t v = part[b0 + k];
       part[b0 + k] = run;
       run += v;
     }
   if (threadIdx.x == 0) {
-    if (mode == 0) {
-      uint32_t sumG = 0;
-      for (uint32_t d = 0; d < dims; ++d) sumG += P->G[d];
-      const uint64_t meta = n_leaves * (uint64_t)(dims * mbits + sumG);
-      P->meta_bits = meta;
-      P->payload_bits = tot;
-      P->total_bytes = kHeaderBytes + ((meta + 63) / 64) * 8 + ((tot + 63) / 64) * 8;
-      if (P->total_bytes > out_cap) P->status = BBX_ENOSPC;
-    } else {
-      if (tot != expect_payload) P->status = BBX_ECORRUPT;
+    if (total) *total = tot;
+    if (P) {
+      if (tot != expect) P->status = BBX_ECORRUPT;
       P->payload_bits = tot;
     }
   }
@@ -94,7 +88,7 @@ __global__ void __launch_bounds__(kBlock) k_scan_top(uint64_t nparts, uint64_t* 
 
 __global__ void __launch_bounds__(kBlock) k_scan_down(uint64_t count, uint64_t* bits,
                                                       const uint64_t* part, const DevParams* P) {
-  if (P->status != BBX_OK) return;
+  if (P && P->status != BBX_OK) return;
   const uint64_t base = blockIdx.x * kScanChunk + (uint64_t)threadIdx.x * kScanPer;
   uint64_t v[kScanPer];
   uint64_t s = 0;
@@ -111,16 +105,39 @@ __global__ void __launch_bounds__(kBlock) k_scan_down(uint64_t count, uint64_t* 
     }
 }
 
-hipError_t launch_scan(uint64_t count, uint64_t* bits, uint64_t* part, DevParams* params,
-                       const CompressPlan* cp, uint64_t expect_payload, size_t out_cap,
-                       uint64_t* /*d_size*/, hipStream_t s) {
+static hipError_t scan_launch(uint64_t count, uint64_t* bits, uint64_t* part, uint64_t* total,
+                              DevParams* P, uint64_t expect, hipStream_t s) {
   const uint64_t nb = scan_blocks(count);
-  if (nb > 0)
-    BBX_LAUNCH("scan_reduce", k_scan_reduce, nb, kBlock, 0, s, count, bits, part, params);
-  BBX_LAUNCH("scan_top", k_scan_top, 1, kBlock, 0, s, nb, part, params, cp ? 0u : 1u, count,
-             cp ? cp->dims : 0u, cp ? cp->mbits : 0u, (uint64_t)out_cap, expect_payload);
-  if (nb > 0) BBX_LAUNCH("scan_down", k_scan_down, nb, kBlock, 0, s, count, bits, part, params);
+  if (nb > 0) BBX_LAUNCH("scan_reduce", k_scan_reduce, nb, kBlock, 0, s, count, bits, part, P);
+  BBX_LAUNCH("scan_top", k_scan_top, 1, kBlock, 0, s, nb, part, total, P, expect);
+  if (nb > 0) BBX_LAUNCH("scan_down", k_scan_down, nb, kBlock, 0, s, count, bits, part, P);
   return hipGetLastError();
+}
+
+hipError_t launch_dec_scan(uint64_t count, uint64_t* bits, uint64_t* part, DevParams* params,
+                           uint64_t expect_payload, hipStream_t s) {
+  return scan_launch(count, bits, part, nullptr, params, expect_payload, s);
+}
+
+// per set: payload/meta bits, stream size, capacity check
+__global__ void k_set_sizes(uint32_t nsets, const SetDesc* sets, DevParams* params,
+                            const uint64_t* off, uint64_t total_leaves, const uint64_t* total) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nsets) return;
+  const SetDesc& S = sets[s];
+  DevParams* P = params + s;
+  if (P->status != BBX_OK) return;
+  const uint64_t b = S.leaf_off, e = S.leaf_off + S.n_leaves;
+  const uint64_t base = S.n_leaves ? off[b] : 0;
+  const uint64_t endv = S.n_leaves ? (e < total_leaves ? off[e] : *total) : 0;
+  uint32_t sumG = 0;
+  for (uint32_t d = 0; d < S.dims; ++d) sumG += P->G[d];
+  const uint64_t meta = S.n_leaves * (uint64_t)(S.dims * S.mbits + sumG);
+  P->payload_base = base;
+  P->meta_bits = meta;
+  P->payload_bits = endv - base;
+  P->total_bytes = kHeaderBytes + ((meta + 63) / 64) * 8 + ((P->payload_bits + 63) / 64) * 8;
+  if (P->total_bytes > S.out_cap) P->status = BBX_ENOSPC;
 }
 
 // ---------------------------------------------------------------- packing
@@ -138,20 +155,27 @@ __device__ inline void or_into(uint64_t& word, uint64_t w0, u128 val, uint64_t a
     word |= (uint64_t)(val >> (-rel));
 }
 
-__global__ void __launch_bounds__(kBlock) k_pack_meta(uint64_t n_leaves, uint32_t dims,
-                                                      uint32_t mbits, const DevParams* P,
-                                                      const LeafRec* leaves, uint8_t* out) {
+__global__ void __launch_bounds__(kBlock) k_pack_meta(uint32_t nsets, const uint64_t* pre,
+                                                      const SetDesc* sets,
+                                                      const DevParams* params,
+                                                      const LeafRec* leaves0) {
+  const uint32_t s = find_set(pre, nsets, blockIdx.x);
+  const SetDesc& S = sets[s];
+  const DevParams* P = params + s;
   if (P->status != BBX_OK) return;
-  uint32_t G[3] = {P->G[0], P->G[1], P->G[2]};
-  uint32_t S = dims * mbits;
-  for (uint32_t d = 0; d < dims; ++d) S += G[d];
+  const uint64_t lb = blockIdx.x - pre[s], nblk = pre[s + 1] - pre[s];
+  const uint32_t dims = S.dims, mbits = S.mbits;
+  const uint32_t G[3] = {P->G[0], P->G[1], P->G[2]};
+  uint32_t Sb = dims * mbits;
+  for (uint32_t d = 0; d < dims; ++d) Sb += G[d];
   const uint64_t nwords = (P->meta_bits + 63) / 64;
-  uint64_t* meta = (uint64_t*)(out + kHeaderBytes);
-  for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nwords;
-       w += (uint64_t)gridDim.x * blockDim.x) {
+  const LeafRec* leaves = leaves0 + S.leaf_off;
+  uint64_t* meta = (uint64_t*)(S.out + kHeaderBytes);
+  for (uint64_t w = lb * blockDim.x + threadIdx.x; w < nwords; w += nblk * blockDim.x) {
     const uint64_t b0 = w * 64;
-    uint64_t i0 = b0 / S, i1 = (b0 + 63) / S;
-    if (i1 >= n_leaves) i1 = n_leaves - 1;
+    const uint64_t i0 = b0 / Sb;
+    uint64_t i1 = (b0 + 63) / Sb;
+    if (i1 >= S.n_leaves) i1 = S.n_leaves - 1;
     uint64_t word = 0;
     for (uint64_t i = i0; i <= i1; ++i) {
       const LeafRec rec = leaves[i];
@@ -165,7 +189,7 @@ __global__ void __launch_bounds__(kBlock) k_pack_meta(uint64_t n_leaves, uint32_
         v |= (u128)rec.qref[d] << at;
         at += G[d];
       }
-      or_into(word, b0, v, i * S, S);
+      or_into(word, b0, v, i * Sb, Sb);
     }
     meta[w] = word;
   }
@@ -189,11 +213,12 @@ __device__ inline u128 member_code(const KT* keys, uint64_t n, uint32_t dims, co
 
 __device__ inline uint32_t sum_m(uint32_t m) { return (m & 0xffu) + ((m >> 8) & 0xffu) + ((m >> 16) & 0xffu); }
 
-// largest i in [lo, hi] with off[i] <= b (off non-decreasing, off[lo] <= b)
-__device__ inline uint64_t search_off(const uint64_t* off, uint64_t lo, uint64_t hi, uint64_t b) {
+// largest i in [lo, hi] with off[i] - base <= b (offsets non-decreasing)
+__device__ inline uint64_t search_off(const uint64_t* off, uint64_t base, uint64_t lo, uint64_t hi,
+                                      uint64_t b) {
   while (lo < hi) {
-    uint64_t mid = lo + (hi - lo + 1) / 2;
-    if (off[mid] <= b)
+    const uint64_t mid = lo + (hi - lo + 1) / 2;
+    if (off[mid] - base <= b)
       lo = mid;
     else
       hi = mid - 1;
@@ -202,20 +227,21 @@ __device__ inline uint64_t search_off(const uint64_t* off, uint64_t lo, uint64_t
 }
 
 template <typename KT>
-__device__ void pack_payload_body(uint64_t n, uint32_t dims, uint64_t n_leaves,
-                                  const DevParams* P, const LeafRec* leaves, const uint64_t* off,
-                                  const KT* keys, uint8_t* out, uint64_t* s_off) {
+__device__ void pack_payload_body(const SetDesc& S, const DevParams* P, uint64_t lb, uint64_t nblk,
+                                  const LeafRec* leaves, const uint64_t* off, const KT* keys,
+                                  uint64_t* s_off) {
   __shared__ uint64_t s_lo, s_cnt;
-  const uint64_t total = P->payload_bits;
-  const uint64_t nwords = (total + 63) / 64;
-  uint64_t* pay = (uint64_t*)(out + kHeaderBytes + ((P->meta_bits + 63) / 64) * 8);
+  const uint64_t n = S.n, nl = S.n_leaves, base = P->payload_base;
+  const uint32_t dims = S.dims;
+  const uint64_t nwords = (P->payload_bits + 63) / 64;
+  uint64_t* pay = (uint64_t*)(S.out + kHeaderBytes + ((P->meta_bits + 63) / 64) * 8);
   const uint64_t ngroups = (nwords + kBlock - 1) / kBlock;
-  for (uint64_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+  for (uint64_t grp = lb; grp < ngroups; grp += nblk) {
     const uint64_t W0 = grp * kBlock;
     const uint64_t Wend = W0 + kBlock < nwords ? W0 + kBlock : nwords;
     if (threadIdx.x == 0) {
-      uint64_t lo = search_off(off, 0, n_leaves - 1, W0 * 64);
-      uint64_t hi = search_off(off, lo, n_leaves - 1, Wend * 64 - 1);
+      const uint64_t lo = search_off(off, base, 0, nl - 1, W0 * 64);
+      const uint64_t hi = search_off(off, base, lo, nl - 1, Wend * 64 - 1);
       s_lo = lo;
       s_cnt = hi - lo + 1;
     }
@@ -223,7 +249,7 @@ __device__ void pack_payload_body(uint64_t n, uint32_t dims, uint64_t n_leaves,
     const uint64_t lo = s_lo, cnt = s_cnt;
     const bool in_lds = cnt <= 2048;
     if (in_lds)
-      for (uint64_t t = threadIdx.x; t < cnt; t += kBlock) s_off[t] = off[lo + t];
+      for (uint64_t t = threadIdx.x; t < cnt; t += kBlock) s_off[t] = off[lo + t] - base;
     __syncthreads();
     const uint64_t w = W0 + threadIdx.x;
     if (w < Wend) {
@@ -232,7 +258,7 @@ __device__ void pack_payload_body(uint64_t n, uint32_t dims, uint64_t n_leaves,
       if (in_lds) {
         uint64_t a = 0, z = cnt - 1;
         while (a < z) {
-          uint64_t mid = a + (z - a + 1) / 2;
+          const uint64_t mid = a + (z - a + 1) / 2;
           if (s_off[mid] <= b0)
             a = mid;
           else
@@ -240,23 +266,23 @@ __device__ void pack_payload_body(uint64_t n, uint32_t dims, uint64_t n_leaves,
         }
         i = lo + a;
       } else {
-        i = search_off(off, lo, lo + cnt - 1, b0);
+        i = search_off(off, base, lo, lo + cnt - 1, b0);
       }
       LeafRec rec = leaves[i];
       uint32_t sm = sum_m(rec.m);
-      uint64_t oi = off[i];
+      const uint64_t oi = off[i] - base;
       uint64_t jm = sm ? (b0 - oi) / sm : 0;
       uint64_t at = oi + jm * sm;
       uint64_t word = 0;
       while (at < b0 + 64) {
         if (sm > 0 && jm + 1 < rec.size) {
-          u128 c = member_code(keys, n, dims, rec, (uint64_t)rec.start + 1 + jm);
+          const u128 c = member_code(keys, n, dims, rec, (uint64_t)rec.start + 1 + jm);
           or_into(word, b0, c, at, sm);
           at += sm;
           ++jm;
         } else {
           ++i;
-          if (i >= n_leaves) break;
+          if (i >= nl) break;
           rec = leaves[i];
           sm = sum_m(rec.m);
           jm = 0;
@@ -268,73 +294,79 @@ __device__ void pack_payload_body(uint64_t n, uint32_t dims, uint64_t n_leaves,
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_pack_payload(uint64_t n, uint32_t dims,
-                                                         uint64_t n_leaves, const DevParams* P,
-                                                         const LeafRec* leaves,
-                                                         const uint64_t* off, const void* keys,
-                                                         uint8_t* out) {
+__global__ void __launch_bounds__(kBlock) k_pack_payload(uint32_t nsets, const uint64_t* pre,
+                                                         const SetDesc* sets,
+                                                         const DevParams* params,
+                                                         const LeafRec* leaves0,
+                                                         const uint64_t* off0,
+                                                         const uint8_t* keys0,
+                                                         const uint8_t* keys1) {
+  const uint32_t s = find_set(pre, nsets, blockIdx.x);
+  const SetDesc& S = sets[s];
+  const DevParams* P = params + s;
   if (P->status != BBX_OK) return;
   if (P->payload_bits == 0) return;
   __shared__ uint64_t s_off[2048];
+  const uint64_t lb = blockIdx.x - pre[s], nblk = pre[s + 1] - pre[s];
+  const uint8_t* keys = (S.final_buf ? keys1 : keys0) + S.key_off;
+  const LeafRec* leaves = leaves0 + S.leaf_off;
+  const uint64_t* off = off0 + S.leaf_off;
   if (P->key16)
-    pack_payload_body<uint16_t>(n, dims, n_leaves, P, leaves, off, (const uint16_t*)keys, out,
-                                s_off);
+    pack_payload_body<uint16_t>(S, P, lb, nblk, leaves, off, (const uint16_t*)keys, s_off);
   else
-    pack_payload_body<uint32_t>(n, dims, n_leaves, P, leaves, off, (const uint32_t*)keys, out,
-                                s_off);
+    pack_payload_body<uint32_t>(S, P, lb, nblk, leaves, off, (const uint32_t*)keys, s_off);
 }
 
-__global__ void k_header(uint64_t n, uint32_t dims, uint32_t dtype, uint32_t r, uint32_t eb_mode,
-                         uint32_t mbits, uint64_t n_leaves, const DevParams* P, uint8_t* out) {
+__global__ void k_header(const SetDesc* sets, const DevParams* params) {
+  const SetDesc& S = sets[blockIdx.x];
+  const DevParams* P = params + blockIdx.x;
   if (P->status != BBX_OK) return;
   if (threadIdx.x != 0) return;
+  const uint32_t dims = S.dims;
   uint64_t h[16];
   for (int k = 0; k < 16; ++k) h[k] = 0;
-  h[0] = (uint64_t)kMagic | ((uint64_t)1 << 32) | ((uint64_t)dtype << 48) | ((uint64_t)dims << 56);
-  h[1] = n;
-  h[2] = (uint64_t)r | ((uint64_t)eb_mode << 32) | ((uint64_t)mbits << 56);
+  h[0] = (uint64_t)kMagic | ((uint64_t)1 << 32) | ((uint64_t)S.dtype << 48) | ((uint64_t)dims << 56);
+  h[1] = S.n;
+  h[2] = (uint64_t)S.r | ((uint64_t)S.eb_mode << 32) | ((uint64_t)S.mbits << 56);
   h[3] = __double_as_longlong(P->eb_user);
   h[4] = __double_as_longlong(P->eb_abs);
   h[5] = __double_as_longlong(P->eb_eff);
   h[6] = __double_as_longlong(P->w);
   h[7] = __double_as_longlong(P->inv_w);
   for (uint32_t d = 0; d < 3; ++d) h[8 + d] = d < dims ? __double_as_longlong(P->lo[d]) : 0;
-  h[11] = (uint64_t)(dims > 0 ? P->G[0] : 0) | ((uint64_t)(dims > 1 ? P->G[1] : 0) << 8) |
+  h[11] = (uint64_t)P->G[0] | ((uint64_t)(dims > 1 ? P->G[1] : 0) << 8) |
           ((uint64_t)(dims > 2 ? P->G[2] : 0) << 16);
-  h[12] = n_leaves;
+  h[12] = S.n_leaves;
   h[13] = P->meta_bits;
   h[14] = P->payload_bits;
   h[15] = 0;
-  uint64_t* o = (uint64_t*)out;
+  uint64_t* o = (uint64_t*)S.out;
   for (int k = 0; k < 16; ++k) o[k] = h[k];
 }
 
-__global__ void k_finish(const DevParams* P, uint64_t* d_size, uint32_t* d_status) {
-  if (threadIdx.x != 0) return;
-  const uint32_t st = P->status;
-  if (d_size) *d_size = st == BBX_OK ? P->total_bytes : ~0ull;
-  if (d_status) *d_status = st;
+__global__ void k_finish(uint32_t nsets, const SetDesc* sets, const DevParams* params) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nsets) return;
+  const SetDesc& S = sets[s];
+  const uint32_t st = params[s].status;
+  if (S.d_size) *S.d_size = st == BBX_OK ? params[s].total_bytes : ~0ull;
+  if (S.d_status) *S.d_status = st;
 }
 
-hipError_t launch_pack(const CompressPlan& p, const CompressWs& w, int buf, uint8_t* out,
-                       uint64_t* d_size, uint32_t* d_status, hipStream_t s) {
-  if (p.n_leaves > 0) {
-    uint64_t meta_words_max = (p.n_leaves * (uint64_t)(p.dims * (p.mbits + 30)) + 63) / 64;
-    uint64_t g = (meta_words_max + kBlock - 1) / kBlock;
-    if (g > 2048) g = 2048;
-    if (g == 0) g = 1;
-    BBX_LAUNCH("pack_meta", k_pack_meta, g, kBlock, 0, s, p.n_leaves, p.dims, p.mbits, w.params,
-               w.leaves, out);
-    uint64_t pay_words_max = (p.n * (uint64_t)p.dims * 31 + 63) / 64;
-    uint64_t g2 = (pay_words_max + kBlock - 1) / kBlock;
-    if (g2 > 4096) g2 = 4096;
-    if (g2 == 0) g2 = 1;
-    BBX_LAUNCH("pack_payload", k_pack_payload, g2, kBlock, 0, s, p.n, p.dims, p.n_leaves,
-               w.params, w.leaves, w.leaf_bits, w.keys[buf], out);
-  }
-  BBX_LAUNCH("header", k_header, 1, 64, 0, s, p.n, p.dims, p.dtype, p.r, p.eb_mode, p.mbits,
-             p.n_leaves, w.params, out);
-  BBX_LAUNCH("finish", k_finish, 1, 64, 0, s, w.params, d_size, d_status);
+hipError_t launch_pack(const BatchPlan& bp, const Ws& w, hipStream_t s) {
+  hipError_t e = scan_launch(bp.total_leaves, w.leaf_bits, w.scan_part, w.scan_total, nullptr, 0, s);
+  if (e != hipSuccess) return e;
+  const uint32_t g = (bp.nsets + kBlock - 1) / kBlock;
+  BBX_LAUNCH("set_sizes", k_set_sizes, g, kBlock, 0, s, bp.nsets, w.sets, w.params, w.leaf_bits,
+             bp.total_leaves, w.scan_total);
+  if (bp.g_pm > 0)
+    BBX_LAUNCH("pack_meta", k_pack_meta, bp.g_pm, kBlock, 0, s, bp.nsets, w.pre + bp.o_pm, w.sets,
+               w.params, w.leaves);
+  if (bp.g_pp > 0)
+    BBX_LAUNCH("pack_payload", k_pack_payload, bp.g_pp, kBlock, 0, s, bp.nsets, w.pre + bp.o_pp,
+               w.sets, w.params, w.leaves, w.leaf_bits, w.keys[0], w.keys[1]);
+  BBX_LAUNCH("header", k_header, bp.nsets, 64, 0, s, w.sets, w.params);
+  BBX_LAUNCH("finish", k_finish, g, kBlock, 0, s, bp.nsets, w.sets, w.params);
   return hipGetLastError();
 }
 

@@ -1,12 +1,13 @@
 // k_range.hip -- range and bound (Sec. 3) and quantization (Sec. 3,
-// linear-scale quantization into bins of width 2*eb).
+// linear-scale quantization into bins of width 2*eb), for every set of a batch.
 //
 //   k_minmax    per-block per-axis min/max + non-finite flag (one HBM read)
-//   k_epilogue  one block: reduces the partials and computes, in FP64 with
-//               one rounding per operation, Delta_max, eb_abs, the rounding
-//               guard, eb_eff, w = 2*eb_eff, inv_w and the code widths G_d
+//   k_epilogue  one block per set: reduces the partials and computes, in FP64
+//               with one rounding per operation, Delta_max, eb_abs, the
+//               rounding guard, eb_eff, w = 2*eb_eff, inv_w and the code
+//               widths G_d
 //   k_quantize  q = floor((x - lo) * inv_w + 1/2) per coordinate, written as
-//               structure-of-arrays keys (u16 when every G_d <= 16, else u32)
+//               structure-of-arrays codes (u16 when every G_d <= 16, else u32)
 #include <math.h>
 
 #include "bbx_internal.h"
@@ -34,17 +35,16 @@ __device__ inline double wave_max(double v) {
   return v;
 }
 
-// partials layout per block: lo[3], hi[3], bad, count (8 doubles)
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_minmax(const T* pos, uint64_t n, uint32_t dims,
-                                                   uint32_t layout, double* partials) {
+__device__ void minmax_body(const SetDesc& S, uint64_t lb, double* part) {
   double lo[3] = {INFINITY, INFINITY, INFINITY};
   double hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   double bad = 0.0;
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    for (uint32_t d = 0; d < dims; ++d) {
-      double v = load_coord(pos, n, dims, layout, i, d);
+  const T* pos = (const T*)S.pos;
+  const uint64_t stride = (uint64_t)S.mm_blocks * blockDim.x;
+  for (uint64_t i = lb * blockDim.x + threadIdx.x; i < S.n; i += stride) {
+    for (uint32_t d = 0; d < S.dims; ++d) {
+      const double v = load_coord(pos, S.n, S.dims, S.layout, i, d);
       if (!isfinite(v)) bad = 1.0;
       lo[d] = v < lo[d] ? v : lo[d];
       hi[d] = v > hi[d] ? v : hi[d];
@@ -53,36 +53,49 @@ __global__ void __launch_bounds__(kBlock) k_minmax(const T* pos, uint64_t n, uin
   __shared__ double sh[8][kBlock / 64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int d = 0; d < 3; ++d) {
-    double a = wave_min(lo[d]), b = wave_max(hi[d]);
+    const double a = wave_min(lo[d]), b = wave_max(hi[d]);
     if (lane == 0) sh[d][wv] = a, sh[3 + d][wv] = b;
   }
-  double bb = wave_max(bad);
+  const double bb = wave_max(bad);
   if (lane == 0) sh[6][wv] = bb;
   __syncthreads();
   if (threadIdx.x < 7) {
-    int f = threadIdx.x;
+    const int f = threadIdx.x;
     double v = sh[f][0];
     for (int k = 1; k < kBlock / 64; ++k) {
-      double u = sh[f][k];
+      const double u = sh[f][k];
       if (f < 3)
         v = u < v ? u : v;
       else
         v = u > v ? u : v;
     }
-    partials[blockIdx.x * 8 + f] = v;
+    part[f] = v;
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_epilogue(const double* partials, uint32_t nparts,
-                                                     uint64_t n, uint32_t dims, uint32_t dtype,
-                                                     uint32_t eb_mode, double eb,
-                                                     DevParams* P) {
+// partials layout per block: lo[3], hi[3], bad, unused (8 doubles)
+__global__ void __launch_bounds__(kBlock) k_minmax(uint32_t nsets, const uint64_t* pre,
+                                                   const SetDesc* sets, double* partials) {
+  const uint32_t s = find_set(pre, nsets, blockIdx.x);
+  const SetDesc& S = sets[s];
+  const uint64_t lb = blockIdx.x - pre[s];
+  double* part = partials + (S.part_off + lb) * 8;
+  if (S.dtype == BBX_F32)
+    minmax_body<float>(S, lb, part);
+  else
+    minmax_body<double>(S, lb, part);
+}
+
+__global__ void __launch_bounds__(kBlock) k_epilogue(const SetDesc* sets, const double* partials,
+                                                     DevParams* params) {
+  const SetDesc& S = sets[blockIdx.x];
+  DevParams* P = params + blockIdx.x;
   __shared__ double red[7][kBlock];
   double v[7];
   for (int f = 0; f < 7; ++f) v[f] = f < 3 ? INFINITY : (f < 6 ? -INFINITY : 0.0);
-  for (uint32_t b = threadIdx.x; b < nparts; b += blockDim.x)
+  for (uint32_t b = threadIdx.x; b < S.mm_blocks; b += blockDim.x)
     for (int f = 0; f < 7; ++f) {
-      double u = partials[b * 8 + f];
+      const double u = partials[(S.part_off + b) * 8 + f];
       if (f < 3)
         v[f] = u < v[f] ? u : v[f];
       else
@@ -93,13 +106,16 @@ __global__ void __launch_bounds__(kBlock) k_epilogue(const double* partials, uin
   if (threadIdx.x != 0) return;
   for (int f = 0; f < 7; ++f)
     for (int t = 1; t < kBlock; ++t) {
-      double u = red[f][t];
+      const double u = red[f][t];
       if (f < 3)
         v[f] = u < v[f] ? u : v[f];
       else
         v[f] = u > v[f] ? u : v[f];
     }
 
+  const uint64_t n = S.n;
+  const uint32_t dims = S.dims;
+  const double eb = S.eb;
   DevParams p;
   for (int d = 0; d < 3; ++d) p.lo[d] = p.hi[d] = 0.0, p.G[d] = 0;
   p.eb_user = eb;
@@ -107,10 +123,10 @@ __global__ void __launch_bounds__(kBlock) k_epilogue(const double* partials, uin
   p.key16 = 1;
   p.status = BBX_OK;
   p.pad0 = 0;
-  p.meta_bits = p.payload_bits = p.total_bytes = 0;
-  for (int k = 0; k < 4; ++k) p.pad1[k] = 0;
+  p.meta_bits = p.payload_bits = p.total_bytes = p.payload_base = 0;
+  for (int k = 0; k < 3; ++k) p.pad1[k] = 0;
   if (n == 0) {
-    p.eb_abs = eb_mode == BBX_EB_ABS ? eb : 0.0;
+    p.eb_abs = S.eb_mode == BBX_EB_ABS ? eb : 0.0;
     *P = p;
     return;
   }
@@ -125,10 +141,10 @@ __global__ void __launch_bounds__(kBlock) k_epilogue(const double* partials, uin
   }
   double delta = 0.0;
   for (uint32_t d = 0; d < dims; ++d) {
-    double rg = p.hi[d] - p.lo[d];
+    const double rg = p.hi[d] - p.lo[d];
     if (rg > delta) delta = rg;
   }
-  p.eb_abs = eb_mode == BBX_EB_REL ? eb * delta : eb;
+  p.eb_abs = S.eb_mode == BBX_EB_REL ? eb * delta : eb;
   if (!isfinite(delta) || !isfinite(p.eb_abs)) {
     p.status = BBX_EBOUND;
     *P = p;
@@ -137,16 +153,16 @@ __global__ void __launch_bounds__(kBlock) k_epilogue(const double* partials, uin
   if (delta != 0.0) {
     double amax = 0.0;
     for (uint32_t d = 0; d < dims; ++d) {
-      double a = fabs(p.lo[d]) > fabs(p.hi[d]) ? fabs(p.lo[d]) : fabs(p.hi[d]);
+      const double a = fabs(p.lo[d]) > fabs(p.hi[d]) ? fabs(p.lo[d]) : fabs(p.hi[d]);
       if (a > amax) amax = a;
     }
     amax = amax + p.eb_abs;
     double guard = ldexp(amax, -48);
-    if (dtype == BBX_F32) {
+    if (S.dtype == BBX_F32) {
       int e = 0;
       (void)frexp(amax, &e);
       double half_ulp = ldexp(1.0, e - 25);
-      double tiny = ldexp(1.0, -150);
+      const double tiny = ldexp(1.0, -150);
       if (half_ulp < tiny) half_ulp = tiny;
       guard = guard + half_ulp;
     }
@@ -164,7 +180,7 @@ __global__ void __launch_bounds__(kBlock) k_epilogue(const double* partials, uin
       return;
     }
     for (uint32_t d = 0; d < dims; ++d) {
-      double qm = floor((p.hi[d] - p.lo[d]) * p.inv_w + 0.5);
+      const double qm = floor((p.hi[d] - p.lo[d]) * p.inv_w + 0.5);
       if (!(qm < 1073741824.0)) {
         p.status = BBX_EBOUND;
         *P = p;
@@ -178,17 +194,17 @@ __global__ void __launch_bounds__(kBlock) k_epilogue(const double* partials, uin
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_quantize(const T* pos, uint64_t n, uint32_t dims,
-                                                     uint32_t layout, const DevParams* P,
-                                                     void* keys, uint32_t* idx) {
-  if (P->status != BBX_OK) return;
+__device__ void quantize_body(const SetDesc& S, const DevParams* P, uint64_t lb, uint64_t nblk,
+                              uint8_t* keys, uint32_t* idx) {
   const double inv_w = P->inv_w;
   const bool k16 = P->key16 != 0;
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    for (uint32_t d = 0; d < dims; ++d) {
-      double x = load_coord(pos, n, dims, layout, i, d);
-      uint32_t q = (uint32_t)floor((x - P->lo[d]) * inv_w + 0.5);
+  const T* pos = (const T*)S.pos;
+  const uint64_t n = S.n;
+  const uint64_t stride = nblk * blockDim.x;
+  for (uint64_t i = lb * blockDim.x + threadIdx.x; i < n; i += stride) {
+    for (uint32_t d = 0; d < S.dims; ++d) {
+      const double x = load_coord(pos, n, S.dims, S.layout, i, d);
+      const uint32_t q = (uint32_t)floor((x - P->lo[d]) * inv_w + 0.5);
       if (k16)
         ((uint16_t*)keys)[(uint64_t)d * n + i] = (uint16_t)q;
       else
@@ -198,32 +214,29 @@ __global__ void __launch_bounds__(kBlock) k_quantize(const T* pos, uint64_t n, u
   }
 }
 
-hipError_t launch_range(const CompressPlan& p, const CompressWs& w, const void* pos,
-                        hipStream_t s) {
-  uint32_t nparts = 0;
-  if (p.n > 0) {
-    uint64_t want = (p.n + kBlock * 8 - 1) / (kBlock * 8);
-    nparts = (uint32_t)(want < kMinMaxBlocks ? want : kMinMaxBlocks);
-    if (p.dtype == BBX_F32)
-      BBX_LAUNCH("range_minmax", k_minmax<float>, nparts, kBlock, 0, s, (const float*)pos, p.n,
-                 p.dims, p.layout, w.partials);
-    else
-      BBX_LAUNCH("range_minmax", k_minmax<double>, nparts, kBlock, 0, s, (const double*)pos, p.n,
-                 p.dims, p.layout, w.partials);
-  }
-  BBX_LAUNCH("range_epilogue", k_epilogue, 1, kBlock, 0, s, w.partials, nparts, p.n, p.dims,
-             p.dtype, p.eb_mode, p.eb, w.params);
-  if (p.n > 0) {
-    uint64_t want = (p.n + kBlock * 4 - 1) / (kBlock * 4);
-    uint32_t nb = (uint32_t)(want < 65536 ? want : 65536);
-    uint32_t* idx = p.track_idx ? w.idx[0] : nullptr;
-    if (p.dtype == BBX_F32)
-      BBX_LAUNCH("quantize", k_quantize<float>, nb, kBlock, 0, s, (const float*)pos, p.n, p.dims,
-                 p.layout, w.params, w.keys[0], idx);
-    else
-      BBX_LAUNCH("quantize", k_quantize<double>, nb, kBlock, 0, s, (const double*)pos, p.n,
-                 p.dims, p.layout, w.params, w.keys[0], idx);
-  }
+__global__ void __launch_bounds__(kBlock) k_quantize(uint32_t nsets, const uint64_t* pre,
+                                                     const SetDesc* sets, const DevParams* params,
+                                                     uint8_t* keys0, uint32_t* idx0) {
+  const uint32_t s = find_set(pre, nsets, blockIdx.x);
+  const SetDesc& S = sets[s];
+  const DevParams* P = params + s;
+  if (P->status != BBX_OK) return;
+  const uint64_t lb = blockIdx.x - pre[s], nblk = pre[s + 1] - pre[s];
+  uint32_t* idx = S.perm ? idx0 + S.idx_off : nullptr;
+  if (S.dtype == BBX_F32)
+    quantize_body<float>(S, P, lb, nblk, keys0 + S.key_off, idx);
+  else
+    quantize_body<double>(S, P, lb, nblk, keys0 + S.key_off, idx);
+}
+
+hipError_t launch_range(const BatchPlan& bp, const Ws& w, hipStream_t s) {
+  if (bp.g_mm > 0)
+    BBX_LAUNCH("range_minmax", k_minmax, bp.g_mm, kBlock, 0, s, bp.nsets, w.pre + bp.o_mm, w.sets,
+               w.partials);
+  BBX_LAUNCH("range_epilogue", k_epilogue, bp.nsets, kBlock, 0, s, w.sets, w.partials, w.params);
+  if (bp.g_qz > 0)
+    BBX_LAUNCH("quantize", k_quantize, bp.g_qz, kBlock, 0, s, bp.nsets, w.pre + bp.o_qz, w.sets,
+               w.params, w.keys[0], w.idx[0]);
   return hipGetLastError();
 }
 

@@ -1,42 +1,49 @@
 // k_tile.hip -- the on-chip stage of the k-d partition plus the per-leaf bit
 // box (Sec. 4.1), and the equivalent stage for leaves larger than a tile.
 //
-// k_tile: one workgroup per node of the tile depth (<= TILE particles).  The
-// node's keys are staged in LDS once; every remaining level is a radix select
-// over LDS histograms followed by a stable partition of a u16 position
-// permutation (the keys themselves never move in LDS).  Then one wavefront per
-// leaf computes the AABB, the reference (member nearest the AABB centre,
-// squared distance in doubled code space, ties to the first member), Eq. 2's
-// widths m_d = bitlen(D_d) + 1 (0 when D_d = 0), and writes the leaf's keys
-// back in output-slot order (reference first) together with its record.
+// k_tile: one wavefront per node of the tile depth (<= TILE particles), with
+// no workgroup barriers: the node's codes are staged in the wavefront's own
+// LDS slice once, and LDS operations of one wavefront complete in program
+// order.  Every remaining level is a radix select over LDS histograms
+// followed by a stable partition of a u16 position permutation (the codes
+// never move in LDS).  Leaves are then handled by aligned lane groups (a
+// power of two >= the leaf size, up to the wavefront): AABB, reference =
+// member nearest the AABB centre (squared distance in doubled code space,
+// ties to the first member), Eq. 2's widths m_d = bitlen(D_d) + 1 (0 when
+// D_d = 0).  Finally the node is written back in output-slot order (reference
+// first in each leaf) with coalesced stores.
 //
 // k_bigleaf: one workgroup per leaf when leaves exceed the tile capacity.
 #include "bbx_internal.h"
 
 namespace bbx {
 
-__device__ inline uint32_t wmin_u32(uint32_t v) {
-  for (int o = 32; o > 0; o >>= 1) {
-    uint32_t u = __shfl_xor(v, o);
+// reductions within aligned groups of gs lanes (gs a power of two <= 64)
+__device__ inline uint32_t gmin_u32(uint32_t v, uint32_t gs) {
+  for (uint32_t o = gs >> 1; o > 0; o >>= 1) {
+    uint32_t u = __shfl_xor(v, (int)o);
     v = u < v ? u : v;
   }
   return v;
 }
-__device__ inline uint32_t wmax_u32(uint32_t v) {
-  for (int o = 32; o > 0; o >>= 1) {
-    uint32_t u = __shfl_xor(v, o);
+__device__ inline uint32_t gmax_u32(uint32_t v, uint32_t gs) {
+  for (uint32_t o = gs >> 1; o > 0; o >>= 1) {
+    uint32_t u = __shfl_xor(v, (int)o);
     v = u > v ? u : v;
   }
   return v;
 }
 // (dist, pos) minimum: smaller distance, then smaller position
-__device__ inline void wargmin(uint64_t& dist, uint32_t& pos) {
-  for (int o = 32; o > 0; o >>= 1) {
-    uint64_t d2 = __shfl_xor(dist, o);
-    uint32_t p2 = __shfl_xor(pos, o);
+__device__ inline void gargmin(uint64_t& dist, uint32_t& pos, uint32_t gs) {
+  for (uint32_t o = gs >> 1; o > 0; o >>= 1) {
+    uint64_t d2 = __shfl_xor(dist, (int)o);
+    uint32_t p2 = __shfl_xor(pos, (int)o);
     if (d2 < dist || (d2 == dist && p2 < pos)) dist = d2, pos = p2;
   }
 }
+__device__ inline uint32_t wmin_u32(uint32_t v) { return gmin_u32(v, 64); }
+__device__ inline uint32_t wmax_u32(uint32_t v) { return gmax_u32(v, 64); }
+__device__ inline void wargmin(uint64_t& dist, uint32_t& pos) { gargmin(dist, pos, 64); }
 
 __device__ inline uint32_t width_of(uint32_t D) { return D ? bitlen32(D) + 1u : 0u; }
 
@@ -49,84 +56,103 @@ __device__ inline uint64_t sqdist3(const uint32_t* q, const uint32_t* C, uint32_
   return s;
 }
 
-template <int TILE>
-struct TileSmem {
-  uint32_t K[3][TILE];
-  uint16_t Pm[2][TILE];
-  uint32_t I[TILE];
-  uint32_t H[2048];
-  uint32_t S[TILE];
-  uint16_t nst[TILE / 2], nsz[TILE / 2];
-  uint32_t npre[TILE / 2], nrank[TILE / 2];
-  uint32_t wsum[kBlock / 64];
-  uint32_t nleaves;
-};
-
-template <int TILE>
-__device__ inline uint32_t find_node(const TileSmem<TILE>& sm, uint32_t N, uint32_t p) {
-  uint32_t lo = 0, hi = N - 1;  // largest i with nst[i] <= p
-  while (lo < hi) {
-    uint32_t mid = (lo + hi + 1) >> 1;
-    if (sm.nst[mid] <= p)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  return lo;
+// Orders the wavefront's LDS accesses around a phase boundary (no cross-wave
+// synchronization is needed: each wavefront owns its tile).
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// block exclusive scan of u32 (256 threads)
-template <int TILE>
-__device__ inline uint32_t tile_exscan(TileSmem<TILE>& sm, uint32_t v) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  uint32_t x = v;
+// inclusive scan over the 64 lanes
+__device__ inline uint32_t wave_incl(uint32_t x) {
+  const int lane = threadIdx.x & 63;
   for (int o = 1; o < 64; o <<= 1) {
     uint32_t y = __shfl_up(x, o);
     if (lane >= o) x += y;
   }
-  if (lane == 63) sm.wsum[wv] = x;
-  __syncthreads();
-  uint32_t off = 0;
-  for (int k = 0; k < wv; ++k) off += sm.wsum[k];
-  __syncthreads();
-  return off + x - v;
+  return x;
 }
 
+template <int TILE>
+struct WaveTile {
+  uint32_t K[3][TILE];           // codes at their original tile slots
+  uint16_t Pm[2][TILE];          // position -> slot (ping-pong)
+  uint32_t I[TILE];              // source indices (only with a perm output)
+  uint32_t H[TILE];              // histogram bins (all zero between passes); then the leaf table
+  uint32_t S[TILE];              // exclusive (lt | eq << 16) prefix; then position -> leaf
+  uint16_t nst[TILE / 2], nsz[TILE / 2];
+  uint32_t npre[TILE / 2], nrank[TILE / 2];
+  uint16_t lref[TILE];           // reference position within each leaf
+};
+
+template <int TILE>
+__device__ inline uint32_t node_of(const WaveTile<TILE>& sm, uint32_t N, uint32_t s0, uint32_t p) {
+  uint32_t i = (p * N) / s0;
+  if (i >= N) i = N - 1;
+  while (sm.nst[i] > p) --i;
+  while (p >= (uint32_t)sm.nst[i] + sm.nsz[i]) ++i;
+  return i;
+}
+
+__device__ inline uint32_t leaf_fold(uint32_t s, uint32_t r) { return s <= r ? s : s - (s >> 1); }
+
 template <int TILE, typename KT>
-__device__ void tile_body(TileSmem<TILE>& sm, uint32_t K0, uint64_t n, uint32_t dims, uint32_t r,
-                          uint64_t n_leaves, const TreeGeom& g, DevParams* P, KT* keys,
-                          const uint32_t* idx,
-                          uint32_t* perm, LeafRec* leaves, uint64_t* leaf_bits) {
-  constexpr int ITEMS = TILE / kBlock;
-  const uint64_t j = blockIdx.x;
+__device__ void tile_body(WaveTile<TILE>& sm, uint64_t j, uint32_t K0, uint64_t n, uint32_t dims,
+                          uint32_t r, uint64_t n_leaves, const TreeGeom& g, DevParams* P, KT* keys,
+                          const uint32_t* idx, uint32_t* perm, LeafRec* leaves,
+                          uint64_t* leaf_bits) {
+  constexpr int E = TILE / 64;
+  const uint32_t lane = threadIdx.x & 63;
   uint64_t tst, s0_64;
   node_span(n, K0, j, &tst, &s0_64);
   if (s0_64 > (uint64_t)TILE) {  // launch plan violated: never expected
-    if (threadIdx.x == 0) P->status = BBX_EHIP;
+    if (lane == 0) P->status = BBX_EHIP;
     return;
   }
   const uint32_t s0 = (uint32_t)s0_64;
   const uint64_t first_leaf = leaves_before_node(g, K0, j, tst);
   const bool track = idx != nullptr;
 
-  for (uint32_t d = 0; d < dims; ++d)
-    for (uint32_t p = threadIdx.x; p < s0; p += kBlock) sm.K[d][p] = keys[(uint64_t)d * n + tst + p];
-  for (uint32_t p = threadIdx.x; p < s0; p += kBlock) {
-    sm.Pm[0][p] = (uint16_t)p;
-    if (track) sm.I[p] = idx[tst + p];
+  // stage the node: loads of up to 8 rows in flight, then LDS stores
+  constexpr int EB = E < 8 ? E : 8;
+  for (int k0 = 0; k0 < E; k0 += EB) {
+    uint32_t v[3][EB];
+    uint32_t ix[EB];
+#pragma unroll
+    for (int k = 0; k < EB; ++k) {
+      const uint32_t p = lane + 64u * (k0 + k);
+#pragma unroll
+      for (uint32_t d = 0; d < 3; ++d)
+        v[d][k] = (p < s0 && d < dims) ? (uint32_t)keys[(uint64_t)d * n + tst + p] : 0u;
+      ix[k] = (p < s0 && track) ? idx[tst + p] : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < EB; ++k) {
+      const uint32_t p = lane + 64u * (k0 + k);
+      if (p < s0) {
+#pragma unroll
+        for (uint32_t d = 0; d < 3; ++d)
+          if (d < dims) sm.K[d][p] = v[d][k];
+        sm.Pm[0][p] = (uint16_t)p;
+        if (track) sm.I[p] = ix[k];
+      }
+      sm.H[p] = 0;
+    }
   }
-  __syncthreads();
+  wave_sync();
 
   int cur = 0;
   int last_l = -1;
   uint32_t lastN = 0;
+  const uint32_t p0 = lane * E;
   for (uint32_t l = 0;; ++l) {
     const uint32_t N = 1u << l;
     const uint32_t maxsz = (s0 + N - 1) >> l;
     if (maxsz <= r) break;
     const uint32_t d = (K0 + l) % dims;
     const uint32_t G = P->G[d];
-    for (uint32_t i = threadIdx.x; i < N; i += kBlock) {
+    for (uint32_t i = lane; i < N; i += 64) {
       uint64_t a, b;
       node_span(s0, l, i, &a, &b);
       sm.nst[i] = (uint16_t)a;
@@ -134,12 +160,28 @@ __device__ void tile_body(TileSmem<TILE>& sm, uint32_t K0, uint64_t n, uint32_t 
       sm.npre[i] = 0;
       sm.nrank[i] = (uint32_t)(b >> 1);
     }
-    __syncthreads();
-    // ---- radix select of each internal node's median code
-    const uint32_t Wl = (11u - l) < 8u ? (11u - l) : 8u;
+    wave_sync();
+    // this level's view of the lane's E consecutive positions, kept in registers
+    uint32_t ni[E], nsr[E], nzz[E], slot[E], q[E];
+    bool inner[E];
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const uint32_t p = p0 + k;
+      const bool valid = p < s0;
+      const uint32_t i = valid ? node_of(sm, N, s0, p) : 0u;
+      ni[k] = i;
+      nsr[k] = sm.nst[i];
+      nzz[k] = sm.nsz[i];
+      inner[k] = valid && nzz[k] > r;
+      slot[k] = sm.Pm[cur][p & (TILE - 1)] & (TILE - 1);
+    }
+#pragma unroll
+    for (int k = 0; k < E; ++k) q[k] = sm.K[d][slot[k]];
+    // ---- radix select of each internal node's median code (N << w <= TILE bins)
+    uint32_t Wl = 0;
+    while ((N << (Wl + 1)) <= (uint32_t)TILE && Wl < 8) ++Wl;
     const uint32_t npass = G == 0 ? 1u : (G + Wl - 1) / Wl;
     const uint32_t firstw = G - (npass - 1) * Wl;
-    const uint32_t p0 = threadIdx.x * ITEMS;
     uint32_t used = 0;
     for (uint32_t pass = 0; pass < npass; ++pass) {
       const uint32_t w = pass == 0 ? firstw : Wl;
@@ -147,97 +189,86 @@ __device__ void tile_body(TileSmem<TILE>& sm, uint32_t K0, uint64_t n, uint32_t 
       used += w;
       const uint32_t sh = G - used;
       const uint32_t nb = 1u << w, mask = nb - 1;
-      for (uint32_t b = threadIdx.x; b < (N << w); b += kBlock) sm.H[b] = 0;
-      __syncthreads();
-      if (p0 < s0) {
-        uint32_t i = find_node(sm, N, p0);
-        for (int k = 0; k < ITEMS; ++k) {
-          uint32_t p = p0 + k;
-          if (p >= s0) break;
-          while (p >= (uint32_t)sm.nst[i] + sm.nsz[i]) ++i;
+      uint32_t pre[E];
+#pragma unroll
+      for (int k = 0; k < E; ++k) pre[k] = sm.npre[ni[k]];
+#pragma unroll
+      for (int k = 0; k < E; ++k)
+        if (inner[k] && (q[k] >> hs) == pre[k]) atomicAdd(&sm.H[(ni[k] << w) + ((q[k] >> sh) & mask)], 1u);
+      wave_sync();
+      if (N <= 8) {  // few nodes: the whole wavefront scans each node's bins
+        for (uint32_t i = 0; i < N; ++i) {
           if (sm.nsz[i] <= r) continue;
-          uint32_t q = sm.K[d][sm.Pm[cur][p]];
-          if ((hs >= 32 ? 0u : (q >> hs)) == sm.npre[i]) atomicAdd(&sm.H[(i << w) + ((q >> sh) & mask)], 1u);
-        }
-      }
-      __syncthreads();
-      // wave per node: find the bin holding the rank
-      const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-      for (uint32_t i = wv; i < N; i += kBlock / 64) {
-        if (sm.nsz[i] <= r) continue;
-        const uint32_t per = (nb + 63) / 64;  // <= 4
-        uint32_t c[4] = {0, 0, 0, 0};
-        uint32_t mine = 0;
-        for (uint32_t k = 0; k < per; ++k) {
-          uint32_t b = lane * per + k;
-          c[k] = b < nb ? sm.H[(i << w) + b] : 0u;
-          mine += c[k];
-        }
-        uint32_t x = mine;
-        for (int o = 1; o < 64; o <<= 1) {
-          uint32_t y = __shfl_up(x, o);
-          if (lane >= o) x += y;
-        }
-        uint32_t cum = x - mine;
-        const uint32_t rank = sm.nrank[i];
-        const uint32_t pre = sm.npre[i];
-        for (uint32_t k = 0; k < per; ++k) {
-          if (cum <= rank && rank < cum + c[k]) {
-            sm.npre[i] = (pre << w) | (lane * per + k);
-            sm.nrank[i] = rank - cum;
+          const uint32_t per = (nb + 63) / 64;  // <= 4
+          uint32_t c[4] = {0, 0, 0, 0};
+          uint32_t mine = 0;
+          for (uint32_t k = 0; k < per; ++k) {
+            const uint32_t b = lane * per + k;
+            if (b < nb) {
+              c[k] = sm.H[(i << w) + b];
+              if (c[k]) sm.H[(i << w) + b] = 0;
+            }
+            mine += c[k];
           }
-          cum += c[k];
+          uint32_t cum = wave_incl(mine) - mine;
+          const uint32_t rank = sm.nrank[i];
+          const uint32_t pr = sm.npre[i];
+          for (uint32_t k = 0; k < per; ++k) {
+            if (cum <= rank && rank < cum + c[k]) {
+              sm.npre[i] = (pr << w) | (lane * per + k);
+              sm.nrank[i] = rank - cum;
+            }
+            cum += c[k];
+          }
+        }
+      } else {  // many small nodes: one lane per node scans its few bins
+        for (uint32_t i = lane; i < N; i += 64) {
+          if (sm.nsz[i] <= r) continue;
+          const uint32_t rank = sm.nrank[i];
+          uint32_t cum = 0, found = 0xffffffffu, below = 0;
+          for (uint32_t b = 0; b < nb; ++b) {
+            const uint32_t c = sm.H[(i << w) + b];
+            if (c) sm.H[(i << w) + b] = 0;
+            if (found == 0xffffffffu && rank < cum + c) found = b, below = cum;
+            cum += c;
+          }
+          sm.npre[i] = (sm.npre[i] << w) | found;
+          sm.nrank[i] = rank - below;
         }
       }
-      __syncthreads();
+      wave_sync();
     }
     // ---- stable partition: exclusive prefix of (lt | eq << 16) over the tile
-    uint32_t fl[ITEMS];
+    uint32_t fl[E], jq[E];
     uint32_t mine = 0;
-    {
-      uint32_t i = p0 < s0 ? find_node(sm, N, p0) : 0;
-      for (int k = 0; k < ITEMS; ++k) {
-        uint32_t p = p0 + k;
-        fl[k] = 0;
-        if (p >= s0) continue;
-        while (p >= (uint32_t)sm.nst[i] + sm.nsz[i]) ++i;
-        if (sm.nsz[i] > r) {
-          uint32_t q = sm.K[d][sm.Pm[cur][p]];
-          uint32_t v = sm.npre[i];
-          fl[k] = (q < v ? 1u : 0u) | (q == v ? 0x10000u : 0u);
-        }
-        mine += fl[k];
-      }
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const uint32_t v = sm.npre[ni[k]];
+      jq[k] = sm.nrank[ni[k]];
+      fl[k] = inner[k] ? ((q[k] < v ? 1u : 0u) | (q[k] == v ? 0x10000u : 0u)) : 0u;
+      mine += fl[k];
     }
-    uint32_t ex = tile_exscan(sm, mine);
-    for (int k = 0; k < ITEMS; ++k) {
-      uint32_t p = p0 + k;
-      if (p < s0) sm.S[p] = ex;
+    uint32_t ex = wave_incl(mine) - mine;
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      if (p0 + k < s0) sm.S[p0 + k] = ex;
       ex += fl[k];
     }
-    __syncthreads();
-    if (p0 < s0) {
-      uint32_t i = find_node(sm, N, p0);
-      for (int k = 0; k < ITEMS; ++k) {
-        uint32_t p = p0 + k;
-        if (p >= s0) break;
-        while (p >= (uint32_t)sm.nst[i] + sm.nsz[i]) ++i;
-        const uint32_t ns = sm.nst[i], nz = sm.nsz[i];
-        if (nz <= r) {
-          sm.Pm[cur ^ 1][p] = sm.Pm[cur][p];
-          continue;
-        }
-        const uint32_t X = sm.S[p] - sm.S[ns];
-        const uint32_t L = X & 0xffffu, E = X >> 16;
-        const uint32_t jeq = sm.nrank[i];
-        const uint32_t lb = L + (E < jeq ? E : jeq);
-        const bool lt = fl[k] & 1u, eq = (fl[k] >> 16) & 1u;
-        const bool left = lt || (eq && E < jeq);
-        const uint32_t dest = left ? lb : (nz >> 1) + (p - ns) - lb;
-        if (dest < nz) sm.Pm[cur ^ 1][ns + dest] = sm.Pm[cur][p];
-      }
+    wave_sync();
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const uint32_t p = p0 + k;
+      const uint32_t ns = nsr[k], nz = nzz[k];
+      const uint32_t X = sm.S[p & (TILE - 1)] - sm.S[ns];
+      const uint32_t L = X & 0xffffu, Eq = X >> 16;
+      const uint32_t jeq = jq[k];
+      const uint32_t lb = L + (Eq < jeq ? Eq : jeq);
+      const bool lt = fl[k] & 1u, eq = (fl[k] >> 16) & 1u;
+      const bool left = lt || (eq && Eq < jeq);
+      const uint32_t dest = inner[k] ? ns + (left ? lb : (nz >> 1) + (p - ns) - lb) : p;
+      if (p < s0 && dest < s0) sm.Pm[cur ^ 1][dest] = (uint16_t)slot[k];
     }
-    __syncthreads();
+    wave_sync();
     cur ^= 1;
     last_l = (int)l;
     lastN = N;
@@ -245,22 +276,23 @@ __device__ void tile_body(TileSmem<TILE>& sm, uint32_t K0, uint64_t n, uint32_t 
 
   // ---- leaf list (depth-first): nodes of the last level that were split give
   // two leaves, the others are leaves themselves
+  uint32_t nl, maxleaf;
   if (last_l < 0) {
-    if (threadIdx.x == 0) {
-      sm.H[0] = 0u | ((uint32_t)s0 << 16);
-      sm.nleaves = 1;
-    }
+    if (lane == 0) sm.H[0] = (uint32_t)s0 << 16;
+    nl = 1;
+    maxleaf = s0;
   } else {
     const uint32_t N = lastN;
-    const uint32_t per = (N + kBlock - 1) / kBlock;  // <= 4
+    const uint32_t per = (N + 63) / 64;
     uint32_t cnt = 0;
     for (uint32_t k = 0; k < per; ++k) {
-      uint32_t i = threadIdx.x * per + k;
+      const uint32_t i = lane * per + k;
       if (i < N) cnt += sm.nsz[i] > r ? 2u : 1u;
     }
-    uint32_t at = tile_exscan(sm, cnt);
+    const uint32_t incl = wave_incl(cnt);
+    uint32_t at = incl - cnt;
     for (uint32_t k = 0; k < per; ++k) {
-      uint32_t i = threadIdx.x * per + k;
+      const uint32_t i = lane * per + k;
       if (i >= N) break;
       const uint32_t ns = sm.nst[i], nz = sm.nsz[i];
       if (nz > r) {
@@ -270,87 +302,115 @@ __device__ void tile_body(TileSmem<TILE>& sm, uint32_t K0, uint64_t n, uint32_t 
         sm.H[at++] = ns | (nz << 16);
       }
     }
-    if (threadIdx.x == kBlock - 1) sm.nleaves = at;
+    nl = __shfl(incl, 63);
+    const uint32_t a = s0 / N, b = (s0 + N - 1) / N;  // the two node sizes of the level
+    maxleaf = leaf_fold(b, r);
+    if (s0 % N != 0 && leaf_fold(a, r) > maxleaf) maxleaf = leaf_fold(a, r);
   }
-  __syncthreads();
+  wave_sync();
 
-  // ---- bit box per leaf, one wavefront each
-  const uint32_t nl = sm.nleaves;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (uint32_t L = wv; L < nl; L += kBlock / 64) {
-    const uint32_t ls = sm.H[L] & 0xffffu, lz = sm.H[L] >> 16;
+  // ---- bit box per leaf: aligned groups of gs lanes, 64/gs leaves at a time
+  uint32_t gs = 1;
+  while (gs < maxleaf && gs < 64) gs <<= 1;
+  const uint32_t lpw = 64 / gs;
+  const uint32_t sub = lane & (gs - 1);
+  for (uint32_t base = 0; base < nl; base += lpw) {
+    const uint32_t L = base + lane / gs;
+    const bool act = L < nl;
+    const uint32_t ls = act ? (sm.H[L] & 0xffffu) : 0u, lz = act ? (sm.H[L] >> 16) : 0u;
     uint32_t mn[3] = {0xffffffffu, 0xffffffffu, 0xffffffffu}, mx[3] = {0, 0, 0};
-    for (uint32_t t = lane; t < lz; t += 64) {
+    for (uint32_t t = sub; t < lz; t += gs) {
       const uint32_t slot = sm.Pm[cur][ls + t];
       for (uint32_t d = 0; d < dims; ++d) {
-        uint32_t q = sm.K[d][slot];
+        const uint32_t q = sm.K[d][slot];
         mn[d] = q < mn[d] ? q : mn[d];
         mx[d] = q > mx[d] ? q : mx[d];
       }
     }
     uint32_t C[3] = {0, 0, 0};
     for (uint32_t d = 0; d < dims; ++d) {
-      mn[d] = wmin_u32(mn[d]);
-      mx[d] = wmax_u32(mx[d]);
+      mn[d] = gmin_u32(mn[d], gs);
+      mx[d] = gmax_u32(mx[d], gs);
       C[d] = mn[d] + mx[d];
     }
     uint64_t best = ~0ull;
     uint32_t bpos = 0xffffffffu;
-    for (uint32_t t = lane; t < lz; t += 64) {
+    for (uint32_t t = sub; t < lz; t += gs) {
       const uint32_t slot = sm.Pm[cur][ls + t];
       uint32_t q[3] = {0, 0, 0};
       for (uint32_t d = 0; d < dims; ++d) q[d] = sm.K[d][slot];
-      uint64_t dist = sqdist3(q, C, dims);
+      const uint64_t dist = sqdist3(q, C, dims);
       if (dist < best) best = dist, bpos = t;  // t increases: ties keep the first
     }
-    wargmin(best, bpos);
+    gargmin(best, bpos, gs);
+    if (!act) continue;
     const uint32_t ref = bpos;
-    const uint32_t rslot = sm.Pm[cur][ls + ref];
-    uint32_t m[3] = {0, 0, 0}, qr[3] = {0, 0, 0};
-    uint32_t summ = 0;
-    for (uint32_t d = 0; d < dims; ++d) {
-      qr[d] = sm.K[d][rslot];
-      uint32_t D = (qr[d] - mn[d]) > (mx[d] - qr[d]) ? qr[d] - mn[d] : mx[d] - qr[d];
-      m[d] = width_of(D);
-      summ += m[d];
+    for (uint32_t t = sub; t < lz; t += gs) sm.S[ls + t] = L;  // position -> leaf
+    if (sub == 0) {
+      const uint32_t rslot = sm.Pm[cur][ls + ref];
+      uint32_t m[3] = {0, 0, 0}, qr[3] = {0, 0, 0};
+      uint32_t summ = 0;
+      for (uint32_t d = 0; d < dims; ++d) {
+        qr[d] = sm.K[d][rslot];
+        const uint32_t D = (qr[d] - mn[d]) > (mx[d] - qr[d]) ? qr[d] - mn[d] : mx[d] - qr[d];
+        m[d] = width_of(D);
+        summ += m[d];
+      }
+      sm.lref[L] = (uint16_t)ref;
+      const uint64_t lid = first_leaf + L;
+      if (lid < n_leaves) {
+        LeafRec rec;
+        rec.start = (uint32_t)(tst + ls);
+        rec.size = lz;
+        rec.m = m[0] | (m[1] << 8) | (m[2] << 16);
+        rec.qref[0] = qr[0];
+        rec.qref[1] = qr[1];
+        rec.qref[2] = qr[2];
+        leaves[lid] = rec;
+        leaf_bits[lid] = (uint64_t)(lz - 1) * summ;
+      } else {
+        P->status = BBX_EHIP;  // leaf count mismatch: never expected
+      }
     }
-    const uint64_t lid = first_leaf + L;
-    if (lid >= n_leaves) continue;  // leaf count mismatch: never expected
-    if (lane == 0) {
-      LeafRec rec;
-      rec.start = (uint32_t)(tst + ls);
-      rec.size = lz;
-      rec.m = m[0] | (m[1] << 8) | (m[2] << 16);
-      rec.qref[0] = qr[0];
-      rec.qref[1] = qr[1];
-      rec.qref[2] = qr[2];
-      leaves[lid] = rec;
-      leaf_bits[lid] = (uint64_t)(lz - 1) * summ;
-    }
-    for (uint32_t t = lane; t < lz; t += 64) {
-      const uint32_t slot = sm.Pm[cur][ls + t];
-      const uint32_t o = t == ref ? 0u : (t < ref ? t + 1 : t);
-      const uint64_t gpos = tst + ls + o;
-      for (uint32_t d = 0; d < dims; ++d) keys[(uint64_t)d * n + gpos] = (KT)sm.K[d][slot];
-      if (track) perm[gpos] = sm.I[slot];
-    }
+  }
+  wave_sync();
+
+  // ---- write the node back in output-slot order (reference first per leaf)
+  for (uint32_t p = lane; p < s0; p += 64) {
+    const uint32_t L = sm.S[p];
+    const uint32_t ls = sm.H[L] & 0xffffu, ref = sm.lref[L];
+    const uint32_t t = p - ls;
+    const uint32_t o = t == ref ? 0u : (t < ref ? t + 1 : t);
+    const uint32_t slot = sm.Pm[cur][p];
+    const uint64_t gpos = tst + ls + o;
+    for (uint32_t d = 0; d < dims; ++d) keys[(uint64_t)d * n + gpos] = (KT)sm.K[d][slot];
+    if (track) perm[gpos] = sm.I[slot];
   }
 }
 
 template <int TILE>
-__global__ void __launch_bounds__(kBlock) k_tile(uint32_t K0, uint64_t n, uint32_t dims,
-                                                 uint32_t r, uint64_t n_leaves, TreeGeom g,
-                                                 DevParams* P,
-                                                 void* keys, const uint32_t* idx, uint32_t* perm,
-                                                 LeafRec* leaves, uint64_t* leaf_bits) {
+__global__ void __launch_bounds__(64) k_tile(uint32_t nsets, const uint64_t* pre,
+                                             const SetDesc* sets, DevParams* params,
+                                             uint8_t* keys0, uint8_t* keys1, uint32_t* idx0,
+                                             uint32_t* idx1, LeafRec* leaves0,
+                                             uint64_t* leaf_bits0) {
+  const uint32_t s = find_set(pre, nsets, blockIdx.x);
+  const SetDesc& S = sets[s];
+  DevParams* P = params + s;
   if (P->status != BBX_OK) return;
-  __shared__ TileSmem<TILE> sm;
+  __shared__ WaveTile<TILE> sm;
+  const uint64_t j = blockIdx.x - pre[s];
+  const uint32_t buf = S.gl & 1;
+  uint8_t* keys = (buf ? keys1 : keys0) + S.key_off;
+  const uint32_t* idx = S.perm ? (buf ? idx1 : idx0) + S.idx_off : nullptr;
+  LeafRec* leaves = leaves0 + S.leaf_off;
+  uint64_t* leaf_bits = leaf_bits0 + S.leaf_off;
   if (P->key16)
-    tile_body<TILE, uint16_t>(sm, K0, n, dims, r, n_leaves, g, P, (uint16_t*)keys, idx, perm, leaves,
-                              leaf_bits);
+    tile_body<TILE, uint16_t>(sm, j, S.gl, S.n, S.dims, S.r, S.n_leaves, S.geom, P,
+                              (uint16_t*)keys, idx, S.perm, leaves, leaf_bits);
   else
-    tile_body<TILE, uint32_t>(sm, K0, n, dims, r, n_leaves, g, P, (uint32_t*)keys, idx, perm, leaves,
-                              leaf_bits);
+    tile_body<TILE, uint32_t>(sm, j, S.gl, S.n, S.dims, S.r, S.n_leaves, S.geom, P,
+                              (uint32_t*)keys, idx, S.perm, leaves, leaf_bits);
 }
 
 // ---------------------------------------------------------------- big leaves
@@ -377,13 +437,12 @@ __device__ inline uint32_t bmax_u32(uint32_t v, uint32_t* red) {
 }
 
 template <typename KT>
-__device__ void bigleaf_body(uint64_t n, uint32_t dims, const TreeGeom& g, const KT* src, KT* dst,
-                             const uint32_t* idx, uint32_t* perm, LeafRec* leaves,
-                             uint64_t* leaf_bits) {
+__device__ void bigleaf_body(uint64_t i, uint64_t n, uint32_t dims, const TreeGeom& g,
+                             const KT* src, KT* dst, const uint32_t* idx, uint32_t* perm,
+                             LeafRec* leaves, uint64_t* leaf_bits) {
   __shared__ uint32_t red[kBlock / 64];
   __shared__ uint64_t rd[kBlock / 64];
   __shared__ uint32_t rp[kBlock / 64];
-  const uint64_t i = blockIdx.x;
   uint64_t st, sz;
   leaf_span(g, i, &st, &sz);
   uint32_t mn[3] = {0, 0, 0}, mx[3] = {0, 0, 0}, C[3] = {0, 0, 0};
@@ -440,37 +499,40 @@ __device__ void bigleaf_body(uint64_t n, uint32_t dims, const TreeGeom& g, const
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_bigleaf(uint64_t n, uint32_t dims, TreeGeom g,
-                                                    const DevParams* P, const void* src,
-                                                    void* dst, const uint32_t* idx,
-                                                    uint32_t* perm, LeafRec* leaves,
-                                                    uint64_t* leaf_bits) {
+__global__ void __launch_bounds__(kBlock) k_bigleaf(uint32_t nsets, const uint64_t* pre,
+                                                    const SetDesc* sets, DevParams* params,
+                                                    uint8_t* keys0, uint8_t* keys1,
+                                                    uint32_t* idx0, uint32_t* idx1,
+                                                    LeafRec* leaves0, uint64_t* leaf_bits0) {
+  const uint32_t s = find_set(pre, nsets, blockIdx.x);
+  const SetDesc& S = sets[s];
+  DevParams* P = params + s;
   if (P->status != BBX_OK) return;
+  const uint32_t buf = S.gl & 1;
+  const uint8_t* src = (buf ? keys1 : keys0) + S.key_off;
+  uint8_t* dst = (buf ? keys0 : keys1) + S.key_off;
+  const uint32_t* idx = S.perm ? (buf ? idx1 : idx0) + S.idx_off : nullptr;
+  const uint64_t i = blockIdx.x - pre[s];
   if (P->key16)
-    bigleaf_body<uint16_t>(n, dims, g, (const uint16_t*)src, (uint16_t*)dst, idx, perm, leaves,
-                           leaf_bits);
+    bigleaf_body<uint16_t>(i, S.n, S.dims, S.geom, (const uint16_t*)src, (uint16_t*)dst, idx,
+                           S.perm, leaves0 + S.leaf_off, leaf_bits0 + S.leaf_off);
   else
-    bigleaf_body<uint32_t>(n, dims, g, (const uint32_t*)src, (uint32_t*)dst, idx, perm, leaves,
-                           leaf_bits);
+    bigleaf_body<uint32_t>(i, S.n, S.dims, S.geom, (const uint32_t*)src, (uint32_t*)dst, idx,
+                           S.perm, leaves0 + S.leaf_off, leaf_bits0 + S.leaf_off);
 }
 
-hipError_t launch_leaves(const CompressPlan& p, const CompressWs& w, int buf, uint32_t* perm,
-                         hipStream_t s, int* out_buf) {
-  const uint32_t* idx = p.track_idx ? w.idx[buf] : nullptr;
-  if (p.tile_mode) {
-    const uint64_t tiles = 1ull << p.global_levels;
-    if (p.tile == 1024)
-      BBX_LAUNCH("tile", k_tile<1024>, tiles, kBlock, 0, s, p.global_levels, p.n, p.dims, p.r,
-                 p.n_leaves, p.geom, w.params, w.keys[buf], idx, perm, w.leaves, w.leaf_bits);
+hipError_t launch_leaves(const BatchPlan& bp, const Ws& w, hipStream_t s) {
+  if (bp.g_tile > 0) {
+    if (bp.tile == 256)
+      BBX_LAUNCH("tile", k_tile<256>, bp.g_tile, 64, 0, s, bp.nsets, w.pre + bp.o_tile, w.sets,
+                 w.params, w.keys[0], w.keys[1], w.idx[0], w.idx[1], w.leaves, w.leaf_bits);
     else
-      BBX_LAUNCH("tile", k_tile<2048>, tiles, kBlock, 0, s, p.global_levels, p.n, p.dims, p.r,
-                 p.n_leaves, p.geom, w.params, w.keys[buf], idx, perm, w.leaves, w.leaf_bits);
-    *out_buf = buf;
-  } else {
-    BBX_LAUNCH("bigleaf", k_bigleaf, p.n_leaves, kBlock, 0, s, p.n, p.dims, p.geom, w.params,
-               w.keys[buf], w.keys[buf ^ 1], idx, perm, w.leaves, w.leaf_bits);
-    *out_buf = buf ^ 1;
+      BBX_LAUNCH("tile", k_tile<512>, bp.g_tile, 64, 0, s, bp.nsets, w.pre + bp.o_tile, w.sets,
+                 w.params, w.keys[0], w.keys[1], w.idx[0], w.idx[1], w.leaves, w.leaf_bits);
   }
+  if (bp.g_big > 0)
+    BBX_LAUNCH("bigleaf", k_bigleaf, bp.g_big, kBlock, 0, s, bp.nsets, w.pre + bp.o_big, w.sets,
+               w.params, w.keys[0], w.keys[1], w.idx[0], w.idx[1], w.leaves, w.leaf_bits);
   return hipGetLastError();
 }
 

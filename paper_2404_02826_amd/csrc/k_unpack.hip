@@ -183,8 +183,7 @@ hipError_t launch_decompress(const DecompressPlan& p, const DecompressWs& w, con
     if (g > 65536) g = 65536;
     BBX_LAUNCH("dec_meta", k_dec_meta, g, kBlock, 0, s, p.n_leaves, p.dims, p.mbits, p.G[0],
                p.G[1], p.G[2], p.meta_bits, p.geom, stream, w.leaves, w.leaf_bits, w.params);
-    hipError_t e = launch_scan(p.n_leaves, w.leaf_bits, w.scan_part, w.params, nullptr,
-                               p.payload_bits, 0, nullptr, s);
+    hipError_t e = launch_dec_scan(p.n_leaves, w.leaf_bits, w.scan_part, w.params, p.payload_bits, s);
     if (e != hipSuccess) return e;
     const uint64_t blocks = (p.n + 1023) / 1024;
     if (p.dtype == BBX_F32)
