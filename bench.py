@@ -63,13 +63,317 @@ def kernel_bytes_per_particle(name, key_bytes, in_bytes, stream_bytes_pp):
     }.get(name)
 
 
+def _gen_batch_set(job):
+    from synth import batch_set
+    s, n, kind, seed0 = job
+    return batch_set(s, n, kind, seed0)
+
+
+def _pctl(v, q):
+    v = sorted(v)
+    return v[min(len(v) - 1, max(0, int(math.ceil(q * len(v))) - 1))]
+
+
+def bench_batch(args):
+    """Batched compress of many independent sets in one recorded launch,
+    against one compress call per set on the same GPU."""
+    import numpy as np
+    import torch
+    from concurrent.futures import ProcessPoolExecutor
+
+    import paper_2404_02826_amd as bbx
+    from paper_2404_02826_amd import autotune
+    from synth import batch_plan
+
+    nsets, seed0 = args.nsets, 5
+    sizes, kinds, ebs = batch_plan(nsets, seed0)
+    t0 = time.time()
+    jobs = [(s, int(sizes[s]), kinds[s], seed0) for s in range(nsets)]
+    with ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        arrays = list(ex.map(_gen_batch_set, jobs, chunksize=32))
+    log(f"generated {nsets} sets, {int(sizes.sum())} particles in {time.time() - t0:.1f}s")
+    dev = torch.device("cuda:0")
+    xs = [torch.from_numpy(a).to(dev) for a in arrays]
+    torch.cuda.synchronize()
+    B_in = sum(a.nbytes for a in arrays)
+    n_tot = int(sizes.sum())
+
+    base = [dict(pos=xs[i], eb=ebs[i], eb_mode="rel") for i in range(nsets)]
+    if args.leaf_size > 0 and args.tile > 0:
+        tuned = autotune.Tuned(leaf_sizes=[args.leaf_size] * nsets, tile=args.tile)
+    else:
+        t1 = time.time()
+        tuned = autotune.tune(base)
+        log(f"autotuned in {time.time() - t1:.1f}s: tile {tuned.tile}, tile ms {tuned.tile_ms}, "
+            f"bytes per r {tuned.stream_bytes}")
+    specs = [dict(b, leaf_size=tuned.leaf_sizes[i]) for i, b in enumerate(base)]
+
+    # ---- batched path: upload once, record the kernels once, replay
+    bc = bbx.BatchCompressor(specs, tile=tuned.tile)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        bc.upload(side)
+        bc.launch(side)
+    side.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        bc.launch()
+    for _ in range(args.warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    st = bc.d_status.cpu().numpy()[:nsets]
+    assert (st == 0).all(), f"batched sets failed: {np.nonzero(st)[0][:8]}"
+    b_sizes = bc.d_size.cpu().numpy()[:nsets]
+    S_tot = int(b_sizes.sum())
+
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    evs = []
+    for _ in range(args.steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        g.replay()
+        e1.record()
+        evs.append((e0, e1))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    job_ms = [a.elapsed_time(b) for a, b in evs]
+    value = B_in * args.steps / elapsed / 1e9
+    log(f"batched: {elapsed * 1e3 / args.steps:.2f} ms/job, {value:.1f} GB/s")
+
+    # ---- per-set path: one bbx_compress per set, same leaf sizes and tile
+    comps = [bbx.Compressor(int(sizes[i]), 3, torch.float32, leaf_size=tuned.leaf_sizes[i],
+                            tile=tuned.tile) for i in range(nsets)]
+
+    def per_set_job(record):
+        marks = []
+        for i in range(nsets):
+            comps[i].launch(xs[i], ebs[i])
+            if record:
+                e = torch.cuda.Event(enable_timing=True)
+                e.record()
+                marks.append(e)
+        return marks
+
+    for _ in range(args.warmup):
+        per_set_job(False)
+    torch.cuda.synchronize()
+    ps_job_ms, ps_lat = [], []
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        marks = per_set_job(True)
+        torch.cuda.synchronize()
+        lat = [e0.elapsed_time(m) for m in marks]
+        ps_lat += lat
+        ps_job_ms.append(lat[-1])
+    ps_elapsed = time.perf_counter() - t_start
+    ps_value = B_in * args.steps / ps_elapsed / 1e9
+    log(f"per-set: {ps_elapsed * 1e3 / args.steps:.2f} ms/job, {ps_value:.1f} GB/s")
+
+    # every set's stream equals its per-set stream
+    same = 0
+    for i in range(nsets):
+        n_i = int(comps[i].d_size.item())
+        if n_i == int(b_sizes[i]) and torch.equal(comps[i].out[:n_i],
+                                                  bc.out[bc.offsets[i]: bc.offsets[i] + n_i]):
+            same += 1
+    log(f"identical streams: {same}/{nsets}")
+
+    # per-kernel times of one batched job (eager launch on the same workspace)
+    with bbx.profile() as prof:
+        bc.launch()
+        torch.cuda.synchronize()
+    dname, (dcount, dms) = max(prof.items(), key=lambda kv: kv[1][1])
+    bpp = kernel_bytes_per_particle(dname, 2, 12, S_tot / n_tot)
+    roofline = None
+    if bpp is not None:
+        per_launch = bpp * n_tot / dcount
+        avg_ms = dms / dcount
+        achieved = per_launch / (avg_ms * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "kernel": dname, "avg_ms": round(avg_ms, 4), "launches_per_step": dcount,
+                    "alg_bytes_per_launch": int(per_launch)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import Oracle
+        orc = Oracle()
+        t, done_b, k, checked = time.perf_counter(), 0, 0, 0
+        order = np.random.default_rng(1).permutation(nsets)
+        while time.perf_counter() - t < 15.0 and k < nsets:
+            i = int(order[k])
+            so = orc.compress(arrays[i], ebs[i], "rel", tuned.leaf_sizes[i])
+            got = bc.out[bc.offsets[i]: bc.offsets[i] + int(b_sizes[i])].cpu().numpy().tobytes()
+            checked += int(got == so)
+            done_b += arrays[i].nbytes
+            k += 1
+        dt = time.perf_counter() - t
+        cpu = {"value": round(done_b / dt / 1e9, 5), "unit": "GB/s", "cores": 1, "kind": "oracle",
+               "sample": f"{k} randomly chosen sets of the batch ({done_b} bytes), compress only, "
+                         f"single thread; {checked}/{k} oracle streams equal the batched ones"}
+
+    lat_b = [m for m in job_ms for _ in range(nsets)]  # every set completes with its job
+    out = {
+        "metric": "batched compress GB/s (4,096 FP32 xyz sets, log-uniform 10^3..10^6), p99 set latency",
+        "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(elapsed * 1e3 / args.steps, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"batch-{nsets}-f32", "nsets": nsets, "particles": n_tot,
+                   "input_bytes": B_in, "stream_bytes": S_tot, "cr": round(B_in / S_tot, 4),
+                   "tile": tuned.tile, "leaf_sizes": {str(r): tuned.leaf_sizes.count(r)
+                                                      for r in sorted(set(tuned.leaf_sizes))},
+                   "tuner_stream_bytes_per_r": {str(k): v for k, v in tuned.stream_bytes.items()},
+                   "tuner_tile_ms": {str(k): round(v, 3) for k, v in tuned.tile_ms.items()},
+                   "batched": {"gbps": round(value, 2), "job_ms_p50": round(_pctl(job_ms, .5), 3),
+                               "set_latency_ms_p50": round(_pctl(lat_b, .5), 3),
+                               "set_latency_ms_p99": round(_pctl(lat_b, .99), 3)},
+                   "per_set_calls": {"gbps": round(ps_value, 2),
+                                     "job_ms_p50": round(_pctl(ps_job_ms, .5), 3),
+                                     "set_latency_ms_p50": round(_pctl(ps_lat, .5), 3),
+                                     "set_latency_ms_p99": round(_pctl(ps_lat, .99), 3)},
+                   "identical_to_per_set": f"{same}/{nsets}",
+                   "kernels": {k: {"launches": c, "ms": round(ms, 4)} for k, (c, ms) in
+                               sorted(prof.items(), key=lambda kv: -kv[1][1])}},
+        "roofline": roofline, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def _serve_session(bbx, torch, reqs, arrivals, inputs, cfg, sample):
+    """Runs one served session; returns per-request (latency s, bytes) and
+    the results of the sampled requests (device tensors, cloned)."""
+    srv = bbx.Server(cfg["budget"], max_jobs=cfg["max_jobs"], max_batch=cfg["max_batch"],
+                     nstreams=cfg["nstreams"], tile=cfg.get("tile", 0))
+    t0 = srv.now() + 0.05
+    arr = [t0 + a for a in arrivals]
+    lat, nbytes, kept, jobs_per_launch = {}, {}, {}, []
+    ids, k, max_inflight = {}, 0, 0
+    while len(lat) < len(reqs):
+        now = srv.now()
+        while k < len(reqs) and now >= arr[k]:
+            n, kind, comp = reqs[k]
+            if comp:
+                jid = srv.submit_compress(inputs[k]["x"], 1e-4, "rel", 32)
+            else:
+                jid = srv.submit_decompress(inputs[k]["stream"], inputs[k]["header"])
+            ids[jid] = k
+            k += 1
+        srv.progress()
+        max_inflight = max(max_inflight, srv.counts()["inflight"])
+        while True:
+            jid = srv.pop_done()
+            if not jid:
+                break
+            d = srv.info(jid)
+            i = ids[jid]
+            if d["status"] != 0:
+                raise RuntimeError(f"served request {i} failed: {d}")
+            lat[i] = d["t_done"] - arr[i]
+            nbytes[i] = 12 * reqs[i][0]
+            jobs_per_launch.append(d["batch_jobs"])
+            if i in sample:
+                kept[i] = srv.result(jid).clone()
+            srv.release(jid)
+        if srv.now() - t0 > 300:
+            raise RuntimeError("served session did not finish in 300 s")
+    makespan = max(arr[i] + lat[i] for i in lat) - t0
+    launches = srv.counts()["launches"]
+    srv.close()
+    return lat, nbytes, kept, makespan, launches, max_inflight, jobs_per_launch
+
+
+def bench_served(args):
+    """Poisson arrivals of compress/decompress requests served with
+    continuous batching, against one launch per request on the same GPU."""
+    import numpy as np
+    import torch
+
+    import paper_2404_02826_amd as bbx
+    from synth import poisson_arrivals, request_pool, served_requests
+
+    nreq = args.requests
+    reqs = served_requests(nreq, seed0=6)
+    nmax = max(r[0] for r in reqs)
+    t0 = time.time()
+    pools = {k: torch.from_numpy(request_pool(k, nmax)).cuda() for k in ("uniform", "cosmology")}
+    log(f"pools of {nmax} particles in {time.time() - t0:.1f}s")
+    inputs = []
+    for n, kind, comp in reqs:
+        x = pools[kind][:n]
+        d = {"x": x}
+        if not comp:
+            st = bbx.compress(x, 1e-4, "rel", 32)
+            d["stream"] = st
+            d["header"] = st[:128].cpu().numpy().tobytes()
+        inputs.append(d)
+    torch.cuda.synchronize()
+    log(f"prepared {nreq} requests ({sum(1 for r in reqs if not r[2])} decompress streams)")
+    arrivals = poisson_arrivals(nreq, args.qps, seed=7)
+    sample = set(int(i) for i in np.random.default_rng(2).choice(nreq, size=min(64, nreq),
+                                                                  replace=False))
+    budget = 64 << 30
+    cfgs = {"continuous_batching": dict(budget=budget, max_jobs=4096, max_batch=256, nstreams=4),
+            "one_launch_per_request": dict(budget=budget, max_jobs=4096, max_batch=1, nstreams=1)}
+    res = {}
+    for name, cfg in cfgs.items():
+        for _ in range(args.warmup):  # a short warm-up session on the first requests
+            _serve_session(bbx, torch, reqs[:32], arrivals[:32], inputs[:32], cfg, set())
+        lat, nbytes, kept, span, launches, infl, jpl = _serve_session(
+            bbx, torch, reqs, arrivals, inputs, cfg, sample)
+        ls = [lat[i] * 1e3 for i in range(nreq)]
+        res[name] = dict(gbps=round(sum(nbytes.values()) / span / 1e9, 2),
+                         makespan_s=round(span, 4), p50_ms=round(_pctl(ls, .5), 3),
+                         p99_ms=round(_pctl(ls, .99), 3), launches=launches,
+                         max_launches_in_flight=infl,
+                         mean_jobs_per_launch=round(float(np.mean(jpl)), 2), kept=kept)
+        log(f"{name}: {res[name]['gbps']} GB/s, p50 {res[name]['p50_ms']} ms, "
+            f"p99 {res[name]['p99_ms']} ms, {launches} launches")
+    # each sampled result is the same alone and in the mix
+    same = 0
+    for i in sample:
+        n, kind, comp = reqs[i]
+        alone = (bbx.compress(inputs[i]["x"], 1e-4, "rel", 32) if comp
+                 else bbx.decompress(inputs[i]["stream"]).view(torch.uint8).reshape(-1))
+        a = res["continuous_batching"]["kept"][i].reshape(-1).view(torch.uint8)
+        b = res["one_launch_per_request"]["kept"][i].reshape(-1).view(torch.uint8)
+        same += int(torch.equal(a, alone.reshape(-1)) and torch.equal(b, alone.reshape(-1)))
+    for r in res.values():
+        r.pop("kept")
+    cb, pr = res["continuous_batching"], res["one_launch_per_request"]
+    out = {
+        "metric": "served compress+decompress GB/s and p50/p99 latency (Poisson arrivals, "
+                  "10^4..10^7 FP32 xyz particles per request, rel eb 1e-4)",
+        "value": cb["gbps"], "unit": "GB/s", "n_gpus": 1, "steps": nreq, "warmup": args.warmup,
+        "ms_per_step": round(cb["makespan_s"] * 1e3 / nreq, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"served-poisson-{args.qps:g}qps-{nreq}req", "qps": args.qps,
+                   "requests": nreq, "hbm_budget_bytes": budget,
+                   "compress_requests": sum(1 for r in reqs if r[2]),
+                   "input_bytes": int(sum(12 * r[0] for r in reqs)),
+                   "continuous_batching": cb, "one_launch_per_request": pr,
+                   "sampled_results_equal_alone": f"{same}/{len(sample)}"},
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="fluid-2^27-f32", choices=sorted(WORKLOADS))
-    ap.add_argument("--leaf-size", type=int, default=32)
+    ap.add_argument("--workload", default="fluid-2^27-f32",
+                    choices=sorted(WORKLOADS) + ["batch-4096-f32", "served"])
+    ap.add_argument("--leaf-size", type=int, default=32,
+                    help="leaf size r (batch workload: 0 = autotuned per set)")
+    ap.add_argument("--tile", type=int, default=0, help="batch workload: 0 = autotuned")
+    ap.add_argument("--nsets", type=int, default=4096)
+    ap.add_argument("--requests", type=int, default=2000, help="served workload: requests")
+    ap.add_argument("--qps", type=float, default=400.0, help="served workload: arrival rate")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 22)
     args = ap.parse_args()
@@ -77,6 +381,12 @@ def main():
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for {args.gpus})",
               file=sys.stderr)
         sys.exit(2)
+    if args.workload.startswith("batch-"):
+        bench_batch(args)
+        return
+    if args.workload == "served":
+        bench_served(args)
+        return
 
     import numpy as np
     import torch

@@ -10,11 +10,13 @@ library is missing, every call raises.
 from __future__ import annotations
 
 from ._binding import (  # noqa: F401
+    Arena,
     BatchCompressor,
     BitboxError,
     Compressor,
     Decompressor,
     STATUS,
+    Server,
     compress,
     compress_bound,
     compress_workspace_size,

@@ -38,6 +38,18 @@ class _Set(C.Structure):
                 ("d_status", C.c_void_p), ("d_perm", C.c_void_p)]
 
 
+class _ServerConfig(C.Structure):
+    _fields_ = [("hbm_budget", C.c_size_t), ("max_jobs", C.c_uint32), ("max_batch", C.c_uint32),
+                ("nstreams", C.c_uint32), ("tile_override", C.c_uint32)]
+
+
+class _JobInfo(C.Structure):
+    _fields_ = [("state", C.c_uint32), ("status", C.c_uint32), ("bytes", C.c_uint64),
+                ("d_result", C.c_void_p), ("t_submit", C.c_double), ("t_admit", C.c_double),
+                ("t_launch", C.c_double), ("t_done", C.c_double), ("batch_jobs", C.c_uint32),
+                ("kind", C.c_uint32)]
+
+
 def lib_path() -> str:
     return _LIB_PATH
 
@@ -64,6 +76,38 @@ def load():
         f = getattr(lib, nm)
         f.restype = i32
         f.argtypes = [C.POINTER(_Set), u32, vp, sz, vp]
+    vpp = C.POINTER(C.c_void_p)
+    lib.bbx_arena_create.restype = i32
+    lib.bbx_arena_create.argtypes = [sz, sz, vpp]
+    lib.bbx_arena_destroy.restype = None
+    lib.bbx_arena_destroy.argtypes = [vp]
+    lib.bbx_arena_alloc.restype = i32
+    lib.bbx_arena_alloc.argtypes = [vp, sz, C.POINTER(sz)]
+    lib.bbx_arena_free.restype = i32
+    lib.bbx_arena_free.argtypes = [vp, sz]
+    lib.bbx_arena_stats.restype = None
+    lib.bbx_arena_stats.argtypes = [vp] + [C.POINTER(sz)] * 4
+    lib.bbx_server_create.restype = i32
+    lib.bbx_server_create.argtypes = [C.POINTER(_ServerConfig), vp, sz, vpp]
+    lib.bbx_server_destroy.restype = i32
+    lib.bbx_server_destroy.argtypes = [vp]
+    lib.bbx_server_submit_compress.restype = i32
+    lib.bbx_server_submit_compress.argtypes = [vp, vp, u64, u32, i32, dbl, C.POINTER(_Params),
+                                               C.POINTER(u64)]
+    lib.bbx_server_submit_decompress.restype = i32
+    lib.bbx_server_submit_decompress.argtypes = [vp, vp, sz, vp, i32, C.POINTER(u64)]
+    lib.bbx_server_progress.restype = i32
+    lib.bbx_server_progress.argtypes = [vp, C.POINTER(u32)]
+    lib.bbx_server_pop_done.restype = u64
+    lib.bbx_server_pop_done.argtypes = [vp]
+    lib.bbx_server_job_info.restype = i32
+    lib.bbx_server_job_info.argtypes = [vp, u64, C.POINTER(_JobInfo)]
+    lib.bbx_server_release.restype = i32
+    lib.bbx_server_release.argtypes = [vp, u64]
+    lib.bbx_server_now.restype = dbl
+    lib.bbx_server_now.argtypes = [vp]
+    lib.bbx_server_counts.restype = None
+    lib.bbx_server_counts.argtypes = [vp] + [C.POINTER(u32)] * 4 + [C.POINTER(u64), C.POINTER(sz)]
     lib.bbx_stream_info.restype = i32
     lib.bbx_stream_info.argtypes = [vp, sz, C.POINTER(u64), C.POINTER(u32), C.POINTER(i32),
                                     C.POINTER(dbl), C.POINTER(u32), C.POINTER(u64), C.POINTER(u64)]
@@ -300,6 +344,142 @@ class BatchCompressor:
         self.upload(stream)
         self.launch(stream)
         return self.results()
+
+
+class Arena:
+    """Host bookkeeping of the serving runtime's device-memory arena
+    (offsets only; no device access)."""
+
+    def __init__(self, size: int, align: int = 256):
+        self._lib = load()
+        h = C.c_void_p()
+        _check(self._lib.bbx_arena_create(size, align, C.byref(h)))
+        self._h = h
+
+    def alloc(self, nbytes: int) -> int:
+        off = C.c_size_t()
+        _check(self._lib.bbx_arena_alloc(self._h, nbytes, C.byref(off)))
+        return off.value
+
+    def free(self, off: int):
+        _check(self._lib.bbx_arena_free(self._h, off))
+
+    def stats(self) -> dict:
+        v = [C.c_size_t() for _ in range(4)]
+        self._lib.bbx_arena_stats(self._h, *[C.byref(x) for x in v])
+        return dict(used=v[0].value, free_total=v[1].value, largest_free=v[2].value,
+                    free_ranges=v[3].value)
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            self._lib.bbx_arena_destroy(self._h)
+            self._h = None
+
+
+JOB_STATES = {0: "queued", 1: "admitted", 2: "running", 3: "done"}
+
+
+class Server:
+    """Continuous-batching server over one device arena of ``hbm_budget``
+    bytes (allocated here once; the runtime sub-allocates inside it).
+
+    Jobs reference caller-owned device inputs, which must stay unchanged
+    until the job is done.  ``progress()`` never waits for the GPU.
+    """
+
+    def __init__(self, hbm_budget: int, max_jobs: int = 1024, max_batch: int = 256,
+                 nstreams: int = 4, tile: int = 0, device="cuda"):
+        self._lib = load()
+        self.arena = torch.empty(hbm_budget, dtype=torch.uint8, device=device)
+        cfg = _ServerConfig(hbm_budget, max_jobs, max_batch, nstreams, tile)
+        h = C.c_void_p()
+        _check(self._lib.bbx_server_create(C.byref(cfg), self.arena.data_ptr(), hbm_budget,
+                                           C.byref(h)))
+        self._h = h
+        self._meta = {}
+
+    def submit_compress(self, pos: torch.Tensor, eb: float, eb_mode: str = "rel",
+                        leaf_size: int = 32, layout: str = "aos") -> int:
+        n, dims, lay = _shape(pos, layout)
+        if not pos.is_cuda or not pos.is_contiguous():
+            raise ValueError("positions must be a contiguous device tensor")
+        prm = _params(leaf_size, eb_mode, lay, 0)
+        jid = C.c_uint64()
+        _check(self._lib.bbx_server_submit_compress(self._h, pos.data_ptr() if n else None, n, dims,
+                                                    _dtype_code(pos), float(eb), C.byref(prm),
+                                                    C.byref(jid)))
+        self._meta[jid.value] = ("c", None)
+        return jid.value
+
+    def submit_decompress(self, stream_t: torch.Tensor, header: bytes, layout: str = "aos") -> int:
+        hb = bytes(header[:128])
+        info = stream_info(hb)
+        jid = C.c_uint64()
+        _check(self._lib.bbx_server_submit_decompress(self._h, stream_t.data_ptr(),
+                                                      stream_t.numel(), hb,
+                                                      AOS if layout == "aos" else SOA,
+                                                      C.byref(jid)))
+        self._meta[jid.value] = ("d", (info, layout))
+        return jid.value
+
+    def progress(self) -> int:
+        nd = C.c_uint32()
+        _check(self._lib.bbx_server_progress(self._h, C.byref(nd)))
+        return nd.value
+
+    def pop_done(self) -> int:
+        return int(self._lib.bbx_server_pop_done(self._h))
+
+    def info(self, jid: int) -> dict:
+        ji = _JobInfo()
+        _check(self._lib.bbx_server_job_info(self._h, jid, C.byref(ji)))
+        return dict(state=JOB_STATES[ji.state], status=ji.status, bytes=ji.bytes,
+                    d_result=ji.d_result, t_submit=ji.t_submit, t_admit=ji.t_admit,
+                    t_launch=ji.t_launch, t_done=ji.t_done, batch_jobs=ji.batch_jobs,
+                    kind="compress" if ji.kind == 0 else "decompress")
+
+    def result(self, jid: int) -> torch.Tensor:
+        """The finished job's result as a view into the arena (valid until
+        release): uint8 stream bytes, or positions of the stream's type."""
+        d = self.info(jid)
+        if d["state"] != "done":
+            raise RuntimeError("job not finished")
+        if d["status"] != 0:
+            raise BitboxError(d["status"], f"job {jid}")
+        off = d["d_result"] - self.arena.data_ptr()
+        raw = self.arena[off: off + d["bytes"]]
+        kind, extra = self._meta[jid]
+        if kind == "c":
+            return raw
+        info, layout = extra
+        dt = torch.float32 if info["dtype"] == F32 else torch.float64
+        n, dims = info["n"], info["dims"]
+        return raw.view(dt).view((n, dims) if layout == "aos" else (dims, n))
+
+    def release(self, jid: int):
+        _check(self._lib.bbx_server_release(self._h, jid))
+        self._meta.pop(jid, None)
+
+    def now(self) -> float:
+        return float(self._lib.bbx_server_now(self._h))
+
+    def counts(self) -> dict:
+        v = [C.c_uint32() for _ in range(4)]
+        la, au = C.c_uint64(), C.c_size_t()
+        self._lib.bbx_server_counts(self._h, *[C.byref(x) for x in v], C.byref(la), C.byref(au))
+        return dict(queued=v[0].value, admitted=v[1].value, running=v[2].value,
+                    inflight=v[3].value, launches=la.value, arena_used=au.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(self._lib.bbx_server_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass
 
 
 def stream_info(header: bytes) -> dict:

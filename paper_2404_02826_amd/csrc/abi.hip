@@ -20,6 +20,8 @@ static bbx_status fail(bbx_status st, const std::string& msg) {
   return st;
 }
 
+bbx_status set_error(bbx_status st, const char* msg) { return fail(st, msg); }
+
 // ---------------------------------------------------------------- profiling
 
 struct ProfEntry {
@@ -120,6 +122,7 @@ struct SetIn {
   uint64_t* d_size;
   uint32_t* d_status;
   uint32_t* d_perm;
+  bool need_idx;  // plan source-index buffers (a perm output is asked for)
 };
 
 static bbx_status check_compress_args(uint64_t n, uint32_t dims, bbx_dtype dtype, double eb,
@@ -233,7 +236,7 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
       D.leaf_off = leaves_n;
       D.part_off = parts;
       key_bytes += align_up((uint64_t)D.dims * n * 4);
-      idx_n += (n + 63) & ~63ull;
+      if (I.need_idx) idx_n += (n + 63) & ~63ull;
       hist_n += max_nodes * kHistBins;
       sel_n += max_nodes;
       rows_n += max_blocks;
@@ -325,7 +328,20 @@ static bbx_status check_batch(const SetIn* in, uint32_t nsets) {
   return BBX_OK;
 }
 
-// Uploads descriptors and prefix arrays (stream-ordered copy from host memory).
+// A small descriptor blob travels as a kernel argument: no host-to-device
+// copy, so the host never waits for the stream and the upload can be
+// recorded in a graph.
+constexpr uint32_t kArgBlob = 2304;  // one set at any size fits
+struct ArgBlob {
+  uint32_t words;
+  uint32_t w[kArgBlob / 4];
+};
+
+__global__ void __launch_bounds__(kBlock) k_put_blob(ArgBlob b, uint32_t* dst) {
+  for (uint32_t i = threadIdx.x; i < b.words; i += blockDim.x) dst[i] = b.w[i];
+}
+
+// Uploads descriptors and prefix arrays (stream-ordered).
 static bbx_status batch_upload(const SetIn* in, uint32_t nsets, void* d_ws, size_t ws_size,
                                hipStream_t stream) {
   BatchPlan bp;
@@ -338,6 +354,16 @@ static bbx_status batch_upload(const SetIn* in, uint32_t nsets, void* d_ws, size
   std::vector<uint8_t> blob(lay.pre + 8 * pre.size() - lay.sets);
   memcpy(blob.data(), descs.data(), sizeof(SetDesc) * nsets);
   memcpy(blob.data() + (lay.pre - lay.sets), pre.data(), 8 * pre.size());
+  if (blob.size() <= kArgBlob) {
+    ArgBlob ab;
+    memset(&ab, 0, sizeof(ab));
+    ab.words = (uint32_t)((blob.size() + 3) / 4);
+    memcpy(ab.w, blob.data(), blob.size());
+    BBX_LAUNCH("upload", k_put_blob, 1, kBlock, 0, stream, ab, (uint32_t*)((uint8_t*)d_ws + lay.sets));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(BBX_EHIP, std::string("descriptor upload failed: ") + hipGetErrorString(e));
+    return BBX_OK;
+  }
   hipError_t e = hipMemcpyAsync((uint8_t*)d_ws + lay.sets, blob.data(), blob.size(),
                                 hipMemcpyHostToDevice, stream);
   if (e != hipSuccess) return fail(BBX_EHIP, std::string("descriptor upload failed: ") + hipGetErrorString(e));
@@ -467,6 +493,7 @@ size_t bbx_compress_workspace_size(uint64_t n, uint32_t dims, bbx_dtype dtype,
   in.dtype = dtype;
   in.eb = 1.0;
   in.prm = *params;
+  in.need_idx = true;  // the caller may ask for a perm output
   BatchPlan bp;
   std::vector<SetDesc> descs;
   std::vector<uint64_t> pre;
@@ -493,6 +520,7 @@ bbx_status bbx_compress(const void* d_pos, uint64_t n, uint32_t dims, bbx_dtype 
   in.d_size = d_size;
   in.d_status = d_status;
   in.d_perm = d_perm;
+  in.need_idx = true;  // same plan as bbx_compress_workspace_size
   st = check_set(in);
   if (st != BBX_OK) return st;
   st = batch_upload(&in, 1, d_ws, ws_size, stream);
@@ -532,6 +560,7 @@ static bool sets_from_abi(const bbx_set* sets, uint32_t nsets, std::vector<SetIn
     I.d_size = sets[s].d_size;
     I.d_status = sets[s].d_status;
     I.d_perm = sets[s].d_perm;
+    I.need_idx = I.d_perm != nullptr;
   }
   return true;
 }

@@ -288,6 +288,9 @@ struct DecompressWs {
 
 uint64_t scan_blocks(uint64_t count);
 
+// Sets the calling thread's error message (bbx_last_error) and returns st.
+bbx_status set_error(bbx_status st, const char* msg);
+
 // launchers (one group per translation unit)
 hipError_t launch_range(const BatchPlan& bp, const Ws& w, hipStream_t s);
 hipError_t launch_levels(const BatchPlan& bp, const Ws& w, hipStream_t s);

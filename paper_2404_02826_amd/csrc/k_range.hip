@@ -36,15 +36,17 @@ __device__ inline double wave_max(double v) {
 }
 
 template <typename T>
-__device__ void minmax_body(const SetDesc& S, uint64_t lb, double* part) {
+__device__ void minmax_body(const T* __restrict__ pos, uint64_t n, uint32_t dims, uint32_t layout,
+                            uint64_t lb, uint32_t mm_blocks, double* part) {
   double lo[3] = {INFINITY, INFINITY, INFINITY};
   double hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   double bad = 0.0;
-  const T* pos = (const T*)S.pos;
-  const uint64_t stride = (uint64_t)S.mm_blocks * blockDim.x;
-  for (uint64_t i = lb * blockDim.x + threadIdx.x; i < S.n; i += stride) {
-    for (uint32_t d = 0; d < S.dims; ++d) {
-      const double v = load_coord(pos, S.n, S.dims, S.layout, i, d);
+  const uint64_t stride = (uint64_t)mm_blocks * blockDim.x;
+  for (uint64_t i = lb * blockDim.x + threadIdx.x; i < n; i += stride) {
+#pragma unroll
+    for (uint32_t d = 0; d < 3; ++d) {
+      if (d >= dims) break;
+      const double v = load_coord(pos, n, dims, layout, i, d);
       if (!isfinite(v)) bad = 1.0;
       lo[d] = v < lo[d] ? v : lo[d];
       hi[d] = v > hi[d] ? v : hi[d];
@@ -80,10 +82,12 @@ __global__ void __launch_bounds__(kBlock) k_minmax(uint32_t nsets, const uint64_
   const SetDesc& S = sets[s];
   const uint64_t lb = blockIdx.x - pre[s];
   double* part = partials + (S.part_off + lb) * 8;
+  const uint64_t n = S.n;
+  const uint32_t dims = S.dims, layout = S.layout, mmb = S.mm_blocks;
   if (S.dtype == BBX_F32)
-    minmax_body<float>(S, lb, part);
+    minmax_body<float>((const float*)S.pos, n, dims, layout, lb, mmb, part);
   else
-    minmax_body<double>(S, lb, part);
+    minmax_body<double>((const double*)S.pos, n, dims, layout, lb, mmb, part);
 }
 
 __global__ void __launch_bounds__(kBlock) k_epilogue(const SetDesc* sets, const double* partials,
@@ -193,25 +197,35 @@ __global__ void __launch_bounds__(kBlock) k_epilogue(const SetDesc* sets, const 
   *P = p;
 }
 
-template <typename T>
-__device__ void quantize_body(const SetDesc& S, const DevParams* P, uint64_t lb, uint64_t nblk,
-                              uint8_t* keys, uint32_t* idx) {
-  const double inv_w = P->inv_w;
-  const bool k16 = P->key16 != 0;
-  const T* pos = (const T*)S.pos;
-  const uint64_t n = S.n;
+template <typename T, typename KT>
+__device__ void quantize_body(const T* __restrict__ pos, uint64_t n, uint32_t dims,
+                              uint32_t layout, double lo0, double lo1, double lo2, double inv_w,
+                              uint64_t lb, uint64_t nblk, KT* __restrict__ keys,
+                              uint32_t* __restrict__ idx) {
+  const double lo[3] = {lo0, lo1, lo2};
   const uint64_t stride = nblk * blockDim.x;
   for (uint64_t i = lb * blockDim.x + threadIdx.x; i < n; i += stride) {
-    for (uint32_t d = 0; d < S.dims; ++d) {
-      const double x = load_coord(pos, n, S.dims, S.layout, i, d);
-      const uint32_t q = (uint32_t)floor((x - P->lo[d]) * inv_w + 0.5);
-      if (k16)
-        ((uint16_t*)keys)[(uint64_t)d * n + i] = (uint16_t)q;
-      else
-        ((uint32_t*)keys)[(uint64_t)d * n + i] = q;
+#pragma unroll
+    for (uint32_t d = 0; d < 3; ++d) {
+      if (d >= dims) break;
+      const double x = load_coord(pos, n, dims, layout, i, d);
+      keys[(uint64_t)d * n + i] = (KT)(uint32_t)floor((x - lo[d]) * inv_w + 0.5);
     }
     if (idx) idx[i] = (uint32_t)i;
   }
+}
+
+template <typename T>
+__device__ void quantize_set(const SetDesc& S, const DevParams* P, uint64_t lb, uint64_t nblk,
+                             uint8_t* keys, uint32_t* idx) {
+  const T* pos = (const T*)S.pos;
+  const uint64_t n = S.n;
+  const uint32_t dims = S.dims, layout = S.layout;
+  const double l0 = P->lo[0], l1 = P->lo[1], l2 = P->lo[2], iw = P->inv_w;
+  if (P->key16)
+    quantize_body<T, uint16_t>(pos, n, dims, layout, l0, l1, l2, iw, lb, nblk, (uint16_t*)keys, idx);
+  else
+    quantize_body<T, uint32_t>(pos, n, dims, layout, l0, l1, l2, iw, lb, nblk, (uint32_t*)keys, idx);
 }
 
 __global__ void __launch_bounds__(kBlock) k_quantize(uint32_t nsets, const uint64_t* pre,
@@ -224,9 +238,9 @@ __global__ void __launch_bounds__(kBlock) k_quantize(uint32_t nsets, const uint6
   const uint64_t lb = blockIdx.x - pre[s], nblk = pre[s + 1] - pre[s];
   uint32_t* idx = S.perm ? idx0 + S.idx_off : nullptr;
   if (S.dtype == BBX_F32)
-    quantize_body<float>(S, P, lb, nblk, keys0 + S.key_off, idx);
+    quantize_set<float>(S, P, lb, nblk, keys0 + S.key_off, idx);
   else
-    quantize_body<double>(S, P, lb, nblk, keys0 + S.key_off, idx);
+    quantize_set<double>(S, P, lb, nblk, keys0 + S.key_off, idx);
 }
 
 hipError_t launch_range(const BatchPlan& bp, const Ws& w, hipStream_t s) {

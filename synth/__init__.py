@@ -10,7 +10,11 @@ from .generators import (  # noqa: F401
     cosmology,
     fluid,
     fluid_lattice_dims,
+    batch_plan,
+    batch_set,
     batch_sets,
     served_requests,
+    request_pool,
+    poisson_arrivals,
     sha256_of,
 )

@@ -113,6 +113,24 @@ def fluid(nx: int, ny: int, nz: int, seed: int = 4, amp: float = 2.0,
     return np.ascontiguousarray(out[perm])
 
 
+def batch_plan(nsets: int, seed0: int = 5, lo_exp: float = 3.0, hi_exp: float = 6.0):
+    """Sizes (log-uniform 10^lo_exp..10^hi_exp), kinds and relative bounds
+    of the sets of ``batch_sets``: (sizes int64[nsets], kinds list, ebs list)."""
+    master = _rng((seed0, 0x5E75))
+    sizes = np.rint(10.0 ** master.uniform(lo_exp, hi_exp, size=nsets)).astype(np.int64)
+    kinds = master.integers(0, 2, size=nsets)
+    ebs = np.where(master.integers(0, 2, size=nsets) == 0, 1e-3, 1e-4)
+    return (sizes, ["uniform" if k == 0 else "cosmology" for k in kinds],
+            [float(e) for e in ebs])
+
+
+def batch_set(s: int, n: int, kind: str, seed0: int = 5, dtype=np.float32):
+    """Positions of set s of ``batch_sets`` (independent of the other sets)."""
+    if kind == "uniform":
+        return uniform_cube(n, seed=(seed0, s), dtype=dtype)
+    return cosmology(n, seed=(seed0, s), dtype=dtype, halo_seed=(seed0, 0xC0DE))
+
+
 def batch_sets(nsets: int, seed0: int = 5, lo_exp: float = 3.0, hi_exp: float = 6.0,
                dtype=np.float32):
     """Many independent sets of log-uniform sizes 10^lo_exp..10^hi_exp.
@@ -122,19 +140,9 @@ def batch_sets(nsets: int, seed0: int = 5, lo_exp: float = 3.0, hi_exp: float = 
     error bound of 1e-3 or 1e-4 with probability 1/2 each.  Yields
     (positions, rel_eb, kind) tuples lazily.
     """
-    master = _rng((seed0, 0x5E75))
-    sizes = np.rint(10.0 ** master.uniform(lo_exp, hi_exp, size=nsets)).astype(np.int64)
-    kinds = master.integers(0, 2, size=nsets)
-    ebs = np.where(master.integers(0, 2, size=nsets) == 0, 1e-3, 1e-4)
+    sizes, kinds, ebs = batch_plan(nsets, seed0, lo_exp, hi_exp)
     for s in range(nsets):
-        n = int(sizes[s])
-        if kinds[s] == 0:
-            pos = uniform_cube(n, seed=(seed0, s), dtype=dtype)
-            kind = "uniform"
-        else:
-            pos = cosmology(n, seed=(seed0, s), dtype=dtype, halo_seed=(seed0, 0xC0DE))
-            kind = "cosmology"
-        yield pos, float(ebs[s]), kind
+        yield batch_set(s, int(sizes[s]), kinds[s], seed0, dtype), ebs[s], kinds[s]
 
 
 def served_requests(nreq: int, seed0: int = 6, lo_exp: float = 4.0, hi_exp: float = 7.0):
@@ -142,7 +150,9 @@ def served_requests(nreq: int, seed0: int = 6, lo_exp: float = 4.0, hi_exp: floa
 
     Sizes are log-uniform 10^lo_exp..10^hi_exp; kind is uniform-cube or
     cosmology with probability 1/2; half the requests compress, half
-    decompress.  Positions are drawn separately with ``request_positions``.
+    decompress.  A request of size n and kind k takes the first n particles
+    of ``request_pool(k, ...)`` (a shuffled set, so every prefix is a uniform
+    random subset of it).
     """
     rng = _rng((seed0, 0x5E7E))
     sizes = np.rint(10.0 ** rng.uniform(lo_exp, hi_exp, size=nreq)).astype(np.int64)
@@ -150,3 +160,16 @@ def served_requests(nreq: int, seed0: int = 6, lo_exp: float = 4.0, hi_exp: floa
     comp = rng.integers(0, 2, size=nreq) == 0
     return [(int(sizes[i]), "uniform" if kinds[i] == 0 else "cosmology", bool(comp[i]))
             for i in range(nreq)]
+
+
+def request_pool(kind: str, nmax: int, seed0: int = 6, dtype=np.float32):
+    """The positions that served requests of one kind take prefixes of."""
+    if kind == "uniform":
+        return uniform_cube(nmax, seed=(seed0, 0x900), dtype=dtype)
+    return cosmology(nmax, seed=(seed0, 0x901), dtype=dtype)
+
+
+def poisson_arrivals(nreq: int, qps: float, seed: int = 7):
+    """Arrival times (seconds from 0) of a Poisson process of rate qps."""
+    rng = _rng((seed, 0xA77))
+    return np.cumsum(rng.exponential(1.0 / qps, size=nreq))

@@ -9,13 +9,16 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "bitbox.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("bitbox.h", "bitbox_serve.h")]
 
 
 def _declared():
-    src = open(HEADER).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(bbx_[a-z_0-9]+)\s*\(", src)))
+    names = set()
+    for h in HEADERS:
+        src = open(h).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names |= set(re.findall(r"\b(bbx_[a-z_0-9]+)\s*\(", src))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -30,8 +33,9 @@ def lib():
 def test_exports_every_declared_symbol(lib):
     names = _declared()
     assert "bbx_compress" in names and "bbx_decompress" in names
+    assert "bbx_compress_batch" in names and "bbx_server_progress" in names
     for nm in names:
-        assert hasattr(lib, nm), f"{nm} declared in bitbox.h but not exported"
+        assert hasattr(lib, nm), f"{nm} declared in include/ but not exported"
 
 
 def test_status_strings(lib):
