@@ -64,19 +64,45 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// inclusive scan over the 64 lanes
+// Wavefront-wide inclusive scans with DPP row shifts and row broadcasts (no
+// LDS traffic): rows of 16 lanes first, then row 0's total into row 1, row
+// 2's into row 3, and rows 0-1's total into rows 2-3.  Lanes whose source is
+// outside the row read the identity.
 __device__ inline uint32_t wave_incl(uint32_t x) {
-  const int lane = threadIdx.x & 63;
-  for (int o = 1; o < 64; o <<= 1) {
-    uint32_t y = __shfl_up(x, o);
-    if (lane >= o) x += y;
-  }
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false);  // row_shr:1
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false);  // row_shr:2
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false);  // row_shr:4
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false);  // row_shr:8
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);  // row_bcast:31
   return x;
+}
+__device__ inline uint32_t umin32(uint32_t a, uint32_t b) { return a < b ? a : b; }
+__device__ inline uint32_t umax32(uint32_t a, uint32_t b) { return a > b ? a : b; }
+// wavefront minimum / maximum, uniform result
+__device__ inline uint32_t wave_min_dpp(uint32_t x) {
+  const int I = -1;  // identity of min (0xffffffff)
+  x = umin32(x, (uint32_t)__builtin_amdgcn_update_dpp(I, (int)x, 0x111, 0xf, 0xf, false));
+  x = umin32(x, (uint32_t)__builtin_amdgcn_update_dpp(I, (int)x, 0x112, 0xf, 0xf, false));
+  x = umin32(x, (uint32_t)__builtin_amdgcn_update_dpp(I, (int)x, 0x114, 0xf, 0xf, false));
+  x = umin32(x, (uint32_t)__builtin_amdgcn_update_dpp(I, (int)x, 0x118, 0xf, 0xf, false));
+  x = umin32(x, (uint32_t)__builtin_amdgcn_update_dpp(I, (int)x, 0x142, 0xa, 0xf, false));
+  x = umin32(x, (uint32_t)__builtin_amdgcn_update_dpp(I, (int)x, 0x143, 0xc, 0xf, false));
+  return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
+}
+__device__ inline uint32_t wave_max_dpp(uint32_t x) {
+  x = umax32(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false));
+  x = umax32(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false));
+  x = umax32(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false));
+  x = umax32(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false));
+  x = umax32(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false));
+  x = umax32(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false));
+  return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
 }
 
 template <int TILE>
 struct WaveTile {
-  uint32_t K[3][TILE];           // codes at their original tile slots
+  uint32_t K[3][TILE];           // codes minus the tile's per-axis minimum, at original slots
   uint16_t Pm[2][TILE];          // position -> slot (ping-pong)
   uint32_t I[TILE];              // source indices (only with a perm output)
   uint32_t H[TILE];              // histogram bins (all zero between passes); then the leaf table
@@ -86,16 +112,96 @@ struct WaveTile {
   uint16_t lref[TILE];           // reference position within each leaf
 };
 
-template <int TILE>
-__device__ inline uint32_t node_of(const WaveTile<TILE>& sm, uint32_t N, uint32_t s0, uint32_t p) {
-  uint32_t i = (p * N) / s0;
-  if (i >= N) i = N - 1;
-  while (sm.nst[i] > p) --i;
-  while (p >= (uint32_t)sm.nst[i] + sm.nsz[i]) ++i;
-  return i;
-}
-
 __device__ inline uint32_t leaf_fold(uint32_t s, uint32_t r) { return s <= r ? s : s - (s >> 1); }
+
+// Bit boxes of the tile's leaves (Sec. 4.1, Eq. 2) by aligned groups of gs
+// lanes; DT holds squared distances in doubled code space (32 bits suffice
+// when every code span is below 2^14).
+template <int TILE, typename DT>
+__device__ void tile_bitboxes(WaveTile<TILE>& sm, int cur, uint32_t nl, uint32_t gs, uint32_t dims,
+                              uint32_t t0, uint32_t t1, uint32_t t2, uint64_t tst, uint64_t first_leaf,
+                              uint64_t n_leaves, DevParams* P, LeafRec* leaves,
+                              uint64_t* leaf_bits) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t lpw = 64 / gs;
+  const uint32_t sub = lane & (gs - 1);
+  for (uint32_t base = 0; base < nl; base += lpw) {
+    const uint32_t L = base + lane / gs;
+    const bool act = L < nl;
+    const uint32_t ls = act ? (sm.H[L] & 0xffffu) : 0u, lz = act ? (sm.H[L] >> 16) : 0u;
+    uint32_t mn[3] = {0xffffffffu, 0xffffffffu, 0xffffffffu}, mx[3] = {0, 0, 0};
+    for (uint32_t t = sub; t < lz; t += gs) {
+      const uint32_t slot = sm.Pm[cur][ls + t];
+#pragma unroll
+      for (uint32_t d = 0; d < 3; ++d) {
+        if (d >= dims) break;
+        const uint32_t q = sm.K[d][slot];
+        mn[d] = umin32(q, mn[d]);
+        mx[d] = umax32(q, mx[d]);
+      }
+    }
+    DT C[3] = {0, 0, 0};
+#pragma unroll
+    for (uint32_t d = 0; d < 3; ++d) {
+      if (d >= dims) break;
+      mn[d] = gmin_u32(mn[d], gs);
+      mx[d] = gmax_u32(mx[d], gs);
+      C[d] = (DT)mn[d] + (DT)mx[d];
+    }
+    DT best = (DT)~(DT)0;
+    uint32_t bpos = 0xffffffffu;
+    for (uint32_t t = sub; t < lz; t += gs) {
+      const uint32_t slot = sm.Pm[cur][ls + t];
+      DT dist = 0;
+#pragma unroll
+      for (uint32_t d = 0; d < 3; ++d) {
+        if (d >= dims) break;
+        const DT q2 = 2 * (DT)sm.K[d][slot];
+        const DT a = q2 > C[d] ? q2 - C[d] : C[d] - q2;
+        dist += a * a;
+      }
+      if (dist < best) best = dist, bpos = t;  // t increases: ties keep the first
+    }
+    for (uint32_t o = gs >> 1; o > 0; o >>= 1) {
+      const DT d2 = __shfl_xor(best, (int)o);
+      const uint32_t p2 = __shfl_xor(bpos, (int)o);
+      if (d2 < best || (d2 == best && p2 < bpos)) best = d2, bpos = p2;
+    }
+    if (!act) continue;
+    const uint32_t ref = bpos;
+    for (uint32_t t = sub; t < lz; t += gs) sm.S[ls + t] = L;  // position -> leaf
+    if (sub == 0) {
+      const uint32_t rslot = sm.Pm[cur][ls + ref];
+      const uint32_t tmin[3] = {t0, t1, t2};
+      uint32_t m[3] = {0, 0, 0}, qr[3] = {0, 0, 0};
+      uint32_t summ = 0;
+#pragma unroll
+      for (uint32_t d = 0; d < 3; ++d) {
+        if (d >= dims) break;
+        const uint32_t q = sm.K[d][rslot];
+        const uint32_t D = umax32(q - mn[d], mx[d] - q);
+        m[d] = width_of(D);
+        qr[d] = q + tmin[d];
+        summ += m[d];
+      }
+      sm.lref[L] = (uint16_t)ref;
+      const uint64_t lid = first_leaf + L;
+      if (lid < n_leaves) {
+        LeafRec rec;
+        rec.start = (uint32_t)(tst + ls);
+        rec.size = lz;
+        rec.m = m[0] | (m[1] << 8) | (m[2] << 16);
+        rec.qref[0] = qr[0];
+        rec.qref[1] = qr[1];
+        rec.qref[2] = qr[2];
+        leaves[lid] = rec;
+        leaf_bits[lid] = (uint64_t)(lz - 1) * summ;
+      } else {
+        P->status = BBX_EHIP;  // leaf count mismatch: never expected
+      }
+    }
+  }
+}
 
 template <int TILE, typename KT>
 __device__ void tile_body(WaveTile<TILE>& sm, uint64_t j, uint32_t K0, uint64_t n, uint32_t dims,
@@ -114,8 +220,11 @@ __device__ void tile_body(WaveTile<TILE>& sm, uint64_t j, uint32_t K0, uint64_t 
   const uint64_t first_leaf = leaves_before_node(g, K0, j, tst);
   const bool track = idx != nullptr;
 
-  // stage the node: loads of up to 8 rows in flight, then LDS stores
+  // ---- stage the node (loads of up to 8 rows in flight) and find the tile's
+  // per-axis code range: every later step works on codes minus the minimum,
+  // which keeps the radix digits few and the bins spread
   constexpr int EB = E < 8 ? E : 8;
+  uint32_t lo[3] = {0xffffffffu, 0xffffffffu, 0xffffffffu}, hi[3] = {0, 0, 0};
   for (int k0 = 0; k0 < E; k0 += EB) {
     uint32_t v[3][EB];
     uint32_t ix[EB];
@@ -132,13 +241,34 @@ __device__ void tile_body(WaveTile<TILE>& sm, uint64_t j, uint32_t K0, uint64_t 
       const uint32_t p = lane + 64u * (k0 + k);
       if (p < s0) {
 #pragma unroll
-        for (uint32_t d = 0; d < 3; ++d)
-          if (d < dims) sm.K[d][p] = v[d][k];
+        for (uint32_t d = 0; d < 3; ++d) {
+          if (d < dims) {
+            sm.K[d][p] = v[d][k];
+            lo[d] = umin32(lo[d], v[d][k]);
+            hi[d] = umax32(hi[d], v[d][k]);
+          }
+        }
         sm.Pm[0][p] = (uint16_t)p;
         if (track) sm.I[p] = ix[k];
       }
       sm.H[p] = 0;
     }
+  }
+  uint32_t tmin[3] = {0, 0, 0}, Gt[3] = {0, 0, 0};
+#pragma unroll
+  for (uint32_t d = 0; d < 3; ++d) {
+    if (d >= dims) break;
+    tmin[d] = wave_min_dpp(lo[d]);
+    Gt[d] = bitlen32(wave_max_dpp(hi[d]) - tmin[d]);
+  }
+  wave_sync();
+#pragma unroll
+  for (int k = 0; k < E; ++k) {
+    const uint32_t p = lane + 64u * k;
+    if (p < s0)
+#pragma unroll
+      for (uint32_t d = 0; d < 3; ++d)
+        if (d < dims) sm.K[d][p] -= tmin[d];
   }
   wave_sync();
 
@@ -146,12 +276,18 @@ __device__ void tile_body(WaveTile<TILE>& sm, uint64_t j, uint32_t K0, uint64_t 
   int last_l = -1;
   uint32_t lastN = 0;
   const uint32_t p0 = lane * E;
+  // the lane's E consecutive positions: node start and size at the current
+  // level, followed from level to level (a node's left child keeps the first
+  // floor(s/2) positions)
+  uint32_t nsr[E], nzz[E], ni[E];
+#pragma unroll
+  for (int k = 0; k < E; ++k) nsr[k] = 0, nzz[k] = s0, ni[k] = 0;
   for (uint32_t l = 0;; ++l) {
     const uint32_t N = 1u << l;
     const uint32_t maxsz = (s0 + N - 1) >> l;
     if (maxsz <= r) break;
     const uint32_t d = (K0 + l) % dims;
-    const uint32_t G = P->G[d];
+    const uint32_t G = d == 0 ? Gt[0] : (d == 1 ? Gt[1] : Gt[2]);
     for (uint32_t i = lane; i < N; i += 64) {
       uint64_t a, b;
       node_span(s0, l, i, &a, &b);
@@ -161,82 +297,86 @@ __device__ void tile_body(WaveTile<TILE>& sm, uint64_t j, uint32_t K0, uint64_t 
       sm.nrank[i] = (uint32_t)(b >> 1);
     }
     wave_sync();
-    // this level's view of the lane's E consecutive positions, kept in registers
-    uint32_t ni[E], nsr[E], nzz[E], slot[E], q[E];
+    uint32_t slot[E], q[E];
     bool inner[E];
 #pragma unroll
     for (int k = 0; k < E; ++k) {
       const uint32_t p = p0 + k;
-      const bool valid = p < s0;
-      const uint32_t i = valid ? node_of(sm, N, s0, p) : 0u;
-      ni[k] = i;
-      nsr[k] = sm.nst[i];
-      nzz[k] = sm.nsz[i];
-      inner[k] = valid && nzz[k] > r;
+      inner[k] = p < s0 && nzz[k] > r;
       slot[k] = sm.Pm[cur][p & (TILE - 1)] & (TILE - 1);
     }
 #pragma unroll
     for (int k = 0; k < E; ++k) q[k] = sm.K[d][slot[k]];
-    // ---- radix select of each internal node's median code (N << w <= TILE bins)
-    uint32_t Wl = 0;
-    while ((N << (Wl + 1)) <= (uint32_t)TILE && Wl < 8) ++Wl;
-    const uint32_t npass = G == 0 ? 1u : (G + Wl - 1) / Wl;
-    const uint32_t firstw = G - (npass - 1) * Wl;
-    uint32_t used = 0;
-    for (uint32_t pass = 0; pass < npass; ++pass) {
-      const uint32_t w = pass == 0 ? firstw : Wl;
-      const uint32_t hs = G - used;
-      used += w;
-      const uint32_t sh = G - used;
-      const uint32_t nb = 1u << w, mask = nb - 1;
-      uint32_t pre[E];
+    // ---- radix select of each internal node's median code (N << w <= TILE bins);
+    // with all codes equal the median is that code and nothing is counted
+    if (G > 0) {
+      uint32_t Wl = 0;
+      while ((N << (Wl + 1)) <= (uint32_t)TILE && Wl < 8) ++Wl;
+      const uint32_t npass = (G + Wl - 1) / Wl;
+      const uint32_t firstw = G - (npass - 1) * Wl;
+      uint32_t used = 0;
+      for (uint32_t pass = 0; pass < npass; ++pass) {
+        const uint32_t w = pass == 0 ? firstw : Wl;
+        const uint32_t hs = G - used;
+        used += w;
+        const uint32_t sh = G - used;
+        const uint32_t nb = 1u << w, mask = nb - 1;
+        if (pass == 0) {
 #pragma unroll
-      for (int k = 0; k < E; ++k) pre[k] = sm.npre[ni[k]];
+          for (int k = 0; k < E; ++k)
+            if (inner[k]) atomicAdd(&sm.H[(ni[k] << w) + ((q[k] >> sh) & mask)], 1u);
+        } else {
+          uint32_t pre[E];
 #pragma unroll
-      for (int k = 0; k < E; ++k)
-        if (inner[k] && (q[k] >> hs) == pre[k]) atomicAdd(&sm.H[(ni[k] << w) + ((q[k] >> sh) & mask)], 1u);
-      wave_sync();
-      if (N <= 8) {  // few nodes: the whole wavefront scans each node's bins
-        for (uint32_t i = 0; i < N; ++i) {
-          if (sm.nsz[i] <= r) continue;
-          const uint32_t per = (nb + 63) / 64;  // <= 4
-          uint32_t c[4] = {0, 0, 0, 0};
-          uint32_t mine = 0;
-          for (uint32_t k = 0; k < per; ++k) {
-            const uint32_t b = lane * per + k;
-            if (b < nb) {
-              c[k] = sm.H[(i << w) + b];
-              if (c[k]) sm.H[(i << w) + b] = 0;
+          for (int k = 0; k < E; ++k) pre[k] = sm.npre[ni[k]];
+#pragma unroll
+          for (int k = 0; k < E; ++k)
+            if (inner[k] && (q[k] >> hs) == pre[k])
+              atomicAdd(&sm.H[(ni[k] << w) + ((q[k] >> sh) & mask)], 1u);
+        }
+        wave_sync();
+        if (N <= 8) {  // few nodes: the whole wavefront scans each node's bins
+          for (uint32_t i = 0; i < N; ++i) {
+            if (sm.nsz[i] <= r) continue;
+            const uint32_t per = (nb + 63) / 64;  // <= 4
+            uint32_t c[4] = {0, 0, 0, 0};
+            uint32_t mine = 0;
+            for (uint32_t k = 0; k < per; ++k) {
+              const uint32_t b = lane * per + k;
+              if (b < nb) {
+                c[k] = sm.H[(i << w) + b];
+                if (c[k]) sm.H[(i << w) + b] = 0;
+              }
+              mine += c[k];
             }
-            mine += c[k];
+            uint32_t cum = wave_incl(mine) - mine;
+            const uint32_t rank = sm.nrank[i];
+            const uint32_t pr = sm.npre[i];
+            for (uint32_t k = 0; k < per; ++k) {
+              if (cum <= rank && rank < cum + c[k]) {
+                sm.npre[i] = (pr << w) | (lane * per + k);
+                sm.nrank[i] = rank - cum;
+              }
+              cum += c[k];
+            }
           }
-          uint32_t cum = wave_incl(mine) - mine;
-          const uint32_t rank = sm.nrank[i];
-          const uint32_t pr = sm.npre[i];
-          for (uint32_t k = 0; k < per; ++k) {
-            if (cum <= rank && rank < cum + c[k]) {
-              sm.npre[i] = (pr << w) | (lane * per + k);
-              sm.nrank[i] = rank - cum;
+        } else {  // many small nodes: one lane per node scans its few bins
+          for (uint32_t i = lane; i < N; i += 64) {
+            if (sm.nsz[i] <= r) continue;
+            const uint32_t rank = sm.nrank[i];
+            uint32_t cum = 0, found = 0xffffffffu, below = 0;
+            for (uint32_t b = 0; b < nb; ++b) {
+              const uint32_t c = sm.H[(i << w) + b];
+              if (c) sm.H[(i << w) + b] = 0;
+              if (found == 0xffffffffu && rank < cum + c) found = b, below = cum;
+              cum += c;
             }
-            cum += c[k];
+            sm.npre[i] = (sm.npre[i] << w) | found;
+            sm.nrank[i] = rank - below;
           }
         }
-      } else {  // many small nodes: one lane per node scans its few bins
-        for (uint32_t i = lane; i < N; i += 64) {
-          if (sm.nsz[i] <= r) continue;
-          const uint32_t rank = sm.nrank[i];
-          uint32_t cum = 0, found = 0xffffffffu, below = 0;
-          for (uint32_t b = 0; b < nb; ++b) {
-            const uint32_t c = sm.H[(i << w) + b];
-            if (c) sm.H[(i << w) + b] = 0;
-            if (found == 0xffffffffu && rank < cum + c) found = b, below = cum;
-            cum += c;
-          }
-          sm.npre[i] = (sm.npre[i] << w) | found;
-          sm.nrank[i] = rank - below;
-        }
+        wave_sync();
       }
-      wave_sync();
     }
     // ---- stable partition: exclusive prefix of (lt | eq << 16) over the tile
     uint32_t fl[E], jq[E];
@@ -259,14 +399,20 @@ __device__ void tile_body(WaveTile<TILE>& sm, uint64_t j, uint32_t K0, uint64_t 
     for (int k = 0; k < E; ++k) {
       const uint32_t p = p0 + k;
       const uint32_t ns = nsr[k], nz = nzz[k];
-      const uint32_t X = sm.S[p & (TILE - 1)] - sm.S[ns];
+      const uint32_t X = sm.S[p & (TILE - 1)] - sm.S[ns & (TILE - 1)];
       const uint32_t L = X & 0xffffu, Eq = X >> 16;
       const uint32_t jeq = jq[k];
-      const uint32_t lb = L + (Eq < jeq ? Eq : jeq);
+      const uint32_t lb = L + umin32(Eq, jeq);
       const bool lt = fl[k] & 1u, eq = (fl[k] >> 16) & 1u;
       const bool left = lt || (eq && Eq < jeq);
       const uint32_t dest = inner[k] ? ns + (left ? lb : (nz >> 1) + (p - ns) - lb) : p;
       if (p < s0 && dest < s0) sm.Pm[cur ^ 1][dest] = (uint16_t)slot[k];
+      // follow this position into its child of the next level
+      const uint32_t half = nz >> 1;
+      const bool right = p - ns >= half;
+      ni[k] = 2 * ni[k] + (right ? 1u : 0u);
+      nsr[k] = right ? ns + half : ns;
+      nzz[k] = right ? nz - half : half;
     }
     wave_sync();
     cur ^= 1;
@@ -302,77 +448,28 @@ __device__ void tile_body(WaveTile<TILE>& sm, uint64_t j, uint32_t K0, uint64_t 
         sm.H[at++] = ns | (nz << 16);
       }
     }
-    nl = __shfl(incl, 63);
+    nl = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
     const uint32_t a = s0 / N, b = (s0 + N - 1) / N;  // the two node sizes of the level
     maxleaf = leaf_fold(b, r);
     if (s0 % N != 0 && leaf_fold(a, r) > maxleaf) maxleaf = leaf_fold(a, r);
   }
   wave_sync();
 
-  // ---- bit box per leaf: aligned groups of gs lanes, 64/gs leaves at a time
+  // ---- bit box per leaf: all leaves in one pass when they fit the wavefront
+  // (groups of 64/nl lanes, each lane walking several members), else one lane
+  // group per leaf sized to the largest leaf
   uint32_t gs = 1;
-  while (gs < maxleaf && gs < 64) gs <<= 1;
-  const uint32_t lpw = 64 / gs;
-  const uint32_t sub = lane & (gs - 1);
-  for (uint32_t base = 0; base < nl; base += lpw) {
-    const uint32_t L = base + lane / gs;
-    const bool act = L < nl;
-    const uint32_t ls = act ? (sm.H[L] & 0xffffu) : 0u, lz = act ? (sm.H[L] >> 16) : 0u;
-    uint32_t mn[3] = {0xffffffffu, 0xffffffffu, 0xffffffffu}, mx[3] = {0, 0, 0};
-    for (uint32_t t = sub; t < lz; t += gs) {
-      const uint32_t slot = sm.Pm[cur][ls + t];
-      for (uint32_t d = 0; d < dims; ++d) {
-        const uint32_t q = sm.K[d][slot];
-        mn[d] = q < mn[d] ? q : mn[d];
-        mx[d] = q > mx[d] ? q : mx[d];
-      }
-    }
-    uint32_t C[3] = {0, 0, 0};
-    for (uint32_t d = 0; d < dims; ++d) {
-      mn[d] = gmin_u32(mn[d], gs);
-      mx[d] = gmax_u32(mx[d], gs);
-      C[d] = mn[d] + mx[d];
-    }
-    uint64_t best = ~0ull;
-    uint32_t bpos = 0xffffffffu;
-    for (uint32_t t = sub; t < lz; t += gs) {
-      const uint32_t slot = sm.Pm[cur][ls + t];
-      uint32_t q[3] = {0, 0, 0};
-      for (uint32_t d = 0; d < dims; ++d) q[d] = sm.K[d][slot];
-      const uint64_t dist = sqdist3(q, C, dims);
-      if (dist < best) best = dist, bpos = t;  // t increases: ties keep the first
-    }
-    gargmin(best, bpos, gs);
-    if (!act) continue;
-    const uint32_t ref = bpos;
-    for (uint32_t t = sub; t < lz; t += gs) sm.S[ls + t] = L;  // position -> leaf
-    if (sub == 0) {
-      const uint32_t rslot = sm.Pm[cur][ls + ref];
-      uint32_t m[3] = {0, 0, 0}, qr[3] = {0, 0, 0};
-      uint32_t summ = 0;
-      for (uint32_t d = 0; d < dims; ++d) {
-        qr[d] = sm.K[d][rslot];
-        const uint32_t D = (qr[d] - mn[d]) > (mx[d] - qr[d]) ? qr[d] - mn[d] : mx[d] - qr[d];
-        m[d] = width_of(D);
-        summ += m[d];
-      }
-      sm.lref[L] = (uint16_t)ref;
-      const uint64_t lid = first_leaf + L;
-      if (lid < n_leaves) {
-        LeafRec rec;
-        rec.start = (uint32_t)(tst + ls);
-        rec.size = lz;
-        rec.m = m[0] | (m[1] << 8) | (m[2] << 16);
-        rec.qref[0] = qr[0];
-        rec.qref[1] = qr[1];
-        rec.qref[2] = qr[2];
-        leaves[lid] = rec;
-        leaf_bits[lid] = (uint64_t)(lz - 1) * summ;
-      } else {
-        P->status = BBX_EHIP;  // leaf count mismatch: never expected
-      }
-    }
+  if (nl <= 64) {
+    while (gs * 2 * nl <= 64) gs <<= 1;
   }
+  while (gs > 1 && gs / 2 >= maxleaf) gs >>= 1;
+  const uint32_t span = umax32(Gt[0], umax32(Gt[1], Gt[2]));
+  if (span <= 14)
+    tile_bitboxes<TILE, uint32_t>(sm, cur, nl, gs, dims, tmin[0], tmin[1], tmin[2], tst,
+                                  first_leaf, n_leaves, P, leaves, leaf_bits);
+  else
+    tile_bitboxes<TILE, uint64_t>(sm, cur, nl, gs, dims, tmin[0], tmin[1], tmin[2], tst,
+                                  first_leaf, n_leaves, P, leaves, leaf_bits);
   wave_sync();
 
   // ---- write the node back in output-slot order (reference first per leaf)
@@ -383,7 +480,9 @@ __device__ void tile_body(WaveTile<TILE>& sm, uint64_t j, uint32_t K0, uint64_t 
     const uint32_t o = t == ref ? 0u : (t < ref ? t + 1 : t);
     const uint32_t slot = sm.Pm[cur][p];
     const uint64_t gpos = tst + ls + o;
-    for (uint32_t d = 0; d < dims; ++d) keys[(uint64_t)d * n + gpos] = (KT)sm.K[d][slot];
+#pragma unroll
+    for (uint32_t d = 0; d < 3; ++d)
+      if (d < dims) keys[(uint64_t)d * n + gpos] = (KT)(sm.K[d][slot] + tmin[d]);
     if (track) perm[gpos] = sm.I[slot];
   }
 }
