@@ -215,8 +215,8 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
       bg[s] = D.tile_mode ? 0 : D.n_leaves;
       const uint64_t mw = (D.n_leaves * (uint64_t)(D.dims * (D.mbits + 30)) + 63) / 64;
       pm[s] = std::max<uint64_t>(1, std::min<uint64_t>((mw + kBlock - 1) / kBlock, 1024));
-      const uint64_t pw = (n * (uint64_t)D.dims * 31 + 63) / 64;
-      pp[s] = std::max<uint64_t>(1, std::min<uint64_t>((pw + kBlock - 1) / kBlock, 4096));
+      const uint64_t lpb = leaves_per_block(D.r);
+      pp[s] = (D.n_leaves + lpb - 1) / lpb;
       uint64_t max_nodes = 0, max_blocks = 0;
       for (uint32_t k = 0; k < D.gl; ++k) {
         const LevelShape sh = level_shape(n, k);
@@ -235,7 +235,8 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
       D.cb_off = rows_n * 2;
       D.leaf_off = leaves_n;
       D.part_off = parts;
-      key_bytes += align_up((uint64_t)D.dims * n * 4);
+      D.kst = (n + 63) & ~63ull;
+      key_bytes += align_up((uint64_t)D.dims * D.kst * 4);
       if (I.need_idx) idx_n += (n + 63) & ~63ull;
       hist_n += max_nodes * kHistBins;
       sel_n += max_nodes;

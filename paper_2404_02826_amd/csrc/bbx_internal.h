@@ -74,6 +74,7 @@ struct SetDesc {
   uint64_t* d_size;       // optional stream length (UINT64_MAX on error)
   uint32_t* d_status;     // optional status
   uint64_t n, out_cap;
+  uint64_t kst;           // element stride between the code arrays of two axes (n rounded up to 64)
   double eb;
   uint32_t dims, dtype, layout, r, eb_mode, mbits;
   uint32_t gl;            // global levels
@@ -222,6 +223,13 @@ __host__ __device__ inline LevelShape level_shape(uint64_t n, uint32_t depth) {
   return sh;
 }
 
+// Leaves per block of the leaf-aligned packing and unpacking kernels: at most
+// 2048 slots and 256 leaves per block.
+__host__ __device__ inline uint32_t leaves_per_block(uint32_t r) {
+  const uint32_t l = r >= 2048 ? 1u : 2048u / r;
+  return l < 256u ? l : 256u;
+}
+
 // set owning global block b: largest s with pre[s] <= b (pre non-decreasing,
 // pre[0] = 0, b < pre[nsets])
 __device__ inline uint32_t find_set(const uint64_t* pre, uint32_t nsets, uint64_t b) {
@@ -234,6 +242,27 @@ __device__ inline uint32_t find_set(const uint64_t* pre, uint32_t nsets, uint64_
       hi = mid - 1;
   }
   return lo;
+}
+
+// ---------------------------------------------------------------- wavefront helpers
+
+// Inclusive scan over the 64 lanes with DPP row shifts and row broadcasts (no
+// LDS traffic): rows of 16 lanes first, then row 0's total into row 1, row
+// 2's into row 3, and rows 0-1's total into rows 2-3.  Lanes whose source is
+// outside the row read 0.
+__device__ inline uint32_t wave_incl(uint32_t x) {
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false);  // row_shr:1
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false);  // row_shr:2
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false);  // row_shr:4
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false);  // row_shr:8
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  return x;
+}
+
+// set bits of a wavefront mask in the lanes below this one
+__device__ inline uint32_t lanes_below(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
 // ---------------------------------------------------------------- launch plumbing

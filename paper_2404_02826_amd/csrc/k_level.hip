@@ -96,14 +96,15 @@ __device__ void hist_mid_body(uint32_t depth, uint32_t pass, const SetDesc& S, c
   const uint32_t nb = 1u << w, mask = nb - 1;
   lh[threadIdx.x] = 0;
   __syncthreads();
-  const KT* q = (const KT*)keys + (uint64_t)d * n + st;
-  const uint64_t beg = ch * (uint64_t)c.sh.chunk_elems;
-  const uint64_t end = beg + c.sh.chunk_elems < sz ? beg + c.sh.chunk_elems : sz;
-  for (uint64_t g = beg; g < end; g += kGroup) {
+  const KT* q = (const KT*)keys + (uint64_t)d * S.kst + st;
+  const uint64_t beg64 = ch * (uint64_t)c.sh.chunk_elems;
+  const uint32_t beg = (uint32_t)(beg64 < sz ? beg64 : sz);
+  const uint32_t end = (uint32_t)(beg64 + c.sh.chunk_elems < sz ? beg64 + c.sh.chunk_elems : sz);
+  for (uint32_t g = beg; g < end; g += kGroup) {
     uint32_t v[kRows];
 #pragma unroll
     for (int i = 0; i < kRows; ++i) {
-      const uint64_t p = g + (uint64_t)i * kBlock + threadIdx.x;
+      const uint32_t p = g + (uint32_t)i * kBlock + threadIdx.x;
       v[i] = p < end ? (uint32_t)q[p] : 0xffffffffu;
     }
 #pragma unroll
@@ -134,38 +135,57 @@ __global__ void __launch_bounds__(kBlock) k_hist_mid(uint32_t depth, uint32_t pa
 }
 
 // Per node: find the bin that holds the median's rank, then clear the bins.
+// One wavefront per node (4 bins per lane); the grid is capped and strides
+// over the level's nodes, so passes that a code does not need cost little.
 __global__ void __launch_bounds__(kBlock) k_select_mid(uint32_t depth, uint32_t pass,
                                                        uint32_t nsets, const uint64_t* pre,
                                                        const SetDesc* sets,
                                                        const DevParams* params, NodeSel* sel0,
                                                        uint32_t* hist0) {
-  const uint32_t s = find_set(pre, nsets, blockIdx.x);
-  const SetDesc& S = sets[s];
-  const DevParams* P = params + s;
-  if (P->status != BBX_OK) return;
-  const DigitPlan pl = digit_plan(P->G[depth % S.dims]);
-  if (pass + 1 >= pl.npass) return;
-  const uint64_t j = blockIdx.x - pre[s];
-  uint64_t st, sz;
-  node_span(S.n, depth, j, &st, &sz);
-  if (sz <= S.r) return;
-  NodeSel* sel = sel0 + S.sel_off;
-  uint32_t* hist = hist0 + S.hist_off + (j << 8);
-  const uint32_t w = dp_width(pl, pass);
-  const uint32_t nb = 1u << w;
-  const uint32_t rank = pass == 0 ? (uint32_t)(sz >> 1) : sel[j].rank;
-  const uint32_t prefix = pass == 0 ? 0u : sel[j].prefix;
-  const uint32_t c = threadIdx.x < nb ? hist[threadIdx.x] : 0u;
-  if (c) hist[threadIdx.x] = 0;
-  uint64_t tot;
-  const uint64_t cum = block_exscan_u64(c, &tot);
-  if (threadIdx.x < nb && cum <= rank && rank < cum + c) {
-    NodeSel ns;
-    ns.prefix = (prefix << w) | threadIdx.x;
-    ns.rank = rank - (uint32_t)cum;
-    ns.v = 0;
-    ns.jeq = 0;
-    sel[j] = ns;
+  const uint32_t lane = threadIdx.x & 63;
+  const uint64_t total = pre[nsets];
+  constexpr uint32_t wpb = kBlock / 64;
+  for (uint64_t gn = (uint64_t)blockIdx.x * wpb + (threadIdx.x >> 6); gn < total;
+       gn += (uint64_t)gridDim.x * wpb) {
+    const uint32_t s = find_set(pre, nsets, gn);
+    const SetDesc& S = sets[s];
+    const DevParams* P = params + s;
+    if (P->status != BBX_OK) continue;
+    const DigitPlan pl = digit_plan(P->G[depth % S.dims]);
+    if (pass + 1 >= pl.npass) continue;
+    const uint64_t j = gn - pre[s];
+    uint64_t st, sz;
+    node_span(S.n, depth, j, &st, &sz);
+    if (sz <= S.r) continue;
+    NodeSel* sel = sel0 + S.sel_off;
+    uint32_t* hist = hist0 + S.hist_off + (j << 8);
+    const uint32_t w = dp_width(pl, pass);
+    const uint32_t nb = 1u << w;
+    const uint32_t rank = pass == 0 ? (uint32_t)(sz >> 1) : sel[j].rank;
+    const uint32_t prefix = pass == 0 ? 0u : sel[j].prefix;
+    uint32_t c[4], mine = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t b = lane * 4 + k;
+      c[k] = b < nb ? hist[b] : 0u;
+      mine += c[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (c[k]) hist[lane * 4 + k] = 0;
+    uint32_t cum = wave_incl(mine) - mine;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (cum <= rank && rank < cum + c[k]) {
+        NodeSel ns;
+        ns.prefix = (prefix << w) | (lane * 4 + k);
+        ns.rank = rank - cum;
+        ns.v = 0;
+        ns.jeq = 0;
+        sel[j] = ns;
+      }
+      cum += c[k];
+    }
   }
 }
 
@@ -221,15 +241,16 @@ __device__ void hist_last_body(uint32_t depth, const SetDesc& S, const DevParams
   const uint32_t nb = 1u << w, mask = nb - 1;
   lh[threadIdx.x] = 0;
   __syncthreads();
-  const KT* q = (const KT*)keys + (uint64_t)d * n + st;
-  const uint64_t beg = ch * (uint64_t)c.sh.chunk_elems;
-  const uint64_t end = beg + c.sh.chunk_elems < sz ? beg + c.sh.chunk_elems : sz;
+  const KT* q = (const KT*)keys + (uint64_t)d * S.kst + st;
+  const uint64_t beg64 = ch * (uint64_t)c.sh.chunk_elems;
+  const uint32_t beg = (uint32_t)(beg64 < sz ? beg64 : sz);
+  const uint32_t end = (uint32_t)(beg64 + c.sh.chunk_elems < sz ? beg64 + c.sh.chunk_elems : sz);
   uint32_t below = 0;
-  for (uint64_t g = beg; g < end; g += kGroup) {
+  for (uint32_t g = beg; g < end; g += kGroup) {
     uint32_t v[kRows];
 #pragma unroll
     for (int i = 0; i < kRows; ++i) {
-      const uint64_t p = g + (uint64_t)i * kBlock + threadIdx.x;
+      const uint32_t p = g + (uint32_t)i * kBlock + threadIdx.x;
       v[i] = p < end ? (uint32_t)q[p] : 0xffffffffu;
     }
 #pragma unroll
@@ -274,73 +295,94 @@ __global__ void __launch_bounds__(kBlock) k_hist_last(uint32_t depth, uint32_t n
                              rows0 + S.rows_off, lh);
 }
 
+// Per node: the median code v and how many members equal to v go left, then
+// each chunk's (lt, eq) base by an exclusive scan over the node's chunks.
+// One wavefront per node, capped grid striding over the nodes.
 __global__ void __launch_bounds__(kBlock) k_select_last(uint32_t depth, uint32_t nsets,
                                                         const uint64_t* pre, const SetDesc* sets,
                                                         const DevParams* params, NodeSel* sel0,
                                                         uint32_t* hist0, const uint32_t* rows0,
                                                         uint32_t* cb0) {
-  const uint32_t s = find_set(pre, nsets, blockIdx.x);
-  const SetDesc& S = sets[s];
-  const DevParams* P = params + s;
-  if (P->status != BBX_OK) return;
-  const DigitPlan pl = digit_plan(P->G[depth % S.dims]);
-  const uint32_t pass = pl.npass - 1;
-  const uint64_t j = blockIdx.x - pre[s];
-  uint64_t st, sz;
-  node_span(S.n, depth, j, &st, &sz);
-  if (sz <= S.r) return;
-  const uint64_t chunks = level_shape(S.n, depth).chunks;
-  NodeSel* sel = sel0 + S.sel_off;
-  uint32_t* hist = hist0 + S.hist_off + (j << 8);
-  const uint32_t* rows = rows0 + S.rows_off;
-  uint32_t* chunk_base = cb0 + S.cb_off;
-  const uint32_t w = dp_width(pl, pass);
-  const uint32_t nb = 1u << w;
-  const uint32_t rank = pass == 0 ? (uint32_t)(sz >> 1) : sel[j].rank;
-  const uint32_t prefix = pass == 0 ? 0u : sel[j].prefix;
-  __shared__ uint32_t s_b, s_jeq;
-  if (threadIdx.x == 0) s_b = 0, s_jeq = 0;  // ordered before the finder by the scan's barriers
-  const uint32_t c = threadIdx.x < nb ? hist[threadIdx.x] : 0u;
-  if (c) hist[threadIdx.x] = 0;
-  uint64_t tot;
-  const uint64_t cum = block_exscan_u64(c, &tot);
-  if (threadIdx.x < nb && cum <= rank && rank < cum + c) {
-    s_b = threadIdx.x;
-    s_jeq = rank - (uint32_t)cum;
-  }
-  __syncthreads();
-  const uint32_t b = s_b, jeq = s_jeq;
-  if (threadIdx.x == 0) {
-    NodeSel ns;
-    ns.prefix = prefix;
-    ns.rank = rank;
-    ns.v = (prefix << w) | b;
-    ns.jeq = jeq;
-    sel[j] = ns;
-  }
-  // per-chunk counts of members below v (lt) and equal to v (eq), then an
-  // exclusive scan over the node's chunks (both packed in one u64)
-  const uint64_t per = (chunks + kBlock - 1) / kBlock;
-  const uint64_t c0 = threadIdx.x * per;
-  uint64_t mine = 0;
-  for (uint64_t k = 0; k < per; ++k) {
-    const uint64_t ch = c0 + k;
-    if (ch >= chunks) break;
-    const uint32_t* row = rows + (j * chunks + ch) * kRowStride;
-    const uint64_t lt = (uint64_t)row[257] + row[b];
-    const uint64_t eq = (uint64_t)row[b + 1] - row[b];
-    mine += (eq << 32) | lt;
-  }
-  uint64_t run = block_exscan_u64(mine, &tot);
-  for (uint64_t k = 0; k < per; ++k) {
-    const uint64_t ch = c0 + k;
-    if (ch >= chunks) break;
-    const uint32_t* row = rows + (j * chunks + ch) * kRowStride;
-    const uint64_t lt = (uint64_t)row[257] + row[b];
-    const uint64_t eq = (uint64_t)row[b + 1] - row[b];
-    chunk_base[(j * chunks + ch) * 2 + 0] = (uint32_t)run;
-    chunk_base[(j * chunks + ch) * 2 + 1] = (uint32_t)(run >> 32);
-    run += (eq << 32) | lt;
+  const uint32_t lane = threadIdx.x & 63;
+  const uint64_t total = pre[nsets];
+  constexpr uint32_t wpb = kBlock / 64;
+  for (uint64_t gn = (uint64_t)blockIdx.x * wpb + (threadIdx.x >> 6); gn < total;
+       gn += (uint64_t)gridDim.x * wpb) {
+    const uint32_t s = find_set(pre, nsets, gn);
+    const SetDesc& S = sets[s];
+    const DevParams* P = params + s;
+    if (P->status != BBX_OK) continue;
+    const DigitPlan pl = digit_plan(P->G[depth % S.dims]);
+    const uint32_t pass = pl.npass - 1;
+    const uint64_t j = gn - pre[s];
+    uint64_t st, sz;
+    node_span(S.n, depth, j, &st, &sz);
+    if (sz <= S.r) continue;
+    const uint64_t chunks = level_shape(S.n, depth).chunks;
+    NodeSel* sel = sel0 + S.sel_off;
+    uint32_t* hist = hist0 + S.hist_off + (j << 8);
+    const uint32_t* rows = rows0 + S.rows_off + j * chunks * kRowStride;
+    uint32_t* chunk_base = cb0 + S.cb_off + j * chunks * 2;
+    const uint32_t w = dp_width(pl, pass);
+    const uint32_t nb = 1u << w;
+    const uint32_t rank = pass == 0 ? (uint32_t)(sz >> 1) : sel[j].rank;
+    const uint32_t prefix = pass == 0 ? 0u : sel[j].prefix;
+    uint32_t c[4], mine = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t b = lane * 4 + k;
+      c[k] = b < nb ? hist[b] : 0u;
+      mine += c[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (c[k]) hist[lane * 4 + k] = 0;
+    uint32_t cum = wave_incl(mine) - mine;
+    uint32_t fb = 0, fj = 0;
+    bool found = false;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (cum <= rank && rank < cum + c[k]) found = true, fb = lane * 4 + k, fj = rank - cum;
+      cum += c[k];
+    }
+    const uint64_t fm = __ballot(found);
+    if (fm == 0) {  // histogram total below the rank: inconsistent counts, never expected
+      if (lane == 0) ((DevParams*)P)->status = BBX_EHIP;
+      continue;
+    }
+    const int fl = __ffsll((unsigned long long)fm) - 1;  // exactly one lane finds the rank
+    const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)fb, fl);
+    const uint32_t jeq = (uint32_t)__builtin_amdgcn_readlane((int)fj, fl);
+    if (lane == 0) {
+      NodeSel ns;
+      ns.prefix = prefix;
+      ns.rank = rank;
+      ns.v = (prefix << w) | b;
+      ns.jeq = jeq;
+      sel[j] = ns;
+    }
+    // per-chunk counts of members below v (lt) and equal to v (eq), then an
+    // exclusive scan over the node's chunks, lanes owning consecutive chunks
+    const uint64_t per = (chunks + 63) / 64;
+    const uint64_t c0 = lane * per;
+    uint32_t mlt = 0, meq = 0;
+    for (uint64_t k = 0; k < per; ++k) {
+      const uint64_t ch = c0 + k;
+      if (ch >= chunks) break;
+      const uint32_t* row = rows + ch * kRowStride;
+      mlt += row[257] + row[b];
+      meq += row[b + 1] - row[b];
+    }
+    uint32_t rl = wave_incl(mlt) - mlt, re = wave_incl(meq) - meq;
+    for (uint64_t k = 0; k < per; ++k) {
+      const uint64_t ch = c0 + k;
+      if (ch >= chunks) break;
+      const uint32_t* row = rows + ch * kRowStride;
+      chunk_base[ch * 2 + 0] = rl;
+      chunk_base[ch * 2 + 1] = re;
+      rl += row[257] + row[b];
+      re += row[b + 1] - row[b];
+    }
   }
 }
 
@@ -349,26 +391,37 @@ __device__ void scatter_body(uint32_t depth, const SetDesc& S, DevParams* P, con
                              const NodeSel* sel, const uint32_t* chunk_base, const uint8_t* src,
                              uint8_t* dst, const uint32_t* isrc, uint32_t* idst, uint32_t* hist,
                              uint32_t* lhist) {
-  const uint64_t n = S.n;
+  static_assert(kBlock == 256, "four wavefronts per block");
+  const uint64_t n = S.n, kst = S.kst;
   const uint32_t dims = S.dims, r = S.r;
   const uint32_t d = depth % dims;
   const uint64_t j = c.lb / c.sh.chunks, ch = c.lb % c.sh.chunks;
-  uint64_t st, sz;
-  node_span(n, depth, j, &st, &sz);
-  const uint64_t beg = ch * (uint64_t)c.sh.chunk_elems;
-  if (beg >= sz) return;
-  const uint64_t end = beg + c.sh.chunk_elems < sz ? beg + c.sh.chunk_elems : sz;
-  const KT* s0 = (const KT*)src;
-  KT* d0 = (KT*)dst;
+  uint64_t st, sz64;
+  node_span(n, depth, j, &st, &sz64);
+  const uint64_t beg64 = ch * (uint64_t)c.sh.chunk_elems;
+  if (beg64 >= sz64) return;
+  // positions inside the node fit 32 bits (n < 2^32)
+  const uint32_t sz = (uint32_t)sz64, beg = (uint32_t)beg64;
+  const uint32_t end = (uint32_t)(beg64 + c.sh.chunk_elems < sz64 ? beg64 + c.sh.chunk_elems : sz64);
+  const KT* s0 = (const KT*)src + st;
+  const KT* s1 = s0 + kst;
+  const KT* s2 = s1 + kst;
+  KT* d0 = (KT*)dst + st;
+  KT* d1 = d0 + kst;
+  KT* d2 = d1 + kst;
+  const uint32_t* is = isrc ? isrc + st : nullptr;
+  uint32_t* id = idst ? idst + st : nullptr;
   if (sz <= r) {  // leaf: copy through
-    for (uint64_t p = beg + threadIdx.x; p < end; p += blockDim.x) {
-      for (uint32_t dd = 0; dd < dims; ++dd) d0[(uint64_t)dd * n + st + p] = s0[(uint64_t)dd * n + st + p];
-      if (isrc) idst[st + p] = isrc[st + p];
+    for (uint32_t p = beg + threadIdx.x; p < end; p += blockDim.x) {
+      d0[p] = s0[p];
+      if (dims > 1) d1[p] = s1[p];
+      if (dims > 2) d2[p] = s2[p];
+      if (is) id[p] = is[p];
     }
     return;
   }
   // next level's first digit, built here when that level runs a mid pass
-  const uint64_t half = sz >> 1;
+  const uint32_t half = sz >> 1;
   const uint32_t dn = (depth + 1) % dims;
   const DigitPlan pn = digit_plan(P->G[dn]);
   const bool fuse = depth + 1 < S.gl && pn.npass >= 2;
@@ -377,68 +430,68 @@ __device__ void scatter_body(uint32_t depth, const SetDesc& S, DevParams* P, con
   if (fuse) lhist[threadIdx.x] = lhist[kBlock + threadIdx.x] = 0;
   const NodeSel ns = sel[j];
   const uint32_t v = ns.v, jeq = ns.jeq;
-  uint64_t lt_run = chunk_base[c.lb * 2 + 0];
-  uint64_t eq_run = chunk_base[c.lb * 2 + 1];
-  __shared__ uint32_t cnt[2][kBlock / 64][kRows][2];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const uint64_t below_me = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  uint32_t lt_run = chunk_base[c.lb * 2 + 0];
+  uint32_t eq_run = chunk_base[c.lb * 2 + 1];
+  // per group, row and wavefront: (lt, eq) counts; double-buffered so that one
+  // barrier per group suffices
+  __shared__ __align__(16) uint32_t cnt[2][kRows][kBlock / 64][2];
+  const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   int buf = 0;
-  for (uint64_t g = beg; g < end; g += kGroup, buf ^= 1) {
+  for (uint32_t g = beg; g < end; g += kGroup, buf ^= 1) {
     uint32_t key[kRows][3];
-    uint64_t mlt[kRows], meq[kRows];
 #pragma unroll
     for (int i = 0; i < kRows; ++i) {
-      const uint64_t p = g + (uint64_t)i * kBlock + threadIdx.x;
+      const uint32_t p = g + (uint32_t)i * kBlock + threadIdx.x;
       const bool active = p < end;
-#pragma unroll
-      for (uint32_t dd = 0; dd < 3; ++dd)
-        key[i][dd] = (active && dd < dims) ? (uint32_t)s0[(uint64_t)dd * n + st + p] : 0u;
+      key[i][0] = active ? (uint32_t)s0[p] : 0u;
+      key[i][1] = (active && dims > 1) ? (uint32_t)s1[p] : 0u;
+      key[i][2] = (active && dims > 2) ? (uint32_t)s2[p] : 0u;
     }
+    uint32_t blt[kRows], beq[kRows];
 #pragma unroll
     for (int i = 0; i < kRows; ++i) {
-      const uint64_t p = g + (uint64_t)i * kBlock + threadIdx.x;
+      const uint32_t p = g + (uint32_t)i * kBlock + threadIdx.x;
       const bool active = p < end;
       const uint32_t kd = pick3(key[i], d);
-      mlt[i] = __ballot(active && kd < v);
-      meq[i] = __ballot(active && kd == v);
+      const uint64_t mlt = __ballot(active && kd < v);
+      const uint64_t meq = __ballot(active && kd == v);
+      blt[i] = lanes_below(mlt);
+      beq[i] = lanes_below(meq);
       if (lane == 0) {
-        cnt[buf][wv][i][0] = popc64(mlt[i]);
-        cnt[buf][wv][i][1] = popc64(meq[i]);
+        cnt[buf][i][wv][0] = (uint32_t)__popcll(mlt);
+        cnt[buf][i][wv][1] = (uint32_t)__popcll(meq);
       }
     }
     __syncthreads();
-    uint64_t off_l = 0, off_e = 0;  // elements of this group before row i
+    uint32_t off_l = 0, off_e = 0;  // elements of this group before row i
 #pragma unroll
     for (int i = 0; i < kRows; ++i) {
-      uint64_t rl = 0, re = 0, bl = 0, be = 0;
-      for (int w = 0; w < kBlock / 64; ++w) {
-        const uint32_t a = cnt[buf][w][i][0], b = cnt[buf][w][i][1];
-        if (w < wv) bl += a, be += b;
-        rl += a;
-        re += b;
-      }
-      const uint64_t p = g + (uint64_t)i * kBlock + threadIdx.x;
+      const uint4 A = *(const uint4*)&cnt[buf][i][0][0];  // waves 0, 1
+      const uint4 B = *(const uint4*)&cnt[buf][i][2][0];  // waves 2, 3
+      const uint32_t bl = (wv > 0 ? A.x : 0u) + (wv > 1 ? A.z : 0u) + (wv > 2 ? B.x : 0u);
+      const uint32_t be = (wv > 0 ? A.y : 0u) + (wv > 1 ? A.w : 0u) + (wv > 2 ? B.y : 0u);
+      const uint32_t p = g + (uint32_t)i * kBlock + threadIdx.x;
       if (p < end) {
         const uint32_t kd = pick3(key[i], d);
         const bool lt = kd < v, eq = kd == v;
-        const uint64_t L = lt_run + off_l + bl + popc64(mlt[i] & below_me);
-        const uint64_t E = eq_run + off_e + be + popc64(meq[i] & below_me);
-        const uint64_t lb = L + (E < jeq ? E : (uint64_t)jeq);
+        const uint32_t L = lt_run + off_l + bl + blt[i];
+        const uint32_t E = eq_run + off_e + be + beq[i];
+        const uint32_t lb = L + (E < jeq ? E : jeq);
         const bool left = lt || (eq && E < jeq);
-        const uint64_t dest = left ? lb : half + (p - lb);
+        const uint32_t dest = left ? lb : half + (p - lb);
         if (dest < sz) {
-#pragma unroll
-          for (uint32_t dd = 0; dd < 3; ++dd)
-            if (dd < dims) d0[(uint64_t)dd * n + st + dest] = (KT)key[i][dd];
-          if (isrc) idst[st + dest] = isrc[st + p];
+          d0[dest] = (KT)key[i][0];
+          if (dims > 1) d1[dest] = (KT)key[i][1];
+          if (dims > 2) d2[dest] = (KT)key[i][2];
+          if (is) id[dest] = is[p];
           if (left ? cl : cr)
             atomicAdd(&lhist[(left ? 0u : (uint32_t)kBlock) + ((pick3(key[i], dn) >> shn) & maskn)], 1u);
         } else {
           P->status = BBX_EHIP;  // inconsistent counts: never expected
         }
       }
-      off_l += rl;
-      off_e += re;
+      off_l += A.x + A.z + B.x + B.z;
+      off_e += A.y + A.w + B.y + B.w;
     }
     lt_run += off_l;
     eq_run += off_e;
@@ -473,6 +526,12 @@ __global__ void __launch_bounds__(kBlock) k_scatter(uint32_t depth, uint32_t nse
                            dst0 + S.key_off, isrc, idst, hist0 + S.hist_off, lhist);
 }
 
+// blocks of a select launch: one wavefront per node up to 8192 blocks, then striding
+static uint64_t sel_grid(uint64_t nodes) {
+  const uint64_t b = (nodes + kBlock / 64 - 1) / (kBlock / 64);
+  return b < 8192 ? (b ? b : 1) : 8192;
+}
+
 hipError_t launch_levels(const BatchPlan& bp, const Ws& w, hipStream_t s) {
   if (bp.max_gl == 0) return hipGetLastError();
   BBX_LAUNCH("level_hist_zero", k_hist_zero, 1024, kBlock, 0, s, bp.hist_entries, w.hist);
@@ -488,13 +547,13 @@ hipError_t launch_levels(const BatchPlan& bp, const Ws& w, hipStream_t s) {
       if (pass > 0)
         BBX_LAUNCH("level_hist_mid", k_hist_mid, bp.g_lv[k], kBlock, 0, s, k, pass, bp.nsets, plv,
                    w.sets, w.params, w.keys[cur], w.sel, w.hist);
-      BBX_LAUNCH("level_select_mid", k_select_mid, bp.g_nd[k], kBlock, 0, s, k, pass, bp.nsets, pnd,
-                 w.sets, w.params, w.sel, w.hist);
+      BBX_LAUNCH("level_select_mid", k_select_mid, sel_grid(bp.g_nd[k]), kBlock, 0, s, k, pass,
+                 bp.nsets, pnd, w.sets, w.params, w.sel, w.hist);
     }
     BBX_LAUNCH("level_hist_last", k_hist_last, bp.g_lv[k], kBlock, 0, s, k, bp.nsets, plv, w.sets,
                w.params, w.keys[cur], w.sel, w.hist, w.rows);
-    BBX_LAUNCH("level_select_last", k_select_last, bp.g_nd[k], kBlock, 0, s, k, bp.nsets, pnd,
-               w.sets, w.params, w.sel, w.hist, w.rows, w.chunk_base);
+    BBX_LAUNCH("level_select_last", k_select_last, sel_grid(bp.g_nd[k]), kBlock, 0, s, k,
+               bp.nsets, pnd, w.sets, w.params, w.sel, w.hist, w.rows, w.chunk_base);
     BBX_LAUNCH("level_scatter", k_scatter, bp.g_lv[k], kBlock, 0, s, k, bp.nsets, plv, w.sets,
                w.params, w.sel, w.chunk_base, w.keys[cur], w.keys[cur ^ 1], w.idx[cur],
                w.idx[cur ^ 1], w.hist);

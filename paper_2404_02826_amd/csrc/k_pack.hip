@@ -196,14 +196,14 @@ __global__ void __launch_bounds__(kBlock) k_pack_meta(uint32_t nsets, const uint
 }
 
 template <typename KT>
-__device__ inline u128 member_code(const KT* keys, uint64_t n, uint32_t dims, const LeafRec& rec,
+__device__ inline u128 member_code(const KT* keys, uint64_t stride, uint32_t dims, const LeafRec& rec,
                                    uint64_t slot) {
   u128 v = 0;
   uint32_t at = 0;
   for (uint32_t d = 0; d < dims; ++d) {
     const uint32_t m = (rec.m >> (8 * d)) & 0xffu;
     if (m == 0) continue;
-    const uint32_t q = keys[(uint64_t)d * n + slot];
+    const uint32_t q = keys[(uint64_t)d * stride + slot];
     const uint64_t u = (uint64_t)((int64_t)q - (int64_t)rec.qref[d] + ((int64_t)1 << (m - 1)));
     v |= (u128)u << at;
     at += m;
@@ -226,72 +226,176 @@ __device__ inline uint64_t search_off(const uint64_t* off, uint64_t base, uint64
   return lo;
 }
 
+constexpr uint32_t kLeafStage = 256;   // leaves per block (leaves_per_block)
+constexpr uint32_t kSlotStage = 2048;  // staged slots per block
+
+// code of the member at `slot` from a staged copy of slots [slot0, slot0 + ns)
 template <typename KT>
-__device__ void pack_payload_body(const SetDesc& S, const DevParams* P, uint64_t lb, uint64_t nblk,
+__device__ inline u128 member_code_lds(const KT* sk, uint32_t ns, uint32_t dims, const LeafRec& rec,
+                                       uint64_t slot, uint64_t slot0) {
+  u128 v = 0;
+  uint32_t at = 0;
+  const uint32_t t = (uint32_t)(slot - slot0);
+  for (uint32_t d = 0; d < dims; ++d) {
+    const uint32_t m = (rec.m >> (8 * d)) & 0xffu;
+    if (m == 0) continue;
+    const uint32_t q = sk[d * ns + t];
+    const uint64_t u = (uint64_t)((int64_t)q - (int64_t)rec.qref[d] + ((int64_t)1 << (m - 1)));
+    v |= (u128)u << at;
+    at += m;
+  }
+  return v;
+}
+
+// 64-bit forms for members whose code has at most 64 bits (the usual case)
+template <typename KT>
+__device__ inline uint64_t member_code64(const KT* base, uint64_t stride, uint32_t dims,
+                                         const LeafRec& rec, uint64_t t) {
+  uint64_t v = 0;
+  uint32_t at = 0;
+#pragma unroll
+  for (uint32_t d = 0; d < 3; ++d) {
+    if (d >= dims) break;
+    const uint32_t m = (rec.m >> (8 * d)) & 0xffu;
+    if (m == 0) continue;
+    const uint32_t q = base[d * stride + t];
+    const uint64_t u = (uint64_t)((int64_t)q - (int64_t)rec.qref[d] + ((int64_t)1 << (m - 1)));
+    v |= u << at;
+    at += m;
+  }
+  return v;
+}
+// OR a code of len <= 64 bits starting at absolute bit `at` into the word at w0
+__device__ inline void or_into64(uint64_t& word, uint64_t w0, uint64_t val, uint64_t at) {
+  if (at >= w0)
+    word |= val << (uint32_t)(at - w0);  // at - w0 < 64 (callers keep at < w0 + 64)
+  else
+    word |= val >> (uint32_t)(w0 - at);  // w0 - at < len <= 64
+}
+
+constexpr uint32_t kPackLdsWords = 3072;  // payload words of one block's members (24 KB)
+
+// Leaf-aligned packing: a block takes leaves_per_block(r) consecutive leaves
+// and stages their records and bit offsets.  Every member (thread per slot,
+// coalesced code loads) ORs its code into an LDS copy of the payload words its
+// leaves' bits touch (LDS atomics), and the block stores the words whose first
+// bit lies in its leaves' bit range with coalesced plain stores.  The last such
+// word can also hold the first bits of the next block's leaves: one thread
+// adds those few members from global memory.  Blocks whose bits exceed the LDS
+// copy (very large leaves) assemble each word from global memory instead.
+template <typename KT>
+__device__ void pack_payload_body(const SetDesc& S, const DevParams* P, uint64_t blk,
                                   const LeafRec* leaves, const uint64_t* off, const KT* keys,
-                                  uint64_t* s_off) {
-  __shared__ uint64_t s_lo, s_cnt;
-  const uint64_t n = S.n, nl = S.n_leaves, base = P->payload_base;
+                                  LeafRec* s_rec, uint64_t* s_off, unsigned long long* s_w) {
+  const uint64_t kst = S.kst, nl = S.n_leaves, base = P->payload_base, pbits = P->payload_bits;
   const uint32_t dims = S.dims;
-  const uint64_t nwords = (P->payload_bits + 63) / 64;
+  const uint32_t lpb = leaves_per_block(S.r);
+  const uint64_t L0 = blk * lpb;
+  if (L0 >= nl) return;
+  const uint32_t nlb = (uint32_t)(nl - L0 < lpb ? nl - L0 : lpb);
+  for (uint32_t t = threadIdx.x; t < nlb; t += kBlock) {
+    s_rec[t] = leaves[L0 + t];
+    s_off[t] = off[L0 + t] - base;
+  }
+  const uint64_t bo1 = L0 + nlb < nl ? off[L0 + nlb] - base : pbits;
+  __syncthreads();
+  const uint64_t bo0 = s_off[0];
+  if (bo1 <= bo0) return;  // no payload bits in these leaves (uniform)
   uint64_t* pay = (uint64_t*)(S.out + kHeaderBytes + ((P->meta_bits + 63) / 64) * 8);
-  const uint64_t ngroups = (nwords + kBlock - 1) / kBlock;
-  for (uint64_t grp = lb; grp < ngroups; grp += nblk) {
-    const uint64_t W0 = grp * kBlock;
-    const uint64_t Wend = W0 + kBlock < nwords ? W0 + kBlock : nwords;
-    if (threadIdx.x == 0) {
-      const uint64_t lo = search_off(off, base, 0, nl - 1, W0 * 64);
-      const uint64_t hi = search_off(off, base, lo, nl - 1, Wend * 64 - 1);
-      s_lo = lo;
-      s_cnt = hi - lo + 1;
-    }
-    __syncthreads();
-    const uint64_t lo = s_lo, cnt = s_cnt;
-    const bool in_lds = cnt <= 2048;
-    if (in_lds)
-      for (uint64_t t = threadIdx.x; t < cnt; t += kBlock) s_off[t] = off[lo + t] - base;
-    __syncthreads();
-    const uint64_t w = W0 + threadIdx.x;
-    if (w < Wend) {
+  const uint64_t w_first = (bo0 + 63) / 64, w_end = (bo1 + 63) / 64;  // owned words
+  const uint64_t wlo = bo0 / 64;
+  const uint64_t nwb = w_end - wlo;
+  const uint64_t Lend = L0 + nlb;
+  if (nwb > kPackLdsWords) {  // large leaves: each owned word from global memory
+    for (uint64_t w = w_first + threadIdx.x; w < w_end; w += kBlock) {
       const uint64_t b0 = w * 64;
-      uint64_t i;
-      if (in_lds) {
-        uint64_t a = 0, z = cnt - 1;
-        while (a < z) {
-          const uint64_t mid = a + (z - a + 1) / 2;
-          if (s_off[mid] <= b0)
-            a = mid;
-          else
-            z = mid - 1;
-        }
-        i = lo + a;
-      } else {
-        i = search_off(off, base, lo, lo + cnt - 1, b0);
+      uint32_t a = 0, z = nlb - 1;
+      while (a < z) {
+        const uint32_t mid = (a + z + 1) >> 1;
+        if (s_off[mid] <= b0)
+          a = mid;
+        else
+          z = mid - 1;
       }
-      LeafRec rec = leaves[i];
+      uint64_t i = L0 + a;
+      LeafRec rec = s_rec[a];
       uint32_t sm = sum_m(rec.m);
-      const uint64_t oi = off[i] - base;
+      const uint64_t oi = s_off[a];
       uint64_t jm = sm ? (b0 - oi) / sm : 0;
       uint64_t at = oi + jm * sm;
       uint64_t word = 0;
       while (at < b0 + 64) {
         if (sm > 0 && jm + 1 < rec.size) {
-          const u128 c = member_code(keys, n, dims, rec, (uint64_t)rec.start + 1 + jm);
+          const u128 c = member_code(keys, kst, dims, rec, (uint64_t)rec.start + 1 + jm);
           or_into(word, b0, c, at, sm);
           at += sm;
           ++jm;
         } else {
           ++i;
           if (i >= nl) break;
-          rec = leaves[i];
+          rec = i < Lend ? s_rec[i - L0] : leaves[i];
           sm = sum_m(rec.m);
           jm = 0;
         }
       }
       pay[w] = word;
     }
-    __syncthreads();
+    return;
   }
+  for (uint32_t t = threadIdx.x; t < (uint32_t)nwb; t += kBlock) s_w[t] = 0;
+  __syncthreads();
+  const uint64_t slot0 = s_rec[0].start;
+  const uint64_t slot_end = (uint64_t)s_rec[nlb - 1].start + s_rec[nlb - 1].size;
+  for (uint64_t slot = slot0 + threadIdx.x; slot < slot_end; slot += kBlock) {
+    uint32_t a = 0, z = nlb - 1;  // last staged leaf starting at or before the slot
+    while (a < z) {
+      const uint32_t mid = (a + z + 1) >> 1;
+      if (s_rec[mid].start <= slot)
+        a = mid;
+      else
+        z = mid - 1;
+    }
+    const LeafRec rec = s_rec[a];
+    const uint64_t j = slot - rec.start;
+    const uint32_t sm = sum_m(rec.m);
+    if (j == 0 || sm == 0) continue;  // the reference, or a leaf without payload
+    const uint64_t at = s_off[a] + (j - 1) * sm - wlo * 64;  // bit in the LDS copy
+    const uint32_t w = (uint32_t)(at >> 6), sh = (uint32_t)(at & 63);
+    if (sm <= 64) {
+      const uint64_t c = member_code64(keys, kst, dims, rec, slot);
+      atomicOr(&s_w[w], (unsigned long long)(c << sh));
+      if (sh + sm > 64) atomicOr(&s_w[w + 1], (unsigned long long)(c >> (64 - sh)));
+    } else {
+      const u128 c = member_code(keys, kst, dims, rec, slot) << sh;
+      atomicOr(&s_w[w], (unsigned long long)(uint64_t)c);
+      atomicOr(&s_w[w + 1], (unsigned long long)(uint64_t)(c >> 64));
+      if (sh + sm > 128) {
+        const u128 c3 = member_code(keys, kst, dims, rec, slot) >> (128 - sh);
+        atomicOr(&s_w[w + 2], (unsigned long long)(uint64_t)c3);
+      }
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && (bo1 & 63) != 0 && bo1 < pbits) {
+    // bits [bo1, w_end * 64) of the last owned word come from the next leaves
+    const uint64_t b0 = (w_end - 1) * 64;
+    uint64_t word = s_w[w_end - 1 - wlo];
+    uint64_t i = Lend;
+    uint64_t at = bo1;
+    while (i < nl && at < w_end * 64) {
+      const LeafRec rec = leaves[i];
+      const uint32_t sm = sum_m(rec.m);
+      for (uint64_t jm = 0; sm > 0 && jm + 1 < rec.size && at < w_end * 64; ++jm) {
+        const u128 c = member_code(keys, kst, dims, rec, (uint64_t)rec.start + 1 + jm);
+        or_into(word, b0, c, at, sm);
+        at += sm;
+      }
+      ++i;
+    }
+    s_w[w_end - 1 - wlo] = word;
+  }
+  __syncthreads();
+  for (uint64_t w = w_first + threadIdx.x; w < w_end; w += kBlock) pay[w] = s_w[w - wlo];
 }
 
 __global__ void __launch_bounds__(kBlock) k_pack_payload(uint32_t nsets, const uint64_t* pre,
@@ -306,15 +410,17 @@ __global__ void __launch_bounds__(kBlock) k_pack_payload(uint32_t nsets, const u
   const DevParams* P = params + s;
   if (P->status != BBX_OK) return;
   if (P->payload_bits == 0) return;
-  __shared__ uint64_t s_off[2048];
-  const uint64_t lb = blockIdx.x - pre[s], nblk = pre[s + 1] - pre[s];
+  __shared__ LeafRec s_rec[kLeafStage];
+  __shared__ uint64_t s_off[kLeafStage];
+  __shared__ unsigned long long s_w[kPackLdsWords];
+  const uint64_t blk = blockIdx.x - pre[s];
   const uint8_t* keys = (S.final_buf ? keys1 : keys0) + S.key_off;
   const LeafRec* leaves = leaves0 + S.leaf_off;
   const uint64_t* off = off0 + S.leaf_off;
   if (P->key16)
-    pack_payload_body<uint16_t>(S, P, lb, nblk, leaves, off, (const uint16_t*)keys, s_off);
+    pack_payload_body<uint16_t>(S, P, blk, leaves, off, (const uint16_t*)keys, s_rec, s_off, s_w);
   else
-    pack_payload_body<uint32_t>(S, P, lb, nblk, leaves, off, (const uint32_t*)keys, s_off);
+    pack_payload_body<uint32_t>(S, P, blk, leaves, off, (const uint32_t*)keys, s_rec, s_off, s_w);
 }
 
 __global__ void k_header(const SetDesc* sets, const DevParams* params) {

@@ -198,7 +198,7 @@ __global__ void __launch_bounds__(kBlock) k_epilogue(const SetDesc* sets, const 
 }
 
 template <typename T, typename KT>
-__device__ void quantize_body(const T* __restrict__ pos, uint64_t n, uint32_t dims,
+__device__ void quantize_body(const T* __restrict__ pos, uint64_t n, uint64_t kst, uint32_t dims,
                               uint32_t layout, double lo0, double lo1, double lo2, double inv_w,
                               uint64_t lb, uint64_t nblk, KT* __restrict__ keys,
                               uint32_t* __restrict__ idx) {
@@ -209,7 +209,7 @@ __device__ void quantize_body(const T* __restrict__ pos, uint64_t n, uint32_t di
     for (uint32_t d = 0; d < 3; ++d) {
       if (d >= dims) break;
       const double x = load_coord(pos, n, dims, layout, i, d);
-      keys[(uint64_t)d * n + i] = (KT)(uint32_t)floor((x - lo[d]) * inv_w + 0.5);
+      keys[(uint64_t)d * kst + i] = (KT)(uint32_t)floor((x - lo[d]) * inv_w + 0.5);
     }
     if (idx) idx[i] = (uint32_t)i;
   }
@@ -223,9 +223,9 @@ __device__ void quantize_set(const SetDesc& S, const DevParams* P, uint64_t lb, 
   const uint32_t dims = S.dims, layout = S.layout;
   const double l0 = P->lo[0], l1 = P->lo[1], l2 = P->lo[2], iw = P->inv_w;
   if (P->key16)
-    quantize_body<T, uint16_t>(pos, n, dims, layout, l0, l1, l2, iw, lb, nblk, (uint16_t*)keys, idx);
+    quantize_body<T, uint16_t>(pos, n, S.kst, dims, layout, l0, l1, l2, iw, lb, nblk, (uint16_t*)keys, idx);
   else
-    quantize_body<T, uint32_t>(pos, n, dims, layout, l0, l1, l2, iw, lb, nblk, (uint32_t*)keys, idx);
+    quantize_body<T, uint32_t>(pos, n, S.kst, dims, layout, l0, l1, l2, iw, lb, nblk, (uint32_t*)keys, idx);
 }
 
 __global__ void __launch_bounds__(kBlock) k_quantize(uint32_t nsets, const uint64_t* pre,

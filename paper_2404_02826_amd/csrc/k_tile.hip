@@ -64,19 +64,6 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Wavefront-wide inclusive scans with DPP row shifts and row broadcasts (no
-// LDS traffic): rows of 16 lanes first, then row 0's total into row 1, row
-// 2's into row 3, and rows 0-1's total into rows 2-3.  Lanes whose source is
-// outside the row read the identity.
-__device__ inline uint32_t wave_incl(uint32_t x) {
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false);  // row_shr:1
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false);  // row_shr:2
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false);  // row_shr:4
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false);  // row_shr:8
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);  // row_bcast:15
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);  // row_bcast:31
-  return x;
-}
 __device__ inline uint32_t umin32(uint32_t a, uint32_t b) { return a < b ? a : b; }
 __device__ inline uint32_t umax32(uint32_t a, uint32_t b) { return a > b ? a : b; }
 // wavefront minimum / maximum, uniform result
@@ -204,7 +191,8 @@ __device__ void tile_bitboxes(WaveTile<TILE>& sm, int cur, uint32_t nl, uint32_t
 }
 
 template <int TILE, typename KT>
-__device__ void tile_body(WaveTile<TILE>& sm, uint64_t j, uint32_t K0, uint64_t n, uint32_t dims,
+__device__ void tile_body(WaveTile<TILE>& sm, uint64_t j, uint32_t K0, uint64_t n, uint64_t kst,
+                          uint32_t dims,
                           uint32_t r, uint64_t n_leaves, const TreeGeom& g, DevParams* P, KT* keys,
                           const uint32_t* idx, uint32_t* perm, LeafRec* leaves,
                           uint64_t* leaf_bits) {
@@ -233,7 +221,7 @@ __device__ void tile_body(WaveTile<TILE>& sm, uint64_t j, uint32_t K0, uint64_t 
       const uint32_t p = lane + 64u * (k0 + k);
 #pragma unroll
       for (uint32_t d = 0; d < 3; ++d)
-        v[d][k] = (p < s0 && d < dims) ? (uint32_t)keys[(uint64_t)d * n + tst + p] : 0u;
+        v[d][k] = (p < s0 && d < dims) ? (uint32_t)keys[(uint64_t)d * kst + tst + p] : 0u;
       ix[k] = (p < s0 && track) ? idx[tst + p] : 0u;
     }
 #pragma unroll
@@ -482,7 +470,7 @@ __device__ void tile_body(WaveTile<TILE>& sm, uint64_t j, uint32_t K0, uint64_t 
     const uint64_t gpos = tst + ls + o;
 #pragma unroll
     for (uint32_t d = 0; d < 3; ++d)
-      if (d < dims) keys[(uint64_t)d * n + gpos] = (KT)(sm.K[d][slot] + tmin[d]);
+      if (d < dims) keys[(uint64_t)d * kst + gpos] = (KT)(sm.K[d][slot] + tmin[d]);
     if (track) perm[gpos] = sm.I[slot];
   }
 }
@@ -505,10 +493,10 @@ __global__ void __launch_bounds__(64) k_tile(uint32_t nsets, const uint64_t* pre
   LeafRec* leaves = leaves0 + S.leaf_off;
   uint64_t* leaf_bits = leaf_bits0 + S.leaf_off;
   if (P->key16)
-    tile_body<TILE, uint16_t>(sm, j, S.gl, S.n, S.dims, S.r, S.n_leaves, S.geom, P,
+    tile_body<TILE, uint16_t>(sm, j, S.gl, S.n, S.kst, S.dims, S.r, S.n_leaves, S.geom, P,
                               (uint16_t*)keys, idx, S.perm, leaves, leaf_bits);
   else
-    tile_body<TILE, uint32_t>(sm, j, S.gl, S.n, S.dims, S.r, S.n_leaves, S.geom, P,
+    tile_body<TILE, uint32_t>(sm, j, S.gl, S.n, S.kst, S.dims, S.r, S.n_leaves, S.geom, P,
                               (uint32_t*)keys, idx, S.perm, leaves, leaf_bits);
 }
 
@@ -536,7 +524,8 @@ __device__ inline uint32_t bmax_u32(uint32_t v, uint32_t* red) {
 }
 
 template <typename KT>
-__device__ void bigleaf_body(uint64_t i, uint64_t n, uint32_t dims, const TreeGeom& g,
+__device__ void bigleaf_body(uint64_t i, uint64_t n /* code-array stride */, uint32_t dims,
+                             const TreeGeom& g,
                              const KT* src, KT* dst, const uint32_t* idx, uint32_t* perm,
                              LeafRec* leaves, uint64_t* leaf_bits) {
   __shared__ uint32_t red[kBlock / 64];
@@ -613,10 +602,10 @@ __global__ void __launch_bounds__(kBlock) k_bigleaf(uint32_t nsets, const uint64
   const uint32_t* idx = S.perm ? (buf ? idx1 : idx0) + S.idx_off : nullptr;
   const uint64_t i = blockIdx.x - pre[s];
   if (P->key16)
-    bigleaf_body<uint16_t>(i, S.n, S.dims, S.geom, (const uint16_t*)src, (uint16_t*)dst, idx,
+    bigleaf_body<uint16_t>(i, S.kst, S.dims, S.geom, (const uint16_t*)src, (uint16_t*)dst, idx,
                            S.perm, leaves0 + S.leaf_off, leaf_bits0 + S.leaf_off);
   else
-    bigleaf_body<uint32_t>(i, S.n, S.dims, S.geom, (const uint32_t*)src, (uint32_t*)dst, idx,
+    bigleaf_body<uint32_t>(i, S.kst, S.dims, S.geom, (const uint32_t*)src, (uint32_t*)dst, idx,
                            S.perm, leaves0 + S.leaf_off, leaf_bits0 + S.leaf_off);
 }
 

@@ -68,67 +68,85 @@ __global__ void __launch_bounds__(kBlock) k_dec_meta(uint64_t n_leaves, uint32_t
   }
 }
 
+constexpr uint32_t kLeafStage = 256;     // leaves per block (leaves_per_block)
+constexpr uint32_t kUnpackWords = 1536;  // staged payload words per block (12 KB)
+
+// Leaf-aligned decoding: a block takes leaves_per_block(r) consecutive
+// leaves, stages their records, bit offsets and payload words with coalesced
+// loads, and decodes their slots (reference -> its code; member j -> payload
+// code j-1) from LDS.
+// up to 64 bits at absolute bit `at` of a word array (the words exist)
+__device__ inline uint64_t read64(const uint64_t* sec, uint64_t at, uint32_t len) {
+  const uint64_t w = at >> 6;
+  const uint32_t s = (uint32_t)(at & 63);
+  uint64_t v = sec[w] >> s;
+  if (s + len > 64) v |= sec[w + 1] << (64 - s);
+  return len < 64 ? v & ((1ull << len) - 1) : v;
+}
+
 template <typename T>
-__device__ void unpack_body(uint64_t n, uint32_t dims, uint32_t layout, TreeGeom g, double w,
-                            const double* origin, const uint32_t* G, uint64_t n_leaves,
+__device__ void unpack_body(uint64_t n, uint32_t dims, uint32_t layout, uint32_t r, double w,
+                            const double* origin, const uint32_t* G, uint64_t nl,
                             const LeafRec* leaves, const uint64_t* off, const uint64_t* pay,
-                            uint64_t pay_words, T* out, DevParams* P, uint32_t* s_start) {
-  __shared__ uint64_t s_i0;
-  __shared__ uint32_t s_cnt;
-  const uint64_t S0 = (uint64_t)blockIdx.x * 1024;
-  if (threadIdx.x == 0) {
-    // descend to the leaf holding slot S0
-    uint64_t s = g.n, st = 0, base = 0;
-    uint32_t k = 0;
-    while (s > g.r) {
-      uint64_t sl = s >> 1;
-      if (S0 < st + sl) {
-        s = sl;
-      } else {
-        base += geom_L(g, k + 1, sl);
-        st += sl;
-        s -= sl;
-      }
-      ++k;
-    }
-    s_i0 = base;
+                            uint64_t pay_words, uint64_t pbits, T* out, DevParams* P,
+                            LeafRec* s_rec, uint64_t* s_off, uint64_t* s_pay) {
+  const uint32_t lpb = leaves_per_block(r);
+  const uint64_t L0 = (uint64_t)blockIdx.x * lpb;
+  if (L0 >= nl) return;
+  const uint32_t nlb = (uint32_t)(nl - L0 < lpb ? nl - L0 : lpb);
+  for (uint32_t t = threadIdx.x; t < nlb; t += kBlock) {
+    s_rec[t] = leaves[L0 + t];
+    s_off[t] = off[L0 + t];
   }
+  const uint64_t bo1 = L0 + nlb < nl ? off[L0 + nlb] : pbits;
   __syncthreads();
-  const uint64_t i0 = s_i0;
-  const uint64_t Send = S0 + 1024 < n ? S0 + 1024 : n;
-  // leaves overlapping [S0, Send): at most 1024
-  for (uint32_t t = threadIdx.x; t < 1024; t += kBlock) {
-    uint64_t i = i0 + t;
-    s_start[t] = i < n_leaves ? leaves[i].start : 0xffffffffu;
-  }
+  const uint64_t bo0 = s_off[0];
+  const uint64_t w0 = bo0 / 64, w1 = bo1 > bo0 ? (bo1 + 63) / 64 : w0;
+  const bool staged = w1 - w0 <= kUnpackWords;
+  const uint32_t nw = staged ? (uint32_t)(w1 - w0) : 0u;
+  for (uint32_t t = threadIdx.x; t < nw; t += kBlock) s_pay[t] = w0 + t < pay_words ? pay[w0 + t] : 0;
   __syncthreads();
+  const uint64_t slot0 = s_rec[0].start;
+  const uint64_t slot1 = (uint64_t)s_rec[nlb - 1].start + s_rec[nlb - 1].size;
   bool corrupt = false;
-  for (uint32_t k = 0; k < 1024 / kBlock; ++k) {
-    const uint64_t p = S0 + k * kBlock + threadIdx.x;
-    if (p >= Send) break;
-    uint32_t a = 0, z = 1023;
+  for (uint64_t p = slot0 + threadIdx.x; p < slot1; p += kBlock) {
+    uint32_t a = 0, z = nlb - 1;  // last staged leaf starting at or before p
     while (a < z) {
-      uint32_t mid = (a + z + 1) >> 1;
-      if (s_start[mid] <= p)
+      const uint32_t mid = (a + z + 1) >> 1;
+      if (s_rec[mid].start <= p)
         a = mid;
       else
         z = mid - 1;
     }
-    const uint64_t i = i0 + a;
-    const LeafRec rec = leaves[i];
+    const LeafRec rec = s_rec[a];
     const uint64_t j = p - rec.start;
     int64_t q[3] = {rec.qref[0], rec.qref[1], rec.qref[2]};
     if (j > 0) {
       uint32_t summ = 0;
       for (uint32_t d = 0; d < dims; ++d) summ += (rec.m >> (8 * d)) & 0xffu;
-      u128 v = read_bits(pay, pay_words, off[i] + (j - 1) * summ, summ);
-      for (uint32_t d = 0; d < dims; ++d) {
-        const uint32_t m = (rec.m >> (8 * d)) & 0xffu;
-        if (m == 0) continue;
-        const uint64_t u = (uint64_t)(v & ((((u128)1) << m) - 1));
-        v >>= m;
-        if (u == 0) corrupt = true;
-        q[d] = (int64_t)rec.qref[d] + (int64_t)u - ((int64_t)1 << (m - 1));
+      const uint64_t at = s_off[a] + (j - 1) * summ;
+      if (summ <= 64) {
+        uint64_t v = staged ? read64(s_pay, at - w0 * 64, summ) : read64(pay, at, summ);
+#pragma unroll
+        for (uint32_t d = 0; d < 3; ++d) {
+          if (d >= dims) break;
+          const uint32_t m = (rec.m >> (8 * d)) & 0xffu;
+          if (m == 0) continue;
+          const uint64_t u = v & ((1ull << m) - 1);
+          v >>= m;
+          if (u == 0) corrupt = true;
+          q[d] = (int64_t)rec.qref[d] + (int64_t)u - ((int64_t)1 << (m - 1));
+        }
+      } else {
+        u128 v = staged ? read_bits(s_pay, nw, at - w0 * 64, summ) : read_bits(pay, pay_words, at, summ);
+        for (uint32_t d = 0; d < dims; ++d) {
+          const uint32_t m = (rec.m >> (8 * d)) & 0xffu;
+          if (m == 0) continue;
+          const uint64_t u = (uint64_t)(v & ((((u128)1) << m) - 1));
+          v >>= m;
+          if (u == 0) corrupt = true;
+          q[d] = (int64_t)rec.qref[d] + (int64_t)u - ((int64_t)1 << (m - 1));
+        }
       }
     }
     for (uint32_t d = 0; d < dims; ++d) {
@@ -149,19 +167,21 @@ __device__ void unpack_body(uint64_t n, uint32_t dims, uint32_t layout, TreeGeom
 
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_unpack(uint64_t n, uint32_t dims, uint32_t layout,
-                                                   TreeGeom g, double w, double o0, double o1,
+                                                   uint32_t r, double w, double o0, double o1,
                                                    double o2, uint32_t G0, uint32_t G1,
                                                    uint32_t G2, uint64_t n_leaves,
                                                    uint64_t meta_bits, const LeafRec* leaves,
                                                    const uint64_t* off, const uint8_t* stream,
                                                    uint64_t pay_bits, T* out, DevParams* P) {
   if (P->status != BBX_OK) return;
-  __shared__ uint32_t s_start[1024];
+  __shared__ LeafRec s_rec[kLeafStage];
+  __shared__ uint64_t s_off[kLeafStage];
+  __shared__ uint64_t s_pay[kUnpackWords];
   const double origin[3] = {o0, o1, o2};
   const uint32_t G[3] = {G0, G1, G2};
   const uint64_t* pay = (const uint64_t*)(stream + kHeaderBytes + ((meta_bits + 63) / 64) * 8);
-  unpack_body<T>(n, dims, layout, g, w, origin, G, n_leaves, leaves, off, pay, (pay_bits + 63) / 64,
-                 out, P, s_start);
+  unpack_body<T>(n, dims, layout, r, w, origin, G, n_leaves, leaves, off, pay, (pay_bits + 63) / 64,
+                 pay_bits, out, P, s_rec, s_off, s_pay);
 }
 
 __global__ void k_dec_init(DevParams* P) {
@@ -185,14 +205,15 @@ hipError_t launch_decompress(const DecompressPlan& p, const DecompressWs& w, con
                p.G[1], p.G[2], p.meta_bits, p.geom, stream, w.leaves, w.leaf_bits, w.params);
     hipError_t e = launch_dec_scan(p.n_leaves, w.leaf_bits, w.scan_part, w.params, p.payload_bits, s);
     if (e != hipSuccess) return e;
-    const uint64_t blocks = (p.n + 1023) / 1024;
+    const uint64_t lpb = leaves_per_block(p.r);
+    const uint64_t blocks = (p.n_leaves + lpb - 1) / lpb;
     if (p.dtype == BBX_F32)
-      BBX_LAUNCH("unpack", k_unpack<float>, blocks, kBlock, 0, s, p.n, p.dims, p.layout, p.geom,
+      BBX_LAUNCH("unpack", k_unpack<float>, blocks, kBlock, 0, s, p.n, p.dims, p.layout, p.r,
                  p.w, p.origin[0], p.origin[1], p.origin[2], p.G[0], p.G[1], p.G[2], p.n_leaves,
                  p.meta_bits, w.leaves, w.leaf_bits, stream, p.payload_bits, (float*)pos,
                  w.params);
     else
-      BBX_LAUNCH("unpack", k_unpack<double>, blocks, kBlock, 0, s, p.n, p.dims, p.layout, p.geom,
+      BBX_LAUNCH("unpack", k_unpack<double>, blocks, kBlock, 0, s, p.n, p.dims, p.layout, p.r,
                  p.w, p.origin[0], p.origin[1], p.origin[2], p.G[0], p.G[1], p.G[2], p.n_leaves,
                  p.meta_bits, w.leaves, w.leaf_bits, stream, p.payload_bits, (double*)pos,
                  w.params);
