@@ -63,6 +63,56 @@ def kernel_bytes_per_particle(name, key_bytes, in_bytes, stream_bytes_pp):
     }.get(name)
 
 
+def bench_copy(args):
+    """A plain device-to-device copy of 1 GiB: the achievable-bandwidth
+    reference and the known-size kernel the HBM byte counters are scaled by."""
+    import torch
+    nbytes = 1 << 30
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    for _ in range(args.warmup):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    gbps = 2 * nbytes * args.steps / el / 1e9
+    print(json.dumps({"metric": "device copy GB/s (read + write)", "value": round(gbps, 1),
+                      "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                      "ms_per_step": round(el * 1e3 / args.steps, 4), "higher_is_better": True,
+                      "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+                      "config": {"workload": "copy-1GiB", "bytes": nbytes},
+                      "roofline": {"bound": "hbm", "achieved": round(gbps, 1), "peak": HBM_PEAK_GBS,
+                                   "unit": "GB/s", "frac": round(gbps / HBM_PEAK_GBS, 4),
+                                   "traffic": None},
+                      "cpu_baseline": None}), flush=True)
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` on the fluid 2^27 workload, from the
+    committed counter summary, or None when the kernel's source has changed
+    since the counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", f"{kernel}_fluid27_hbm_bytes.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_b = re.search(r"hbm_bytes_per_launch:\s*(\d+)", text)
+    m_f = re.search(r"source:\s*(\S+)\s+sha256:\s*([0-9a-f]{64})", text)
+    if not (m_b and m_f):
+        return None
+    src = os.path.join(ROOT, m_f.group(1))
+    if not os.path.exists(src):
+        return None
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != m_f.group(2):
+        return None
+    return int(m_b.group(1))
+
+
 def _gen_batch_set(job):
     from synth import batch_set
     s, n, kind, seed0 = job
@@ -367,7 +417,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="fluid-2^27-f32",
-                    choices=sorted(WORKLOADS) + ["batch-4096-f32", "served"])
+                    choices=sorted(WORKLOADS) + ["batch-4096-f32", "served", "copy-1GiB"])
     ap.add_argument("--leaf-size", type=int, default=32,
                     help="leaf size r (batch workload: 0 = autotuned per set)")
     ap.add_argument("--tile", type=int, default=0, help="batch workload: 0 = autotuned")
@@ -386,6 +436,9 @@ def main():
         return
     if args.workload == "served":
         bench_served(args)
+        return
+    if args.workload == "copy-1GiB":
+        bench_copy(args)
         return
 
     import numpy as np
@@ -472,7 +525,9 @@ def main():
         per_launch = bpp * n
         achieved = per_launch / (avg_ms * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": (measured_traffic(dname) if args.workload == "fluid-2^27-f32"
+                                and args.leaf_size == 32 else None),
                     "kernel": dname, "avg_ms": round(avg_ms, 4),
                     "launches_per_step": dcount / args.steps,
                     "alg_bytes_per_launch": int(per_launch)}

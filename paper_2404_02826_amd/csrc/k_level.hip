@@ -72,12 +72,47 @@ struct LevelCtx {
 };
 
 __device__ inline LevelCtx level_ctx(uint32_t nsets, const uint64_t* pre, const SetDesc* sets,
-                                     uint32_t depth) {
+                                     uint32_t depth, uint64_t vb) {
   LevelCtx c;
-  c.s = find_set(pre, nsets, blockIdx.x);
-  c.lb = blockIdx.x - pre[c.s];
+  c.s = find_set(pre, nsets, vb);
+  c.lb = vb - pre[c.s];
   c.sh = level_shape(sets[c.s].n, depth);
   return c;
+}
+__device__ inline LevelCtx level_ctx(uint32_t nsets, const uint64_t* pre, const SetDesc* sets,
+                                     uint32_t depth) {
+  return level_ctx(nsets, pre, sets, depth, blockIdx.x);
+}
+
+// Calls f(code) for every code of axis[A, B) (absolute element indices) with
+// 16-byte loads, U of them in flight per thread.  The axis array is 16-byte
+// aligned and readable up to B rounded up to 16 bytes.
+template <typename KT, typename F>
+__device__ inline void scan_codes(const KT* axis, uint64_t A, uint64_t B, F&& f) {
+  constexpr uint32_t V = 16 / sizeof(KT);
+  constexpr uint32_t U = 4;
+  constexpr uint64_t STEP = (uint64_t)kBlock * V * U;
+  for (uint64_t W = A & ~(uint64_t)(V - 1); W < B; W += STEP) {
+    union {
+      uint4 v;
+      KT e[V];
+    } u[U];
+#pragma unroll
+    for (uint32_t i = 0; i < U; ++i) {
+      const uint64_t e0 = W + ((uint64_t)i * kBlock + threadIdx.x) * V;
+      u[i].v = make_uint4(0, 0, 0, 0);
+      if (e0 < B && e0 + V > A) u[i].v = *(const uint4*)(axis + e0);
+    }
+#pragma unroll
+    for (uint32_t i = 0; i < U; ++i) {
+      const uint64_t e0 = W + ((uint64_t)i * kBlock + threadIdx.x) * V;
+#pragma unroll
+      for (uint32_t k = 0; k < V; ++k) {
+        const uint64_t e = e0 + k;
+        if (e >= A && e < B) f((uint32_t)u[i].e[k]);
+      }
+    }
+  }
 }
 
 template <typename KT>
@@ -96,21 +131,13 @@ __device__ void hist_mid_body(uint32_t depth, uint32_t pass, const SetDesc& S, c
   const uint32_t nb = 1u << w, mask = nb - 1;
   lh[threadIdx.x] = 0;
   __syncthreads();
-  const KT* q = (const KT*)keys + (uint64_t)d * S.kst + st;
+  const KT* q = (const KT*)keys + (uint64_t)d * S.kst;
   const uint64_t beg64 = ch * (uint64_t)c.sh.chunk_elems;
-  const uint32_t beg = (uint32_t)(beg64 < sz ? beg64 : sz);
-  const uint32_t end = (uint32_t)(beg64 + c.sh.chunk_elems < sz ? beg64 + c.sh.chunk_elems : sz);
-  for (uint32_t g = beg; g < end; g += kGroup) {
-    uint32_t v[kRows];
-#pragma unroll
-    for (int i = 0; i < kRows; ++i) {
-      const uint32_t p = g + (uint32_t)i * kBlock + threadIdx.x;
-      v[i] = p < end ? (uint32_t)q[p] : 0xffffffffu;
-    }
-#pragma unroll
-    for (int i = 0; i < kRows; ++i)
-      if (v[i] != 0xffffffffu && (v[i] >> hs) == prefix) atomicAdd(&lh[(v[i] >> sh) & mask], 1u);
-  }
+  const uint64_t A = st + (beg64 < sz ? beg64 : sz);
+  const uint64_t B = st + (beg64 + c.sh.chunk_elems < sz ? beg64 + c.sh.chunk_elems : sz);
+  scan_codes(q, A, B, [&](uint32_t v) {
+    if ((v >> hs) == prefix) atomicAdd(&lh[(v >> sh) & mask], 1u);
+  });
   __syncthreads();
   if (threadIdx.x < nb && lh[threadIdx.x]) atomicAdd(&hist[(j << 8) + threadIdx.x], lh[threadIdx.x]);
 }
@@ -121,17 +148,20 @@ __global__ void __launch_bounds__(kBlock) k_hist_mid(uint32_t depth, uint32_t pa
                                                      const uint64_t* pre, const SetDesc* sets,
                                                      const DevParams* params, uint8_t* keys0,
                                                      const NodeSel* sel0, uint32_t* hist0) {
-  const LevelCtx c = level_ctx(nsets, pre, sets, depth);
-  const SetDesc& S = sets[c.s];
-  const DevParams* P = params + c.s;
-  if (P->status != BBX_OK) return;
-  if (pass + 1 >= digit_plan(P->G[depth % S.dims]).npass) return;
   __shared__ uint32_t lh[kHistBins];
-  const uint8_t* keys = keys0 + S.key_off;
-  if (P->key16)
-    hist_mid_body<uint16_t>(depth, pass, S, P, c, keys, sel0 + S.sel_off, hist0 + S.hist_off, lh);
-  else
-    hist_mid_body<uint32_t>(depth, pass, S, P, c, keys, sel0 + S.sel_off, hist0 + S.hist_off, lh);
+  const uint64_t total = pre[nsets];
+  for (uint64_t vb = blockIdx.x; vb < total; vb += gridDim.x) {  // block-uniform
+    const LevelCtx c = level_ctx(nsets, pre, sets, depth, vb);
+    const SetDesc& S = sets[c.s];
+    const DevParams* P = params + c.s;
+    if (P->status != BBX_OK) continue;
+    if (pass + 1 >= digit_plan(P->G[depth % S.dims]).npass) continue;
+    const uint8_t* keys = keys0 + S.key_off;
+    if (P->key16)
+      hist_mid_body<uint16_t>(depth, pass, S, P, c, keys, sel0 + S.sel_off, hist0 + S.hist_off, lh);
+    else
+      hist_mid_body<uint32_t>(depth, pass, S, P, c, keys, sel0 + S.sel_off, hist0 + S.hist_off, lh);
+  }
 }
 
 // Per node: find the bin that holds the median's rank, then clear the bins.
@@ -207,18 +237,11 @@ __global__ void __launch_bounds__(kBlock) k_hist_root(uint32_t nsets, const uint
   const uint64_t beg = c.lb * (uint64_t)c.sh.chunk_elems;
   const uint64_t end = beg + c.sh.chunk_elems < S.n ? beg + c.sh.chunk_elems : S.n;
   const uint8_t* keys = keys0 + S.key_off;
-  for (uint64_t g = beg; g < end; g += kGroup) {
-    uint32_t v[kRows];
-#pragma unroll
-    for (int i = 0; i < kRows; ++i) {
-      const uint64_t p = g + (uint64_t)i * kBlock + threadIdx.x;
-      v[i] = p < end ? (P->key16 ? (uint32_t)((const uint16_t*)keys)[p] : ((const uint32_t*)keys)[p])
-                     : 0xffffffffu;
-    }
-#pragma unroll
-    for (int i = 0; i < kRows; ++i)
-      if (v[i] != 0xffffffffu) atomicAdd(&lh[(v[i] >> sh) & mask], 1u);
-  }
+  auto add = [&](uint32_t v) { atomicAdd(&lh[(v >> sh) & mask], 1u); };
+  if (P->key16)
+    scan_codes((const uint16_t*)keys, beg, end, add);
+  else
+    scan_codes((const uint32_t*)keys, beg, end, add);
   __syncthreads();
   if (threadIdx.x <= mask && lh[threadIdx.x])
     atomicAdd(&hist0[S.hist_off + threadIdx.x], lh[threadIdx.x]);
@@ -241,28 +264,18 @@ __device__ void hist_last_body(uint32_t depth, const SetDesc& S, const DevParams
   const uint32_t nb = 1u << w, mask = nb - 1;
   lh[threadIdx.x] = 0;
   __syncthreads();
-  const KT* q = (const KT*)keys + (uint64_t)d * S.kst + st;
+  const KT* q = (const KT*)keys + (uint64_t)d * S.kst;
   const uint64_t beg64 = ch * (uint64_t)c.sh.chunk_elems;
-  const uint32_t beg = (uint32_t)(beg64 < sz ? beg64 : sz);
-  const uint32_t end = (uint32_t)(beg64 + c.sh.chunk_elems < sz ? beg64 + c.sh.chunk_elems : sz);
+  const uint64_t A = st + (beg64 < sz ? beg64 : sz);
+  const uint64_t B = st + (beg64 + c.sh.chunk_elems < sz ? beg64 + c.sh.chunk_elems : sz);
   uint32_t below = 0;
-  for (uint32_t g = beg; g < end; g += kGroup) {
-    uint32_t v[kRows];
-#pragma unroll
-    for (int i = 0; i < kRows; ++i) {
-      const uint32_t p = g + (uint32_t)i * kBlock + threadIdx.x;
-      v[i] = p < end ? (uint32_t)q[p] : 0xffffffffu;
-    }
-#pragma unroll
-    for (int i = 0; i < kRows; ++i) {
-      if (v[i] == 0xffffffffu) continue;
-      const uint32_t hi = v[i] >> hs;
-      if (hi == prefix)
-        atomicAdd(&lh[(v[i] >> sh) & mask], 1u);
-      else if (hi < prefix)
-        ++below;
-    }
-  }
+  scan_codes(q, A, B, [&](uint32_t v) {
+    const uint32_t hi = v >> hs;
+    if (hi == prefix)
+      atomicAdd(&lh[(v >> sh) & mask], 1u);
+    else if (hi < prefix)
+      ++below;
+  });
   __syncthreads();
   const uint32_t cnt = threadIdx.x < nb ? lh[threadIdx.x] : 0u;
   uint64_t tot;
@@ -545,8 +558,8 @@ hipError_t launch_levels(const BatchPlan& bp, const Ws& w, hipStream_t s) {
     // mid passes: pass 0 was built above or by the previous scatter
     for (uint32_t pass = 0; pass < 3; ++pass) {
       if (pass > 0)
-        BBX_LAUNCH("level_hist_mid", k_hist_mid, bp.g_lv[k], kBlock, 0, s, k, pass, bp.nsets, plv,
-                   w.sets, w.params, w.keys[cur], w.sel, w.hist);
+        BBX_LAUNCH("level_hist_mid", k_hist_mid, bp.g_lv[k] < 2048 ? bp.g_lv[k] : 2048, kBlock, 0, s,
+                   k, pass, bp.nsets, plv, w.sets, w.params, w.keys[cur], w.sel, w.hist);
       BBX_LAUNCH("level_select_mid", k_select_mid, sel_grid(bp.g_nd[k]), kBlock, 0, s, k, pass,
                  bp.nsets, pnd, w.sets, w.params, w.sel, w.hist);
     }
