@@ -152,7 +152,7 @@ static bbx_status check_set(const SetIn& in) {
 // Byte offsets of the batch workspace regions.
 struct WsLayout {
   size_t params, sets, pre, partials, keys[2], idx[2], hist, sel, rows, cb, leaves, bits, spart,
-      stotal, total;
+      stotal, pneed, total;
 };
 
 struct Carve {
@@ -294,6 +294,7 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
   lay->bits = c.take(8 * leaves_n);
   lay->spart = c.take(8 * (scan_blocks(leaves_n) + 1));
   lay->stotal = c.take(8);
+  lay->pneed = c.take(4 * 4 * kMaxDepth);
   lay->total = c.off;
 }
 
@@ -315,6 +316,7 @@ static Ws carve_ws(const WsLayout& L, uint8_t* base) {
   w.leaf_bits = (uint64_t*)(base + L.bits);
   w.scan_part = (uint64_t*)(base + L.spart);
   w.scan_total = (uint64_t*)(base + L.stotal);
+  w.pass_need = (uint32_t*)(base + L.pneed);
   return w;
 }
 

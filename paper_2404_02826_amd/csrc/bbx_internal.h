@@ -109,6 +109,7 @@ struct Ws {
   uint64_t* scan_part;
   uint64_t* scan_total;
   const uint64_t* pre;  // block-count prefix arrays (see BatchPlan)
+  uint32_t* pass_need;  // [kMaxDepth][4]: some set runs mid pass p at depth k
 };
 
 // ---------------------------------------------------------------- device helpers

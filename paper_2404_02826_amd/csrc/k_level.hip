@@ -58,6 +58,25 @@ __device__ inline uint64_t block_exscan_u64(uint64_t v, uint64_t* total) {
   return off + x - v;
 }
 
+// Which optional mid passes run: flag [k][p] is set when some set has a
+// global level k whose code needs more than p + 1 digit passes.  Kernels of a
+// pass nobody needs exit at their first instruction.
+__global__ void __launch_bounds__(kBlock) k_pass_flags(uint32_t nsets, const SetDesc* sets,
+                                                       const DevParams* params,
+                                                       uint32_t* pass_need) {
+  for (uint32_t i = threadIdx.x; i < 4 * kMaxDepth; i += blockDim.x) pass_need[i] = 0;
+  __syncthreads();
+  for (uint32_t s = threadIdx.x; s < nsets; s += blockDim.x) {
+    const SetDesc& S = sets[s];
+    const DevParams& P = params[s];
+    if (P.status != BBX_OK) continue;
+    for (uint32_t k = 0; k < S.gl && k < (uint32_t)kMaxDepth; ++k) {
+      const uint32_t np = digit_plan(P.G[k % S.dims]).npass;
+      for (uint32_t p = 0; p + 1 < np && p < 4; ++p) atomicOr(&pass_need[k * 4 + p], 1u);
+    }
+  }
+}
+
 __global__ void __launch_bounds__(kBlock) k_hist_zero(uint64_t entries, uint32_t* hist) {
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < entries;
        i += (uint64_t)gridDim.x * blockDim.x)
@@ -147,7 +166,9 @@ __device__ void hist_mid_body(uint32_t depth, uint32_t pass, const SetDesc& S, c
 __global__ void __launch_bounds__(kBlock) k_hist_mid(uint32_t depth, uint32_t pass, uint32_t nsets,
                                                      const uint64_t* pre, const SetDesc* sets,
                                                      const DevParams* params, uint8_t* keys0,
-                                                     const NodeSel* sel0, uint32_t* hist0) {
+                                                     const NodeSel* sel0, uint32_t* hist0,
+                                                     const uint32_t* pass_need) {
+  if (!pass_need[depth * 4 + pass]) return;
   __shared__ uint32_t lh[kHistBins];
   const uint64_t total = pre[nsets];
   for (uint64_t vb = blockIdx.x; vb < total; vb += gridDim.x) {  // block-uniform
@@ -171,7 +192,8 @@ __global__ void __launch_bounds__(kBlock) k_select_mid(uint32_t depth, uint32_t 
                                                        uint32_t nsets, const uint64_t* pre,
                                                        const SetDesc* sets,
                                                        const DevParams* params, NodeSel* sel0,
-                                                       uint32_t* hist0) {
+                                                       uint32_t* hist0, const uint32_t* pass_need) {
+  if (!pass_need[depth * 4 + pass]) return;
   const uint32_t lane = threadIdx.x & 63;
   const uint64_t total = pre[nsets];
   constexpr uint32_t wpb = kBlock / 64;
@@ -548,6 +570,8 @@ static uint64_t sel_grid(uint64_t nodes) {
 hipError_t launch_levels(const BatchPlan& bp, const Ws& w, hipStream_t s) {
   if (bp.max_gl == 0) return hipGetLastError();
   BBX_LAUNCH("level_hist_zero", k_hist_zero, 1024, kBlock, 0, s, bp.hist_entries, w.hist);
+  BBX_LAUNCH("level_pass_flags", k_pass_flags, 1, kBlock, 0, s, bp.nsets, w.sets, w.params,
+             w.pass_need);
   for (uint32_t k = 0; k < bp.max_gl; ++k) {
     const uint64_t* plv = w.pre + bp.o_lv[k];
     const uint64_t* pnd = w.pre + bp.o_nd[k];
@@ -559,9 +583,10 @@ hipError_t launch_levels(const BatchPlan& bp, const Ws& w, hipStream_t s) {
     for (uint32_t pass = 0; pass < 3; ++pass) {
       if (pass > 0)
         BBX_LAUNCH("level_hist_mid", k_hist_mid, bp.g_lv[k] < 2048 ? bp.g_lv[k] : 2048, kBlock, 0, s,
-                   k, pass, bp.nsets, plv, w.sets, w.params, w.keys[cur], w.sel, w.hist);
+                   k, pass, bp.nsets, plv, w.sets, w.params, w.keys[cur], w.sel, w.hist,
+                   w.pass_need);
       BBX_LAUNCH("level_select_mid", k_select_mid, sel_grid(bp.g_nd[k]), kBlock, 0, s, k, pass,
-                 bp.nsets, pnd, w.sets, w.params, w.sel, w.hist);
+                 bp.nsets, pnd, w.sets, w.params, w.sel, w.hist, w.pass_need);
     }
     BBX_LAUNCH("level_hist_last", k_hist_last, bp.g_lv[k], kBlock, 0, s, k, bp.nsets, plv, w.sets,
                w.params, w.keys[cur], w.sel, w.hist, w.rows);

@@ -10,6 +10,8 @@
 //               structure-of-arrays codes (u16 when every G_d <= 16, else u32)
 #include <math.h>
 
+#include <type_traits>
+
 #include "bbx_internal.h"
 
 namespace bbx {
@@ -35,6 +37,34 @@ __device__ inline double wave_max(double v) {
   return v;
 }
 
+// Array-of-structures input with a 16-byte aligned base: a thread reads V
+// consecutive particles (DIMS 16-byte loads) at a time, so each loaded
+// element's axis is fixed; the remaining particles go one by one.
+template <typename T, int DIMS>
+__device__ uint64_t minmax_aos_vec(const T* __restrict__ pos, uint64_t n, uint64_t t0, uint64_t nt,
+                                   double* lo, double* hi, double& bad) {
+  constexpr uint32_t V = 16 / sizeof(T);
+  const uint64_t ng = n / V;
+  const uint4* p4 = (const uint4*)pos;
+  for (uint64_t g = t0; g < ng; g += nt) {
+    union {
+      uint4 v[DIMS];
+      T e[DIMS * V];
+    } u;
+#pragma unroll
+    for (int i = 0; i < DIMS; ++i) u.v[i] = p4[g * DIMS + i];
+#pragma unroll
+    for (int e = 0; e < DIMS * (int)V; ++e) {
+      const int d = e % DIMS;
+      const double v = (double)u.e[e];
+      if (!isfinite(v)) bad = 1.0;
+      lo[d] = v < lo[d] ? v : lo[d];
+      hi[d] = v > hi[d] ? v : hi[d];
+    }
+  }
+  return ng * V;  // particles handled
+}
+
 template <typename T>
 __device__ void minmax_body(const T* __restrict__ pos, uint64_t n, uint32_t dims, uint32_t layout,
                             uint64_t lb, uint32_t mm_blocks, double* part) {
@@ -42,7 +72,11 @@ __device__ void minmax_body(const T* __restrict__ pos, uint64_t n, uint32_t dims
   double hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   double bad = 0.0;
   const uint64_t stride = (uint64_t)mm_blocks * blockDim.x;
-  for (uint64_t i = lb * blockDim.x + threadIdx.x; i < n; i += stride) {
+  uint64_t first = 0;
+  if (layout == BBX_AOS && ((uintptr_t)pos & 15) == 0)
+    first = dims == 3 ? minmax_aos_vec<T, 3>(pos, n, lb * blockDim.x + threadIdx.x, stride, lo, hi, bad)
+                      : minmax_aos_vec<T, 2>(pos, n, lb * blockDim.x + threadIdx.x, stride, lo, hi, bad);
+  for (uint64_t i = first + lb * blockDim.x + threadIdx.x; i < n; i += stride) {
 #pragma unroll
     for (uint32_t d = 0; d < 3; ++d) {
       if (d >= dims) break;
@@ -197,6 +231,39 @@ __global__ void __launch_bounds__(kBlock) k_epilogue(const SetDesc* sets, const 
   *P = p;
 }
 
+template <typename T, typename KT, int DIMS>
+__device__ uint64_t quantize_aos_vec(const T* __restrict__ pos, uint64_t n, uint64_t kst,
+                                     const double* lo, double inv_w, uint64_t t0, uint64_t nt,
+                                     KT* __restrict__ keys, uint32_t* __restrict__ idx) {
+  constexpr uint32_t V = 16 / sizeof(T);  // particles per group (2 or 4)
+  const uint64_t ng = n / V;
+  const uint4* p4 = (const uint4*)pos;
+  for (uint64_t g = t0; g < ng; g += nt) {
+    union {
+      uint4 v[DIMS];
+      T e[DIMS * V];
+    } u;
+#pragma unroll
+    for (int i = 0; i < DIMS; ++i) u.v[i] = p4[g * DIMS + i];
+#pragma unroll
+    for (int d = 0; d < DIMS; ++d) {
+      union {
+        KT k[V];
+        typename std::conditional<sizeof(KT) * V == 16, uint4,
+                 typename std::conditional<sizeof(KT) * V == 8, uint2, uint32_t>::type>::type w;
+      } o;
+#pragma unroll
+      for (uint32_t j = 0; j < V; ++j)
+        o.k[j] = (KT)(uint32_t)floor(((double)u.e[j * DIMS + d] - lo[d]) * inv_w + 0.5);
+      *(decltype(o.w)*)(keys + (uint64_t)d * kst + g * V) = o.w;
+    }
+    if (idx)
+#pragma unroll
+      for (uint32_t j = 0; j < V; ++j) idx[g * V + j] = (uint32_t)(g * V + j);
+  }
+  return ng * V;
+}
+
 template <typename T, typename KT>
 __device__ void quantize_body(const T* __restrict__ pos, uint64_t n, uint64_t kst, uint32_t dims,
                               uint32_t layout, double lo0, double lo1, double lo2, double inv_w,
@@ -204,7 +271,13 @@ __device__ void quantize_body(const T* __restrict__ pos, uint64_t n, uint64_t ks
                               uint32_t* __restrict__ idx) {
   const double lo[3] = {lo0, lo1, lo2};
   const uint64_t stride = nblk * blockDim.x;
-  for (uint64_t i = lb * blockDim.x + threadIdx.x; i < n; i += stride) {
+  uint64_t first = 0;
+  if (layout == BBX_AOS && ((uintptr_t)pos & 15) == 0)
+    first = dims == 3 ? quantize_aos_vec<T, KT, 3>(pos, n, kst, lo, inv_w, lb * blockDim.x + threadIdx.x,
+                                                   stride, keys, idx)
+                      : quantize_aos_vec<T, KT, 2>(pos, n, kst, lo, inv_w, lb * blockDim.x + threadIdx.x,
+                                                   stride, keys, idx);
+  for (uint64_t i = first + lb * blockDim.x + threadIdx.x; i < n; i += stride) {
 #pragma unroll
     for (uint32_t d = 0; d < 3; ++d) {
       if (d >= dims) break;
