@@ -152,7 +152,7 @@ static bbx_status check_set(const SetIn& in) {
 // Byte offsets of the batch workspace regions.
 struct WsLayout {
   size_t params, sets, pre, partials, keys[2], idx[2], hist, sel, rows, cb, leaves, bits, spart,
-      stotal, pneed, total;
+      stotal, pneed, defer, total;
 };
 
 struct Carve {
@@ -295,6 +295,7 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
   lay->spart = c.take(8 * (scan_blocks(leaves_n) + 1));
   lay->stotal = c.take(8);
   lay->pneed = c.take(4 * 4 * kMaxDepth);
+  lay->defer = c.take(4 * (bp->g_tile + 1));
   lay->total = c.off;
 }
 
@@ -317,6 +318,7 @@ static Ws carve_ws(const WsLayout& L, uint8_t* base) {
   w.scan_part = (uint64_t*)(base + L.spart);
   w.scan_total = (uint64_t*)(base + L.stotal);
   w.pass_need = (uint32_t*)(base + L.pneed);
+  w.tile_defer = (uint32_t*)(base + L.defer);
   return w;
 }
 

@@ -110,6 +110,7 @@ struct Ws {
   uint64_t* scan_total;
   const uint64_t* pre;  // block-count prefix arrays (see BatchPlan)
   uint32_t* pass_need;  // [kMaxDepth][4]: some set runs mid pass p at depth k
+  uint32_t* tile_defer; // [0] = count, then global tile indices left to the 32-bit tile pass
 };
 
 // ---------------------------------------------------------------- device helpers

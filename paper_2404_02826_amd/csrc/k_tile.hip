@@ -87,15 +87,20 @@ __device__ inline uint32_t wave_max_dpp(uint32_t x) {
   return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
 }
 
-template <int TILE>
+// LDS of one tile.  KL holds codes minus the tile's per-axis minimum: 16 bits
+// for every tile whose spans fit (the first pass), 32 bits for the rest (a
+// second pass over the tiles the first one deferred).  Source indices only
+// take space when some set asks for a perm output.
+template <int TILE, typename KL, bool TRACK>
 struct WaveTile {
-  uint32_t K[3][TILE];           // codes minus the tile's per-axis minimum, at original slots
+  KL K[3][TILE];                 // codes minus the tile minimum, at original slots
   uint16_t Pm[2][TILE];          // position -> slot (ping-pong)
-  uint32_t I[TILE];              // source indices (only with a perm output)
+  uint32_t I[TRACK ? TILE : 1];  // source indices
   uint32_t H[TILE];              // histogram bins (all zero between passes); then the leaf table
   uint32_t S[TILE];              // exclusive (lt | eq << 16) prefix; then position -> leaf
   uint16_t nst[TILE / 2], nsz[TILE / 2];
-  uint32_t npre[TILE / 2], nrank[TILE / 2];
+  KL npre[TILE / 2];             // high digits of each node's median found so far
+  uint16_t nrank[TILE / 2];      // rank of the median among the remaining candidates
   uint16_t lref[TILE];           // reference position within each leaf
 };
 
@@ -104,8 +109,8 @@ __device__ inline uint32_t leaf_fold(uint32_t s, uint32_t r) { return s <= r ? s
 // Bit boxes of the tile's leaves (Sec. 4.1, Eq. 2) by aligned groups of gs
 // lanes; DT holds squared distances in doubled code space (32 bits suffice
 // when every code span is below 2^14).
-template <int TILE, typename DT>
-__device__ void tile_bitboxes(WaveTile<TILE>& sm, int cur, uint32_t nl, uint32_t gs, uint32_t dims,
+template <int TILE, typename KL, bool TRACK, typename DT>
+__device__ void tile_bitboxes(WaveTile<TILE, KL, TRACK>& sm, int cur, uint32_t nl, uint32_t gs, uint32_t dims,
                               uint32_t t0, uint32_t t1, uint32_t t2, uint64_t tst, uint64_t first_leaf,
                               uint64_t n_leaves, DevParams* P, LeafRec* leaves,
                               uint64_t* leaf_bits) {
@@ -190,12 +195,15 @@ __device__ void tile_bitboxes(WaveTile<TILE>& sm, int cur, uint32_t nl, uint32_t
   }
 }
 
-template <int TILE, typename KT>
-__device__ void tile_body(WaveTile<TILE>& sm, uint64_t j, uint32_t K0, uint64_t n, uint64_t kst,
-                          uint32_t dims,
-                          uint32_t r, uint64_t n_leaves, const TreeGeom& g, DevParams* P, KT* keys,
-                          const uint32_t* idx, uint32_t* perm, LeafRec* leaves,
-                          uint64_t* leaf_bits) {
+// One node of the tile depth.  With 16-bit tile codes, a node whose code
+// span along some axis exceeds 16 bits is appended to `defer` ([0] = count,
+// then global tile indices) and left to the 32-bit pass.
+template <int TILE, typename KT, typename KL, bool TRACK>
+__device__ void tile_body(WaveTile<TILE, KL, TRACK>& sm, uint64_t j, uint32_t K0, uint64_t n,
+                          uint64_t kst, uint32_t dims, uint32_t r, uint64_t n_leaves,
+                          const TreeGeom& g, DevParams* P, KT* keys, const uint32_t* idx,
+                          uint32_t* perm, LeafRec* leaves, uint64_t* leaf_bits, uint32_t* defer,
+                          uint32_t gtile) {
   constexpr int E = TILE / 64;
   const uint32_t lane = threadIdx.x & 63;
   uint64_t tst, s0_64;
@@ -211,36 +219,27 @@ __device__ void tile_body(WaveTile<TILE>& sm, uint64_t j, uint32_t K0, uint64_t 
   // ---- stage the node (loads of up to 8 rows in flight) and find the tile's
   // per-axis code range: every later step works on codes minus the minimum,
   // which keeps the radix digits few and the bins spread
-  constexpr int EB = E < 8 ? E : 8;
+  static_assert(E <= 8, "all rows of the node are held in registers while staging");
   uint32_t lo[3] = {0xffffffffu, 0xffffffffu, 0xffffffffu}, hi[3] = {0, 0, 0};
-  for (int k0 = 0; k0 < E; k0 += EB) {
-    uint32_t v[3][EB];
-    uint32_t ix[EB];
+  uint32_t v[3][E];
+  uint32_t ix[E];
 #pragma unroll
-    for (int k = 0; k < EB; ++k) {
-      const uint32_t p = lane + 64u * (k0 + k);
+  for (int k = 0; k < E; ++k) {
+    const uint32_t p = lane + 64u * k;
 #pragma unroll
-      for (uint32_t d = 0; d < 3; ++d)
-        v[d][k] = (p < s0 && d < dims) ? (uint32_t)keys[(uint64_t)d * kst + tst + p] : 0u;
-      ix[k] = (p < s0 && track) ? idx[tst + p] : 0u;
-    }
+    for (uint32_t d = 0; d < 3; ++d)
+      v[d][k] = (p < s0 && d < dims) ? (uint32_t)keys[(uint64_t)d * kst + tst + p] : 0u;
+    ix[k] = (TRACK && p < s0 && track) ? idx[tst + p] : 0u;
+  }
 #pragma unroll
-    for (int k = 0; k < EB; ++k) {
-      const uint32_t p = lane + 64u * (k0 + k);
-      if (p < s0) {
+  for (int k = 0; k < E; ++k) {
+    const uint32_t p = lane + 64u * k;
+    if (p < s0)
 #pragma unroll
-        for (uint32_t d = 0; d < 3; ++d) {
-          if (d < dims) {
-            sm.K[d][p] = v[d][k];
-            lo[d] = umin32(lo[d], v[d][k]);
-            hi[d] = umax32(hi[d], v[d][k]);
-          }
-        }
-        sm.Pm[0][p] = (uint16_t)p;
-        if (track) sm.I[p] = ix[k];
+      for (uint32_t d = 0; d < 3; ++d) {
+        lo[d] = umin32(lo[d], v[d][k]);
+        hi[d] = umax32(hi[d], v[d][k]);
       }
-      sm.H[p] = 0;
-    }
   }
   uint32_t tmin[3] = {0, 0, 0}, Gt[3] = {0, 0, 0};
 #pragma unroll
@@ -249,14 +248,21 @@ __device__ void tile_body(WaveTile<TILE>& sm, uint64_t j, uint32_t K0, uint64_t 
     tmin[d] = wave_min_dpp(lo[d]);
     Gt[d] = bitlen32(wave_max_dpp(hi[d]) - tmin[d]);
   }
-  wave_sync();
+  if (sizeof(KL) == 2 && umax32(Gt[0], umax32(Gt[1], Gt[2])) > 16) {
+    if (lane == 0) defer[1 + atomicAdd(&defer[0], 1u)] = gtile;  // the 32-bit pass takes it
+    return;
+  }
 #pragma unroll
   for (int k = 0; k < E; ++k) {
     const uint32_t p = lane + 64u * k;
-    if (p < s0)
+    if (p < s0) {
 #pragma unroll
       for (uint32_t d = 0; d < 3; ++d)
-        if (d < dims) sm.K[d][p] -= tmin[d];
+        if (d < dims) sm.K[d][p] = (KL)(v[d][k] - tmin[d]);
+      sm.Pm[0][p] = (uint16_t)p;
+      if (TRACK && track) sm.I[p] = ix[k];
+    }
+    sm.H[p] = 0;
   }
   wave_sync();
 
@@ -282,7 +288,7 @@ __device__ void tile_body(WaveTile<TILE>& sm, uint64_t j, uint32_t K0, uint64_t 
       sm.nst[i] = (uint16_t)a;
       sm.nsz[i] = (uint16_t)b;
       sm.npre[i] = 0;
-      sm.nrank[i] = (uint32_t)(b >> 1);
+      sm.nrank[i] = (uint16_t)(b >> 1);
     }
     wave_sync();
     uint32_t slot[E], q[E];
@@ -342,8 +348,8 @@ __device__ void tile_body(WaveTile<TILE>& sm, uint64_t j, uint32_t K0, uint64_t 
             const uint32_t pr = sm.npre[i];
             for (uint32_t k = 0; k < per; ++k) {
               if (cum <= rank && rank < cum + c[k]) {
-                sm.npre[i] = (pr << w) | (lane * per + k);
-                sm.nrank[i] = rank - cum;
+                sm.npre[i] = (KL)((pr << w) | (lane * per + k));
+                sm.nrank[i] = (uint16_t)(rank - cum);
               }
               cum += c[k];
             }
@@ -359,8 +365,8 @@ __device__ void tile_body(WaveTile<TILE>& sm, uint64_t j, uint32_t K0, uint64_t 
               if (found == 0xffffffffu && rank < cum + c) found = b, below = cum;
               cum += c;
             }
-            sm.npre[i] = (sm.npre[i] << w) | found;
-            sm.nrank[i] = rank - below;
+            sm.npre[i] = (KL)(((uint32_t)sm.npre[i] << w) | found);
+            sm.nrank[i] = (uint16_t)(rank - below);
           }
         }
         wave_sync();
@@ -453,10 +459,10 @@ __device__ void tile_body(WaveTile<TILE>& sm, uint64_t j, uint32_t K0, uint64_t 
   while (gs > 1 && gs / 2 >= maxleaf) gs >>= 1;
   const uint32_t span = umax32(Gt[0], umax32(Gt[1], Gt[2]));
   if (span <= 14)
-    tile_bitboxes<TILE, uint32_t>(sm, cur, nl, gs, dims, tmin[0], tmin[1], tmin[2], tst,
+    tile_bitboxes<TILE, KL, TRACK, uint32_t>(sm, cur, nl, gs, dims, tmin[0], tmin[1], tmin[2], tst,
                                   first_leaf, n_leaves, P, leaves, leaf_bits);
   else
-    tile_bitboxes<TILE, uint64_t>(sm, cur, nl, gs, dims, tmin[0], tmin[1], tmin[2], tst,
+    tile_bitboxes<TILE, KL, TRACK, uint64_t>(sm, cur, nl, gs, dims, tmin[0], tmin[1], tmin[2], tst,
                                   first_leaf, n_leaves, P, leaves, leaf_bits);
   wave_sync();
 
@@ -471,33 +477,65 @@ __device__ void tile_body(WaveTile<TILE>& sm, uint64_t j, uint32_t K0, uint64_t 
 #pragma unroll
     for (uint32_t d = 0; d < 3; ++d)
       if (d < dims) keys[(uint64_t)d * kst + gpos] = (KT)(sm.K[d][slot] + tmin[d]);
-    if (track) perm[gpos] = sm.I[slot];
+    if (TRACK && track) perm[gpos] = sm.I[slot];
   }
 }
 
-template <int TILE>
-__global__ void __launch_bounds__(64) k_tile(uint32_t nsets, const uint64_t* pre,
-                                             const SetDesc* sets, DevParams* params,
-                                             uint8_t* keys0, uint8_t* keys1, uint32_t* idx0,
-                                             uint32_t* idx1, LeafRec* leaves0,
-                                             uint64_t* leaf_bits0) {
-  const uint32_t s = find_set(pre, nsets, blockIdx.x);
+template <int TILE, typename KL, bool TRACK>
+__device__ void tile_node(uint32_t nsets, const uint64_t* pre, const SetDesc* sets,
+                          DevParams* params, uint8_t* keys0, uint8_t* keys1, uint32_t* idx0,
+                          uint32_t* idx1, LeafRec* leaves0, uint64_t* leaf_bits0, uint32_t* defer,
+                          uint32_t gtile, WaveTile<TILE, KL, TRACK>& sm) {
+  const uint32_t s = find_set(pre, nsets, gtile);
   const SetDesc& S = sets[s];
   DevParams* P = params + s;
   if (P->status != BBX_OK) return;
-  __shared__ WaveTile<TILE> sm;
-  const uint64_t j = blockIdx.x - pre[s];
+  const uint64_t j = gtile - pre[s];
   const uint32_t buf = S.gl & 1;
   uint8_t* keys = (buf ? keys1 : keys0) + S.key_off;
   const uint32_t* idx = S.perm ? (buf ? idx1 : idx0) + S.idx_off : nullptr;
   LeafRec* leaves = leaves0 + S.leaf_off;
   uint64_t* leaf_bits = leaf_bits0 + S.leaf_off;
   if (P->key16)
-    tile_body<TILE, uint16_t>(sm, j, S.gl, S.n, S.kst, S.dims, S.r, S.n_leaves, S.geom, P,
-                              (uint16_t*)keys, idx, S.perm, leaves, leaf_bits);
+    tile_body<TILE, uint16_t, KL, TRACK>(sm, j, S.gl, S.n, S.kst, S.dims, S.r, S.n_leaves, S.geom,
+                                         P, (uint16_t*)keys, idx, S.perm, leaves, leaf_bits, defer,
+                                         gtile);
   else
-    tile_body<TILE, uint32_t>(sm, j, S.gl, S.n, S.kst, S.dims, S.r, S.n_leaves, S.geom, P,
-                              (uint32_t*)keys, idx, S.perm, leaves, leaf_bits);
+    tile_body<TILE, uint32_t, KL, TRACK>(sm, j, S.gl, S.n, S.kst, S.dims, S.r, S.n_leaves, S.geom,
+                                         P, (uint32_t*)keys, idx, S.perm, leaves, leaf_bits, defer,
+                                         gtile);
+}
+
+// first pass: every tile, 16-bit tile codes
+template <int TILE, bool TRACK>
+__global__ void __launch_bounds__(64) k_tile(uint32_t nsets, const uint64_t* pre,
+                                             const SetDesc* sets, DevParams* params,
+                                             uint8_t* keys0, uint8_t* keys1, uint32_t* idx0,
+                                             uint32_t* idx1, LeafRec* leaves0,
+                                             uint64_t* leaf_bits0, uint32_t* defer) {
+  __shared__ WaveTile<TILE, uint16_t, TRACK> sm;
+  tile_node<TILE, uint16_t, TRACK>(nsets, pre, sets, params, keys0, keys1, idx0, idx1, leaves0,
+                                   leaf_bits0, defer, blockIdx.x, sm);
+}
+
+// second pass: the deferred tiles, 32-bit tile codes (capped grid, striding)
+template <int TILE, bool TRACK>
+__global__ void __launch_bounds__(64) k_tile_wide(uint32_t nsets, const uint64_t* pre,
+                                                  const SetDesc* sets, DevParams* params,
+                                                  uint8_t* keys0, uint8_t* keys1, uint32_t* idx0,
+                                                  uint32_t* idx1, LeafRec* leaves0,
+                                                  uint64_t* leaf_bits0, const uint32_t* defer) {
+  __shared__ WaveTile<TILE, uint32_t, TRACK> sm;
+  const uint32_t count = defer[0];
+  for (uint32_t q = blockIdx.x; q < count; q += gridDim.x) {
+    tile_node<TILE, uint32_t, TRACK>(nsets, pre, sets, params, keys0, keys1, idx0, idx1, leaves0,
+                                     leaf_bits0, nullptr, defer[1 + q], sm);
+    wave_sync();  // the next tile reuses the LDS
+  }
+}
+
+__global__ void k_zero_u32(uint32_t* p) {
+  if (threadIdx.x == 0) *p = 0;
 }
 
 // ---------------------------------------------------------------- big leaves
@@ -609,14 +647,24 @@ __global__ void __launch_bounds__(kBlock) k_bigleaf(uint32_t nsets, const uint64
                            S.perm, leaves0 + S.leaf_off, leaf_bits0 + S.leaf_off);
 }
 
+template <int TILE, bool TRACK>
+static void launch_tiles(const BatchPlan& bp, const Ws& w, hipStream_t s) {
+  BBX_LAUNCH("tile", (k_tile<TILE, TRACK>), bp.g_tile, 64, 0, s, bp.nsets, w.pre + bp.o_tile, w.sets,
+             w.params, w.keys[0], w.keys[1], w.idx[0], w.idx[1], w.leaves, w.leaf_bits,
+             w.tile_defer);
+  const uint64_t gw = bp.g_tile < 4096 ? bp.g_tile : 4096;
+  BBX_LAUNCH("tile_wide", (k_tile_wide<TILE, TRACK>), gw, 64, 0, s, bp.nsets, w.pre + bp.o_tile,
+             w.sets, w.params, w.keys[0], w.keys[1], w.idx[0], w.idx[1], w.leaves, w.leaf_bits,
+             w.tile_defer);
+}
+
 hipError_t launch_leaves(const BatchPlan& bp, const Ws& w, hipStream_t s) {
   if (bp.g_tile > 0) {
+    BBX_LAUNCH("tile_defer_zero", k_zero_u32, 1, 64, 0, s, w.tile_defer);
     if (bp.tile == 256)
-      BBX_LAUNCH("tile", k_tile<256>, bp.g_tile, 64, 0, s, bp.nsets, w.pre + bp.o_tile, w.sets,
-                 w.params, w.keys[0], w.keys[1], w.idx[0], w.idx[1], w.leaves, w.leaf_bits);
+      bp.track ? launch_tiles<256, true>(bp, w, s) : launch_tiles<256, false>(bp, w, s);
     else
-      BBX_LAUNCH("tile", k_tile<512>, bp.g_tile, 64, 0, s, bp.nsets, w.pre + bp.o_tile, w.sets,
-                 w.params, w.keys[0], w.keys[1], w.idx[0], w.idx[1], w.leaves, w.leaf_bits);
+      bp.track ? launch_tiles<512, true>(bp, w, s) : launch_tiles<512, false>(bp, w, s);
   }
   if (bp.g_big > 0)
     BBX_LAUNCH("bigleaf", k_bigleaf, bp.g_big, kBlock, 0, s, bp.nsets, w.pre + bp.o_big, w.sets,
