@@ -84,12 +84,13 @@ __device__ inline uint64_t read64(const uint64_t* sec, uint64_t at, uint32_t len
   return len < 64 ? v & ((1ull << len) - 1) : v;
 }
 
-template <typename T>
-__device__ void unpack_body(uint64_t n, uint32_t dims, uint32_t layout, uint32_t r, double w,
+template <typename T, int DIMS>
+__device__ void unpack_body(uint64_t n, uint32_t layout, uint32_t r, double w,
                             const double* origin, const uint32_t* G, uint64_t nl,
                             const LeafRec* leaves, const uint64_t* off, const uint64_t* pay,
                             uint64_t pay_words, uint64_t pbits, T* out, DevParams* P,
                             LeafRec* s_rec, uint64_t* s_off, uint64_t* s_pay) {
+  constexpr uint32_t dims = DIMS;
   const uint32_t lpb = leaves_per_block(r);
   const uint64_t L0 = (uint64_t)blockIdx.x * lpb;
   if (L0 >= nl) return;
@@ -109,57 +110,82 @@ __device__ void unpack_body(uint64_t n, uint32_t dims, uint32_t layout, uint32_t
   const uint64_t slot0 = s_rec[0].start;
   const uint64_t slot1 = (uint64_t)s_rec[nlb - 1].start + s_rec[nlb - 1].size;
   bool corrupt = false;
-  for (uint64_t p = slot0 + threadIdx.x; p < slot1; p += kBlock) {
-    uint32_t a = 0, z = nlb - 1;  // last staged leaf starting at or before p
+  // each thread decodes 4 consecutive slots (4-aligned slot indices); with an
+  // aligned array-of-structures output the 4 particles go out as whole
+  // 16-byte stores
+  const bool vec = layout == BBX_AOS && ((uintptr_t)out & 15) == 0;
+  for (uint64_t gs = (slot0 & ~3ull) + 4ull * threadIdx.x; gs < slot1; gs += 4ull * kBlock) {
+    const bool full = vec && gs >= slot0 && gs + 4 <= slot1;
+    union {
+      T e[4 * DIMS];
+      uint4 v[4 * DIMS * sizeof(T) / 16];
+    } o;
+    const uint64_t pfirst = gs > slot0 ? gs : slot0;
+    uint32_t a = 0, z = nlb - 1;  // last staged leaf starting at or before pfirst
     while (a < z) {
       const uint32_t mid = (a + z + 1) >> 1;
-      if (s_rec[mid].start <= p)
+      if (s_rec[mid].start <= pfirst)
         a = mid;
       else
         z = mid - 1;
     }
-    const LeafRec rec = s_rec[a];
-    const uint64_t j = p - rec.start;
-    int64_t q[3] = {rec.qref[0], rec.qref[1], rec.qref[2]};
-    if (j > 0) {
-      uint32_t summ = 0;
-      for (uint32_t d = 0; d < dims; ++d) summ += (rec.m >> (8 * d)) & 0xffu;
-      const uint64_t at = s_off[a] + (j - 1) * summ;
-      if (summ <= 64) {
-        uint64_t v = staged ? read64(s_pay, at - w0 * 64, summ) : read64(pay, at, summ);
 #pragma unroll
-        for (uint32_t d = 0; d < 3; ++d) {
-          if (d >= dims) break;
-          const uint32_t m = (rec.m >> (8 * d)) & 0xffu;
-          if (m == 0) continue;
-          const uint64_t u = v & ((1ull << m) - 1);
-          v >>= m;
-          if (u == 0) corrupt = true;
-          q[d] = (int64_t)rec.qref[d] + (int64_t)u - ((int64_t)1 << (m - 1));
+    for (uint32_t k = 0; k < 4; ++k) {
+      const uint64_t p = gs + k;
+      if (p < slot0 || p >= slot1) continue;
+      while (a + 1 < nlb && s_rec[a + 1].start <= p) ++a;
+      const LeafRec rec = s_rec[a];
+      const uint64_t j = p - rec.start;
+      int64_t q[3] = {rec.qref[0], rec.qref[1], rec.qref[2]};
+      if (j > 0) {
+        uint32_t summ = 0;
+        for (uint32_t d = 0; d < dims; ++d) summ += (rec.m >> (8 * d)) & 0xffu;
+        const uint64_t at = s_off[a] + (j - 1) * summ;
+        if (summ <= 64) {
+          uint64_t v = staged ? read64(s_pay, at - w0 * 64, summ) : read64(pay, at, summ);
+#pragma unroll
+          for (uint32_t d = 0; d < 3; ++d) {
+            if (d >= dims) break;
+            const uint32_t m = (rec.m >> (8 * d)) & 0xffu;
+            if (m == 0) continue;
+            const uint64_t u = v & ((1ull << m) - 1);
+            v >>= m;
+            if (u == 0) corrupt = true;
+            q[d] = (int64_t)rec.qref[d] + (int64_t)u - ((int64_t)1 << (m - 1));
+          }
+        } else {
+          u128 v = staged ? read_bits(s_pay, nw, at - w0 * 64, summ) : read_bits(pay, pay_words, at, summ);
+          for (uint32_t d = 0; d < dims; ++d) {
+            const uint32_t m = (rec.m >> (8 * d)) & 0xffu;
+            if (m == 0) continue;
+            const uint64_t u = (uint64_t)(v & ((((u128)1) << m) - 1));
+            v >>= m;
+            if (u == 0) corrupt = true;
+            q[d] = (int64_t)rec.qref[d] + (int64_t)u - ((int64_t)1 << (m - 1));
+          }
         }
-      } else {
-        u128 v = staged ? read_bits(s_pay, nw, at - w0 * 64, summ) : read_bits(pay, pay_words, at, summ);
-        for (uint32_t d = 0; d < dims; ++d) {
-          const uint32_t m = (rec.m >> (8 * d)) & 0xffu;
-          if (m == 0) continue;
-          const uint64_t u = (uint64_t)(v & ((((u128)1) << m) - 1));
-          v >>= m;
-          if (u == 0) corrupt = true;
-          q[d] = (int64_t)rec.qref[d] + (int64_t)u - ((int64_t)1 << (m - 1));
+      }
+#pragma unroll
+      for (uint32_t d = 0; d < 3; ++d) {
+        if (d >= dims) break;
+        if (q[d] < 0 || q[d] >= ((int64_t)1 << G[d])) {
+          corrupt = true;
+          q[d] = 0;
         }
+        const double x = origin[d] + (double)q[d] * w;
+        const T t = (T)x;
+        if (full)
+          o.e[k * dims + d] = t;
+        else if (layout == BBX_AOS)
+          out[p * dims + d] = t;
+        else
+          out[(uint64_t)d * n + p] = t;
       }
     }
-    for (uint32_t d = 0; d < dims; ++d) {
-      if (q[d] < 0 || q[d] >= ((int64_t)1 << G[d])) {
-        corrupt = true;
-        q[d] = 0;
-      }
-      const double x = origin[d] + (double)q[d] * w;
-      const T t = (T)x;
-      if (layout == BBX_AOS)
-        out[p * dims + d] = t;
-      else
-        out[(uint64_t)d * n + p] = t;
+    if (full) {
+      uint4* dst = (uint4*)(out + gs * dims);
+#pragma unroll
+      for (uint32_t i = 0; i < 4 * DIMS * sizeof(T) / 16; ++i) dst[i] = o.v[i];
     }
   }
   if (corrupt) P->status = BBX_ECORRUPT;
@@ -180,8 +206,12 @@ __global__ void __launch_bounds__(kBlock) k_unpack(uint64_t n, uint32_t dims, ui
   const double origin[3] = {o0, o1, o2};
   const uint32_t G[3] = {G0, G1, G2};
   const uint64_t* pay = (const uint64_t*)(stream + kHeaderBytes + ((meta_bits + 63) / 64) * 8);
-  unpack_body<T>(n, dims, layout, r, w, origin, G, n_leaves, leaves, off, pay, (pay_bits + 63) / 64,
-                 pay_bits, out, P, s_rec, s_off, s_pay);
+  if (dims == 3)
+    unpack_body<T, 3>(n, layout, r, w, origin, G, n_leaves, leaves, off, pay, (pay_bits + 63) / 64,
+                      pay_bits, out, P, s_rec, s_off, s_pay);
+  else
+    unpack_body<T, 2>(n, layout, r, w, origin, G, n_leaves, leaves, off, pay, (pay_bits + 63) / 64,
+                      pay_bits, out, P, s_rec, s_off, s_pay);
 }
 
 __global__ void k_dec_init(DevParams* P) {
