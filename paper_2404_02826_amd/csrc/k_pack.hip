@@ -200,7 +200,9 @@ __device__ inline u128 member_code(const KT* keys, uint64_t stride, uint32_t dim
                                    uint64_t slot) {
   u128 v = 0;
   uint32_t at = 0;
-  for (uint32_t d = 0; d < dims; ++d) {
+#pragma unroll
+  for (uint32_t d = 0; d < 3; ++d) {
+    if (d >= dims) break;
     const uint32_t m = (rec.m >> (8 * d)) & 0xffu;
     if (m == 0) continue;
     const uint32_t q = keys[(uint64_t)d * stride + slot];
@@ -227,25 +229,6 @@ __device__ inline uint64_t search_off(const uint64_t* off, uint64_t base, uint64
 }
 
 constexpr uint32_t kLeafStage = 256;   // leaves per block (leaves_per_block)
-constexpr uint32_t kSlotStage = 2048;  // staged slots per block
-
-// code of the member at `slot` from a staged copy of slots [slot0, slot0 + ns)
-template <typename KT>
-__device__ inline u128 member_code_lds(const KT* sk, uint32_t ns, uint32_t dims, const LeafRec& rec,
-                                       uint64_t slot, uint64_t slot0) {
-  u128 v = 0;
-  uint32_t at = 0;
-  const uint32_t t = (uint32_t)(slot - slot0);
-  for (uint32_t d = 0; d < dims; ++d) {
-    const uint32_t m = (rec.m >> (8 * d)) & 0xffu;
-    if (m == 0) continue;
-    const uint32_t q = sk[d * ns + t];
-    const uint64_t u = (uint64_t)((int64_t)q - (int64_t)rec.qref[d] + ((int64_t)1 << (m - 1)));
-    v |= (u128)u << at;
-    at += m;
-  }
-  return v;
-}
 
 // 64-bit forms for members whose code has at most 64 bits (the usual case)
 template <typename KT>
@@ -346,32 +329,64 @@ __device__ void pack_payload_body(const SetDesc& S, const DevParams* P, uint64_t
   __syncthreads();
   const uint64_t slot0 = s_rec[0].start;
   const uint64_t slot_end = (uint64_t)s_rec[nlb - 1].start + s_rec[nlb - 1].size;
-  for (uint64_t slot = slot0 + threadIdx.x; slot < slot_end; slot += kBlock) {
-    uint32_t a = 0, z = nlb - 1;  // last staged leaf starting at or before the slot
+  // each thread takes V consecutive slots (V-aligned slot indices): one
+  // 16-byte code load per axis, one leaf search, and LDS atomics that land on
+  // different words across the lanes
+  constexpr uint32_t V = 16 / sizeof(KT);
+  for (uint64_t gs = (slot0 & ~(uint64_t)(V - 1)) + (uint64_t)V * threadIdx.x; gs < slot_end;
+       gs += (uint64_t)V * kBlock) {
+    union {
+      uint4 v;
+      KT e[V];
+    } kk[3];
+#pragma unroll
+    for (uint32_t d = 0; d < 3; ++d) {
+      kk[d].v = make_uint4(0, 0, 0, 0);
+      if (d < dims) kk[d].v = *(const uint4*)(keys + (uint64_t)d * kst + gs);
+    }
+    const uint64_t pfirst = gs > slot0 ? gs : slot0;
+    uint32_t a = 0, z = nlb - 1;  // last staged leaf starting at or before pfirst
     while (a < z) {
       const uint32_t mid = (a + z + 1) >> 1;
-      if (s_rec[mid].start <= slot)
+      if (s_rec[mid].start <= pfirst)
         a = mid;
       else
         z = mid - 1;
     }
-    const LeafRec rec = s_rec[a];
-    const uint64_t j = slot - rec.start;
-    const uint32_t sm = sum_m(rec.m);
-    if (j == 0 || sm == 0) continue;  // the reference, or a leaf without payload
-    const uint64_t at = s_off[a] + (j - 1) * sm - wlo * 64;  // bit in the LDS copy
-    const uint32_t w = (uint32_t)(at >> 6), sh = (uint32_t)(at & 63);
-    if (sm <= 64) {
-      const uint64_t c = member_code64(keys, kst, dims, rec, slot);
-      atomicOr(&s_w[w], (unsigned long long)(c << sh));
-      if (sh + sm > 64) atomicOr(&s_w[w + 1], (unsigned long long)(c >> (64 - sh)));
-    } else {
-      const u128 c = member_code(keys, kst, dims, rec, slot) << sh;
-      atomicOr(&s_w[w], (unsigned long long)(uint64_t)c);
-      atomicOr(&s_w[w + 1], (unsigned long long)(uint64_t)(c >> 64));
-      if (sh + sm > 128) {
-        const u128 c3 = member_code(keys, kst, dims, rec, slot) >> (128 - sh);
-        atomicOr(&s_w[w + 2], (unsigned long long)(uint64_t)c3);
+#pragma unroll
+    for (uint32_t k = 0; k < V; ++k) {
+      const uint64_t slot = gs + k;
+      if (slot < slot0 || slot >= slot_end) continue;
+      while (a + 1 < nlb && s_rec[a + 1].start <= slot) ++a;
+      const LeafRec rec = s_rec[a];
+      const uint64_t j = slot - rec.start;
+      const uint32_t sm = sum_m(rec.m);
+      if (j == 0 || sm == 0) continue;  // the reference, or a leaf without payload
+      const uint64_t at = s_off[a] + (j - 1) * sm - wlo * 64;  // bit in the LDS copy
+      const uint32_t w = (uint32_t)(at >> 6), sh = (uint32_t)(at & 63);
+      if (sm <= 64) {
+        uint64_t c = 0;
+        uint32_t cat = 0;
+#pragma unroll
+        for (uint32_t d = 0; d < 3; ++d) {
+          if (d >= dims) break;
+          const uint32_t m = (rec.m >> (8 * d)) & 0xffu;
+          if (m == 0) continue;
+          const uint64_t u = (uint64_t)((int64_t)(uint32_t)kk[d].e[k] - (int64_t)rec.qref[d] +
+                                        ((int64_t)1 << (m - 1)));
+          c |= u << cat;
+          cat += m;
+        }
+        atomicOr(&s_w[w], (unsigned long long)(c << sh));
+        if (sh + sm > 64) atomicOr(&s_w[w + 1], (unsigned long long)(c >> (64 - sh)));
+      } else {
+        const u128 c = member_code(keys, kst, dims, rec, slot) << sh;
+        atomicOr(&s_w[w], (unsigned long long)(uint64_t)c);
+        atomicOr(&s_w[w + 1], (unsigned long long)(uint64_t)(c >> 64));
+        if (sh + sm > 128) {
+          const u128 c3 = member_code(keys, kst, dims, rec, slot) >> (128 - sh);
+          atomicOr(&s_w[w + 2], (unsigned long long)(uint64_t)c3);
+        }
       }
     }
   }
