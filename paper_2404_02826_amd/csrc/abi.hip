@@ -220,6 +220,13 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
       uint64_t max_nodes = 0, max_blocks = 0;
       for (uint32_t k = 0; k < D.gl; ++k) {
         const LevelShape sh = level_shape(n, k);
+        const int kind = level_kind(n, k);
+        if (kind == 2)
+          bp->lv_wave[k] = 1;
+        else if (kind == 1)
+          bp->lv_local[k] = 1;
+        else
+          bp->lv_global[k] = 1;
         lv[s].push_back(sh.nodes * sh.chunks);
         nd[s].push_back(sh.nodes);
         max_nodes = std::max(max_nodes, sh.nodes);

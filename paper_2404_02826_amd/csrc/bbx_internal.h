@@ -225,6 +225,22 @@ __host__ __device__ inline LevelShape level_shape(uint64_t n, uint32_t depth) {
   return sh;
 }
 
+// How a global level of a set runs.  Nodes of at most kWaveNode members: one
+// wavefront per node (k_level_wave).  Otherwise, nodes that each fit one
+// block (one chunk per node): one block per node (k_level_local).  Both find
+// the median and partition the node with no global histograms or chunk
+// tables.  Otherwise: global histograms over chunks.  Node sizes only shrink
+// with depth, so the global levels come first.
+constexpr uint64_t kWaveNode = 4096;
+enum { kLevelGlobal = 0, kLevelBlock = 1, kLevelWave = 2 };
+__host__ __device__ inline int level_kind(uint64_t n, uint32_t depth) {
+  if (((n + (1ull << depth) - 1) >> depth) <= kWaveNode) return kLevelWave;
+  return level_shape(n, depth).chunks == 1 ? kLevelBlock : kLevelGlobal;
+}
+__host__ __device__ inline bool level_is_local(uint64_t n, uint32_t depth) {
+  return level_kind(n, depth) != kLevelGlobal;
+}
+
 // Leaves per block of the leaf-aligned packing and unpacking kernels: at most
 // 2048 slots and 256 leaves per block.
 __host__ __device__ inline uint32_t leaves_per_block(uint32_t r) {
@@ -260,6 +276,37 @@ __device__ inline uint32_t wave_incl(uint32_t x) {
   x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);  // row_bcast:15
   x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);  // row_bcast:31
   return x;
+}
+
+// Orders the wavefront's LDS accesses around a phase boundary (no cross-wave
+// synchronization is needed: each wavefront owns its tile).
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline uint32_t umin32(uint32_t a, uint32_t b) { return a < b ? a : b; }
+__device__ inline uint32_t umax32(uint32_t a, uint32_t b) { return a > b ? a : b; }
+// wavefront minimum / maximum, uniform result
+__device__ inline uint32_t wave_min_dpp(uint32_t x) {
+  const int I = -1;  // identity of min (0xffffffff)
+  x = umin32(x, (uint32_t)__builtin_amdgcn_update_dpp(I, (int)x, 0x111, 0xf, 0xf, false));
+  x = umin32(x, (uint32_t)__builtin_amdgcn_update_dpp(I, (int)x, 0x112, 0xf, 0xf, false));
+  x = umin32(x, (uint32_t)__builtin_amdgcn_update_dpp(I, (int)x, 0x114, 0xf, 0xf, false));
+  x = umin32(x, (uint32_t)__builtin_amdgcn_update_dpp(I, (int)x, 0x118, 0xf, 0xf, false));
+  x = umin32(x, (uint32_t)__builtin_amdgcn_update_dpp(I, (int)x, 0x142, 0xa, 0xf, false));
+  x = umin32(x, (uint32_t)__builtin_amdgcn_update_dpp(I, (int)x, 0x143, 0xc, 0xf, false));
+  return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
+}
+__device__ inline uint32_t wave_max_dpp(uint32_t x) {
+  x = umax32(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false));
+  x = umax32(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false));
+  x = umax32(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false));
+  x = umax32(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false));
+  x = umax32(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false));
+  x = umax32(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false));
+  return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
 }
 
 // set bits of a wavefront mask in the lanes below this one
@@ -298,6 +345,9 @@ struct BatchPlan {
   uint64_t o_mm, o_qz, o_tile, o_big, o_pm, o_pp;
   uint64_t g_lv[kMaxDepth], g_nd[kMaxDepth];
   uint64_t o_lv[kMaxDepth], o_nd[kMaxDepth];
+  uint8_t lv_local[kMaxDepth];   // some set handles level k one block per node
+  uint8_t lv_global[kMaxDepth];  // some set handles level k with global histograms
+  uint8_t lv_wave[kMaxDepth];    // some set handles level k one wavefront per node
   uint64_t pre_entries;       // total u64 entries of the prefix buffer
 };
 

@@ -71,6 +71,7 @@ __global__ void __launch_bounds__(kBlock) k_pass_flags(uint32_t nsets, const Set
     const DevParams& P = params[s];
     if (P.status != BBX_OK) continue;
     for (uint32_t k = 0; k < S.gl && k < (uint32_t)kMaxDepth; ++k) {
+      if (level_is_local(S.n, k)) break;  // local levels form a suffix
       const uint32_t np = digit_plan(P.G[k % S.dims]).npass;
       for (uint32_t p = 0; p + 1 < np && p < 4; ++p) atomicOr(&pass_need[k * 4 + p], 1u);
     }
@@ -176,6 +177,7 @@ __global__ void __launch_bounds__(kBlock) k_hist_mid(uint32_t depth, uint32_t pa
     const SetDesc& S = sets[c.s];
     const DevParams* P = params + c.s;
     if (P->status != BBX_OK) continue;
+    if (level_is_local(S.n, depth)) continue;
     if (pass + 1 >= digit_plan(P->G[depth % S.dims]).npass) continue;
     const uint8_t* keys = keys0 + S.key_off;
     if (P->key16)
@@ -203,6 +205,7 @@ __global__ void __launch_bounds__(kBlock) k_select_mid(uint32_t depth, uint32_t 
     const SetDesc& S = sets[s];
     const DevParams* P = params + s;
     if (P->status != BBX_OK) continue;
+    if (level_is_local(S.n, depth)) continue;
     const DigitPlan pl = digit_plan(P->G[depth % S.dims]);
     if (pass + 1 >= pl.npass) continue;
     const uint64_t j = gn - pre[s];
@@ -249,6 +252,7 @@ __global__ void __launch_bounds__(kBlock) k_hist_root(uint32_t nsets, const uint
   const SetDesc& S = sets[c.s];
   const DevParams* P = params + c.s;
   if (P->status != BBX_OK) return;
+  if (level_is_local(S.n, 0)) return;
   const DigitPlan pl = digit_plan(P->G[0]);
   if (pl.npass < 2) return;
   if (S.n <= S.r) return;
@@ -320,6 +324,7 @@ __global__ void __launch_bounds__(kBlock) k_hist_last(uint32_t depth, uint32_t n
   const SetDesc& S = sets[c.s];
   const DevParams* P = params + c.s;
   if (P->status != BBX_OK) return;
+  if (level_is_local(S.n, depth)) return;
   __shared__ uint32_t lh[kBlock];
   const uint8_t* keys = keys0 + S.key_off;
   if (P->key16)
@@ -347,6 +352,7 @@ __global__ void __launch_bounds__(kBlock) k_select_last(uint32_t depth, uint32_t
     const SetDesc& S = sets[s];
     const DevParams* P = params + s;
     if (P->status != BBX_OK) continue;
+    if (level_is_local(S.n, depth)) continue;
     const DigitPlan pl = digit_plan(P->G[depth % S.dims]);
     const uint32_t pass = pl.npass - 1;
     const uint64_t j = gn - pre[s];
@@ -423,9 +429,9 @@ __global__ void __launch_bounds__(kBlock) k_select_last(uint32_t depth, uint32_t
 
 template <typename KT>
 __device__ void scatter_body(uint32_t depth, const SetDesc& S, DevParams* P, const LevelCtx& c,
-                             const NodeSel* sel, const uint32_t* chunk_base, const uint8_t* src,
-                             uint8_t* dst, const uint32_t* isrc, uint32_t* idst, uint32_t* hist,
-                             uint32_t* lhist) {
+                             uint32_t v, uint32_t jeq, uint32_t lt_run, uint32_t eq_run,
+                             const uint8_t* src, uint8_t* dst, const uint32_t* isrc, uint32_t* idst,
+                             uint32_t* hist, uint32_t* lhist) {
   static_assert(kBlock == 256, "four wavefronts per block");
   const uint64_t n = S.n, kst = S.kst;
   const uint32_t dims = S.dims, r = S.r;
@@ -459,14 +465,10 @@ __device__ void scatter_body(uint32_t depth, const SetDesc& S, DevParams* P, con
   const uint32_t half = sz >> 1;
   const uint32_t dn = (depth + 1) % dims;
   const DigitPlan pn = digit_plan(P->G[dn]);
-  const bool fuse = depth + 1 < S.gl && pn.npass >= 2;
+  const bool fuse = depth + 1 < S.gl && pn.npass >= 2 && !level_is_local(n, depth + 1);
   const uint32_t wn = pn.width[0], shn = pn.shift[0], maskn = (1u << wn) - 1;
   const bool cl = fuse && half > r, cr = fuse && (sz - half) > r;  // children that split again
   if (fuse) lhist[threadIdx.x] = lhist[kBlock + threadIdx.x] = 0;
-  const NodeSel ns = sel[j];
-  const uint32_t v = ns.v, jeq = ns.jeq;
-  uint32_t lt_run = chunk_base[c.lb * 2 + 0];
-  uint32_t eq_run = chunk_base[c.lb * 2 + 1];
   // per group, row and wavefront: (lt, eq) counts; double-buffered so that one
   // barrier per group suffices
   __shared__ __align__(16) uint32_t cnt[2][kRows][kBlock / 64][2];
@@ -550,15 +552,273 @@ __global__ void __launch_bounds__(kBlock) k_scatter(uint32_t depth, uint32_t nse
   const SetDesc& S = sets[c.s];
   DevParams* P = params + c.s;
   if (P->status != BBX_OK) return;
+  if (level_is_local(S.n, depth)) return;
   __shared__ uint32_t lhist[2 * kBlock];
   const uint32_t* isrc = S.perm ? isrc0 + S.idx_off : nullptr;
   uint32_t* idst = S.perm ? idst0 + S.idx_off : nullptr;
+  const NodeSel ns = (sel0 + S.sel_off)[c.lb / c.sh.chunks];
+  const uint32_t* cb = cb0 + S.cb_off + c.lb * 2;
   if (P->key16)
-    scatter_body<uint16_t>(depth, S, P, c, sel0 + S.sel_off, cb0 + S.cb_off, src0 + S.key_off,
+    scatter_body<uint16_t>(depth, S, P, c, ns.v, ns.jeq, cb[0], cb[1], src0 + S.key_off,
                            dst0 + S.key_off, isrc, idst, hist0 + S.hist_off, lhist);
   else
-    scatter_body<uint32_t>(depth, S, P, c, sel0 + S.sel_off, cb0 + S.cb_off, src0 + S.key_off,
+    scatter_body<uint32_t>(depth, S, P, c, ns.v, ns.jeq, cb[0], cb[1], src0 + S.key_off,
                            dst0 + S.key_off, isrc, idst, hist0 + S.hist_off, lhist);
+}
+
+// Median of one node's axis codes, inside one block: the node's code range,
+// then radix passes of at most 8 bits over the codes minus the minimum (the
+// re-reads of a node of at most a few tens of KB hit the cache).  Returns the
+// median code v and how many members equal to v precede it (they go left).
+template <typename KT>
+__device__ void local_median(const KT* axis, uint64_t A, uint64_t B, uint32_t rank, uint32_t* v_out,
+                             uint32_t* jeq_out, uint32_t* bins, uint32_t* red) {
+  const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint32_t lo = 0xffffffffu, hi = 0;
+  scan_codes(axis, A, B, [&](uint32_t q) {
+    lo = q < lo ? q : lo;
+    hi = q > hi ? q : hi;
+  });
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint32_t a = __shfl_xor(lo, o), b = __shfl_xor(hi, o);
+    lo = a < lo ? a : lo;
+    hi = b > hi ? b : hi;
+  }
+  if (lane == 0) red[wv] = lo, red[4 + wv] = hi;
+  __syncthreads();
+  const uint32_t mn = red[0] < red[1] ? (red[0] < red[2] ? (red[0] < red[3] ? red[0] : red[3])
+                                                          : (red[2] < red[3] ? red[2] : red[3]))
+                                      : (red[1] < red[2] ? (red[1] < red[3] ? red[1] : red[3])
+                                                          : (red[2] < red[3] ? red[2] : red[3]));
+  uint32_t mx = red[4];
+  for (int k = 5; k < 8; ++k) mx = red[k] > mx ? red[k] : mx;
+  const uint32_t Gs = bitlen32(mx - mn);
+  uint32_t prefix = 0;
+  if (Gs > 0) {
+    // widest digit first: the first pass sees every member, so it spreads
+    // them over up to 256 bins; later passes see only the members that
+    // match the prefix found so far
+    uint32_t used = 0;
+    while (used < Gs) {
+      const uint32_t w = Gs - used < 8 ? Gs - used : 8;
+      const uint32_t hs = Gs - used;
+      used += w;
+      const uint32_t sh = Gs - used, mask = (1u << w) - 1;
+      bins[threadIdx.x] = 0;
+      __syncthreads();
+      scan_codes(axis, A, B, [&](uint32_t q) {
+        const uint32_t k = q - mn;
+        if ((k >> hs) == prefix) atomicAdd(&bins[(k >> sh) & mask], 1u);
+      });
+      __syncthreads();
+      if (wv == 0) {  // one wavefront finds the bin holding the rank
+        uint32_t c[4], mine = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) c[k] = bins[lane * 4 + k], mine += c[k];
+        uint32_t cum = wave_incl(mine) - mine;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          if (cum <= rank && rank < cum + c[k]) red[8] = lane * 4 + k, red[9] = rank - cum;
+          cum += c[k];
+        }
+      }
+      __syncthreads();
+      prefix = (prefix << w) | red[8];
+      rank = red[9];
+      __syncthreads();  // red and bins are rewritten by the next pass
+    }
+  }
+  *v_out = mn + prefix;
+  *jeq_out = rank;
+}
+
+// A level whose nodes each fit one block: median and stable partition of
+// each node in one block, for every set whose level is local.
+__global__ void __launch_bounds__(kBlock) k_level_local(uint32_t depth, uint32_t nsets,
+                                                        const uint64_t* pre, const SetDesc* sets,
+                                                        DevParams* params, uint8_t* src0,
+                                                        uint8_t* dst0, uint32_t* isrc0,
+                                                        uint32_t* idst0, uint32_t* hist0) {
+  const LevelCtx c = level_ctx(nsets, pre, sets, depth);
+  const SetDesc& S = sets[c.s];
+  DevParams* P = params + c.s;
+  if (P->status != BBX_OK) return;
+  if (level_kind(S.n, depth) != kLevelBlock) return;
+  __shared__ uint32_t lhist[2 * kBlock];
+  __shared__ uint32_t red[16];
+  const uint32_t* isrc = S.perm ? isrc0 + S.idx_off : nullptr;
+  uint32_t* idst = S.perm ? idst0 + S.idx_off : nullptr;
+  uint64_t st, sz;
+  node_span(S.n, depth, c.lb, &st, &sz);
+  uint32_t v = 0, jeq = 0;
+  const uint32_t d = depth % S.dims;
+  const uint8_t* keys = src0 + S.key_off;
+  if (sz > S.r) {
+    if (P->key16)
+      local_median((const uint16_t*)keys + (uint64_t)d * S.kst, st, st + sz, (uint32_t)(sz >> 1), &v,
+                   &jeq, lhist, red);
+    else
+      local_median((const uint32_t*)keys + (uint64_t)d * S.kst, st, st + sz, (uint32_t)(sz >> 1), &v,
+                   &jeq, lhist, red);
+    __syncthreads();  // lhist is reused by the partition
+  }
+  if (P->key16)
+    scatter_body<uint16_t>(depth, S, P, c, v, jeq, 0, 0, src0 + S.key_off, dst0 + S.key_off, isrc,
+                           idst, hist0 + S.hist_off, lhist);
+  else
+    scatter_body<uint32_t>(depth, S, P, c, v, jeq, 0, 0, src0 + S.key_off, dst0 + S.key_off, isrc,
+                           idst, hist0 + S.hist_off, lhist);
+}
+
+// Median of a node's axis codes by one wavefront (nodes of at most kWaveNode
+// members): code range by DPP reductions, then radix passes of at most 8 bits
+// (widest first) over codes minus the minimum, in the wavefront's own bins.
+template <typename KT>
+__device__ void wave_median(const KT* axis, uint32_t sz, uint32_t rank, uint32_t* bins,
+                            uint32_t* v_out, uint32_t* jeq_out) {
+  const uint32_t lane = threadIdx.x & 63;
+  uint32_t lo = 0xffffffffu, hi = 0;
+  for (uint32_t e = lane; e < sz; e += 64) {
+    const uint32_t q = axis[e];
+    lo = umin32(lo, q);
+    hi = umax32(hi, q);
+  }
+  const uint32_t mn = wave_min_dpp(lo);
+  const uint32_t Gs = bitlen32(wave_max_dpp(hi) - mn);
+  uint32_t prefix = 0, used = 0;
+  while (used < Gs) {
+    const uint32_t w = Gs - used < 8 ? Gs - used : 8;
+    const uint32_t hs = Gs - used;
+    used += w;
+    const uint32_t sh = Gs - used, mask = (1u << w) - 1;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) bins[lane * 4 + k] = 0;
+    wave_sync();
+    for (uint32_t e = lane; e < sz; e += 64) {
+      const uint32_t k = axis[e] - mn;
+      if ((k >> hs) == prefix) atomicAdd(&bins[(k >> sh) & mask], 1u);
+    }
+    wave_sync();
+    uint32_t c[4], mine = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) c[k] = bins[lane * 4 + k], mine += c[k];
+    uint32_t cum = wave_incl(mine) - mine;
+    uint32_t fb = 0, fr = 0;
+    bool found = false;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (cum <= rank && rank < cum + c[k]) found = true, fb = lane * 4 + k, fr = rank - cum;
+      cum += c[k];
+    }
+    const uint64_t fm = __ballot(found);
+    const int fl = fm ? __ffsll((unsigned long long)fm) - 1 : 0;
+    prefix = (prefix << w) | (uint32_t)__builtin_amdgcn_readlane((int)fb, fl);
+    rank = (uint32_t)__builtin_amdgcn_readlane((int)fr, fl);
+    wave_sync();  // the bins are cleared by the next pass
+  }
+  *v_out = mn + prefix;
+  *jeq_out = rank;
+}
+
+// Stable partition of one node by one wavefront: members in storage order, 64
+// at a time; ballots give each member's rank among the members below / equal
+// to the median before it.
+template <typename KT>
+__device__ void wave_partition(const KT* s0, const KT* s1, const KT* s2, KT* d0, KT* d1, KT* d2,
+                               const uint32_t* is, uint32_t* id, uint32_t dims, uint32_t d,
+                               uint32_t sz, uint32_t v, uint32_t jeq, DevParams* P) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t half = sz >> 1;
+  uint32_t lt_run = 0, eq_run = 0;
+  for (uint32_t base = 0; base < sz; base += 256) {
+    uint32_t key[4][3];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint32_t p = base + 64 * u + lane;
+      const bool a = p < sz;
+      key[u][0] = a ? (uint32_t)s0[p] : 0u;
+      key[u][1] = (a && dims > 1) ? (uint32_t)s1[p] : 0u;
+      key[u][2] = (a && dims > 2) ? (uint32_t)s2[p] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint32_t p = base + 64 * u + lane;
+      const bool a = p < sz;
+      const uint32_t kd = pick3(key[u], d);
+      const bool lt = a && kd < v, eq = a && kd == v;
+      const uint64_t mlt = __ballot(lt), meq = __ballot(eq);
+      if (a) {
+        const uint32_t L = lt_run + lanes_below(mlt);
+        const uint32_t E = eq_run + lanes_below(meq);
+        const uint32_t lb = L + (E < jeq ? E : jeq);
+        const bool left = lt || (eq && E < jeq);
+        const uint32_t dest = left ? lb : half + (p - lb);
+        if (dest < sz) {
+          d0[dest] = (KT)key[u][0];
+          if (dims > 1) d1[dest] = (KT)key[u][1];
+          if (dims > 2) d2[dest] = (KT)key[u][2];
+          if (is) id[dest] = is[p];
+        } else {
+          P->status = BBX_EHIP;  // inconsistent counts: never expected
+        }
+      }
+      lt_run += (uint32_t)__popcll(mlt);
+      eq_run += (uint32_t)__popcll(meq);
+    }
+  }
+}
+
+template <typename KT>
+__device__ void level_wave_body(uint32_t depth, const SetDesc& S, DevParams* P, uint64_t j,
+                                const uint8_t* src, uint8_t* dst, const uint32_t* isrc,
+                                uint32_t* idst, uint32_t* bins) {
+  uint64_t st, sz64;
+  node_span(S.n, depth, j, &st, &sz64);
+  const uint32_t sz = (uint32_t)sz64;
+  const uint32_t dims = S.dims, d = depth % dims;
+  const uint64_t kst = S.kst;
+  const KT* s0 = (const KT*)src + st;
+  KT* d0 = (KT*)dst + st;
+  const uint32_t* is = isrc ? isrc + st : nullptr;
+  uint32_t* id = idst ? idst + st : nullptr;
+  if (sz <= S.r) {  // leaf: copy through
+    for (uint32_t p = threadIdx.x & 63; p < sz; p += 64) {
+      d0[p] = s0[p];
+      if (dims > 1) d0[kst + p] = s0[kst + p];
+      if (dims > 2) d0[2 * kst + p] = s0[2 * kst + p];
+      if (is) id[p] = is[p];
+    }
+    return;
+  }
+  uint32_t v, jeq;
+  wave_median(s0 + (uint64_t)d * kst, sz, sz >> 1, bins, &v, &jeq);
+  wave_partition(s0, s0 + kst, s0 + 2 * kst, d0, d0 + kst, d0 + 2 * kst, is, id, dims, d, sz, v,
+                 jeq, P);
+}
+
+// Levels whose nodes have at most kWaveNode members: one wavefront per node,
+// four nodes per block, no block barriers.
+__global__ void __launch_bounds__(kBlock) k_level_wave(uint32_t depth, uint32_t nsets,
+                                                       const uint64_t* pre, const SetDesc* sets,
+                                                       DevParams* params, uint8_t* src0,
+                                                       uint8_t* dst0, uint32_t* isrc0,
+                                                       uint32_t* idst0) {
+  __shared__ uint32_t bins[kBlock / 64][256];
+  const uint32_t wv = threadIdx.x >> 6;
+  const uint64_t gn = (uint64_t)blockIdx.x * (kBlock / 64) + wv;
+  if (gn >= pre[nsets]) return;  // whole wavefront
+  const uint32_t s = find_set(pre, nsets, gn);
+  const SetDesc& S = sets[s];
+  DevParams* P = params + s;
+  if (P->status != BBX_OK) return;
+  if (level_kind(S.n, depth) != kLevelWave) return;
+  const uint64_t j = gn - pre[s];
+  const uint32_t* isrc = S.perm ? isrc0 + S.idx_off : nullptr;
+  uint32_t* idst = S.perm ? idst0 + S.idx_off : nullptr;
+  if (P->key16)
+    level_wave_body<uint16_t>(depth, S, P, j, src0 + S.key_off, dst0 + S.key_off, isrc, idst, bins[wv]);
+  else
+    level_wave_body<uint32_t>(depth, S, P, j, src0 + S.key_off, dst0 + S.key_off, isrc, idst, bins[wv]);
 }
 
 // blocks of a select launch: one wavefront per node up to 8192 blocks, then striding
@@ -576,6 +836,14 @@ hipError_t launch_levels(const BatchPlan& bp, const Ws& w, hipStream_t s) {
     const uint64_t* plv = w.pre + bp.o_lv[k];
     const uint64_t* pnd = w.pre + bp.o_nd[k];
     const int cur = k & 1;
+    if (bp.lv_local[k])
+      BBX_LAUNCH("level_local", k_level_local, bp.g_lv[k], kBlock, 0, s, k, bp.nsets, plv, w.sets,
+                 w.params, w.keys[cur], w.keys[cur ^ 1], w.idx[cur], w.idx[cur ^ 1], w.hist);
+    if (bp.lv_wave[k])
+      BBX_LAUNCH("level_wave", k_level_wave, (bp.g_nd[k] + kBlock / 64 - 1) / (kBlock / 64), kBlock,
+                 0, s, k, bp.nsets, pnd, w.sets, w.params, w.keys[cur], w.keys[cur ^ 1], w.idx[cur],
+                 w.idx[cur ^ 1]);
+    if (!bp.lv_global[k]) continue;
     if (k == 0)
       BBX_LAUNCH("level_hist_mid", k_hist_root, bp.g_lv[0], kBlock, 0, s, bp.nsets, plv, w.sets,
                  w.params, w.keys[0], w.hist);

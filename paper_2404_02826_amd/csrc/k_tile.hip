@@ -56,37 +56,6 @@ __device__ inline uint64_t sqdist3(const uint32_t* q, const uint32_t* C, uint32_
   return s;
 }
 
-// Orders the wavefront's LDS accesses around a phase boundary (no cross-wave
-// synchronization is needed: each wavefront owns its tile).
-__device__ inline void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-__device__ inline uint32_t umin32(uint32_t a, uint32_t b) { return a < b ? a : b; }
-__device__ inline uint32_t umax32(uint32_t a, uint32_t b) { return a > b ? a : b; }
-// wavefront minimum / maximum, uniform result
-__device__ inline uint32_t wave_min_dpp(uint32_t x) {
-  const int I = -1;  // identity of min (0xffffffff)
-  x = umin32(x, (uint32_t)__builtin_amdgcn_update_dpp(I, (int)x, 0x111, 0xf, 0xf, false));
-  x = umin32(x, (uint32_t)__builtin_amdgcn_update_dpp(I, (int)x, 0x112, 0xf, 0xf, false));
-  x = umin32(x, (uint32_t)__builtin_amdgcn_update_dpp(I, (int)x, 0x114, 0xf, 0xf, false));
-  x = umin32(x, (uint32_t)__builtin_amdgcn_update_dpp(I, (int)x, 0x118, 0xf, 0xf, false));
-  x = umin32(x, (uint32_t)__builtin_amdgcn_update_dpp(I, (int)x, 0x142, 0xa, 0xf, false));
-  x = umin32(x, (uint32_t)__builtin_amdgcn_update_dpp(I, (int)x, 0x143, 0xc, 0xf, false));
-  return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
-}
-__device__ inline uint32_t wave_max_dpp(uint32_t x) {
-  x = umax32(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false));
-  x = umax32(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false));
-  x = umax32(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false));
-  x = umax32(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false));
-  x = umax32(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false));
-  x = umax32(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false));
-  return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
-}
-
 // LDS of one tile.  KL holds codes minus the tile's per-axis minimum: 16 bits
 // for every tile whose spans fit (the first pass), 32 bits for the rest (a
 // second pass over the tiles the first one deferred).  Source indices only
