@@ -678,10 +678,20 @@ __device__ void wave_median(const KT* axis, uint32_t sz, uint32_t rank, uint32_t
                             uint32_t* v_out, uint32_t* jeq_out) {
   const uint32_t lane = threadIdx.x & 63;
   uint32_t lo = 0xffffffffu, hi = 0;
-  for (uint32_t e = lane; e < sz; e += 64) {
-    const uint32_t q = axis[e];
-    lo = umin32(lo, q);
-    hi = umax32(hi, q);
+  for (uint32_t b = 0; b < sz; b += 512) {  // 8 loads in flight per lane
+    uint32_t q[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const uint32_t e = b + 64 * u + lane;
+      q[u] = e < sz ? (uint32_t)axis[e] : 0xffffffffu;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (b + 64 * u + lane < sz) {
+        lo = umin32(lo, q[u]);
+        hi = umax32(hi, q[u]);
+      }
+    }
   }
   const uint32_t mn = wave_min_dpp(lo);
   const uint32_t Gs = bitlen32(wave_max_dpp(hi) - mn);
@@ -694,9 +704,18 @@ __device__ void wave_median(const KT* axis, uint32_t sz, uint32_t rank, uint32_t
 #pragma unroll
     for (int k = 0; k < 4; ++k) bins[lane * 4 + k] = 0;
     wave_sync();
-    for (uint32_t e = lane; e < sz; e += 64) {
-      const uint32_t k = axis[e] - mn;
-      if ((k >> hs) == prefix) atomicAdd(&bins[(k >> sh) & mask], 1u);
+    for (uint32_t b = 0; b < sz; b += 512) {
+      uint32_t q[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const uint32_t e = b + 64 * u + lane;
+        q[u] = e < sz ? (uint32_t)axis[e] : 0u;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const uint32_t k = q[u] - mn;
+        if (b + 64 * u + lane < sz && (k >> hs) == prefix) atomicAdd(&bins[(k >> sh) & mask], 1u);
+      }
     }
     wave_sync();
     uint32_t c[4], mine = 0;
