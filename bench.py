@@ -57,6 +57,8 @@ def kernel_bytes_per_particle(name, key_bytes, in_bytes, stream_bytes_pp):
         "level_hist_mid": key_bytes,
         "level_hist_last": key_bytes,
         "level_scatter": 2 * kb,
+        "level_local": 2 * kb,
+        "level_wave": 2 * kb,
         "tile": 2 * kb,
         "pack_payload": kb + stream_bytes_pp,
         "unpack": stream_bytes_pp + in_bytes,
@@ -111,6 +113,40 @@ def measured_traffic(kernel):
     if hashlib.sha256(open(src, "rb").read()).hexdigest() != m_f.group(2):
         return None
     return int(m_b.group(1))
+
+
+def _level_shape_chunks(n, depth):
+    """Chunks per node of a global level (mirrors the library's level shape:
+    about 4096 blocks per level, chunks of whole 2048-element groups)."""
+    nodes = 1 << depth
+    maxsz = (n + nodes - 1) >> depth
+    cpn = max(1, (4096 + nodes - 1) // nodes)
+    elems = (maxsz + cpn - 1) // cpn
+    groups = max(1, (elems + 2047) // 2048)
+    chunk = groups * 2048
+    return max(1, (maxsz + chunk - 1) // chunk)
+
+
+def _level_kind(n, depth):
+    """0: global histograms, 1: one block per node, 2: one wavefront per node."""
+    if ((n + (1 << depth) - 1) >> depth) <= 4096:
+        return 2
+    return 1 if _level_shape_chunks(n, depth) == 1 else 0
+
+
+def _global_levels(n, r, tile):
+    """Levels above the on-chip stage (tile or large-leaf stage)."""
+    tile = tile or 512
+    if n == 0:
+        return 0
+    k = 0
+    if r < tile:
+        while ((n + (1 << k) - 1) >> k) > tile:
+            k += 1
+        return k
+    while (n >> k) > r:
+        k += 1
+    return k if ((n + (1 << k) - 1) >> k) <= r else k + 1
 
 
 def _gen_batch_set(job):
@@ -236,10 +272,20 @@ def bench_batch(args):
         bc.launch()
         torch.cuda.synchronize()
     dname, (dcount, dms) = max(prof.items(), key=lambda kv: kv[1][1])
-    bpp = kernel_bytes_per_particle(dname, 2, 12, S_tot / n_tot)
+    # particles a kernel touches per job: level kernels see each set once per
+    # global level of their kind (the library's launch plan), the others once
+    kinds = {"level_scatter": 0, "level_local": 1, "level_wave": 2}
+    if dname in kinds:
+        touched = sum(int(sizes[i]) * sum(1 for k in range(_global_levels(int(sizes[i]), tuned.leaf_sizes[i], tuned.tile))
+                                          if _level_kind(int(sizes[i]), k) == kinds[dname])
+                      for i in range(nsets))
+        bpp = 12.0
+    else:
+        touched = n_tot
+        bpp = kernel_bytes_per_particle(dname, 2, 12, S_tot / n_tot)
     roofline = None
-    if bpp is not None:
-        per_launch = bpp * n_tot / dcount
+    if bpp is not None and touched > 0:
+        per_launch = bpp * touched / dcount
         avg_ms = dms / dcount
         achieved = per_launch / (avg_ms * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
