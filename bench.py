@@ -136,7 +136,7 @@ def _level_kind(n, depth):
 
 def _global_levels(n, r, tile):
     """Levels above the on-chip stage (tile or large-leaf stage)."""
-    tile = tile or 512
+    tile = tile or 256
     if n == 0:
         return 0
     k = 0
@@ -466,7 +466,8 @@ def main():
                     choices=sorted(WORKLOADS) + ["batch-4096-f32", "served", "copy-1GiB"])
     ap.add_argument("--leaf-size", type=int, default=32,
                     help="leaf size r (batch workload: 0 = autotuned per set)")
-    ap.add_argument("--tile", type=int, default=0, help="batch workload: 0 = autotuned")
+    ap.add_argument("--tile", type=int, default=0,
+                    help="tile capacity 256 or 512 (0: library default; batch workload: autotuned)")
     ap.add_argument("--nsets", type=int, default=4096)
     ap.add_argument("--requests", type=int, default=2000, help="served workload: requests")
     ap.add_argument("--qps", type=float, default=400.0, help="served workload: arrival rate")
@@ -502,7 +503,7 @@ def main():
     torch.cuda.synchronize()
     B_in = x.numel() * x.element_size()
 
-    comp = bbx.Compressor(n, 3, x.dtype, leaf_size=args.leaf_size)
+    comp = bbx.Compressor(n, 3, x.dtype, leaf_size=args.leaf_size, tile=args.tile)
     s = comp(x, xi)
     S = s.numel()
     header = s[:128].cpu().numpy().tobytes()
@@ -583,7 +584,7 @@ def main():
     # ---- error bound on the measured output (sampled slots)
     perm_check = None
     try:
-        pc = bbx.Compressor(n, 3, x.dtype, leaf_size=args.leaf_size, want_perm=True)
+        pc = bbx.Compressor(n, 3, x.dtype, leaf_size=args.leaf_size, tile=args.tile, want_perm=True)
         s2 = pc(x, xi)
         assert s2.numel() == S
         perm = pc.perm[:n].long()

@@ -81,7 +81,7 @@ typedef struct {
   uint32_t leaf_size;     /* r >= 1 */
   uint32_t eb_mode;       /* bbx_eb_mode */
   uint32_t layout;        /* bbx_layout of the input positions */
-  uint32_t tile_override; /* 0 (= 512), 256 or 512 */
+  uint32_t tile_override; /* 0 (= 256), 256 or 512 */
 } bbx_params;
 
 /* Worst-case stream size in bytes for n particles of the given type. */

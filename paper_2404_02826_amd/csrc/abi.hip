@@ -170,7 +170,7 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
                        std::vector<uint64_t>* pre, WsLayout* lay) {
   memset(bp, 0, sizeof(*bp));
   bp->nsets = nsets;
-  bp->tile = in[0].prm.tile_override ? in[0].prm.tile_override : 512;
+  bp->tile = in[0].prm.tile_override ? in[0].prm.tile_override : 256;
   descs->assign(nsets, SetDesc());
   uint64_t key_bytes = 0, idx_n = 0, hist_n = 0, sel_n = 0, rows_n = 0, leaves_n = 0, parts = 0;
   std::vector<uint64_t> mm(nsets), qz(nsets), tl(nsets), bg(nsets), pm(nsets), pp(nsets);
