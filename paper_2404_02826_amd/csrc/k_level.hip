@@ -117,6 +117,16 @@ __device__ inline void scan_codes(const KT* axis, uint64_t A, uint64_t B, F&& f)
       uint4 v;
       KT e[V];
     } u[U];
+    if (W >= A && W + STEP <= B) {  // interior step: no bounds checks
+      const uint4* a = (const uint4*)(axis + W) + threadIdx.x;
+#pragma unroll
+      for (uint32_t i = 0; i < U; ++i) u[i].v = a[i * kBlock];
+#pragma unroll
+      for (uint32_t i = 0; i < U; ++i)
+#pragma unroll
+        for (uint32_t k = 0; k < V; ++k) f((uint32_t)u[i].e[k]);
+      continue;
+    }
 #pragma unroll
     for (uint32_t i = 0; i < U; ++i) {
       const uint64_t e0 = W + ((uint64_t)i * kBlock + threadIdx.x) * V;
@@ -297,10 +307,8 @@ __device__ void hist_last_body(uint32_t depth, const SetDesc& S, const DevParams
   uint32_t below = 0;
   scan_codes(q, A, B, [&](uint32_t v) {
     const uint32_t hi = v >> hs;
-    if (hi == prefix)
-      atomicAdd(&lh[(v >> sh) & mask], 1u);
-    else if (hi < prefix)
-      ++below;
+    below += hi < prefix ? 1u : 0u;
+    if (hi == prefix) atomicAdd(&lh[(v >> sh) & mask], 1u);
   });
   __syncthreads();
   const uint32_t cnt = threadIdx.x < nb ? lh[threadIdx.x] : 0u;
@@ -427,6 +435,98 @@ __global__ void __launch_bounds__(kBlock) k_select_last(uint32_t depth, uint32_t
   }
 }
 
+// One streaming group of a stable partition: wavefront w of the block takes
+// the 512 consecutive elements [g + 512 w, g + 512 w + 512) as 8 rows of 64.
+// Codes are handled in axis order (split axis, next axis, third axis), so the
+// split code is always k0 and the next level's code k1: no per-element axis
+// selection.  Ranks below / equal to the median come from ballots within the
+// wavefront, a running count across its rows, and one exchange of wavefront
+// totals per group (double-buffered: one barrier per group).
+template <typename KT, int NA, bool FULL>
+__device__ __forceinline__ void scatter_group(uint32_t g, uint32_t end, const KT* A0, const KT* A1,
+                                     const KT* A2, KT* B0, KT* B1, KT* B2, const uint32_t* is,
+                                     uint32_t* id, uint32_t sz, uint32_t v, uint32_t jeq,
+                                     uint32_t& lt_run, uint32_t& eq_run, bool cl, bool cr,
+                                     uint32_t shn, uint32_t maskn, uint32_t* lhist,
+                                     uint32_t (*cnt)[kBlock / 64][2], int buf, DevParams* P) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t wv = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const uint32_t base = g + wv * (kGroup / (kBlock / 64));
+  const uint32_t half = sz >> 1;
+  uint32_t k0[kRows], k1[kRows], k2[kRows];
+  {
+    // one 64-bit address per axis; the rows are immediate offsets from it
+    const KT* a0 = A0 + base + lane;
+    const KT* a1 = A1 + base + lane;
+    const KT* a2 = A2 + base + lane;
+#pragma unroll
+    for (int i = 0; i < kRows; ++i) {
+      const bool act = FULL || base + 64u * i + lane < end;
+      k0[i] = act ? (uint32_t)a0[64 * i] : 0u;
+      k1[i] = (NA > 1 && act) ? (uint32_t)a1[64 * i] : 0u;
+      k2[i] = (NA > 2 && act) ? (uint32_t)a2[64 * i] : 0u;
+    }
+  }
+  uint32_t rl[kRows], re[kRows], wl = 0, we = 0;
+#pragma unroll
+  for (int i = 0; i < kRows; ++i) {
+    const bool act = FULL || base + 64u * i + lane < end;
+    const uint64_t mlt = __ballot(act && k0[i] < v);
+    const uint64_t meq = __ballot(act && k0[i] == v);
+    rl[i] = wl + lanes_below(mlt);
+    re[i] = we + lanes_below(meq);
+    wl += popc64(mlt);
+    we += popc64(meq);
+  }
+  if (lane == 0) cnt[buf][wv][0] = wl, cnt[buf][wv][1] = we;
+  __syncthreads();
+  const uint4 X = *(const uint4*)&cnt[buf][0][0];  // wavefronts 0, 1
+  const uint4 Y = *(const uint4*)&cnt[buf][2][0];  // wavefronts 2, 3
+  const uint32_t bl = lt_run + (wv > 0 ? X.x : 0u) + (wv > 1 ? X.z : 0u) + (wv > 2 ? Y.x : 0u);
+  const uint32_t be = eq_run + (wv > 0 ? X.y : 0u) + (wv > 1 ? X.w : 0u) + (wv > 2 ? Y.y : 0u);
+  lt_run += X.x + X.z + Y.x + Y.z;
+  eq_run += X.y + X.w + Y.y + Y.w;
+#pragma unroll
+  for (int i = 0; i < kRows; ++i) {
+    const uint32_t p = base + 64u * i + lane;
+    if (!FULL && p >= end) continue;
+    const bool lt = k0[i] < v, eq = k0[i] == v;
+    const uint32_t L = bl + rl[i], E = be + re[i];
+    const uint32_t lb = L + umin32(E, jeq);
+    const bool left = lt || (eq && E < jeq);
+    const uint32_t dest = left ? lb : half + (p - lb);
+    if (dest < sz) {
+      B0[dest] = (KT)k0[i];
+      if (NA > 1) B1[dest] = (KT)k1[i];
+      if (NA > 2) B2[dest] = (KT)k2[i];
+      if (is) id[dest] = is[p];
+      if (left ? cl : cr)
+        atomicAdd(&lhist[(left ? 0u : (uint32_t)kBlock) + (((NA > 1 ? k1[i] : k0[i]) >> shn) & maskn)],
+                  1u);
+    } else {
+      P->status = BBX_EHIP;  // inconsistent counts: never expected
+    }
+  }
+}
+
+template <typename KT, int NA>
+__device__ __forceinline__ void scatter_range(uint32_t beg, uint32_t end, const KT* A0, const KT* A1, const KT* A2,
+                              KT* B0, KT* B1, KT* B2, const uint32_t* is, uint32_t* id,
+                              uint32_t sz, uint32_t v, uint32_t jeq, uint32_t lt_run,
+                              uint32_t eq_run, bool cl, bool cr, uint32_t shn, uint32_t maskn,
+                              uint32_t* lhist, DevParams* P) {
+  __shared__ __align__(16) uint32_t cnt[2][kBlock / 64][2];
+  int buf = 0;
+  for (uint32_t g = beg; g < end; g += kGroup, buf ^= 1) {
+    if (g + kGroup <= end)
+      scatter_group<KT, NA, true>(g, end, A0, A1, A2, B0, B1, B2, is, id, sz, v, jeq, lt_run,
+                                  eq_run, cl, cr, shn, maskn, lhist, cnt, buf, P);
+    else
+      scatter_group<KT, NA, false>(g, end, A0, A1, A2, B0, B1, B2, is, id, sz, v, jeq, lt_run,
+                                   eq_run, cl, cr, shn, maskn, lhist, cnt, buf, P);
+  }
+}
+
 template <typename KT>
 __device__ void scatter_body(uint32_t depth, const SetDesc& S, DevParams* P, const LevelCtx& c,
                              uint32_t v, uint32_t jeq, uint32_t lt_run, uint32_t eq_run,
@@ -444,19 +544,15 @@ __device__ void scatter_body(uint32_t depth, const SetDesc& S, DevParams* P, con
   // positions inside the node fit 32 bits (n < 2^32)
   const uint32_t sz = (uint32_t)sz64, beg = (uint32_t)beg64;
   const uint32_t end = (uint32_t)(beg64 + c.sh.chunk_elems < sz64 ? beg64 + c.sh.chunk_elems : sz64);
-  const KT* s0 = (const KT*)src + st;
-  const KT* s1 = s0 + kst;
-  const KT* s2 = s1 + kst;
-  KT* d0 = (KT*)dst + st;
-  KT* d1 = d0 + kst;
-  KT* d2 = d1 + kst;
   const uint32_t* is = isrc ? isrc + st : nullptr;
   uint32_t* id = idst ? idst + st : nullptr;
   if (sz <= r) {  // leaf: copy through
+    const KT* s0 = (const KT*)src + st;
+    KT* d0 = (KT*)dst + st;
     for (uint32_t p = beg + threadIdx.x; p < end; p += blockDim.x) {
       d0[p] = s0[p];
-      if (dims > 1) d1[p] = s1[p];
-      if (dims > 2) d2[p] = s2[p];
+      if (dims > 1) d0[kst + p] = s0[kst + p];
+      if (dims > 2) d0[2 * kst + p] = s0[2 * kst + p];
       if (is) id[p] = is[p];
     }
     return;
@@ -469,70 +565,20 @@ __device__ void scatter_body(uint32_t depth, const SetDesc& S, DevParams* P, con
   const uint32_t wn = pn.width[0], shn = pn.shift[0], maskn = (1u << wn) - 1;
   const bool cl = fuse && half > r, cr = fuse && (sz - half) > r;  // children that split again
   if (fuse) lhist[threadIdx.x] = lhist[kBlock + threadIdx.x] = 0;
-  // per group, row and wavefront: (lt, eq) counts; double-buffered so that one
-  // barrier per group suffices
-  __shared__ __align__(16) uint32_t cnt[2][kRows][kBlock / 64][2];
-  const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  int buf = 0;
-  for (uint32_t g = beg; g < end; g += kGroup, buf ^= 1) {
-    uint32_t key[kRows][3];
-#pragma unroll
-    for (int i = 0; i < kRows; ++i) {
-      const uint32_t p = g + (uint32_t)i * kBlock + threadIdx.x;
-      const bool active = p < end;
-      key[i][0] = active ? (uint32_t)s0[p] : 0u;
-      key[i][1] = (active && dims > 1) ? (uint32_t)s1[p] : 0u;
-      key[i][2] = (active && dims > 2) ? (uint32_t)s2[p] : 0u;
-    }
-    uint32_t blt[kRows], beq[kRows];
-#pragma unroll
-    for (int i = 0; i < kRows; ++i) {
-      const uint32_t p = g + (uint32_t)i * kBlock + threadIdx.x;
-      const bool active = p < end;
-      const uint32_t kd = pick3(key[i], d);
-      const uint64_t mlt = __ballot(active && kd < v);
-      const uint64_t meq = __ballot(active && kd == v);
-      blt[i] = lanes_below(mlt);
-      beq[i] = lanes_below(meq);
-      if (lane == 0) {
-        cnt[buf][i][wv][0] = (uint32_t)__popcll(mlt);
-        cnt[buf][i][wv][1] = (uint32_t)__popcll(meq);
-      }
-    }
-    __syncthreads();
-    uint32_t off_l = 0, off_e = 0;  // elements of this group before row i
-#pragma unroll
-    for (int i = 0; i < kRows; ++i) {
-      const uint4 A = *(const uint4*)&cnt[buf][i][0][0];  // waves 0, 1
-      const uint4 B = *(const uint4*)&cnt[buf][i][2][0];  // waves 2, 3
-      const uint32_t bl = (wv > 0 ? A.x : 0u) + (wv > 1 ? A.z : 0u) + (wv > 2 ? B.x : 0u);
-      const uint32_t be = (wv > 0 ? A.y : 0u) + (wv > 1 ? A.w : 0u) + (wv > 2 ? B.y : 0u);
-      const uint32_t p = g + (uint32_t)i * kBlock + threadIdx.x;
-      if (p < end) {
-        const uint32_t kd = pick3(key[i], d);
-        const bool lt = kd < v, eq = kd == v;
-        const uint32_t L = lt_run + off_l + bl + blt[i];
-        const uint32_t E = eq_run + off_e + be + beq[i];
-        const uint32_t lb = L + (E < jeq ? E : jeq);
-        const bool left = lt || (eq && E < jeq);
-        const uint32_t dest = left ? lb : half + (p - lb);
-        if (dest < sz) {
-          d0[dest] = (KT)key[i][0];
-          if (dims > 1) d1[dest] = (KT)key[i][1];
-          if (dims > 2) d2[dest] = (KT)key[i][2];
-          if (is) id[dest] = is[p];
-          if (left ? cl : cr)
-            atomicAdd(&lhist[(left ? 0u : (uint32_t)kBlock) + ((pick3(key[i], dn) >> shn) & maskn)], 1u);
-        } else {
-          P->status = BBX_EHIP;  // inconsistent counts: never expected
-        }
-      }
-      off_l += A.x + A.z + B.x + B.z;
-      off_e += A.y + A.w + B.y + B.w;
-    }
-    lt_run += off_l;
-    eq_run += off_e;
-  }
+  // axis order: split axis, next axis, third axis
+  const uint32_t a1 = dims > 1 ? dn : d, a2 = dims > 2 ? (d + 2) % dims : d;
+  const KT* A0 = (const KT*)src + st + (uint64_t)d * kst;
+  const KT* A1 = (const KT*)src + st + (uint64_t)a1 * kst;
+  const KT* A2 = (const KT*)src + st + (uint64_t)a2 * kst;
+  KT* B0 = (KT*)dst + st + (uint64_t)d * kst;
+  KT* B1 = (KT*)dst + st + (uint64_t)a1 * kst;
+  KT* B2 = (KT*)dst + st + (uint64_t)a2 * kst;
+  if (dims == 3)
+    scatter_range<KT, 3>(beg, end, A0, A1, A2, B0, B1, B2, is, id, sz, v, jeq, lt_run, eq_run, cl,
+                         cr, shn, maskn, lhist, P);
+  else  // fewer axes: the missing ones repeat the split axis (same value, same slot)
+    scatter_range<KT, 3>(beg, end, A0, A1, A0, B0, B1, B0, is, id, sz, v, jeq, lt_run, eq_run, cl,
+                         cr, shn, maskn, lhist, P);
   if (fuse) {
     __syncthreads();
     for (uint32_t child = 0; child < 2; ++child) {
@@ -673,23 +719,34 @@ __global__ void __launch_bounds__(kBlock) k_level_local(uint32_t depth, uint32_t
 // Median of a node's axis codes by one wavefront (nodes of at most kWaveNode
 // members): code range by DPP reductions, then radix passes of at most 8 bits
 // (widest first) over codes minus the minimum, in the wavefront's own bins.
+// Median of a node's axis codes by one wavefront (nodes of at most kWaveNode
+// members): code range by DPP reductions, then radix passes of at most 8 bits
+// (widest first) over codes minus the minimum, in the wavefront's own bins.
 template <typename KT>
 __device__ void wave_median(const KT* axis, uint32_t sz, uint32_t rank, uint32_t* bins,
                             uint32_t* v_out, uint32_t* jeq_out) {
   const uint32_t lane = threadIdx.x & 63;
+  const KT* al = axis + lane;
   uint32_t lo = 0xffffffffu, hi = 0;
   for (uint32_t b = 0; b < sz; b += 512) {  // 8 loads in flight per lane
     uint32_t q[8];
+    if (b + 512 <= sz) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const uint32_t e = b + 64 * u + lane;
-      q[u] = e < sz ? (uint32_t)axis[e] : 0xffffffffu;
-    }
+      for (int u = 0; u < 8; ++u) q[u] = (uint32_t)al[b + 64 * u];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      if (b + 64 * u + lane < sz) {
-        lo = umin32(lo, q[u]);
-        hi = umax32(hi, q[u]);
+      for (int u = 0; u < 8; ++u) lo = umin32(lo, q[u]), hi = umax32(hi, q[u]);
+    } else {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const uint32_t e = b + 64 * u + lane;
+        q[u] = e < sz ? (uint32_t)axis[e] : 0xffffffffu;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (b + 64 * u + lane < sz) {
+          lo = umin32(lo, q[u]);
+          hi = umax32(hi, q[u]);
+        }
       }
     }
   }
@@ -706,15 +763,22 @@ __device__ void wave_median(const KT* axis, uint32_t sz, uint32_t rank, uint32_t
     wave_sync();
     for (uint32_t b = 0; b < sz; b += 512) {
       uint32_t q[8];
+      const bool full = b + 512 <= sz;
+      if (full) {
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const uint32_t e = b + 64 * u + lane;
-        q[u] = e < sz ? (uint32_t)axis[e] : 0u;
+        for (int u = 0; u < 8; ++u) q[u] = (uint32_t)al[b + 64 * u];
+      } else {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const uint32_t e = b + 64 * u + lane;
+          q[u] = e < sz ? (uint32_t)axis[e] : 0u;
+        }
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const uint32_t k = q[u] - mn;
-        if (b + 64 * u + lane < sz && (k >> hs) == prefix) atomicAdd(&bins[(k >> sh) & mask], 1u);
+        if ((full || b + 64 * u + lane < sz) && (k >> hs) == prefix)
+          atomicAdd(&bins[(k >> sh) & mask], 1u);
       }
     }
     wave_sync();
@@ -739,51 +803,76 @@ __device__ void wave_median(const KT* axis, uint32_t sz, uint32_t rank, uint32_t
   *jeq_out = rank;
 }
 
-// Stable partition of one node by one wavefront: members in storage order, 64
-// at a time; ballots give each member's rank among the members below / equal
-// to the median before it.
-template <typename KT>
-__device__ void wave_partition(const KT* s0, const KT* s1, const KT* s2, KT* d0, KT* d1, KT* d2,
-                               const uint32_t* is, uint32_t* id, uint32_t dims, uint32_t d,
-                               uint32_t sz, uint32_t v, uint32_t jeq, DevParams* P) {
+// 512 members of a node by one wavefront (8 rows of 64), codes in axis order
+// (split axis first); ballots give each member's rank among the members
+// below / equal to the median before it.
+template <typename KT, bool FULL>
+__device__ __forceinline__ void wave_part_rows(uint32_t base, uint32_t sz, const KT* A0,
+                                               const KT* A1, const KT* A2, KT* B0, KT* B1, KT* B2,
+                                               const uint32_t* is, uint32_t* id, uint32_t v,
+                                               uint32_t jeq, uint32_t& lt_run, uint32_t& eq_run,
+                                               DevParams* P) {
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t half = sz >> 1;
-  uint32_t lt_run = 0, eq_run = 0;
-  for (uint32_t base = 0; base < sz; base += 256) {
-    uint32_t key[4][3];
+  uint32_t k0[8], k1[8], k2[8];
+  {
+    const KT* a0 = A0 + base + lane;
+    const KT* a1 = A1 + base + lane;
+    const KT* a2 = A2 + base + lane;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const uint32_t p = base + 64 * u + lane;
-      const bool a = p < sz;
-      key[u][0] = a ? (uint32_t)s0[p] : 0u;
-      key[u][1] = (a && dims > 1) ? (uint32_t)s1[p] : 0u;
-      key[u][2] = (a && dims > 2) ? (uint32_t)s2[p] : 0u;
+    for (int i = 0; i < 8; ++i) {
+      const bool act = FULL || base + 64u * i + lane < sz;
+      k0[i] = act ? (uint32_t)a0[64 * i] : 0u;
+      k1[i] = act ? (uint32_t)a1[64 * i] : 0u;
+      k2[i] = act ? (uint32_t)a2[64 * i] : 0u;
     }
+  }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const uint32_t p = base + 64 * u + lane;
-      const bool a = p < sz;
-      const uint32_t kd = pick3(key[u], d);
-      const bool lt = a && kd < v, eq = a && kd == v;
-      const uint64_t mlt = __ballot(lt), meq = __ballot(eq);
-      if (a) {
-        const uint32_t L = lt_run + lanes_below(mlt);
-        const uint32_t E = eq_run + lanes_below(meq);
-        const uint32_t lb = L + (E < jeq ? E : jeq);
-        const bool left = lt || (eq && E < jeq);
-        const uint32_t dest = left ? lb : half + (p - lb);
-        if (dest < sz) {
-          d0[dest] = (KT)key[u][0];
-          if (dims > 1) d1[dest] = (KT)key[u][1];
-          if (dims > 2) d2[dest] = (KT)key[u][2];
-          if (is) id[dest] = is[p];
-        } else {
-          P->status = BBX_EHIP;  // inconsistent counts: never expected
-        }
+  for (int i = 0; i < 8; ++i) {
+    const uint32_t p = base + 64u * i + lane;
+    const bool act = FULL || p < sz;
+    const bool lt = k0[i] < v, eq = k0[i] == v;
+    const uint64_t mlt = __ballot(act && lt), meq = __ballot(act && eq);
+    if (act) {
+      const uint32_t L = lt_run + lanes_below(mlt);
+      const uint32_t E = eq_run + lanes_below(meq);
+      const uint32_t lb = L + umin32(E, jeq);
+      const bool left = lt || (eq && E < jeq);
+      const uint32_t dest = left ? lb : half + (p - lb);
+      if (dest < sz) {
+        B0[dest] = (KT)k0[i];
+        B1[dest] = (KT)k1[i];
+        B2[dest] = (KT)k2[i];
+        if (is) id[dest] = is[p];
+      } else {
+        P->status = BBX_EHIP;  // inconsistent counts: never expected
       }
-      lt_run += (uint32_t)__popcll(mlt);
-      eq_run += (uint32_t)__popcll(meq);
     }
+    lt_run += (uint32_t)__popcll(mlt);
+    eq_run += (uint32_t)__popcll(meq);
+  }
+}
+
+// Stable partition of one node by one wavefront.  With fewer than three axes
+// the missing ones repeat the split axis (the same value to the same slot).
+template <typename KT>
+__device__ void wave_partition(const KT* src, KT* dst, uint64_t kst, const uint32_t* is,
+                               uint32_t* id, uint32_t dims, uint32_t d, uint32_t sz, uint32_t v,
+                               uint32_t jeq, DevParams* P) {
+  const uint32_t a1 = dims > 1 ? (d + 1) % dims : d, a2 = dims > 2 ? (d + 2) % dims : d;
+  const KT* A0 = src + (uint64_t)d * kst;
+  const KT* A1 = src + (uint64_t)a1 * kst;
+  const KT* A2 = src + (uint64_t)a2 * kst;
+  KT* B0 = dst + (uint64_t)d * kst;
+  KT* B1 = dst + (uint64_t)a1 * kst;
+  KT* B2 = dst + (uint64_t)a2 * kst;
+  uint32_t lt_run = 0, eq_run = 0;
+  for (uint32_t base = 0; base < sz; base += 512) {
+    if (base + 512 <= sz)
+      wave_part_rows<KT, true>(base, sz, A0, A1, A2, B0, B1, B2, is, id, v, jeq, lt_run, eq_run, P);
+    else
+      wave_part_rows<KT, false>(base, sz, A0, A1, A2, B0, B1, B2, is, id, v, jeq, lt_run, eq_run,
+                                P);
   }
 }
 
@@ -811,8 +900,7 @@ __device__ void level_wave_body(uint32_t depth, const SetDesc& S, DevParams* P, 
   }
   uint32_t v, jeq;
   wave_median(s0 + (uint64_t)d * kst, sz, sz >> 1, bins, &v, &jeq);
-  wave_partition(s0, s0 + kst, s0 + 2 * kst, d0, d0 + kst, d0 + 2 * kst, is, id, dims, d, sz, v,
-                 jeq, P);
+  wave_partition(s0, d0, kst, is, id, dims, d, sz, v, jeq, P);
 }
 
 // Levels whose nodes have at most kWaveNode members: one wavefront per node,

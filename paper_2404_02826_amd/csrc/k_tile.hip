@@ -298,26 +298,37 @@ __device__ void tile_body(WaveTile<TILE, KL, TRACK>& sm, uint64_t j, uint32_t K0
               atomicAdd(&sm.H[(ni[k] << w) + ((q[k] >> sh) & mask)], 1u);
         }
         wave_sync();
-        if (N <= 8) {  // few nodes: the whole wavefront scans each node's bins
-          for (uint32_t i = 0; i < N; ++i) {
-            if (sm.nsz[i] <= r) continue;
-            const uint32_t per = (nb + 63) / 64;  // <= 4
-            uint32_t c[4] = {0, 0, 0, 0};
-            uint32_t mine = 0;
-            for (uint32_t k = 0; k < per; ++k) {
-              const uint32_t b = lane * per + k;
-              if (b < nb) {
-                c[k] = sm.H[(i << w) + b];
-                if (c[k]) sm.H[(i << w) + b] = 0;
-              }
-              mine += c[k];
+        if (N <= 8) {
+          // few nodes: every node's bins at once.  The N * 2^w bins are
+          // split evenly over the lanes, each lane's bins inside one node;
+          // a node's prefix is the wavefront prefix minus its value at the
+          // node's first lane.
+          const uint32_t T = N << w;
+          const uint32_t lp = T > 64 ? bitlen32(T) - 7 : 0u;  // T is a power of two
+          const uint32_t per = 1u << lp;                       // bins per lane, <= TILE / 64
+          const uint32_t b0 = lane << lp;
+          uint32_t c[TILE / 64];
+          uint32_t mine = 0;
+#pragma unroll
+          for (int k = 0; k < TILE / 64; ++k) {
+            const uint32_t b = b0 + k;
+            c[k] = 0;
+            if ((uint32_t)k < per && b < T) {
+              c[k] = sm.H[b];
+              if (c[k]) sm.H[b] = 0;
             }
-            uint32_t cum = wave_incl(mine) - mine;
+            mine += c[k];
+          }
+          const uint32_t ex = wave_incl(mine) - mine;
+          const uint32_t i = b0 < T ? b0 >> w : 0u;
+          uint32_t cum = ex - (uint32_t)__shfl((int)ex, (int)((i << w) >> lp));
+          if (b0 < T && sm.nsz[i] > r) {
             const uint32_t rank = sm.nrank[i];
             const uint32_t pr = sm.npre[i];
-            for (uint32_t k = 0; k < per; ++k) {
-              if (cum <= rank && rank < cum + c[k]) {
-                sm.npre[i] = (KL)((pr << w) | (lane * per + k));
+#pragma unroll
+            for (int k = 0; k < TILE / 64; ++k) {
+              if ((uint32_t)k < per && cum <= rank && rank < cum + c[k]) {
+                sm.npre[i] = (KL)((pr << w) | ((b0 + k) & (nb - 1)));
                 sm.nrank[i] = (uint16_t)(rank - cum);
               }
               cum += c[k];
