@@ -435,73 +435,84 @@ __global__ void __launch_bounds__(kBlock) k_select_last(uint32_t depth, uint32_t
   }
 }
 
-// One streaming group of a stable partition: wavefront w of the block takes
-// the 512 consecutive elements [g + 512 w, g + 512 w + 512) as 8 rows of 64.
-// Codes are handled in axis order (split axis, next axis, third axis), so the
-// split code is always k0 and the next level's code k1: no per-element axis
-// selection.  Ranks below / equal to the median come from ballots within the
-// wavefront, a running count across its rows, and one exchange of wavefront
-// totals per group (double-buffered: one barrier per group).
-template <typename KT, int NA, bool FULL>
-__device__ __forceinline__ void scatter_group(uint32_t g, uint32_t end, const KT* A0, const KT* A1,
-                                     const KT* A2, KT* B0, KT* B1, KT* B2, const uint32_t* is,
-                                     uint32_t* id, uint32_t sz, uint32_t v, uint32_t jeq,
-                                     uint32_t& lt_run, uint32_t& eq_run, bool cl, bool cr,
-                                     uint32_t shn, uint32_t maskn, uint32_t* lhist,
-                                     uint32_t (*cnt)[kBlock / 64][2], int buf, DevParams* P) {
+// Stable partition of a chunk in streaming groups of kGroup elements:
+// wavefront w of the block takes the 512 consecutive elements
+// [g + 512 w, g + 512 w + 512) of a group as 8 rows of 64.  Codes are handled
+// in axis order (split axis, next axis, third axis), so the split code is
+// always k0 and the next level's code k1: no per-element axis selection.
+// Ranks below / equal to the median come from ballots within the wavefront, a
+// running count across its rows, and one exchange of wavefront totals per
+// group (double-buffered: one barrier per group).  The next group's codes are
+// loaded before that barrier, so they are in flight while this group waits
+// and stores.
+template <typename KT, bool FULL>
+__device__ __forceinline__ void scatter_load(uint32_t g, uint32_t end, const KT* A0, const KT* A1,
+                                             const KT* A2, uint32_t (&k)[3][kRows]) {
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t wv = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const uint32_t base = g + wv * (kGroup / (kBlock / 64));
-  const uint32_t half = sz >> 1;
-  uint32_t k0[kRows], k1[kRows], k2[kRows];
-  {
-    // one 64-bit address per axis; the rows are immediate offsets from it
-    const KT* a0 = A0 + base + lane;
-    const KT* a1 = A1 + base + lane;
-    const KT* a2 = A2 + base + lane;
-#pragma unroll
-    for (int i = 0; i < kRows; ++i) {
-      const bool act = FULL || base + 64u * i + lane < end;
-      k0[i] = act ? (uint32_t)a0[64 * i] : 0u;
-      k1[i] = (NA > 1 && act) ? (uint32_t)a1[64 * i] : 0u;
-      k2[i] = (NA > 2 && act) ? (uint32_t)a2[64 * i] : 0u;
-    }
-  }
-  uint32_t rl[kRows], re[kRows], wl = 0, we = 0;
+  const KT* a0 = A0 + base + lane;  // one 64-bit address per axis; rows are immediate offsets
+  const KT* a1 = A1 + base + lane;
+  const KT* a2 = A2 + base + lane;
 #pragma unroll
   for (int i = 0; i < kRows; ++i) {
     const bool act = FULL || base + 64u * i + lane < end;
-    const uint64_t mlt = __ballot(act && k0[i] < v);
-    const uint64_t meq = __ballot(act && k0[i] == v);
+    k[0][i] = act ? (uint32_t)a0[64 * i] : 0u;
+    k[1][i] = act ? (uint32_t)a1[64 * i] : 0u;
+    k[2][i] = act ? (uint32_t)a2[64 * i] : 0u;
+  }
+}
+
+template <bool FULL>
+__device__ __forceinline__ void scatter_ranks(uint32_t g, uint32_t end, const uint32_t (&k)[3][kRows],
+                                              uint32_t v, uint32_t (&rl)[kRows],
+                                              uint32_t (&re)[kRows], uint32_t& wl, uint32_t& we) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t wv = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const uint32_t base = g + wv * (kGroup / (kBlock / 64));
+  wl = 0;
+  we = 0;
+#pragma unroll
+  for (int i = 0; i < kRows; ++i) {
+    const bool act = FULL || base + 64u * i + lane < end;
+    const uint64_t mlt = __ballot(act && k[0][i] < v);
+    const uint64_t meq = __ballot(act && k[0][i] == v);
     rl[i] = wl + lanes_below(mlt);
     re[i] = we + lanes_below(meq);
     wl += popc64(mlt);
     we += popc64(meq);
   }
-  if (lane == 0) cnt[buf][wv][0] = wl, cnt[buf][wv][1] = we;
-  __syncthreads();
-  const uint4 X = *(const uint4*)&cnt[buf][0][0];  // wavefronts 0, 1
-  const uint4 Y = *(const uint4*)&cnt[buf][2][0];  // wavefronts 2, 3
-  const uint32_t bl = lt_run + (wv > 0 ? X.x : 0u) + (wv > 1 ? X.z : 0u) + (wv > 2 ? Y.x : 0u);
-  const uint32_t be = eq_run + (wv > 0 ? X.y : 0u) + (wv > 1 ? X.w : 0u) + (wv > 2 ? Y.y : 0u);
-  lt_run += X.x + X.z + Y.x + Y.z;
-  eq_run += X.y + X.w + Y.y + Y.w;
+}
+
+template <typename KT, int NA, bool FULL>
+__device__ __forceinline__ void scatter_store(uint32_t g, uint32_t end, const uint32_t (&k)[3][kRows],
+                                              const uint32_t (&rl)[kRows],
+                                              const uint32_t (&re)[kRows], uint32_t bl,
+                                              uint32_t be, KT* B0, KT* B1, KT* B2,
+                                              const uint32_t* is, uint32_t* id, uint32_t sz,
+                                              uint32_t v, uint32_t jeq, bool cl, bool cr,
+                                              uint32_t shn, uint32_t maskn, uint32_t* lhist,
+                                              DevParams* P) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t wv = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const uint32_t base = g + wv * (kGroup / (kBlock / 64));
+  const uint32_t half = sz >> 1;
 #pragma unroll
   for (int i = 0; i < kRows; ++i) {
     const uint32_t p = base + 64u * i + lane;
     if (!FULL && p >= end) continue;
-    const bool lt = k0[i] < v, eq = k0[i] == v;
+    const bool lt = k[0][i] < v, eq = k[0][i] == v;
     const uint32_t L = bl + rl[i], E = be + re[i];
     const uint32_t lb = L + umin32(E, jeq);
     const bool left = lt || (eq && E < jeq);
     const uint32_t dest = left ? lb : half + (p - lb);
     if (dest < sz) {
-      B0[dest] = (KT)k0[i];
-      if (NA > 1) B1[dest] = (KT)k1[i];
-      if (NA > 2) B2[dest] = (KT)k2[i];
+      B0[dest] = (KT)k[0][i];
+      if (NA > 1) B1[dest] = (KT)k[1][i];
+      if (NA > 2) B2[dest] = (KT)k[2][i];
       if (is) id[dest] = is[p];
       if (left ? cl : cr)
-        atomicAdd(&lhist[(left ? 0u : (uint32_t)kBlock) + (((NA > 1 ? k1[i] : k0[i]) >> shn) & maskn)],
+        atomicAdd(&lhist[(left ? 0u : (uint32_t)kBlock) + (((NA > 1 ? k[1][i] : k[0][i]) >> shn) & maskn)],
                   1u);
     } else {
       P->status = BBX_EHIP;  // inconsistent counts: never expected
@@ -516,14 +527,47 @@ __device__ __forceinline__ void scatter_range(uint32_t beg, uint32_t end, const 
                               uint32_t eq_run, bool cl, bool cr, uint32_t shn, uint32_t maskn,
                               uint32_t* lhist, DevParams* P) {
   __shared__ __align__(16) uint32_t cnt[2][kBlock / 64][2];
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t wv = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  uint32_t k[3][kRows], kn[3][kRows];
+  if (beg >= end) return;
+  if (beg + kGroup <= end)
+    scatter_load<KT, true>(beg, end, A0, A1, A2, k);
+  else
+    scatter_load<KT, false>(beg, end, A0, A1, A2, k);
   int buf = 0;
   for (uint32_t g = beg; g < end; g += kGroup, buf ^= 1) {
-    if (g + kGroup <= end)
-      scatter_group<KT, NA, true>(g, end, A0, A1, A2, B0, B1, B2, is, id, sz, v, jeq, lt_run,
-                                  eq_run, cl, cr, shn, maskn, lhist, cnt, buf, P);
+    const bool full = g + kGroup <= end;
+    uint32_t rl[kRows], re[kRows], wl, we;
+    if (full)
+      scatter_ranks<true>(g, end, k, v, rl, re, wl, we);
     else
-      scatter_group<KT, NA, false>(g, end, A0, A1, A2, B0, B1, B2, is, id, sz, v, jeq, lt_run,
-                                   eq_run, cl, cr, shn, maskn, lhist, cnt, buf, P);
+      scatter_ranks<false>(g, end, k, v, rl, re, wl, we);
+    const uint32_t gn = g + kGroup;
+    if (gn < end) {
+      if (gn + kGroup <= end)
+        scatter_load<KT, true>(gn, end, A0, A1, A2, kn);
+      else
+        scatter_load<KT, false>(gn, end, A0, A1, A2, kn);
+    }
+    if (lane == 0) cnt[buf][wv][0] = wl, cnt[buf][wv][1] = we;
+    __syncthreads();
+    const uint4 X = *(const uint4*)&cnt[buf][0][0];  // wavefronts 0, 1
+    const uint4 Y = *(const uint4*)&cnt[buf][2][0];  // wavefronts 2, 3
+    const uint32_t bl = lt_run + (wv > 0 ? X.x : 0u) + (wv > 1 ? X.z : 0u) + (wv > 2 ? Y.x : 0u);
+    const uint32_t be = eq_run + (wv > 0 ? X.y : 0u) + (wv > 1 ? X.w : 0u) + (wv > 2 ? Y.y : 0u);
+    lt_run += X.x + X.z + Y.x + Y.z;
+    eq_run += X.y + X.w + Y.y + Y.w;
+    if (full)
+      scatter_store<KT, NA, true>(g, end, k, rl, re, bl, be, B0, B1, B2, is, id, sz, v, jeq, cl, cr,
+                                  shn, maskn, lhist, P);
+    else
+      scatter_store<KT, NA, false>(g, end, k, rl, re, bl, be, B0, B1, B2, is, id, sz, v, jeq, cl,
+                                   cr, shn, maskn, lhist, P);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int i = 0; i < kRows; ++i) k[a][i] = kn[a][i];
   }
 }
 
