@@ -8,9 +8,9 @@
 // in index order, "index order" is "storage order", so the split is an exact
 // radix select on q_d followed by a stable partition.
 //
-//   k_hist_zero    zero the histogram bins once per call (every select kernel
-//                  re-zeroes the bins it reads)
-//   k_hist_root    first-digit histogram of depth 0
+//   (the histogram bins are zeroed once per call before quantization, which
+//   also builds the first-digit histogram of depth 0; every select kernel
+//   re-zeroes the bins it reads)
 //   k_hist_mid     histogram of a further high digit over the candidates
 //                  (members matching the digits found so far)
 //   k_select_mid   per node: the digit holding the median's rank
@@ -78,11 +78,6 @@ __global__ void __launch_bounds__(kBlock) k_pass_flags(uint32_t nsets, const Set
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_hist_zero(uint64_t entries, uint32_t* hist) {
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < entries;
-       i += (uint64_t)gridDim.x * blockDim.x)
-    hist[i] = 0;
-}
 
 // The block's set, local block index and level shape.
 struct LevelCtx {
@@ -173,7 +168,7 @@ __device__ void hist_mid_body(uint32_t depth, uint32_t pass, const SetDesc& S, c
 }
 
 // passes >= 1 of a code with more than two digits (pass 0 is built by the
-// previous scatter, or by k_hist_root at depth 0)
+// previous scatter, or by the quantize pass at depth 0)
 __global__ void __launch_bounds__(kBlock) k_hist_mid(uint32_t depth, uint32_t pass, uint32_t nsets,
                                                      const uint64_t* pre, const SetDesc* sets,
                                                      const DevParams* params, uint8_t* keys0,
@@ -254,34 +249,6 @@ __global__ void __launch_bounds__(kBlock) k_select_mid(uint32_t depth, uint32_t 
   }
 }
 
-// depth 0 builds its first digit here (deeper levels get it from the scatter)
-__global__ void __launch_bounds__(kBlock) k_hist_root(uint32_t nsets, const uint64_t* pre,
-                                                      const SetDesc* sets, const DevParams* params,
-                                                      uint8_t* keys0, uint32_t* hist0) {
-  const LevelCtx c = level_ctx(nsets, pre, sets, 0);
-  const SetDesc& S = sets[c.s];
-  const DevParams* P = params + c.s;
-  if (P->status != BBX_OK) return;
-  if (level_is_local(S.n, 0)) return;
-  const DigitPlan pl = digit_plan(P->G[0]);
-  if (pl.npass < 2) return;
-  if (S.n <= S.r) return;
-  __shared__ uint32_t lh[kHistBins];
-  const uint32_t w = pl.width[0], sh = pl.shift[0], mask = (1u << w) - 1;
-  lh[threadIdx.x] = 0;
-  __syncthreads();
-  const uint64_t beg = c.lb * (uint64_t)c.sh.chunk_elems;
-  const uint64_t end = beg + c.sh.chunk_elems < S.n ? beg + c.sh.chunk_elems : S.n;
-  const uint8_t* keys = keys0 + S.key_off;
-  auto add = [&](uint32_t v) { atomicAdd(&lh[(v >> sh) & mask], 1u); };
-  if (P->key16)
-    scan_codes((const uint16_t*)keys, beg, end, add);
-  else
-    scan_codes((const uint32_t*)keys, beg, end, add);
-  __syncthreads();
-  if (threadIdx.x <= mask && lh[threadIdx.x])
-    atomicAdd(&hist0[S.hist_off + threadIdx.x], lh[threadIdx.x]);
-}
 
 template <typename KT>
 __device__ void hist_last_body(uint32_t depth, const SetDesc& S, const DevParams* P,
@@ -980,7 +947,6 @@ static uint64_t sel_grid(uint64_t nodes) {
 
 hipError_t launch_levels(const BatchPlan& bp, const Ws& w, hipStream_t s) {
   if (bp.max_gl == 0) return hipGetLastError();
-  BBX_LAUNCH("level_hist_zero", k_hist_zero, 1024, kBlock, 0, s, bp.hist_entries, w.hist);
   BBX_LAUNCH("level_pass_flags", k_pass_flags, 1, kBlock, 0, s, bp.nsets, w.sets, w.params,
              w.pass_need);
   for (uint32_t k = 0; k < bp.max_gl; ++k) {
@@ -995,10 +961,8 @@ hipError_t launch_levels(const BatchPlan& bp, const Ws& w, hipStream_t s) {
                  0, s, k, bp.nsets, pnd, w.sets, w.params, w.keys[cur], w.keys[cur ^ 1], w.idx[cur],
                  w.idx[cur ^ 1]);
     if (!bp.lv_global[k]) continue;
-    if (k == 0)
-      BBX_LAUNCH("level_hist_mid", k_hist_root, bp.g_lv[0], kBlock, 0, s, bp.nsets, plv, w.sets,
-                 w.params, w.keys[0], w.hist);
-    // mid passes: pass 0 was built above or by the previous scatter
+    // mid passes: pass 0 was built by the quantize pass (depth 0) or by the
+    // previous scatter
     for (uint32_t pass = 0; pass < 3; ++pass) {
       if (pass > 0)
         BBX_LAUNCH("level_hist_mid", k_hist_mid, bp.g_lv[k] < 2048 ? bp.g_lv[k] : 2048, kBlock, 0, s,

@@ -359,22 +359,24 @@ __device__ void pack_payload_body(const SetDesc& S, const DevParams* P, uint64_t
       if (slot < slot0 || slot >= slot_end) continue;
       while (a + 1 < nlb && s_rec[a + 1].start <= slot) ++a;
       const LeafRec rec = s_rec[a];
-      const uint64_t j = slot - rec.start;
+      const uint32_t j = (uint32_t)(slot - rec.start);
       const uint32_t sm = sum_m(rec.m);
       if (j == 0 || sm == 0) continue;  // the reference, or a leaf without payload
-      const uint64_t at = s_off[a] + (j - 1) * sm - wlo * 64;  // bit in the LDS copy
-      const uint32_t w = (uint32_t)(at >> 6), sh = (uint32_t)(at & 63);
+      // bit in the LDS copy (below kPackLdsWords * 64: 32-bit arithmetic)
+      const uint32_t at = (uint32_t)(s_off[a] - wlo * 64) + (j - 1) * sm;
+      const uint32_t w = at >> 6, sh = at & 63;
       if (sm <= 64) {
+        // u_d = q_d - q_ref,d + 2^(m_d - 1) lies in [0, 2^m_d) (m_d <= 32), so
+        // 32-bit wrap-around arithmetic gives it exactly; an axis with m_d = 0
+        // has q_d = q_ref,d and adds nothing
         uint64_t c = 0;
         uint32_t cat = 0;
 #pragma unroll
         for (uint32_t d = 0; d < 3; ++d) {
           if (d >= dims) break;
           const uint32_t m = (rec.m >> (8 * d)) & 0xffu;
-          if (m == 0) continue;
-          const uint64_t u = (uint64_t)((int64_t)(uint32_t)kk[d].e[k] - (int64_t)rec.qref[d] +
-                                        ((int64_t)1 << (m - 1)));
-          c |= u << cat;
+          const uint32_t u = (uint32_t)kk[d].e[k] - rec.qref[d] + (uint32_t)((1ull << m) >> 1);
+          c |= (uint64_t)u << cat;
           cat += m;
         }
         atomicOr(&s_w[w], (unsigned long long)(c << sh));

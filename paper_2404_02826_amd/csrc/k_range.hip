@@ -7,7 +7,8 @@
 //               rounding guard, eb_eff, w = 2*eb_eff, inv_w and the code
 //               widths G_d
 //   k_quantize  q = floor((x - lo) * inv_w + 1/2) per coordinate, written as
-//               structure-of-arrays codes (u16 when every G_d <= 16, else u32)
+//               structure-of-arrays codes (u16 when every G_d <= 16, else u32);
+//               also the depth-0 first-digit histogram of the k-d partition
 #include <math.h>
 
 #include <type_traits>
@@ -128,7 +129,7 @@ __global__ void __launch_bounds__(kBlock) k_epilogue(const SetDesc* sets, const 
                                                      DevParams* params) {
   const SetDesc& S = sets[blockIdx.x];
   DevParams* P = params + blockIdx.x;
-  __shared__ double red[7][kBlock];
+  __shared__ double red[7][kBlock / 64];
   double v[7];
   for (int f = 0; f < 7; ++f) v[f] = f < 3 ? INFINITY : (f < 6 ? -INFINITY : 0.0);
   for (uint32_t b = threadIdx.x; b < S.mm_blocks; b += blockDim.x)
@@ -139,11 +140,15 @@ __global__ void __launch_bounds__(kBlock) k_epilogue(const SetDesc* sets, const 
       else
         v[f] = u > v[f] ? u : v[f];
     }
-  for (int f = 0; f < 7; ++f) red[f][threadIdx.x] = v[f];
+  // min / max are exact in any order: wavefront reductions, then the four
+  // wavefront results
+  for (int f = 0; f < 7; ++f) v[f] = f < 3 ? wave_min(v[f]) : wave_max(v[f]);
+  if ((threadIdx.x & 63) == 0)
+    for (int f = 0; f < 7; ++f) red[f][threadIdx.x >> 6] = v[f];
   __syncthreads();
   if (threadIdx.x != 0) return;
   for (int f = 0; f < 7; ++f)
-    for (int t = 1; t < kBlock; ++t) {
+    for (int t = 1; t < kBlock / 64; ++t) {
       const double u = red[f][t];
       if (f < 3)
         v[f] = u < v[f] ? u : v[f];
@@ -231,10 +236,14 @@ __global__ void __launch_bounds__(kBlock) k_epilogue(const SetDesc* sets, const 
   *P = p;
 }
 
+// Root histogram: when the depth-0 median is selected with global histograms,
+// quantization also counts the first radix digit of every axis-0 code into
+// the block's LDS bins (lh != null), so that level needs no pass of its own.
 template <typename T, typename KT, int DIMS>
 __device__ uint64_t quantize_aos_vec(const T* __restrict__ pos, uint64_t n, uint64_t kst,
                                      const double* lo, double inv_w, uint64_t t0, uint64_t nt,
-                                     KT* __restrict__ keys, uint32_t* __restrict__ idx) {
+                                     KT* __restrict__ keys, uint32_t* __restrict__ idx,
+                                     uint32_t* lh, uint32_t hsh, uint32_t hmask) {
   constexpr uint32_t V = 16 / sizeof(T);  // particles per group (2 or 4)
   const uint64_t ng = n / V;
   const uint4* p4 = (const uint4*)pos;
@@ -253,8 +262,11 @@ __device__ uint64_t quantize_aos_vec(const T* __restrict__ pos, uint64_t n, uint
                  typename std::conditional<sizeof(KT) * V == 8, uint2, uint32_t>::type>::type w;
       } o;
 #pragma unroll
-      for (uint32_t j = 0; j < V; ++j)
-        o.k[j] = (KT)(uint32_t)floor(((double)u.e[j * DIMS + d] - lo[d]) * inv_w + 0.5);
+      for (uint32_t j = 0; j < V; ++j) {
+        const uint32_t q = (uint32_t)floor(((double)u.e[j * DIMS + d] - lo[d]) * inv_w + 0.5);
+        o.k[j] = (KT)q;
+        if (d == 0 && lh) atomicAdd(&lh[(q >> hsh) & hmask], 1u);
+      }
       *(decltype(o.w)*)(keys + (uint64_t)d * kst + g * V) = o.w;
     }
     if (idx)
@@ -268,21 +280,24 @@ template <typename T, typename KT>
 __device__ void quantize_body(const T* __restrict__ pos, uint64_t n, uint64_t kst, uint32_t dims,
                               uint32_t layout, double lo0, double lo1, double lo2, double inv_w,
                               uint64_t lb, uint64_t nblk, KT* __restrict__ keys,
-                              uint32_t* __restrict__ idx) {
+                              uint32_t* __restrict__ idx, uint32_t* lh, uint32_t hsh,
+                              uint32_t hmask) {
   const double lo[3] = {lo0, lo1, lo2};
   const uint64_t stride = nblk * blockDim.x;
   uint64_t first = 0;
   if (layout == BBX_AOS && ((uintptr_t)pos & 15) == 0)
     first = dims == 3 ? quantize_aos_vec<T, KT, 3>(pos, n, kst, lo, inv_w, lb * blockDim.x + threadIdx.x,
-                                                   stride, keys, idx)
+                                                   stride, keys, idx, lh, hsh, hmask)
                       : quantize_aos_vec<T, KT, 2>(pos, n, kst, lo, inv_w, lb * blockDim.x + threadIdx.x,
-                                                   stride, keys, idx);
+                                                   stride, keys, idx, lh, hsh, hmask);
   for (uint64_t i = first + lb * blockDim.x + threadIdx.x; i < n; i += stride) {
 #pragma unroll
     for (uint32_t d = 0; d < 3; ++d) {
       if (d >= dims) break;
       const double x = load_coord(pos, n, dims, layout, i, d);
-      keys[(uint64_t)d * kst + i] = (KT)(uint32_t)floor((x - lo[d]) * inv_w + 0.5);
+      const uint32_t q = (uint32_t)floor((x - lo[d]) * inv_w + 0.5);
+      keys[(uint64_t)d * kst + i] = (KT)q;
+      if (d == 0 && lh) atomicAdd(&lh[(q >> hsh) & hmask], 1u);
     }
     if (idx) idx[i] = (uint32_t)i;
   }
@@ -290,30 +305,55 @@ __device__ void quantize_body(const T* __restrict__ pos, uint64_t n, uint64_t ks
 
 template <typename T>
 __device__ void quantize_set(const SetDesc& S, const DevParams* P, uint64_t lb, uint64_t nblk,
-                             uint8_t* keys, uint32_t* idx) {
+                             uint8_t* keys, uint32_t* idx, uint32_t* lh, uint32_t hsh,
+                             uint32_t hmask) {
   const T* pos = (const T*)S.pos;
   const uint64_t n = S.n;
   const uint32_t dims = S.dims, layout = S.layout;
   const double l0 = P->lo[0], l1 = P->lo[1], l2 = P->lo[2], iw = P->inv_w;
   if (P->key16)
-    quantize_body<T, uint16_t>(pos, n, S.kst, dims, layout, l0, l1, l2, iw, lb, nblk, (uint16_t*)keys, idx);
+    quantize_body<T, uint16_t>(pos, n, S.kst, dims, layout, l0, l1, l2, iw, lb, nblk,
+                               (uint16_t*)keys, idx, lh, hsh, hmask);
   else
-    quantize_body<T, uint32_t>(pos, n, S.kst, dims, layout, l0, l1, l2, iw, lb, nblk, (uint32_t*)keys, idx);
+    quantize_body<T, uint32_t>(pos, n, S.kst, dims, layout, l0, l1, l2, iw, lb, nblk,
+                               (uint32_t*)keys, idx, lh, hsh, hmask);
 }
 
 __global__ void __launch_bounds__(kBlock) k_quantize(uint32_t nsets, const uint64_t* pre,
                                                      const SetDesc* sets, const DevParams* params,
-                                                     uint8_t* keys0, uint32_t* idx0) {
+                                                     uint8_t* keys0, uint32_t* idx0,
+                                                     uint32_t* hist0) {
   const uint32_t s = find_set(pre, nsets, blockIdx.x);
   const SetDesc& S = sets[s];
   const DevParams* P = params + s;
   if (P->status != BBX_OK) return;
   const uint64_t lb = blockIdx.x - pre[s], nblk = pre[s + 1] - pre[s];
   uint32_t* idx = S.perm ? idx0 + S.idx_off : nullptr;
+  // the depth-0 first-digit histogram, when depth 0 uses global histograms
+  // with more than one digit pass (the same condition the level kernels use)
+  __shared__ uint32_t lh[kHistBins];
+  const DigitPlan pl = digit_plan(P->G[0]);
+  const bool root = !level_is_local(S.n, 0) && pl.npass >= 2 && S.n > S.r;
+  const uint32_t hsh = pl.shift[0], hmask = (1u << pl.width[0]) - 1;
+  if (root) {
+    lh[threadIdx.x] = 0;
+    __syncthreads();
+  }
   if (S.dtype == BBX_F32)
-    quantize_set<float>(S, P, lb, nblk, keys0 + S.key_off, idx);
+    quantize_set<float>(S, P, lb, nblk, keys0 + S.key_off, idx, root ? lh : nullptr, hsh, hmask);
   else
-    quantize_set<double>(S, P, lb, nblk, keys0 + S.key_off, idx);
+    quantize_set<double>(S, P, lb, nblk, keys0 + S.key_off, idx, root ? lh : nullptr, hsh, hmask);
+  if (root) {
+    __syncthreads();
+    if (threadIdx.x <= hmask && lh[threadIdx.x])
+      atomicAdd(&hist0[S.hist_off + threadIdx.x], lh[threadIdx.x]);
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_hist_zero(uint64_t entries, uint32_t* hist) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < entries;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    hist[i] = 0;
 }
 
 hipError_t launch_range(const BatchPlan& bp, const Ws& w, hipStream_t s) {
@@ -321,9 +361,13 @@ hipError_t launch_range(const BatchPlan& bp, const Ws& w, hipStream_t s) {
     BBX_LAUNCH("range_minmax", k_minmax, bp.g_mm, kBlock, 0, s, bp.nsets, w.pre + bp.o_mm, w.sets,
                w.partials);
   BBX_LAUNCH("range_epilogue", k_epilogue, bp.nsets, kBlock, 0, s, w.sets, w.partials, w.params);
+  // histogram bins start at zero (the quantize pass adds the root histogram;
+  // every select kernel re-zeroes the bins it reads)
+  if (bp.hist_entries > 0)
+    BBX_LAUNCH("level_hist_zero", k_hist_zero, 1024, kBlock, 0, s, bp.hist_entries, w.hist);
   if (bp.g_qz > 0)
     BBX_LAUNCH("quantize", k_quantize, bp.g_qz, kBlock, 0, s, bp.nsets, w.pre + bp.o_qz, w.sets,
-               w.params, w.keys[0], w.idx[0]);
+               w.params, w.keys[0], w.idx[0], w.hist);
   return hipGetLastError();
 }
 

@@ -135,44 +135,44 @@ __device__ void unpack_body(uint64_t n, uint32_t layout, uint32_t r, double w,
       if (p < slot0 || p >= slot1) continue;
       while (a + 1 < nlb && s_rec[a + 1].start <= p) ++a;
       const LeafRec rec = s_rec[a];
-      const uint64_t j = p - rec.start;
-      int64_t q[3] = {rec.qref[0], rec.qref[1], rec.qref[2]};
+      const uint32_t j = (uint32_t)(p - rec.start);
+      // widths (m_d <= 31: the meta check rejects wider); m_d = 0 gives a
+      // zero mask and a zero offset, so such an axis keeps the reference code
+      const uint32_t m0 = rec.m & 0xffu, m1 = dims > 1 ? (rec.m >> 8) & 0xffu : 0u,
+                     m2 = dims > 2 ? (rec.m >> 16) & 0xffu : 0u;
+      const uint32_t summ = m0 + m1 + m2;
+      uint32_t u[3] = {0, 0, 0};
+      const uint32_t mm[3] = {m0, m1, m2};
       if (j > 0) {
-        uint32_t summ = 0;
-        for (uint32_t d = 0; d < dims; ++d) summ += (rec.m >> (8 * d)) & 0xffu;
-        const uint64_t at = s_off[a] + (j - 1) * summ;
+        const uint64_t at = s_off[a] + (uint64_t)(j - 1) * summ;
         if (summ <= 64) {
-          uint64_t v = staged ? read64(s_pay, at - w0 * 64, summ) : read64(pay, at, summ);
-#pragma unroll
-          for (uint32_t d = 0; d < 3; ++d) {
-            if (d >= dims) break;
-            const uint32_t m = (rec.m >> (8 * d)) & 0xffu;
-            if (m == 0) continue;
-            const uint64_t u = v & ((1ull << m) - 1);
-            v >>= m;
-            if (u == 0) corrupt = true;
-            q[d] = (int64_t)rec.qref[d] + (int64_t)u - ((int64_t)1 << (m - 1));
-          }
+          const uint64_t v = staged ? read64(s_pay, at - w0 * 64, summ) : read64(pay, at, summ);
+          u[0] = (uint32_t)v & ((1u << m0) - 1);
+          u[1] = (uint32_t)(v >> m0) & ((1u << m1) - 1);
+          u[2] = (uint32_t)(v >> (m0 + m1)) & ((1u << m2) - 1);
         } else {
           u128 v = staged ? read_bits(s_pay, nw, at - w0 * 64, summ) : read_bits(pay, pay_words, at, summ);
-          for (uint32_t d = 0; d < dims; ++d) {
-            const uint32_t m = (rec.m >> (8 * d)) & 0xffu;
-            if (m == 0) continue;
-            const uint64_t u = (uint64_t)(v & ((((u128)1) << m) - 1));
-            v >>= m;
-            if (u == 0) corrupt = true;
-            q[d] = (int64_t)rec.qref[d] + (int64_t)u - ((int64_t)1 << (m - 1));
+#pragma unroll
+          for (uint32_t d = 0; d < 3; ++d) {
+            u[d] = (uint32_t)(v & ((((u128)1) << mm[d]) - 1));
+            v >>= mm[d];
           }
         }
+#pragma unroll
+        for (uint32_t d = 0; d < 3; ++d)
+          if (d < dims && mm[d] != 0 && u[d] == 0) corrupt = true;
       }
 #pragma unroll
       for (uint32_t d = 0; d < 3; ++d) {
         if (d >= dims) break;
-        if (q[d] < 0 || q[d] >= ((int64_t)1 << G[d])) {
+        // q = q_ref + u - 2^(m-1) for a member, q_ref for the reference
+        const int64_t q = (int64_t)rec.qref[d] + (j > 0 ? (int64_t)u[d] - (int64_t)((1u << mm[d]) >> 1) : 0);
+        uint32_t qq = (uint32_t)q;
+        if ((uint64_t)q >= (1ull << G[d])) {
           corrupt = true;
-          q[d] = 0;
+          qq = 0;
         }
-        const double x = origin[d] + (double)q[d] * w;
+        const double x = origin[d] + (double)qq * w;
         const T t = (T)x;
         if (full)
           o.e[k * dims + d] = t;
