@@ -173,6 +173,15 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
   bp->tile = in[0].prm.tile_override ? in[0].prm.tile_override : 256;
   descs->assign(nsets, SetDesc());
   uint64_t key_bytes = 0, idx_n = 0, hist_n = 0, sel_n = 0, rows_n = 0, leaves_n = 0, parts = 0;
+  // block target of the global levels: kLevelBlocks for a set alone; in a
+  // batch each set's share of 4 * kLevelBlocks by particle count
+  uint64_t n_total = 0;
+  for (uint32_t s = 0; s < nsets; ++s) n_total += in[s].n;
+  auto level_blocks = [&](uint64_t n) -> uint32_t {
+    if (nsets == 1 || n_total == 0) return (uint32_t)kLevelBlocks;
+    const double share = 4.0 * (double)kLevelBlocks * (double)n / (double)n_total;
+    return (uint32_t)std::min<double>((double)kLevelBlocks, std::max(1.0, std::floor(share + 0.5)));
+  };
   std::vector<uint64_t> mm(nsets), qz(nsets), tl(nsets), bg(nsets), pm(nsets), pp(nsets);
   std::vector<std::vector<uint64_t>> lv(nsets), nd(nsets);
   for (uint32_t s = 0; s < nsets; ++s) {
@@ -195,6 +204,7 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
     D.mbits = I.dtype == BBX_F32 ? 5u : 6u;
     const uint64_t n = I.n;
     if (n > 0) {
+      D.level_blocks = level_blocks(n);
       D.geom = make_geom(n, D.r);
       D.n_leaves = D.geom.L[0][0];
       if (D.r < bp->tile) {
@@ -219,7 +229,7 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
       pp[s] = (D.n_leaves + lpb - 1) / lpb;
       uint64_t max_nodes = 0, max_blocks = 0;
       for (uint32_t k = 0; k < D.gl; ++k) {
-        const LevelShape sh = level_shape(n, k);
+        const LevelShape sh = level_shape(n, k, D.level_blocks);
         const int kind = level_kind(n, k);
         if (kind == 2)
           bp->lv_wave[k] = 1;

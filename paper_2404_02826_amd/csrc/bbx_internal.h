@@ -22,6 +22,7 @@ constexpr int kHistBins = 256;            // per-node bins of the global radix s
 constexpr int kRowStride = 258;           // per-chunk row: 257 prefix counts + below count
 constexpr int kRows = 8;                  // rows of kBlock elements per streaming group
 constexpr int kGroup = kRows * kBlock;    // elements per streaming group
+constexpr uint64_t kLevelBlocks = 4096;   // blocks per global level of a set alone
 
 // Scalars of the range-and-bound step (Sec. 3), computed on the device by the
 // range epilogue and read by every later compress kernel of the set.
@@ -81,6 +82,7 @@ struct SetDesc {
   uint32_t tile_mode;     // 1: tile stage at depth gl; 0: big-leaf stage
   uint32_t final_buf;     // key buffer that ends in output-slot order
   uint32_t mm_blocks;     // blocks of the range pass
+  uint32_t level_blocks;  // block target of the set's global levels (level_shape)
   uint64_t n_leaves;
   uint64_t key_off;       // byte offset into each key buffer (capacity dims*n*4)
   uint64_t idx_off;       // u32 offset into each index buffer
@@ -202,18 +204,22 @@ __host__ __device__ inline uint32_t dp_shift(const DigitPlan& p, uint32_t i) {
 }
 
 // Blocks of one global level of one set: nodes x chunks, each chunk a whole
-// number of streaming groups.
+// number of streaming groups, about target_blocks blocks per level.  A set
+// alone targets kLevelBlocks; in a batch each set targets its share of that
+// (by particle count, at least 1), so that a batch of many small sets does
+// not launch a block per 2048 codes.  Which levels are global does not depend
+// on the target (level_kind below always asks for kLevelBlocks).
 struct LevelShape {
   uint64_t nodes;
   uint32_t chunk_elems;
   uint64_t chunks;
 };
 
-__host__ __device__ inline LevelShape level_shape(uint64_t n, uint32_t depth) {
+__host__ __device__ inline LevelShape level_shape(uint64_t n, uint32_t depth,
+                                                  uint64_t target_blocks) {
   LevelShape sh;
   sh.nodes = 1ull << depth;
   const uint64_t maxsz = (n + sh.nodes - 1) >> depth;  // ceil(n / 2^depth)
-  const uint64_t target_blocks = 4096;
   uint64_t cpn = (target_blocks + sh.nodes - 1) / sh.nodes;
   if (cpn == 0) cpn = 1;
   const uint64_t elems = (maxsz + cpn - 1) / cpn;
@@ -235,7 +241,7 @@ constexpr uint64_t kWaveNode = 4096;
 enum { kLevelGlobal = 0, kLevelBlock = 1, kLevelWave = 2 };
 __host__ __device__ inline int level_kind(uint64_t n, uint32_t depth) {
   if (((n + (1ull << depth) - 1) >> depth) <= kWaveNode) return kLevelWave;
-  return level_shape(n, depth).chunks == 1 ? kLevelBlock : kLevelGlobal;
+  return level_shape(n, depth, kLevelBlocks).chunks == 1 ? kLevelBlock : kLevelGlobal;
 }
 __host__ __device__ inline bool level_is_local(uint64_t n, uint32_t depth) {
   return level_kind(n, depth) != kLevelGlobal;

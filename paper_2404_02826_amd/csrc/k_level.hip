@@ -91,7 +91,7 @@ __device__ inline LevelCtx level_ctx(uint32_t nsets, const uint64_t* pre, const 
   LevelCtx c;
   c.s = find_set(pre, nsets, vb);
   c.lb = vb - pre[c.s];
-  c.sh = level_shape(sets[c.s].n, depth);
+  c.sh = level_shape(sets[c.s].n, depth, sets[c.s].level_blocks);
   return c;
 }
 __device__ inline LevelCtx level_ctx(uint32_t nsets, const uint64_t* pre, const SetDesc* sets,
@@ -334,7 +334,7 @@ __global__ void __launch_bounds__(kBlock) k_select_last(uint32_t depth, uint32_t
     uint64_t st, sz;
     node_span(S.n, depth, j, &st, &sz);
     if (sz <= S.r) continue;
-    const uint64_t chunks = level_shape(S.n, depth).chunks;
+    const uint64_t chunks = level_shape(S.n, depth, S.level_blocks).chunks;
     NodeSel* sel = sel0 + S.sel_off;
     uint32_t* hist = hist0 + S.hist_off + (j << 8);
     const uint32_t* rows = rows0 + S.rows_off + j * chunks * kRowStride;
