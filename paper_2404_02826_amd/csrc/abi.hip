@@ -239,8 +239,10 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
           bp->lv_global[k] = 1;
         lv[s].push_back(sh.nodes * sh.chunks);
         nd[s].push_back(sh.nodes);
-        max_nodes = std::max(max_nodes, sh.nodes);
-        max_blocks = std::max(max_blocks, sh.nodes * sh.chunks);
+        if (kind == kLevelGlobal) {  // only these use histogram bins, selections and rows
+          max_nodes = std::max(max_nodes, sh.nodes);
+          max_blocks = std::max(max_blocks, sh.nodes * sh.chunks);
+        }
       }
       bp->max_gl = std::max(bp->max_gl, D.gl);
       D.mm_blocks = (uint32_t)mm[s];
