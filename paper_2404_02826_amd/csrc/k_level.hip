@@ -378,26 +378,33 @@ __global__ void __launch_bounds__(kBlock) k_select_last(uint32_t depth, uint32_t
       sel[j] = ns;
     }
     // per-chunk counts of members below v (lt) and equal to v (eq), then an
-    // exclusive scan over the node's chunks, lanes owning consecutive chunks
-    const uint64_t per = (chunks + 63) / 64;
-    const uint64_t c0 = lane * per;
-    uint32_t mlt = 0, meq = 0;
-    for (uint64_t k = 0; k < per; ++k) {
-      const uint64_t ch = c0 + k;
-      if (ch >= chunks) break;
-      const uint32_t* row = rows + ch * kRowStride;
-      mlt += row[257] + row[b];
-      meq += row[b + 1] - row[b];
-    }
-    uint32_t rl = wave_incl(mlt) - mlt, re = wave_incl(meq) - meq;
-    for (uint64_t k = 0; k < per; ++k) {
-      const uint64_t ch = c0 + k;
-      if (ch >= chunks) break;
-      const uint32_t* row = rows + ch * kRowStride;
-      chunk_base[ch * 2 + 0] = rl;
-      chunk_base[ch * 2 + 1] = re;
-      rl += row[257] + row[b];
-      re += row[b + 1] - row[b];
+    // exclusive scan over the node's chunks in rounds of 64 (chunk = round *
+    // 64 + lane), four rounds of loads in flight
+    uint32_t run_l = 0, run_e = 0;
+    for (uint64_t r0 = 0; r0 < chunks; r0 += 4 * 64) {
+      uint32_t lt[4], eq[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const uint64_t ch = r0 + (uint64_t)u * 64 + lane;
+        lt[u] = eq[u] = 0;
+        if (ch < chunks) {
+          const uint32_t* row = rows + ch * kRowStride;
+          const uint32_t lo = row[b], hi = row[b + 1];
+          lt[u] = row[257] + lo;
+          eq[u] = hi - lo;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const uint64_t ch = r0 + (uint64_t)u * 64 + lane;
+        const uint32_t il = wave_incl(lt[u]), ie = wave_incl(eq[u]);
+        if (ch < chunks) {
+          chunk_base[ch * 2 + 0] = run_l + il - lt[u];
+          chunk_base[ch * 2 + 1] = run_e + ie - eq[u];
+        }
+        run_l += (uint32_t)__builtin_amdgcn_readlane((int)il, 63);
+        run_e += (uint32_t)__builtin_amdgcn_readlane((int)ie, 63);
+      }
     }
   }
 }
