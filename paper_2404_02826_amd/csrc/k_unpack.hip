@@ -69,7 +69,7 @@ __global__ void __launch_bounds__(kBlock) k_dec_meta(uint64_t n_leaves, uint32_t
 }
 
 constexpr uint32_t kLeafStage = 256;     // leaves per block (leaves_per_block)
-constexpr uint32_t kUnpackWords = 1536;  // staged payload words per block (12 KB)
+constexpr uint32_t kUnpackWords = 1534;  // staged payload words per block (+2 zero words: 12 KB)
 
 // Leaf-aligned decoding: a block takes leaves_per_block(r) consecutive
 // leaves, stages their records, bit offsets and payload words with coalesced
@@ -106,6 +106,7 @@ __device__ void unpack_body(uint64_t n, uint32_t layout, uint32_t r, double w,
   const bool staged = w1 - w0 <= kUnpackWords;
   const uint32_t nw = staged ? (uint32_t)(w1 - w0) : 0u;
   for (uint32_t t = threadIdx.x; t < nw; t += kBlock) s_pay[t] = w0 + t < pay_words ? pay[w0 + t] : 0;
+  if (threadIdx.x < 2) s_pay[nw + threadIdx.x] = 0;  // read past the end, then unused
   __syncthreads();
   const uint64_t slot0 = s_rec[0].start;
   const uint64_t slot1 = (uint64_t)s_rec[nlb - 1].start + s_rec[nlb - 1].size;
@@ -114,12 +115,64 @@ __device__ void unpack_body(uint64_t n, uint32_t layout, uint32_t r, double w,
   // aligned array-of-structures output the 4 particles go out as whole
   // 16-byte stores
   const bool vec = layout == BBX_AOS && ((uintptr_t)out & 15) == 0;
+  // staged payload, 16-byte AoS stores, and every member within 64 code bits
+  // (m_d <= G_d + 1, so sum_d (G_d + 1) <= 64 bounds every leaf): the four
+  // slots of a thread decode without branches (below)
+  uint32_t gsum = 0;
+#pragma unroll
+  for (uint32_t d = 0; d < DIMS; ++d) gsum += G[d] + 1;
+  const bool simple = staged && vec && gsum <= 64;
+  const uint32_t bit0 = (uint32_t)(w0 * 64);  // staged bit offsets fit 32 bits
   for (uint64_t gs = (slot0 & ~3ull) + 4ull * threadIdx.x; gs < slot1; gs += 4ull * kBlock) {
     const bool full = vec && gs >= slot0 && gs + 4 <= slot1;
     union {
       T e[4 * DIMS];
       uint4 v[4 * DIMS * sizeof(T) / 16];
     } o;
+    if (simple && full) {
+      uint32_t a = 0, z = nlb - 1;  // last staged leaf starting at or before gs
+      while (a < z) {
+        const uint32_t mid = (a + z + 1) >> 1;
+        if (s_rec[mid].start <= gs)
+          a = mid;
+        else
+          z = mid - 1;
+      }
+#pragma unroll
+      for (uint32_t k = 0; k < 4; ++k) {
+        const uint32_t p = (uint32_t)(gs + k);
+        while (a + 1 < nlb && s_rec[a + 1].start <= p) ++a;
+        const LeafRec rec = s_rec[a];
+        const uint32_t j = p - rec.start;
+        const uint32_t mm[3] = {rec.m & 0xffu, DIMS > 1 ? (rec.m >> 8) & 0xffu : 0u,
+                                DIMS > 2 ? (rec.m >> 16) & 0xffu : 0u};
+        const uint32_t summ = mm[0] + mm[1] + mm[2];
+        // member j > 0 holds payload code j - 1; the reference reads a code
+        // it does not use
+        const uint32_t at = (uint32_t)s_off[a] - bit0 + (j ? j - 1 : 0u) * summ;
+        const uint32_t wi = at >> 6, sh = at & 63u;
+        const uint64_t lo = s_pay[wi], hi = s_pay[wi + 1];
+        const uint64_t v = sh ? (lo >> sh) | (hi << (64 - sh)) : lo;
+        const uint32_t fo[3] = {0u, mm[0], mm[0] + mm[1]};
+#pragma unroll
+        for (uint32_t d = 0; d < DIMS; ++d) {
+          const uint32_t half = (1u << mm[d]) >> 1;
+          const uint32_t u = (uint32_t)(v >> fo[d]) & ((1u << mm[d]) - 1u);
+          if (j && mm[d] && !u) corrupt = true;
+          const int64_t q = (int64_t)rec.qref[d] + (j ? (int64_t)u - (int64_t)half : 0);
+          uint32_t qq = (uint32_t)q;
+          if ((uint64_t)q >= (1ull << G[d])) {
+            corrupt = true;
+            qq = 0;
+          }
+          o.e[k * DIMS + d] = (T)(origin[d] + (double)qq * w);
+        }
+      }
+      uint4* dst = (uint4*)(out + gs * dims);
+#pragma unroll
+      for (uint32_t i = 0; i < 4 * DIMS * sizeof(T) / 16; ++i) dst[i] = o.v[i];
+      continue;
+    }
     const uint64_t pfirst = gs > slot0 ? gs : slot0;
     uint32_t a = 0, z = nlb - 1;  // last staged leaf starting at or before pfirst
     while (a < z) {
@@ -202,7 +255,7 @@ __global__ void __launch_bounds__(kBlock) k_unpack(uint64_t n, uint32_t dims, ui
   if (P->status != BBX_OK) return;
   __shared__ LeafRec s_rec[kLeafStage];
   __shared__ uint64_t s_off[kLeafStage];
-  __shared__ uint64_t s_pay[kUnpackWords];
+  __shared__ uint64_t s_pay[kUnpackWords + 2];
   const double origin[3] = {o0, o1, o2};
   const uint32_t G[3] = {G0, G1, G2};
   const uint64_t* pay = (const uint64_t*)(stream + kHeaderBytes + ((meta_bits + 63) / 64) * 8);
