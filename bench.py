@@ -29,6 +29,8 @@ WORKLOADS = {
     "cosmology-2^24-f32-xi1e-4": ("cosmology", 1 << 24, "float32", 1e-4),
     "cosmology-2^24-f32-xi1e-3": ("cosmology", 1 << 24, "float32", 1e-3),
     "uniform-65536-f32-xi1e-3": ("uniform", 65536, "float32", 1e-3),
+    # fusion-shaped 2-D set of the size of the paper's XGC Poincare data
+    "poincare-2d-13077313-f32": ("poincare", 13077313, "float32", 1e-4),
 }
 
 
@@ -38,19 +40,21 @@ def log(*a):
 
 def make_points(kind, n, dtype):
     import numpy as np
-    from synth import cosmology, fluid, fluid_lattice_dims, uniform_cube
+    from synth import cosmology, fluid, fluid_lattice_dims, poincare, uniform_cube
     dt = np.float32 if dtype == "float32" else np.float64
     if kind == "fluid":
         return fluid(*fluid_lattice_dims(n), seed=4, dtype=dt)
+    if kind == "poincare":
+        return poincare(n, seed=8, dtype=dt)
     if kind == "cosmology":
         return cosmology(n, seed=2, dtype=dt)
     return uniform_cube(n, seed=1, dtype=dt)
 
 
-# Algorithmic bytes per particle of each kernel (u16 codes, 3-D, no perm):
-# what the kernel must read and write, not what it happens to move.
-def kernel_bytes_per_particle(name, key_bytes, in_bytes, stream_bytes_pp):
-    kb = 3 * key_bytes
+# Algorithmic bytes per particle of each kernel (no perm): what the kernel
+# must read and write, not what it happens to move.
+def kernel_bytes_per_particle(name, key_bytes, in_bytes, stream_bytes_pp, dims=3):
+    kb = dims * key_bytes
     return {
         "range_minmax": in_bytes,
         "quantize": in_bytes + kb,
@@ -524,7 +528,8 @@ def main():
     torch.cuda.synchronize()
     B_in = x.numel() * x.element_size()
 
-    comp = bbx.Compressor(n, 3, x.dtype, leaf_size=args.leaf_size, tile=args.tile)
+    dims = int(x.shape[1])
+    comp = bbx.Compressor(n, dims, x.dtype, leaf_size=args.leaf_size, tile=args.tile)
     s = comp(x, xi)
     S = s.numel()
     header = s[:128].cpu().numpy().tobytes()
@@ -580,13 +585,13 @@ def main():
             step()
         torch.cuda.synchronize()
     h = np.frombuffer(header, dtype=np.uint8)
-    G = [int(h[88 + d]) for d in range(3)]
+    G = [int(h[88 + d]) for d in range(dims)]
     key_bytes = 2 if max(G) <= 16 else 4
-    in_pp = 3 * x.element_size()
+    in_pp = dims * x.element_size()
     S_pp = S / n
     dominant = max(prof.items(), key=lambda kv: kv[1][1])
     dname, (dcount, dms) = dominant
-    bpp = kernel_bytes_per_particle(dname, key_bytes, in_pp, S_pp)
+    bpp = kernel_bytes_per_particle(dname, key_bytes, in_pp, S_pp, dims)
     avg_ms = dms / dcount
     roofline = None
     if bpp is not None:
@@ -605,7 +610,8 @@ def main():
     # ---- error bound on the measured output (sampled slots)
     perm_check = None
     try:
-        pc = bbx.Compressor(n, 3, x.dtype, leaf_size=args.leaf_size, tile=args.tile, want_perm=True)
+        pc = bbx.Compressor(n, dims, x.dtype, leaf_size=args.leaf_size, tile=args.tile,
+                            want_perm=True)
         s2 = pc(x, xi)
         assert s2.numel() == S
         perm = pc.perm[:n].long()
@@ -642,7 +648,7 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "n": n, "input": dtype, "eb_rel": xi,
+        "config": {"workload": args.workload, "n": n, "dims": dims, "input": dtype, "eb_rel": xi,
                    "leaf_size": args.leaf_size, "stream_bytes": S, "cr": round(B_in / S, 4),
                    "bpp": round(8 * S / n, 4),
                    "compress_gbps": round(B_in / (mc * 1e-3) / 1e9, 2),

@@ -2,7 +2,7 @@
 
 This package holds no compressor arithmetic: it only draws particle
 positions with the shapes and value distributions of the paper's workloads
-(cosmology- and fluid-shaped sets, Table 2 of the paper), since the paper's
+(cosmology-, fluid- and fusion-shaped sets, Table 2 of the paper), since the paper's
 datasets are not available.
 """
 from .generators import (  # noqa: F401
@@ -10,6 +10,7 @@ from .generators import (  # noqa: F401
     cosmology,
     fluid,
     fluid_lattice_dims,
+    poincare,
     batch_plan,
     batch_set,
     batch_sets,

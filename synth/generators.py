@@ -5,8 +5,9 @@ requested floating type, in shuffled storage order (particle data carries no
 spatial coherence in its storage order, Section 2 of the paper).  The
 recipes stand in for the paper's benchmark sets (Table 2): a uniform cube,
 a cosmology-shaped set (uniform background plus Gaussian halos, Nyx/HACC
-style) and a fluid-shaped set (jittered lattice displaced by a smooth vortex
-field, SPH/FPM style).  Nothing here knows about quantization, trees or bit
+style), a fluid-shaped set (jittered lattice displaced by a smooth vortex
+field, SPH/FPM style) and a fusion-shaped 2-D set (Poincare-plot-like flux
+surfaces and island chains, XGC style).  Nothing here knows about quantization, trees or bit
 packing.
 """
 from __future__ import annotations
@@ -109,6 +110,54 @@ def fluid(nx: int, ny: int, nz: int, seed: int = 4, amp: float = 2.0,
         p[:, 1] += d1
         p[:, 2] += d2
         out[k * slab:(k + 1) * slab] = p
+    perm = rng.permutation(n)
+    return np.ascontiguousarray(out[perm])
+
+
+def poincare(n: int, seed: int = 8, dtype=np.float32) -> np.ndarray:
+    """Fusion-shaped 2-D set (R, Z): a Poincare-plot-like cross-section of a
+    tokamak plasma, standing in for the XGC Poincare data of Table 2.
+
+    Points lie on curves rather than filling the plane, with very uneven
+    density: 70% on 600 nested flux surfaces (minor radius rho = 0.57 sqrt(u),
+    u uniform; poloidal angle uniform), 20% on three island chains (m = 3, 4,
+    5 islands around the surfaces rho = 0.33, 0.45, 0.54; each point on a
+    closed loop of relative size s ~ U(0.2, 1) around an island's O-point) and
+    10% in a chaotic edge band rho ~ U(0.576, 0.624).  (rho, theta) map to an
+    elongated, triangular, egg-shaped section R = 1.7 + rho cos(theta +
+    0.35 sin theta) + 0.1 rho sin^2 theta, Z = 1.7 rho sin theta, plus
+    N(0, 1e-4) jitter; storage order is shuffled.
+    """
+    dt = np.dtype(dtype)
+    rng = _rng(seed)
+    a = 0.6
+    n_isl = int(round(0.2 * n))
+    n_edge = int(round(0.1 * n))
+    n_surf = n - n_isl - n_edge
+    two_pi = 2.0 * math.pi
+    surfaces = 0.95 * a * np.sqrt(rng.random(600))
+    rho_s = surfaces[rng.integers(0, 600, size=n_surf)]
+    th_s = rng.random(n_surf) * two_pi
+    chains = np.array([[0.55 * a, 3, 0.030 * a], [0.75 * a, 4, 0.025 * a], [0.90 * a, 5, 0.020 * a]])
+    c = chains[rng.integers(0, 3, size=n_isl)]
+    r_c, m_c, w_c = c[:, 0], c[:, 1], c[:, 2]
+    k = np.floor(rng.random(n_isl) * m_c)
+    t = rng.random(n_isl) * two_pi
+    sz = rng.uniform(0.2, 1.0, size=n_isl)
+    rho_i = r_c + w_c * sz * np.sin(t)
+    th_i = two_pi * (k + 0.25) / m_c + (w_c / r_c) * 2.0 * sz * np.cos(t)
+    rho_e = a * rng.uniform(0.96, 1.04, size=n_edge)
+    th_e = rng.random(n_edge) * two_pi
+    rho = np.concatenate([rho_s, rho_i, rho_e])
+    th = np.concatenate([th_s, th_i, th_e])
+    del rho_s, th_s, rho_i, th_i, rho_e, th_e, c, k, t, sz
+    pos = np.empty((n, 2), dtype=np.float64)
+    pos[:, 0] = 1.7 + rho * np.cos(th + 0.35 * np.sin(th)) + 0.1 * rho * np.sin(th) ** 2
+    pos[:, 1] = 1.7 * rho * np.sin(th)
+    del rho, th
+    pos += rng.normal(0.0, 1e-4, size=(n, 2))
+    out = pos.astype(dt)
+    del pos
     perm = rng.permutation(n)
     return np.ascontiguousarray(out[perm])
 

@@ -13,7 +13,7 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 import numpy as np  # noqa: E402
 
-from synth import cosmology, fluid, sha256_of, uniform_cube  # noqa: E402
+from synth import cosmology, fluid, poincare, sha256_of, uniform_cube  # noqa: E402
 
 CASES = {
     "uniform_65536_seed1_f32": lambda: uniform_cube(65536, seed=1),
@@ -21,6 +21,7 @@ CASES = {
     "cosmology_4096_seed3_f64": lambda: cosmology(4096, seed=3, dtype=np.float64),
     "fluid_32x32x32_seed4_f32": lambda: fluid(32, 32, 32, seed=4),
     "fluid_16x16x8_seed4_f64": lambda: fluid(16, 16, 8, seed=4, dtype=np.float64),
+    "poincare_65536_seed8_f32": lambda: poincare(65536, seed=8),
 }
 
 

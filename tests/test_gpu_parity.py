@@ -16,7 +16,7 @@ import pytest
 
 import props
 from oracle import Oracle, OracleError
-from synth import cosmology, fluid, fluid_lattice_dims, uniform_cube
+from synth import cosmology, fluid, fluid_lattice_dims, poincare, uniform_cube
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -47,6 +47,8 @@ def gen(kind, n, dims=3, dtype=np.float32, seed=1):
         return cosmology(n, seed=seed, dims=dims, dtype=dtype)
     if kind == "fluid":
         return fluid(*fluid_lattice_dims(n), seed=seed, dtype=dtype)
+    if kind == "poincare":  # 2-D, points on curves
+        return poincare(n, seed=seed, dtype=dtype)
     if kind == "ties":  # heavy duplication: many equal codes at every median
         rng = np.random.default_rng(seed)
         return (np.floor(rng.random((n, dims)) * 5) / 5).astype(dtype)
@@ -112,6 +114,9 @@ CASES = [
     ("cosmology", 60000, 3, np.float32, 1e-4, "rel", 60000),  # single leaf
     ("uniform", 10000, 3, np.float32, 1e-3, "rel", 4999),     # leaves of r+1 split once more
     ("ties", 50000, 2, np.float64, 1e-3, "rel", 2100),
+    ("poincare", 100003, 2, np.float32, 1e-4, "rel", 32),     # fusion-shaped 2-D
+    ("poincare", 300007, 2, np.float32, 1e-3, "rel", 16),
+    ("poincare", 65536, 2, np.float64, 1e-6, "rel", 32),
 ]
 
 
