@@ -76,12 +76,20 @@ typedef enum { BBX_AOS = 0, BBX_SOA = 1 } bbx_layout;         /* [n][dims] or [d
 
 /* Compression parameters.  leaf_size is r of Sec. 4.1 (a node of <= r
  * particles is not split); it changes the stream.  tile_override selects the
- * on-chip tile capacity (0 = library default); it never changes the stream. */
+ * on-chip tile capacity (0 = library default); it never changes the stream.
+ * ref_rule picks each leaf's reference particle (the bit box centre, Sec.
+ * 4.1): 0 = the member nearest the centre of the leaf's AABB (the paper's
+ * rule; squared distance in doubled code space, ties to the first member in
+ * leaf order); 1 = the member whose Eq. 2 widths sum_d m_d are smallest
+ * (ties to the first member), which minimises the leaf's payload bits for
+ * its AABB.  Either stream decodes the same way (the reference's code is
+ * stored). */
 typedef struct {
   uint32_t leaf_size;     /* r >= 1 */
   uint32_t eb_mode;       /* bbx_eb_mode */
   uint32_t layout;        /* bbx_layout of the input positions */
   uint32_t tile_override; /* 0 (= 256), 256 or 512 */
+  uint32_t ref_rule;      /* 0 (AABB centre) or 1 (fewest code bits) */
 } bbx_params;
 
 /* Worst-case stream size in bytes for n particles of the given type. */

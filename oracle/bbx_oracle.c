@@ -303,9 +303,11 @@ uint64_t bbxo_leaf_count(uint64_t n, uint32_t r) {
 
 /* Sec. 4.1 bit box of one leaf: AABB, reference = member nearest the AABB
  * centre (squared Euclidean distance in code space, doubled to stay integral;
- * ties to the first member), then Eq. 2 per axis. */
+ * ties to the first member), then Eq. 2 per axis.  rule 1 (an ablation of
+ * that choice): the reference is the member whose own Eq. 2 widths, taken
+ * against the AABB, have the smallest sum (ties to the first member). */
 static void bit_box(const uint32_t* q, uint64_t n, uint32_t dims, const uint32_t* mem,
-                    uint64_t s, uint32_t* ref_out, uint32_t m_out[3]) {
+                    uint64_t s, int rule, uint32_t* ref_out, uint32_t m_out[3]) {
   uint64_t qmin[3] = {0, 0, 0}, qmax[3] = {0, 0, 0};
   for (uint32_t d = 0; d < dims; d++) {
     qmin[d] = qmax[d] = q[(uint64_t)d * n + mem[0]];
@@ -319,6 +321,11 @@ static void bit_box(const uint32_t* q, uint64_t n, uint32_t dims, const uint32_t
   for (uint64_t j = 0; j < s; j++) {
     uint64_t dist = 0;
     for (uint32_t d = 0; d < dims; d++) {
+      if (rule == 1) {
+        uint64_t c = q[(uint64_t)d * n + mem[j]];
+        dist += bbxo_bits_for_offset(c - qmin[d] > qmax[d] - c ? c - qmin[d] : qmax[d] - c);
+        continue;
+      }
       int64_t t = 2 * (int64_t)q[(uint64_t)d * n + mem[j]] - (int64_t)(qmin[d] + qmax[d]);
       dist += (uint64_t)(t * t);
     }
@@ -371,7 +378,8 @@ static void core_free(core_t* c) {
 }
 
 static int check_args(uint64_t n, uint32_t dims, int dtype, int layout, double eb, int eb_mode,
-                      uint32_t r) {
+                      uint32_t r, int ref_rule) {
+  if (ref_rule != 0 && ref_rule != 1) return BBXO_EINVAL;
   if (dtype != 0 && dtype != 1) return BBXO_EINVAL;
   if (layout != 0 && layout != 1) return BBXO_EINVAL;
   if (eb_mode != 0 && eb_mode != 1) return BBXO_EINVAL;
@@ -383,9 +391,9 @@ static int check_args(uint64_t n, uint32_t dims, int dtype, int layout, double e
 }
 
 static int core_run(core_t* c, const void* pos, uint64_t n, uint32_t dims, int dtype, int layout,
-                    double eb, int eb_mode, uint32_t r) {
+                    double eb, int eb_mode, uint32_t r, int ref_rule) {
   memset(c, 0, sizeof(*c));
-  int st = check_args(n, dims, dtype, layout, eb, eb_mode, r);
+  int st = check_args(n, dims, dtype, layout, eb, eb_mode, r, ref_rule);
   if (st) return st;
   params_t* p = &c->p;
   p->n = n;
@@ -457,7 +465,8 @@ static int core_run(core_t* c, const void* pos, uint64_t n, uint32_t dims, int d
   c->payload_bits = 0;
   for (uint64_t i = 0; i < nl; i++) {
     uint32_t m[3];
-    bit_box(c->q, n, dims, c->order + c->leaf_start[i], c->leaf_size[i], &c->leaf_ref[i], m);
+    bit_box(c->q, n, dims, c->order + c->leaf_start[i], c->leaf_size[i], ref_rule,
+            &c->leaf_ref[i], m);
     uint32_t sm = 0;
     for (uint32_t d = 0; d < 3; d++) {
       c->leaf_m[i * 3 + d] = m[d];
@@ -507,8 +516,15 @@ static void write_header(uint8_t* h, const core_t* c) {
 int bbxo_compress(const void* pos, uint64_t n, uint32_t dims, int dtype, int layout, double eb,
                   int eb_mode, uint32_t r, uint8_t* out, uint64_t out_cap, uint64_t* out_size,
                   uint32_t* perm) {
+  return bbxo_compress_ex(pos, n, dims, dtype, layout, eb, eb_mode, r, 0, out, out_cap, out_size,
+                          perm);
+}
+
+int bbxo_compress_ex(const void* pos, uint64_t n, uint32_t dims, int dtype, int layout, double eb,
+                     int eb_mode, uint32_t r, int ref_rule, uint8_t* out, uint64_t out_cap,
+                     uint64_t* out_size, uint32_t* perm) {
   core_t c;
-  int st = core_run(&c, pos, n, dims, dtype, layout, eb, eb_mode, r);
+  int st = core_run(&c, pos, n, dims, dtype, layout, eb, eb_mode, r, ref_rule);
   if (st) {
     core_free(&c);
     return st;
@@ -572,8 +588,16 @@ int bbxo_stages(const void* pos, uint64_t n, uint32_t dims, int dtype, int layou
                 int eb_mode, uint32_t r, uint32_t* q, uint32_t* order, uint64_t max_leaves,
                 uint32_t* leaf_start, uint32_t* leaf_size, uint32_t* leaf_ref, uint8_t* leaf_m,
                 uint64_t* leaf_bits, double* scal) {
+  return bbxo_stages_ex(pos, n, dims, dtype, layout, eb, eb_mode, r, 0, q, order, max_leaves,
+                        leaf_start, leaf_size, leaf_ref, leaf_m, leaf_bits, scal);
+}
+
+int bbxo_stages_ex(const void* pos, uint64_t n, uint32_t dims, int dtype, int layout, double eb,
+                   int eb_mode, uint32_t r, int ref_rule, uint32_t* q, uint32_t* order,
+                   uint64_t max_leaves, uint32_t* leaf_start, uint32_t* leaf_size,
+                   uint32_t* leaf_ref, uint8_t* leaf_m, uint64_t* leaf_bits, double* scal) {
   core_t c;
-  int st = core_run(&c, pos, n, dims, dtype, layout, eb, eb_mode, r);
+  int st = core_run(&c, pos, n, dims, dtype, layout, eb, eb_mode, r, ref_rule);
   if (st) {
     core_free(&c);
     return st;

@@ -44,6 +44,14 @@ int bbxo_compress(const void* pos, uint64_t n, uint32_t dims, int dtype, int lay
                   double eb, int eb_mode, uint32_t r,
                   uint8_t* out, uint64_t out_cap, uint64_t* out_size, uint32_t* perm);
 
+/* As bbxo_compress, with the leaf reference rule: 0 = the member nearest the
+ * AABB centre (the paper's rule, what bbxo_compress uses), 1 = the member
+ * whose Eq. 2 widths against the AABB have the smallest sum; ties to the
+ * first member in leaf order either way. */
+int bbxo_compress_ex(const void* pos, uint64_t n, uint32_t dims, int dtype, int layout,
+                     double eb, int eb_mode, uint32_t r, int ref_rule,
+                     uint8_t* out, uint64_t out_cap, uint64_t* out_size, uint32_t* perm);
+
 /* Decompress a stream into pos (n*dims values of the stream's dtype). */
 int bbxo_decompress(const uint8_t* stream, uint64_t size, void* pos, uint64_t pos_cap_bytes,
                     int layout);
@@ -62,6 +70,13 @@ int bbxo_stages(const void* pos, uint64_t n, uint32_t dims, int dtype, int layou
                 uint32_t* q, uint32_t* order, uint64_t max_leaves,
                 uint32_t* leaf_start, uint32_t* leaf_size, uint32_t* leaf_ref,
                 uint8_t* leaf_m, uint64_t* leaf_bits, double* scal);
+
+/* As bbxo_stages, with the leaf reference rule of bbxo_compress_ex. */
+int bbxo_stages_ex(const void* pos, uint64_t n, uint32_t dims, int dtype, int layout,
+                   double eb, int eb_mode, uint32_t r, int ref_rule,
+                   uint32_t* q, uint32_t* order, uint64_t max_leaves,
+                   uint32_t* leaf_start, uint32_t* leaf_size, uint32_t* leaf_ref,
+                   uint8_t* leaf_m, uint64_t* leaf_bits, double* scal);
 
 /* Number of leaves of the size-only recursion for n particles, capacity r. */
 uint64_t bbxo_leaf_count(uint64_t n, uint32_t r);

@@ -7,7 +7,9 @@ instead of a bit-at-a-time byte writer.
 
   * bin widths: smallest m whose Eq. 1 predictable range holds every member
     (searched m = 0, 1, 2, ...), instead of the bitlen(D) + 1 closed form;
-  * reference: exact rational distance to the AABB centre (Sec. 4.1);
+  * reference: exact rational distance to the AABB centre (Sec. 4.1), or
+    (reference rule 1) every member tried as the reference, keeping the one
+    whose searched widths have the smallest sum;
   * tree: the median definition applied with ``sorted`` at every node.
 """
 from __future__ import annotations
@@ -94,18 +96,21 @@ def minimal_bits(offsets) -> int:
         m += 1
 
 
-def bit_box(codes, members, dims):
-    lo = [min(codes[i][d] for i in members) for d in range(dims)]
-    hi = [max(codes[i][d] for i in members) for d in range(dims)]
-    centre = [Fraction(lo[d] + hi[d], 2) for d in range(dims)]
-    best = min(range(len(members)),
-               key=lambda j: (sum((codes[members[j]][d] - centre[d]) ** 2 for d in range(dims)), j))
-    ref = members[best]
-    m = [minimal_bits([codes[i][d] - codes[ref][d] for i in members]) for d in range(dims)]
-    return best, m
+def bit_box(codes, members, dims, ref_rule=0):
+    def widths(ref):
+        return [minimal_bits([codes[i][d] - codes[ref][d] for i in members]) for d in range(dims)]
+    if ref_rule == 1:
+        best = min(range(len(members)), key=lambda j: (sum(widths(members[j])), j))
+    else:
+        lo = [min(codes[i][d] for i in members) for d in range(dims)]
+        hi = [max(codes[i][d] for i in members) for d in range(dims)]
+        centre = [Fraction(lo[d] + hi[d], 2) for d in range(dims)]
+        best = min(range(len(members)),
+                   key=lambda j: (sum((codes[members[j]][d] - centre[d]) ** 2 for d in range(dims)), j))
+    return best, widths(members[best])
 
 
-def compress(points: np.ndarray, eb: float, eb_mode: str = "rel", r: int = 32):
+def compress(points: np.ndarray, eb: float, eb_mode: str = "rel", r: int = 32, ref_rule: int = 0):
     """Returns (stream bytes, perm, details) for an (n, dims) float array."""
     n, dims = points.shape
     f32 = points.dtype == np.float32
@@ -121,7 +126,7 @@ def compress(points: np.ndarray, eb: float, eb_mode: str = "rel", r: int = 32):
     perm = []
     boxes = []
     for members in leaves:
-        j, m = bit_box(codes, members, dims)
+        j, m = bit_box(codes, members, dims, ref_rule)
         ref = members[j]
         boxes.append((j, m))
         for d in range(dims):

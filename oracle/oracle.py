@@ -51,6 +51,12 @@ class Oracle:
         lib.bbxo_stages.restype = i32
         lib.bbxo_stages.argtypes = [vp, u64, u32, i32, i32, dbl, i32, u32, vp, vp, u64, vp, vp,
                                     vp, vp, vp, vp]
+        lib.bbxo_compress_ex.restype = i32
+        lib.bbxo_compress_ex.argtypes = [vp, u64, u32, i32, i32, dbl, i32, u32, i32, vp, u64,
+                                         C.POINTER(u64), vp]
+        lib.bbxo_stages_ex.restype = i32
+        lib.bbxo_stages_ex.argtypes = [vp, u64, u32, i32, i32, dbl, i32, u32, i32, vp, vp, u64,
+                                       vp, vp, vp, vp, vp, vp]
         lib.bbxo_leaf_count.restype = u64
         lib.bbxo_leaf_count.argtypes = [u64, u32]
         lib.bbxo_bits_for_offset.restype = u32
@@ -79,7 +85,8 @@ class Oracle:
 
     # -- API ---------------------------------------------------------------
     def compress(self, pos: np.ndarray, eb: float, eb_mode: str = "rel", r: int = 32,
-                 layout: str = "aos", want_perm: bool = False, out_cap: int | None = None):
+                 layout: str = "aos", want_perm: bool = False, out_cap: int | None = None,
+                 ref_rule: int = 0):
         pos = np.ascontiguousarray(pos)
         n, dims, lay = self._shape(pos, layout)
         dt = _dt(pos)
@@ -87,9 +94,10 @@ class Oracle:
         out = np.zeros(max(cap, 1), dtype=np.uint8)
         size = C.c_uint64(0)
         perm = np.zeros(max(n, 1), dtype=np.uint32) if want_perm else None
-        st = self.lib.bbxo_compress(pos.ctypes.data, n, dims, dt, lay, float(eb),
-                                    0 if eb_mode == "rel" else 1, r, out.ctypes.data, cap,
-                                    C.byref(size), None if perm is None else perm.ctypes.data)
+        st = self.lib.bbxo_compress_ex(pos.ctypes.data, n, dims, dt, lay, float(eb),
+                                       0 if eb_mode == "rel" else 1, r, int(ref_rule),
+                                       out.ctypes.data, cap, C.byref(size),
+                                       None if perm is None else perm.ctypes.data)
         if st:
             raise OracleError(st)
         stream = out[: size.value].tobytes()
@@ -115,7 +123,7 @@ class Oracle:
         return out
 
     def stages(self, pos: np.ndarray, eb: float, eb_mode: str = "rel", r: int = 32,
-               layout: str = "aos") -> dict:
+               layout: str = "aos", ref_rule: int = 0) -> dict:
         pos = np.ascontiguousarray(pos)
         n, dims, lay = self._shape(pos, layout)
         nl = self.leaf_count(n, r)
@@ -127,10 +135,11 @@ class Oracle:
         lm = np.zeros((max(nl, 1), 3), dtype=np.uint8)
         lb = np.zeros(max(nl, 1), dtype=np.uint64)
         sc = np.zeros(16, dtype=np.float64)
-        st = self.lib.bbxo_stages(pos.ctypes.data, n, dims, _dt(pos), lay, float(eb),
-                                  0 if eb_mode == "rel" else 1, r, q.ctypes.data,
-                                  order.ctypes.data, nl, ls.ctypes.data, lz.ctypes.data,
-                                  lr.ctypes.data, lm.ctypes.data, lb.ctypes.data, sc.ctypes.data)
+        st = self.lib.bbxo_stages_ex(pos.ctypes.data, n, dims, _dt(pos), lay, float(eb),
+                                     0 if eb_mode == "rel" else 1, r, int(ref_rule),
+                                     q.ctypes.data, order.ctypes.data, nl, ls.ctypes.data,
+                                     lz.ctypes.data, lr.ctypes.data, lm.ctypes.data,
+                                     lb.ctypes.data, sc.ctypes.data)
         if st:
             raise OracleError(st)
         return {

@@ -28,7 +28,7 @@ class BitboxError(RuntimeError):
 
 class _Params(C.Structure):
     _fields_ = [("leaf_size", C.c_uint32), ("eb_mode", C.c_uint32), ("layout", C.c_uint32),
-                ("tile_override", C.c_uint32)]
+                ("tile_override", C.c_uint32), ("ref_rule", C.c_uint32)]
 
 
 class _Set(C.Structure):
@@ -159,8 +159,8 @@ def _shape(pos: torch.Tensor, layout: str):
     raise ValueError(layout)
 
 
-def _params(leaf_size: int, eb_mode: str, layout: int, tile: int) -> _Params:
-    return _Params(leaf_size, REL if eb_mode == "rel" else ABS, layout, tile)
+def _params(leaf_size: int, eb_mode: str, layout: int, tile: int, ref_rule: int = 0) -> _Params:
+    return _Params(leaf_size, REL if eb_mode == "rel" else ABS, layout, tile, ref_rule)
 
 
 def compress_bound(n: int, dims: int = 3, dtype=torch.float32) -> int:
@@ -168,8 +168,9 @@ def compress_bound(n: int, dims: int = 3, dtype=torch.float32) -> int:
 
 
 def compress_workspace_size(n: int, dims: int = 3, dtype=torch.float32, leaf_size: int = 32,
-                            eb_mode: str = "rel", layout: str = "aos", tile: int = 0) -> int:
-    p = _params(leaf_size, eb_mode, AOS if layout == "aos" else SOA, tile)
+                            eb_mode: str = "rel", layout: str = "aos", tile: int = 0,
+                            ref_rule: int = 0) -> int:
+    p = _params(leaf_size, eb_mode, AOS if layout == "aos" else SOA, tile, ref_rule)
     code = F32 if dtype == torch.float32 else F64
     lib = load()
     v = int(lib.bbx_compress_workspace_size(n, dims, code, C.byref(p)))
@@ -191,12 +192,13 @@ class Compressor:
 
     def __init__(self, n: int, dims: int = 3, dtype=torch.float32, leaf_size: int = 32,
                  eb_mode: str = "rel", layout: str = "aos", tile: int = 0, want_perm: bool = False,
-                 device="cuda"):
+                 device="cuda", ref_rule: int = 0):
         self.n, self.dims, self.dtype = n, dims, dtype
         self.layout = layout
-        self.params = _params(leaf_size, eb_mode, AOS if layout == "aos" else SOA, tile)
+        self.params = _params(leaf_size, eb_mode, AOS if layout == "aos" else SOA, tile, ref_rule)
         lib = load()
-        self.ws_size = compress_workspace_size(n, dims, dtype, leaf_size, eb_mode, layout, tile)
+        self.ws_size = compress_workspace_size(n, dims, dtype, leaf_size, eb_mode, layout, tile,
+                                               ref_rule)
         self.ws = torch.empty(self.ws_size, dtype=torch.uint8, device=device)
         self.cap = compress_bound(n, dims, dtype)
         self.out = torch.empty((self.cap + 7) // 8 * 8, dtype=torch.uint8, device=device)
@@ -306,7 +308,8 @@ class BatchCompressor:
             S = arr[i]
             S.d_pos = pos.data_ptr() if n else None
             S.n, S.dims, S.dtype, S.eb = n, dims, _dtype_code(pos), float(spec["eb"])
-            S.params = _params(spec.get("leaf_size", 32), spec.get("eb_mode", "rel"), lay, tile)
+            S.params = _params(spec.get("leaf_size", 32), spec.get("eb_mode", "rel"), lay, tile,
+                               spec.get("ref_rule", 0))
             S.d_out = base + offs[i]
             S.out_cap = caps[i]
             S.d_size = self.d_size.data_ptr() + 8 * i
@@ -399,11 +402,11 @@ class Server:
         self._meta = {}
 
     def submit_compress(self, pos: torch.Tensor, eb: float, eb_mode: str = "rel",
-                        leaf_size: int = 32, layout: str = "aos") -> int:
+                        leaf_size: int = 32, layout: str = "aos", ref_rule: int = 0) -> int:
         n, dims, lay = _shape(pos, layout)
         if not pos.is_cuda or not pos.is_contiguous():
             raise ValueError("positions must be a contiguous device tensor")
-        prm = _params(leaf_size, eb_mode, lay, 0)
+        prm = _params(leaf_size, eb_mode, lay, 0, ref_rule)
         jid = C.c_uint64()
         _check(self._lib.bbx_server_submit_compress(self._h, pos.data_ptr() if n else None, n, dims,
                                                     _dtype_code(pos), float(eb), C.byref(prm),
@@ -498,11 +501,15 @@ def decompress_workspace_size(header: bytes) -> int:
 
 
 def compress(pos: torch.Tensor, eb: float, eb_mode: str = "rel", leaf_size: int = 32,
-             layout: str = "aos", want_perm: bool = False, tile: int = 0, stream=None):
+             layout: str = "aos", want_perm: bool = False, tile: int = 0, stream=None,
+             ref_rule: int = 0):
     """One-shot compress of a device tensor; returns the stream as a uint8
-    device tensor (and the int32 source index of every output slot)."""
+    device tensor (and the int32 source index of every output slot).
+    ref_rule: 0 = leaf reference nearest the AABB centre (the paper's rule),
+    1 = the member with the fewest code bits."""
     n, dims, _ = _shape(pos, layout)
-    c = Compressor(n, dims, pos.dtype, leaf_size, eb_mode, layout, tile, want_perm, pos.device)
+    c = Compressor(n, dims, pos.dtype, leaf_size, eb_mode, layout, tile, want_perm, pos.device,
+                   ref_rule)
     s = c(pos.contiguous(), eb, stream).clone()
     if want_perm:
         return s, c.perm[:n].clone()

@@ -135,6 +135,7 @@ static bbx_status check_compress_args(uint64_t n, uint32_t dims, bbx_dtype dtype
   if (!isfinite(eb) || !(eb > 0.0)) return fail(BBX_EINVAL, "eb must be finite and > 0");
   if (prm->tile_override != 0 && prm->tile_override != 256 && prm->tile_override != 512)
     return fail(BBX_EINVAL, "tile_override must be 0, 256 or 512");
+  if (prm->ref_rule > 1) return fail(BBX_EINVAL, "ref_rule must be 0 or 1");
   if (dims != 2 && dims != 3) return fail(BBX_EUNSUPPORTED, "dims must be 2 or 3");
   if (n >= (1ull << 32)) return fail(BBX_EUNSUPPORTED, "n must be below 2^32");
   return BBX_OK;
@@ -200,6 +201,7 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
     D.dtype = (uint32_t)I.dtype;
     D.layout = I.prm.layout;
     D.r = I.prm.leaf_size;
+    D.ref_rule = I.prm.ref_rule;
     D.eb_mode = I.prm.eb_mode;
     D.mbits = I.dtype == BBX_F32 ? 5u : 6u;
     const uint64_t n = I.n;

@@ -83,6 +83,7 @@ struct SetDesc {
   uint32_t final_buf;     // key buffer that ends in output-slot order
   uint32_t mm_blocks;     // blocks of the range pass
   uint32_t level_blocks;  // block target of the set's global levels (level_shape)
+  uint32_t ref_rule;      // leaf reference: 0 nearest the AABB centre, 1 fewest code bits
   uint64_t n_leaves;
   uint64_t key_off;       // byte offset into each key buffer (capacity dims*n*4)
   uint64_t idx_off;       // u32 offset into each index buffer

@@ -8,9 +8,10 @@
 // followed by a stable partition of a u16 position permutation (the codes
 // never move in LDS).  Leaves are then handled by aligned lane groups (a
 // power of two >= the leaf size, up to the wavefront): AABB, reference =
-// member nearest the AABB centre (squared distance in doubled code space,
-// ties to the first member), Eq. 2's widths m_d = bitlen(D_d) + 1 (0 when
-// D_d = 0).  Finally the node is written back in output-slot order (reference
+// member nearest the AABB centre (squared distance in doubled code space) or,
+// with reference rule 1, the member with the smallest sum of Eq. 2 widths
+// (ties to the first member either way), Eq. 2's widths m_d = bitlen(D_d) + 1
+// (0 when D_d = 0).  Finally the node is written back in output-slot order (reference
 // first in each leaf) with coalesced stores.
 //
 // k_bigleaf: one workgroup per leaf when leaves exceed the tile capacity.
@@ -82,7 +83,7 @@ template <int TILE, typename KL, bool TRACK, typename DT>
 __device__ void tile_bitboxes(WaveTile<TILE, KL, TRACK>& sm, int cur, uint32_t nl, uint32_t gs, uint32_t dims,
                               uint32_t t0, uint32_t t1, uint32_t t2, uint64_t tst, uint64_t first_leaf,
                               uint64_t n_leaves, DevParams* P, LeafRec* leaves,
-                              uint64_t* leaf_bits) {
+                              uint64_t* leaf_bits, uint32_t rule) {
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t lpw = 64 / gs;
   const uint32_t sub = lane & (gs - 1);
@@ -114,12 +115,23 @@ __device__ void tile_bitboxes(WaveTile<TILE, KL, TRACK>& sm, int cur, uint32_t n
     for (uint32_t t = sub; t < lz; t += gs) {
       const uint32_t slot = sm.Pm[cur][ls + t];
       DT dist = 0;
+      if (rule) {  // fewest code bits: sum_d m_d with this member as the reference
+        uint32_t bits = 0;
 #pragma unroll
-      for (uint32_t d = 0; d < 3; ++d) {
-        if (d >= dims) break;
-        const DT q2 = 2 * (DT)sm.K[d][slot];
-        const DT a = q2 > C[d] ? q2 - C[d] : C[d] - q2;
-        dist += a * a;
+        for (uint32_t d = 0; d < 3; ++d) {
+          if (d >= dims) break;
+          const uint32_t q = sm.K[d][slot];
+          bits += width_of(umax32(q - mn[d], mx[d] - q));
+        }
+        dist = (DT)bits;
+      } else {  // nearest the AABB centre
+#pragma unroll
+        for (uint32_t d = 0; d < 3; ++d) {
+          if (d >= dims) break;
+          const DT q2 = 2 * (DT)sm.K[d][slot];
+          const DT a = q2 > C[d] ? q2 - C[d] : C[d] - q2;
+          dist += a * a;
+        }
       }
       if (dist < best) best = dist, bpos = t;  // t increases: ties keep the first
     }
@@ -172,7 +184,7 @@ __device__ void tile_body(WaveTile<TILE, KL, TRACK>& sm, uint64_t j, uint32_t K0
                           uint64_t kst, uint32_t dims, uint32_t r, uint64_t n_leaves,
                           const TreeGeom& g, DevParams* P, KT* keys, const uint32_t* idx,
                           uint32_t* perm, LeafRec* leaves, uint64_t* leaf_bits, uint32_t* defer,
-                          uint32_t gtile) {
+                          uint32_t gtile, uint32_t rule) {
   constexpr int E = TILE / 64;
   const uint32_t lane = threadIdx.x & 63;
   uint64_t tst, s0_64;
@@ -440,10 +452,10 @@ __device__ void tile_body(WaveTile<TILE, KL, TRACK>& sm, uint64_t j, uint32_t K0
   const uint32_t span = umax32(Gt[0], umax32(Gt[1], Gt[2]));
   if (span <= 14)
     tile_bitboxes<TILE, KL, TRACK, uint32_t>(sm, cur, nl, gs, dims, tmin[0], tmin[1], tmin[2], tst,
-                                  first_leaf, n_leaves, P, leaves, leaf_bits);
+                                  first_leaf, n_leaves, P, leaves, leaf_bits, rule);
   else
     tile_bitboxes<TILE, KL, TRACK, uint64_t>(sm, cur, nl, gs, dims, tmin[0], tmin[1], tmin[2], tst,
-                                  first_leaf, n_leaves, P, leaves, leaf_bits);
+                                  first_leaf, n_leaves, P, leaves, leaf_bits, rule);
   wave_sync();
 
   // ---- write the node back in output-slot order (reference first per leaf)
@@ -479,11 +491,11 @@ __device__ void tile_node(uint32_t nsets, const uint64_t* pre, const SetDesc* se
   if (P->key16)
     tile_body<TILE, uint16_t, KL, TRACK>(sm, j, S.gl, S.n, S.kst, S.dims, S.r, S.n_leaves, S.geom,
                                          P, (uint16_t*)keys, idx, S.perm, leaves, leaf_bits, defer,
-                                         gtile);
+                                         gtile, S.ref_rule);
   else
     tile_body<TILE, uint32_t, KL, TRACK>(sm, j, S.gl, S.n, S.kst, S.dims, S.r, S.n_leaves, S.geom,
                                          P, (uint32_t*)keys, idx, S.perm, leaves, leaf_bits, defer,
-                                         gtile);
+                                         gtile, S.ref_rule);
 }
 
 // first pass: every tile, 16-bit tile codes
@@ -545,7 +557,7 @@ template <typename KT>
 __device__ void bigleaf_body(uint64_t i, uint64_t n /* code-array stride */, uint32_t dims,
                              const TreeGeom& g,
                              const KT* src, KT* dst, const uint32_t* idx, uint32_t* perm,
-                             LeafRec* leaves, uint64_t* leaf_bits) {
+                             LeafRec* leaves, uint64_t* leaf_bits, uint32_t rule) {
   __shared__ uint32_t red[kBlock / 64];
   __shared__ uint64_t rd[kBlock / 64];
   __shared__ uint32_t rp[kBlock / 64];
@@ -568,7 +580,15 @@ __device__ void bigleaf_body(uint64_t i, uint64_t n /* code-array stride */, uin
   for (uint64_t p = threadIdx.x; p < sz; p += kBlock) {
     uint32_t q[3] = {0, 0, 0};
     for (uint32_t d = 0; d < dims; ++d) q[d] = src[(uint64_t)d * n + st + p];
-    uint64_t dist = sqdist3(q, C, dims);
+    uint64_t dist;
+    if (rule) {  // fewest code bits
+      uint32_t bits = 0;
+      for (uint32_t d = 0; d < dims; ++d)
+        bits += width_of(q[d] - mn[d] > mx[d] - q[d] ? q[d] - mn[d] : mx[d] - q[d]);
+      dist = bits;
+    } else {  // nearest the AABB centre
+      dist = sqdist3(q, C, dims);
+    }
     if (dist < best) best = dist, bpos = (uint32_t)p;
   }
   wargmin(best, bpos);
@@ -621,10 +641,10 @@ __global__ void __launch_bounds__(kBlock) k_bigleaf(uint32_t nsets, const uint64
   const uint64_t i = blockIdx.x - pre[s];
   if (P->key16)
     bigleaf_body<uint16_t>(i, S.kst, S.dims, S.geom, (const uint16_t*)src, (uint16_t*)dst, idx,
-                           S.perm, leaves0 + S.leaf_off, leaf_bits0 + S.leaf_off);
+                           S.perm, leaves0 + S.leaf_off, leaf_bits0 + S.leaf_off, S.ref_rule);
   else
     bigleaf_body<uint32_t>(i, S.kst, S.dims, S.geom, (const uint32_t*)src, (uint32_t*)dst, idx,
-                           S.perm, leaves0 + S.leaf_off, leaf_bits0 + S.leaf_off);
+                           S.perm, leaves0 + S.leaf_off, leaf_bits0 + S.leaf_off, S.ref_rule);
 }
 
 template <int TILE, bool TRACK>

@@ -163,3 +163,24 @@ def test_batch_graph_replay(orc, bbx):
             _check_set(orc, host, sp, res[i], bc.perms[i], f"replay {rep} set {i}")
             if rep == 0:
                 assert res[i].cpu().numpy().tobytes() == eager[i]
+
+
+def test_batch_mixed_reference_rules(orc, bbx):
+    """Sets of one batch may use different reference rules; each matches the
+    oracle under its own rule."""
+    cases = [("cosmology", 30011, 3, np.float32, 1e-4, "rel", 32, "aos", False),
+             ("uniform", 9001, 2, np.float32, 1e-3, "rel", 16, "aos", True),
+             ("cosmology", 60000, 3, np.float32, 1e-4, "rel", 700, "soa", False)]
+    hosts, specs = _specs(cases, seed0=40)
+    rules = [1, 0, 1]
+    for spec, rule in zip(specs, rules):
+        spec["ref_rule"] = rule
+    _say("batch with reference rules", rules)
+    bc = bbx.BatchCompressor(specs)
+    res = bc()
+    for i, (host, spec) in enumerate(zip(hosts, specs)):
+        ref = orc.compress(host, spec["eb"], spec["eb_mode"], spec["leaf_size"],
+                           layout=spec["layout"], want_perm=spec["want_perm"],
+                           ref_rule=spec["ref_rule"])
+        ref_s = ref[0] if spec["want_perm"] else ref
+        assert res[i].cpu().numpy().tobytes() == ref_s, f"set {i} rule {rules[i]}"

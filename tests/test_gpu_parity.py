@@ -55,10 +55,10 @@ def gen(kind, n, dims=3, dtype=np.float32, seed=1):
     raise ValueError(kind)
 
 
-def gpu_roundtrip(bbx, pts, eb, mode, r, layout="aos", tile=0):
+def gpu_roundtrip(bbx, pts, eb, mode, r, layout="aos", tile=0, ref_rule=0):
     host = pts if layout == "aos" else np.ascontiguousarray(pts.T)
     x = torch.from_numpy(host).cuda()
-    s, perm = bbx.compress(x, eb, mode, r, layout, want_perm=True, tile=tile)
+    s, perm = bbx.compress(x, eb, mode, r, layout, want_perm=True, tile=tile, ref_rule=ref_rule)
     dec = bbx.decompress(s, layout)
     torch.cuda.synchronize()
     return s.cpu().numpy().tobytes(), perm.cpu().numpy().astype(np.uint32), dec.cpu().numpy()
@@ -71,10 +71,11 @@ def first_diff(a: bytes, b: bytes):
     return min(len(a), len(b))
 
 
-def check_parity(orc, bbx, pts, eb, mode, r, layout="aos", tile=0):
+def check_parity(orc, bbx, pts, eb, mode, r, layout="aos", tile=0, ref_rule=0):
     host = pts if layout == "aos" else np.ascontiguousarray(pts.T)
-    ref_s, ref_p = orc.compress(host, eb, mode, r, layout=layout, want_perm=True)
-    got_s, got_p, got_d = gpu_roundtrip(bbx, pts, eb, mode, r, layout, tile)
+    ref_s, ref_p = orc.compress(host, eb, mode, r, layout=layout, want_perm=True,
+                                ref_rule=ref_rule)
+    got_s, got_p, got_d = gpu_roundtrip(bbx, pts, eb, mode, r, layout, tile, ref_rule)
     if got_s != ref_s:
         h = props.parse_header(ref_s)
         mb = 8 * ((h["meta_bits"] + 63) // 64)
@@ -135,6 +136,29 @@ def test_layout_and_tile_invariance(orc, bbx, layout, tile):
     _say("layout", layout, "tile", tile)
     pts = cosmology(70001, seed=5)
     check_parity(orc, bbx, pts, 1e-4, "rel", 32, layout=layout, tile=tile)
+
+
+RULE1_CASES = [
+    ("cosmology", 100003, 3, np.float32, 1e-4, "rel", 32, 0),
+    ("cosmology", 100003, 3, np.float32, 1e-4, "rel", 32, 512),
+    ("ties", 20000, 3, np.float32, 1e-2, "rel", 7, 0),
+    ("uniform", 4097, 2, np.float32, 1e-3, "rel", 5, 0),
+    ("cosmology", 20011, 3, np.float64, 1e-6, "rel", 33, 0),      # u32 codes
+    ("cosmology", 150001, 3, np.float32, 1e-7, "rel", 32, 0),     # wide tiles
+    ("cosmology", 60000, 3, np.float32, 1e-4, "rel", 3000, 0),    # leaves above the tile
+    ("poincare", 100003, 2, np.float32, 1e-4, "rel", 32, 0),
+]
+
+
+@pytest.mark.parametrize("case", RULE1_CASES, ids=lambda c: f"{c[0]}-n{c[1]}-d{c[2]}-r{c[6]}-t{c[7]}")
+def test_reference_rule_fewest_bits(orc, bbx, case):
+    """Reference rule 1 (fewest code bits) matches the oracle's rule 1 byte for
+    byte in every leaf stage (tiles of 256 / 512, the 32-bit tile pass,
+    leaves above the tile capacity)."""
+    kind, n, dims, dt, eb, mode, r, tile = case
+    _say("rule 1", case)
+    pts = gen(kind, n, dims, dt, seed=n % 89 + 3)
+    check_parity(orc, bbx, pts, eb, mode, r, tile=tile, ref_rule=1)
 
 
 def test_empty(orc, bbx):

@@ -345,3 +345,29 @@ def test_hypothesis_properties(oracle, data):
     props.check_bound(pts, dec, perm, h["eb_abs"])
     s2, p2, _ = brute.compress(pts, eb, "rel", r)
     assert stream == s2 and np.array_equal(perm, p2)
+
+
+def test_reference_rule_fewest_bits_brute_force(oracle):
+    """Reference rule 1 (an ablation of the paper's AABB-centre rule): the C
+    oracle's closed form (widths from the AABB extremes) equals the exhaustive
+    search that tries every member as the reference, byte for byte."""
+    for pts, eb, mode, r in pins.tiny_cases(seed=211, count=60):
+        s1, p1 = oracle.compress(pts, eb, mode, r, want_perm=True, ref_rule=1)
+        s2, p2, _ = brute.compress(pts, eb, mode, r, ref_rule=1)
+        assert s1 == s2 and np.array_equal(p1, p2), (pts.shape, eb, mode, r)
+
+
+def test_reference_rule_fewest_bits_never_costs_more(oracle):
+    """Per leaf, rule 1's width sum is at most rule 0's (same tree, same AABB),
+    and its stream still reconstructs every particle within the bound."""
+    pts = cosmology(20000, seed=23)
+    a = oracle.stages(pts, 1e-4, "rel", r=32, ref_rule=0)
+    b = oracle.stages(pts, 1e-4, "rel", r=32, ref_rule=1)
+    assert np.array_equal(a["order"], b["order"]) and np.array_equal(a["leaf_size"], b["leaf_size"])
+    sa = a["leaf_m"].astype(int).sum(axis=1)
+    sb = b["leaf_m"].astype(int).sum(axis=1)
+    assert (sb <= sa).all() and (sb < sa).any()
+    s, perm = oracle.compress(pts, 1e-4, "rel", 32, want_perm=True, ref_rule=1)
+    out = oracle.decompress(s).astype(np.float64)
+    err = np.abs(out - pts[perm].astype(np.float64)).max()
+    assert err <= a["eb_abs"]
