@@ -16,7 +16,9 @@
  *   4. bit box per leaf     Sec. 4.1 (AABB, reference = particle nearest the
  *                           AABB centre, Eq. 2 bit widths)
  *   5. offsets + packing    Sec. 4.2 (sequence layout, 5/6-bit width fields;
- *                           storage-cost model) in a structure-of-arrays form
+ *                           storage-cost model) in a structure-of-arrays form;
+ *                           the reference stored as its codes, or (ref_mode
+ *                           1) losslessly as its original coordinates
  *   6. unpack + dequantize  Sec. 3 (reconstruction at the bin centre)
  *
  * Parity pins live in tests/: a worked example of Sec. 4.1, a pure-Python
@@ -120,6 +122,20 @@ typedef struct {
 static double coord(const void* pos, const params_t* p, int layout, uint64_t i, uint32_t d) {
   uint64_t k = (layout == 0) ? i * p->dims + d : (uint64_t)d * p->n + i;
   return p->dtype == 0 ? (double)((const float*)pos)[k] : ((const double*)pos)[k];
+}
+
+/* Bits of one stored coordinate (M of Sec. 4.2), and a coordinate's bits. */
+static uint32_t coord_bits(int dtype) { return dtype == 0 ? 32u : 64u; }
+static uint64_t coord_raw(const void* pos, const params_t* p, int layout, uint64_t i, uint32_t d) {
+  uint64_t k = (layout == 0) ? i * p->dims + d : (uint64_t)d * p->n + i;
+  if (p->dtype == 0) {
+    uint32_t u;
+    memcpy(&u, (const float*)pos + k, 4);
+    return u;
+  }
+  uint64_t u;
+  memcpy(&u, (const double*)pos + k, 8);
+  return u;
 }
 
 /* Sec. 3 quantization: index of the bin of width w (= 2*eb_eff) holding x,
@@ -364,6 +380,7 @@ typedef struct {
   uint32_t* leaf_m; /* [nleaves][3] */
   uint64_t* leaf_bits;
   uint64_t meta_bits, payload_bits;
+  int ref_mode; /* 0: reference stored as its code; 1: as its original coordinates */
 } core_t;
 
 static void core_free(core_t* c) {
@@ -378,8 +395,9 @@ static void core_free(core_t* c) {
 }
 
 static int check_args(uint64_t n, uint32_t dims, int dtype, int layout, double eb, int eb_mode,
-                      uint32_t r, int ref_rule) {
+                      uint32_t r, int ref_rule, int ref_mode) {
   if (ref_rule != 0 && ref_rule != 1) return BBXO_EINVAL;
+  if (ref_mode != 0 && ref_mode != 1) return BBXO_EINVAL;
   if (dtype != 0 && dtype != 1) return BBXO_EINVAL;
   if (layout != 0 && layout != 1) return BBXO_EINVAL;
   if (eb_mode != 0 && eb_mode != 1) return BBXO_EINVAL;
@@ -391,10 +409,11 @@ static int check_args(uint64_t n, uint32_t dims, int dtype, int layout, double e
 }
 
 static int core_run(core_t* c, const void* pos, uint64_t n, uint32_t dims, int dtype, int layout,
-                    double eb, int eb_mode, uint32_t r, int ref_rule) {
+                    double eb, int eb_mode, uint32_t r, int ref_rule, int ref_mode) {
   memset(c, 0, sizeof(*c));
-  int st = check_args(n, dims, dtype, layout, eb, eb_mode, r, ref_rule);
+  int st = check_args(n, dims, dtype, layout, eb, eb_mode, r, ref_rule, ref_mode);
   if (st) return st;
+  c->ref_mode = ref_mode;
   params_t* p = &c->p;
   p->n = n;
   p->dims = dims;
@@ -458,9 +477,11 @@ static int core_run(core_t* c, const void* pos, uint64_t n, uint32_t dims, int d
   free(sz);
   if (!same) return BBXO_ENOMEM; /* internal inconsistency: never expected */
 
-  /* Step 4: bit box of every leaf; Step 5: section sizes. */
+  /* Step 4: bit box of every leaf; Step 5: section sizes.  The reference
+   * field of a meta record holds its code (G_d bits per axis), or with
+   * ref_mode 1 its original coordinate (M = 32 or 64 bits per axis). */
   uint32_t sumG = 0;
-  for (uint32_t d = 0; d < dims; d++) sumG += p->G[d];
+  for (uint32_t d = 0; d < dims; d++) sumG += ref_mode ? coord_bits(dtype) : p->G[d];
   c->meta_bits = nl * (uint64_t)(dims * p->mbits + sumG);
   c->payload_bits = 0;
   for (uint64_t i = 0; i < nl; i++) {
@@ -481,10 +502,16 @@ static int core_run(core_t* c, const void* pos, uint64_t n, uint32_t dims, int d
 static uint64_t words_bytes(uint64_t bits) { return ((bits + 63) / 64) * 8; }
 
 uint64_t bbxo_compress_bound(uint64_t n, uint32_t dims, int dtype) {
+  return bbxo_compress_bound_mode(n, dims, dtype, 0);
+}
+
+uint64_t bbxo_compress_bound_mode(uint64_t n, uint32_t dims, int dtype, int ref_mode) {
   uint64_t mbits = dtype == 1 ? 6 : 5;
   /* every particle is either a reference (dims*(mbits + G) <= dims*(mbits+30)
-   * meta bits) or a member (dims*31 payload bits at most) */
-  return HEADER_BYTES + 16 + words_bytes(n * dims * (mbits + 30));
+   * meta bits, or dims*(mbits + M) with ref_mode 1) or a member (dims*31
+   * payload bits at most) */
+  uint64_t ref = ref_mode ? coord_bits(dtype) : 30;
+  return HEADER_BYTES + 16 + words_bytes(n * dims * (mbits + ref));
 }
 
 static void write_header(uint8_t* h, const core_t* c) {
@@ -498,7 +525,7 @@ static void write_header(uint8_t* h, const core_t* c) {
   put_u32le(h + 16, p->r);
   h[20] = (uint8_t)p->eb_mode;
   h[21] = 0; /* split rule: median, round-robin axis */
-  h[22] = 0; /* reference stored as its code */
+  h[22] = (uint8_t)c->ref_mode; /* reference stored as its code (0) or coordinates (1) */
   h[23] = (uint8_t)p->mbits;
   put_f64le(h + 24, p->eb_user);
   put_f64le(h + 32, p->eb_abs);
@@ -516,15 +543,15 @@ static void write_header(uint8_t* h, const core_t* c) {
 int bbxo_compress(const void* pos, uint64_t n, uint32_t dims, int dtype, int layout, double eb,
                   int eb_mode, uint32_t r, uint8_t* out, uint64_t out_cap, uint64_t* out_size,
                   uint32_t* perm) {
-  return bbxo_compress_ex(pos, n, dims, dtype, layout, eb, eb_mode, r, 0, out, out_cap, out_size,
-                          perm);
+  return bbxo_compress_ex(pos, n, dims, dtype, layout, eb, eb_mode, r, 0, 0, out, out_cap,
+                          out_size, perm);
 }
 
 int bbxo_compress_ex(const void* pos, uint64_t n, uint32_t dims, int dtype, int layout, double eb,
-                     int eb_mode, uint32_t r, int ref_rule, uint8_t* out, uint64_t out_cap,
-                     uint64_t* out_size, uint32_t* perm) {
+                     int eb_mode, uint32_t r, int ref_rule, int ref_mode, uint8_t* out,
+                     uint64_t out_cap, uint64_t* out_size, uint32_t* perm) {
   core_t c;
-  int st = core_run(&c, pos, n, dims, dtype, layout, eb, eb_mode, r, ref_rule);
+  int st = core_run(&c, pos, n, dims, dtype, layout, eb, eb_mode, r, ref_rule, ref_mode);
   if (st) {
     core_free(&c);
     return st;
@@ -546,11 +573,22 @@ int bbxo_compress_ex(const void* pos, uint64_t n, uint32_t dims, int dtype, int 
     const uint32_t* mem = c.order + c.leaf_start[i];
     uint32_t s = c.leaf_size[i], ref = c.leaf_ref[i];
     const uint32_t* m = c.leaf_m + 3 * i;
-    /* meta record: widths m_d (mbits each), then the reference's codes */
+    /* meta record: widths m_d (mbits each), then the reference's codes, or
+     * with ref_mode 1 the bits of its original coordinates (Sec. 4.2) */
     for (uint32_t d = 0; d < p->dims; d++) put_bits(meta, mpos, m[d], p->mbits), mpos += p->mbits;
     for (uint32_t d = 0; d < p->dims; d++) {
-      put_bits(meta, mpos, c.q[(uint64_t)d * n + mem[ref]], p->G[d]);
-      mpos += p->G[d];
+      if (ref_mode) {
+#if MUT(16)
+        uint32_t src = mem[0];
+#else
+        uint32_t src = mem[ref];
+#endif
+        put_bits(meta, mpos, coord_raw(pos, p, layout, src, d), coord_bits(dtype));
+        mpos += coord_bits(dtype);
+      } else {
+        put_bits(meta, mpos, c.q[(uint64_t)d * n + mem[ref]], p->G[d]);
+        mpos += p->G[d];
+      }
     }
     /* payload: every other member in leaf order, codes o + 2^(m-1) per axis */
     for (uint32_t jj = 0; jj < s; jj++) {
@@ -597,7 +635,7 @@ int bbxo_stages_ex(const void* pos, uint64_t n, uint32_t dims, int dtype, int la
                    uint64_t max_leaves, uint32_t* leaf_start, uint32_t* leaf_size,
                    uint32_t* leaf_ref, uint8_t* leaf_m, uint64_t* leaf_bits, double* scal) {
   core_t c;
-  int st = core_run(&c, pos, n, dims, dtype, layout, eb, eb_mode, r, ref_rule);
+  int st = core_run(&c, pos, n, dims, dtype, layout, eb, eb_mode, r, ref_rule, 0);
   if (st) {
     core_free(&c);
     return st;
@@ -645,10 +683,12 @@ int bbxo_decompress(const uint8_t* s, uint64_t size, void* pos, uint64_t pos_cap
   uint64_t n = get_u64le(s + 8);
   uint32_t r = get_u32le(s + 16);
   uint32_t eb_mode = s[20], mbits = s[23];
-  if (dtype > 1 || (dims != 2 && dims != 3) || eb_mode > 1 || s[21] != 0 || s[22] != 0)
+  if (dtype > 1 || (dims != 2 && dims != 3) || eb_mode > 1 || s[21] != 0 || s[22] > 1)
     return BBXO_ECORRUPT;
+  int ref_mode = s[22];
+  uint32_t M = coord_bits(dtype);
   if (mbits != (dtype == 0 ? 5u : 6u) || r == 0 || n >= ((uint64_t)1 << 32)) return BBXO_ECORRUPT;
-  double w = get_f64le(s + 48);
+  double w = get_f64le(s + 48), inv_w = get_f64le(s + 56);
   double origin[3];
   uint32_t G[3], sumG = 0;
   for (uint32_t d = 0; d < 3; d++) {
@@ -658,13 +698,14 @@ int bbxo_decompress(const uint8_t* s, uint64_t size, void* pos, uint64_t pos_cap
     if (G[d] > 30 || !isfinite(origin[d])) return BBXO_ECORRUPT;
     sumG += G[d];
   }
-  if (!isfinite(w) || w < 0.0) return BBXO_ECORRUPT;
+  if (!isfinite(w) || w < 0.0 || !isfinite(inv_w) || inv_w < 0.0) return BBXO_ECORRUPT;
   for (int k = 91; k < 96; k++)
     if (s[k] != 0) return BBXO_ECORRUPT;
   uint64_t nl = get_u64le(s + 96), meta_bits = get_u64le(s + 104), payload_bits = get_u64le(s + 112);
   if (get_u64le(s + 120) != 0) return BBXO_ECORRUPT;
   if (nl != bbxo_leaf_count(n, r)) return BBXO_ECORRUPT;
-  if (meta_bits != nl * (uint64_t)(dims * mbits + sumG)) return BBXO_ECORRUPT;
+  if (meta_bits != nl * (uint64_t)(dims * mbits + (ref_mode ? dims * M : sumG)))
+    return BBXO_ECORRUPT;
   if (payload_bits > n * (uint64_t)dims * 31u) return BBXO_ECORRUPT;
   uint64_t mb = words_bytes(meta_bits), pb = words_bytes(payload_bits);
   if (size < HEADER_BYTES + mb + pb) return BBXO_ECORRUPT;
@@ -676,9 +717,11 @@ int bbxo_decompress(const uint8_t* s, uint64_t size, void* pos, uint64_t pos_cap
   const uint8_t* pay = meta + mb;
   uint32_t* sizes = (uint32_t*)malloc((size_t)nl * sizeof(uint32_t));
   uint32_t* codes = (uint32_t*)malloc((size_t)(n * dims) * sizeof(uint32_t)); /* [slot][d] */
-  if (!sizes || !codes) {
+  uint64_t* rraw = (uint64_t*)malloc((size_t)(nl * dims) * sizeof(uint64_t)); /* ref_mode 1 */
+  if (!sizes || !codes || !rraw) {
     free(sizes);
     free(codes);
+    free(rraw);
     return BBXO_ENOMEM;
   }
   uint64_t k = 0;
@@ -694,8 +737,28 @@ int bbxo_decompress(const uint8_t* s, uint64_t size, void* pos, uint64_t pos_cap
       if (m[d] == 1 || m[d] > 31 || m[d] > G[d] + 1) st = BBXO_ECORRUPT;
     }
     for (uint32_t d = 0; d < dims; d++) {
-      qref[d] = get_bits(meta, mpos, G[d]);
-      mpos += G[d];
+      if (ref_mode) {
+        /* the stored coordinate; its code is what the encoder's quantization
+         * gave it (same origin, same 1/w, same FP64 operations) */
+        uint64_t raw = get_bits(meta, mpos, M);
+        mpos += M;
+        rraw[i * dims + d] = raw;
+        double x;
+        if (dtype == 0) {
+          uint32_t u32 = (uint32_t)raw;
+          float f;
+          memcpy(&f, &u32, 4);
+          x = (double)f;
+        } else {
+          memcpy(&x, &raw, 8);
+        }
+        double qd = isfinite(x) ? quantize_real(x, origin[d], inv_w) : -1.0;
+        if (!(qd >= 0.0 && qd < (double)((uint64_t)1 << G[d]))) st = BBXO_ECORRUPT;
+        qref[d] = st ? 0 : (uint64_t)qd;
+      } else {
+        qref[d] = get_bits(meta, mpos, G[d]);
+        mpos += G[d];
+      }
     }
     if (st) break;
     uint32_t sm = 0;
@@ -738,8 +801,24 @@ int bbxo_decompress(const uint8_t* s, uint64_t size, void* pos, uint64_t pos_cap
         else
           ((double*)pos)[kk] = v;
       }
+#if !MUT(17)
+    /* ref_mode 1: each leaf's reference (its first slot) is its stored
+     * coordinate, exactly */
+    for (uint64_t i = 0, slot0 = 0; ref_mode && i < nl; slot0 += sizes[i], i++)
+      for (uint32_t d = 0; d < dims; d++) {
+        uint64_t kk = (layout == 0) ? slot0 * dims + d : (uint64_t)d * n + slot0;
+        uint64_t raw = rraw[i * dims + d];
+        if (dtype == 0) {
+          uint32_t u32 = (uint32_t)raw;
+          memcpy((float*)pos + kk, &u32, 4);
+        } else {
+          memcpy((double*)pos + kk, &raw, 8);
+        }
+      }
+#endif
   }
   free(sizes);
   free(codes);
+  free(rraw);
   return st;
 }

@@ -30,8 +30,10 @@ enum {
   BBXO_ENOMEM = 7
 };
 
-/* Worst-case stream size in bytes for n particles. */
+/* Worst-case stream size in bytes for n particles (reference stored as its
+ * code), and for a given reference storage mode (see bbxo_compress_ex). */
 uint64_t bbxo_compress_bound(uint64_t n, uint32_t dims, int dtype);
+uint64_t bbxo_compress_bound_mode(uint64_t n, uint32_t dims, int dtype, int ref_mode);
 
 /*
  * Compress n particles.  pos: dtype 0 = float32, 1 = float64; layout 0 =
@@ -47,9 +49,12 @@ int bbxo_compress(const void* pos, uint64_t n, uint32_t dims, int dtype, int lay
 /* As bbxo_compress, with the leaf reference rule: 0 = the member nearest the
  * AABB centre (the paper's rule, what bbxo_compress uses), 1 = the member
  * whose Eq. 2 widths against the AABB have the smallest sum; ties to the
- * first member in leaf order either way. */
+ * first member in leaf order either way.  ref_mode selects how a meta record
+ * stores the reference: 0 = its codes (G_d bits per axis, what bbxo_compress
+ * uses), 1 = the bits of its original coordinates (32 or 64 per axis, the
+ * paper's lossless centre of Sec. 4.2), which decode exactly. */
 int bbxo_compress_ex(const void* pos, uint64_t n, uint32_t dims, int dtype, int layout,
-                     double eb, int eb_mode, uint32_t r, int ref_rule,
+                     double eb, int eb_mode, uint32_t r, int ref_rule, int ref_mode,
                      uint8_t* out, uint64_t out_cap, uint64_t* out_size, uint32_t* perm);
 
 /* Decompress a stream into pos (n*dims values of the stream's dtype). */

@@ -110,11 +110,27 @@ def bit_box(codes, members, dims, ref_rule=0):
     return best, widths(members[best])
 
 
-def compress(points: np.ndarray, eb: float, eb_mode: str = "rel", r: int = 32, ref_rule: int = 0):
-    """Returns (stream bytes, perm, details) for an (n, dims) float array."""
+def _raw_bits(points: np.ndarray, i: int, d: int) -> int:
+    """IEEE bits of one input coordinate (32 or 64 of them)."""
+    v = points[i, d:d + 1]
+    return int(v.view(np.uint32 if points.dtype == np.float32 else np.uint64)[0])
+
+
+def _from_bits(raw: int, f32: bool):
+    if f32:
+        return np.array([raw], dtype=np.uint32).view(np.float32)[0]
+    return np.array([raw], dtype=np.uint64).view(np.float64)[0]
+
+
+def compress(points: np.ndarray, eb: float, eb_mode: str = "rel", r: int = 32, ref_rule: int = 0,
+             ref_mode: int = 0):
+    """Returns (stream bytes, perm, details) for an (n, dims) float array.
+    ref_mode 1 stores each reference's original coordinates (32 or 64 bits
+    per axis) in place of its codes."""
     n, dims = points.shape
     f32 = points.dtype == np.float32
     mbits = 5 if f32 else 6
+    M = 32 if f32 else 64
     prm = bound_params(points, eb, eb_mode)
     codes = quantize(points, prm)
     leaves = kd_leaves(codes, r, dims)
@@ -133,8 +149,12 @@ def compress(points: np.ndarray, eb: float, eb_mode: str = "rel", r: int = 32, r
             meta |= m[d] << mpos
             mpos += mbits
         for d in range(dims):
-            meta |= codes[ref][d] << mpos
-            mpos += G[d]
+            if ref_mode:
+                meta |= _raw_bits(points, ref, d) << mpos
+                mpos += M
+            else:
+                meta |= codes[ref][d] << mpos
+                mpos += G[d]
         perm.append(ref)
         for i in members:
             if i == ref:
@@ -150,7 +170,7 @@ def compress(points: np.ndarray, eb: float, eb_mode: str = "rel", r: int = 32, r
     G3 = list(G) + [0] * (3 - dims)
     header = struct.pack(
         "<4sHBBQIBBBBddddd3d3B5xQQQQ", b"BBX1", 1, 0 if f32 else 1, dims, n, r,
-        0 if eb_mode == "rel" else 1, 0, 0, mbits, eb, prm["eb_abs"], prm["eb_eff"], prm["w"],
+        0 if eb_mode == "rel" else 1, 0, ref_mode, mbits, eb, prm["eb_abs"], prm["eb_eff"], prm["w"],
         prm["inv_w"], *lo3, *G3, len(leaves), mpos, ppos, 0)
     assert len(header) == 128
     stream = header + meta.to_bytes(mbytes, "little") + pay.to_bytes(pbytes, "little")
@@ -160,8 +180,9 @@ def compress(points: np.ndarray, eb: float, eb_mode: str = "rel", r: int = 32, r
 
 def decompress(stream: bytes) -> np.ndarray:
     """Independent decoder for tiny streams (big-integer bit extraction)."""
-    (magic, ver, dt, dims, n, r, mode, _s, _rm, mbits, _eu, _ea, _ee, w, _iw, o0, o1, o2, g0, g1,
-     g2, nl, meta_bits, pay_bits, _res) = struct.unpack("<4sHBBQIBBBBddddd3d3B5xQQQQ", stream[:128])
+    (magic, ver, dt, dims, n, r, mode, _s, ref_mode, mbits, _eu, _ea, _ee, w, inv_w, o0, o1, o2, g0,
+     g1, g2, nl, meta_bits, pay_bits, _res) = struct.unpack("<4sHBBQIBBBBddddd3d3B5xQQQQ",
+                                                            stream[:128])
     assert magic == b"BBX1" and ver == 1
     origin = [o0, o1, o2][:dims]
     G = [g0, g1, g2][:dims]
@@ -181,6 +202,7 @@ def decompress(stream: bytes) -> np.ndarray:
         rec(n)
     assert len(sizes) == nl
     T = np.float32 if dt == 0 else np.float64
+    M = 32 if dt == 0 else 64
     out = np.zeros((n, dims), dtype=T)
     mpos = ppos = slot = 0
     for s in sizes:
@@ -189,9 +211,17 @@ def decompress(stream: bytes) -> np.ndarray:
             m.append((meta >> mpos) & ((1 << mbits) - 1))
             mpos += mbits
         ref = []
+        exact = None
         for d in range(dims):
-            ref.append((meta >> mpos) & ((1 << G[d]) - 1))
-            mpos += G[d]
+            if ref_mode:
+                # the stored coordinate, and the code the encoder gave it
+                x = _from_bits((meta >> mpos) & ((1 << M) - 1), dt == 0)
+                mpos += M
+                exact = (exact or []) + [x]
+                ref.append(math.floor((float(x) - origin[d]) * inv_w + 0.5))
+            else:
+                ref.append((meta >> mpos) & ((1 << G[d]) - 1))
+                mpos += G[d]
         rows = [ref]
         for _ in range(s - 1):
             q = []
@@ -203,8 +233,11 @@ def decompress(stream: bytes) -> np.ndarray:
                 else:
                     q.append(ref[d])
             rows.append(q)
-        for q in rows:
-            out[slot] = [T(origin[d] + float(q[d]) * w) for d in range(dims)]
+        for k, q in enumerate(rows):
+            if k == 0 and exact is not None:
+                out[slot] = exact
+            else:
+                out[slot] = [T(origin[d] + float(q[d]) * w) for d in range(dims)]
             slot += 1
     assert ppos == pay_bits
     return out

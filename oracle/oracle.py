@@ -52,8 +52,10 @@ class Oracle:
         lib.bbxo_stages.argtypes = [vp, u64, u32, i32, i32, dbl, i32, u32, vp, vp, u64, vp, vp,
                                     vp, vp, vp, vp]
         lib.bbxo_compress_ex.restype = i32
-        lib.bbxo_compress_ex.argtypes = [vp, u64, u32, i32, i32, dbl, i32, u32, i32, vp, u64,
-                                         C.POINTER(u64), vp]
+        lib.bbxo_compress_ex.argtypes = [vp, u64, u32, i32, i32, dbl, i32, u32, i32, i32, vp,
+                                         u64, C.POINTER(u64), vp]
+        lib.bbxo_compress_bound_mode.restype = u64
+        lib.bbxo_compress_bound_mode.argtypes = [u64, u32, i32, i32]
         lib.bbxo_stages_ex.restype = i32
         lib.bbxo_stages_ex.argtypes = [vp, u64, u32, i32, i32, dbl, i32, u32, i32, vp, vp, u64,
                                        vp, vp, vp, vp, vp, vp]
@@ -74,8 +76,11 @@ class Oracle:
             return pos.shape[1], pos.shape[0], 1
         raise ValueError(layout)
 
-    def compress_bound(self, n: int, dims: int, dtype) -> int:
-        return int(self.lib.bbxo_compress_bound(n, dims, 0 if np.dtype(dtype) == np.float32 else 1))
+    def compress_bound(self, n: int, dims: int, dtype, ref_mode: int = 0) -> int:
+        dt = 0 if np.dtype(dtype) == np.float32 else 1
+        if ref_mode:
+            return int(self.lib.bbxo_compress_bound_mode(n, dims, dt, int(ref_mode)))
+        return int(self.lib.bbxo_compress_bound(n, dims, dt))
 
     def leaf_count(self, n: int, r: int) -> int:
         return int(self.lib.bbxo_leaf_count(n, r))
@@ -86,17 +91,17 @@ class Oracle:
     # -- API ---------------------------------------------------------------
     def compress(self, pos: np.ndarray, eb: float, eb_mode: str = "rel", r: int = 32,
                  layout: str = "aos", want_perm: bool = False, out_cap: int | None = None,
-                 ref_rule: int = 0):
+                 ref_rule: int = 0, ref_mode: int = 0):
         pos = np.ascontiguousarray(pos)
         n, dims, lay = self._shape(pos, layout)
         dt = _dt(pos)
-        cap = self.compress_bound(n, dims, pos.dtype) if out_cap is None else out_cap
+        cap = self.compress_bound(n, dims, pos.dtype, ref_mode) if out_cap is None else out_cap
         out = np.zeros(max(cap, 1), dtype=np.uint8)
         size = C.c_uint64(0)
         perm = np.zeros(max(n, 1), dtype=np.uint32) if want_perm else None
         st = self.lib.bbxo_compress_ex(pos.ctypes.data, n, dims, dt, lay, float(eb),
                                        0 if eb_mode == "rel" else 1, r, int(ref_rule),
-                                       out.ctypes.data, cap, C.byref(size),
+                                       int(ref_mode), out.ctypes.data, cap, C.byref(size),
                                        None if perm is None else perm.ctypes.data)
         if st:
             raise OracleError(st)

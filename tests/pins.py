@@ -89,11 +89,37 @@ def pin_properties(orc, seed=12, count=30):
         assert len(s) == props.stream_size(h["meta_bits"], h["payload_bits"])
 
 
+def pin_lossless_reference(orc, seed=13, count=30):
+    """Reference stored as its original coordinates (Sec. 4.2 keeps the centre
+    losslessly): the stream equals the brute-force writer's; each leaf's first
+    decoded slot is its reference's input coordinate bit for bit; every other
+    slot decodes as in the code-reference stream (same codes); a meta record
+    is dims * (mbits + M) bits."""
+    for pts, eb, mode, r in tiny_cases(seed, count):
+        n, dims = pts.shape
+        s1, p1 = orc.compress(pts, eb, mode, r, want_perm=True, ref_mode=1)
+        s2, p2, _ = brute.compress(pts, eb, mode, r, ref_mode=1)
+        assert s1 == s2 and np.array_equal(p1, p2), ("lossless-reference stream differs",
+                                                     pts.shape, r, eb, mode)
+        s0, p0 = orc.compress(pts, eb, mode, r, want_perm=True)
+        assert np.array_equal(p0, p1)
+        h = props.parse_header(s1)
+        M = 32 if pts.dtype == np.float32 else 64
+        assert h["ref_mode"] == 1 and h["meta_bits"] == h["n_leaves"] * dims * (h["mbits"] + M)
+        d1, d0 = orc.decompress(s1), orc.decompress(s0)
+        assert np.array_equal(d1, brute.decompress(s2))
+        first = np.zeros(n, dtype=bool)
+        first[np.concatenate([[0], np.cumsum(props.leaf_sizes(n, r))[:-1]]).astype(int)] = True
+        raw = np.uint32 if pts.dtype == np.float32 else np.uint64
+        assert np.array_equal(d1[first].view(raw), pts[p1[first]].view(raw)), "reference not exact"
+        assert np.array_equal(d1[~first], d0[~first]), "members differ from the code stream"
+
+
 def run_battery(orc):
     """Returns the names of the pins that fail."""
     failed = []
     for name, fn in (("worked_example", pin_worked_example), ("brute_force", pin_brute_force),
-                     ("properties", pin_properties)):
+                     ("properties", pin_properties), ("lossless_reference", pin_lossless_reference)):
         try:
             fn(orc)
         except Exception as e:  # noqa: BLE001 -- any failure counts as caught

@@ -29,6 +29,8 @@ MUTANTS = {
     13: "members written in reverse order",
     14: "reference code field one bit too narrow",
     15: "relative bound scaled by the smallest range instead of the largest",
+    16: "lossless reference field holds the leaf's first member, not its reference",
+    17: "lossless reference decoded to its bin centre instead of its stored value",
 }
 
 

@@ -371,3 +371,58 @@ def test_reference_rule_fewest_bits_never_costs_more(oracle):
     out = oracle.decompress(s).astype(np.float64)
     err = np.abs(out - pts[perm].astype(np.float64)).max()
     assert err <= a["eb_abs"]
+
+
+def test_lossless_reference_mode(oracle):
+    """ref_mode 1 (the paper's lossless centre, Sec. 4.2) at a moderate size:
+    references exact, others within the bound and equal to the code-reference
+    decode, and the stream longer by exactly (M - G_d) bits per leaf and axis
+    (before word padding)."""
+    for dt, M in ((np.float32, 32), (np.float64, 64)):
+        pts = cosmology(20000, seed=29, dtype=dt)
+        s0, p0 = oracle.compress(pts, 1e-4, "rel", 32, want_perm=True)
+        s1, p1 = oracle.compress(pts, 1e-4, "rel", 32, want_perm=True, ref_mode=1)
+        assert np.array_equal(p0, p1)
+        h0, h1 = props.parse_header(s0), props.parse_header(s1)
+        assert h1["payload_bits"] == h0["payload_bits"]
+        assert h1["meta_bits"] - h0["meta_bits"] == h0["n_leaves"] * sum(M - g for g in h0["G"])
+        d0, d1 = oracle.decompress(s0), oracle.decompress(s1)
+        sizes = props.leaf_sizes(len(pts), 32)
+        first = np.zeros(len(pts), dtype=bool)
+        first[np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(int)] = True
+        assert np.array_equal(d1[first], pts[p1[first]])
+        assert np.array_equal(d1[~first], d0[~first])
+        props.check_bound(pts, d1, p1, h1["eb_abs"])
+        assert len(s1) <= oracle.compress_bound(len(pts), 3, dt, ref_mode=1)
+        # the code-reference bound is too small for single-particle leaves
+        assert oracle.compress_bound(1000, 3, dt, ref_mode=1) > oracle.compress_bound(1000, 3, dt)
+        s = oracle.compress(pts[:1000], 1e-4, "rel", 1, ref_mode=1)
+        assert len(s) <= oracle.compress_bound(1000, 3, dt, ref_mode=1)
+
+
+def test_lossless_reference_corrupt(oracle):
+    """A stored reference that is not finite, or whose code falls outside
+    [0, 2^G_d), is a corrupt stream; so is a reference-mode byte above 1."""
+    pts = cosmology(2000, seed=31)
+    good = oracle.compress(pts, 1e-3, "rel", 32, ref_mode=1)
+    oracle.decompress(good)
+    h = props.parse_header(good)
+    # first record: dims widths of 5 bits, then the x coordinate's 32 bits
+    off = 128 * 8 + 3 * 5
+    meta = int.from_bytes(good[128:136], "little")
+
+    def with_x(bits):
+        m = (meta & ~(((1 << 32) - 1) << 15)) | (bits << 15)
+        b = bytearray(good)
+        b[128:136] = m.to_bytes(8, "little")
+        return bytes(b)
+
+    assert off // 8 == 129
+    nan = int(np.array([np.nan], dtype=np.float32).view(np.uint32)[0])
+    _expect("ECORRUPT", oracle.decompress, with_x(nan))
+    far = float(h["origin"][0]) - 4.0 * float(h["w"])  # code -4
+    _expect("ECORRUPT", oracle.decompress,
+            with_x(int(np.array([far], dtype=np.float32).view(np.uint32)[0])))
+    b = bytearray(good)
+    b[22] = 2
+    _expect("ECORRUPT", oracle.decompress, bytes(b))
