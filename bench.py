@@ -495,6 +495,8 @@ def main():
                     help="tile capacity 256 or 512 (0: library default; batch workload: autotuned)")
     ap.add_argument("--ref-rule", type=int, default=0, choices=(0, 1),
                     help="leaf reference: 0 nearest the AABB centre (the paper's), 1 fewest bits")
+    ap.add_argument("--ref-mode", type=int, default=0, choices=(0, 1),
+                    help="reference stored as 0 its codes, 1 its original coordinates (lossless)")
     ap.add_argument("--nsets", type=int, default=4096)
     ap.add_argument("--requests", type=int, default=2000, help="served workload: requests")
     ap.add_argument("--qps", type=float, default=400.0, help="served workload: arrival rate")
@@ -532,13 +534,18 @@ def main():
 
     dims = int(x.shape[1])
     comp = bbx.Compressor(n, dims, x.dtype, leaf_size=args.leaf_size, tile=args.tile,
-                          ref_rule=args.ref_rule)
+                          ref_rule=args.ref_rule, ref_mode=args.ref_mode)
     s = comp(x, xi)
     S = s.numel()
-    # the other leaf-reference rule on the same input: its stream size only
+    # the other leaf-reference rule, and the other reference storage, on the
+    # same input: their stream sizes only
     alt = bbx.Compressor(n, dims, x.dtype, leaf_size=args.leaf_size, tile=args.tile,
-                         ref_rule=1 - args.ref_rule)
+                         ref_rule=1 - args.ref_rule, ref_mode=args.ref_mode)
     S_alt = alt(x, xi).numel()
+    del alt
+    alt = bbx.Compressor(n, dims, x.dtype, leaf_size=args.leaf_size, tile=args.tile,
+                         ref_rule=args.ref_rule, ref_mode=1 - args.ref_mode)
+    S_alt_mode = alt(x, xi).numel()
     del alt
     torch.cuda.empty_cache()
     header = s[:128].cpu().numpy().tobytes()
@@ -620,7 +627,7 @@ def main():
     perm_check = None
     try:
         pc = bbx.Compressor(n, dims, x.dtype, leaf_size=args.leaf_size, tile=args.tile,
-                            want_perm=True, ref_rule=args.ref_rule)
+                            want_perm=True, ref_rule=args.ref_rule, ref_mode=args.ref_mode)
         s2 = pc(x, xi)
         assert s2.numel() == S
         perm = pc.perm[:n].long()
@@ -641,7 +648,8 @@ def main():
         orc = Oracle()
         log(f"cpu oracle on {m} particles")
         t = time.perf_counter()
-        so = orc.compress(sample, xi, "rel", args.leaf_size, ref_rule=args.ref_rule)
+        so = orc.compress(sample, xi, "rel", args.leaf_size, ref_rule=args.ref_rule,
+                          ref_mode=args.ref_mode)
         t1 = time.perf_counter()
         orc.decompress(so)
         t2 = time.perf_counter()
@@ -659,8 +667,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "dims": dims, "input": dtype, "eb_rel": xi,
                    "leaf_size": args.leaf_size, "ref_rule": args.ref_rule,
+                   "ref_mode": args.ref_mode,
                    "stream_bytes": S, "cr": round(B_in / S, 4),
                    "cr_other_ref_rule": round(B_in / S_alt, 4),
+                   "cr_other_ref_mode": round(B_in / S_alt_mode, 4),
                    "bpp": round(8 * S / n, 4),
                    "compress_gbps": round(B_in / (mc * 1e-3) / 1e9, 2),
                    "decompress_gbps": round(B_in / (md * 1e-3) / 1e9, 2),

@@ -23,14 +23,18 @@
  * Stream format v1 (little-endian), produced byte-for-byte identically to the
  * CPU oracle:
  *   [0,128)   header: magic 'BBX1' u32 | version u16 = 1 | dtype u8 | dims u8 |
- *             n u64 | r u32 | eb_mode u8 | split_rule u8 = 0 | ref_mode u8 = 0 |
+ *             n u64 | r u32 | eb_mode u8 | split_rule u8 = 0 | ref_mode u8 (0, 1) |
  *             mbits u8 (5 for f32, 6 for f64: Sec. 4.2) | eb_user f64 |
  *             eb_abs f64 | eb_eff f64 | w f64 | inv_w f64 | origin[3] f64 |
  *             G[3] u8 + 5 zero bytes | n_leaves u64 | meta_bits u64 |
  *             payload_bits u64 | reserved u64 = 0
  *   meta      n_leaves fixed-stride records, leaves in depth-first order:
- *             m_d (mbits each, d < dims) then the reference's code q_d (G_d
- *             bits each); zero-padded to 8 bytes
+ *             m_d (mbits each, d < dims) then, with ref_mode 0, the
+ *             reference's code q_d (G_d bits each), or with ref_mode 1 the
+ *             bits of the reference's original coordinate on each axis (M =
+ *             32 for f32, 64 for f64: the paper's losslessly stored centre,
+ *             Sec. 4.2; its code is recomputed by the quantization of Sec. 3
+ *             from origin and inv_w); zero-padded to 8 bytes
  *   payload   per leaf, every non-reference member in ascending original
  *             index, per axis the code q - q_ref + 2^(m_d - 1) in m_d bits
  *             (nothing when m_d = 0); zero-padded to 8 bytes
@@ -39,7 +43,8 @@
  * Decompressed order: leaves depth-first; in each leaf the reference first,
  * then the other members in ascending original index (the paper keeps all
  * particles but not their order, Sec. 2.2).  The optional perm[] output of
- * compress gives the source index of every output slot.
+ * compress gives the source index of every output slot.  With ref_mode 1
+ * each reference decodes to its original coordinates exactly.
  *
  * Error bound: every reconstructed coordinate satisfies |x - x_hat| <= eb_abs
  * (eb_abs = eb * Delta_max for the relative mode, Delta_max the largest
@@ -83,17 +88,25 @@ typedef enum { BBX_AOS = 0, BBX_SOA = 1 } bbx_layout;         /* [n][dims] or [d
  * leaf order); 1 = the member whose Eq. 2 widths sum_d m_d are smallest
  * (ties to the first member), which minimises the leaf's payload bits for
  * its AABB.  Either stream decodes the same way (the reference's code is
- * stored). */
+ * stored).  ref_mode says how a leaf's meta record stores the reference:
+ * 0 = its codes (G_d bits per axis); 1 = its original coordinates (32 or 64
+ * bits per axis, the paper's lossless centre of Sec. 4.2), which decode
+ * exactly; the other members decode identically in both modes.  ref_mode 1
+ * carries source indices through the partition (as a perm output does). */
 typedef struct {
   uint32_t leaf_size;     /* r >= 1 */
   uint32_t eb_mode;       /* bbx_eb_mode */
   uint32_t layout;        /* bbx_layout of the input positions */
   uint32_t tile_override; /* 0 (= 256), 256 or 512 */
   uint32_t ref_rule;      /* 0 (AABB centre) or 1 (fewest code bits) */
+  uint32_t ref_mode;      /* 0 (reference code) or 1 (reference coordinates) */
 } bbx_params;
 
-/* Worst-case stream size in bytes for n particles of the given type. */
+/* Worst-case stream size in bytes for n particles of the given type, with
+ * ref_mode 0; bbx_compress_bound_mode gives it for either ref_mode (returns
+ * 0 for a ref_mode other than 0 or 1). */
 size_t bbx_compress_bound(uint64_t n, uint32_t dims, bbx_dtype dtype);
+size_t bbx_compress_bound_mode(uint64_t n, uint32_t dims, bbx_dtype dtype, uint32_t ref_mode);
 
 /* Device workspace bytes needed by bbx_compress for these arguments
  * (0 on invalid arguments; bbx_last_error() says why). */

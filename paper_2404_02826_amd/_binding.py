@@ -28,7 +28,7 @@ class BitboxError(RuntimeError):
 
 class _Params(C.Structure):
     _fields_ = [("leaf_size", C.c_uint32), ("eb_mode", C.c_uint32), ("layout", C.c_uint32),
-                ("tile_override", C.c_uint32), ("ref_rule", C.c_uint32)]
+                ("tile_override", C.c_uint32), ("ref_rule", C.c_uint32), ("ref_mode", C.c_uint32)]
 
 
 class _Set(C.Structure):
@@ -65,6 +65,8 @@ def load():
     u64, u32, i32, dbl, vp, sz = C.c_uint64, C.c_uint32, C.c_int, C.c_double, C.c_void_p, C.c_size_t
     lib.bbx_compress_bound.restype = sz
     lib.bbx_compress_bound.argtypes = [u64, u32, i32]
+    lib.bbx_compress_bound_mode.restype = sz
+    lib.bbx_compress_bound_mode.argtypes = [u64, u32, i32, u32]
     lib.bbx_compress_workspace_size.restype = sz
     lib.bbx_compress_workspace_size.argtypes = [u64, u32, i32, C.POINTER(_Params)]
     lib.bbx_compress.restype = i32
@@ -159,18 +161,22 @@ def _shape(pos: torch.Tensor, layout: str):
     raise ValueError(layout)
 
 
-def _params(leaf_size: int, eb_mode: str, layout: int, tile: int, ref_rule: int = 0) -> _Params:
-    return _Params(leaf_size, REL if eb_mode == "rel" else ABS, layout, tile, ref_rule)
+def _params(leaf_size: int, eb_mode: str, layout: int, tile: int, ref_rule: int = 0,
+            ref_mode: int = 0) -> _Params:
+    return _Params(leaf_size, REL if eb_mode == "rel" else ABS, layout, tile, ref_rule, ref_mode)
 
 
-def compress_bound(n: int, dims: int = 3, dtype=torch.float32) -> int:
-    return int(load().bbx_compress_bound(n, dims, F32 if dtype == torch.float32 else F64))
+def compress_bound(n: int, dims: int = 3, dtype=torch.float32, ref_mode: int = 0) -> int:
+    code = F32 if dtype == torch.float32 else F64
+    if ref_mode:
+        return int(load().bbx_compress_bound_mode(n, dims, code, ref_mode))
+    return int(load().bbx_compress_bound(n, dims, code))
 
 
 def compress_workspace_size(n: int, dims: int = 3, dtype=torch.float32, leaf_size: int = 32,
                             eb_mode: str = "rel", layout: str = "aos", tile: int = 0,
-                            ref_rule: int = 0) -> int:
-    p = _params(leaf_size, eb_mode, AOS if layout == "aos" else SOA, tile, ref_rule)
+                            ref_rule: int = 0, ref_mode: int = 0) -> int:
+    p = _params(leaf_size, eb_mode, AOS if layout == "aos" else SOA, tile, ref_rule, ref_mode)
     code = F32 if dtype == torch.float32 else F64
     lib = load()
     v = int(lib.bbx_compress_workspace_size(n, dims, code, C.byref(p)))
@@ -192,15 +198,16 @@ class Compressor:
 
     def __init__(self, n: int, dims: int = 3, dtype=torch.float32, leaf_size: int = 32,
                  eb_mode: str = "rel", layout: str = "aos", tile: int = 0, want_perm: bool = False,
-                 device="cuda", ref_rule: int = 0):
+                 device="cuda", ref_rule: int = 0, ref_mode: int = 0):
         self.n, self.dims, self.dtype = n, dims, dtype
         self.layout = layout
-        self.params = _params(leaf_size, eb_mode, AOS if layout == "aos" else SOA, tile, ref_rule)
+        self.params = _params(leaf_size, eb_mode, AOS if layout == "aos" else SOA, tile, ref_rule,
+                              ref_mode)
         lib = load()
         self.ws_size = compress_workspace_size(n, dims, dtype, leaf_size, eb_mode, layout, tile,
-                                               ref_rule)
+                                               ref_rule, ref_mode)
         self.ws = torch.empty(self.ws_size, dtype=torch.uint8, device=device)
-        self.cap = compress_bound(n, dims, dtype)
+        self.cap = compress_bound(n, dims, dtype, ref_mode)
         self.out = torch.empty((self.cap + 7) // 8 * 8, dtype=torch.uint8, device=device)
         self.perm = torch.empty(max(n, 1), dtype=torch.int32, device=device) if want_perm else None
         self.d_size = torch.zeros(1, dtype=torch.int64, device=device)
@@ -284,7 +291,7 @@ class BatchCompressor:
             pos = spec["pos"]
             layout = spec.get("layout", "aos")
             n, dims, _ = _shape(pos, layout)
-            cap = (compress_bound(n, dims, pos.dtype) + 7) // 8 * 8
+            cap = (compress_bound(n, dims, pos.dtype, spec.get("ref_mode", 0)) + 7) // 8 * 8
             if "out_cap" in spec:  # a smaller capacity, reported per set as ENOSPC
                 cap = int(spec["out_cap"])
             caps.append(cap)
@@ -309,7 +316,7 @@ class BatchCompressor:
             S.d_pos = pos.data_ptr() if n else None
             S.n, S.dims, S.dtype, S.eb = n, dims, _dtype_code(pos), float(spec["eb"])
             S.params = _params(spec.get("leaf_size", 32), spec.get("eb_mode", "rel"), lay, tile,
-                               spec.get("ref_rule", 0))
+                               spec.get("ref_rule", 0), spec.get("ref_mode", 0))
             S.d_out = base + offs[i]
             S.out_cap = caps[i]
             S.d_size = self.d_size.data_ptr() + 8 * i
@@ -402,11 +409,12 @@ class Server:
         self._meta = {}
 
     def submit_compress(self, pos: torch.Tensor, eb: float, eb_mode: str = "rel",
-                        leaf_size: int = 32, layout: str = "aos", ref_rule: int = 0) -> int:
+                        leaf_size: int = 32, layout: str = "aos", ref_rule: int = 0,
+                        ref_mode: int = 0) -> int:
         n, dims, lay = _shape(pos, layout)
         if not pos.is_cuda or not pos.is_contiguous():
             raise ValueError("positions must be a contiguous device tensor")
-        prm = _params(leaf_size, eb_mode, lay, 0, ref_rule)
+        prm = _params(leaf_size, eb_mode, lay, 0, ref_rule, ref_mode)
         jid = C.c_uint64()
         _check(self._lib.bbx_server_submit_compress(self._h, pos.data_ptr() if n else None, n, dims,
                                                     _dtype_code(pos), float(eb), C.byref(prm),
@@ -502,14 +510,15 @@ def decompress_workspace_size(header: bytes) -> int:
 
 def compress(pos: torch.Tensor, eb: float, eb_mode: str = "rel", leaf_size: int = 32,
              layout: str = "aos", want_perm: bool = False, tile: int = 0, stream=None,
-             ref_rule: int = 0):
+             ref_rule: int = 0, ref_mode: int = 0):
     """One-shot compress of a device tensor; returns the stream as a uint8
     device tensor (and the int32 source index of every output slot).
     ref_rule: 0 = leaf reference nearest the AABB centre (the paper's rule),
-    1 = the member with the fewest code bits."""
+    1 = the member with the fewest code bits.  ref_mode: 0 = the reference
+    stored as its codes, 1 = as its original coordinates (decoded exactly)."""
     n, dims, _ = _shape(pos, layout)
     c = Compressor(n, dims, pos.dtype, leaf_size, eb_mode, layout, tile, want_perm, pos.device,
-                   ref_rule)
+                   ref_rule, ref_mode)
     s = c(pos.contiguous(), eb, stream).clone()
     if want_perm:
         return s, c.perm[:n].clone()

@@ -122,7 +122,7 @@ struct SetIn {
   uint64_t* d_size;
   uint32_t* d_status;
   uint32_t* d_perm;
-  bool need_idx;  // plan source-index buffers (a perm output is asked for)
+  bool need_idx;  // plan source-index buffers (a perm output or ref_mode 1)
 };
 
 static bbx_status check_compress_args(uint64_t n, uint32_t dims, bbx_dtype dtype, double eb,
@@ -136,6 +136,7 @@ static bbx_status check_compress_args(uint64_t n, uint32_t dims, bbx_dtype dtype
   if (prm->tile_override != 0 && prm->tile_override != 256 && prm->tile_override != 512)
     return fail(BBX_EINVAL, "tile_override must be 0, 256 or 512");
   if (prm->ref_rule > 1) return fail(BBX_EINVAL, "ref_rule must be 0 or 1");
+  if (prm->ref_mode > 1) return fail(BBX_EINVAL, "ref_mode must be 0 or 1");
   if (dims != 2 && dims != 3) return fail(BBX_EUNSUPPORTED, "dims must be 2 or 3");
   if (n >= (1ull << 32)) return fail(BBX_EUNSUPPORTED, "n must be below 2^32");
   return BBX_OK;
@@ -202,6 +203,8 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
     D.layout = I.prm.layout;
     D.r = I.prm.leaf_size;
     D.ref_rule = I.prm.ref_rule;
+    D.ref_mode = I.prm.ref_mode;
+    D.track = (I.d_perm != nullptr || I.prm.ref_mode == 1) ? 1u : 0u;
     D.eb_mode = I.prm.eb_mode;
     D.mbits = I.dtype == BBX_F32 ? 5u : 6u;
     const uint64_t n = I.n;
@@ -225,7 +228,8 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
       qz[s] = std::min<uint64_t>((n + 1023) / 1024, 16384);
       tl[s] = D.tile_mode ? (1ull << D.gl) : 0;
       bg[s] = D.tile_mode ? 0 : D.n_leaves;
-      const uint64_t mw = (D.n_leaves * (uint64_t)(D.dims * (D.mbits + 30)) + 63) / 64;
+      const uint64_t ref_bits = D.ref_mode ? (D.dtype == BBX_F32 ? 32u : 64u) : 30u;
+      const uint64_t mw = (D.n_leaves * (uint64_t)(D.dims * (D.mbits + ref_bits)) + 63) / 64;
       pm[s] = std::max<uint64_t>(1, std::min<uint64_t>((mw + kBlock - 1) / kBlock, 1024));
       const uint64_t lpb = leaves_per_block(D.r);
       pp[s] = (D.n_leaves + lpb - 1) / lpb;
@@ -258,14 +262,14 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
       D.part_off = parts;
       D.kst = (n + 63) & ~63ull;
       key_bytes += align_up((uint64_t)D.dims * D.kst * 4);
-      if (I.need_idx) idx_n += (n + 63) & ~63ull;
+      if (I.need_idx || D.track) idx_n += (n + 63) & ~63ull;
       hist_n += max_nodes * kHistBins;
       sel_n += max_nodes;
       rows_n += max_blocks;
       leaves_n += D.n_leaves;
       parts += mm[s];
     }
-    if (D.perm) bp->track = 1;
+    if (D.track) bp->track = 1;
   }
   bp->total_leaves = leaves_n;
   bp->hist_entries = hist_n;
@@ -419,7 +423,7 @@ static bbx_status batch_launch(const SetIn* in, uint32_t nsets, void* d_ws, size
 
 struct HostHeader {
   uint64_t n, n_leaves, meta_bits, payload_bits;
-  uint32_t dims, dtype, r, eb_mode, mbits;
+  uint32_t dims, dtype, r, eb_mode, mbits, ref_mode;
   uint32_t G[3];
   double eb_user, eb_abs, eb_eff, w, inv_w, origin[3];
 };
@@ -447,8 +451,9 @@ static bbx_status parse_header(const uint8_t* h, size_t bytes, HostHeader* o) {
   o->n = rd64(h + 8);
   memcpy(&o->r, h + 16, 4);
   o->eb_mode = h[20];
+  o->ref_mode = h[22];
   o->mbits = h[23];
-  if (o->dtype > 1 || (o->dims != 2 && o->dims != 3) || o->eb_mode > 1 || h[21] != 0 || h[22] != 0)
+  if (o->dtype > 1 || (o->dims != 2 && o->dims != 3) || o->eb_mode > 1 || h[21] != 0 || h[22] > 1)
     return fail(BBX_ECORRUPT, "bad dtype, dims, eb_mode or rule fields");
   if (o->mbits != (o->dtype == 0 ? 5u : 6u) || o->r == 0 || o->n >= (1ull << 32))
     return fail(BBX_ECORRUPT, "bad width-field size, leaf size or n");
@@ -465,7 +470,8 @@ static bbx_status parse_header(const uint8_t* h, size_t bytes, HostHeader* o) {
     if (o->G[d] > 30 || !isfinite(o->origin[d])) return fail(BBX_ECORRUPT, "bad code width or origin");
     sumG += o->G[d];
   }
-  if (!isfinite(o->w) || o->w < 0.0) return fail(BBX_ECORRUPT, "bad bin width");
+  if (!isfinite(o->w) || o->w < 0.0 || !isfinite(o->inv_w) || o->inv_w < 0.0)
+    return fail(BBX_ECORRUPT, "bad bin width");
   for (int k = 91; k < 96; ++k)
     if (h[k] != 0) return fail(BBX_ECORRUPT, "header padding not zero");
   o->n_leaves = rd64(h + 96);
@@ -474,7 +480,9 @@ static bbx_status parse_header(const uint8_t* h, size_t bytes, HostHeader* o) {
   if (rd64(h + 120) != 0) return fail(BBX_ECORRUPT, "reserved field not zero");
   const uint64_t nl = o->n ? make_geom(o->n, o->r).L[0][0] : 0;
   if (o->n_leaves != nl) return fail(BBX_ECORRUPT, "leaf count does not match (n, r)");
-  if (o->meta_bits != nl * (uint64_t)(o->dims * o->mbits + sumG)) return fail(BBX_ECORRUPT, "meta size mismatch");
+  const uint32_t ref_bits = o->ref_mode ? o->dims * (o->dtype == 0 ? 32u : 64u) : sumG;
+  if (o->meta_bits != nl * (uint64_t)(o->dims * o->mbits + ref_bits))
+    return fail(BBX_ECORRUPT, "meta size mismatch");
   if (o->payload_bits > o->n * (uint64_t)o->dims * 31u) return fail(BBX_ECORRUPT, "payload size out of range");
   return BBX_OK;
 }
@@ -505,8 +513,17 @@ using namespace bbx;
 extern "C" {
 
 size_t bbx_compress_bound(uint64_t n, uint32_t dims, bbx_dtype dtype) {
+  return bbx_compress_bound_mode(n, dims, dtype, 0);
+}
+
+// Every particle is a leaf's reference (dims * (mbits + G_d) <= dims * (mbits
+// + 30) meta bits, or dims * (mbits + M) with ref_mode 1) or a member (at most
+// dims * 31 payload bits).
+size_t bbx_compress_bound_mode(uint64_t n, uint32_t dims, bbx_dtype dtype, uint32_t ref_mode) {
+  if (ref_mode > 1) return 0;
   const uint64_t mbits = dtype == BBX_F64 ? 6 : 5;
-  return kHeaderBytes + 16 + ((n * dims * (mbits + 30) + 63) / 64) * 8;
+  const uint64_t ref = ref_mode ? (dtype == BBX_F64 ? 64 : 32) : 30;
+  return kHeaderBytes + 16 + ((n * dims * (mbits + ref) + 63) / 64) * 8;
 }
 
 size_t bbx_compress_workspace_size(uint64_t n, uint32_t dims, bbx_dtype dtype,
@@ -586,7 +603,7 @@ static bool sets_from_abi(const bbx_set* sets, uint32_t nsets, std::vector<SetIn
     I.d_size = sets[s].d_size;
     I.d_status = sets[s].d_status;
     I.d_perm = sets[s].d_perm;
-    I.need_idx = I.d_perm != nullptr;
+    I.need_idx = I.d_perm != nullptr || I.prm.ref_mode == 1;
   }
   return true;
 }
@@ -687,8 +704,10 @@ bbx_status bbx_decompress(const void* d_stream, size_t stream_size, const void* 
   p.r = h.r;
   p.mbits = h.mbits;
   p.layout = layout;
+  p.ref_mode = h.ref_mode;
   for (int d = 0; d < 3; ++d) p.G[d] = h.G[d], p.origin[d] = h.origin[d];
   p.w = h.w;
+  p.inv_w = h.inv_w;
   if (h.n) p.geom = make_geom(h.n, h.r);
   hipError_t e = launch_decompress(p, w, (const uint8_t*)d_stream, d_pos, d_status, stream);
   if (e != hipSuccess) return fail(BBX_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));

@@ -57,6 +57,7 @@ struct LeafRec {
   uint32_t size;     // particles
   uint32_t m;        // widths m_x | m_y << 8 | m_z << 16
   uint32_t qref[3];  // codes of the reference particle
+  uint32_t ref_src;  // source index of the reference (compress, when indices are carried)
 };
 
 // Selection state of one node of a global level.
@@ -84,6 +85,8 @@ struct SetDesc {
   uint32_t mm_blocks;     // blocks of the range pass
   uint32_t level_blocks;  // block target of the set's global levels (level_shape)
   uint32_t ref_rule;      // leaf reference: 0 nearest the AABB centre, 1 fewest code bits
+  uint32_t ref_mode;      // reference stored as 0 its codes, 1 its original coordinates
+  uint32_t track;         // source indices follow the codes (perm output or ref_mode 1)
   uint64_t n_leaves;
   uint64_t key_off;       // byte offset into each key buffer (capacity dims*n*4)
   uint64_t idx_off;       // u32 offset into each index buffer
@@ -119,6 +122,9 @@ struct Ws {
 // ---------------------------------------------------------------- device helpers
 
 __host__ __device__ inline uint32_t bitlen32(uint32_t v) { return v ? 32u - (uint32_t)__builtin_clz(v) : 0u; }
+
+// Bits of one stored original coordinate (M of Sec. 4.2): 32 for f32, 64 for f64.
+__host__ __device__ inline uint32_t coord_bits(uint32_t dtype) { return dtype == BBX_F32 ? 32u : 64u; }
 
 // Node j of depth k: walk the path bits from the root (left child floor(s/2)).
 __host__ __device__ inline void node_span(uint64_t n, uint32_t k, uint64_t j, uint64_t* start,
@@ -345,7 +351,7 @@ struct BatchPlan {
   uint32_t nsets;
   uint32_t max_gl;            // deepest global level count over the sets
   uint32_t tile;              // tile capacity (256 or 512)
-  uint32_t track;             // source indices are carried (some set wants perm)
+  uint32_t track;             // source indices are carried (some set wants perm or ref_mode 1)
   uint64_t total_leaves;
   uint64_t hist_entries;      // u32 bins zeroed once per call
   uint64_t g_mm, g_qz, g_tile, g_big, g_pm, g_pp;
@@ -360,10 +366,10 @@ struct BatchPlan {
 
 struct DecompressPlan {
   uint64_t n, n_leaves, meta_bits, payload_bits;
-  uint32_t dims, dtype, r, mbits, layout;
+  uint32_t dims, dtype, r, mbits, layout, ref_mode;
   uint32_t G[3];
   double origin[3];
-  double w;
+  double w, inv_w;
   TreeGeom geom;
 };
 

@@ -618,8 +618,8 @@ __global__ void __launch_bounds__(kBlock) k_scatter(uint32_t depth, uint32_t nse
   if (P->status != BBX_OK) return;
   if (level_is_local(S.n, depth)) return;
   __shared__ uint32_t lhist[2 * kBlock];
-  const uint32_t* isrc = S.perm ? isrc0 + S.idx_off : nullptr;
-  uint32_t* idst = S.perm ? idst0 + S.idx_off : nullptr;
+  const uint32_t* isrc = S.track ? isrc0 + S.idx_off : nullptr;
+  uint32_t* idst = S.track ? idst0 + S.idx_off : nullptr;
   const NodeSel ns = (sel0 + S.sel_off)[c.lb / c.sh.chunks];
   const uint32_t* cb = cb0 + S.cb_off + c.lb * 2;
   if (P->key16)
@@ -710,8 +710,8 @@ __global__ void __launch_bounds__(kBlock) k_level_local(uint32_t depth, uint32_t
   if (level_kind(S.n, depth) != kLevelBlock) return;
   __shared__ uint32_t lhist[2 * kBlock];
   __shared__ uint32_t red[16];
-  const uint32_t* isrc = S.perm ? isrc0 + S.idx_off : nullptr;
-  uint32_t* idst = S.perm ? idst0 + S.idx_off : nullptr;
+  const uint32_t* isrc = S.track ? isrc0 + S.idx_off : nullptr;
+  uint32_t* idst = S.track ? idst0 + S.idx_off : nullptr;
   uint64_t st, sz;
   node_span(S.n, depth, c.lb, &st, &sz);
   uint32_t v = 0, jeq = 0;
@@ -938,8 +938,8 @@ __global__ void __launch_bounds__(kBlock) k_level_wave(uint32_t depth, uint32_t 
   if (P->status != BBX_OK) return;
   if (level_kind(S.n, depth) != kLevelWave) return;
   const uint64_t j = gn - pre[s];
-  const uint32_t* isrc = S.perm ? isrc0 + S.idx_off : nullptr;
-  uint32_t* idst = S.perm ? idst0 + S.idx_off : nullptr;
+  const uint32_t* isrc = S.track ? isrc0 + S.idx_off : nullptr;
+  uint32_t* idst = S.track ? idst0 + S.idx_off : nullptr;
   if (P->key16)
     level_wave_body<uint16_t>(depth, S, P, j, src0 + S.key_off, dst0 + S.key_off, isrc, idst, bins[wv]);
   else

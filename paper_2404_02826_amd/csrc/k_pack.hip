@@ -130,8 +130,8 @@ __global__ void k_set_sizes(uint32_t nsets, const SetDesc* sets, DevParams* para
   const uint64_t b = S.leaf_off, e = S.leaf_off + S.n_leaves;
   const uint64_t base = S.n_leaves ? off[b] : 0;
   const uint64_t endv = S.n_leaves ? (e < total_leaves ? off[e] : *total) : 0;
-  uint32_t sumG = 0;
-  for (uint32_t d = 0; d < S.dims; ++d) sumG += P->G[d];
+  uint32_t sumG = 0;  // reference field: codes, or original coordinates with ref_mode 1
+  for (uint32_t d = 0; d < S.dims; ++d) sumG += S.ref_mode ? coord_bits(S.dtype) : P->G[d];
   const uint64_t meta = S.n_leaves * (uint64_t)(S.dims * S.mbits + sumG);
   P->payload_base = base;
   P->meta_bits = meta;
@@ -155,6 +155,14 @@ __device__ inline void or_into(uint64_t& word, uint64_t w0, u128 val, uint64_t a
     word |= (uint64_t)(val >> (-rel));
 }
 
+// Bits of the reference's original coordinate on axis d (ref_mode 1): the
+// caller's value at the reference's source index.
+__device__ inline uint64_t ref_coord_bits(const SetDesc& S, uint32_t src, uint32_t d) {
+  const uint64_t k = S.layout == BBX_AOS ? (uint64_t)src * S.dims + d : (uint64_t)d * S.n + src;
+  if (S.dtype == BBX_F32) return ((const uint32_t*)S.pos)[k];
+  return ((const uint64_t*)S.pos)[k];
+}
+
 __global__ void __launch_bounds__(kBlock) k_pack_meta(uint32_t nsets, const uint64_t* pre,
                                                       const SetDesc* sets,
                                                       const DevParams* params,
@@ -166,11 +174,32 @@ __global__ void __launch_bounds__(kBlock) k_pack_meta(uint32_t nsets, const uint
   const uint64_t lb = blockIdx.x - pre[s], nblk = pre[s + 1] - pre[s];
   const uint32_t dims = S.dims, mbits = S.mbits;
   const uint32_t G[3] = {P->G[0], P->G[1], P->G[2]};
-  uint32_t Sb = dims * mbits;
-  for (uint32_t d = 0; d < dims; ++d) Sb += G[d];
   const uint64_t nwords = (P->meta_bits + 63) / 64;
   const LeafRec* leaves = leaves0 + S.leaf_off;
   uint64_t* meta = (uint64_t*)(S.out + kHeaderBytes);
+  if (S.ref_mode) {  // records of dims * (mbits + M) bits, written field by field
+    const uint32_t M = coord_bits(S.dtype);
+    const uint32_t Sb = dims * (mbits + M);
+    for (uint64_t w = lb * blockDim.x + threadIdx.x; w < nwords; w += nblk * blockDim.x) {
+      const uint64_t b0 = w * 64;
+      const uint64_t i0 = b0 / Sb;
+      uint64_t i1 = (b0 + 63) / Sb;
+      if (i1 >= S.n_leaves) i1 = S.n_leaves - 1;
+      uint64_t word = 0;
+      for (uint64_t i = i0; i <= i1; ++i) {
+        const LeafRec rec = leaves[i];
+        uint64_t at = i * Sb;
+        for (uint32_t d = 0; d < dims; ++d, at += mbits)
+          or_into(word, b0, (rec.m >> (8 * d)) & 0xffu, at, mbits);
+        for (uint32_t d = 0; d < dims; ++d, at += M)
+          or_into(word, b0, ref_coord_bits(S, rec.ref_src, d), at, M);
+      }
+      meta[w] = word;
+    }
+    return;
+  }
+  uint32_t Sb = dims * mbits;
+  for (uint32_t d = 0; d < dims; ++d) Sb += G[d];
   for (uint64_t w = lb * blockDim.x + threadIdx.x; w < nwords; w += nblk * blockDim.x) {
     const uint64_t b0 = w * 64;
     const uint64_t i0 = b0 / Sb;
@@ -450,7 +479,8 @@ __global__ void k_header(const SetDesc* sets, const DevParams* params) {
   for (int k = 0; k < 16; ++k) h[k] = 0;
   h[0] = (uint64_t)kMagic | ((uint64_t)1 << 32) | ((uint64_t)S.dtype << 48) | ((uint64_t)dims << 56);
   h[1] = S.n;
-  h[2] = (uint64_t)S.r | ((uint64_t)S.eb_mode << 32) | ((uint64_t)S.mbits << 56);
+  h[2] = (uint64_t)S.r | ((uint64_t)S.eb_mode << 32) | ((uint64_t)S.ref_mode << 48) |
+         ((uint64_t)S.mbits << 56);
   h[3] = __double_as_longlong(P->eb_user);
   h[4] = __double_as_longlong(P->eb_abs);
   h[5] = __double_as_longlong(P->eb_eff);

@@ -328,7 +328,7 @@ __global__ void __launch_bounds__(kBlock) k_quantize(uint32_t nsets, const uint6
   const DevParams* P = params + s;
   if (P->status != BBX_OK) return;
   const uint64_t lb = blockIdx.x - pre[s], nblk = pre[s + 1] - pre[s];
-  uint32_t* idx = S.perm ? idx0 + S.idx_off : nullptr;
+  uint32_t* idx = S.track ? idx0 + S.idx_off : nullptr;
   // the depth-0 first-digit histogram, when depth 0 uses global histograms
   // with more than one digit pass (the same condition the level kernels use)
   __shared__ uint32_t lh[kHistBins];

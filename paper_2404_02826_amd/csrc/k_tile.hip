@@ -167,6 +167,7 @@ __device__ void tile_bitboxes(WaveTile<TILE, KL, TRACK>& sm, int cur, uint32_t n
         rec.qref[0] = qr[0];
         rec.qref[1] = qr[1];
         rec.qref[2] = qr[2];
+        rec.ref_src = TRACK ? sm.I[rslot] : 0u;  // meaningful when the set carries indices
         leaves[lid] = rec;
         leaf_bits[lid] = (uint64_t)(lz - 1) * summ;
       } else {
@@ -469,7 +470,7 @@ __device__ void tile_body(WaveTile<TILE, KL, TRACK>& sm, uint64_t j, uint32_t K0
 #pragma unroll
     for (uint32_t d = 0; d < 3; ++d)
       if (d < dims) keys[(uint64_t)d * kst + gpos] = (KT)(sm.K[d][slot] + tmin[d]);
-    if (TRACK && track) perm[gpos] = sm.I[slot];
+    if (TRACK && track && perm) perm[gpos] = sm.I[slot];
   }
 }
 
@@ -485,7 +486,7 @@ __device__ void tile_node(uint32_t nsets, const uint64_t* pre, const SetDesc* se
   const uint64_t j = gtile - pre[s];
   const uint32_t buf = S.gl & 1;
   uint8_t* keys = (buf ? keys1 : keys0) + S.key_off;
-  const uint32_t* idx = S.perm ? (buf ? idx1 : idx0) + S.idx_off : nullptr;
+  const uint32_t* idx = S.track ? (buf ? idx1 : idx0) + S.idx_off : nullptr;
   LeafRec* leaves = leaves0 + S.leaf_off;
   uint64_t* leaf_bits = leaf_bits0 + S.leaf_off;
   if (P->key16)
@@ -615,13 +616,14 @@ __device__ void bigleaf_body(uint64_t i, uint64_t n /* code-array stride */, uin
     rec.qref[0] = qr[0];
     rec.qref[1] = qr[1];
     rec.qref[2] = qr[2];
+    rec.ref_src = idx ? idx[st + ref] : 0u;
     leaves[i] = rec;
     leaf_bits[i] = (sz - 1) * (uint64_t)summ;
   }
   for (uint64_t p = threadIdx.x; p < sz; p += kBlock) {
     const uint64_t o = p == ref ? 0 : (p < ref ? p + 1 : p);
     for (uint32_t d = 0; d < dims; ++d) dst[(uint64_t)d * n + st + o] = src[(uint64_t)d * n + st + p];
-    if (idx) perm[st + o] = idx[st + p];
+    if (idx && perm) perm[st + o] = idx[st + p];
   }
 }
 
@@ -637,7 +639,7 @@ __global__ void __launch_bounds__(kBlock) k_bigleaf(uint32_t nsets, const uint64
   const uint32_t buf = S.gl & 1;
   const uint8_t* src = (buf ? keys1 : keys0) + S.key_off;
   uint8_t* dst = (buf ? keys0 : keys1) + S.key_off;
-  const uint32_t* idx = S.perm ? (buf ? idx1 : idx0) + S.idx_off : nullptr;
+  const uint32_t* idx = S.track ? (buf ? idx1 : idx0) + S.idx_off : nullptr;
   const uint64_t i = blockIdx.x - pre[s];
   if (P->key16)
     bigleaf_body<uint16_t>(i, S.kst, S.dims, S.geom, (const uint16_t*)src, (uint16_t*)dst, idx,

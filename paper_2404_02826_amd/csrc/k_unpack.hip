@@ -3,12 +3,15 @@
 //
 //   k_dec_meta   one thread per leaf: reads its fixed-stride meta record,
 //                validates the widths, and derives its span from (n, r) alone
-//                (the tree's leaf sizes depend on n and r only)
+//                (the tree's leaf sizes depend on n and r only); with
+//                ref_mode 1 the reference's code comes from its stored
+//                coordinates by the quantization of Sec. 3
 //   (scan)       payload bit offset of every leaf, total checked against the
 //                header
 //   k_unpack     blocks of 1024 output slots: the block finds the leaves that
 //                cover its slots, every thread decodes slots
 //                (reference -> its code; member j -> payload code j-1)
+//   k_dec_refs   ref_mode 1: the references' stored coordinates, exactly
 #include "bbx_internal.h"
 
 namespace bbx {
@@ -27,19 +30,41 @@ __device__ inline u128 read_bits(const uint64_t* sec, uint64_t nwords, uint64_t 
   return v;
 }
 
+// Reference field of a ref_mode 1 record: the stored coordinate of axis d
+// (M bits at absolute bit `at`), and the code the encoder's quantization gave
+// it: floor((x - origin) * inv_w + 1/2) in FP64, the same separately rounded
+// operations as the quantize pass (no contraction).  Returns false when the
+// value is not finite or its code lies outside [0, 2^G).
+__device__ inline bool ref_code_from_coord(const uint64_t* meta, uint64_t nwords, uint64_t at,
+                                           uint32_t dtype, double origin, double inv_w,
+                                           uint32_t G, uint32_t* q) {
+  const uint64_t raw = (uint64_t)read_bits(meta, nwords, at, coord_bits(dtype));
+  const double x = dtype == BBX_F32 ? (double)__uint_as_float((uint32_t)raw) : __longlong_as_double((long long)raw);
+  if (!isfinite(x)) return false;
+  const double t = floor((x - origin) * inv_w + 0.5);
+  if (!(t >= 0.0 && t < (double)(1ull << G))) return false;
+  *q = (uint32_t)t;
+  return true;
+}
+
 __global__ void __launch_bounds__(kBlock) k_dec_meta(uint64_t n_leaves, uint32_t dims,
                                                      uint32_t mbits, uint32_t G0, uint32_t G1,
                                                      uint32_t G2, uint64_t meta_bits, TreeGeom g,
                                                      const uint8_t* stream, LeafRec* leaves,
-                                                     uint64_t* bits, DevParams* P) {
+                                                     uint64_t* bits, DevParams* P,
+                                                     uint32_t ref_mode, uint32_t dtype, double o0,
+                                                     double o1, double o2, double inv_w) {
   const uint32_t G[3] = {G0, G1, G2};
+  const double origin[3] = {o0, o1, o2};
   uint32_t S = dims * mbits;
-  for (uint32_t d = 0; d < dims; ++d) S += G[d];
+  for (uint32_t d = 0; d < dims; ++d) S += ref_mode ? coord_bits(dtype) : G[d];
   const uint64_t* meta = (const uint64_t*)(stream + kHeaderBytes);
   const uint64_t nwords = (meta_bits + 63) / 64;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_leaves;
        i += (uint64_t)gridDim.x * blockDim.x) {
-    u128 v = read_bits(meta, nwords, i * S, S);
+    // widths (and with ref_mode 0 the reference codes) in one read: at most
+    // 3 * (6 + 30) bits
+    u128 v = read_bits(meta, nwords, i * S, ref_mode ? dims * mbits : S);
     LeafRec rec;
     uint32_t m = 0, summ = 0;
     bool bad = false;
@@ -52,11 +77,16 @@ __global__ void __launch_bounds__(kBlock) k_dec_meta(uint64_t n_leaves, uint32_t
     }
     for (uint32_t d = 0; d < 3; ++d) {
       rec.qref[d] = 0;
-      if (d < dims) {
+      if (d < dims && ref_mode) {
+        const uint64_t at = i * S + dims * mbits + d * coord_bits(dtype);
+        if (!ref_code_from_coord(meta, nwords, at, dtype, origin[d], inv_w, G[d], &rec.qref[d]))
+          bad = true;
+      } else if (d < dims) {
         rec.qref[d] = (uint32_t)(v & ((((u128)1) << G[d]) - 1));
         v >>= G[d];
       }
     }
+    rec.ref_src = 0;
     uint64_t st, sz;
     leaf_span(g, i, &st, &sz);
     rec.start = (uint32_t)st;
@@ -278,6 +308,30 @@ __global__ void k_dec_finish(const DevParams* P, uint32_t* d_status) {
   if (threadIdx.x == 0 && d_status) *d_status = P->status;
 }
 
+// ref_mode 1: each leaf's first output slot (its reference, where k_unpack
+// wrote the bin centre of its code) receives the stored original
+// coordinates, bit for bit.  One thread per leaf.
+template <typename U>
+__global__ void __launch_bounds__(kBlock) k_dec_refs(uint64_t n, uint64_t n_leaves, uint32_t dims,
+                                                     uint32_t mbits, uint32_t layout,
+                                                     uint64_t meta_bits, const LeafRec* leaves,
+                                                     const uint8_t* stream, U* pos,
+                                                     const DevParams* P) {
+  if (P->status != BBX_OK) return;
+  constexpr uint32_t M = 8 * sizeof(U);
+  const uint32_t S = dims * (mbits + M);
+  const uint64_t* meta = (const uint64_t*)(stream + kHeaderBytes);
+  const uint64_t nwords = (meta_bits + 63) / 64;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_leaves;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t st = leaves[i].start;
+    for (uint32_t d = 0; d < dims; ++d) {
+      const U raw = (U)read_bits(meta, nwords, i * S + dims * mbits + d * M, M);
+      pos[layout == BBX_AOS ? st * dims + d : (uint64_t)d * n + st] = raw;
+    }
+  }
+}
+
 hipError_t launch_decompress(const DecompressPlan& p, const DecompressWs& w, const uint8_t* stream,
                              void* pos, uint32_t* d_status, hipStream_t s) {
   BBX_LAUNCH("dec_init", k_dec_init, 1, 64, 0, s, w.params);
@@ -285,7 +339,8 @@ hipError_t launch_decompress(const DecompressPlan& p, const DecompressWs& w, con
     uint64_t g = (p.n_leaves + kBlock - 1) / kBlock;
     if (g > 65536) g = 65536;
     BBX_LAUNCH("dec_meta", k_dec_meta, g, kBlock, 0, s, p.n_leaves, p.dims, p.mbits, p.G[0],
-               p.G[1], p.G[2], p.meta_bits, p.geom, stream, w.leaves, w.leaf_bits, w.params);
+               p.G[1], p.G[2], p.meta_bits, p.geom, stream, w.leaves, w.leaf_bits, w.params,
+               p.ref_mode, p.dtype, p.origin[0], p.origin[1], p.origin[2], p.inv_w);
     hipError_t e = launch_dec_scan(p.n_leaves, w.leaf_bits, w.scan_part, w.params, p.payload_bits, s);
     if (e != hipSuccess) return e;
     const uint64_t lpb = leaves_per_block(p.r);
@@ -300,6 +355,12 @@ hipError_t launch_decompress(const DecompressPlan& p, const DecompressWs& w, con
                  p.w, p.origin[0], p.origin[1], p.origin[2], p.G[0], p.G[1], p.G[2], p.n_leaves,
                  p.meta_bits, w.leaves, w.leaf_bits, stream, p.payload_bits, (double*)pos,
                  w.params);
+    if (p.ref_mode && p.dtype == BBX_F32)
+      BBX_LAUNCH("dec_refs", k_dec_refs<uint32_t>, g, kBlock, 0, s, p.n, p.n_leaves, p.dims,
+                 p.mbits, p.layout, p.meta_bits, w.leaves, stream, (uint32_t*)pos, w.params);
+    else if (p.ref_mode)
+      BBX_LAUNCH("dec_refs", k_dec_refs<uint64_t>, g, kBlock, 0, s, p.n, p.n_leaves, p.dims,
+                 p.mbits, p.layout, p.meta_bits, w.leaves, stream, (uint64_t*)pos, w.params);
   }
   BBX_LAUNCH("dec_finish", k_dec_finish, 1, 64, 0, s, w.params, d_status);
   return hipGetLastError();

@@ -184,3 +184,28 @@ def test_batch_mixed_reference_rules(orc, bbx):
                            ref_rule=spec["ref_rule"])
         ref_s = ref[0] if spec["want_perm"] else ref
         assert res[i].cpu().numpy().tobytes() == ref_s, f"set {i} rule {rules[i]}"
+
+
+def test_batch_mixed_reference_modes(orc, bbx):
+    """Sets of one batch may store their references differently (codes or
+    original coordinates), with or without perm outputs; each matches the
+    oracle under its own mode."""
+    cases = [("cosmology", 30011, 3, np.float32, 1e-4, "rel", 32, "aos", False),
+             ("uniform", 9001, 2, np.float64, 1e-3, "rel", 16, "aos", True),
+             ("cosmology", 60000, 3, np.float32, 1e-4, "rel", 700, "soa", False),
+             ("uniform", 4000, 3, np.float32, 1e-3, "rel", 8, "soa", False)]
+    hosts, specs = _specs(cases, seed0=50)
+    modes = [1, 1, 1, 0]
+    for spec, m in zip(specs, modes):
+        spec["ref_mode"] = m
+    _say("batch with reference modes", modes)
+    bc = bbx.BatchCompressor(specs)
+    res = bc()
+    for i, (host, spec) in enumerate(zip(hosts, specs)):
+        ref = orc.compress(host, spec["eb"], spec["eb_mode"], spec["leaf_size"],
+                           layout=spec["layout"], want_perm=spec["want_perm"],
+                           ref_mode=spec["ref_mode"])
+        ref_s = ref[0] if spec["want_perm"] else ref
+        assert res[i].cpu().numpy().tobytes() == ref_s, f"set {i} mode {modes[i]}"
+        if spec["want_perm"]:
+            assert np.array_equal(bc.perms[i][:len(ref[1])].cpu().numpy().astype(np.uint32), ref[1])

@@ -55,13 +55,17 @@ def gen(kind, n, dims=3, dtype=np.float32, seed=1):
     raise ValueError(kind)
 
 
-def gpu_roundtrip(bbx, pts, eb, mode, r, layout="aos", tile=0, ref_rule=0):
+def gpu_roundtrip(bbx, pts, eb, mode, r, layout="aos", tile=0, ref_rule=0, ref_mode=0,
+                  want_perm=True):
     host = pts if layout == "aos" else np.ascontiguousarray(pts.T)
     x = torch.from_numpy(host).cuda()
-    s, perm = bbx.compress(x, eb, mode, r, layout, want_perm=True, tile=tile, ref_rule=ref_rule)
+    out = bbx.compress(x, eb, mode, r, layout, want_perm=want_perm, tile=tile, ref_rule=ref_rule,
+                       ref_mode=ref_mode)
+    s, perm = out if want_perm else (out, None)
     dec = bbx.decompress(s, layout)
     torch.cuda.synchronize()
-    return s.cpu().numpy().tobytes(), perm.cpu().numpy().astype(np.uint32), dec.cpu().numpy()
+    return (s.cpu().numpy().tobytes(),
+            perm.cpu().numpy().astype(np.uint32) if want_perm else None, dec.cpu().numpy())
 
 
 def first_diff(a: bytes, b: bytes):
@@ -71,18 +75,20 @@ def first_diff(a: bytes, b: bytes):
     return min(len(a), len(b))
 
 
-def check_parity(orc, bbx, pts, eb, mode, r, layout="aos", tile=0, ref_rule=0):
+def check_parity(orc, bbx, pts, eb, mode, r, layout="aos", tile=0, ref_rule=0, ref_mode=0,
+                 want_perm=True):
     host = pts if layout == "aos" else np.ascontiguousarray(pts.T)
     ref_s, ref_p = orc.compress(host, eb, mode, r, layout=layout, want_perm=True,
-                                ref_rule=ref_rule)
-    got_s, got_p, got_d = gpu_roundtrip(bbx, pts, eb, mode, r, layout, tile, ref_rule)
+                                ref_rule=ref_rule, ref_mode=ref_mode)
+    got_s, got_p, got_d = gpu_roundtrip(bbx, pts, eb, mode, r, layout, tile, ref_rule, ref_mode,
+                                        want_perm)
     if got_s != ref_s:
         h = props.parse_header(ref_s)
         mb = 8 * ((h["meta_bits"] + 63) // 64)
         i = first_diff(got_s, ref_s)
         where = "header" if i < 128 else ("meta" if i < 128 + mb else "payload")
         raise AssertionError(f"stream differs at byte {i} ({where}); sizes {len(got_s)} vs {len(ref_s)}")
-    assert np.array_equal(got_p, ref_p), "perm differs"
+    assert got_p is None or np.array_equal(got_p, ref_p), "perm differs"
     ref_d = orc.decompress(ref_s, layout)
     assert np.array_equal(got_d, ref_d), "decompressed positions differ"
     return ref_s
@@ -159,6 +165,56 @@ def test_reference_rule_fewest_bits(orc, bbx, case):
     _say("rule 1", case)
     pts = gen(kind, n, dims, dt, seed=n % 89 + 3)
     check_parity(orc, bbx, pts, eb, mode, r, tile=tile, ref_rule=1)
+
+
+# (generator, n, dims, dtype, eb, mode, r, tile, layout, want_perm)
+REF_MODE1_CASES = [
+    ("uniform", 1, 3, np.float32, 1e-3, "rel", 32, 0, "aos", False),
+    ("uniform", 3, 2, np.float64, 1e-3, "rel", 1, 0, "aos", True),
+    ("ties", 20000, 3, np.float32, 1e-2, "rel", 7, 0, "aos", False),
+    ("cosmology", 100003, 3, np.float32, 1e-4, "rel", 32, 0, "aos", False),
+    ("cosmology", 100003, 3, np.float32, 1e-4, "rel", 32, 512, "soa", True),
+    ("cosmology", 20011, 3, np.float64, 1e-6, "rel", 33, 0, "soa", False),  # u32 codes
+    ("cosmology", 150001, 3, np.float32, 1e-7, "rel", 32, 0, "aos", False),  # wide tiles
+    ("cosmology", 60000, 3, np.float32, 1e-4, "rel", 3000, 0, "aos", False),  # leaves above the tile
+    ("ties", 50000, 2, np.float64, 1e-3, "rel", 2100, 0, "soa", False),
+    ("poincare", 100003, 2, np.float32, 1e-4, "rel", 32, 0, "aos", False),
+    ("fluid", 32768, 3, np.float32, 1e-4, "abs", 32, 0, "aos", True),
+    ("uniform", 100003, 3, np.float64, 1e-5, "abs", 1, 0, "aos", False),  # every particle a reference
+]
+
+
+@pytest.mark.parametrize("case", REF_MODE1_CASES,
+                         ids=lambda c: f"{c[0]}-n{c[1]}-d{c[2]}-{np.dtype(c[3]).name}-r{c[6]}-t{c[7]}-{c[8]}-p{int(c[9])}")
+def test_lossless_reference(orc, bbx, case):
+    """Reference stored as its original coordinates (ref_mode 1): the stream
+    equals the oracle's byte for byte and decodes identically (references
+    exact), with and without a perm output (source indices are carried
+    either way), in every leaf stage and both layouts."""
+    kind, n, dims, dt, eb, mode, r, tile, layout, want_perm = case
+    _say("ref_mode 1", case)
+    pts = gen(kind, n, dims, dt, seed=n % 83 + 5)
+    if mode == "abs":
+        eb = eb * float(np.ptp(pts, axis=0).max() or 1.0)
+    check_parity(orc, bbx, pts, eb, mode, r, layout=layout, tile=tile, ref_mode=1,
+                 want_perm=want_perm)
+
+
+def test_lossless_reference_corrupt_on_device(orc, bbx):
+    """A non-finite stored reference is a corrupt stream on the device too."""
+    pts = cosmology(20000, seed=12)
+    good = orc.compress(pts, 1e-3, "rel", 32, ref_mode=1)
+    meta = int.from_bytes(good[128:136], "little")
+    nan = int(np.array([np.nan], dtype=np.float32).view(np.uint32)[0])
+    meta = (meta & ~(((1 << 32) - 1) << 15)) | (nan << 15)  # first record's x coordinate
+    b = bytearray(good)
+    b[128:136] = meta.to_bytes(8, "little")
+    t = torch.from_numpy(np.frombuffer(bytes(b), dtype=np.uint8).copy()).cuda()
+    with pytest.raises(bbx.BitboxError) as e:
+        bbx.decompress(t)
+    assert e.value.name == "ECORRUPT"
+    with pytest.raises(OracleError):
+        orc.decompress(bytes(b))
 
 
 def test_empty(orc, bbx):
