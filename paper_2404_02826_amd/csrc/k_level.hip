@@ -419,9 +419,13 @@ __global__ void __launch_bounds__(kBlock) k_select_last(uint32_t depth, uint32_t
 // group (double-buffered: one barrier per group).  The next group's codes are
 // loaded before that barrier, so they are in flight while this group waits
 // and stores.
-template <typename KT, bool FULL>
+// With TRACK the source indices (when the set carries them) are loaded with
+// the codes, so they are in flight together.
+template <typename KT, bool FULL, bool TRACK>
 __device__ __forceinline__ void scatter_load(uint32_t g, uint32_t end, const KT* A0, const KT* A1,
-                                             const KT* A2, uint32_t (&k)[3][kRows]) {
+                                             const KT* A2, const uint32_t* is,
+                                             uint32_t (&k)[3][kRows],
+                                             uint32_t (&ki)[TRACK ? kRows : 1]) {
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t wv = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const uint32_t base = g + wv * (kGroup / (kBlock / 64));
@@ -434,6 +438,7 @@ __device__ __forceinline__ void scatter_load(uint32_t g, uint32_t end, const KT*
     k[0][i] = act ? (uint32_t)a0[64 * i] : 0u;
     k[1][i] = act ? (uint32_t)a1[64 * i] : 0u;
     k[2][i] = act ? (uint32_t)a2[64 * i] : 0u;
+    if (TRACK) ki[i] = (act && is) ? is[base + 64u * i + lane] : 0u;
   }
 }
 
@@ -458,8 +463,9 @@ __device__ __forceinline__ void scatter_ranks(uint32_t g, uint32_t end, const ui
   }
 }
 
-template <typename KT, int NA, bool FULL>
+template <typename KT, int NA, bool FULL, bool TRACK>
 __device__ __forceinline__ void scatter_store(uint32_t g, uint32_t end, const uint32_t (&k)[3][kRows],
+                                              const uint32_t (&ki)[TRACK ? kRows : 1],
                                               const uint32_t (&rl)[kRows],
                                               const uint32_t (&re)[kRows], uint32_t bl,
                                               uint32_t be, KT* B0, KT* B1, KT* B2,
@@ -484,7 +490,10 @@ __device__ __forceinline__ void scatter_store(uint32_t g, uint32_t end, const ui
       B0[dest] = (KT)k[0][i];
       if (NA > 1) B1[dest] = (KT)k[1][i];
       if (NA > 2) B2[dest] = (KT)k[2][i];
-      if (is) id[dest] = is[p];
+      if (TRACK && is)
+        id[dest] = ki[i];
+      else if (!TRACK && is)
+        id[dest] = is[p];
       if (left ? cl : cr)
         atomicAdd(&lhist[(left ? 0u : (uint32_t)kBlock) + (((NA > 1 ? k[1][i] : k[0][i]) >> shn) & maskn)],
                   1u);
@@ -494,7 +503,7 @@ __device__ __forceinline__ void scatter_store(uint32_t g, uint32_t end, const ui
   }
 }
 
-template <typename KT, int NA>
+template <typename KT, int NA, bool TRACK>
 __device__ __forceinline__ void scatter_range(uint32_t beg, uint32_t end, const KT* A0, const KT* A1, const KT* A2,
                               KT* B0, KT* B1, KT* B2, const uint32_t* is, uint32_t* id,
                               uint32_t sz, uint32_t v, uint32_t jeq, uint32_t lt_run,
@@ -504,11 +513,12 @@ __device__ __forceinline__ void scatter_range(uint32_t beg, uint32_t end, const 
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t wv = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   uint32_t k[3][kRows], kn[3][kRows];
+  uint32_t ki[TRACK ? kRows : 1], kin[TRACK ? kRows : 1];
   if (beg >= end) return;
   if (beg + kGroup <= end)
-    scatter_load<KT, true>(beg, end, A0, A1, A2, k);
+    scatter_load<KT, true, TRACK>(beg, end, A0, A1, A2, is, k, ki);
   else
-    scatter_load<KT, false>(beg, end, A0, A1, A2, k);
+    scatter_load<KT, false, TRACK>(beg, end, A0, A1, A2, is, k, ki);
   int buf = 0;
   for (uint32_t g = beg; g < end; g += kGroup, buf ^= 1) {
     const bool full = g + kGroup <= end;
@@ -520,9 +530,9 @@ __device__ __forceinline__ void scatter_range(uint32_t beg, uint32_t end, const 
     const uint32_t gn = g + kGroup;
     if (gn < end) {
       if (gn + kGroup <= end)
-        scatter_load<KT, true>(gn, end, A0, A1, A2, kn);
+        scatter_load<KT, true, TRACK>(gn, end, A0, A1, A2, is, kn, kin);
       else
-        scatter_load<KT, false>(gn, end, A0, A1, A2, kn);
+        scatter_load<KT, false, TRACK>(gn, end, A0, A1, A2, is, kn, kin);
     }
     if (lane == 0) cnt[buf][wv][0] = wl, cnt[buf][wv][1] = we;
     __syncthreads();
@@ -533,19 +543,22 @@ __device__ __forceinline__ void scatter_range(uint32_t beg, uint32_t end, const 
     lt_run += X.x + X.z + Y.x + Y.z;
     eq_run += X.y + X.w + Y.y + Y.w;
     if (full)
-      scatter_store<KT, NA, true>(g, end, k, rl, re, bl, be, B0, B1, B2, is, id, sz, v, jeq, cl, cr,
-                                  shn, maskn, lhist, P);
+      scatter_store<KT, NA, true, TRACK>(g, end, k, ki, rl, re, bl, be, B0, B1, B2, is, id, sz, v,
+                                         jeq, cl, cr, shn, maskn, lhist, P);
     else
-      scatter_store<KT, NA, false>(g, end, k, rl, re, bl, be, B0, B1, B2, is, id, sz, v, jeq, cl,
-                                   cr, shn, maskn, lhist, P);
+      scatter_store<KT, NA, false, TRACK>(g, end, k, ki, rl, re, bl, be, B0, B1, B2, is, id, sz, v,
+                                          jeq, cl, cr, shn, maskn, lhist, P);
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
       for (int i = 0; i < kRows; ++i) k[a][i] = kn[a][i];
+    if (TRACK)
+#pragma unroll
+      for (int i = 0; i < kRows; ++i) ki[i] = kin[i];
   }
 }
 
-template <typename KT>
+template <typename KT, bool TRACK>
 __device__ void scatter_body(uint32_t depth, const SetDesc& S, DevParams* P, const LevelCtx& c,
                              uint32_t v, uint32_t jeq, uint32_t lt_run, uint32_t eq_run,
                              const uint8_t* src, uint8_t* dst, const uint32_t* isrc, uint32_t* idst,
@@ -592,10 +605,10 @@ __device__ void scatter_body(uint32_t depth, const SetDesc& S, DevParams* P, con
   KT* B1 = (KT*)dst + st + (uint64_t)a1 * kst;
   KT* B2 = (KT*)dst + st + (uint64_t)a2 * kst;
   if (dims == 3)
-    scatter_range<KT, 3>(beg, end, A0, A1, A2, B0, B1, B2, is, id, sz, v, jeq, lt_run, eq_run, cl,
+    scatter_range<KT, 3, TRACK>(beg, end, A0, A1, A2, B0, B1, B2, is, id, sz, v, jeq, lt_run, eq_run, cl,
                          cr, shn, maskn, lhist, P);
   else  // fewer axes: the missing ones repeat the split axis (same value, same slot)
-    scatter_range<KT, 3>(beg, end, A0, A1, A0, B0, B1, B0, is, id, sz, v, jeq, lt_run, eq_run, cl,
+    scatter_range<KT, 3, TRACK>(beg, end, A0, A1, A0, B0, B1, B0, is, id, sz, v, jeq, lt_run, eq_run, cl,
                          cr, shn, maskn, lhist, P);
   if (fuse) {
     __syncthreads();
@@ -606,6 +619,8 @@ __device__ void scatter_body(uint32_t depth, const SetDesc& S, DevParams* P, con
   }
 }
 
+// TRACK: some set of the batch carries source indices (loaded with the codes)
+template <bool TRACK>
 __global__ void __launch_bounds__(kBlock) k_scatter(uint32_t depth, uint32_t nsets,
                                                     const uint64_t* pre, const SetDesc* sets,
                                                     DevParams* params, const NodeSel* sel0,
@@ -623,10 +638,10 @@ __global__ void __launch_bounds__(kBlock) k_scatter(uint32_t depth, uint32_t nse
   const NodeSel ns = (sel0 + S.sel_off)[c.lb / c.sh.chunks];
   const uint32_t* cb = cb0 + S.cb_off + c.lb * 2;
   if (P->key16)
-    scatter_body<uint16_t>(depth, S, P, c, ns.v, ns.jeq, cb[0], cb[1], src0 + S.key_off,
+    scatter_body<uint16_t, TRACK>(depth, S, P, c, ns.v, ns.jeq, cb[0], cb[1], src0 + S.key_off,
                            dst0 + S.key_off, isrc, idst, hist0 + S.hist_off, lhist);
   else
-    scatter_body<uint32_t>(depth, S, P, c, ns.v, ns.jeq, cb[0], cb[1], src0 + S.key_off,
+    scatter_body<uint32_t, TRACK>(depth, S, P, c, ns.v, ns.jeq, cb[0], cb[1], src0 + S.key_off,
                            dst0 + S.key_off, isrc, idst, hist0 + S.hist_off, lhist);
 }
 
@@ -727,10 +742,10 @@ __global__ void __launch_bounds__(kBlock) k_level_local(uint32_t depth, uint32_t
     __syncthreads();  // lhist is reused by the partition
   }
   if (P->key16)
-    scatter_body<uint16_t>(depth, S, P, c, v, jeq, 0, 0, src0 + S.key_off, dst0 + S.key_off, isrc,
+    scatter_body<uint16_t, false>(depth, S, P, c, v, jeq, 0, 0, src0 + S.key_off, dst0 + S.key_off, isrc,
                            idst, hist0 + S.hist_off, lhist);
   else
-    scatter_body<uint32_t>(depth, S, P, c, v, jeq, 0, 0, src0 + S.key_off, dst0 + S.key_off, isrc,
+    scatter_body<uint32_t, false>(depth, S, P, c, v, jeq, 0, 0, src0 + S.key_off, dst0 + S.key_off, isrc,
                            idst, hist0 + S.hist_off, lhist);
 }
 
@@ -824,7 +839,7 @@ __device__ void wave_median(const KT* axis, uint32_t sz, uint32_t rank, uint32_t
 // 512 members of a node by one wavefront (8 rows of 64), codes in axis order
 // (split axis first); ballots give each member's rank among the members
 // below / equal to the median before it.
-template <typename KT, bool FULL>
+template <typename KT, bool FULL, bool TRACK>
 __device__ __forceinline__ void wave_part_rows(uint32_t base, uint32_t sz, const KT* A0,
                                                const KT* A1, const KT* A2, KT* B0, KT* B1, KT* B2,
                                                const uint32_t* is, uint32_t* id, uint32_t v,
@@ -832,7 +847,7 @@ __device__ __forceinline__ void wave_part_rows(uint32_t base, uint32_t sz, const
                                                DevParams* P) {
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t half = sz >> 1;
-  uint32_t k0[8], k1[8], k2[8];
+  uint32_t k0[8], k1[8], k2[8], ix[TRACK ? 8 : 1];
   {
     const KT* a0 = A0 + base + lane;
     const KT* a1 = A1 + base + lane;
@@ -843,6 +858,7 @@ __device__ __forceinline__ void wave_part_rows(uint32_t base, uint32_t sz, const
       k0[i] = act ? (uint32_t)a0[64 * i] : 0u;
       k1[i] = act ? (uint32_t)a1[64 * i] : 0u;
       k2[i] = act ? (uint32_t)a2[64 * i] : 0u;
+      if (TRACK) ix[i] = (act && is) ? is[base + 64u * i + lane] : 0u;  // with the codes
     }
   }
 #pragma unroll
@@ -861,7 +877,10 @@ __device__ __forceinline__ void wave_part_rows(uint32_t base, uint32_t sz, const
         B0[dest] = (KT)k0[i];
         B1[dest] = (KT)k1[i];
         B2[dest] = (KT)k2[i];
-        if (is) id[dest] = is[p];
+        if (TRACK && is)
+          id[dest] = ix[i];
+        else if (!TRACK && is)
+          id[dest] = is[p];
       } else {
         P->status = BBX_EHIP;  // inconsistent counts: never expected
       }
@@ -873,7 +892,7 @@ __device__ __forceinline__ void wave_part_rows(uint32_t base, uint32_t sz, const
 
 // Stable partition of one node by one wavefront.  With fewer than three axes
 // the missing ones repeat the split axis (the same value to the same slot).
-template <typename KT>
+template <typename KT, bool TRACK>
 __device__ void wave_partition(const KT* src, KT* dst, uint64_t kst, const uint32_t* is,
                                uint32_t* id, uint32_t dims, uint32_t d, uint32_t sz, uint32_t v,
                                uint32_t jeq, DevParams* P) {
@@ -887,14 +906,15 @@ __device__ void wave_partition(const KT* src, KT* dst, uint64_t kst, const uint3
   uint32_t lt_run = 0, eq_run = 0;
   for (uint32_t base = 0; base < sz; base += 512) {
     if (base + 512 <= sz)
-      wave_part_rows<KT, true>(base, sz, A0, A1, A2, B0, B1, B2, is, id, v, jeq, lt_run, eq_run, P);
+      wave_part_rows<KT, true, TRACK>(base, sz, A0, A1, A2, B0, B1, B2, is, id, v, jeq, lt_run,
+                                      eq_run, P);
     else
-      wave_part_rows<KT, false>(base, sz, A0, A1, A2, B0, B1, B2, is, id, v, jeq, lt_run, eq_run,
-                                P);
+      wave_part_rows<KT, false, TRACK>(base, sz, A0, A1, A2, B0, B1, B2, is, id, v, jeq, lt_run,
+                                       eq_run, P);
   }
 }
 
-template <typename KT>
+template <typename KT, bool TRACK>
 __device__ void level_wave_body(uint32_t depth, const SetDesc& S, DevParams* P, uint64_t j,
                                 const uint8_t* src, uint8_t* dst, const uint32_t* isrc,
                                 uint32_t* idst, uint32_t* bins) {
@@ -918,11 +938,12 @@ __device__ void level_wave_body(uint32_t depth, const SetDesc& S, DevParams* P, 
   }
   uint32_t v, jeq;
   wave_median(s0 + (uint64_t)d * kst, sz, sz >> 1, bins, &v, &jeq);
-  wave_partition(s0, d0, kst, is, id, dims, d, sz, v, jeq, P);
+  wave_partition<KT, TRACK>(s0, d0, kst, is, id, dims, d, sz, v, jeq, P);
 }
 
 // Levels whose nodes have at most kWaveNode members: one wavefront per node,
 // four nodes per block, no block barriers.
+template <bool TRACK>
 __global__ void __launch_bounds__(kBlock) k_level_wave(uint32_t depth, uint32_t nsets,
                                                        const uint64_t* pre, const SetDesc* sets,
                                                        DevParams* params, uint8_t* src0,
@@ -941,9 +962,11 @@ __global__ void __launch_bounds__(kBlock) k_level_wave(uint32_t depth, uint32_t 
   const uint32_t* isrc = S.track ? isrc0 + S.idx_off : nullptr;
   uint32_t* idst = S.track ? idst0 + S.idx_off : nullptr;
   if (P->key16)
-    level_wave_body<uint16_t>(depth, S, P, j, src0 + S.key_off, dst0 + S.key_off, isrc, idst, bins[wv]);
+    level_wave_body<uint16_t, TRACK>(depth, S, P, j, src0 + S.key_off, dst0 + S.key_off, isrc, idst,
+                                     bins[wv]);
   else
-    level_wave_body<uint32_t>(depth, S, P, j, src0 + S.key_off, dst0 + S.key_off, isrc, idst, bins[wv]);
+    level_wave_body<uint32_t, TRACK>(depth, S, P, j, src0 + S.key_off, dst0 + S.key_off, isrc, idst,
+                                     bins[wv]);
 }
 
 // blocks of a select launch: one wavefront per node up to 8192 blocks, then striding
@@ -964,9 +987,9 @@ hipError_t launch_levels(const BatchPlan& bp, const Ws& w, hipStream_t s) {
       BBX_LAUNCH("level_local", k_level_local, bp.g_lv[k], kBlock, 0, s, k, bp.nsets, plv, w.sets,
                  w.params, w.keys[cur], w.keys[cur ^ 1], w.idx[cur], w.idx[cur ^ 1], w.hist);
     if (bp.lv_wave[k])
-      BBX_LAUNCH("level_wave", k_level_wave, (bp.g_nd[k] + kBlock / 64 - 1) / (kBlock / 64), kBlock,
-                 0, s, k, bp.nsets, pnd, w.sets, w.params, w.keys[cur], w.keys[cur ^ 1], w.idx[cur],
-                 w.idx[cur ^ 1]);
+      BBX_LAUNCH("level_wave", bp.track ? k_level_wave<true> : k_level_wave<false>,
+                 (bp.g_nd[k] + kBlock / 64 - 1) / (kBlock / 64), kBlock, 0, s, k, bp.nsets, pnd,
+                 w.sets, w.params, w.keys[cur], w.keys[cur ^ 1], w.idx[cur], w.idx[cur ^ 1]);
     if (!bp.lv_global[k]) continue;
     // mid passes: pass 0 was built by the quantize pass (depth 0) or by the
     // previous scatter
@@ -982,9 +1005,9 @@ hipError_t launch_levels(const BatchPlan& bp, const Ws& w, hipStream_t s) {
                w.params, w.keys[cur], w.sel, w.hist, w.rows);
     BBX_LAUNCH("level_select_last", k_select_last, sel_grid(bp.g_nd[k]), kBlock, 0, s, k,
                bp.nsets, pnd, w.sets, w.params, w.sel, w.hist, w.rows, w.chunk_base);
-    BBX_LAUNCH("level_scatter", k_scatter, bp.g_lv[k], kBlock, 0, s, k, bp.nsets, plv, w.sets,
-               w.params, w.sel, w.chunk_base, w.keys[cur], w.keys[cur ^ 1], w.idx[cur],
-               w.idx[cur ^ 1], w.hist);
+    BBX_LAUNCH("level_scatter", bp.track ? k_scatter<true> : k_scatter<false>, bp.g_lv[k], kBlock,
+               0, s, k, bp.nsets, plv, w.sets, w.params, w.sel, w.chunk_base, w.keys[cur],
+               w.keys[cur ^ 1], w.idx[cur], w.idx[cur ^ 1], w.hist);
   }
   return hipGetLastError();
 }
