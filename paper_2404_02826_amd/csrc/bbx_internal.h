@@ -87,6 +87,7 @@ struct SetDesc {
   uint32_t ref_rule;      // leaf reference: 0 nearest the AABB centre, 1 fewest code bits
   uint32_t ref_mode;      // reference stored as 0 its codes, 1 its original coordinates
   uint32_t track;         // source indices follow the codes (perm output or ref_mode 1)
+  uint32_t fuse_depth;    // depth k whose levels k, k + 1 run fused in place (kNoFuse: none)
   uint64_t n_leaves;
   uint64_t key_off;       // byte offset into each key buffer (capacity dims*n*4)
   uint64_t idx_off;       // u32 offset into each index buffer
@@ -254,6 +255,17 @@ __host__ __device__ inline bool level_is_local(uint64_t n, uint32_t depth) {
   return level_kind(n, depth) != kLevelGlobal;
 }
 
+// The last two levels above the tile stage (depths gl - 2 and gl - 1 of a
+// set with a tile stage) run as one in-place pass when their nodes have at
+// most kFuseNode members: one wavefront holds a node in registers and splits
+// it twice.
+constexpr uint64_t kFuseNode = 1024;
+constexpr uint32_t kNoFuse = 0x80000000u;  // depth - kNoFuse >= 2 for every depth (unsigned)
+__host__ __device__ inline uint32_t fuse_depth_of(uint64_t n, uint32_t gl, bool tile_mode) {
+  if (!tile_mode || gl < 2) return kNoFuse;
+  return ((n + (1ull << (gl - 2)) - 1) >> (gl - 2)) <= kFuseNode ? gl - 2 : kNoFuse;
+}
+
 // Leaves per block of the leaf-aligned packing and unpacking kernels: at most
 // 2048 slots and 256 leaves per block.
 __host__ __device__ inline uint32_t leaves_per_block(uint32_t r) {
@@ -361,6 +373,7 @@ struct BatchPlan {
   uint8_t lv_local[kMaxDepth];   // some set handles level k one block per node
   uint8_t lv_global[kMaxDepth];  // some set handles level k with global histograms
   uint8_t lv_wave[kMaxDepth];    // some set handles level k one wavefront per node
+  uint8_t lv_fused[kMaxDepth];   // some set handles levels k, k + 1 fused (k_level_fused)
   uint64_t pre_entries;       // total u64 entries of the prefix buffer
 };
 

@@ -927,6 +927,7 @@ __device__ void level_wave_body(uint32_t depth, const SetDesc& S, DevParams* P, 
   KT* d0 = (KT*)dst + st;
   const uint32_t* is = isrc ? isrc + st : nullptr;
   uint32_t* id = idst ? idst + st : nullptr;
+  if (depth - S.fuse_depth < 2u) return;  // levels of k_level_fused
   if (sz <= S.r) {  // leaf: copy through
     for (uint32_t p = threadIdx.x & 63; p < sz; p += 64) {
       d0[p] = s0[p];
@@ -969,6 +970,177 @@ __global__ void __launch_bounds__(kBlock) k_level_wave(uint32_t depth, uint32_t 
                                      bins[wv]);
 }
 
+// ---------------------------------------------------------------- fused last levels
+
+constexpr int kFuseRows = (int)(kFuseNode / 64);
+
+// Radix select over codes held in registers (R rows of 64 lanes): the member
+// of rank `rank` among the rows flagged in the lane's bit mask `m` (bit i =
+// row i), ordered by (code, row-major position); widest digit first, at most
+// 8 bits per pass, in the wavefront's own bins.  Returns the code and how
+// many members equal to it precede it.
+template <int R>
+__device__ void reg_select(const uint32_t (&q)[R], uint32_t m, uint32_t rank, uint32_t* bins,
+                           uint32_t* v_out, uint32_t* jeq_out) {
+  const uint32_t lane = threadIdx.x & 63;
+  uint32_t lo = 0xffffffffu, hi = 0;
+#pragma unroll
+  for (int i = 0; i < R; ++i)
+    if ((m >> i) & 1u) lo = umin32(lo, q[i]), hi = umax32(hi, q[i]);
+  const uint32_t mn = wave_min_dpp(lo);
+  const uint32_t Gs = bitlen32(wave_max_dpp(hi) - mn);
+  uint32_t prefix = 0, used = 0;
+  while (used < Gs) {
+    const uint32_t w = Gs - used < 8 ? Gs - used : 8;
+    const uint32_t hs = Gs - used;
+    used += w;
+    const uint32_t sh = Gs - used, mask = (1u << w) - 1;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) bins[lane * 4 + k] = 0;
+    wave_sync();
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const uint32_t k = q[i] - mn;
+      if (((m >> i) & 1u) && (k >> hs) == prefix) atomicAdd(&bins[(k >> sh) & mask], 1u);
+    }
+    wave_sync();
+    uint32_t c[4], mine = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) c[k] = bins[lane * 4 + k], mine += c[k];
+    uint32_t cum = wave_incl(mine) - mine;
+    uint32_t fb = 0, fr = 0;
+    bool found = false;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (cum <= rank && rank < cum + c[k]) found = true, fb = lane * 4 + k, fr = rank - cum;
+      cum += c[k];
+    }
+    const uint64_t fm = __ballot(found);
+    const int fl = fm ? __ffsll((unsigned long long)fm) - 1 : 0;
+    prefix = (prefix << w) | (uint32_t)__builtin_amdgcn_readlane((int)fb, fl);
+    rank = (uint32_t)__builtin_amdgcn_readlane((int)fr, fl);
+    wave_sync();  // the bins are cleared by the next pass
+  }
+  *v_out = mn + prefix;
+  *jeq_out = rank;
+}
+
+// Levels k and k + 1 of one node (at most kFuseNode members) by one
+// wavefront, in place: the node's codes (and source indices) are loaded into
+// registers, the node's median along axis d and then each child's median
+// along the next axis are selected there, and every member is written once,
+// to its grandchild's slot.  Equal to two stable partitions: the children
+// keep the node's member order, and the grandchildren the children's.  All
+// loads precede the first store, and no other wavefront touches the node.
+template <typename KT, bool TRACK>
+__device__ void level_fused_body(uint32_t depth, const SetDesc& S, DevParams* P, uint64_t j,
+                                 uint8_t* keys, uint32_t* idx, uint32_t* bins) {
+  constexpr int R = kFuseRows;
+  const uint32_t lane = threadIdx.x & 63;
+  uint64_t st, sz64;
+  node_span(S.n, depth, j, &st, &sz64);
+  if (sz64 > kFuseNode || sz64 <= S.r) {  // launch plan violated: never expected
+    if (lane == 0) P->status = BBX_EHIP;
+    return;
+  }
+  const uint32_t s = (uint32_t)sz64;
+  const uint32_t dims = S.dims, d = depth % dims;
+  const uint32_t a1 = (d + 1) % dims, a2 = dims > 2 ? (d + 2) % dims : d;
+  const uint64_t kst = S.kst;
+  KT* X0 = (KT*)keys + st + (uint64_t)d * kst;
+  KT* X1 = (KT*)keys + st + (uint64_t)a1 * kst;
+  KT* X2 = (KT*)keys + st + (uint64_t)a2 * kst;
+  uint32_t* I = idx ? idx + st : nullptr;
+  uint32_t q0[R], q1[R], q2[R], ix[TRACK ? R : 1];
+  uint32_t act = 0;  // bit i: row i holds a member in this lane
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const uint32_t p = 64u * i + lane;
+    const bool a = p < s;
+    act |= a ? (1u << i) : 0u;
+    q0[i] = a ? (uint32_t)X0[p] : 0u;
+    q1[i] = a ? (uint32_t)X1[p] : 0u;
+    q2[i] = a ? (uint32_t)X2[p] : 0u;
+    if (TRACK) ix[i] = (a && I) ? I[p] : 0u;
+  }
+  // level k: the node's median along d, then each member's side
+  uint32_t v, jeq;
+  reg_select<R>(q0, act, s >> 1, bins, &v, &jeq);
+  uint32_t left = 0, erun = 0;
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const bool a = (act >> i) & 1u;
+    const bool lt = q0[i] < v, eq = q0[i] == v;
+    const uint64_t meq = __ballot(a && eq);
+    const uint32_t E = erun + lanes_below(meq);
+    left |= (a && (lt || (eq && E < jeq))) ? (1u << i) : 0u;
+    erun += popc64(meq);
+  }
+  const uint32_t right = act & ~left;
+  // level k + 1: each child's median along the next axis
+  const uint32_t sL = s >> 1, sR = s - sL, hL = sL >> 1, hR = sR >> 1;
+  uint32_t vL, jL, vR, jR;
+  reg_select<R>(q1, left, hL, bins, &vL, &jL);
+  reg_select<R>(q1, right, hR, bins, &vR, &jR);
+  // grandchildren: LL [0, hL), LR [hL, sL), RL [sL, sL + hR), RR [sL + hR, s)
+  uint32_t eL = 0, eR = 0, cLL = 0, cLR = 0, cRL = 0, cRR = 0;
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const bool a = (act >> i) & 1u;
+    const bool L = (left >> i) & 1u, Rt = (right >> i) & 1u;
+    const bool eqL = q1[i] == vL, eqR = q1[i] == vR;
+    const uint64_t bEL = __ballot(L && eqL), bER = __ballot(Rt && eqR);
+    const bool toLL = L && (q1[i] < vL || (eqL && eL + lanes_below(bEL) < jL));
+    const bool toRL = Rt && (q1[i] < vR || (eqR && eR + lanes_below(bER) < jR));
+    const uint64_t bLL = __ballot(toLL), bLR = __ballot(L && !toLL);
+    const uint64_t bRL = __ballot(toRL), bRR = __ballot(Rt && !toRL);
+    const uint32_t dest = toLL ? cLL + lanes_below(bLL)
+                          : L  ? hL + cLR + lanes_below(bLR)
+                          : toRL ? sL + cRL + lanes_below(bRL)
+                                 : sL + hR + cRR + lanes_below(bRR);
+    if (a) {
+      if (dest < s) {
+        X0[dest] = (KT)q0[i];
+        X1[dest] = (KT)q1[i];
+        X2[dest] = (KT)q2[i];
+        if (TRACK && I) I[dest] = ix[i];
+      } else {
+        P->status = BBX_EHIP;  // inconsistent counts: never expected
+      }
+    }
+    eL += popc64(bEL);
+    eR += popc64(bER);
+    cLL += popc64(bLL);
+    cLR += popc64(bLR);
+    cRL += popc64(bRL);
+    cRR += popc64(bRR);
+  }
+}
+
+// Levels k and k + 1 of the sets whose fused depth is k: one wavefront per
+// node of depth k, four nodes per block.
+template <bool TRACK>
+__global__ void __launch_bounds__(kBlock) k_level_fused(uint32_t depth, uint32_t nsets,
+                                                        const uint64_t* pre, const SetDesc* sets,
+                                                        DevParams* params, uint8_t* keys0,
+                                                        uint32_t* idx0) {
+  __shared__ uint32_t bins[kBlock / 64][256];
+  const uint32_t wv = threadIdx.x >> 6;
+  const uint64_t gn = (uint64_t)blockIdx.x * (kBlock / 64) + wv;
+  if (gn >= pre[nsets]) return;  // whole wavefront
+  const uint32_t s = find_set(pre, nsets, gn);
+  const SetDesc& S = sets[s];
+  DevParams* P = params + s;
+  if (P->status != BBX_OK) return;
+  if (S.fuse_depth != depth) return;
+  const uint64_t j = gn - pre[s];
+  uint32_t* idx = S.track ? idx0 + S.idx_off : nullptr;
+  if (P->key16)
+    level_fused_body<uint16_t, TRACK>(depth, S, P, j, keys0 + S.key_off, idx, bins[wv]);
+  else
+    level_fused_body<uint32_t, TRACK>(depth, S, P, j, keys0 + S.key_off, idx, bins[wv]);
+}
+
 // blocks of a select launch: one wavefront per node up to 8192 blocks, then striding
 static uint64_t sel_grid(uint64_t nodes) {
   const uint64_t b = (nodes + kBlock / 64 - 1) / (kBlock / 64);
@@ -990,6 +1162,10 @@ hipError_t launch_levels(const BatchPlan& bp, const Ws& w, hipStream_t s) {
       BBX_LAUNCH("level_wave", bp.track ? k_level_wave<true> : k_level_wave<false>,
                  (bp.g_nd[k] + kBlock / 64 - 1) / (kBlock / 64), kBlock, 0, s, k, bp.nsets, pnd,
                  w.sets, w.params, w.keys[cur], w.keys[cur ^ 1], w.idx[cur], w.idx[cur ^ 1]);
+    if (bp.lv_fused[k])  // levels k and k + 1 in place: depth k + 2 keeps buffer `cur`
+      BBX_LAUNCH("level_fused", bp.track ? k_level_fused<true> : k_level_fused<false>,
+                 (bp.g_nd[k] + kBlock / 64 - 1) / (kBlock / 64), kBlock, 0, s, k, bp.nsets, pnd,
+                 w.sets, w.params, w.keys[cur], w.idx[cur]);
     if (!bp.lv_global[k]) continue;
     // mid passes: pass 0 was built by the quantize pass (depth 0) or by the
     // previous scatter

@@ -120,6 +120,7 @@ CASES = [
     ("cosmology", 60000, 3, np.float32, 1e-4, "rel", 3000),
     ("cosmology", 60000, 3, np.float32, 1e-4, "rel", 60000),  # single leaf
     ("uniform", 10000, 3, np.float32, 1e-3, "rel", 4999),     # leaves of r+1 split once more
+    ("uniform", 3001, 2, np.float32, 1e-2, "rel", 700),       # wavefront level at depth 0, no tiles
     ("ties", 50000, 2, np.float64, 1e-3, "rel", 2100),
     ("poincare", 100003, 2, np.float32, 1e-4, "rel", 32),     # fusion-shaped 2-D
     ("poincare", 300007, 2, np.float32, 1e-3, "rel", 16),
