@@ -190,7 +190,7 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
     const SetIn& I = in[s];
     SetDesc& D = (*descs)[s];
     memset(&D, 0, sizeof(D));
-    D.fuse_depth = kNoFuse;
+    D.fuse_depth = D.fuse_depth4 = kNoFuse;
     D.pos = I.pos;
     D.out = (uint8_t*)I.out;
     D.perm = I.d_perm;
@@ -225,7 +225,9 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
         D.gl = ((n + (1ull << K) - 1) >> K) <= D.r ? K : K + 1;
       }
       D.final_buf = D.tile_mode ? (D.gl & 1) : ((D.gl & 1) ^ 1);
-      D.fuse_depth = fuse_depth_of(n, D.gl, D.tile_mode != 0);
+      D.fuse_depth = fuse_depth_of(n, D.gl, D.tile_mode != 0, 2, kFuseNode);
+      if (D.fuse_depth != kNoFuse)
+        D.fuse_depth4 = fuse_depth_of(n, D.gl, D.tile_mode != 0, 4, 4 * kFuseNode);
       mm[s] = std::min<uint64_t>((n + 2047) / 2048, kMaxMinMaxBlocks);
       qz[s] = std::min<uint64_t>((n + 1023) / 1024, 16384);
       tl[s] = D.tile_mode ? (1ull << D.gl) : 0;
@@ -239,8 +241,10 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
       for (uint32_t k = 0; k < D.gl; ++k) {
         const LevelShape sh = level_shape(n, k, D.level_blocks);
         const int kind = level_kind(n, k);
-        if (D.fuse_depth != kNoFuse && (k == D.fuse_depth || k == D.fuse_depth + 1)) {
+        if (k - D.fuse_depth < 2u) {
           if (k == D.fuse_depth) bp->lv_fused[k] = 1;  // both levels in one pass
+        } else if (k - D.fuse_depth4 < 2u) {
+          if (k == D.fuse_depth4) bp->lv_fused4[k] = 1;
         } else if (kind == 2)
           bp->lv_wave[k] = 1;
         else if (kind == 1)

@@ -87,7 +87,8 @@ struct SetDesc {
   uint32_t ref_rule;      // leaf reference: 0 nearest the AABB centre, 1 fewest code bits
   uint32_t ref_mode;      // reference stored as 0 its codes, 1 its original coordinates
   uint32_t track;         // source indices follow the codes (perm output or ref_mode 1)
-  uint32_t fuse_depth;    // depth k whose levels k, k + 1 run fused in place (kNoFuse: none)
+  uint32_t fuse_depth;    // depth k whose levels k, k + 1 run fused in place, a wavefront per node (kNoFuse: none)
+  uint32_t fuse_depth4;   // the same with a block per node (nodes of at most 4 kFuseNode)
   uint64_t n_leaves;
   uint64_t key_off;       // byte offset into each key buffer (capacity dims*n*4)
   uint64_t idx_off;       // u32 offset into each index buffer
@@ -255,15 +256,19 @@ __host__ __device__ inline bool level_is_local(uint64_t n, uint32_t depth) {
   return level_kind(n, depth) != kLevelGlobal;
 }
 
-// The last two levels above the tile stage (depths gl - 2 and gl - 1 of a
-// set with a tile stage) run as one in-place pass when their nodes have at
-// most kFuseNode members: one wavefront holds a node in registers and splits
-// it twice.
+// The last levels above the tile stage of a set with a tile stage run in
+// in-place pairs with the node in registers: depths gl - 2 and gl - 1 when
+// their nodes have at most kFuseNode members (a wavefront per node), and
+// depths gl - 4 and gl - 3 when theirs have at most 4 kFuseNode (a block of
+// four wavefronts per node).  Each pair leaves the data of depth k + 2 in
+// the buffer of depth k, which has its parity.
 constexpr uint64_t kFuseNode = 1024;
 constexpr uint32_t kNoFuse = 0x80000000u;  // depth - kNoFuse >= 2 for every depth (unsigned)
-__host__ __device__ inline uint32_t fuse_depth_of(uint64_t n, uint32_t gl, bool tile_mode) {
-  if (!tile_mode || gl < 2) return kNoFuse;
-  return ((n + (1ull << (gl - 2)) - 1) >> (gl - 2)) <= kFuseNode ? gl - 2 : kNoFuse;
+__host__ __device__ inline uint32_t fuse_depth_of(uint64_t n, uint32_t gl, bool tile_mode,
+                                                  uint32_t back, uint64_t max_node) {
+  if (!tile_mode || gl < back) return kNoFuse;
+  const uint32_t k = gl - back;
+  return ((n + (1ull << k) - 1) >> k) <= max_node ? k : kNoFuse;
 }
 
 // Leaves per block of the leaf-aligned packing and unpacking kernels: at most
@@ -373,7 +378,8 @@ struct BatchPlan {
   uint8_t lv_local[kMaxDepth];   // some set handles level k one block per node
   uint8_t lv_global[kMaxDepth];  // some set handles level k with global histograms
   uint8_t lv_wave[kMaxDepth];    // some set handles level k one wavefront per node
-  uint8_t lv_fused[kMaxDepth];   // some set handles levels k, k + 1 fused (k_level_fused)
+  uint8_t lv_fused[kMaxDepth];   // some set handles levels k, k + 1 fused, a wavefront per node
+  uint8_t lv_fused4[kMaxDepth];  // some set handles levels k, k + 1 fused, a block per node
   uint64_t pre_entries;       // total u64 entries of the prefix buffer
 };
 

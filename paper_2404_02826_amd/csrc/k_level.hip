@@ -927,7 +927,7 @@ __device__ void level_wave_body(uint32_t depth, const SetDesc& S, DevParams* P, 
   KT* d0 = (KT*)dst + st;
   const uint32_t* is = isrc ? isrc + st : nullptr;
   uint32_t* id = idst ? idst + st : nullptr;
-  if (depth - S.fuse_depth < 2u) return;  // levels of k_level_fused
+  if (depth - S.fuse_depth < 2u || depth - S.fuse_depth4 < 2u) return;  // levels of k_level_fused
   if (sz <= S.r) {  // leaf: copy through
     for (uint32_t p = threadIdx.x & 63; p < sz; p += 64) {
       d0[p] = s0[p];
@@ -970,77 +970,142 @@ __global__ void __launch_bounds__(kBlock) k_level_wave(uint32_t depth, uint32_t 
                                      bins[wv]);
 }
 
-// ---------------------------------------------------------------- fused last levels
+// ---------------------------------------------------------------- fused levels
 
+// Pairs of levels run as one in-place pass with a node's codes in registers:
+// W wavefronts per node (1: nodes of at most kFuseNode members, four nodes
+// per block; 4: nodes of at most 4 kFuseNode, one node per block), each
+// wavefront holding R = kFuseNode / 64 rows of 64 consecutive members
+// (wavefront w: members [w kFuseNode, (w + 1) kFuseNode)).
 constexpr int kFuseRows = (int)(kFuseNode / 64);
 
-// Radix select over codes held in registers (R rows of 64 lanes): the member
-// of rank `rank` among the rows flagged in the lane's bit mask `m` (bit i =
-// row i), ordered by (code, row-major position); widest digit first, at most
-// 8 bits per pass, in the wavefront's own bins.  Returns the code and how
-// many members equal to it precede it.
-template <int R>
+// sum over the wavefront (uniform result)
+__device__ inline uint32_t wave_sum(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)wave_incl(x), 63);
+}
+
+template <int W>
+__device__ inline void fuse_sync() {
+  if (W == 1)
+    wave_sync();
+  else
+    __syncthreads();
+}
+
+// Per-wavefront totals t[0..K) (uniform within each wavefront) -> the sum
+// over the node's lower wavefronts (member order is wavefront-major).
+template <int W, int K>
+__device__ inline void fuse_bases(const uint32_t (&t)[K], uint32_t (&b)[K], uint32_t (*xs)[4]) {
+  static_assert(K <= 4, "four totals per exchange");
+#pragma unroll
+  for (int k = 0; k < K; ++k) b[k] = 0;
+  if (W == 1) return;
+  const uint32_t wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int k = 0; k < K; ++k) xs[wv][k] = t[k];
+  __syncthreads();
+#pragma unroll
+  for (int w = 0; w < W; ++w)
+#pragma unroll
+    for (int k = 0; k < K; ++k) b[k] += (uint32_t)w < wv ? xs[w][k] : 0u;
+  __syncthreads();  // xs is reused by the next exchange
+}
+
+// Radix select over the node's codes held in registers: the member of rank
+// `rank` among the rows flagged in the lane's bit mask `m` (bit i = row i),
+// ordered by (code, member order); widest digit first, at most 8 bits per
+// pass, in the node's 256 bins.  Returns the code and how many members equal
+// to it precede it.
+template <int R, int W>
 __device__ void reg_select(const uint32_t (&q)[R], uint32_t m, uint32_t rank, uint32_t* bins,
-                           uint32_t* v_out, uint32_t* jeq_out) {
-  const uint32_t lane = threadIdx.x & 63;
+                           uint32_t* red, uint32_t* v_out, uint32_t* jeq_out) {
+  const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   uint32_t lo = 0xffffffffu, hi = 0;
 #pragma unroll
   for (int i = 0; i < R; ++i)
     if ((m >> i) & 1u) lo = umin32(lo, q[i]), hi = umax32(hi, q[i]);
-  const uint32_t mn = wave_min_dpp(lo);
-  const uint32_t Gs = bitlen32(wave_max_dpp(hi) - mn);
+  uint32_t mn = wave_min_dpp(lo), mx = wave_max_dpp(hi);
+  if (W > 1) {
+    if (lane == 0) red[wv] = mn, red[W + wv] = mx;
+    __syncthreads();
+    mn = red[0], mx = red[W];
+#pragma unroll
+    for (int w = 1; w < W; ++w) mn = umin32(mn, red[w]), mx = umax32(mx, red[W + w]);
+    __syncthreads();
+  }
+  const uint32_t Gs = bitlen32(mx - mn);
   uint32_t prefix = 0, used = 0;
   while (used < Gs) {
     const uint32_t w = Gs - used < 8 ? Gs - used : 8;
     const uint32_t hs = Gs - used;
     used += w;
     const uint32_t sh = Gs - used, mask = (1u << w) - 1;
+    if (W == 1) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) bins[lane * 4 + k] = 0;
-    wave_sync();
+      for (int k = 0; k < 4; ++k) bins[lane * 4 + k] = 0;
+    } else if (threadIdx.x < 256) {
+      bins[threadIdx.x] = 0;
+    }
+    fuse_sync<W>();
 #pragma unroll
     for (int i = 0; i < R; ++i) {
       const uint32_t k = q[i] - mn;
       if (((m >> i) & 1u) && (k >> hs) == prefix) atomicAdd(&bins[(k >> sh) & mask], 1u);
     }
-    wave_sync();
-    uint32_t c[4], mine = 0;
+    fuse_sync<W>();
+    if (W == 1 || wv == 0) {  // the node's (first) wavefront finds the bin holding the rank
+      uint32_t c[4], mine = 0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) c[k] = bins[lane * 4 + k], mine += c[k];
-    uint32_t cum = wave_incl(mine) - mine;
-    uint32_t fb = 0, fr = 0;
-    bool found = false;
+      for (int k = 0; k < 4; ++k) c[k] = bins[lane * 4 + k], mine += c[k];
+      uint32_t cum = wave_incl(mine) - mine;
+      uint32_t fb = 0, fr = 0;
+      bool found = false;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      if (cum <= rank && rank < cum + c[k]) found = true, fb = lane * 4 + k, fr = rank - cum;
-      cum += c[k];
+      for (int k = 0; k < 4; ++k) {
+        if (cum <= rank && rank < cum + c[k]) found = true, fb = lane * 4 + k, fr = rank - cum;
+        cum += c[k];
+      }
+      const uint64_t fm = __ballot(found);
+      const int fl = fm ? __ffsll((unsigned long long)fm) - 1 : 0;
+      fb = (uint32_t)__builtin_amdgcn_readlane((int)fb, fl);
+      fr = (uint32_t)__builtin_amdgcn_readlane((int)fr, fl);
+      if (W == 1) {
+        prefix = (prefix << w) | fb;
+        rank = fr;
+      } else if (lane == 0) {
+        red[2 * W] = fb, red[2 * W + 1] = fr;
+      }
     }
-    const uint64_t fm = __ballot(found);
-    const int fl = fm ? __ffsll((unsigned long long)fm) - 1 : 0;
-    prefix = (prefix << w) | (uint32_t)__builtin_amdgcn_readlane((int)fb, fl);
-    rank = (uint32_t)__builtin_amdgcn_readlane((int)fr, fl);
-    wave_sync();  // the bins are cleared by the next pass
+    if (W > 1) {
+      __syncthreads();
+      prefix = (prefix << w) | red[2 * W];
+      rank = red[2 * W + 1];
+    }
+    fuse_sync<W>();  // the bins (and red) are rewritten by the next pass
   }
   *v_out = mn + prefix;
   *jeq_out = rank;
 }
 
-// Levels k and k + 1 of one node (at most kFuseNode members) by one
-// wavefront, in place: the node's codes (and source indices) are loaded into
-// registers, the node's median along axis d and then each child's median
-// along the next axis are selected there, and every member is written once,
-// to its grandchild's slot.  Equal to two stable partitions: the children
-// keep the node's member order, and the grandchildren the children's.  All
-// loads precede the first store, and no other wavefront touches the node.
-template <typename KT, bool TRACK>
+// Levels k and k + 1 of one node, in place: the node's codes (and source
+// indices) are loaded into registers, the node's median along axis d and
+// then each child's median along the next axis are selected there, and every
+// member is written once, to its grandchild's slot.  Equal to two stable
+// partitions: the children keep the node's member order, and the
+// grandchildren the children's.  All loads precede the first store, and no
+// other wavefront or block touches the node.
+template <typename KT, bool TRACK, int W>
 __device__ void level_fused_body(uint32_t depth, const SetDesc& S, DevParams* P, uint64_t j,
-                                 uint8_t* keys, uint32_t* idx, uint32_t* bins) {
+                                 uint8_t* keys, uint32_t* idx, uint32_t* bins, uint32_t* red,
+                                 uint32_t (*xs)[4]) {
   constexpr int R = kFuseRows;
   const uint32_t lane = threadIdx.x & 63;
+  const uint32_t wv = W == 1 ? 0u : (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   uint64_t st, sz64;
   node_span(S.n, depth, j, &st, &sz64);
-  if (sz64 > kFuseNode || sz64 <= S.r) {  // launch plan violated: never expected
-    if (lane == 0) P->status = BBX_EHIP;
+  if (sz64 > (uint64_t)W * kFuseNode || sz64 <= S.r) {  // launch plan violated: never expected
+    if (threadIdx.x == 0) P->status = BBX_EHIP;
     return;
   }
   const uint32_t s = (uint32_t)sz64;
@@ -1051,11 +1116,12 @@ __device__ void level_fused_body(uint32_t depth, const SetDesc& S, DevParams* P,
   KT* X1 = (KT*)keys + st + (uint64_t)a1 * kst;
   KT* X2 = (KT*)keys + st + (uint64_t)a2 * kst;
   uint32_t* I = idx ? idx + st : nullptr;
+  const uint32_t p0 = wv * (uint32_t)kFuseNode + lane;  // the lane's member of row 0
   uint32_t q0[R], q1[R], q2[R], ix[TRACK ? R : 1];
   uint32_t act = 0;  // bit i: row i holds a member in this lane
 #pragma unroll
   for (int i = 0; i < R; ++i) {
-    const uint32_t p = 64u * i + lane;
+    const uint32_t p = p0 + 64u * i;
     const bool a = p < s;
     act |= a ? (1u << i) : 0u;
     q0[i] = a ? (uint32_t)X0[p] : 0u;
@@ -1063,42 +1129,71 @@ __device__ void level_fused_body(uint32_t depth, const SetDesc& S, DevParams* P,
     q2[i] = a ? (uint32_t)X2[p] : 0u;
     if (TRACK) ix[i] = (a && I) ? I[p] : 0u;
   }
-  // level k: the node's median along d, then each member's side
+  // every load of the node has returned before any wavefront of the node
+  // passes its first barrier (the stores come after it)
+  __builtin_amdgcn_s_waitcnt(0);
+  // level k: the node's median along d, then each member's side (ties by
+  // member order: the lower wavefronts' equal members come first)
   uint32_t v, jeq;
-  reg_select<R>(q0, act, s >> 1, bins, &v, &jeq);
-  uint32_t left = 0, erun = 0;
+  reg_select<R, W>(q0, act, s >> 1, bins, red, &v, &jeq);
+  uint32_t eqb = 0;  // bit i: row i's member equals the median
+#pragma unroll
+  for (int i = 0; i < R; ++i) eqb |= q0[i] == v ? (1u << i) : 0u;
+  eqb &= act;
+  uint32_t t1[1] = {wave_sum(__popc(eqb))}, b1[1];
+  fuse_bases<W, 1>(t1, b1, xs);
+  uint32_t left = 0, erun = b1[0];
 #pragma unroll
   for (int i = 0; i < R; ++i) {
-    const bool a = (act >> i) & 1u;
-    const bool lt = q0[i] < v, eq = q0[i] == v;
-    const uint64_t meq = __ballot(a && eq);
-    const uint32_t E = erun + lanes_below(meq);
-    left |= (a && (lt || (eq && E < jeq))) ? (1u << i) : 0u;
+    const bool a = (act >> i) & 1u, eq = (eqb >> i) & 1u;
+    const uint64_t meq = __ballot(eq);
+    left |= (a && (q0[i] < v || (eq && erun + lanes_below(meq) < jeq))) ? (1u << i) : 0u;
     erun += popc64(meq);
   }
   const uint32_t right = act & ~left;
   // level k + 1: each child's median along the next axis
   const uint32_t sL = s >> 1, sR = s - sL, hL = sL >> 1, hR = sR >> 1;
   uint32_t vL, jL, vR, jR;
-  reg_select<R>(q1, left, hL, bins, &vL, &jL);
-  reg_select<R>(q1, right, hR, bins, &vR, &jR);
-  // grandchildren: LL [0, hL), LR [hL, sL), RL [sL, sL + hR), RR [sL + hR, s)
-  uint32_t eL = 0, eR = 0, cLL = 0, cLR = 0, cRL = 0, cRR = 0;
+  reg_select<R, W>(q1, left, hL, bins, red, &vL, &jL);
+  reg_select<R, W>(q1, right, hR, bins, red, &vR, &jR);
+  // each member's grandchild: first (lower) or second half of its child
+  uint32_t eqL = 0, ltL = 0, eqR = 0, ltR = 0;
 #pragma unroll
   for (int i = 0; i < R; ++i) {
-    const bool a = (act >> i) & 1u;
-    const bool L = (left >> i) & 1u, Rt = (right >> i) & 1u;
-    const bool eqL = q1[i] == vL, eqR = q1[i] == vR;
-    const uint64_t bEL = __ballot(L && eqL), bER = __ballot(Rt && eqR);
-    const bool toLL = L && (q1[i] < vL || (eqL && eL + lanes_below(bEL) < jL));
-    const bool toRL = Rt && (q1[i] < vR || (eqR && eR + lanes_below(bER) < jR));
-    const uint64_t bLL = __ballot(toLL), bLR = __ballot(L && !toLL);
-    const uint64_t bRL = __ballot(toRL), bRR = __ballot(Rt && !toRL);
-    const uint32_t dest = toLL ? cLL + lanes_below(bLL)
-                          : L  ? hL + cLR + lanes_below(bLR)
-                          : toRL ? sL + cRL + lanes_below(bRL)
-                                 : sL + hR + cRR + lanes_below(bRR);
-    if (a) {
+    eqL |= q1[i] == vL ? (1u << i) : 0u;
+    ltL |= q1[i] < vL ? (1u << i) : 0u;
+    eqR |= q1[i] == vR ? (1u << i) : 0u;
+    ltR |= q1[i] < vR ? (1u << i) : 0u;
+  }
+  eqL &= left, ltL &= left, eqR &= right, ltR &= right;
+  uint32_t t2[2] = {wave_sum(__popc(eqL)), wave_sum(__popc(eqR))}, b2[2];
+  fuse_bases<W, 2>(t2, b2, xs);
+  uint32_t lo = 0;  // bit i: row i's member goes to its child's first half
+  uint32_t eL = b2[0], eR = b2[1];
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const uint64_t bEL = __ballot((eqL >> i) & 1u), bER = __ballot((eqR >> i) & 1u);
+    const bool toL = ((ltL >> i) & 1u) || (((eqL >> i) & 1u) && eL + lanes_below(bEL) < jL);
+    const bool toR = ((ltR >> i) & 1u) || (((eqR >> i) & 1u) && eR + lanes_below(bER) < jR);
+    lo |= (toL || toR) ? (1u << i) : 0u;
+    eL += popc64(bEL);
+    eR += popc64(bER);
+  }
+  // grandchildren: LL [0, hL), LR [hL, sL), RL [sL, sL + hR), RR [sL + hR, s)
+  const uint32_t mLL = left & lo, mLR = left & ~lo, mRL = right & lo, mRR = right & ~lo;
+  uint32_t t4[4] = {wave_sum(__popc(mLL)), wave_sum(__popc(mLR)), wave_sum(__popc(mRL)),
+                    wave_sum(__popc(mRR))}, b4[4];
+  fuse_bases<W, 4>(t4, b4, xs);
+  uint32_t cLL = b4[0], cLR = hL + b4[1], cRL = sL + b4[2], cRR = sL + hR + b4[3];
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const uint64_t bLL = __ballot((mLL >> i) & 1u), bLR = __ballot((mLR >> i) & 1u);
+    const uint64_t bRL = __ballot((mRL >> i) & 1u), bRR = __ballot((mRR >> i) & 1u);
+    const uint32_t dest = ((mLL >> i) & 1u)   ? cLL + lanes_below(bLL)
+                          : ((mLR >> i) & 1u) ? cLR + lanes_below(bLR)
+                          : ((mRL >> i) & 1u) ? cRL + lanes_below(bRL)
+                                              : cRR + lanes_below(bRR);
+    if ((act >> i) & 1u) {
       if (dest < s) {
         X0[dest] = (KT)q0[i];
         X1[dest] = (KT)q1[i];
@@ -1108,8 +1203,6 @@ __device__ void level_fused_body(uint32_t depth, const SetDesc& S, DevParams* P,
         P->status = BBX_EHIP;  // inconsistent counts: never expected
       }
     }
-    eL += popc64(bEL);
-    eR += popc64(bER);
     cLL += popc64(bLL);
     cLR += popc64(bLR);
     cRL += popc64(bRL);
@@ -1117,28 +1210,33 @@ __device__ void level_fused_body(uint32_t depth, const SetDesc& S, DevParams* P,
   }
 }
 
-// Levels k and k + 1 of the sets whose fused depth is k: one wavefront per
-// node of depth k, four nodes per block.
-template <bool TRACK>
+// Levels k and k + 1 of the sets whose fused depth for W wavefronts per node
+// is k.  W = 1: one wavefront per node of depth k, four nodes per block;
+// W = 4: one block per node.
+template <bool TRACK, int W>
 __global__ void __launch_bounds__(kBlock) k_level_fused(uint32_t depth, uint32_t nsets,
                                                         const uint64_t* pre, const SetDesc* sets,
                                                         DevParams* params, uint8_t* keys0,
                                                         uint32_t* idx0) {
+  static_assert(W == 1 || W == kBlock / 64, "a wavefront or a block per node");
   __shared__ uint32_t bins[kBlock / 64][256];
+  __shared__ uint32_t red[2 * W + 2];
+  __shared__ uint32_t xs[W][4];
   const uint32_t wv = threadIdx.x >> 6;
-  const uint64_t gn = (uint64_t)blockIdx.x * (kBlock / 64) + wv;
-  if (gn >= pre[nsets]) return;  // whole wavefront
+  const uint64_t gn = W == 1 ? (uint64_t)blockIdx.x * (kBlock / 64) + wv : blockIdx.x;
+  if (gn >= pre[nsets]) return;  // whole wavefront (W = 1) or block
   const uint32_t s = find_set(pre, nsets, gn);
   const SetDesc& S = sets[s];
   DevParams* P = params + s;
   if (P->status != BBX_OK) return;
-  if (S.fuse_depth != depth) return;
+  if ((W == 1 ? S.fuse_depth : S.fuse_depth4) != depth) return;
   const uint64_t j = gn - pre[s];
   uint32_t* idx = S.track ? idx0 + S.idx_off : nullptr;
+  uint32_t* b = W == 1 ? bins[wv] : bins[0];
   if (P->key16)
-    level_fused_body<uint16_t, TRACK>(depth, S, P, j, keys0 + S.key_off, idx, bins[wv]);
+    level_fused_body<uint16_t, TRACK, W>(depth, S, P, j, keys0 + S.key_off, idx, b, red, xs);
   else
-    level_fused_body<uint32_t, TRACK>(depth, S, P, j, keys0 + S.key_off, idx, bins[wv]);
+    level_fused_body<uint32_t, TRACK, W>(depth, S, P, j, keys0 + S.key_off, idx, b, red, xs);
 }
 
 // blocks of a select launch: one wavefront per node up to 8192 blocks, then striding
@@ -1162,10 +1260,15 @@ hipError_t launch_levels(const BatchPlan& bp, const Ws& w, hipStream_t s) {
       BBX_LAUNCH("level_wave", bp.track ? k_level_wave<true> : k_level_wave<false>,
                  (bp.g_nd[k] + kBlock / 64 - 1) / (kBlock / 64), kBlock, 0, s, k, bp.nsets, pnd,
                  w.sets, w.params, w.keys[cur], w.keys[cur ^ 1], w.idx[cur], w.idx[cur ^ 1]);
-    if (bp.lv_fused[k])  // levels k and k + 1 in place: depth k + 2 keeps buffer `cur`
-      BBX_LAUNCH("level_fused", bp.track ? k_level_fused<true> : k_level_fused<false>,
+    // levels k and k + 1 in place: depth k + 2 keeps buffer `cur`
+    if (bp.lv_fused[k])
+      BBX_LAUNCH("level_fused", (bp.track ? k_level_fused<true, 1> : k_level_fused<false, 1>),
                  (bp.g_nd[k] + kBlock / 64 - 1) / (kBlock / 64), kBlock, 0, s, k, bp.nsets, pnd,
                  w.sets, w.params, w.keys[cur], w.idx[cur]);
+    if (bp.lv_fused4[k])
+      BBX_LAUNCH("level_fused4", (bp.track ? k_level_fused<true, 4> : k_level_fused<false, 4>),
+                 bp.g_nd[k], kBlock, 0, s, k, bp.nsets, pnd, w.sets, w.params, w.keys[cur],
+                 w.idx[cur]);
     if (!bp.lv_global[k]) continue;
     // mid passes: pass 0 was built by the quantize pass (depth 0) or by the
     // previous scatter
