@@ -237,7 +237,7 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
       pm[s] = std::max<uint64_t>(1, std::min<uint64_t>((mw + kBlock - 1) / kBlock, 1024));
       const uint64_t lpb = leaves_per_block(D.r);
       pp[s] = (D.n_leaves + lpb - 1) / lpb;
-      uint64_t max_nodes = 0, max_blocks = 0;
+      uint64_t max_nodes = 0, max_blocks = 0, bin_nodes = 0;
       for (uint32_t k = 0; k < D.gl; ++k) {
         const LevelShape sh = level_shape(n, k, D.level_blocks);
         const int kind = level_kind(n, k);
@@ -253,16 +253,18 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
           bp->lv_global[k] = 1;
         lv[s].push_back(sh.nodes * sh.chunks);
         nd[s].push_back(sh.nodes);
-        if (kind == kLevelGlobal) {  // only these use histogram bins, selections and rows
+        if (kind == kLevelGlobal) {  // only these use selections and rows
           max_nodes = std::max(max_nodes, sh.nodes);
           max_blocks = std::max(max_blocks, sh.nodes * sh.chunks);
         }
+        if (kind != kLevelWave) bin_nodes = std::max(bin_nodes, sh.nodes);  // radix bins
       }
       bp->max_gl = std::max(bp->max_gl, D.gl);
       D.mm_blocks = (uint32_t)mm[s];
       D.key_off = key_bytes;
       D.idx_off = idx_n;
       D.hist_off = hist_n;
+      D.hist_half = bin_nodes * kHistBins;
       D.sel_off = sel_n;
       D.rows_off = rows_n * kRowStride;
       D.cb_off = rows_n * 2;
@@ -271,7 +273,7 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
       D.kst = (n + 63) & ~63ull;
       key_bytes += align_up((uint64_t)D.dims * D.kst * 4);
       if (I.need_idx || D.track) idx_n += (n + 63) & ~63ull;
-      hist_n += max_nodes * kHistBins;
+      hist_n += 2 * bin_nodes * kHistBins;
       sel_n += max_nodes;
       rows_n += max_blocks;
       leaves_n += D.n_leaves;

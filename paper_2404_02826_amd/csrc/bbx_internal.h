@@ -93,6 +93,7 @@ struct SetDesc {
   uint64_t key_off;       // byte offset into each key buffer (capacity dims*n*4)
   uint64_t idx_off;       // u32 offset into each index buffer
   uint64_t hist_off;      // u32 offset into the histogram bins
+  uint64_t hist_half;     // u32 entries of each of the set's two bin regions
   uint64_t sel_off;       // NodeSel offset
   uint64_t rows_off;      // u32 offset into the chunk rows
   uint64_t cb_off;        // u32 offset into the chunk bases
@@ -254,6 +255,14 @@ __host__ __device__ inline int level_kind(uint64_t n, uint32_t depth) {
 }
 __host__ __device__ inline bool level_is_local(uint64_t n, uint32_t depth) {
   return level_kind(n, depth) != kLevelGlobal;
+}
+
+// Radix bins of a level's nodes (256 per node): global levels use the set's
+// first region; a block-local level of depth k uses region k & 1, since its
+// kernel reads its own nodes' first-digit bins while it builds those of the
+// next level's nodes.
+__device__ inline uint32_t* hist_level(const SetDesc& S, uint32_t depth, uint32_t* hist) {
+  return level_kind(S.n, depth) == kLevelBlock ? hist + (depth & 1) * S.hist_half : hist;
 }
 
 // The last levels above the tile stage of a set with a tile stage run in

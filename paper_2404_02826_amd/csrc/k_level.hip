@@ -20,6 +20,11 @@
 //   k_scatter      stable partition of the codes (and source indices); also
 //                  builds the next level's first-digit histogram, so that
 //                  level needs no separate pass over its codes for it
+//   k_level_local  a level whose nodes each fit one block: median and
+//                  partition per block, no global histograms
+//   k_level_wave   a level of nodes of <= 4096 members: one wavefront each
+//   k_level_fused  two levels in one in-place pass with the node in
+//                  registers (the last four levels above the tile stage)
 //
 // Streaming kernels keep 8 loads in flight per thread (rows of 256 elements,
 // 8 rows per group) and synchronize once per 2048 elements.
@@ -592,7 +597,9 @@ __device__ void scatter_body(uint32_t depth, const SetDesc& S, DevParams* P, con
   const uint32_t half = sz >> 1;
   const uint32_t dn = (depth + 1) % dims;
   const DigitPlan pn = digit_plan(P->G[dn]);
-  const bool fuse = depth + 1 < S.gl && pn.npass >= 2 && !level_is_local(n, depth + 1);
+  // (not for wavefront levels, whose medians work on registers or on codes
+  // minus the node minimum)
+  const bool fuse = depth + 1 < S.gl && pn.npass >= 2 && level_kind(n, depth + 1) != kLevelWave;
   const uint32_t wn = pn.width[0], shn = pn.shift[0], maskn = (1u << wn) - 1;
   const bool cl = fuse && half > r, cr = fuse && (sz - half) > r;  // children that split again
   if (fuse) lhist[threadIdx.x] = lhist[kBlock + threadIdx.x] = 0;
@@ -614,7 +621,7 @@ __device__ void scatter_body(uint32_t depth, const SetDesc& S, DevParams* P, con
     __syncthreads();
     for (uint32_t child = 0; child < 2; ++child) {
       const uint32_t cnum = lhist[child * kBlock + threadIdx.x];
-      if (cnum) atomicAdd(&hist[((2 * j + child) << 8) + threadIdx.x], cnum);
+      if (cnum) atomicAdd(&hist_level(S, depth + 1, hist)[((2 * j + child) << 8) + threadIdx.x], cnum);
     }
   }
 }
@@ -645,44 +652,56 @@ __global__ void __launch_bounds__(kBlock) k_scatter(uint32_t depth, uint32_t nse
                            dst0 + S.key_off, isrc, idst, hist0 + S.hist_off, lhist);
 }
 
-// Median of one node's axis codes, inside one block: the node's code range,
-// then radix passes of at most 8 bits over the codes minus the minimum (the
-// re-reads of a node of at most a few tens of KB hit the cache).  Returns the
-// median code v and how many members equal to v precede it (they go left).
+// Median of one node's axis codes, inside one block: radix passes of at most
+// 8 bits, either over the code's own digits with the first digit's bins
+// already counted by the partition above (`hist`), or over the codes minus
+// the node minimum after a pass for the node's code range (the re-reads of a
+// node of at most a few hundred KB mostly hit the cache).  Returns the median
+// code v and how many members equal to v precede it (they go left).
 template <typename KT>
 __device__ void local_median(const KT* axis, uint64_t A, uint64_t B, uint32_t rank, uint32_t* v_out,
-                             uint32_t* jeq_out, uint32_t* bins, uint32_t* red) {
+                             uint32_t* jeq_out, uint32_t* bins, uint32_t* red, uint32_t* hist,
+                             const DigitPlan& pl) {
   const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  uint32_t lo = 0xffffffffu, hi = 0;
-  scan_codes(axis, A, B, [&](uint32_t q) {
-    lo = q < lo ? q : lo;
-    hi = q > hi ? q : hi;
-  });
-  for (int o = 32; o > 0; o >>= 1) {
-    const uint32_t a = __shfl_xor(lo, o), b = __shfl_xor(hi, o);
-    lo = a < lo ? a : lo;
-    hi = b > hi ? b : hi;
+  // with `hist` the digits are those of the code itself (the set's digit
+  // plan) and the first one's bins are already counted there; else they are
+  // digits of the code minus the node minimum, widest first
+  uint32_t mn = 0, Gs = pl.shift[0] + pl.width[0];
+  if (!hist) {
+    uint32_t lo = 0xffffffffu, hi = 0;
+    scan_codes(axis, A, B, [&](uint32_t q) {
+      lo = q < lo ? q : lo;
+      hi = q > hi ? q : hi;
+    });
+    for (int o = 32; o > 0; o >>= 1) {
+      const uint32_t a = __shfl_xor(lo, o), b = __shfl_xor(hi, o);
+      lo = a < lo ? a : lo;
+      hi = b > hi ? b : hi;
+    }
+    if (lane == 0) red[wv] = lo, red[4 + wv] = hi;
+    __syncthreads();
+    mn = red[0] < red[1] ? (red[0] < red[2] ? (red[0] < red[3] ? red[0] : red[3])
+                                            : (red[2] < red[3] ? red[2] : red[3]))
+                         : (red[1] < red[2] ? (red[1] < red[3] ? red[1] : red[3])
+                                            : (red[2] < red[3] ? red[2] : red[3]));
+    uint32_t mx = red[4];
+    for (int k = 5; k < 8; ++k) mx = red[k] > mx ? red[k] : mx;
+    Gs = bitlen32(mx - mn);
   }
-  if (lane == 0) red[wv] = lo, red[4 + wv] = hi;
-  __syncthreads();
-  const uint32_t mn = red[0] < red[1] ? (red[0] < red[2] ? (red[0] < red[3] ? red[0] : red[3])
-                                                          : (red[2] < red[3] ? red[2] : red[3]))
-                                      : (red[1] < red[2] ? (red[1] < red[3] ? red[1] : red[3])
-                                                          : (red[2] < red[3] ? red[2] : red[3]));
-  uint32_t mx = red[4];
-  for (int k = 5; k < 8; ++k) mx = red[k] > mx ? red[k] : mx;
-  const uint32_t Gs = bitlen32(mx - mn);
-  uint32_t prefix = 0;
-  if (Gs > 0) {
-    // widest digit first: the first pass sees every member, so it spreads
-    // them over up to 256 bins; later passes see only the members that
-    // match the prefix found so far
-    uint32_t used = 0;
-    while (used < Gs) {
-      const uint32_t w = Gs - used < 8 ? Gs - used : 8;
-      const uint32_t hs = Gs - used;
-      used += w;
-      const uint32_t sh = Gs - used, mask = (1u << w) - 1;
+  uint32_t prefix = 0, used = 0;
+  // the first pass sees every member, so it spreads them over up to 256
+  // bins; later passes see only the members that match the prefix found so
+  // far
+  for (uint32_t pass = 0; used < Gs; ++pass) {
+    const uint32_t w = hist ? dp_width(pl, pass) : (Gs - used < 8 ? Gs - used : 8);
+    const uint32_t hs = Gs - used;
+    used += w;
+    const uint32_t sh = Gs - used, mask = (1u << w) - 1;
+    if (hist && pass == 0) {
+      bins[threadIdx.x] = hist[threadIdx.x];
+      hist[threadIdx.x] = 0;  // zero again for the next use of these bins
+      __syncthreads();
+    } else {
       bins[threadIdx.x] = 0;
       __syncthreads();
       scan_codes(axis, A, B, [&](uint32_t q) {
@@ -690,22 +709,22 @@ __device__ void local_median(const KT* axis, uint64_t A, uint64_t B, uint32_t ra
         if ((k >> hs) == prefix) atomicAdd(&bins[(k >> sh) & mask], 1u);
       });
       __syncthreads();
-      if (wv == 0) {  // one wavefront finds the bin holding the rank
-        uint32_t c[4], mine = 0;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) c[k] = bins[lane * 4 + k], mine += c[k];
-        uint32_t cum = wave_incl(mine) - mine;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          if (cum <= rank && rank < cum + c[k]) red[8] = lane * 4 + k, red[9] = rank - cum;
-          cum += c[k];
-        }
-      }
-      __syncthreads();
-      prefix = (prefix << w) | red[8];
-      rank = red[9];
-      __syncthreads();  // red and bins are rewritten by the next pass
     }
+    if (wv == 0) {  // one wavefront finds the bin holding the rank
+      uint32_t c[4], mine = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) c[k] = bins[lane * 4 + k], mine += c[k];
+      uint32_t cum = wave_incl(mine) - mine;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (cum <= rank && rank < cum + c[k]) red[8] = lane * 4 + k, red[9] = rank - cum;
+        cum += c[k];
+      }
+    }
+    __syncthreads();
+    prefix = (prefix << w) | red[8];
+    rank = red[9];
+    __syncthreads();  // red and bins are rewritten by the next pass
   }
   *v_out = mn + prefix;
   *jeq_out = rank;
@@ -733,12 +752,17 @@ __global__ void __launch_bounds__(kBlock) k_level_local(uint32_t depth, uint32_t
   const uint32_t d = depth % S.dims;
   const uint8_t* keys = src0 + S.key_off;
   if (sz > S.r) {
+    const DigitPlan pl = digit_plan(P->G[d]);
+    // the level above built this node's first-digit histogram when the code
+    // has more than one digit (depth 0 has none for a block-local level)
+    uint32_t* h = depth > 0 && pl.npass >= 2
+                      ? hist_level(S, depth, hist0 + S.hist_off) + (c.lb << 8) : nullptr;
     if (P->key16)
       local_median((const uint16_t*)keys + (uint64_t)d * S.kst, st, st + sz, (uint32_t)(sz >> 1), &v,
-                   &jeq, lhist, red);
+                   &jeq, lhist, red, h, pl);
     else
       local_median((const uint32_t*)keys + (uint64_t)d * S.kst, st, st + sz, (uint32_t)(sz >> 1), &v,
-                   &jeq, lhist, red);
+                   &jeq, lhist, red, h, pl);
     __syncthreads();  // lhist is reused by the partition
   }
   if (P->key16)
@@ -749,9 +773,6 @@ __global__ void __launch_bounds__(kBlock) k_level_local(uint32_t depth, uint32_t
                            idst, hist0 + S.hist_off, lhist);
 }
 
-// Median of a node's axis codes by one wavefront (nodes of at most kWaveNode
-// members): code range by DPP reductions, then radix passes of at most 8 bits
-// (widest first) over codes minus the minimum, in the wavefront's own bins.
 // Median of a node's axis codes by one wavefront (nodes of at most kWaveNode
 // members): code range by DPP reductions, then radix passes of at most 8 bits
 // (widest first) over codes minus the minimum, in the wavefront's own bins.

@@ -10,7 +10,11 @@ properties that hold at any size and on outputs the oracle computes:
 * on 4096 sampled leaves, recomputed from the source points with the header's
   quantization: the stored reference code is the member nearest the AABB
   centre (first in index order on ties), members follow in ascending index,
-  and every stored width is Eq. 2's minimal width.
+  and every stored width is Eq. 2's minimal width;
+* with the reference stored as its original coordinates (ref_mode 1): every
+  leaf's first decoded slot is its reference's input coordinate bit for bit,
+  every other slot decodes exactly as in the code-reference stream, and the
+  meta section grows by exactly n_leaves * sum_d (32 - G_d) bits.
 """
 from __future__ import annotations
 
@@ -98,3 +102,35 @@ def test_fluid_2p27_full_size():
             D = int(max(qref[d] - qmin[d], qmax[d] - qref[d]))
             assert m[d] == _width(D), f"leaf {i} axis {d}: width {m[d]} != {_width(D)}"
     _say("full-size checks passed")
+
+
+def test_fluid_2p27_lossless_reference():
+    import paper_2404_02826_amd as bbx
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    _say("generating the fluid 2^27 workload (lossless references)")
+    pts = fluid(*fluid_lattice_dims(N), seed=4)
+    x = torch.from_numpy(pts).cuda()
+    del pts
+    s1, p1 = bbx.compress(x, 1e-4, "rel", 32, want_perm=True, ref_mode=1)
+    s0, p0 = bbx.compress(x, 1e-4, "rel", 32, want_perm=True)
+    assert torch.equal(p0, p1), "the tree depends on the reference storage"
+    del p0
+    d1, d0 = bbx.decompress(s1), bbx.decompress(s0)
+    torch.cuda.synchronize()
+    h1 = props.parse_header(s1[:128].cpu().numpy().tobytes())
+    h0 = props.parse_header(s0[:128].cpu().numpy().tobytes())
+    assert h1["ref_mode"] == 1 and h0["ref_mode"] == 0
+    assert h1["payload_bits"] == h0["payload_bits"]
+    assert h1["meta_bits"] - h0["meta_bits"] == h0["n_leaves"] * sum(32 - g for g in h0["G"])
+    assert s1.numel() == props.stream_size(h1["meta_bits"], h1["payload_bits"])
+    sizes = props.leaf_sizes_fast(N, 32)
+    first = torch.zeros(N, dtype=torch.bool, device="cuda")
+    first[torch.from_numpy((np.cumsum(sizes) - sizes).astype(np.int64)).cuda()] = True
+    src = x[p1.long()]
+    assert torch.equal(d1[first].view(torch.int32), src[first].view(torch.int32)), \
+        "a reference does not decode to its input coordinate"
+    assert torch.equal(d1[~first].view(torch.int32), d0[~first].view(torch.int32)), \
+        "members decode differently from the code-reference stream"
+    err = (d1.double() - src.double()).abs().max().item()
+    assert err <= h1["eb_abs"], f"bound violated: {err} > {h1['eb_abs']}"
+    _say("lossless-reference full-size checks passed")

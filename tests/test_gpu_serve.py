@@ -2,7 +2,8 @@
 while others run, are admitted under a small device-memory budget, run in
 shared launches on several streams, and each result equals the result of
 the same call made alone (stream bytes, and decompressed positions bit for
-bit), and the oracle's stream for sampled jobs."""
+bit), and the oracle's stream for sampled jobs; a quarter of the jobs store
+their references as original coordinates (ref_mode 1)."""
 from __future__ import annotations
 
 import sys
@@ -39,7 +40,7 @@ def _jobs(nj, seed):
         gen = uniform_cube if i % 2 == 0 else cosmology
         pts = gen(int(sizes[i]), seed=100 + i)
         out.append(dict(pts=pts, kind="compress" if rng.random() < 0.5 else "decompress",
-                        eb=1e-4 if i % 3 else 1e-3))
+                        eb=1e-4 if i % 3 else 1e-3, ref_mode=1 if i % 4 == 3 else 0))
     return out
 
 
@@ -47,13 +48,13 @@ def test_served_results_equal_alone(bbx):
     jobs = _jobs(48, seed=11)
     for j in jobs:
         j["x"] = torch.from_numpy(j["pts"]).cuda()
-        j["alone_stream"] = bbx.compress(j["x"], j["eb"], "rel", 32)
+        j["alone_stream"] = bbx.compress(j["x"], j["eb"], "rel", 32, ref_mode=j["ref_mode"])
         if j["kind"] == "decompress":
             j["header"] = j["alone_stream"][:128].cpu().numpy().tobytes()
             j["alone_pos"] = bbx.decompress(j["alone_stream"])
     torch.cuda.synchronize()
-    need = max(bbx.compress_bound(len(j["pts"])) + bbx.compress_workspace_size(len(j["pts"]))
-               for j in jobs)
+    need = max(bbx.compress_bound(len(j["pts"]), ref_mode=1) +
+               bbx.compress_workspace_size(len(j["pts"]), ref_mode=1) for j in jobs)
     budget = (3 * need + (1 << 20)) // 256 * 256  # forces admission to wait for memory
     srv = bbx.Server(budget, max_jobs=64, max_batch=8, nstreams=3)
     _say(f"served: {len(jobs)} jobs, budget {budget} bytes")
@@ -65,7 +66,8 @@ def test_served_results_equal_alone(bbx):
         now = time.perf_counter() - t0
         while k < len(jobs) and now >= t_next:
             j = jobs[k]
-            jid = (srv.submit_compress(j["x"], j["eb"], "rel", 32) if j["kind"] == "compress"
+            jid = (srv.submit_compress(j["x"], j["eb"], "rel", 32, ref_mode=j["ref_mode"])
+                   if j["kind"] == "compress"
                    else srv.submit_decompress(j["alone_stream"], j["header"]))
             ids[jid] = k
             t_next += gaps[k]
@@ -96,7 +98,7 @@ def test_served_results_equal_alone(bbx):
     for jid, d in list(done.items())[:6]:
         j = jobs[ids[jid]]
         if j["kind"] == "compress":
-            ref = orc.compress(j["pts"], j["eb"], "rel", 32)
+            ref = orc.compress(j["pts"], j["eb"], "rel", 32, ref_mode=j["ref_mode"])
             assert srv.result(jid).cpu().numpy().tobytes() == ref
     for jid in done:
         srv.release(jid)
