@@ -822,3 +822,68 @@ int bbxo_decompress(const uint8_t* s, uint64_t size, void* pos, uint64_t pos_cap
   free(rraw);
   return st;
 }
+
+/* ------------------------------------------------------------------ sequence export */
+
+/* The sequence layout of Sec. 4.2 (figure fig:sequences), written from a
+ * stream whose references are stored as their original coordinates
+ * (ref_mode 1).  One sequence per leaf, in stored order: the centre (the
+ * reference's coordinates, M bits per axis), the widths m_d (mbits each),
+ * the codes of the other members (per member, per axis, m_d bits: the
+ * leaf's payload segment) and a 32-bit end mark (all ones).  Bit i is bit
+ * i mod 8 of byte i/8; the whole is zero-padded to 8 bytes.  Its length in
+ * bits is the storage-cost model of Sec. 4.2 with one sequence per leaf. */
+#define END_MARK 0xffffffffu
+
+int bbxo_export_sequences(const uint8_t* s, uint64_t size, uint8_t* out, uint64_t out_cap,
+                          uint64_t* out_size) {
+  if (!s || size < HEADER_BYTES) return BBXO_ECORRUPT;
+  if (get_u32le(s) != MAGIC || get_u16le(s + 4) != 1) return BBXO_ECORRUPT;
+  int dtype = s[6];
+  uint32_t dims = s[7], r = get_u32le(s + 16), mbits = s[23];
+  uint64_t n = get_u64le(s + 8);
+  if (dtype > 1 || (dims != 2 && dims != 3) || s[22] > 1 || r == 0) return BBXO_ECORRUPT;
+  if (s[22] != 1) return BBXO_EINVAL; /* the centre must be stored losslessly */
+  uint32_t M = coord_bits(dtype);
+  uint64_t nl = get_u64le(s + 96), meta_bits = get_u64le(s + 104), payload_bits = get_u64le(s + 112);
+  if (nl != bbxo_leaf_count(n, r) || meta_bits != nl * (uint64_t)(dims * (mbits + M)))
+    return BBXO_ECORRUPT;
+  uint64_t mb = words_bytes(meta_bits), pb = words_bytes(payload_bits);
+  if (size < HEADER_BYTES + mb + pb) return BBXO_ECORRUPT;
+  uint64_t total = nl * (uint64_t)(dims * (M + mbits) + 32) + payload_bits;
+  if (out_size) *out_size = words_bytes(total);
+  if (words_bytes(total) > out_cap) return BBXO_ENOSPC;
+  if (total) memset(out, 0, (size_t)words_bytes(total));
+  if (n == 0) return BBXO_OK;
+  uint32_t* sizes = (uint32_t*)malloc((size_t)nl * sizeof(uint32_t));
+  if (!sizes) return BBXO_ENOMEM;
+  uint64_t k = 0;
+  size_leaves(n, r, sizes, &k, nl);
+  const uint8_t* meta = s + HEADER_BYTES;
+  const uint8_t* pay = meta + mb;
+  uint64_t mpos = 0, ppos = 0, opos = 0;
+  int st = BBXO_OK;
+  for (uint64_t i = 0; i < nl; i++) {
+    uint32_t m[3] = {0, 0, 0}, sm = 0;
+    for (uint32_t d = 0; d < dims; d++) m[d] = (uint32_t)get_bits(meta, mpos + d * mbits, mbits), sm += m[d];
+    for (uint32_t d = 0; d < dims; d++) /* centre first */
+      put_bits(out, opos, get_bits(meta, mpos + dims * mbits + d * M, M), M), opos += M;
+    for (uint32_t d = 0; d < dims; d++) put_bits(out, opos, m[d], mbits), opos += mbits;
+    mpos += dims * (mbits + M);
+    uint64_t len = (uint64_t)(sizes[i] - 1) * sm;
+    if (ppos + len > payload_bits) {
+      st = BBXO_ECORRUPT;
+      break;
+    }
+    for (uint64_t b = 0; b < len; b += 64) {
+      uint32_t c = len - b < 64 ? (uint32_t)(len - b) : 64u;
+      put_bits(out, opos + b, get_bits(pay, ppos + b, c), c);
+    }
+    ppos += len;
+    opos += len;
+    put_bits(out, opos, END_MARK, 32), opos += 32;
+  }
+  if (st == BBXO_OK && (ppos != payload_bits || opos != total)) st = BBXO_ECORRUPT;
+  free(sizes);
+  return st;
+}

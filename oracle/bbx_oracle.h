@@ -83,6 +83,13 @@ int bbxo_stages_ex(const void* pos, uint64_t n, uint32_t dims, int dtype, int la
                    uint32_t* leaf_start, uint32_t* leaf_size, uint32_t* leaf_ref,
                    uint8_t* leaf_m, uint64_t* leaf_bits, double* scal);
 
+/* The sequence layout of Sec. 4.2 (one sequence per leaf: centre as M-bit
+ * coordinates, widths, member codes, 32-bit end mark of all ones) from a
+ * stream with ref_mode 1 (BBXO_EINVAL for ref_mode 0).  *out_size receives
+ * the layout's length in bytes (zero-padded to 8). */
+int bbxo_export_sequences(const uint8_t* stream, uint64_t size, uint8_t* out, uint64_t out_cap,
+                          uint64_t* out_size);
+
 /* Number of leaves of the size-only recursion for n particles, capacity r. */
 uint64_t bbxo_leaf_count(uint64_t n, uint32_t r);
 

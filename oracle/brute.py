@@ -241,3 +241,47 @@ def decompress(stream: bytes) -> np.ndarray:
             slot += 1
     assert ppos == pay_bits
     return out
+
+
+def export_sequences(stream: bytes) -> bytes:
+    """Sec. 4.2 sequence layout of a ref_mode 1 stream, rebuilt with big
+    integers: per leaf the centre's coordinate bits, the widths, the member
+    codes and a 32-bit end mark of all ones."""
+    (magic, ver, dt, dims, n, r, _mode, _s, ref_mode, mbits, _eu, _ea, _ee, _w, _iw, _o0, _o1, _o2,
+     _g0, _g1, _g2, nl, meta_bits, pay_bits, _res) = struct.unpack("<4sHBBQIBBBBddddd3d3B5xQQQQ",
+                                                                    stream[:128])
+    assert magic == b"BBX1" and ver == 1 and ref_mode == 1
+    M = 32 if dt == 0 else 64
+    mbytes = 8 * ((meta_bits + 63) // 64)
+    meta = int.from_bytes(stream[128:128 + mbytes], "little")
+    pay = int.from_bytes(stream[128 + mbytes:], "little")
+    sizes = []
+
+    def rec(s):
+        if s <= r:
+            sizes.append(s)
+        else:
+            rec(s // 2)
+            rec(s - s // 2)
+
+    if n:
+        rec(n)
+    out, opos, mpos, ppos = 0, 0, 0, 0
+    for s in sizes:
+        m = [(meta >> (mpos + mbits * d)) & ((1 << mbits) - 1) for d in range(dims)]
+        centre = [(meta >> (mpos + mbits * dims + M * d)) & ((1 << M) - 1) for d in range(dims)]
+        mpos += dims * (mbits + M)
+        for c in centre:
+            out |= c << opos
+            opos += M
+        for w in m:
+            out |= w << opos
+            opos += mbits
+        length = (s - 1) * sum(m)
+        out |= ((pay >> ppos) & ((1 << length) - 1)) << opos
+        ppos += length
+        opos += length
+        out |= 0xFFFFFFFF << opos
+        opos += 32
+    assert ppos == pay_bits
+    return out.to_bytes(8 * ((opos + 63) // 64), "little")

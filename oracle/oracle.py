@@ -59,6 +59,8 @@ class Oracle:
         lib.bbxo_stages_ex.restype = i32
         lib.bbxo_stages_ex.argtypes = [vp, u64, u32, i32, i32, dbl, i32, u32, i32, vp, vp, u64,
                                        vp, vp, vp, vp, vp, vp]
+        lib.bbxo_export_sequences.restype = i32
+        lib.bbxo_export_sequences.argtypes = [vp, u64, vp, u64, C.POINTER(u64)]
         lib.bbxo_leaf_count.restype = u64
         lib.bbxo_leaf_count.argtypes = [u64, u32]
         lib.bbxo_bits_for_offset.restype = u32
@@ -126,6 +128,20 @@ class Oracle:
         if st:
             raise OracleError(st)
         return out
+
+    def export_sequences(self, stream: bytes) -> bytes:
+        """The Sec. 4.2 sequence layout of a ref_mode 1 stream."""
+        buf = np.frombuffer(stream, dtype=np.uint8) if len(stream) else np.zeros(1, np.uint8)
+        size = C.c_uint64(0)
+        st = self.lib.bbxo_export_sequences(buf.ctypes.data, len(stream), None, 0, C.byref(size))
+        if st not in (0, 2):  # ENOSPC: the size query
+            raise OracleError(st)
+        out = np.zeros(max(size.value, 8), dtype=np.uint8)
+        st = self.lib.bbxo_export_sequences(buf.ctypes.data, len(stream), out.ctypes.data,
+                                            out.nbytes, C.byref(size))
+        if st:
+            raise OracleError(st)
+        return out[: size.value].tobytes()
 
     def stages(self, pos: np.ndarray, eb: float, eb_mode: str = "rel", r: int = 32,
                layout: str = "aos", ref_rule: int = 0) -> dict:

@@ -426,3 +426,30 @@ def test_lossless_reference_corrupt(oracle):
     b = bytearray(good)
     b[22] = 2
     _expect("ECORRUPT", oracle.decompress, bytes(b))
+
+
+def test_sequence_export_matches_brute_force_and_storage_model(oracle):
+    """The Sec. 4.2 sequence layout exported from a ref_mode 1 stream equals an
+    independent big-integer rebuild, and its length is the paper's
+    storage-cost model with one sequence per leaf: dims * M bits of centre,
+    dims * mbits of widths, sum_d m_d * (particles - 1) bits of codes and 32
+    bits of end mark per sequence (computed from the oracle's stage dump,
+    not from the stream)."""
+    for pts, eb, mode, r in pins.tiny_cases(seed=301, count=40):
+        n, dims = pts.shape
+        s = oracle.compress(pts, eb, mode, r, ref_mode=1)
+        e = oracle.export_sequences(s)
+        assert e == brute.export_sequences(s), (pts.shape, r)
+        st = oracle.stages(pts, eb, mode, r)
+        M, mbits = (32, 5) if pts.dtype == np.float32 else (64, 6)
+        nseq = st["n_leaves"]
+        bits = (dims * M * nseq + dims * mbits * nseq
+                + int((st["leaf_m"].astype(np.int64).sum(axis=1) * (st["leaf_size"].astype(np.int64) - 1)).sum())
+                + 32 * nseq)
+        assert len(e) == 8 * ((bits + 63) // 64)
+        tail = int.from_bytes(e, "little") >> bits
+        assert tail == 0
+    pts = cosmology(20000, seed=37)
+    s = oracle.compress(pts, 1e-4, "rel", 32, ref_mode=1)
+    assert oracle.export_sequences(s) == brute.export_sequences(s)
+    _expect("EINVAL", oracle.export_sequences, oracle.compress(pts, 1e-4, "rel", 32))
