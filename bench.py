@@ -623,6 +623,24 @@ def main():
     kernels = {k: {"launches": c, "ms_per_step": round(ms / args.steps, 4)}
                for k, (c, ms) in sorted(prof.items(), key=lambda kv: -kv[1][1])}
 
+    # ---- the Sec. 4.2 sequence layout of a lossless-reference stream
+    export = None
+    if args.ref_mode == 1:
+        exp = bbx.SequenceExporter(header)
+        for _ in range(args.warmup):
+            exp.launch(stream_buf[:S])
+        ee = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+        for e0, e1 in ee:
+            e0.record(st)
+            exp.launch(stream_buf[:S])
+            e1.record(st)
+        torch.cuda.synchronize()
+        te = sorted(a.elapsed_time(b) for a, b in ee)[len(ee) // 2]
+        export = {"bytes": exp.size, "cr": round(B_in / exp.size, 4), "ms": round(te, 4),
+                  "gbps_of_input": round(B_in / (te * 1e-3) / 1e9, 2)}
+        del exp
+
     # ---- error bound on the measured output (sampled slots)
     perm_check = None
     try:
@@ -671,6 +689,7 @@ def main():
                    "stream_bytes": S, "cr": round(B_in / S, 4),
                    "cr_other_ref_rule": round(B_in / S_alt, 4),
                    "cr_other_ref_mode": round(B_in / S_alt_mode, 4),
+                   "sequence_export": export,
                    "bpp": round(8 * S / n, 4),
                    "compress_gbps": round(B_in / (mc * 1e-3) / 1e9, 2),
                    "decompress_gbps": round(B_in / (md * 1e-3) / 1e9, 2),

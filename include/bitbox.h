@@ -200,6 +200,30 @@ bbx_status bbx_decompress(const void* d_stream, size_t stream_size, const void* 
                           void* d_pos, size_t pos_cap, bbx_layout layout, uint32_t* d_status,
                           void* d_ws, size_t ws_size, hipStream_t stream);
 
+/*
+ * The sequence layout of Sec. 4.2 (figure "data layout of sequences"), for
+ * tools that read the paper's format.  From a stream whose references are
+ * stored as original coordinates (ref_mode 1; BBX_EINVAL otherwise), one
+ * sequence per leaf in stored order: the centre (the reference's
+ * coordinates, 32 or 64 bits per axis), the widths m_d (mbits each), the
+ * codes of the other members (per member, per axis, m_d bits, as in the
+ * stream's payload) and a 32-bit end mark of all ones.  Bit i is bit
+ * (i mod 64) of little-endian u64 word i/64; the whole is zero-padded to 8
+ * bytes, and its length in bits is the paper's storage-cost model with one
+ * sequence per leaf.  There is no header: n, r, the bound and the origin
+ * stay in the stream's header.
+ *   bbx_export_sequences_size  the layout's bytes (0 for an invalid header
+ *                              or ref_mode 0)
+ *   d_out      device, out_cap bytes, 8-byte aligned
+ *   d_ws       the decompression workspace (bbx_decompress_workspace_size)
+ *   d_status   as for bbx_decompress (NULL: the call waits and returns the
+ *              device's verdict on the stream)
+ */
+size_t bbx_export_sequences_size(const void* h_header, size_t header_bytes);
+bbx_status bbx_export_sequences(const void* d_stream, size_t stream_size, const void* h_header,
+                                void* d_out, size_t out_cap, uint32_t* d_status, void* d_ws,
+                                size_t ws_size, hipStream_t stream);
+
 /* Short name of a status value, and the calling thread's last error message. */
 const char* bbx_status_str(bbx_status status);
 const char* bbx_last_error(void);

@@ -16,12 +16,14 @@ from ._binding import (  # noqa: F401
     Compressor,
     Decompressor,
     STATUS,
+    SequenceExporter,
     Server,
     compress,
     compress_bound,
     compress_workspace_size,
     decompress,
     decompress_workspace_size,
+    export_sequences,
     lib_path,
     load,
     profile,

@@ -117,6 +117,10 @@ def load():
     lib.bbx_decompress_workspace_size.argtypes = [vp, sz]
     lib.bbx_decompress.restype = i32
     lib.bbx_decompress.argtypes = [vp, sz, vp, vp, sz, i32, vp, vp, sz, vp]
+    lib.bbx_export_sequences_size.restype = sz
+    lib.bbx_export_sequences_size.argtypes = [vp, sz]
+    lib.bbx_export_sequences.restype = i32
+    lib.bbx_export_sequences.argtypes = [vp, sz, vp, vp, sz, vp, vp, sz, vp]
     lib.bbx_status_str.restype = C.c_char_p
     lib.bbx_status_str.argtypes = [i32]
     lib.bbx_last_error.restype = C.c_char_p
@@ -532,6 +536,46 @@ def decompress(stream_t: torch.Tensor, layout: str = "aos", stream=None) -> torc
     header = stream_t[:128].cpu().numpy().tobytes()
     d = Decompressor(header, layout, stream_t.device)
     return d(stream_t, stream).clone()
+
+
+class SequenceExporter:
+    """Reusable export of ref_mode 1 streams of one header's geometry to the
+    Sec. 4.2 sequence layout: owns the workspace and the output buffer.
+    ``__call__`` waits and returns the layout as a uint8 view of the output
+    buffer (valid until the next call); ``launch`` only enqueues."""
+
+    def __init__(self, header: bytes, device="cuda"):
+        lib = load()
+        self._lib = lib
+        self.header = bytes(header[:128])
+        self.size = int(lib.bbx_export_sequences_size(self.header, 128))
+        if self.size == 0 and stream_info(self.header)["n"] > 0:
+            raise BitboxError(1, "the sequence layout needs references stored as coordinates (ref_mode 1)")
+        self.ws_size = int(lib.bbx_decompress_workspace_size(self.header, 128))
+        self.ws = torch.empty(max(self.ws_size, 1), dtype=torch.uint8, device=device)
+        self.out = torch.empty(max(self.size, 8), dtype=torch.uint8, device=device)
+        self.d_status = torch.zeros(1, dtype=torch.int32, device=device)
+
+    def _call(self, stream_t: torch.Tensor, d_status, stream):
+        return self._lib.bbx_export_sequences(
+            stream_t.data_ptr(), stream_t.numel(), self.header, self.out.data_ptr(), self.out.numel(),
+            d_status, self.ws.data_ptr(), self.ws_size, _stream_ptr(stream))
+
+    def launch(self, stream_t: torch.Tensor, stream=None):
+        _check(self._call(stream_t, self.d_status.data_ptr(), stream))
+
+    def __call__(self, stream_t: torch.Tensor, stream=None):
+        _check(self._call(stream_t, None, stream))
+        return self.out[: self.size]
+
+
+def export_sequences(stream_t: torch.Tensor, stream=None) -> torch.Tensor:
+    """The Sec. 4.2 sequence layout (centre, widths, codes, 32-bit end mark
+    per leaf) of a device uint8 stream compressed with ref_mode = 1."""
+    if stream_t.numel() < 128:
+        raise BitboxError(3, "stream shorter than its header")
+    header = stream_t[:128].cpu().numpy().tobytes()
+    return SequenceExporter(header, stream_t.device)(stream_t, stream).clone()
 
 
 @contextmanager

@@ -516,6 +516,35 @@ static size_t carve_decompress(const HostHeader& h, uint8_t* base, DecompressWs*
   return c.off;
 }
 
+static DecompressPlan plan_of(const HostHeader& h, uint32_t layout) {
+  DecompressPlan p;
+  memset(&p, 0, sizeof(p));
+  p.n = h.n;
+  p.n_leaves = h.n_leaves;
+  p.meta_bits = h.meta_bits;
+  p.payload_bits = h.payload_bits;
+  p.dims = h.dims;
+  p.dtype = h.dtype;
+  p.r = h.r;
+  p.mbits = h.mbits;
+  p.layout = layout;
+  p.ref_mode = h.ref_mode;
+  for (int d = 0; d < 3; ++d) p.G[d] = h.G[d], p.origin[d] = h.origin[d];
+  p.w = h.w;
+  p.inv_w = h.inv_w;
+  if (h.n) p.geom = make_geom(h.n, h.r);
+  return p;
+}
+
+// Bytes of the Sec. 4.2 sequence layout of a ref_mode 1 stream: per leaf the
+// centre (dims * M bits), the widths (dims * mbits), the member codes and a
+// 32-bit end mark, zero-padded to 8 bytes.
+static uint64_t export_bytes(const HostHeader& h) {
+  const uint64_t M = h.dtype == 0 ? 32 : 64;
+  const uint64_t bits = h.n_leaves * (h.dims * (M + h.mbits) + 32) + h.payload_bits;
+  return ((bits + 63) / 64) * 8;
+}
+
 }  // namespace bbx
 
 using namespace bbx;
@@ -703,22 +732,7 @@ bbx_status bbx_decompress(const void* d_stream, size_t stream_size, const void* 
   memset(&w, 0, sizeof(w));
   const size_t need = carve_decompress(h, (uint8_t*)d_ws, &w);
   if (ws_size < need) return fail(BBX_ENOMEM, "workspace too small: need " + std::to_string(need));
-  DecompressPlan p;
-  memset(&p, 0, sizeof(p));
-  p.n = h.n;
-  p.n_leaves = h.n_leaves;
-  p.meta_bits = h.meta_bits;
-  p.payload_bits = h.payload_bits;
-  p.dims = h.dims;
-  p.dtype = h.dtype;
-  p.r = h.r;
-  p.mbits = h.mbits;
-  p.layout = layout;
-  p.ref_mode = h.ref_mode;
-  for (int d = 0; d < 3; ++d) p.G[d] = h.G[d], p.origin[d] = h.origin[d];
-  p.w = h.w;
-  p.inv_w = h.inv_w;
-  if (h.n) p.geom = make_geom(h.n, h.r);
+  const DecompressPlan p = plan_of(h, layout);
   hipError_t e = launch_decompress(p, w, (const uint8_t*)d_stream, d_pos, d_status, stream);
   if (e != hipSuccess) return fail(BBX_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
   if (!d_status) {
@@ -727,6 +741,50 @@ bbx_status bbx_decompress(const void* d_stream, size_t stream_size, const void* 
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return fail(BBX_EHIP, std::string("synchronize failed: ") + hipGetErrorString(e));
     if (hp.status != BBX_OK) return fail((bbx_status)hp.status, "stream payload fails validation");
+  }
+  return BBX_OK;
+}
+
+size_t bbx_export_sequences_size(const void* h_header, size_t header_bytes) {
+  HostHeader h;
+  if (parse_header((const uint8_t*)h_header, header_bytes, &h) != BBX_OK || h.ref_mode != 1) return 0;
+  return (size_t)export_bytes(h);
+}
+
+bbx_status bbx_export_sequences(const void* d_stream, size_t stream_size, const void* h_header,
+                                void* d_out, size_t out_cap, uint32_t* d_status, void* d_ws,
+                                size_t ws_size, hipStream_t stream) {
+  if (!d_stream || ((uintptr_t)d_stream & 7)) return fail(BBX_EINVAL, "d_stream must be 8-byte aligned");
+  if (stream_size < (size_t)kHeaderBytes) return fail(BBX_ECORRUPT, "stream shorter than its header");
+  uint8_t hb[kHeaderBytes];
+  if (!h_header) {
+    hipError_t e = hipMemcpyAsync(hb, d_stream, kHeaderBytes, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return fail(BBX_EHIP, std::string("header copy failed: ") + hipGetErrorString(e));
+    h_header = hb;
+  }
+  HostHeader h;
+  bbx_status st = parse_header((const uint8_t*)h_header, kHeaderBytes, &h);
+  if (st != BBX_OK) return st;
+  if (h.ref_mode != 1) return fail(BBX_EINVAL, "the sequence layout needs references stored as coordinates (ref_mode 1)");
+  if (stream_size < stream_bytes_of(h)) return fail(BBX_ECORRUPT, "stream shorter than its sections");
+  const uint64_t need_out = export_bytes(h);
+  if (out_cap < need_out) return fail(BBX_ENOSPC, "output buffer too small: need " + std::to_string(need_out));
+  if (need_out > 0 && (!d_out || ((uintptr_t)d_out & 7))) return fail(BBX_EINVAL, "d_out is NULL or not 8-byte aligned");
+  if (!d_ws || ((uintptr_t)d_ws & 255)) return fail(BBX_EINVAL, "d_ws must be 256-byte aligned");
+  DecompressWs w;
+  memset(&w, 0, sizeof(w));
+  const size_t need = carve_decompress(h, (uint8_t*)d_ws, &w);
+  if (ws_size < need) return fail(BBX_ENOMEM, "workspace too small: need " + std::to_string(need));
+  const DecompressPlan p = plan_of(h, BBX_AOS);
+  hipError_t e = launch_export(p, w, (const uint8_t*)d_stream, d_out, d_status, stream);
+  if (e != hipSuccess) return fail(BBX_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+  if (!d_status) {
+    DevParams hp;
+    e = hipMemcpyAsync(&hp, w.params, sizeof(hp), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return fail(BBX_EHIP, std::string("synchronize failed: ") + hipGetErrorString(e));
+    if (hp.status != BBX_OK) return fail((bbx_status)hp.status, "stream fails validation");
   }
   return BBX_OK;
 }

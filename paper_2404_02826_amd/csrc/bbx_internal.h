@@ -420,6 +420,8 @@ hipError_t launch_leaves(const BatchPlan& bp, const Ws& w, hipStream_t s);
 hipError_t launch_pack(const BatchPlan& bp, const Ws& w, hipStream_t s);
 hipError_t launch_decompress(const DecompressPlan& p, const DecompressWs& w, const uint8_t* stream,
                              void* pos, uint32_t* d_status, hipStream_t s);
+hipError_t launch_export(const DecompressPlan& p, const DecompressWs& w, const uint8_t* stream,
+                         void* out, uint32_t* d_status, hipStream_t s);
 hipError_t launch_dec_scan(uint64_t count, uint64_t* bits, uint64_t* part, DevParams* params,
                            uint64_t expect_payload, hipStream_t s);
 

@@ -12,6 +12,8 @@
 //                cover its slots, every thread decodes slots
 //                (reference -> its code; member j -> payload code j-1)
 //   k_dec_refs   ref_mode 1: the references' stored coordinates, exactly
+//   k_export     the Sec. 4.2 sequence layout of a ref_mode 1 stream (with
+//                k_dec_meta and the scan for the leaves' code offsets)
 #include "bbx_internal.h"
 
 namespace bbx {
@@ -361,6 +363,130 @@ hipError_t launch_decompress(const DecompressPlan& p, const DecompressWs& w, con
     else if (p.ref_mode)
       BBX_LAUNCH("dec_refs", k_dec_refs<uint64_t>, g, kBlock, 0, s, p.n, p.n_leaves, p.dims,
                  p.mbits, p.layout, p.meta_bits, w.leaves, stream, (uint64_t*)pos, w.params);
+  }
+  BBX_LAUNCH("dec_finish", k_dec_finish, 1, 64, 0, s, w.params, d_status);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- sequence export
+
+constexpr uint32_t kExportLeaves = 256;  // leaves per block of k_export
+
+// ORs the low `len` (<= 64) bits of v, whose bit 0 sits at absolute bit
+// `at`, into the word whose bit 0 sits at absolute bit w0.
+__device__ inline void or_bits(uint64_t& word, uint64_t w0, uint64_t v, uint64_t at, uint32_t len) {
+  if (len == 0 || at >= w0 + 64 || at + len <= w0) return;
+  if (len < 64) v &= (1ull << len) - 1;
+  if (at >= w0)
+    word |= v << (at - w0);
+  else
+    word |= v >> (w0 - at);
+}
+
+// Zeroes the output words that two blocks of k_export share (the word
+// holding the first bit of every block's first sequence but the first).
+// After a failed validation (the offsets may then run past the layout)
+// nothing is written.
+__global__ void k_export_edges(uint64_t n_leaves, uint64_t F, const uint64_t* off, uint64_t* out,
+                               uint64_t out_words, const DevParams* P) {
+  if (P->status != BBX_OK) return;
+  const uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x + 1;
+  const uint64_t L0 = b * kExportLeaves;
+  if (L0 >= n_leaves) return;
+  const uint64_t at = L0 * F + off[L0];
+  if ((at & 63) && (at >> 6) < out_words) out[at >> 6] = 0;
+}
+
+// The Sec. 4.2 sequence layout of a ref_mode 1 stream: per leaf, in stored
+// order, the centre's coordinate bits (M per axis), the widths (mbits each),
+// the member codes (the leaf's payload segment, `off` its exclusive bit
+// offsets) and a 32-bit end mark of all ones.  A block takes kExportLeaves
+// leaves and writes the output words their sequences cover, one thread per
+// word; the words it shares with a neighbouring block (zeroed before) take
+// an atomic OR, every other word a plain store.
+__global__ void __launch_bounds__(kBlock) k_export(uint64_t n_leaves, uint32_t dims, uint32_t mbits,
+                                                   uint32_t M, uint64_t meta_bits,
+                                                   uint64_t payload_bits, const uint64_t* off,
+                                                   const uint8_t* stream, uint64_t* out,
+                                                   const DevParams* P) {
+  if (P->status != BBX_OK) return;
+  __shared__ uint64_t so[kExportLeaves + 1];  // first output bit of each sequence (+ the end)
+  const uint64_t F = (uint64_t)dims * (M + mbits) + 32;  // bits of a sequence besides its codes
+  const uint64_t L0 = (uint64_t)blockIdx.x * kExportLeaves;
+  const uint32_t cnt = (uint32_t)(n_leaves - L0 < kExportLeaves ? n_leaves - L0 : kExportLeaves);
+  for (uint32_t t = threadIdx.x; t <= cnt; t += blockDim.x) {
+    const uint64_t L = L0 + t;
+    so[t] = L * F + (L < n_leaves ? off[L] : payload_bits);
+  }
+  __syncthreads();
+  const uint64_t* meta = (const uint64_t*)(stream + kHeaderBytes);
+  const uint64_t mwords = (meta_bits + 63) / 64;
+  const uint64_t* pay = meta + mwords;
+  const uint64_t pwords = (payload_bits + 63) / 64;
+  const uint64_t S = (uint64_t)dims * (mbits + M);
+  const uint64_t b_beg = so[0], b_end = so[cnt];  // b_end - b_beg >= F > 0
+  const uint64_t w_first = b_beg >> 6, w_last = (b_end - 1) >> 6;
+  for (uint64_t w = w_first + threadIdx.x; w <= w_last; w += blockDim.x) {
+    const uint64_t b0 = w << 6;
+    // the last sequence starting at or before the word (or the block's first)
+    const uint64_t x = b0 > b_beg ? b0 : b_beg;
+    uint32_t lo = 0, hi = cnt;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (so[mid] <= x)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    uint64_t word = 0;
+    for (uint32_t i = lo; i < cnt && so[i] < b0 + 64; ++i) {
+      const uint64_t L = L0 + i, at = so[i], rec = L * S;
+      const uint64_t p0 = at + dims * (M + mbits), plen = so[i + 1] - at - F;
+      if (at < b0 + 64 && p0 > b0) {  // centre and widths reach into the word
+        for (uint32_t d = 0; d < dims; ++d) {
+          or_bits(word, b0, (uint64_t)read_bits(meta, mwords, rec + dims * mbits + d * M, M),
+                  at + d * M, M);
+          or_bits(word, b0, (uint64_t)read_bits(meta, mwords, rec + d * mbits, mbits),
+                  at + dims * M + d * mbits, mbits);
+        }
+      }
+      if (plen && p0 < b0 + 64 && p0 + plen > b0) {  // the part of the codes inside the word
+        const uint64_t s0 = p0 > b0 ? p0 : b0;
+        const uint64_t e0 = p0 + plen < b0 + 64 ? p0 + plen : b0 + 64;
+        const uint32_t len = (uint32_t)(e0 - s0);
+        or_bits(word, b0, (uint64_t)read_bits(pay, pwords, off[L] + (s0 - p0), len), s0, len);
+      }
+      or_bits(word, b0, 0xffffffffull, p0 + plen, 32);  // end mark
+    }
+    const bool shared = (w == w_first && (b_beg & 63) && L0 > 0) ||
+                        (w == w_last && (b_end & 63) && L0 + cnt < n_leaves);
+    if (shared)
+      atomicOr((unsigned long long*)&out[w], (unsigned long long)word);
+    else
+      out[w] = word;
+  }
+}
+
+hipError_t launch_export(const DecompressPlan& p, const DecompressWs& w, const uint8_t* stream,
+                         void* out, uint32_t* d_status, hipStream_t s) {
+  BBX_LAUNCH("dec_init", k_dec_init, 1, 64, 0, s, w.params);
+  if (p.n > 0) {
+    uint64_t g = (p.n_leaves + kBlock - 1) / kBlock;
+    if (g > 65536) g = 65536;
+    BBX_LAUNCH("dec_meta", k_dec_meta, g, kBlock, 0, s, p.n_leaves, p.dims, p.mbits, p.G[0],
+               p.G[1], p.G[2], p.meta_bits, p.geom, stream, w.leaves, w.leaf_bits, w.params,
+               p.ref_mode, p.dtype, p.origin[0], p.origin[1], p.origin[2], p.inv_w);
+    hipError_t e = launch_dec_scan(p.n_leaves, w.leaf_bits, w.scan_part, w.params, p.payload_bits, s);
+    if (e != hipSuccess) return e;
+    const uint32_t M = coord_bits(p.dtype);
+    const uint64_t F = (uint64_t)p.dims * (M + p.mbits) + 32;
+    const uint64_t blocks = (p.n_leaves + kExportLeaves - 1) / kExportLeaves;
+    const uint64_t out_words = (p.n_leaves * F + p.payload_bits + 63) / 64;
+    if (blocks > 1)
+      BBX_LAUNCH("export_edges", k_export_edges, (blocks - 1 + kBlock - 1) / kBlock, kBlock, 0, s,
+                 p.n_leaves, F, w.leaf_bits, (uint64_t*)out, out_words, w.params);
+    BBX_LAUNCH("export", k_export, blocks, kBlock, 0, s, p.n_leaves, p.dims, p.mbits, M,
+               p.meta_bits, p.payload_bits, w.leaf_bits, stream, (uint64_t*)out, w.params);
   }
   BBX_LAUNCH("dec_finish", k_dec_finish, 1, 64, 0, s, w.params, d_status);
   return hipGetLastError();

@@ -218,6 +218,49 @@ def test_lossless_reference_corrupt_on_device(orc, bbx):
         orc.decompress(bytes(b))
 
 
+# (generator, n, dims, dtype, eb, mode, r)
+EXPORT_CASES = [
+    ("uniform", 1, 3, np.float32, 1e-3, "rel", 32),
+    ("uniform", 4097, 2, np.float64, 1e-3, "rel", 1),            # sequences without codes
+    ("ties", 20000, 3, np.float32, 1e-2, "rel", 7),
+    ("cosmology", 100003, 3, np.float32, 1e-4, "rel", 32),       # many blocks, shared words
+    ("cosmology", 60000, 3, np.float64, 1e-6, "rel", 3000),      # long code segments, 64-bit centres
+    ("poincare", 65536, 2, np.float32, 1e-4, "rel", 16),
+]
+
+
+@pytest.mark.parametrize("case", EXPORT_CASES, ids=lambda c: f"{c[0]}-n{c[1]}-d{c[2]}-{np.dtype(c[3]).name}-r{c[6]}")
+def test_sequence_export(orc, bbx, case):
+    """The Sec. 4.2 sequence layout exported on the GPU from a ref_mode 1
+    stream equals the oracle's export byte for byte."""
+    kind, n, dims, dt, eb, mode, r = case
+    _say("export", case)
+    pts = gen(kind, n, dims, dt, seed=n % 71 + 9)
+    ref_s = orc.compress(pts, eb, mode, r, ref_mode=1)
+    want = orc.export_sequences(ref_s)
+    s = bbx.compress(torch.from_numpy(pts).cuda(), eb, mode, r, ref_mode=1)
+    assert s.cpu().numpy().tobytes() == ref_s
+    got = bbx.export_sequences(s).cpu().numpy().tobytes()
+    if got != want:
+        raise AssertionError(f"export differs at byte {first_diff(got, want)}; sizes {len(got)} vs {len(want)}")
+
+
+def test_sequence_export_errors(orc, bbx):
+    """A code-reference stream has no lossless centres to export (EINVAL); a
+    width field that Eq. 2 never produces is reported as ECORRUPT."""
+    pts = cosmology(20000, seed=14)
+    s0 = bbx.compress(torch.from_numpy(pts).cuda(), 1e-3, "rel", 32)
+    with pytest.raises(bbx.BitboxError) as e:
+        bbx.export_sequences(s0)
+    assert e.value.name == "EINVAL"
+    good = orc.compress(pts, 1e-3, "rel", 32, ref_mode=1)
+    b = bytearray(good)
+    b[128] = (b[128] & ~31) | 1  # first record's x width: 1
+    with pytest.raises(bbx.BitboxError) as e:
+        bbx.export_sequences(torch.from_numpy(np.frombuffer(bytes(b), dtype=np.uint8).copy()).cuda())
+    assert e.value.name == "ECORRUPT"
+
+
 def test_empty(orc, bbx):
     pts = np.zeros((0, 3), dtype=np.float32)
     ref = orc.compress(pts, 1e-3, "rel", 32)
