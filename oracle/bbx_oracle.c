@@ -887,3 +887,131 @@ int bbxo_export_sequences(const uint8_t* s, uint64_t size, uint8_t* out, uint64_
   free(sizes);
   return st;
 }
+
+/* ------------------------------------------------------------------ reordered export */
+
+/* The two reorderings of Sec. 4.2 before entropy coding, applied to the
+ * sequence layout: sequences in ascending sum_d m_d (ties in stored order),
+ * and inside each sequence the members in ascending R-index, the
+ * concatenation of their codes with the axes taken in ascending entropy of
+ * the widths m_d over all sequences (ties to the lower axis; the lowest
+ * entropy is the most significant part), ties in stored order.  Entropy is
+ * -sum p log2 p over the empirical distribution of m_d; compared exactly as
+ * counts: H_a < H_b iff sum c log c (over a's counts) > the same for b, the
+ * number of sequences being common. */
+typedef struct {
+  uint64_t key; /* sum of widths */
+  uint64_t idx;
+} seqkey_t;
+static int cmp_seq(const void* a, const void* b) {
+  const seqkey_t *x = (const seqkey_t*)a, *y = (const seqkey_t*)b;
+  if (x->key != y->key) return x->key < y->key ? -1 : 1;
+  return x->idx < y->idx ? -1 : (x->idx > y->idx);
+}
+typedef struct {
+  uint64_t u[3];
+  uint32_t pos;
+} memkey_t;
+static uint32_t g_order[3];
+static int cmp_mem(const void* a, const void* b) {
+  const memkey_t *x = (const memkey_t*)a, *y = (const memkey_t*)b;
+  for (int k = 0; k < 3; k++) {
+    uint32_t d = g_order[k];
+    if (x->u[d] != y->u[d]) return x->u[d] < y->u[d] ? -1 : 1;
+  }
+  return x->pos < y->pos ? -1 : (x->pos > y->pos);
+}
+
+int bbxo_export_sequences_reordered(const uint8_t* s, uint64_t size, uint8_t* out,
+                                    uint64_t out_cap, uint64_t* out_size, uint32_t* axis_order) {
+  uint64_t plain_size = 0;
+  int st = bbxo_export_sequences(s, size, NULL, 0, &plain_size);
+  if (st != BBXO_ENOSPC && st != BBXO_OK) return st;
+  if (out_size) *out_size = plain_size;
+  if (plain_size > out_cap) return BBXO_ENOSPC;
+  uint8_t* plain = (uint8_t*)calloc((size_t)(plain_size ? plain_size : 8), 1);
+  if (!plain) return BBXO_ENOMEM;
+  st = bbxo_export_sequences(s, size, plain, plain_size, &plain_size);
+  if (st) {
+    free(plain);
+    return st;
+  }
+  int dtype = s[6];
+  uint32_t dims = s[7], r = get_u32le(s + 16), mbits = s[23], M = coord_bits(dtype);
+  uint64_t n = get_u64le(s + 8), nl = get_u64le(s + 96);
+  if (plain_size) memset(out, 0, (size_t)plain_size);
+  /* widths and offsets of every sequence in the plain layout */
+  uint32_t* sizes = (uint32_t*)malloc((size_t)(nl ? nl : 1) * sizeof(uint32_t));
+  uint64_t* start = (uint64_t*)malloc((size_t)(nl ? nl : 1) * sizeof(uint64_t));
+  uint32_t* wid = (uint32_t*)malloc((size_t)(nl ? nl : 1) * 3 * sizeof(uint32_t));
+  seqkey_t* seq = (seqkey_t*)malloc((size_t)(nl ? nl : 1) * sizeof(seqkey_t));
+  memkey_t* mem = (memkey_t*)malloc((size_t)(r + 1) * sizeof(memkey_t));
+  uint64_t cnt[3][65];
+  if (!sizes || !start || !wid || !seq || !mem) {
+    free(plain), free(sizes), free(start), free(wid), free(seq), free(mem);
+    return BBXO_ENOMEM;
+  }
+  uint64_t k = 0;
+  if (n) size_leaves(n, r, sizes, &k, nl);
+  memset(cnt, 0, sizeof(cnt));
+  uint64_t pos = 0;
+  for (uint64_t i = 0; i < nl; i++) {
+    uint32_t sm = 0;
+    start[i] = pos;
+    for (uint32_t d = 0; d < dims; d++) {
+      wid[3 * i + d] = (uint32_t)get_bits(plain, pos + dims * M + d * mbits, mbits);
+      cnt[d][wid[3 * i + d]]++;
+      sm += wid[3 * i + d];
+    }
+    seq[i].key = sm;
+    seq[i].idx = i;
+    pos += dims * (M + mbits) + (uint64_t)(sizes[i] - 1) * sm + 32;
+  }
+  /* axes in ascending entropy of their widths: larger sum c log2 c first */
+  double ent[3] = {0, 0, 0};
+  for (uint32_t d = 0; d < dims; d++)
+    for (int w = 0; w < 65; w++)
+      if (cnt[d][w]) ent[d] += (double)cnt[d][w] * log2((double)cnt[d][w]);
+  uint32_t ord[3] = {0, 1, 2};
+  for (uint32_t a = 0; a < dims; a++)
+    for (uint32_t b = a + 1; b < dims; b++)
+      if (ent[ord[b]] > ent[ord[a]]) { uint32_t t = ord[a]; ord[a] = ord[b]; ord[b] = t; }
+  for (uint32_t b = 1; b < dims; b++) /* stable: equal entropy keeps axis order */
+    for (uint32_t a = b; a > 0 && ent[ord[a]] == ent[ord[a - 1]] && ord[a] < ord[a - 1]; a--) {
+      uint32_t t = ord[a]; ord[a] = ord[a - 1]; ord[a - 1] = t;
+    }
+  for (int d = 0; d < 3; d++) g_order[d] = d < (int)dims ? ord[d] : (uint32_t)d;
+  if (axis_order)
+    for (uint32_t d = 0; d < dims; d++) axis_order[d] = ord[d];
+  qsort(seq, (size_t)nl, sizeof(seqkey_t), cmp_seq);
+  uint64_t opos = 0;
+  for (uint64_t q = 0; q < nl; q++) {
+    uint64_t i = seq[q].idx, ip = start[i];
+    const uint32_t* m = wid + 3 * i;
+    uint32_t hdr = dims * (M + mbits), sm = (uint32_t)seq[q].key;
+    for (uint32_t b = 0; b < hdr; b += 32) {
+      uint32_t c = hdr - b < 32 ? hdr - b : 32;
+      put_bits(out, opos + b, get_bits(plain, ip + b, c), c);
+    }
+    uint64_t cp = ip + hdr, op = opos + hdr;
+    uint32_t cntm = sizes[i] - 1;
+    for (uint32_t j = 0; j < cntm; j++) {
+      mem[j].pos = j;
+      uint64_t at = cp + (uint64_t)j * sm;
+      for (uint32_t d = 0; d < 3; d++) {
+        mem[j].u[d] = 0;
+        if (d < dims) {
+          mem[j].u[d] = get_bits(plain, at, m[d]);
+          at += m[d];
+        }
+      }
+    }
+    qsort(mem, cntm, sizeof(memkey_t), cmp_mem);
+    for (uint32_t j = 0; j < cntm; j++)
+      for (uint32_t d = 0; d < dims; d++) put_bits(out, op, mem[j].u[d], m[d]), op += m[d];
+    put_bits(out, op, END_MARK, 32);
+    opos = op + 32;
+  }
+  free(plain), free(sizes), free(start), free(wid), free(seq), free(mem);
+  return BBXO_OK;
+}

@@ -90,6 +90,13 @@ int bbxo_stages_ex(const void* pos, uint64_t n, uint32_t dims, int dtype, int la
 int bbxo_export_sequences(const uint8_t* stream, uint64_t size, uint8_t* out, uint64_t out_cap,
                           uint64_t* out_size);
 
+/* The same layout after the two reorderings of Sec. 4.2: sequences in
+ * ascending sum of widths, members in ascending R-index (codes concatenated
+ * with the axes in ascending entropy of their widths; axis_order, optional,
+ * receives that order).  Same length as the plain export. */
+int bbxo_export_sequences_reordered(const uint8_t* stream, uint64_t size, uint8_t* out,
+                                    uint64_t out_cap, uint64_t* out_size, uint32_t* axis_order);
+
 /* Number of leaves of the size-only recursion for n particles, capacity r. */
 uint64_t bbxo_leaf_count(uint64_t n, uint32_t r);
 

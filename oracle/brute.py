@@ -285,3 +285,59 @@ def export_sequences(stream: bytes) -> bytes:
         opos += 32
     assert ppos == pay_bits
     return out.to_bytes(8 * ((opos + 63) // 64), "little")
+
+
+def export_sequences_reordered(stream: bytes):
+    """The two reorderings of Sec. 4.2 on the sequence layout, restated with
+    Python sorts: sequences by ascending sum of widths (stable), members by
+    ascending R-index (codes concatenated with the axes in ascending entropy
+    of their widths, the lower axis first on equal entropy; stable).
+    Returns (layout, axis order)."""
+    plain = export_sequences(stream)
+    (_m, _v, dt, dims, n, r, _e, _s, _rm, mbits) = struct.unpack("<4sHBBQIBBBB", stream[:24])
+    M = 32 if dt == 0 else 64
+    bits = int.from_bytes(plain, "little")
+    sizes = []
+
+    def rec(s):
+        if s <= r:
+            sizes.append(s)
+        else:
+            rec(s // 2)
+            rec(s - s // 2)
+
+    if n:
+        rec(n)
+    seqs, pos = [], 0
+    for s in sizes:
+        hdr = bits >> pos & ((1 << (dims * (M + mbits))) - 1)
+        m = [(bits >> (pos + dims * M + mbits * d)) & ((1 << mbits) - 1) for d in range(dims)]
+        at = pos + dims * (M + mbits)
+        mem = []
+        for _ in range(s - 1):
+            u = []
+            for d in range(dims):
+                u.append((bits >> at) & ((1 << m[d]) - 1))
+                at += m[d]
+            mem.append(u)
+        seqs.append((hdr, m, mem))
+        pos = at + 32
+    ent = []
+    for d in range(dims):
+        counts = {}
+        for _, m, _ in seqs:
+            counts[m[d]] = counts.get(m[d], 0) + 1
+        ent.append(sum(c * math.log2(c) for c in counts.values()))
+    order = sorted(range(dims), key=lambda d: (-ent[d], d))
+    out, opos = 0, 0
+    for k in sorted(range(len(seqs)), key=lambda i: (sum(seqs[i][1]), i)):
+        hdr, m, mem = seqs[k]
+        out |= hdr << opos
+        opos += dims * (M + mbits)
+        for u in sorted(mem, key=lambda u: tuple(u[d] for d in order)):
+            for d in range(dims):
+                out |= u[d] << opos
+                opos += m[d]
+        out |= 0xFFFFFFFF << opos
+        opos += 32
+    return out.to_bytes(8 * ((opos + 63) // 64), "little"), order

@@ -61,6 +61,8 @@ class Oracle:
                                        vp, vp, vp, vp, vp, vp]
         lib.bbxo_export_sequences.restype = i32
         lib.bbxo_export_sequences.argtypes = [vp, u64, vp, u64, C.POINTER(u64)]
+        lib.bbxo_export_sequences_reordered.restype = i32
+        lib.bbxo_export_sequences_reordered.argtypes = [vp, u64, vp, u64, C.POINTER(u64), vp]
         lib.bbxo_leaf_count.restype = u64
         lib.bbxo_leaf_count.argtypes = [u64, u32]
         lib.bbxo_bits_for_offset.restype = u32
@@ -142,6 +144,22 @@ class Oracle:
         if st:
             raise OracleError(st)
         return out[: size.value].tobytes()
+
+    def export_sequences_reordered(self, stream: bytes):
+        """(layout, axis order) after the two reorderings of Sec. 4.2."""
+        buf = np.frombuffer(stream, dtype=np.uint8) if len(stream) else np.zeros(1, np.uint8)
+        size = C.c_uint64(0)
+        order = np.zeros(3, dtype=np.uint32)
+        st = self.lib.bbxo_export_sequences_reordered(buf.ctypes.data, len(stream), None, 0,
+                                                      C.byref(size), order.ctypes.data)
+        if st not in (0, 2):
+            raise OracleError(st)
+        out = np.zeros(max(size.value, 8), dtype=np.uint8)
+        st = self.lib.bbxo_export_sequences_reordered(buf.ctypes.data, len(stream), out.ctypes.data,
+                                                      out.nbytes, C.byref(size), order.ctypes.data)
+        if st:
+            raise OracleError(st)
+        return out[: size.value].tobytes(), [int(v) for v in order[: stream[7]]]
 
     def stages(self, pos: np.ndarray, eb: float, eb_mode: str = "rel", r: int = 32,
                layout: str = "aos", ref_rule: int = 0) -> dict:

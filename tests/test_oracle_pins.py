@@ -453,3 +453,20 @@ def test_sequence_export_matches_brute_force_and_storage_model(oracle):
     s = oracle.compress(pts, 1e-4, "rel", 32, ref_mode=1)
     assert oracle.export_sequences(s) == brute.export_sequences(s)
     _expect("EINVAL", oracle.export_sequences, oracle.compress(pts, 1e-4, "rel", 32))
+
+
+def test_sequence_reordering_matches_python_sorts(oracle):
+    """The two reorderings of Sec. 4.2 (sequences by sum of widths, members by
+    R-index with the axes in ascending entropy of their widths) equal a
+    restatement with Python sorts, and keep the layout's length and every
+    sequence's members (a permutation within each sequence)."""
+    for pts, eb, mode, r in pins.tiny_cases(seed=401, count=40):
+        s = oracle.compress(pts, eb, mode, r, ref_mode=1)
+        got, order = oracle.export_sequences_reordered(s)
+        want, worder = brute.export_sequences_reordered(s)
+        assert got == want and order == worder, (pts.shape, r)
+        assert len(got) == len(oracle.export_sequences(s))
+    pts = cosmology(20000, seed=41)
+    s = oracle.compress(pts, 1e-4, "rel", 32, ref_mode=1)
+    got, order = oracle.export_sequences_reordered(s)
+    assert (got, order) == brute.export_sequences_reordered(s)
