@@ -502,6 +502,8 @@ def main():
     ap.add_argument("--qps", type=float, default=400.0, help="served workload: arrival rate")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 22)
+    ap.add_argument("--graph", type=int, default=0, choices=(0, 1),
+                    help="single set: replay the compress + decompress step as one recorded HIP graph")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for {args.gpus})",
@@ -562,15 +564,44 @@ def main():
         step()
     torch.cuda.synchronize()
     # correctness guard on the measured configuration: a sampled bound check
-    got = dec(stream_buf[:S])
+    got = dec(stream_buf[:S]).clone()
+    eager_stream = stream_buf[:S].clone()
     torch.cuda.synchronize()
+    run = step
+    if args.graph:
+        # the step recorded once (every library call on the capturing stream,
+        # no host synchronization inside), then replayed; each replay is
+        # checked against the eager result, with eager work in between
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            step()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            step()
+        for _ in range(3):
+            dec.pos.zero_()
+            stream_buf[:S].zero_()
+            torch.cuda.synchronize()
+            graph.replay()
+            torch.cuda.synchronize()
+            if not (torch.equal(stream_buf[:S], eager_stream) and
+                    torch.equal(dec.pos.view(torch.uint8), got.view(torch.uint8))):
+                raise RuntimeError("graph replay differs from the eager step")
+            step()
+            torch.cuda.synchronize()
+        run = graph.replay
+        for _ in range(args.warmup):
+            run()
     log("warmup done")
 
     # ---- timed region: exactly K steps
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for _ in range(args.steps):
-        step()
+        run()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     ms_per_step = elapsed * 1e3 / args.steps
@@ -591,6 +622,15 @@ def main():
     tc = [a.elapsed_time(b) for a, b, _ in ev]
     td = [b.elapsed_time(c) for _, b, c in ev]
     tt = sorted(a + b for a, b in zip(tc, td))
+    if args.graph:  # round-trip latency of the replayed step
+        eg = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+        for e0, e1 in eg:
+            e0.record(st)
+            run()
+            e1.record(st)
+        torch.cuda.synchronize()
+        tt = sorted(a.elapsed_time(b) for a, b in eg)
     p50 = tt[len(tt) // 2]
     p99 = tt[min(len(tt) - 1, int(math.ceil(0.99 * len(tt))) - 1)]
     mc, md = sorted(tc)[len(tc) // 2], sorted(td)[len(td) // 2]
@@ -685,7 +725,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "dims": dims, "input": dtype, "eb_rel": xi,
                    "leaf_size": args.leaf_size, "ref_rule": args.ref_rule,
-                   "ref_mode": args.ref_mode,
+                   "ref_mode": args.ref_mode, "graph": bool(args.graph),
                    "stream_bytes": S, "cr": round(B_in / S, 4),
                    "cr_other_ref_rule": round(B_in / S_alt, 4),
                    "cr_other_ref_mode": round(B_in / S_alt_mode, 4),
