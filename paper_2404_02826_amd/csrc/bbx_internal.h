@@ -23,6 +23,9 @@ constexpr int kRowStride = 258;           // per-chunk row: 257 prefix counts + 
 constexpr int kRows = 8;                  // rows of kBlock elements per streaming group
 constexpr int kGroup = kRows * kBlock;    // elements per streaming group
 constexpr uint64_t kLevelBlocks = 4096;   // blocks per global level of a set alone
+constexpr uint64_t kLocalBlocks = 4096;   // levels of at least this many nodes run block-local
+// a block-local level is one chunk per node under every block target
+static_assert(kLevelBlocks <= kLocalBlocks, "block-local levels must have one chunk per node");
 
 // Scalars of the range-and-bound step (Sec. 3), computed on the device by the
 // range epilogue and read by every later compress kernel of the set.
@@ -218,7 +221,7 @@ __host__ __device__ inline uint32_t dp_shift(const DigitPlan& p, uint32_t i) {
 // alone targets kLevelBlocks; in a batch each set targets its share of that
 // (by particle count, at least 1), so that a batch of many small sets does
 // not launch a block per 2048 codes.  Which levels are global does not depend
-// on the target (level_kind below always asks for kLevelBlocks).
+// on the target (level_kind below asks for kLocalBlocks).
 struct LevelShape {
   uint64_t nodes;
   uint32_t chunk_elems;
@@ -251,7 +254,7 @@ constexpr uint64_t kWaveNode = 4096;
 enum { kLevelGlobal = 0, kLevelBlock = 1, kLevelWave = 2 };
 __host__ __device__ inline int level_kind(uint64_t n, uint32_t depth) {
   if (((n + (1ull << depth) - 1) >> depth) <= kWaveNode) return kLevelWave;
-  return level_shape(n, depth, kLevelBlocks).chunks == 1 ? kLevelBlock : kLevelGlobal;
+  return level_shape(n, depth, kLocalBlocks).chunks == 1 ? kLevelBlock : kLevelGlobal;
 }
 __host__ __device__ inline bool level_is_local(uint64_t n, uint32_t depth) {
   return level_kind(n, depth) != kLevelGlobal;

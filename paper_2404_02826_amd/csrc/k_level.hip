@@ -449,8 +449,8 @@ __device__ __forceinline__ void scatter_load(uint32_t g, uint32_t end, const KT*
 
 template <bool FULL>
 __device__ __forceinline__ void scatter_ranks(uint32_t g, uint32_t end, const uint32_t (&k)[3][kRows],
-                                              uint32_t v, uint32_t (&rl)[kRows],
-                                              uint32_t (&re)[kRows], uint32_t& wl, uint32_t& we) {
+                                              uint32_t v, uint32_t (&rr)[kRows], uint32_t& wl,
+                                              uint32_t& we) {
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t wv = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const uint32_t base = g + wv * (kGroup / (kBlock / 64));
@@ -461,8 +461,8 @@ __device__ __forceinline__ void scatter_ranks(uint32_t g, uint32_t end, const ui
     const bool act = FULL || base + 64u * i + lane < end;
     const uint64_t mlt = __ballot(act && k[0][i] < v);
     const uint64_t meq = __ballot(act && k[0][i] == v);
-    rl[i] = wl + lanes_below(mlt);
-    re[i] = we + lanes_below(meq);
+    // ranks within the wavefront's 512 elements: below v | equal to v << 16
+    rr[i] = (wl + lanes_below(mlt)) | ((we + lanes_below(meq)) << 16);
     wl += popc64(mlt);
     we += popc64(meq);
   }
@@ -471,8 +471,7 @@ __device__ __forceinline__ void scatter_ranks(uint32_t g, uint32_t end, const ui
 template <typename KT, int NA, bool FULL, bool TRACK>
 __device__ __forceinline__ void scatter_store(uint32_t g, uint32_t end, const uint32_t (&k)[3][kRows],
                                               const uint32_t (&ki)[TRACK ? kRows : 1],
-                                              const uint32_t (&rl)[kRows],
-                                              const uint32_t (&re)[kRows], uint32_t bl,
+                                              const uint32_t (&rr)[kRows], uint32_t bl,
                                               uint32_t be, KT* B0, KT* B1, KT* B2,
                                               const uint32_t* is, uint32_t* id, uint32_t sz,
                                               uint32_t v, uint32_t jeq, bool cl, bool cr,
@@ -487,7 +486,7 @@ __device__ __forceinline__ void scatter_store(uint32_t g, uint32_t end, const ui
     const uint32_t p = base + 64u * i + lane;
     if (!FULL && p >= end) continue;
     const bool lt = k[0][i] < v, eq = k[0][i] == v;
-    const uint32_t L = bl + rl[i], E = be + re[i];
+    const uint32_t L = bl + (rr[i] & 0xffffu), E = be + (rr[i] >> 16);
     const uint32_t lb = L + umin32(E, jeq);
     const bool left = lt || (eq && E < jeq);
     const uint32_t dest = left ? lb : half + (p - lb);
@@ -508,12 +507,75 @@ __device__ __forceinline__ void scatter_store(uint32_t g, uint32_t end, const ui
   }
 }
 
+// Staged variant of scatter_store: each element goes to its slot in the
+// group's output order in LDS (stg: three axes of kGroup words, then the
+// source indices), left-goers first.  The group's left-goers land in one
+// contiguous run of the node and its right-goers in another, so the drain
+// below writes both runs with consecutive lanes on consecutive slots (stores
+// straight from the ranks interleave the two runs within every instruction).
+template <int NA, bool FULL, bool TRACK>
+__device__ __forceinline__ void scatter_stage(uint32_t g, uint32_t end, const uint32_t (&k)[3][kRows],
+                                              const uint32_t (&ki)[TRACK ? kRows : 1],
+                                              const uint32_t (&rr)[kRows], uint32_t bl,
+                                              uint32_t be, uint32_t lbg, uint32_t nl,
+                                              uint32_t v, uint32_t jeq, bool cl, bool cr,
+                                              uint32_t shn, uint32_t maskn, uint32_t* lhist,
+                                              uint32_t* stg, bool track, DevParams* P) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t wv = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const uint32_t base = g + wv * (kGroup / (kBlock / 64));
+#pragma unroll
+  for (int i = 0; i < kRows; ++i) {
+    const uint32_t p = base + 64u * i + lane;
+    if (!FULL && p >= end) continue;
+    const bool lt = k[0][i] < v, eq = k[0][i] == v;
+    const uint32_t L = bl + (rr[i] & 0xffffu), E = be + (rr[i] >> 16);
+    const uint32_t lb = L + umin32(E, jeq);
+    const bool left = lt || (eq && E < jeq);
+    const uint32_t loc = left ? lb - lbg : nl + (p - g) - (lb - lbg);
+    if (loc < (uint32_t)kGroup) {
+      stg[loc] = k[0][i];
+      if (NA > 1) stg[kGroup + loc] = k[1][i];
+      if (NA > 2) stg[2 * kGroup + loc] = k[2][i];
+      if (TRACK) stg[3 * kGroup + loc] = ki[i];  // (zero when the set carries none)
+      if (left ? cl : cr)
+        atomicAdd(&lhist[(left ? 0u : (uint32_t)kBlock) + (((NA > 1 ? k[1][i] : k[0][i]) >> shn) & maskn)],
+                  1u);
+    } else {
+      P->status = BBX_EHIP;  // inconsistent counts: never expected
+    }
+  }
+}
+
+// Writes a staged group: output t < nl is the left-goer at node slot lbg + t,
+// the others the right-goers from slot half + (g - lbg) on.
 template <typename KT, int NA, bool TRACK>
+__device__ __forceinline__ void scatter_drain(uint32_t g, uint32_t gsz, uint32_t lbg, uint32_t nl,
+                                              uint32_t half, uint32_t sz, KT* B0, KT* B1, KT* B2,
+                                              uint32_t* id, const uint32_t* stg, DevParams* P) {
+  const uint32_t rbase = half + (g - lbg) - nl;
+#pragma unroll
+  for (int i = 0; i < kRows; ++i) {
+    const uint32_t t = threadIdx.x + (uint32_t)kBlock * i;
+    if (t >= gsz) break;
+    const uint32_t dest = t < nl ? lbg + t : rbase + t;
+    if (dest < sz) {
+      B0[dest] = (KT)stg[t];
+      if (NA > 1) B1[dest] = (KT)stg[kGroup + t];
+      if (NA > 2) B2[dest] = (KT)stg[2 * kGroup + t];
+      if (TRACK && id) id[dest] = stg[3 * kGroup + t];
+    } else {
+      P->status = BBX_EHIP;  // inconsistent counts: never expected
+    }
+  }
+}
+
+template <typename KT, int NA, bool TRACK, bool STAGE>
 __device__ __forceinline__ void scatter_range(uint32_t beg, uint32_t end, const KT* A0, const KT* A1, const KT* A2,
                               KT* B0, KT* B1, KT* B2, const uint32_t* is, uint32_t* id,
                               uint32_t sz, uint32_t v, uint32_t jeq, uint32_t lt_run,
                               uint32_t eq_run, bool cl, bool cr, uint32_t shn, uint32_t maskn,
-                              uint32_t* lhist, DevParams* P) {
+                              uint32_t* lhist, uint32_t* stg, DevParams* P) {
   __shared__ __align__(16) uint32_t cnt[2][kBlock / 64][2];
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t wv = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -527,11 +589,11 @@ __device__ __forceinline__ void scatter_range(uint32_t beg, uint32_t end, const 
   int buf = 0;
   for (uint32_t g = beg; g < end; g += kGroup, buf ^= 1) {
     const bool full = g + kGroup <= end;
-    uint32_t rl[kRows], re[kRows], wl, we;
+    uint32_t rr[kRows], wl, we;
     if (full)
-      scatter_ranks<true>(g, end, k, v, rl, re, wl, we);
+      scatter_ranks<true>(g, end, k, v, rr, wl, we);
     else
-      scatter_ranks<false>(g, end, k, v, rl, re, wl, we);
+      scatter_ranks<false>(g, end, k, v, rr, wl, we);
     const uint32_t gn = g + kGroup;
     if (gn < end) {
       if (gn + kGroup <= end)
@@ -545,14 +607,28 @@ __device__ __forceinline__ void scatter_range(uint32_t beg, uint32_t end, const 
     const uint4 Y = *(const uint4*)&cnt[buf][2][0];  // wavefronts 2, 3
     const uint32_t bl = lt_run + (wv > 0 ? X.x : 0u) + (wv > 1 ? X.z : 0u) + (wv > 2 ? Y.x : 0u);
     const uint32_t be = eq_run + (wv > 0 ? X.y : 0u) + (wv > 1 ? X.w : 0u) + (wv > 2 ? Y.y : 0u);
+    const uint32_t lbg = lt_run + umin32(eq_run, jeq);  // left-goers before the group
     lt_run += X.x + X.z + Y.x + Y.z;
     eq_run += X.y + X.w + Y.y + Y.w;
-    if (full)
-      scatter_store<KT, NA, true, TRACK>(g, end, k, ki, rl, re, bl, be, B0, B1, B2, is, id, sz, v,
+    if (STAGE) {
+      // the previous group's drain finished before the barrier above
+      const uint32_t nl = lt_run + umin32(eq_run, jeq) - lbg;
+      if (full)
+        scatter_stage<NA, true, TRACK>(g, end, k, ki, rr, bl, be, lbg, nl, v, jeq, cl, cr, shn,
+                                       maskn, lhist, stg, is != nullptr, P);
+      else
+        scatter_stage<NA, false, TRACK>(g, end, k, ki, rr, bl, be, lbg, nl, v, jeq, cl, cr, shn,
+                                        maskn, lhist, stg, is != nullptr, P);
+      __syncthreads();
+      scatter_drain<KT, NA, TRACK>(g, full ? (uint32_t)kGroup : end - g, lbg, nl, sz >> 1, sz, B0, B1,
+                                   B2, id, stg, P);
+    } else if (full) {
+      scatter_store<KT, NA, true, TRACK>(g, end, k, ki, rr, bl, be, B0, B1, B2, is, id, sz, v,
                                          jeq, cl, cr, shn, maskn, lhist, P);
-    else
-      scatter_store<KT, NA, false, TRACK>(g, end, k, ki, rl, re, bl, be, B0, B1, B2, is, id, sz, v,
+    } else {
+      scatter_store<KT, NA, false, TRACK>(g, end, k, ki, rr, bl, be, B0, B1, B2, is, id, sz, v,
                                           jeq, cl, cr, shn, maskn, lhist, P);
+    }
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
@@ -563,11 +639,11 @@ __device__ __forceinline__ void scatter_range(uint32_t beg, uint32_t end, const 
   }
 }
 
-template <typename KT, bool TRACK>
+template <typename KT, bool TRACK, bool STAGE>
 __device__ void scatter_body(uint32_t depth, const SetDesc& S, DevParams* P, const LevelCtx& c,
                              uint32_t v, uint32_t jeq, uint32_t lt_run, uint32_t eq_run,
                              const uint8_t* src, uint8_t* dst, const uint32_t* isrc, uint32_t* idst,
-                             uint32_t* hist, uint32_t* lhist) {
+                             uint32_t* hist, uint32_t* lhist, uint32_t* stg) {
   static_assert(kBlock == 256, "four wavefronts per block");
   const uint64_t n = S.n, kst = S.kst;
   const uint32_t dims = S.dims, r = S.r;
@@ -582,6 +658,10 @@ __device__ void scatter_body(uint32_t depth, const SetDesc& S, DevParams* P, con
   const uint32_t end = (uint32_t)(beg64 + c.sh.chunk_elems < sz64 ? beg64 + c.sh.chunk_elems : sz64);
   const uint32_t* is = isrc ? isrc + st : nullptr;
   uint32_t* id = idst ? idst + st : nullptr;
+  if (STAGE && !TRACK && is) {  // the staged path carries indices only with TRACK
+    if (threadIdx.x == 0) P->status = BBX_EHIP;
+    return;
+  }
   if (sz <= r) {  // leaf: copy through
     const KT* s0 = (const KT*)src + st;
     KT* d0 = (KT*)dst + st;
@@ -612,11 +692,11 @@ __device__ void scatter_body(uint32_t depth, const SetDesc& S, DevParams* P, con
   KT* B1 = (KT*)dst + st + (uint64_t)a1 * kst;
   KT* B2 = (KT*)dst + st + (uint64_t)a2 * kst;
   if (dims == 3)
-    scatter_range<KT, 3, TRACK>(beg, end, A0, A1, A2, B0, B1, B2, is, id, sz, v, jeq, lt_run, eq_run, cl,
-                         cr, shn, maskn, lhist, P);
+    scatter_range<KT, 3, TRACK, STAGE>(beg, end, A0, A1, A2, B0, B1, B2, is, id, sz, v, jeq, lt_run,
+                                       eq_run, cl, cr, shn, maskn, lhist, stg, P);
   else  // fewer axes: the missing ones repeat the split axis (same value, same slot)
-    scatter_range<KT, 3, TRACK>(beg, end, A0, A1, A0, B0, B1, B0, is, id, sz, v, jeq, lt_run, eq_run, cl,
-                         cr, shn, maskn, lhist, P);
+    scatter_range<KT, 3, TRACK, STAGE>(beg, end, A0, A1, A0, B0, B1, B0, is, id, sz, v, jeq, lt_run,
+                                       eq_run, cl, cr, shn, maskn, lhist, stg, P);
   if (fuse) {
     __syncthreads();
     for (uint32_t child = 0; child < 2; ++child) {
@@ -640,16 +720,17 @@ __global__ void __launch_bounds__(kBlock) k_scatter(uint32_t depth, uint32_t nse
   if (P->status != BBX_OK) return;
   if (level_is_local(S.n, depth)) return;
   __shared__ uint32_t lhist[2 * kBlock];
+  __shared__ uint32_t stg[(TRACK ? 4 : 3) * kGroup];  // one staged group (codes, indices)
   const uint32_t* isrc = S.track ? isrc0 + S.idx_off : nullptr;
   uint32_t* idst = S.track ? idst0 + S.idx_off : nullptr;
   const NodeSel ns = (sel0 + S.sel_off)[c.lb / c.sh.chunks];
   const uint32_t* cb = cb0 + S.cb_off + c.lb * 2;
   if (P->key16)
-    scatter_body<uint16_t, TRACK>(depth, S, P, c, ns.v, ns.jeq, cb[0], cb[1], src0 + S.key_off,
-                           dst0 + S.key_off, isrc, idst, hist0 + S.hist_off, lhist);
+    scatter_body<uint16_t, TRACK, true>(depth, S, P, c, ns.v, ns.jeq, cb[0], cb[1], src0 + S.key_off,
+                                        dst0 + S.key_off, isrc, idst, hist0 + S.hist_off, lhist, stg);
   else
-    scatter_body<uint32_t, TRACK>(depth, S, P, c, ns.v, ns.jeq, cb[0], cb[1], src0 + S.key_off,
-                           dst0 + S.key_off, isrc, idst, hist0 + S.hist_off, lhist);
+    scatter_body<uint32_t, TRACK, true>(depth, S, P, c, ns.v, ns.jeq, cb[0], cb[1], src0 + S.key_off,
+                                        dst0 + S.key_off, isrc, idst, hist0 + S.hist_off, lhist, stg);
 }
 
 // Median of one node's axis codes, inside one block: radix passes of at most
@@ -766,11 +847,13 @@ __global__ void __launch_bounds__(kBlock) k_level_local(uint32_t depth, uint32_t
     __syncthreads();  // lhist is reused by the partition
   }
   if (P->key16)
-    scatter_body<uint16_t, false>(depth, S, P, c, v, jeq, 0, 0, src0 + S.key_off, dst0 + S.key_off, isrc,
-                           idst, hist0 + S.hist_off, lhist);
+    scatter_body<uint16_t, false, false>(depth, S, P, c, v, jeq, 0, 0, src0 + S.key_off,
+                                         dst0 + S.key_off, isrc, idst, hist0 + S.hist_off, lhist,
+                                         nullptr);
   else
-    scatter_body<uint32_t, false>(depth, S, P, c, v, jeq, 0, 0, src0 + S.key_off, dst0 + S.key_off, isrc,
-                           idst, hist0 + S.hist_off, lhist);
+    scatter_body<uint32_t, false, false>(depth, S, P, c, v, jeq, 0, 0, src0 + S.key_off,
+                                         dst0 + S.key_off, isrc, idst, hist0 + S.hist_off, lhist,
+                                         nullptr);
 }
 
 // Median of a node's axis codes by one wavefront (nodes of at most kWaveNode
