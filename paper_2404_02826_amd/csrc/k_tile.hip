@@ -78,12 +78,15 @@ __device__ inline uint32_t leaf_fold(uint32_t s, uint32_t r) { return s <= r ? s
 
 // Bit boxes of the tile's leaves (Sec. 4.1, Eq. 2) by aligned groups of gs
 // lanes; DT holds squared distances in doubled code space (32 bits suffice
-// when every code span is below 2^14).
-template <int TILE, typename KL, bool TRACK, typename DT>
+// when every code span is below 2^14).  With M > 0 every leaf has at most
+// M * gs members: each lane reads its members' codes once into registers
+// (fixed trip counts); M = 0 walks the members from LDS in each pass.
+template <int TILE, typename KL, bool TRACK, typename DT, int M>
 __device__ void tile_bitboxes(WaveTile<TILE, KL, TRACK>& sm, int cur, uint32_t nl, uint32_t gs, uint32_t dims,
                               uint32_t t0, uint32_t t1, uint32_t t2, uint64_t tst, uint64_t first_leaf,
                               uint64_t n_leaves, DevParams* P, LeafRec* leaves,
                               uint64_t* leaf_bits, uint32_t rule) {
+  constexpr int MR = M > 0 ? M : 1;
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t lpw = 64 / gs;
   const uint32_t sub = lane & (gs - 1);
@@ -92,14 +95,31 @@ __device__ void tile_bitboxes(WaveTile<TILE, KL, TRACK>& sm, int cur, uint32_t n
     const bool act = L < nl;
     const uint32_t ls = act ? (sm.H[L] & 0xffffu) : 0u, lz = act ? (sm.H[L] >> 16) : 0u;
     uint32_t mn[3] = {0xffffffffu, 0xffffffffu, 0xffffffffu}, mx[3] = {0, 0, 0};
-    for (uint32_t t = sub; t < lz; t += gs) {
-      const uint32_t slot = sm.Pm[cur][ls + t];
+    uint32_t rq[3][MR];  // M > 0: the lane's members (member sub + gs * m)
+    if (M > 0) {
 #pragma unroll
-      for (uint32_t d = 0; d < 3; ++d) {
-        if (d >= dims) break;
-        const uint32_t q = sm.K[d][slot];
-        mn[d] = umin32(q, mn[d]);
-        mx[d] = umax32(q, mx[d]);
+      for (int m = 0; m < MR; ++m) {
+        const uint32_t t = sub + gs * (uint32_t)m;
+        const uint32_t slot = t < lz ? sm.Pm[cur][ls + t] : 0u;
+#pragma unroll
+        for (uint32_t d = 0; d < 3; ++d) {
+          rq[d][m] = d < dims ? (uint32_t)sm.K[d][slot] : 0u;
+          if (t < lz) {
+            mn[d] = umin32(rq[d][m], mn[d]);
+            mx[d] = umax32(rq[d][m], mx[d]);
+          }
+        }
+      }
+    } else {
+      for (uint32_t t = sub; t < lz; t += gs) {
+        const uint32_t slot = sm.Pm[cur][ls + t];
+#pragma unroll
+        for (uint32_t d = 0; d < 3; ++d) {
+          if (d >= dims) break;
+          const uint32_t q = sm.K[d][slot];
+          mn[d] = umin32(q, mn[d]);
+          mx[d] = umax32(q, mx[d]);
+        }
       }
     }
     DT C[3] = {0, 0, 0};
@@ -112,28 +132,46 @@ __device__ void tile_bitboxes(WaveTile<TILE, KL, TRACK>& sm, int cur, uint32_t n
     }
     DT best = (DT)~(DT)0;
     uint32_t bpos = 0xffffffffu;
-    for (uint32_t t = sub; t < lz; t += gs) {
-      const uint32_t slot = sm.Pm[cur][ls + t];
+    // candidate distance of a member with codes q (Eq. 2 widths with rule 1)
+    auto dist_of = [&](const uint32_t* q) -> DT {
       DT dist = 0;
       if (rule) {  // fewest code bits: sum_d m_d with this member as the reference
         uint32_t bits = 0;
 #pragma unroll
         for (uint32_t d = 0; d < 3; ++d) {
           if (d >= dims) break;
-          const uint32_t q = sm.K[d][slot];
-          bits += width_of(umax32(q - mn[d], mx[d] - q));
+          bits += width_of(umax32(q[d] - mn[d], mx[d] - q[d]));
         }
         dist = (DT)bits;
       } else {  // nearest the AABB centre
 #pragma unroll
         for (uint32_t d = 0; d < 3; ++d) {
           if (d >= dims) break;
-          const DT q2 = 2 * (DT)sm.K[d][slot];
+          const DT q2 = 2 * (DT)q[d];
           const DT a = q2 > C[d] ? q2 - C[d] : C[d] - q2;
           dist += a * a;
         }
       }
-      if (dist < best) best = dist, bpos = t;  // t increases: ties keep the first
+      return dist;
+    };
+    if (M > 0) {
+#pragma unroll
+      for (int m = 0; m < MR; ++m) {
+        const uint32_t t = sub + gs * (uint32_t)m;
+        const uint32_t q[3] = {rq[0][m], rq[1][m], rq[2][m]};
+        const DT dist = dist_of(q);
+        if (t < lz && dist < best) best = dist, bpos = t;  // t increases: ties keep the first
+      }
+    } else {
+      for (uint32_t t = sub; t < lz; t += gs) {
+        const uint32_t slot = sm.Pm[cur][ls + t];
+        uint32_t q[3] = {0, 0, 0};
+#pragma unroll
+        for (uint32_t d = 0; d < 3; ++d)
+          if (d < dims) q[d] = sm.K[d][slot];
+        const DT dist = dist_of(q);
+        if (dist < best) best = dist, bpos = t;  // t increases: ties keep the first
+      }
     }
     for (uint32_t o = gs >> 1; o > 0; o >>= 1) {
       const DT d2 = __shfl_xor(best, (int)o);
@@ -451,12 +489,18 @@ __device__ void tile_body(WaveTile<TILE, KL, TRACK>& sm, uint64_t j, uint32_t K0
   }
   while (gs > 1 && gs / 2 >= maxleaf) gs >>= 1;
   const uint32_t span = umax32(Gt[0], umax32(Gt[1], Gt[2]));
-  if (span <= 14)
-    tile_bitboxes<TILE, KL, TRACK, uint32_t>(sm, cur, nl, gs, dims, tmin[0], tmin[1], tmin[2], tst,
-                                  first_leaf, n_leaves, P, leaves, leaf_bits, rule);
+  if (TILE == 256 && span <= 14 && maxleaf <= 4 * gs)  // the common shape: members in registers
+    tile_bitboxes<TILE, KL, TRACK, uint32_t, 4>(sm, cur, nl, gs, dims, tmin[0], tmin[1], tmin[2],
+                                                tst, first_leaf, n_leaves, P, leaves, leaf_bits,
+                                                rule);
+  else if (span <= 14)
+    tile_bitboxes<TILE, KL, TRACK, uint32_t, 0>(sm, cur, nl, gs, dims, tmin[0], tmin[1], tmin[2],
+                                                tst, first_leaf, n_leaves, P, leaves, leaf_bits,
+                                                rule);
   else
-    tile_bitboxes<TILE, KL, TRACK, uint64_t>(sm, cur, nl, gs, dims, tmin[0], tmin[1], tmin[2], tst,
-                                  first_leaf, n_leaves, P, leaves, leaf_bits, rule);
+    tile_bitboxes<TILE, KL, TRACK, uint64_t, 0>(sm, cur, nl, gs, dims, tmin[0], tmin[1], tmin[2],
+                                                tst, first_leaf, n_leaves, P, leaves, leaf_bits,
+                                                rule);
   wave_sync();
 
   // ---- write the node back in output-slot order (reference first per leaf)
