@@ -251,6 +251,7 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
           bp->lv_local[k] = 1;
         else
           bp->lv_global[k] = 1;
+        if (kind == kLevelGlobal && sh.chunks > 256) bp->sel_wide[k] = 1;
         lv[s].push_back(sh.nodes * sh.chunks);
         nd[s].push_back(sh.nodes);
         if (kind == kLevelGlobal) {  // only these use selections and rows

@@ -389,6 +389,7 @@ struct BatchPlan {
   uint64_t o_lv[kMaxDepth], o_nd[kMaxDepth];
   uint8_t lv_local[kMaxDepth];   // some set handles level k one block per node
   uint8_t lv_global[kMaxDepth];  // some set handles level k with global histograms
+  uint8_t sel_wide[kMaxDepth];   // some set's nodes have > 256 chunks at global level k
   uint8_t lv_wave[kMaxDepth];    // some set handles level k one wavefront per node
   uint8_t lv_fused[kMaxDepth];   // some set handles levels k, k + 1 fused, a wavefront per node
   uint8_t lv_fused4[kMaxDepth];  // some set handles levels k, k + 1 fused, a block per node

@@ -315,9 +315,74 @@ __global__ void __launch_bounds__(kBlock) k_hist_last(uint32_t depth, uint32_t n
                              rows0 + S.rows_off, lh);
 }
 
+// One wavefront: the last digit b holding the node's median rank among the
+// node's 2^w last-digit bins (re-zeroed after the read) and the rank jeq of
+// the median among the members equal to it.  False when the bins hold fewer
+// members than the rank (inconsistent counts, never expected).
+__device__ inline bool last_digit_of(uint32_t* hist, uint32_t nb, uint32_t rank, uint32_t* b_out,
+                                     uint32_t* jeq_out) {
+  const uint32_t lane = threadIdx.x & 63;
+  uint32_t c[4], mine = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint32_t b = lane * 4 + k;
+    c[k] = b < nb ? hist[b] : 0u;
+    mine += c[k];
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (c[k]) hist[lane * 4 + k] = 0;
+  uint32_t cum = wave_incl(mine) - mine;
+  uint32_t fb = 0, fj = 0;
+  bool found = false;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (cum <= rank && rank < cum + c[k]) found = true, fb = lane * 4 + k, fj = rank - cum;
+    cum += c[k];
+  }
+  const uint64_t fm = __ballot(found);
+  if (fm == 0) return false;
+  const int fl = __ffsll((unsigned long long)fm) - 1;  // exactly one lane finds the rank
+  *b_out = (uint32_t)__builtin_amdgcn_readlane((int)fb, fl);
+  *jeq_out = (uint32_t)__builtin_amdgcn_readlane((int)fj, fl);
+  return true;
+}
+
+// The node of a last-digit select, or false when the set or node has none.
+struct LastSel {
+  const SetDesc* S;
+  DevParams* P;
+  uint64_t j, chunks;
+  uint32_t rank, prefix, w;
+};
+__device__ inline bool last_sel_node(uint32_t depth, uint32_t nsets, const uint64_t* pre,
+                                     const SetDesc* sets, const DevParams* params,
+                                     const NodeSel* sel0, uint64_t gn, LastSel* o) {
+  const uint32_t s = find_set(pre, nsets, gn);
+  const SetDesc& S = sets[s];
+  const DevParams* P = params + s;
+  if (P->status != BBX_OK) return false;
+  if (level_is_local(S.n, depth)) return false;
+  const DigitPlan pl = digit_plan(P->G[depth % S.dims]);
+  const uint32_t pass = pl.npass - 1;
+  const uint64_t j = gn - pre[s];
+  uint64_t st, sz;
+  node_span(S.n, depth, j, &st, &sz);
+  if (sz <= S.r) return false;
+  o->S = &S;
+  o->P = (DevParams*)P;
+  o->j = j;
+  o->chunks = level_shape(S.n, depth, S.level_blocks).chunks;
+  o->w = dp_width(pl, pass);
+  o->rank = pass == 0 ? (uint32_t)(sz >> 1) : sel0[S.sel_off + j].rank;
+  o->prefix = pass == 0 ? 0u : sel0[S.sel_off + j].prefix;
+  return true;
+}
+
 // Per node: the median code v and how many members equal to v go left, then
 // each chunk's (lt, eq) base by an exclusive scan over the node's chunks.
-// One wavefront per node, capped grid striding over the nodes.
+// One wavefront per node, capped grid striding over the nodes (levels whose
+// nodes have few chunks).
 __global__ void __launch_bounds__(kBlock) k_select_last(uint32_t depth, uint32_t nsets,
                                                         const uint64_t* pre, const SetDesc* sets,
                                                         const DevParams* params, NodeSel* sel0,
@@ -328,59 +393,25 @@ __global__ void __launch_bounds__(kBlock) k_select_last(uint32_t depth, uint32_t
   constexpr uint32_t wpb = kBlock / 64;
   for (uint64_t gn = (uint64_t)blockIdx.x * wpb + (threadIdx.x >> 6); gn < total;
        gn += (uint64_t)gridDim.x * wpb) {
-    const uint32_t s = find_set(pre, nsets, gn);
-    const SetDesc& S = sets[s];
-    const DevParams* P = params + s;
-    if (P->status != BBX_OK) continue;
-    if (level_is_local(S.n, depth)) continue;
-    const DigitPlan pl = digit_plan(P->G[depth % S.dims]);
-    const uint32_t pass = pl.npass - 1;
-    const uint64_t j = gn - pre[s];
-    uint64_t st, sz;
-    node_span(S.n, depth, j, &st, &sz);
-    if (sz <= S.r) continue;
-    const uint64_t chunks = level_shape(S.n, depth, S.level_blocks).chunks;
-    NodeSel* sel = sel0 + S.sel_off;
+    LastSel L;
+    if (!last_sel_node(depth, nsets, pre, sets, params, sel0, gn, &L)) continue;
+    const SetDesc& S = *L.S;
+    const uint64_t j = L.j, chunks = L.chunks;
     uint32_t* hist = hist0 + S.hist_off + (j << 8);
     const uint32_t* rows = rows0 + S.rows_off + j * chunks * kRowStride;
     uint32_t* chunk_base = cb0 + S.cb_off + j * chunks * 2;
-    const uint32_t w = dp_width(pl, pass);
-    const uint32_t nb = 1u << w;
-    const uint32_t rank = pass == 0 ? (uint32_t)(sz >> 1) : sel[j].rank;
-    const uint32_t prefix = pass == 0 ? 0u : sel[j].prefix;
-    uint32_t c[4], mine = 0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const uint32_t b = lane * 4 + k;
-      c[k] = b < nb ? hist[b] : 0u;
-      mine += c[k];
-    }
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-      if (c[k]) hist[lane * 4 + k] = 0;
-    uint32_t cum = wave_incl(mine) - mine;
-    uint32_t fb = 0, fj = 0;
-    bool found = false;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      if (cum <= rank && rank < cum + c[k]) found = true, fb = lane * 4 + k, fj = rank - cum;
-      cum += c[k];
-    }
-    const uint64_t fm = __ballot(found);
-    if (fm == 0) {  // histogram total below the rank: inconsistent counts, never expected
-      if (lane == 0) ((DevParams*)P)->status = BBX_EHIP;
+    uint32_t b, jeq;
+    if (!last_digit_of(hist, 1u << L.w, L.rank, &b, &jeq)) {
+      if (lane == 0) L.P->status = BBX_EHIP;
       continue;
     }
-    const int fl = __ffsll((unsigned long long)fm) - 1;  // exactly one lane finds the rank
-    const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)fb, fl);
-    const uint32_t jeq = (uint32_t)__builtin_amdgcn_readlane((int)fj, fl);
     if (lane == 0) {
       NodeSel ns;
-      ns.prefix = prefix;
-      ns.rank = rank;
-      ns.v = (prefix << w) | b;
+      ns.prefix = L.prefix;
+      ns.rank = L.rank;
+      ns.v = (L.prefix << L.w) | b;
       ns.jeq = jeq;
-      sel[j] = ns;
+      sel0[S.sel_off + j] = ns;
     }
     // per-chunk counts of members below v (lt) and equal to v (eq), then an
     // exclusive scan over the node's chunks in rounds of 64 (chunk = round *
@@ -410,6 +441,85 @@ __global__ void __launch_bounds__(kBlock) k_select_last(uint32_t depth, uint32_t
         run_l += (uint32_t)__builtin_amdgcn_readlane((int)il, 63);
         run_e += (uint32_t)__builtin_amdgcn_readlane((int)ie, 63);
       }
+    }
+  }
+}
+
+// As k_select_last for levels whose nodes have many chunks (the top levels
+// of a large set): one block per node, the chunk scan spread over the block
+// (16 consecutive chunks per thread, all their loads in flight).
+__global__ void __launch_bounds__(kBlock) k_select_last_wide(uint32_t depth, uint32_t nsets,
+                                                             const uint64_t* pre,
+                                                             const SetDesc* sets,
+                                                             const DevParams* params,
+                                                             NodeSel* sel0, uint32_t* hist0,
+                                                             const uint32_t* rows0,
+                                                             uint32_t* cb0) {
+  constexpr uint32_t kPer = 16;
+  __shared__ uint32_t bx[2];
+  const uint32_t lane = threadIdx.x & 63;
+  const uint64_t total = pre[nsets];
+  for (uint64_t gn = blockIdx.x; gn < total; gn += gridDim.x) {
+    LastSel L;
+    // every thread reads the set's status; a status set meanwhile by another
+    // block must not split the block at the barriers below
+    const bool mine = last_sel_node(depth, nsets, pre, sets, params, sel0, gn, &L);
+    if (!__syncthreads_and(mine ? 1 : 0)) continue;
+    const SetDesc& S = *L.S;
+    const uint64_t j = L.j, chunks = L.chunks;
+    if (threadIdx.x < 64) {
+      uint32_t b = 0, jeq = 0;
+      const bool ok = last_digit_of(hist0 + S.hist_off + (j << 8), 1u << L.w, L.rank, &b, &jeq);
+      if (lane == 0) {
+        if (ok) {
+          NodeSel ns;
+          ns.prefix = L.prefix;
+          ns.rank = L.rank;
+          ns.v = (L.prefix << L.w) | b;
+          ns.jeq = jeq;
+          sel0[S.sel_off + j] = ns;
+        } else {
+          L.P->status = BBX_EHIP;
+        }
+        bx[0] = ok ? 1u : 0u;
+        bx[1] = b;
+      }
+    }
+    __syncthreads();
+    const bool ok = bx[0] != 0;
+    const uint32_t b = bx[1];
+    __syncthreads();  // bx is rewritten by the next node
+    if (!ok) continue;
+    const uint32_t* rows = rows0 + S.rows_off + j * chunks * kRowStride;
+    uint32_t* chunk_base = cb0 + S.cb_off + j * chunks * 2;
+    uint64_t run = 0;  // (lt << 32) | eq before this round
+    for (uint64_t r0 = 0; r0 < chunks; r0 += (uint64_t)kPer * kBlock) {
+      const uint64_t c0 = r0 + (uint64_t)threadIdx.x * kPer;
+      uint32_t lt[kPer], eq[kPer];
+      uint64_t mine = 0;
+#pragma unroll
+      for (uint32_t u = 0; u < kPer; ++u) {
+        lt[u] = eq[u] = 0;
+        if (c0 + u < chunks) {
+          const uint32_t* row = rows + (c0 + u) * kRowStride;
+          const uint32_t lo = row[b], hi = row[b + 1];
+          lt[u] = row[257] + lo;
+          eq[u] = hi - lo;
+        }
+      }
+#pragma unroll
+      for (uint32_t u = 0; u < kPer; ++u) mine += ((uint64_t)lt[u] << 32) | eq[u];
+      uint64_t tot;
+      uint64_t at = run + block_exscan_u64(mine, &tot);
+#pragma unroll
+      for (uint32_t u = 0; u < kPer; ++u) {
+        if (c0 + u < chunks) {
+          chunk_base[(c0 + u) * 2 + 0] = (uint32_t)(at >> 32);
+          chunk_base[(c0 + u) * 2 + 1] = (uint32_t)at;
+        }
+        at += ((uint64_t)lt[u] << 32) | eq[u];
+      }
+      run += tot;
     }
   }
 }
@@ -1386,8 +1496,13 @@ hipError_t launch_levels(const BatchPlan& bp, const Ws& w, hipStream_t s) {
     }
     BBX_LAUNCH("level_hist_last", k_hist_last, bp.g_lv[k], kBlock, 0, s, k, bp.nsets, plv, w.sets,
                w.params, w.keys[cur], w.sel, w.hist, w.rows);
-    BBX_LAUNCH("level_select_last", k_select_last, sel_grid(bp.g_nd[k]), kBlock, 0, s, k,
-               bp.nsets, pnd, w.sets, w.params, w.sel, w.hist, w.rows, w.chunk_base);
+    if (bp.sel_wide[k])  // some set's nodes have many chunks at this level
+      BBX_LAUNCH("level_select_last", k_select_last_wide,
+                 bp.g_nd[k] < 8192 ? (bp.g_nd[k] ? bp.g_nd[k] : 1) : 8192, kBlock, 0, s, k,
+                 bp.nsets, pnd, w.sets, w.params, w.sel, w.hist, w.rows, w.chunk_base);
+    else
+      BBX_LAUNCH("level_select_last", k_select_last, sel_grid(bp.g_nd[k]), kBlock, 0, s, k,
+                 bp.nsets, pnd, w.sets, w.params, w.sel, w.hist, w.rows, w.chunk_base);
     BBX_LAUNCH("level_scatter", bp.track ? k_scatter<true> : k_scatter<false>, bp.g_lv[k], kBlock,
                0, s, k, bp.nsets, plv, w.sets, w.params, w.sel, w.chunk_base, w.keys[cur],
                w.keys[cur ^ 1], w.idx[cur], w.idx[cur ^ 1], w.hist);
