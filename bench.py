@@ -497,6 +497,8 @@ def main():
                     help="leaf reference: 0 nearest the AABB centre (the paper's), 1 fewest bits")
     ap.add_argument("--ref-mode", type=int, default=0, choices=(0, 1),
                     help="reference stored as 0 its codes, 1 its original coordinates (lossless)")
+    ap.add_argument("--scatter-stage", type=int, default=0, choices=(0, 1, 2),
+                    help="global partition group stores: 0 by chunk size, 1 staged, 2 direct")
     ap.add_argument("--nsets", type=int, default=4096)
     ap.add_argument("--requests", type=int, default=2000, help="served workload: requests")
     ap.add_argument("--qps", type=float, default=400.0, help="served workload: arrival rate")
@@ -536,7 +538,8 @@ def main():
 
     dims = int(x.shape[1])
     comp = bbx.Compressor(n, dims, x.dtype, leaf_size=args.leaf_size, tile=args.tile,
-                          ref_rule=args.ref_rule, ref_mode=args.ref_mode)
+                          ref_rule=args.ref_rule, ref_mode=args.ref_mode,
+                          scatter_stage=args.scatter_stage)
     s = comp(x, xi)
     S = s.numel()
     # the other leaf-reference rule, and the other reference storage, on the
@@ -725,7 +728,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "dims": dims, "input": dtype, "eb_rel": xi,
                    "leaf_size": args.leaf_size, "ref_rule": args.ref_rule,
-                   "ref_mode": args.ref_mode, "graph": bool(args.graph),
+                   "ref_mode": args.ref_mode, "scatter_stage": args.scatter_stage,
+                   "graph": bool(args.graph),
                    "stream_bytes": S, "cr": round(B_in / S, 4),
                    "cr_other_ref_rule": round(B_in / S_alt, 4),
                    "cr_other_ref_mode": round(B_in / S_alt_mode, 4),

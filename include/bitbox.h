@@ -92,7 +92,13 @@ typedef enum { BBX_AOS = 0, BBX_SOA = 1 } bbx_layout;         /* [n][dims] or [d
  * 0 = its codes (G_d bits per axis); 1 = its original coordinates (32 or 64
  * bits per axis, the paper's lossless centre of Sec. 4.2), which decode
  * exactly; the other members decode identically in both modes.  ref_mode 1
- * carries source indices through the partition (as a perm output does). */
+ * carries source indices through the partition (as a perm output does).
+ * scatter_stage says how the partition levels that use global histograms
+ * store a group of members: 1 = staged in on-chip memory in output order and
+ * written with coalesced stores, 2 = stored straight from the ranks, 0 = the
+ * library's choice by the level's chunk size (staged from 16,384 members per
+ * block); like tile_override it never changes the stream, and all sets of a
+ * batch share it. */
 typedef struct {
   uint32_t leaf_size;     /* r >= 1 */
   uint32_t eb_mode;       /* bbx_eb_mode */
@@ -100,6 +106,7 @@ typedef struct {
   uint32_t tile_override; /* 0 (= 256), 256 or 512 */
   uint32_t ref_rule;      /* 0 (AABB centre) or 1 (fewest code bits) */
   uint32_t ref_mode;      /* 0 (reference code) or 1 (reference coordinates) */
+  uint32_t scatter_stage; /* 0 (by chunk size), 1 (always) or 2 (never) */
 } bbx_params;
 
 /* Worst-case stream size in bytes for n particles of the given type, with

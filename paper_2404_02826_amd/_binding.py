@@ -28,7 +28,8 @@ class BitboxError(RuntimeError):
 
 class _Params(C.Structure):
     _fields_ = [("leaf_size", C.c_uint32), ("eb_mode", C.c_uint32), ("layout", C.c_uint32),
-                ("tile_override", C.c_uint32), ("ref_rule", C.c_uint32), ("ref_mode", C.c_uint32)]
+                ("tile_override", C.c_uint32), ("ref_rule", C.c_uint32), ("ref_mode", C.c_uint32),
+                ("scatter_stage", C.c_uint32)]
 
 
 class _Set(C.Structure):
@@ -166,8 +167,9 @@ def _shape(pos: torch.Tensor, layout: str):
 
 
 def _params(leaf_size: int, eb_mode: str, layout: int, tile: int, ref_rule: int = 0,
-            ref_mode: int = 0) -> _Params:
-    return _Params(leaf_size, REL if eb_mode == "rel" else ABS, layout, tile, ref_rule, ref_mode)
+            ref_mode: int = 0, scatter_stage: int = 0) -> _Params:
+    return _Params(leaf_size, REL if eb_mode == "rel" else ABS, layout, tile, ref_rule, ref_mode,
+                   scatter_stage)
 
 
 def compress_bound(n: int, dims: int = 3, dtype=torch.float32, ref_mode: int = 0) -> int:
@@ -179,8 +181,9 @@ def compress_bound(n: int, dims: int = 3, dtype=torch.float32, ref_mode: int = 0
 
 def compress_workspace_size(n: int, dims: int = 3, dtype=torch.float32, leaf_size: int = 32,
                             eb_mode: str = "rel", layout: str = "aos", tile: int = 0,
-                            ref_rule: int = 0, ref_mode: int = 0) -> int:
-    p = _params(leaf_size, eb_mode, AOS if layout == "aos" else SOA, tile, ref_rule, ref_mode)
+                            ref_rule: int = 0, ref_mode: int = 0, scatter_stage: int = 0) -> int:
+    p = _params(leaf_size, eb_mode, AOS if layout == "aos" else SOA, tile, ref_rule, ref_mode,
+                scatter_stage)
     code = F32 if dtype == torch.float32 else F64
     lib = load()
     v = int(lib.bbx_compress_workspace_size(n, dims, code, C.byref(p)))
@@ -202,14 +205,14 @@ class Compressor:
 
     def __init__(self, n: int, dims: int = 3, dtype=torch.float32, leaf_size: int = 32,
                  eb_mode: str = "rel", layout: str = "aos", tile: int = 0, want_perm: bool = False,
-                 device="cuda", ref_rule: int = 0, ref_mode: int = 0):
+                 device="cuda", ref_rule: int = 0, ref_mode: int = 0, scatter_stage: int = 0):
         self.n, self.dims, self.dtype = n, dims, dtype
         self.layout = layout
         self.params = _params(leaf_size, eb_mode, AOS if layout == "aos" else SOA, tile, ref_rule,
-                              ref_mode)
+                              ref_mode, scatter_stage)
         lib = load()
         self.ws_size = compress_workspace_size(n, dims, dtype, leaf_size, eb_mode, layout, tile,
-                                               ref_rule, ref_mode)
+                                               ref_rule, ref_mode, scatter_stage)
         self.ws = torch.empty(self.ws_size, dtype=torch.uint8, device=device)
         self.cap = compress_bound(n, dims, dtype, ref_mode)
         self.out = torch.empty((self.cap + 7) // 8 * 8, dtype=torch.uint8, device=device)
@@ -514,15 +517,17 @@ def decompress_workspace_size(header: bytes) -> int:
 
 def compress(pos: torch.Tensor, eb: float, eb_mode: str = "rel", leaf_size: int = 32,
              layout: str = "aos", want_perm: bool = False, tile: int = 0, stream=None,
-             ref_rule: int = 0, ref_mode: int = 0):
+             ref_rule: int = 0, ref_mode: int = 0, scatter_stage: int = 0):
     """One-shot compress of a device tensor; returns the stream as a uint8
     device tensor (and the int32 source index of every output slot).
     ref_rule: 0 = leaf reference nearest the AABB centre (the paper's rule),
     1 = the member with the fewest code bits.  ref_mode: 0 = the reference
-    stored as its codes, 1 = as its original coordinates (decoded exactly)."""
+    stored as its codes, 1 = as its original coordinates (decoded exactly).
+    scatter_stage: how the global partition levels store their groups (0 =
+    by chunk size, 1 = staged, 2 = direct); the stream is the same."""
     n, dims, _ = _shape(pos, layout)
     c = Compressor(n, dims, pos.dtype, leaf_size, eb_mode, layout, tile, want_perm, pos.device,
-                   ref_rule, ref_mode)
+                   ref_rule, ref_mode, scatter_stage)
     s = c(pos.contiguous(), eb, stream).clone()
     if want_perm:
         return s, c.perm[:n].clone()

@@ -137,6 +137,7 @@ static bbx_status check_compress_args(uint64_t n, uint32_t dims, bbx_dtype dtype
     return fail(BBX_EINVAL, "tile_override must be 0, 256 or 512");
   if (prm->ref_rule > 1) return fail(BBX_EINVAL, "ref_rule must be 0 or 1");
   if (prm->ref_mode > 1) return fail(BBX_EINVAL, "ref_mode must be 0 or 1");
+  if (prm->scatter_stage > 2) return fail(BBX_EINVAL, "scatter_stage must be 0, 1 or 2");
   if (dims != 2 && dims != 3) return fail(BBX_EUNSUPPORTED, "dims must be 2 or 3");
   if (n >= (1ull << 32)) return fail(BBX_EUNSUPPORTED, "n must be below 2^32");
   return BBX_OK;
@@ -185,6 +186,7 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
     return (uint32_t)std::min<double>((double)kLevelBlocks, std::max(1.0, std::floor(share + 0.5)));
   };
   std::vector<uint64_t> mm(nsets), qz(nsets), tl(nsets), bg(nsets), pm(nsets), pp(nsets);
+  std::vector<uint8_t> stage_seen(kMaxDepth, 0);  // a set with global level k seen
   std::vector<std::vector<uint64_t>> lv(nsets), nd(nsets);
   for (uint32_t s = 0; s < nsets; ++s) {
     const SetIn& I = in[s];
@@ -252,6 +254,12 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
         else
           bp->lv_global[k] = 1;
         if (kind == kLevelGlobal && sh.chunks > 256) bp->sel_wide[k] = 1;
+        if (kind == kLevelGlobal) {  // by default staged only when every set's chunks are large
+          const uint32_t mode = in[0].prm.scatter_stage;
+          if (!stage_seen[k]) bp->scat_stage[k] = mode != 2;
+          stage_seen[k] = 1;
+          if (mode == 0 && sh.chunk_elems < kStageChunk) bp->scat_stage[k] = 0;
+        }
         lv[s].push_back(sh.nodes * sh.chunks);
         nd[s].push_back(sh.nodes);
         if (kind == kLevelGlobal) {  // only these use selections and rows
@@ -365,6 +373,8 @@ static bbx_status check_batch(const SetIn* in, uint32_t nsets) {
     bbx_status st = check_set(in[s]);
     if (st != BBX_OK) return fail(st, "set " + std::to_string(s) + ": " + g_err);
     if (in[s].prm.tile_override != tile) return fail(BBX_EINVAL, "all sets of a batch share one tile_override");
+    if (in[s].prm.scatter_stage != in[0].prm.scatter_stage)
+      return fail(BBX_EINVAL, "all sets of a batch share one scatter_stage");
   }
   return BBX_OK;
 }

@@ -24,6 +24,7 @@ constexpr int kRows = 8;                  // rows of kBlock elements per streami
 constexpr int kGroup = kRows * kBlock;    // elements per streaming group
 constexpr uint64_t kLevelBlocks = 4096;   // blocks per global level of a set alone
 constexpr uint64_t kLocalBlocks = 4096;   // levels of at least this many nodes run block-local
+constexpr uint32_t kStageChunk = 16384;   // the global scatter stages groups from this chunk size
 // a block-local level is one chunk per node under every block target
 static_assert(kLevelBlocks <= kLocalBlocks, "block-local levels must have one chunk per node");
 
@@ -390,6 +391,7 @@ struct BatchPlan {
   uint8_t lv_local[kMaxDepth];   // some set handles level k one block per node
   uint8_t lv_global[kMaxDepth];  // some set handles level k with global histograms
   uint8_t sel_wide[kMaxDepth];   // some set's nodes have > 256 chunks at global level k
+  uint8_t scat_stage[kMaxDepth]; // every set's chunks at global level k hold >= kStageChunk codes
   uint8_t lv_wave[kMaxDepth];    // some set handles level k one wavefront per node
   uint8_t lv_fused[kMaxDepth];   // some set handles levels k, k + 1 fused, a wavefront per node
   uint8_t lv_fused4[kMaxDepth];  // some set handles levels k, k + 1 fused, a block per node

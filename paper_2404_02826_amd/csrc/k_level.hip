@@ -816,8 +816,11 @@ __device__ void scatter_body(uint32_t depth, const SetDesc& S, DevParams* P, con
   }
 }
 
-// TRACK: some set of the batch carries source indices (loaded with the codes)
-template <bool TRACK>
+// TRACK: some set of the batch carries source indices (loaded with the codes).
+// STAGE: groups are staged in LDS before the stores (levels whose chunks hold
+// many groups; with one or two groups per block the extra barrier and LDS
+// round trip cost more than the coalesced stores save).
+template <bool TRACK, bool STAGE>
 __global__ void __launch_bounds__(kBlock) k_scatter(uint32_t depth, uint32_t nsets,
                                                     const uint64_t* pre, const SetDesc* sets,
                                                     DevParams* params, const NodeSel* sel0,
@@ -830,16 +833,16 @@ __global__ void __launch_bounds__(kBlock) k_scatter(uint32_t depth, uint32_t nse
   if (P->status != BBX_OK) return;
   if (level_is_local(S.n, depth)) return;
   __shared__ uint32_t lhist[2 * kBlock];
-  __shared__ uint32_t stg[(TRACK ? 4 : 3) * kGroup];  // one staged group (codes, indices)
+  __shared__ uint32_t stg[STAGE ? (TRACK ? 4 : 3) * kGroup : 1];  // one staged group (codes, indices)
   const uint32_t* isrc = S.track ? isrc0 + S.idx_off : nullptr;
   uint32_t* idst = S.track ? idst0 + S.idx_off : nullptr;
   const NodeSel ns = (sel0 + S.sel_off)[c.lb / c.sh.chunks];
   const uint32_t* cb = cb0 + S.cb_off + c.lb * 2;
   if (P->key16)
-    scatter_body<uint16_t, TRACK, true>(depth, S, P, c, ns.v, ns.jeq, cb[0], cb[1], src0 + S.key_off,
+    scatter_body<uint16_t, TRACK, STAGE>(depth, S, P, c, ns.v, ns.jeq, cb[0], cb[1], src0 + S.key_off,
                                         dst0 + S.key_off, isrc, idst, hist0 + S.hist_off, lhist, stg);
   else
-    scatter_body<uint32_t, TRACK, true>(depth, S, P, c, ns.v, ns.jeq, cb[0], cb[1], src0 + S.key_off,
+    scatter_body<uint32_t, TRACK, STAGE>(depth, S, P, c, ns.v, ns.jeq, cb[0], cb[1], src0 + S.key_off,
                                         dst0 + S.key_off, isrc, idst, hist0 + S.hist_off, lhist, stg);
 }
 
@@ -1503,9 +1506,11 @@ hipError_t launch_levels(const BatchPlan& bp, const Ws& w, hipStream_t s) {
     else
       BBX_LAUNCH("level_select_last", k_select_last, sel_grid(bp.g_nd[k]), kBlock, 0, s, k,
                  bp.nsets, pnd, w.sets, w.params, w.sel, w.hist, w.rows, w.chunk_base);
-    BBX_LAUNCH("level_scatter", bp.track ? k_scatter<true> : k_scatter<false>, bp.g_lv[k], kBlock,
-               0, s, k, bp.nsets, plv, w.sets, w.params, w.sel, w.chunk_base, w.keys[cur],
-               w.keys[cur ^ 1], w.idx[cur], w.idx[cur ^ 1], w.hist);
+    BBX_LAUNCH("level_scatter",
+               (bp.track ? (bp.scat_stage[k] ? k_scatter<true, true> : k_scatter<true, false>)
+                         : (bp.scat_stage[k] ? k_scatter<false, true> : k_scatter<false, false>)),
+               bp.g_lv[k], kBlock, 0, s, k, bp.nsets, plv, w.sets, w.params, w.sel, w.chunk_base,
+               w.keys[cur], w.keys[cur ^ 1], w.idx[cur], w.idx[cur ^ 1], w.hist);
   }
   return hipGetLastError();
 }

@@ -231,6 +231,7 @@ extern "C" bbx_status bbx_server_submit_compress(bbx_server* s, const void* d_po
   if (!s || !job || !params) return bbx::set_error(BBX_EINVAL, "server: NULL argument");
   bbx_params p = *params;
   p.tile_override = s->cfg.tile_override;  // one tile per launch
+  p.scatter_stage = 0;                     // the library's choice: jobs of a launch share it
   const size_t ws = bbx_compress_workspace_size(n, dims, dtype, &p);
   if (ws == 0) return bbx_compress(d_pos, n, dims, dtype, eb, &p, nullptr, 0, nullptr, nullptr,
                                    nullptr, nullptr, nullptr, 0, nullptr);  // its argument error

@@ -57,7 +57,11 @@ def test_argument_errors_on_host(lib):
         bbx.compress_workspace_size(100, dims=4)
     with pytest.raises(bbx.BitboxError):
         bbx.compress_workspace_size(100, leaf_size=0)
+    with pytest.raises(bbx.BitboxError, match="scatter_stage"):
+        bbx.compress_workspace_size(100, scatter_stage=3)
     assert bbx.compress_workspace_size(100) > 0
+    for stage in (0, 1, 2):  # a tuning choice: the workspace does not depend on it
+        assert bbx.compress_workspace_size(100000, scatter_stage=stage) == bbx.compress_workspace_size(100000)
 
 
 def test_stream_info_parses_oracle_header(lib, oracle):

@@ -56,11 +56,11 @@ def gen(kind, n, dims=3, dtype=np.float32, seed=1):
 
 
 def gpu_roundtrip(bbx, pts, eb, mode, r, layout="aos", tile=0, ref_rule=0, ref_mode=0,
-                  want_perm=True):
+                  want_perm=True, scatter_stage=0):
     host = pts if layout == "aos" else np.ascontiguousarray(pts.T)
     x = torch.from_numpy(host).cuda()
     out = bbx.compress(x, eb, mode, r, layout, want_perm=want_perm, tile=tile, ref_rule=ref_rule,
-                       ref_mode=ref_mode)
+                       ref_mode=ref_mode, scatter_stage=scatter_stage)
     s, perm = out if want_perm else (out, None)
     dec = bbx.decompress(s, layout)
     torch.cuda.synchronize()
@@ -76,12 +76,12 @@ def first_diff(a: bytes, b: bytes):
 
 
 def check_parity(orc, bbx, pts, eb, mode, r, layout="aos", tile=0, ref_rule=0, ref_mode=0,
-                 want_perm=True):
+                 want_perm=True, scatter_stage=0):
     host = pts if layout == "aos" else np.ascontiguousarray(pts.T)
     ref_s, ref_p = orc.compress(host, eb, mode, r, layout=layout, want_perm=True,
                                 ref_rule=ref_rule, ref_mode=ref_mode)
     got_s, got_p, got_d = gpu_roundtrip(bbx, pts, eb, mode, r, layout, tile, ref_rule, ref_mode,
-                                        want_perm)
+                                        want_perm, scatter_stage)
     if got_s != ref_s:
         h = props.parse_header(ref_s)
         mb = 8 * ((h["meta_bits"] + 63) // 64)
@@ -143,6 +143,30 @@ def test_layout_and_tile_invariance(orc, bbx, layout, tile):
     _say("layout", layout, "tile", tile)
     pts = cosmology(70001, seed=5)
     check_parity(orc, bbx, pts, 1e-4, "rel", 32, layout=layout, tile=tile)
+
+
+# sets with levels that use global histograms: both ways of storing a
+# partition group (1 = staged in LDS, 2 = straight from the ranks) give the
+# oracle's bytes, with and without the source indices carried along
+# (generator, n, dims, dtype, eb, mode, r, want_perm, ref_mode)
+STAGE_CASES = [
+    ("cosmology", 300007, 3, np.float32, 1e-4, "rel", 32, False, 0),
+    ("ties", 300007, 3, np.float32, 1e-3, "rel", 32, True, 0),
+    ("cosmology", 150001, 3, np.float32, 1e-7, "rel", 32, False, 0),   # u32 codes
+    ("cosmology", 100003, 2, np.float32, 1e-4, "rel", 100, True, 0),
+    ("uniform", 100003, 3, np.float64, 1e-5, "abs", 16, False, 1),
+    ("fluid", 262144, 3, np.float32, 1e-4, "rel", 32, False, 0),
+]
+
+
+@pytest.mark.parametrize("stage", [1, 2])
+@pytest.mark.parametrize("case", STAGE_CASES, ids=lambda c: f"{c[0]}-n{c[1]}-d{c[2]}-perm{int(c[7])}-m{c[8]}")
+def test_scatter_stage_invariance(orc, bbx, case, stage):
+    kind, n, dims, dt, eb, mode, r, want_perm, ref_mode = case
+    _say("scatter stage", stage, case)
+    pts = gen(kind, n, dims, dt, seed=n % 83 + 7)
+    check_parity(orc, bbx, pts, eb, mode, r, want_perm=want_perm, ref_mode=ref_mode,
+                 scatter_stage=stage)
 
 
 RULE1_CASES = [
@@ -329,6 +353,9 @@ def test_decompress_oracle_streams(orc, bbx):
 
 def test_full_size_cosmology_1_in_4_oracle(orc, bbx):
     """A quarter of the cosmology workload (2^22 particles, xi = 1e-4), full
-    byte parity with the oracle."""
+    byte parity with the oracle, once with the library's choice of group
+    stores and once with every global level staged (the choice of the
+    full-size sets, whose chunks hold 16,384 codes or more)."""
     pts = cosmology(1 << 22, seed=2)
     check_parity(orc, bbx, pts, 1e-4, "rel", 32)
+    check_parity(orc, bbx, pts, 1e-4, "rel", 32, want_perm=False, scatter_stage=1)
