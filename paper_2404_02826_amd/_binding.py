@@ -287,7 +287,7 @@ class BatchCompressor:
     recorded in a HIP graph and replayed while the upload stays valid).
     """
 
-    def __init__(self, sets, tile: int = 0, device="cuda"):
+    def __init__(self, sets, tile: int = 0, device="cuda", scatter_stage: int = 0):
         lib = load()
         self._lib = lib
         self.nsets = len(sets)
@@ -323,7 +323,7 @@ class BatchCompressor:
             S.d_pos = pos.data_ptr() if n else None
             S.n, S.dims, S.dtype, S.eb = n, dims, _dtype_code(pos), float(spec["eb"])
             S.params = _params(spec.get("leaf_size", 32), spec.get("eb_mode", "rel"), lay, tile,
-                               spec.get("ref_rule", 0), spec.get("ref_mode", 0))
+                               spec.get("ref_rule", 0), spec.get("ref_mode", 0), scatter_stage)
             S.d_out = base + offs[i]
             S.out_cap = caps[i]
             S.d_size = self.d_size.data_ptr() + 8 * i

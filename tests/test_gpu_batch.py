@@ -90,6 +90,18 @@ def test_batch_mixed_sets_match_oracle(orc, bbx, tile):
         _check_set(orc, host, spec, res[i], bc.perms[i], f"set {i} {MIX[i]}")
 
 
+@pytest.mark.parametrize("stage", [1, 2])
+def test_batch_scatter_stage_invariance(orc, bbx, stage):
+    """Forcing either way of storing the global partition's groups for the
+    whole batch leaves every set's stream equal to the oracle's."""
+    hosts, specs = _specs(MIX, seed0=60)
+    _say(f"batch of {len(specs)} mixed sets, scatter_stage {stage}")
+    bc = bbx.BatchCompressor(specs, scatter_stage=stage)
+    res = bc()
+    for i, (host, spec) in enumerate(zip(hosts, specs)):
+        _check_set(orc, host, spec, res[i], bc.perms[i], f"set {i} {MIX[i]} stage {stage}")
+
+
 def test_batch_equals_single_calls(bbx):
     hosts, specs = _specs(MIX[3:8], seed0=40)
     res = bbx.BatchCompressor(specs)()
