@@ -25,6 +25,11 @@
  * brute-force re-derivation on tiny inputs, closed forms (Eq. 1-3), the error
  * bound, and mutation tests that build this file with -DBBXO_MUTANT=k to
  * plant one plausible mistake k and check that some pin catches it.
+ *
+ * Parity unpinned (readings, checked only against the brute-force
+ * restatement): the direction of the sequence reordering in
+ * bbxo_export_sequences_reordered (ascending sum of widths) and the value of
+ * the 32-bit end mark of the exported sequence layout (all ones).
  */
 #include <math.h>
 #include <stdlib.h>
@@ -195,7 +200,11 @@ static int range_and_bound(const void* pos, int layout, params_t* p) {
   if (p->dtype == 0) {
     int e = 0;
     (void)frexp(amax, &e); /* amax = f * 2^e, f in [1/2, 1): f32 ulp is 2^(e-24) */
+#if MUT(18)
+    double half_ulp = ldexp(1.0, e - 24); /* a whole ulp */
+#else
     double half_ulp = ldexp(1.0, e - 25);
+#endif
     if (half_ulp < ldexp(1.0, -150)) half_ulp = ldexp(1.0, -150);
     guard = guard + half_ulp;
   }
@@ -892,13 +901,16 @@ int bbxo_export_sequences(const uint8_t* s, uint64_t size, uint8_t* out, uint64_
 
 /* The two reorderings of Sec. 4.2 before entropy coding, applied to the
  * sequence layout: sequences in ascending sum_d m_d (ties in stored order),
- * and inside each sequence the members in ascending R-index, the
- * concatenation of their codes with the axes taken in ascending entropy of
- * the widths m_d over all sequences (ties to the lower axis; the lowest
- * entropy is the most significant part), ties in stored order.  Entropy is
- * -sum p log2 p over the empirical distribution of m_d; compared exactly as
- * counts: H_a < H_b iff sum c log c (over a's counts) > the same for b, the
- * number of sequences being common. */
+ * and inside each sequence the members in ascending R-index (ties in stored
+ * order).  Two steps, each exported on its own so that it can be checked
+ * against the paper's example:
+ *   bbxo_axis_order_by_entropy: the axes in ascending entropy of the
+ *     empirical distribution of their widths m_d over all sequences (the
+ *     paper's example: m_x uniform on 2..4, m_y uniform on 2..9 and m_z
+ *     single-peaked on 2..9 give the order (x, z, y));
+ *   bbxo_r_index: a member's codes concatenated in that axis order, the
+ *     first axis the most significant part (the paper's example: codes
+ *     (01, 100111, 01010) in the order (x, z, y) give 0101010100111). */
 typedef struct {
   uint64_t key; /* sum of widths */
   uint64_t idx;
@@ -908,17 +920,74 @@ static int cmp_seq(const void* a, const void* b) {
   if (x->key != y->key) return x->key < y->key ? -1 : 1;
   return x->idx < y->idx ? -1 : (x->idx > y->idx);
 }
+
+/* Entropy -sum p log2 p of each axis' widths, compared exactly as counts:
+ * with N sequences in common, H_a < H_b iff sum c log2 c over a's counts
+ * exceeds the same sum for b.  Ties keep the lower axis first. */
+void bbxo_axis_order_by_entropy(const uint32_t* widths, uint64_t nseq, uint32_t dims,
+                                uint32_t* order) {
+  uint64_t cnt[3][65];
+  memset(cnt, 0, sizeof(cnt));
+  for (uint64_t i = 0; i < nseq; i++)
+    for (uint32_t d = 0; d < dims; d++) cnt[d][widths[(uint64_t)dims * i + d] & 63]++;
+  double sclog[3] = {0, 0, 0};
+  for (uint32_t d = 0; d < dims; d++)
+    for (int w = 0; w < 65; w++)
+      if (cnt[d][w]) sclog[d] += (double)cnt[d][w] * log2((double)cnt[d][w]);
+  uint32_t ord[3] = {0, 1, 2};
+  /* insertion sort on ascending entropy (descending sum c log2 c), stable */
+  for (uint32_t b = 1; b < dims; b++)
+    for (uint32_t a = b; a > 0; a--) {
+#if MUT(19)
+      int before = sclog[ord[a]] < sclog[ord[a - 1]]; /* descending entropy */
+#else
+      int before = sclog[ord[a]] > sclog[ord[a - 1]];
+#endif
+      if (!before) break;
+      uint32_t t = ord[a];
+      ord[a] = ord[a - 1];
+      ord[a - 1] = t;
+    }
+  for (uint32_t d = 0; d < dims; d++) order[d] = ord[d];
+}
+
+/* R-index of one member: codes u[d] of m[d] bits concatenated with the axes
+ * in the given order, the first axis most significant.  At most 3 * 31 bits:
+ * the high 64 bits go to *hi, the low 64 bits are returned. */
+uint64_t bbxo_r_index(const uint64_t* u, const uint32_t* m, uint32_t dims, const uint32_t* order,
+                      uint64_t* hi) {
+  uint64_t h = 0, l = 0;
+  for (uint32_t k = 0; k < dims; k++) {
+#if MUT(20)
+    uint32_t d = order[dims - 1 - k]; /* most significant part last */
+#else
+    uint32_t d = order[k];
+#endif
+    uint32_t w = m[d];
+    uint64_t v = w ? (u[d] & (w >= 64 ? ~0ull : ((1ull << w) - 1))) : 0;
+    /* (h, l) <<= w, then or in v */
+    if (w >= 64) {
+      h = l;
+      l = 0;
+    } else if (w > 0) {
+      h = (h << w) | (l >> (64 - w));
+      l <<= w;
+    }
+    l |= v;
+  }
+  if (hi) *hi = h;
+  return l;
+}
+
 typedef struct {
+  uint64_t hi, lo; /* R-index */
   uint64_t u[3];
   uint32_t pos;
 } memkey_t;
-static uint32_t g_order[3];
 static int cmp_mem(const void* a, const void* b) {
   const memkey_t *x = (const memkey_t*)a, *y = (const memkey_t*)b;
-  for (int k = 0; k < 3; k++) {
-    uint32_t d = g_order[k];
-    if (x->u[d] != y->u[d]) return x->u[d] < y->u[d] ? -1 : 1;
-  }
+  if (x->hi != y->hi) return x->hi < y->hi ? -1 : 1;
+  if (x->lo != y->lo) return x->lo < y->lo ? -1 : 1;
   return x->pos < y->pos ? -1 : (x->pos > y->pos);
 }
 
@@ -946,41 +1015,35 @@ int bbxo_export_sequences_reordered(const uint8_t* s, uint64_t size, uint8_t* ou
   uint32_t* wid = (uint32_t*)malloc((size_t)(nl ? nl : 1) * 3 * sizeof(uint32_t));
   seqkey_t* seq = (seqkey_t*)malloc((size_t)(nl ? nl : 1) * sizeof(seqkey_t));
   memkey_t* mem = (memkey_t*)malloc((size_t)(r + 1) * sizeof(memkey_t));
-  uint64_t cnt[3][65];
   if (!sizes || !start || !wid || !seq || !mem) {
     free(plain), free(sizes), free(start), free(wid), free(seq), free(mem);
     return BBXO_ENOMEM;
   }
   uint64_t k = 0;
   if (n) size_leaves(n, r, sizes, &k, nl);
-  memset(cnt, 0, sizeof(cnt));
   uint64_t pos = 0;
   for (uint64_t i = 0; i < nl; i++) {
     uint32_t sm = 0;
     start[i] = pos;
     for (uint32_t d = 0; d < dims; d++) {
       wid[3 * i + d] = (uint32_t)get_bits(plain, pos + dims * M + d * mbits, mbits);
-      cnt[d][wid[3 * i + d]]++;
       sm += wid[3 * i + d];
     }
     seq[i].key = sm;
     seq[i].idx = i;
     pos += dims * (M + mbits) + (uint64_t)(sizes[i] - 1) * sm + 32;
   }
-  /* axes in ascending entropy of their widths: larger sum c log2 c first */
-  double ent[3] = {0, 0, 0};
-  for (uint32_t d = 0; d < dims; d++)
-    for (int w = 0; w < 65; w++)
-      if (cnt[d][w]) ent[d] += (double)cnt[d][w] * log2((double)cnt[d][w]);
+  /* the axis order of the R-index, from every sequence's widths */
+  uint32_t* wd = (uint32_t*)malloc((size_t)(nl ? nl : 1) * dims * sizeof(uint32_t));
+  if (!wd) {
+    free(plain), free(sizes), free(start), free(wid), free(seq), free(mem);
+    return BBXO_ENOMEM;
+  }
+  for (uint64_t i = 0; i < nl; i++)
+    for (uint32_t d = 0; d < dims; d++) wd[(uint64_t)dims * i + d] = wid[3 * i + d];
   uint32_t ord[3] = {0, 1, 2};
-  for (uint32_t a = 0; a < dims; a++)
-    for (uint32_t b = a + 1; b < dims; b++)
-      if (ent[ord[b]] > ent[ord[a]]) { uint32_t t = ord[a]; ord[a] = ord[b]; ord[b] = t; }
-  for (uint32_t b = 1; b < dims; b++) /* stable: equal entropy keeps axis order */
-    for (uint32_t a = b; a > 0 && ent[ord[a]] == ent[ord[a - 1]] && ord[a] < ord[a - 1]; a--) {
-      uint32_t t = ord[a]; ord[a] = ord[a - 1]; ord[a - 1] = t;
-    }
-  for (int d = 0; d < 3; d++) g_order[d] = d < (int)dims ? ord[d] : (uint32_t)d;
+  bbxo_axis_order_by_entropy(wd, nl, dims, ord);
+  free(wd);
   if (axis_order)
     for (uint32_t d = 0; d < dims; d++) axis_order[d] = ord[d];
   qsort(seq, (size_t)nl, sizeof(seqkey_t), cmp_seq);
@@ -1006,6 +1069,7 @@ int bbxo_export_sequences_reordered(const uint8_t* s, uint64_t size, uint8_t* ou
         }
       }
     }
+    for (uint32_t j = 0; j < cntm; j++) mem[j].lo = bbxo_r_index(mem[j].u, m, dims, ord, &mem[j].hi);
     qsort(mem, cntm, sizeof(memkey_t), cmp_mem);
     for (uint32_t j = 0; j < cntm; j++)
       for (uint32_t d = 0; d < dims; d++) put_bits(out, op, mem[j].u[d], m[d]), op += m[d];

@@ -97,6 +97,17 @@ int bbxo_export_sequences(const uint8_t* stream, uint64_t size, uint8_t* out, ui
 int bbxo_export_sequences_reordered(const uint8_t* stream, uint64_t size, uint8_t* out,
                                     uint64_t out_cap, uint64_t* out_size, uint32_t* axis_order);
 
+/* The two steps of the R-index reordering of Sec. 4.2, on their own.
+ * bbxo_axis_order_by_entropy: widths [nseq][dims] (m_d of every sequence) ->
+ * order[dims], the axes in ascending entropy of their width distributions
+ * (ties: lower axis first).  bbxo_r_index: the codes u[d] (m[d] bits each)
+ * of one member concatenated in that order, first axis most significant;
+ * returns the low 64 bits and writes the high 64 bits to *hi (may be NULL). */
+void bbxo_axis_order_by_entropy(const uint32_t* widths, uint64_t nseq, uint32_t dims,
+                                uint32_t* order);
+uint64_t bbxo_r_index(const uint64_t* u, const uint32_t* m, uint32_t dims, const uint32_t* order,
+                      uint64_t* hi);
+
 /* Number of leaves of the size-only recursion for n particles, capacity r. */
 uint64_t bbxo_leaf_count(uint64_t n, uint32_t r);
 

@@ -67,6 +67,10 @@ class Oracle:
         lib.bbxo_leaf_count.argtypes = [u64, u32]
         lib.bbxo_bits_for_offset.restype = u32
         lib.bbxo_bits_for_offset.argtypes = [u64]
+        lib.bbxo_axis_order_by_entropy.restype = None
+        lib.bbxo_axis_order_by_entropy.argtypes = [vp, u64, u32, vp]
+        lib.bbxo_r_index.restype = u64
+        lib.bbxo_r_index.argtypes = [vp, vp, u32, vp, C.POINTER(u64)]
         self.lib = lib
 
     # -- helpers ---------------------------------------------------------
@@ -91,6 +95,28 @@ class Oracle:
 
     def bits_for_offset(self, D: int) -> int:
         return int(self.lib.bbxo_bits_for_offset(D))
+
+    def axis_order_by_entropy(self, widths) -> list:
+        """Axes in ascending entropy of their width distributions (Sec. 4.2);
+        widths is [nseq][dims]."""
+        w = np.ascontiguousarray(np.asarray(widths, dtype=np.uint32))
+        dims = int(w.shape[1])
+        order = np.zeros(3, dtype=np.uint32)
+        self.lib.bbxo_axis_order_by_entropy(w.ctypes.data if w.size else None, int(w.shape[0]),
+                                            dims, order.ctypes.data)
+        return [int(v) for v in order[:dims]]
+
+    def r_index(self, codes, widths, order) -> int:
+        """R-index of one member (Sec. 4.2): its codes concatenated in the
+        given axis order, first axis most significant."""
+        dims = len(codes)
+        u = np.zeros(3, dtype=np.uint64)
+        m = np.zeros(3, dtype=np.uint32)
+        o = np.zeros(3, dtype=np.uint32)
+        u[:dims], m[:dims], o[:dims] = codes, widths, order
+        hi = C.c_uint64(0)
+        lo = self.lib.bbxo_r_index(u.ctypes.data, m.ctypes.data, dims, o.ctypes.data, C.byref(hi))
+        return (int(hi.value) << 64) | int(lo)
 
     # -- API ---------------------------------------------------------------
     def compress(self, pos: np.ndarray, eb: float, eb_mode: str = "rel", r: int = 32,

@@ -37,6 +37,58 @@ def pin_worked_example(orc):
         assert int(sum(st["leaf_m"][0])) == g["bits_per_particle"]
         assert int(st["leaf_bits"][0]) == (len(pts) - 1) * g["bits_per_particle"]
         assert 3 * max(g["m"]) == g["bits_per_particle_shared_width"]
+        # the codes themselves: FP64 input in bins of 2*eps; FP32 input in
+        # bins narrowed by half an FP32 ulp at the largest magnitude
+        want = g["codes_f32"] if dt == np.float32 else g["codes_f64"]
+        assert st["q"].tolist() == want, (dt, st["q"].tolist())
+
+
+def pin_guard_size(orc):
+    """The rounding guard of FP32 input lies between zero and half an FP32 ulp
+    at the largest magnitude plus FP64 slack: eb_abs - eb_eff is positive and
+    at most ulp_f32(A)/2 + A * 2^-47, A = max|x| + eb_abs (so the bins shrink
+    by a relative 6e-5 at most on the benchmark's bounds)."""
+    rng = np.random.default_rng(5)
+    for scale in (1.0, 30.0, 512.0, 1e5):
+        pts = (rng.random((300, 3)) * scale).astype(np.float32)
+        st = orc.stages(pts, 1e-4, "rel", r=32)
+        A = float(np.abs(pts.astype(np.float64)).max()) + st["eb_abs"]
+        half_ulp = float(np.spacing(np.float32(A))) / 2
+        shrink = st["eb_abs"] - st["eb_eff"]
+        assert shrink > 0, scale
+        assert shrink <= half_ulp + A * 2.0 ** -47, (scale, shrink, half_ulp)
+
+
+def r_index_case():
+    with open(os.path.join(GOLDEN, "r_index_example.json")) as f:
+        return json.load(f)
+
+
+def pin_r_index(orc):
+    """Sec. 4.2 R-index example: codes (01, 100111, 01010) for (x, y, z) in the
+    axis order (x, z, y) give 0101010100111; and width distributions like the
+    paper's (x uniform on 2..4, y uniform on 2..9, z single-peaked on 2..9)
+    order the axes (x, z, y) by ascending entropy."""
+    g = r_index_case()
+    axes = "xyz"
+    codes = [int(g["codes"][a], 2) for a in axes]
+    widths = [len(g["codes"][a]) for a in axes]
+    assert orc.r_index(codes, widths, g["axis_order"]) == int(g["r_index"], 2)
+    cols = []
+    for a in axes:
+        col = []
+        for w, c in sorted(g["width_counts"][a].items(), key=lambda t: int(t[0])):
+            col += [int(w)] * c
+        cols.append(col)
+    assert len(set(map(len, cols))) == 1
+    wid = np.array(cols, dtype=np.uint32).T.copy()
+    # the axis order does not depend on the order of the sequences
+    rng = np.random.default_rng(3)
+    for _ in range(3):
+        assert orc.axis_order_by_entropy(wid) == g["axis_order"]
+        wid = wid[rng.permutation(len(wid))]
+        for d in range(3):
+            wid[:, d] = wid[rng.permutation(len(wid)), d]
 
 
 def tiny_cases(seed: int, count: int):
@@ -118,7 +170,8 @@ def pin_lossless_reference(orc, seed=13, count=30):
 def run_battery(orc):
     """Returns the names of the pins that fail."""
     failed = []
-    for name, fn in (("worked_example", pin_worked_example), ("brute_force", pin_brute_force),
+    for name, fn in (("worked_example", pin_worked_example), ("guard_size", pin_guard_size),
+                     ("r_index", pin_r_index), ("brute_force", pin_brute_force),
                      ("properties", pin_properties), ("lossless_reference", pin_lossless_reference)):
         try:
             fn(orc)

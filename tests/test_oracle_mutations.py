@@ -31,6 +31,9 @@ MUTANTS = {
     15: "relative bound scaled by the smallest range instead of the largest",
     16: "lossless reference field holds the leaf's first member, not its reference",
     17: "lossless reference decoded to its bin centre instead of its stored value",
+    18: "rounding guard of a whole FP32 ulp instead of half of one",
+    19: "R-index axes in descending instead of ascending entropy",
+    20: "R-index with the first axis least significant",
 }
 
 
