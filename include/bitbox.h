@@ -98,7 +98,11 @@ typedef enum { BBX_AOS = 0, BBX_SOA = 1 } bbx_layout;         /* [n][dims] or [d
  * written with coalesced stores, 2 = stored straight from the ranks, 0 = the
  * library's choice by the level's chunk size (staged from 16,384 members per
  * block); like tile_override it never changes the stream, and all sets of a
- * batch share it. */
+ * batch share it.  level_blocks caps the number of blocks that each of the
+ * set's partition levels with global histograms is cut into (0 = the
+ * library's choice: 4,096 for a set alone, the set's share by particle count
+ * in a batch; otherwise 1..4096, the smaller of this and that choice); fewer
+ * blocks mean longer chunks per block.  It never changes the stream. */
 typedef struct {
   uint32_t leaf_size;     /* r >= 1 */
   uint32_t eb_mode;       /* bbx_eb_mode */
@@ -107,6 +111,7 @@ typedef struct {
   uint32_t ref_rule;      /* 0 (AABB centre) or 1 (fewest code bits) */
   uint32_t ref_mode;      /* 0 (reference code) or 1 (reference coordinates) */
   uint32_t scatter_stage; /* 0 (by chunk size), 1 (always) or 2 (never) */
+  uint32_t level_blocks;  /* 0 (library's choice) or 1..4096 */
 } bbx_params;
 
 /* Worst-case stream size in bytes for n particles of the given type, with
@@ -141,6 +146,25 @@ bbx_status bbx_compress(const void* d_pos, uint64_t n, uint32_t dims, bbx_dtype 
                         const bbx_params* params, void* d_out, size_t out_cap,
                         size_t* h_out_size, uint64_t* d_size, uint32_t* d_status,
                         uint32_t* d_perm, void* d_ws, size_t ws_size, hipStream_t stream);
+
+/*
+ * bbx_compress without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  The workspace is a static device array
+ * of bbx_compress_static_limit() bytes (64 MiB) per device, allocated when
+ * the library is loaded and held until the process ends; the call itself
+ * allocates nothing.  A set whose bbx_compress_workspace_size() exceeds the
+ * limit (about 1.97 million 3-D FP32 particles) returns BBX_ENOMEM before any
+ * launch.  Every call on one device shares that device's array: calls that
+ * overlap on one device (several host threads or streams) race and must be
+ * serialised by the caller.  Arguments and results are those of
+ * bbx_compress.
+ */
+size_t bbx_compress_static_limit(void);
+bbx_status bbx_compress_static(const void* d_pos, uint64_t n, uint32_t dims, bbx_dtype dtype,
+                               double eb, const bbx_params* params, void* d_out, size_t out_cap,
+                               size_t* h_out_size, uint64_t* d_size, uint32_t* d_status,
+                               uint32_t* d_perm, hipStream_t stream);
 
 /*
  * Batched compression: many independent particle sets in one launch sequence
@@ -184,6 +208,16 @@ bbx_status bbx_batch_launch(const bbx_set* sets, uint32_t nsets, void* d_ws, siz
 /* bbx_batch_upload followed by bbx_batch_launch; never waits. */
 bbx_status bbx_compress_batch(const bbx_set* sets, uint32_t nsets, void* d_ws, size_t ws_size,
                               hipStream_t stream);
+
+/* Host-only self-check of the launch plan of a batch (no device access; the
+ * sets' pointers are not read): plans the sets as bbx_compress_batch would
+ * and checks what the partition kernels assume of the plan (level kinds in
+ * order; chunks of whole streaming groups that cover every node; one chunk
+ * per node on block-local levels; enough chunk rows, node selections and
+ * radix bins for every level; fused pairs and the leaf stage within their
+ * node capacities).  BBX_OK, or BBX_EHIP with bbx_last_error() naming the
+ * set, level and check; BBX_EINVAL for invalid arguments. */
+bbx_status bbx_plan_check(const bbx_set* sets, uint32_t nsets);
 
 /* Parses and validates a stream header (host copy of its first 128 bytes). */
 bbx_status bbx_stream_info(const void* h_header, size_t header_bytes, uint64_t* n,

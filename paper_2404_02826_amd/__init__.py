@@ -20,12 +20,15 @@ from ._binding import (  # noqa: F401
     Server,
     compress,
     compress_bound,
+    compress_static,
+    compress_static_limit,
     compress_workspace_size,
     decompress,
     decompress_workspace_size,
     export_sequences,
     lib_path,
     load,
+    plan_check,
     profile,
     stream_info,
 )

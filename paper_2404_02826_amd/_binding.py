@@ -29,7 +29,7 @@ class BitboxError(RuntimeError):
 class _Params(C.Structure):
     _fields_ = [("leaf_size", C.c_uint32), ("eb_mode", C.c_uint32), ("layout", C.c_uint32),
                 ("tile_override", C.c_uint32), ("ref_rule", C.c_uint32), ("ref_mode", C.c_uint32),
-                ("scatter_stage", C.c_uint32)]
+                ("scatter_stage", C.c_uint32), ("level_blocks", C.c_uint32)]
 
 
 class _Set(C.Structure):
@@ -75,6 +75,13 @@ def load():
                                  C.POINTER(sz), vp, vp, vp, vp, sz, vp]
     lib.bbx_batch_workspace_size.restype = sz
     lib.bbx_batch_workspace_size.argtypes = [C.POINTER(_Set), u32]
+    lib.bbx_compress_static_limit.restype = sz
+    lib.bbx_compress_static_limit.argtypes = []
+    lib.bbx_compress_static.restype = i32
+    lib.bbx_compress_static.argtypes = [vp, u64, u32, i32, dbl, C.POINTER(_Params), vp, sz,
+                                        C.POINTER(sz), vp, vp, vp, vp]
+    lib.bbx_plan_check.restype = i32
+    lib.bbx_plan_check.argtypes = [C.POINTER(_Set), u32]
     for nm in ("bbx_batch_upload", "bbx_batch_launch", "bbx_compress_batch"):
         f = getattr(lib, nm)
         f.restype = i32
@@ -167,9 +174,9 @@ def _shape(pos: torch.Tensor, layout: str):
 
 
 def _params(leaf_size: int, eb_mode: str, layout: int, tile: int, ref_rule: int = 0,
-            ref_mode: int = 0, scatter_stage: int = 0) -> _Params:
+            ref_mode: int = 0, scatter_stage: int = 0, level_blocks: int = 0) -> _Params:
     return _Params(leaf_size, REL if eb_mode == "rel" else ABS, layout, tile, ref_rule, ref_mode,
-                   scatter_stage)
+                   scatter_stage, level_blocks)
 
 
 def compress_bound(n: int, dims: int = 3, dtype=torch.float32, ref_mode: int = 0) -> int:
@@ -181,9 +188,10 @@ def compress_bound(n: int, dims: int = 3, dtype=torch.float32, ref_mode: int = 0
 
 def compress_workspace_size(n: int, dims: int = 3, dtype=torch.float32, leaf_size: int = 32,
                             eb_mode: str = "rel", layout: str = "aos", tile: int = 0,
-                            ref_rule: int = 0, ref_mode: int = 0, scatter_stage: int = 0) -> int:
+                            ref_rule: int = 0, ref_mode: int = 0, scatter_stage: int = 0,
+                            level_blocks: int = 0) -> int:
     p = _params(leaf_size, eb_mode, AOS if layout == "aos" else SOA, tile, ref_rule, ref_mode,
-                scatter_stage)
+                scatter_stage, level_blocks)
     code = F32 if dtype == torch.float32 else F64
     lib = load()
     v = int(lib.bbx_compress_workspace_size(n, dims, code, C.byref(p)))
@@ -205,14 +213,15 @@ class Compressor:
 
     def __init__(self, n: int, dims: int = 3, dtype=torch.float32, leaf_size: int = 32,
                  eb_mode: str = "rel", layout: str = "aos", tile: int = 0, want_perm: bool = False,
-                 device="cuda", ref_rule: int = 0, ref_mode: int = 0, scatter_stage: int = 0):
+                 device="cuda", ref_rule: int = 0, ref_mode: int = 0, scatter_stage: int = 0,
+                 level_blocks: int = 0):
         self.n, self.dims, self.dtype = n, dims, dtype
         self.layout = layout
         self.params = _params(leaf_size, eb_mode, AOS if layout == "aos" else SOA, tile, ref_rule,
-                              ref_mode, scatter_stage)
+                              ref_mode, scatter_stage, level_blocks)
         lib = load()
         self.ws_size = compress_workspace_size(n, dims, dtype, leaf_size, eb_mode, layout, tile,
-                                               ref_rule, ref_mode, scatter_stage)
+                                               ref_rule, ref_mode, scatter_stage, level_blocks)
         self.ws = torch.empty(self.ws_size, dtype=torch.uint8, device=device)
         self.cap = compress_bound(n, dims, dtype, ref_mode)
         self.out = torch.empty((self.cap + 7) // 8 * 8, dtype=torch.uint8, device=device)
@@ -323,7 +332,8 @@ class BatchCompressor:
             S.d_pos = pos.data_ptr() if n else None
             S.n, S.dims, S.dtype, S.eb = n, dims, _dtype_code(pos), float(spec["eb"])
             S.params = _params(spec.get("leaf_size", 32), spec.get("eb_mode", "rel"), lay, tile,
-                               spec.get("ref_rule", 0), spec.get("ref_mode", 0), scatter_stage)
+                               spec.get("ref_rule", 0), spec.get("ref_mode", 0), scatter_stage,
+                               spec.get("level_blocks", 0))
             S.d_out = base + offs[i]
             S.out_cap = caps[i]
             S.d_size = self.d_size.data_ptr() + 8 * i
@@ -511,23 +521,69 @@ def stream_info(header: bytes) -> dict:
                 n_leaves=nl.value, stream_bytes=sb.value)
 
 
+def compress_static(pos: torch.Tensor, eb: float, out: torch.Tensor, eb_mode: str = "rel",
+                    leaf_size: int = 32, layout: str = "aos", perm: torch.Tensor | None = None,
+                    stream=None) -> int:
+    """bbx_compress_static: compress into the caller's ``out`` (uint8 device
+    tensor) with the library's static per-device workspace (no device
+    allocation by the library or here).  Waits once and returns the stream
+    length."""
+    n, dims, lay = _shape(pos, layout)
+    if not pos.is_cuda or not pos.is_contiguous() or out.dtype != torch.uint8:
+        raise ValueError("positions must be a contiguous device tensor, out a uint8 device tensor")
+    p = _params(leaf_size, eb_mode, lay, 0)
+    size = C.c_size_t(0)
+    _check(load().bbx_compress_static(
+        pos.data_ptr() if n else None, n, dims, _dtype_code(pos), float(eb), C.byref(p),
+        out.data_ptr(), out.numel(), C.byref(size), None, None,
+        perm.data_ptr() if perm is not None else None, _stream_ptr(stream)))
+    return size.value
+
+
+def compress_static_limit() -> int:
+    return int(load().bbx_compress_static_limit())
+
+
+def plan_check(sets) -> None:
+    """Host-only check of a batch's launch plan (no GPU needed).  ``sets`` is
+    a list of dicts with ``n`` and optionally ``dims``, ``dtype`` (0 f32, 1
+    f64), ``eb``, ``leaf_size``, ``tile``, ``scatter_stage``,
+    ``level_blocks``, ``want_perm``, ``ref_mode``; raises BitboxError naming
+    the failing check."""
+    arr = (_Set * max(len(sets), 1))()
+    for i, spec in enumerate(sets):
+        S = arr[i]
+        S.d_pos = None
+        S.n, S.dims = int(spec["n"]), int(spec.get("dims", 3))
+        S.dtype, S.eb = int(spec.get("dtype", F32)), float(spec.get("eb", 1e-4))
+        S.params = _params(spec.get("leaf_size", 32), spec.get("eb_mode", "rel"), AOS,
+                           spec.get("tile", 0), spec.get("ref_rule", 0), spec.get("ref_mode", 0),
+                           spec.get("scatter_stage", 0), spec.get("level_blocks", 0))
+        S.d_out, S.out_cap, S.d_size, S.d_status = None, 0, None, None
+        S.d_perm = 8 if spec.get("want_perm") else None  # planned, never read
+    _check(load().bbx_plan_check(arr, len(sets)))
+
+
 def decompress_workspace_size(header: bytes) -> int:
     return int(load().bbx_decompress_workspace_size(bytes(header[:128]), 128))
 
 
 def compress(pos: torch.Tensor, eb: float, eb_mode: str = "rel", leaf_size: int = 32,
              layout: str = "aos", want_perm: bool = False, tile: int = 0, stream=None,
-             ref_rule: int = 0, ref_mode: int = 0, scatter_stage: int = 0):
+             ref_rule: int = 0, ref_mode: int = 0, scatter_stage: int = 0,
+             level_blocks: int = 0):
     """One-shot compress of a device tensor; returns the stream as a uint8
     device tensor (and the int32 source index of every output slot).
     ref_rule: 0 = leaf reference nearest the AABB centre (the paper's rule),
     1 = the member with the fewest code bits.  ref_mode: 0 = the reference
     stored as its codes, 1 = as its original coordinates (decoded exactly).
     scatter_stage: how the global partition levels store their groups (0 =
-    by chunk size, 1 = staged, 2 = direct); the stream is the same."""
+    by chunk size, 1 = staged, 2 = direct); level_blocks: cap on the blocks
+    per global partition level (0 = the library's choice); neither changes
+    the stream."""
     n, dims, _ = _shape(pos, layout)
     c = Compressor(n, dims, pos.dtype, leaf_size, eb_mode, layout, tile, want_perm, pos.device,
-                   ref_rule, ref_mode, scatter_stage)
+                   ref_rule, ref_mode, scatter_stage, level_blocks)
     s = c(pos.contiguous(), eb, stream).clone()
     if want_perm:
         return s, c.perm[:n].clone()

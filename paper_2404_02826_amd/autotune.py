@@ -63,6 +63,7 @@ class Tuned:
     stream_bytes: dict[int, int] = field(default_factory=dict)  # total per candidate r
     tile_ms: dict[int, float] = field(default_factory=dict)
     tuned_bytes: int = 0
+    per_set_bytes: dict[int, list[int]] = field(default_factory=dict)  # [r][set], -1 failed
 
 
 def tune(specs, leaf_candidates=DEFAULT_LEAF_CANDIDATES, tiles=DEFAULT_TILES, reps: int = 3,
@@ -116,4 +117,4 @@ def tune(specs, leaf_candidates=DEFAULT_LEAF_CANDIDATES, tiles=DEFAULT_TILES, re
     tuned_bytes = sum(sizes[leaf[i]][i] for i in range(len(base)) if sizes[leaf[i]][i] >= 0)
     return Tuned(leaf_sizes=leaf, tile=pick_tile(times),
                  stream_bytes={r: sum(v for v in sizes[r] if v >= 0) for r in sizes},
-                 tile_ms=times, tuned_bytes=tuned_bytes)
+                 tile_ms=times, tuned_bytes=tuned_bytes, per_set_bytes=sizes)

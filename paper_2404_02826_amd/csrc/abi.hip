@@ -138,6 +138,7 @@ static bbx_status check_compress_args(uint64_t n, uint32_t dims, bbx_dtype dtype
   if (prm->ref_rule > 1) return fail(BBX_EINVAL, "ref_rule must be 0 or 1");
   if (prm->ref_mode > 1) return fail(BBX_EINVAL, "ref_mode must be 0 or 1");
   if (prm->scatter_stage > 2) return fail(BBX_EINVAL, "scatter_stage must be 0, 1 or 2");
+  if (prm->level_blocks > kLevelBlocks) return fail(BBX_EINVAL, "level_blocks must be 0..4096");
   if (dims != 2 && dims != 3) return fail(BBX_EUNSUPPORTED, "dims must be 2 or 3");
   if (n >= (1ull << 32)) return fail(BBX_EUNSUPPORTED, "n must be below 2^32");
   return BBX_OK;
@@ -180,10 +181,13 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
   // batch each set's share of 4 * kLevelBlocks by particle count
   uint64_t n_total = 0;
   for (uint32_t s = 0; s < nsets; ++s) n_total += in[s].n;
-  auto level_blocks = [&](uint64_t n) -> uint32_t {
-    if (nsets == 1 || n_total == 0) return (uint32_t)kLevelBlocks;
-    const double share = 4.0 * (double)kLevelBlocks * (double)n / (double)n_total;
-    return (uint32_t)std::min<double>((double)kLevelBlocks, std::max(1.0, std::floor(share + 0.5)));
+  auto level_blocks = [&](uint64_t n, uint32_t cap) -> uint32_t {
+    uint32_t b = (uint32_t)kLevelBlocks;
+    if (nsets > 1 && n_total > 0) {
+      const double share = 4.0 * (double)kLevelBlocks * (double)n / (double)n_total;
+      b = (uint32_t)std::min<double>((double)kLevelBlocks, std::max(1.0, std::floor(share + 0.5)));
+    }
+    return cap ? std::min(b, cap) : b;
   };
   std::vector<uint64_t> mm(nsets), qz(nsets), tl(nsets), bg(nsets), pm(nsets), pp(nsets);
   std::vector<uint8_t> stage_seen(kMaxDepth, 0);  // a set with global level k seen
@@ -212,7 +216,7 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
     D.mbits = I.dtype == BBX_F32 ? 5u : 6u;
     const uint64_t n = I.n;
     if (n > 0) {
-      D.level_blocks = level_blocks(n);
+      D.level_blocks = level_blocks(n, I.prm.level_blocks);
       D.geom = make_geom(n, D.r);
       D.n_leaves = D.geom.L[0][0];
       if (D.r < bp->tile) {
@@ -379,6 +383,81 @@ static bbx_status check_batch(const SetIn* in, uint32_t nsets) {
   return BBX_OK;
 }
 
+// Host-side check of a batch plan against what the kernels assume of it
+// (bbx_plan_check).  Returns an empty string when every check holds.
+static std::string check_plan(const SetIn* in, uint32_t nsets) {
+  BatchPlan bp;
+  std::vector<SetDesc> descs;
+  std::vector<uint64_t> pre;
+  WsLayout lay;
+  plan_batch(in, nsets, &bp, &descs, &pre, &lay);
+  auto where = [](uint32_t s, uint32_t k) {
+    return "set " + std::to_string(s) + " level " + std::to_string(k) + ": ";
+  };
+  const uint64_t rows_total = (lay.cb - lay.rows) / (4 * kRowStride);
+  for (uint32_t s = 0; s < nsets; ++s) {
+    const SetDesc& D = descs[s];
+    const uint64_t n = D.n;
+    if (n == 0) continue;
+    if (D.level_blocks < 1 || D.level_blocks > kLevelBlocks) return where(s, 0) + "block target out of range";
+    const uint64_t next_rows = s + 1 < nsets && descs[s + 1].n ? descs[s + 1].rows_off / kRowStride
+                                                               : rows_total;
+    const uint64_t rows_cap = next_rows - D.rows_off / kRowStride;
+    const uint64_t bin_nodes = D.hist_half / kHistBins;
+    int prev_kind = kLevelGlobal;
+    uint64_t sel_need = 0;
+    for (uint32_t k = 0; k < D.gl; ++k) {
+      const int kind = level_kind(n, k);
+      const LevelShape sh = level_shape(n, k, D.level_blocks);
+      const uint64_t maxsz = (n + (1ull << k) - 1) >> k;
+      if (kind < prev_kind) return where(s, k) + "level kinds are not global, then block, then wavefront";
+      prev_kind = kind;
+      if (sh.nodes != (1ull << k)) return where(s, k) + "node count";
+      const bool fused = k - D.fuse_depth < 2u || k - D.fuse_depth4 < 2u;
+      if (fused) {
+        const uint32_t f = k - D.fuse_depth < 2u ? D.fuse_depth : D.fuse_depth4;
+        const uint64_t cap = f == D.fuse_depth ? kFuseNode : 4 * kFuseNode;
+        if (f + 1 >= D.gl) return where(s, k) + "fused pair reaches the leaf stage";
+        if (((n + (1ull << f) - 1) >> f) > cap) return where(s, k) + "fused node above its capacity";
+        if (kind != kLevelWave) return where(s, k) + "fused level is not a wavefront level";
+        if (D.fuse_depth != kNoFuse && D.fuse_depth4 != kNoFuse && D.fuse_depth4 + 2 > D.fuse_depth)
+          return where(s, k) + "fused pairs overlap";
+        continue;
+      }
+      if (kind == kLevelWave) {
+        if (maxsz > kWaveNode) return where(s, k) + "wavefront node above its capacity";
+        continue;
+      }
+      // block-local and global levels count radix bins of their nodes
+      if (sh.nodes > bin_nodes) return where(s, k) + "radix bins too few";
+      if (kind == kLevelBlock) {
+        if (sh.chunks != 1) return where(s, k) + "block-local level with more than one chunk per node";
+        if (level_shape(n, k, kLocalBlocks).chunks != 1) return where(s, k) + "block-local kind";
+        continue;
+      }
+      if (sh.chunk_elems == 0 || sh.chunk_elems % kGroup) return where(s, k) + "chunk not whole groups";
+      if (sh.chunks * (uint64_t)sh.chunk_elems < maxsz) return where(s, k) + "chunks do not cover the node";
+      if ((sh.chunks - 1) * (uint64_t)sh.chunk_elems >= maxsz) return where(s, k) + "empty chunk in the largest node";
+      if (sh.nodes * sh.chunks > rows_cap) return where(s, k) + "chunk rows too few";
+      if (bp.pre_entries == 0 || pre[bp.o_lv[k] + s + 1] - pre[bp.o_lv[k] + s] != sh.nodes * sh.chunks)
+        return where(s, k) + "grid share differs from the level shape";
+      if (sh.chunks > 256 && !bp.sel_wide[k]) return where(s, k) + "wide select not launched";
+      if (bp.scat_stage[k] && in[0].prm.scatter_stage == 0 && sh.chunk_elems < kStageChunk)
+        return where(s, k) + "staged scatter on short chunks";
+      sel_need = std::max(sel_need, sh.nodes);
+    }
+    const uint64_t next_sel = s + 1 < nsets && descs[s + 1].n ? descs[s + 1].sel_off
+                                                              : (lay.rows - lay.sel) / sizeof(NodeSel);
+    if (sel_need > next_sel - D.sel_off) return where(s, D.gl) + "node selections too few";
+    // the leaf stage below the partition levels
+    const uint64_t leafsz = (n + (1ull << D.gl) - 1) >> D.gl;
+    if (D.tile_mode ? leafsz > bp.tile : leafsz > D.r) return where(s, D.gl) + "leaf stage node too large";
+    if (D.gl > 0 && ((n + (1ull << (D.gl - 1)) - 1) >> (D.gl - 1)) <= (D.tile_mode ? bp.tile : D.r))
+      return where(s, D.gl) + "a partition level above the leaf stage is not needed";
+  }
+  return std::string();
+}
+
 // A small descriptor blob travels as a kernel argument: no host-to-device
 // copy, so the host never waits for the stream and the upload can be
 // recorded in a graph.
@@ -527,9 +606,10 @@ static size_t carve_decompress(const HostHeader& h, uint8_t* base, DecompressWs*
   return c.off;
 }
 
-static DecompressPlan plan_of(const HostHeader& h, uint32_t layout) {
+static DecompressPlan plan_of(const HostHeader& h, const void* raw, uint32_t layout) {
   DecompressPlan p;
   memset(&p, 0, sizeof(p));
+  memcpy(p.header.w, raw, kHeaderBytes);
   p.n = h.n;
   p.n_leaves = h.n_leaves;
   p.meta_bits = h.meta_bits;
@@ -630,6 +710,8 @@ bbx_status bbx_compress(const void* d_pos, uint64_t n, uint32_t dims, bbx_dtype 
                         : hp.status == BBX_EBOUND ? "error bound too small for the input type or 30-bit codes"
                         : hp.status == BBX_ENOSPC ? "out_cap smaller than the stream"
                                                   : "device error";
+      if (hp.status == BBX_EHIP && hp.diag)
+        return fail(BBX_EHIP, "device consistency check " + std::to_string(hp.diag) + " failed");
       return fail((bbx_status)hp.status, why);
     }
     *h_out_size = (size_t)hp.total_bytes;
@@ -696,6 +778,18 @@ bbx_status bbx_compress_batch(const bbx_set* sets, uint32_t nsets, void* d_ws, s
   return bbx_batch_launch(sets, nsets, d_ws, ws_size, stream);
 }
 
+bbx_status bbx_plan_check(const bbx_set* sets, uint32_t nsets) {
+  std::vector<SetIn> v;
+  if (!sets_from_abi(sets, nsets, &v) || nsets == 0) return fail(BBX_EINVAL, "sets is NULL or empty");
+  for (uint32_t s = 0; s < nsets; ++s) {
+    bbx_status st = check_compress_args(v[s].n, v[s].dims, v[s].dtype, v[s].eb, &v[s].prm);
+    if (st != BBX_OK) return fail(st, "set " + std::to_string(s) + ": " + g_err);
+  }
+  const std::string why = check_plan(v.data(), nsets);
+  if (!why.empty()) return fail(BBX_EHIP, "launch plan: " + why);
+  return BBX_OK;
+}
+
 bbx_status bbx_stream_info(const void* h_header, size_t header_bytes, uint64_t* n, uint32_t* dims,
                            bbx_dtype* dtype, double* eb_abs, uint32_t* leaf_size,
                            uint64_t* n_leaves, uint64_t* stream_bytes) {
@@ -743,7 +837,7 @@ bbx_status bbx_decompress(const void* d_stream, size_t stream_size, const void* 
   memset(&w, 0, sizeof(w));
   const size_t need = carve_decompress(h, (uint8_t*)d_ws, &w);
   if (ws_size < need) return fail(BBX_ENOMEM, "workspace too small: need " + std::to_string(need));
-  const DecompressPlan p = plan_of(h, layout);
+  const DecompressPlan p = plan_of(h, h_header, layout);
   hipError_t e = launch_decompress(p, w, (const uint8_t*)d_stream, d_pos, d_status, stream);
   if (e != hipSuccess) return fail(BBX_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
   if (!d_status) {
@@ -787,7 +881,7 @@ bbx_status bbx_export_sequences(const void* d_stream, size_t stream_size, const 
   memset(&w, 0, sizeof(w));
   const size_t need = carve_decompress(h, (uint8_t*)d_ws, &w);
   if (ws_size < need) return fail(BBX_ENOMEM, "workspace too small: need " + std::to_string(need));
-  const DecompressPlan p = plan_of(h, BBX_AOS);
+  const DecompressPlan p = plan_of(h, h_header, BBX_AOS);
   hipError_t e = launch_export(p, w, (const uint8_t*)d_stream, d_out, d_status, stream);
   if (e != hipSuccess) return fail(BBX_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
   if (!d_status) {

@@ -36,7 +36,7 @@ struct DevParams {
   uint32_t G[3];        // bits of the largest code per axis
   uint32_t key16;       // 1 when every code fits 16 bits
   uint32_t status;      // bbx_status of the set so far
-  uint32_t pad0;
+  uint32_t diag;        // first internal consistency check that failed (Check), 0 if none
   uint64_t meta_bits, payload_bits, total_bytes;
   uint64_t payload_base;  // global payload-bit offset of the set's first leaf
   uint64_t pad1[3];
@@ -127,6 +127,28 @@ struct Ws {
 };
 
 // ---------------------------------------------------------------- device helpers
+
+// Internal consistency checks of the partition and leaf kernels.  None can
+// fail on a correct build; a failing one sets the set's status to BBX_EHIP
+// and records which check failed first (DevParams::diag), which the host
+// reports in bbx_last_error.
+enum Check : uint32_t {
+  kChkLastDigit = 1,    // a node's last-digit bins hold fewer members than the median's rank
+  kChkLastDigitWide = 2,
+  kChkScatterStore = 3, // a member's slot falls outside its node
+  kChkScatterStage = 4, // a member's staged slot falls outside its group
+  kChkScatterDrain = 5,
+  kChkStageIdx = 6,     // staged partition without carried indices
+  kChkWavePart = 7,
+  kChkFusedIdx = 8,
+  kChkFusedPart = 9,
+  kChkTileLeaves = 10,  // leaf count of a tile differs from the tree geometry
+  kChkTileRange = 11,
+};
+__device__ inline void check_failed(DevParams* P, uint32_t which) {
+  atomicCAS(&P->diag, 0u, which);
+  P->status = BBX_EHIP;
+}
 
 __host__ __device__ inline uint32_t bitlen32(uint32_t v) { return v ? 32u - (uint32_t)__builtin_clz(v) : 0u; }
 
@@ -398,7 +420,15 @@ struct BatchPlan {
   uint64_t pre_entries;       // total u64 entries of the prefix buffer
 };
 
+// The 128 header bytes the host planned a decode from; the decoder's first
+// kernel compares them with the stream's own header (a mismatch makes the
+// stream corrupt).
+struct HeaderCopy {
+  uint64_t w[kHeaderBytes / 8];
+};
+
 struct DecompressPlan {
+  HeaderCopy header;
   uint64_t n, n_leaves, meta_bits, payload_bits;
   uint32_t dims, dtype, r, mbits, layout, ref_mode;
   uint32_t G[3];

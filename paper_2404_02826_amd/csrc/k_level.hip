@@ -402,7 +402,7 @@ __global__ void __launch_bounds__(kBlock) k_select_last(uint32_t depth, uint32_t
     uint32_t* chunk_base = cb0 + S.cb_off + j * chunks * 2;
     uint32_t b, jeq;
     if (!last_digit_of(hist, 1u << L.w, L.rank, &b, &jeq)) {
-      if (lane == 0) L.P->status = BBX_EHIP;
+      if (lane == 0) check_failed(L.P, kChkLastDigit);
       continue;
     }
     if (lane == 0) {
@@ -479,7 +479,7 @@ __global__ void __launch_bounds__(kBlock) k_select_last_wide(uint32_t depth, uin
           ns.jeq = jeq;
           sel0[S.sel_off + j] = ns;
         } else {
-          L.P->status = BBX_EHIP;
+          check_failed(L.P, kChkLastDigitWide);
         }
         bx[0] = ok ? 1u : 0u;
         bx[1] = b;
@@ -612,7 +612,7 @@ __device__ __forceinline__ void scatter_store(uint32_t g, uint32_t end, const ui
         atomicAdd(&lhist[(left ? 0u : (uint32_t)kBlock) + (((NA > 1 ? k[1][i] : k[0][i]) >> shn) & maskn)],
                   1u);
     } else {
-      P->status = BBX_EHIP;  // inconsistent counts: never expected
+      check_failed(P, kChkScatterStore);
     }
   }
 }
@@ -652,7 +652,7 @@ __device__ __forceinline__ void scatter_stage(uint32_t g, uint32_t end, const ui
         atomicAdd(&lhist[(left ? 0u : (uint32_t)kBlock) + (((NA > 1 ? k[1][i] : k[0][i]) >> shn) & maskn)],
                   1u);
     } else {
-      P->status = BBX_EHIP;  // inconsistent counts: never expected
+      check_failed(P, kChkScatterStage);
     }
   }
 }
@@ -675,7 +675,7 @@ __device__ __forceinline__ void scatter_drain(uint32_t g, uint32_t gsz, uint32_t
       if (NA > 2) B2[dest] = (KT)stg[2 * kGroup + t];
       if (TRACK && id) id[dest] = stg[3 * kGroup + t];
     } else {
-      P->status = BBX_EHIP;  // inconsistent counts: never expected
+      check_failed(P, kChkScatterDrain);
     }
   }
 }
@@ -769,7 +769,7 @@ __device__ void scatter_body(uint32_t depth, const SetDesc& S, DevParams* P, con
   const uint32_t* is = isrc ? isrc + st : nullptr;
   uint32_t* id = idst ? idst + st : nullptr;
   if (STAGE && !TRACK && is) {  // the staged path carries indices only with TRACK
-    if (threadIdx.x == 0) P->status = BBX_EHIP;
+    if (threadIdx.x == 0) check_failed(P, kChkStageIdx);
     return;
   }
   if (sz <= r) {  // leaf: copy through
@@ -1099,7 +1099,7 @@ __device__ __forceinline__ void wave_part_rows(uint32_t base, uint32_t sz, const
         else if (!TRACK && is)
           id[dest] = is[p];
       } else {
-        P->status = BBX_EHIP;  // inconsistent counts: never expected
+        check_failed(P, kChkWavePart);
       }
     }
     lt_run += (uint32_t)__popcll(mlt);
@@ -1322,7 +1322,7 @@ __device__ void level_fused_body(uint32_t depth, const SetDesc& S, DevParams* P,
   uint64_t st, sz64;
   node_span(S.n, depth, j, &st, &sz64);
   if (sz64 > (uint64_t)W * kFuseNode || sz64 <= S.r) {  // launch plan violated: never expected
-    if (threadIdx.x == 0) P->status = BBX_EHIP;
+    if (threadIdx.x == 0) check_failed(P, kChkFusedIdx);
     return;
   }
   const uint32_t s = (uint32_t)sz64;
@@ -1417,7 +1417,7 @@ __device__ void level_fused_body(uint32_t depth, const SetDesc& S, DevParams* P,
         X2[dest] = (KT)q2[i];
         if (TRACK && I) I[dest] = ix[i];
       } else {
-        P->status = BBX_EHIP;  // inconsistent counts: never expected
+        check_failed(P, kChkFusedPart);
       }
     }
     cLL += popc64(bLL);

@@ -8,10 +8,13 @@
 //   k_set_sizes     per set: payload and meta bits, stream size, capacity check
 //   k_pack_meta     one thread per 64-bit meta word: gathers the fixed-stride
 //                   leaf records (widths, reference codes) that overlap it
-//   k_pack_payload  one thread per 64-bit payload word: finds the leaf holding
-//                   the word's first bit and gathers the member codes
-//                   q - q_ref + 2^(m-1) that overlap it, so every word is
-//                   written once with a plain store (no atomics, no zeroing)
+//   k_pack_payload  leaf-aligned blocks: each block owns the payload words
+//                   that start inside its leaves, ORs every member code
+//                   q - q_ref + 2^(m-1) into an LDS copy of those words (LDS
+//                   atomics; 8 consecutive members per thread), completes its
+//                   last word from the next leaves, then writes every owned
+//                   word once with a coalesced plain store (no global
+//                   atomics, no zeroing of the output)
 //   k_header        the 128-byte header
 //   k_finish        reports size and status
 #include "bbx_internal.h"

@@ -165,7 +165,7 @@ __global__ void __launch_bounds__(kBlock) k_epilogue(const SetDesc* sets, const 
   p.eb_abs = p.eb_eff = p.w = p.inv_w = 0.0;
   p.key16 = 1;
   p.status = BBX_OK;
-  p.pad0 = 0;
+  p.diag = 0;
   p.meta_bits = p.payload_bits = p.total_bytes = p.payload_base = 0;
   for (int k = 0; k < 3; ++k) p.pad1[k] = 0;
   if (n == 0) {

@@ -209,7 +209,7 @@ __device__ void tile_bitboxes(WaveTile<TILE, KL, TRACK>& sm, int cur, uint32_t n
         leaves[lid] = rec;
         leaf_bits[lid] = (uint64_t)(lz - 1) * summ;
       } else {
-        P->status = BBX_EHIP;  // leaf count mismatch: never expected
+        check_failed(P, kChkTileLeaves);  // leaf count mismatch: never expected
       }
     }
   }
@@ -229,7 +229,7 @@ __device__ void tile_body(WaveTile<TILE, KL, TRACK>& sm, uint64_t j, uint32_t K0
   uint64_t tst, s0_64;
   node_span(n, K0, j, &tst, &s0_64);
   if (s0_64 > (uint64_t)TILE) {  // launch plan violated: never expected
-    if (lane == 0) P->status = BBX_EHIP;
+    if (lane == 0) check_failed(P, kChkTileRange);
     return;
   }
   const uint32_t s0 = (uint32_t)s0_64;

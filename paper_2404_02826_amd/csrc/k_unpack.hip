@@ -299,9 +299,14 @@ __global__ void __launch_bounds__(kBlock) k_unpack(uint64_t n, uint32_t dims, ui
                       pay_bits, out, P, s_rec, s_off, s_pay);
 }
 
-__global__ void k_dec_init(DevParams* P) {
-  if (threadIdx.x == 0) {
-    P->status = BBX_OK;
+// Starts a decode: clears the status and checks that the stream's own
+// header is the one the launch was planned from (one 8-byte word per lane).
+__global__ void k_dec_init(DevParams* P, const uint8_t* stream, HeaderCopy h) {
+  const uint32_t lane = threadIdx.x;
+  const bool diff = lane < kHeaderBytes / 8 && ((const uint64_t*)stream)[lane] != h.w[lane];
+  const uint64_t any = __ballot(diff);
+  if (lane == 0) {
+    P->status = any ? BBX_ECORRUPT : BBX_OK;
     P->payload_bits = 0;
   }
 }
@@ -336,7 +341,7 @@ __global__ void __launch_bounds__(kBlock) k_dec_refs(uint64_t n, uint64_t n_leav
 
 hipError_t launch_decompress(const DecompressPlan& p, const DecompressWs& w, const uint8_t* stream,
                              void* pos, uint32_t* d_status, hipStream_t s) {
-  BBX_LAUNCH("dec_init", k_dec_init, 1, 64, 0, s, w.params);
+  BBX_LAUNCH("dec_init", k_dec_init, 1, 64, 0, s, w.params, stream, p.header);
   if (p.n > 0) {
     uint64_t g = (p.n_leaves + kBlock - 1) / kBlock;
     if (g > 65536) g = 65536;
@@ -469,7 +474,7 @@ __global__ void __launch_bounds__(kBlock) k_export(uint64_t n_leaves, uint32_t d
 
 hipError_t launch_export(const DecompressPlan& p, const DecompressWs& w, const uint8_t* stream,
                          void* out, uint32_t* d_status, hipStream_t s) {
-  BBX_LAUNCH("dec_init", k_dec_init, 1, 64, 0, s, w.params);
+  BBX_LAUNCH("dec_init", k_dec_init, 1, 64, 0, s, w.params, stream, p.header);
   if (p.n > 0) {
     uint64_t g = (p.n_leaves + kBlock - 1) / kBlock;
     if (g > 65536) g = 65536;

@@ -232,6 +232,7 @@ extern "C" bbx_status bbx_server_submit_compress(bbx_server* s, const void* d_po
   bbx_params p = *params;
   p.tile_override = s->cfg.tile_override;  // one tile per launch
   p.scatter_stage = 0;                     // the library's choice: jobs of a launch share it
+  p.level_blocks = 0;                      // the library's choice (the set's share of the launch)
   const size_t ws = bbx_compress_workspace_size(n, dims, dtype, &p);
   if (ws == 0) return bbx_compress(d_pos, n, dims, dtype, eb, &p, nullptr, 0, nullptr, nullptr,
                                    nullptr, nullptr, nullptr, 0, nullptr);  // its argument error

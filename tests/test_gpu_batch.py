@@ -221,3 +221,41 @@ def test_batch_mixed_reference_modes(orc, bbx):
         assert res[i].cpu().numpy().tobytes() == ref_s, f"set {i} mode {modes[i]}"
         if spec["want_perm"]:
             assert np.array_equal(bc.perms[i][:len(ref[1])].cpu().numpy().astype(np.uint32), ref[1])
+
+
+def test_autotune_picks_smallest_stream(orc, bbx):
+    """The autotuner on a small mixed batch: per set, the chosen leaf size
+    gives the smallest stream among the candidates (ties to the larger r),
+    and the tuned batch equals the oracle at that leaf size at every tile
+    capacity (the tile never changes the bytes)."""
+    from paper_2404_02826_amd import autotune
+    rng = np.random.default_rng(8)
+    arrays, specs = [], []
+    for i in range(12):
+        n = int(10 ** rng.uniform(3, 4.7))
+        pts = (uniform_cube if i % 2 else cosmology)(n, seed=300 + i)
+        eb = 1e-3 if i % 3 else 1e-4
+        arrays.append(pts)
+        specs.append(dict(pos=torch.from_numpy(pts).cuda(), eb=eb))
+    tuned = autotune.tune(specs, leaf_candidates=(8, 16, 32, 64), reps=1)
+    cands = sorted(tuned.per_set_bytes)
+    for i in range(len(specs)):
+        sizes = {r: tuned.per_set_bytes[r][i] for r in cands}
+        best = min(sizes.values())
+        assert sizes[tuned.leaf_sizes[i]] == best, (i, sizes, tuned.leaf_sizes[i])
+        assert tuned.leaf_sizes[i] == max(r for r in cands if sizes[r] == best)
+    assert tuned.tile in (256, 512)
+    for tile in (256, 512):
+        bc = bbx.BatchCompressor([dict(sp, leaf_size=tuned.leaf_sizes[i]) for i, sp in enumerate(specs)],
+                                 tile=tile)
+        bc.upload()
+        bc.launch()
+        torch.cuda.synchronize()
+        assert (bc.d_status.cpu().numpy()[: len(specs)] == 0).all()
+        sz = bc.d_size.cpu().numpy()
+        for i, pts in enumerate(arrays):
+            ref = orc.compress(pts, specs[i]["eb"], "rel", tuned.leaf_sizes[i])
+            got = bc.out[bc.offsets[i]: bc.offsets[i] + int(sz[i])].cpu().numpy().tobytes()
+            assert got == ref, f"tile {tile}, set {i}: stream differs from the oracle's"
+            assert len(ref) == tuned.per_set_bytes[tuned.leaf_sizes[i]][i]
+

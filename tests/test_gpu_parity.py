@@ -56,11 +56,11 @@ def gen(kind, n, dims=3, dtype=np.float32, seed=1):
 
 
 def gpu_roundtrip(bbx, pts, eb, mode, r, layout="aos", tile=0, ref_rule=0, ref_mode=0,
-                  want_perm=True, scatter_stage=0):
+                  want_perm=True, scatter_stage=0, level_blocks=0):
     host = pts if layout == "aos" else np.ascontiguousarray(pts.T)
     x = torch.from_numpy(host).cuda()
     out = bbx.compress(x, eb, mode, r, layout, want_perm=want_perm, tile=tile, ref_rule=ref_rule,
-                       ref_mode=ref_mode, scatter_stage=scatter_stage)
+                       ref_mode=ref_mode, scatter_stage=scatter_stage, level_blocks=level_blocks)
     s, perm = out if want_perm else (out, None)
     dec = bbx.decompress(s, layout)
     torch.cuda.synchronize()
@@ -76,12 +76,12 @@ def first_diff(a: bytes, b: bytes):
 
 
 def check_parity(orc, bbx, pts, eb, mode, r, layout="aos", tile=0, ref_rule=0, ref_mode=0,
-                 want_perm=True, scatter_stage=0):
+                 want_perm=True, scatter_stage=0, level_blocks=0, ref=None):
     host = pts if layout == "aos" else np.ascontiguousarray(pts.T)
-    ref_s, ref_p = orc.compress(host, eb, mode, r, layout=layout, want_perm=True,
-                                ref_rule=ref_rule, ref_mode=ref_mode)
+    ref_s, ref_p = ref if ref is not None else orc.compress(
+        host, eb, mode, r, layout=layout, want_perm=True, ref_rule=ref_rule, ref_mode=ref_mode)
     got_s, got_p, got_d = gpu_roundtrip(bbx, pts, eb, mode, r, layout, tile, ref_rule, ref_mode,
-                                        want_perm, scatter_stage)
+                                        want_perm, scatter_stage, level_blocks)
     if got_s != ref_s:
         h = props.parse_header(ref_s)
         mb = 8 * ((h["meta_bits"] + 63) // 64)
@@ -342,6 +342,26 @@ def test_corrupt_payload_detected_on_device(orc, bbx):
         orc.decompress(bytes(b))
 
 
+def test_decompress_checks_the_callers_header_copy(bbx):
+    """A decode is planned from the caller's host copy of the header; the
+    device compares it with the stream's own header and reports a mismatch
+    as a corrupt stream (the same stream with its own header decodes)."""
+    pts = cosmology(30000, seed=12)
+    s = bbx.compress(torch.from_numpy(pts).cuda(), 1e-3)
+    good = s[:128].cpu().numpy().tobytes()
+    bad = bytearray(good)
+    bad[24] ^= 1  # eb_user: still a valid header, not this stream's
+    d = bbx.Decompressor(bytes(bad))
+    with pytest.raises(bbx.BitboxError) as e:
+        d(s)
+    assert e.value.name == "ECORRUPT"
+    d.d_status.fill_(0)
+    d.launch(s)
+    torch.cuda.synchronize()
+    assert int(d.d_status.item()) == 3  # ECORRUPT in the asynchronous form too
+    assert torch.equal(bbx.Decompressor(good)(s), bbx.decompress(s))
+
+
 def test_decompress_oracle_streams(orc, bbx):
     """The GPU decoder reproduces the oracle's decoder on oracle-written streams."""
     for r in (1, 32, 3000):
@@ -359,3 +379,22 @@ def test_full_size_cosmology_1_in_4_oracle(orc, bbx):
     pts = cosmology(1 << 22, seed=2)
     check_parity(orc, bbx, pts, 1e-4, "rel", 32)
     check_parity(orc, bbx, pts, 1e-4, "rel", 32, want_perm=False, scatter_stage=1)
+
+
+# Few blocks per global level: every block's chunk spans many 2048-member
+# groups (up to the whole node at level_blocks = 1), with a partial last
+# group, so the multi-group loop of the global partition (next-group
+# prefetch, running below/equal counts, the staged group's reuse) is
+# byte-checked at sizes the oracle finishes quickly; the stream must not
+# depend on the chunking.
+@pytest.mark.parametrize("n,kind,xi", [(262461, "cosmology", 1e-4), (1 << 20, "fluid", 1e-4),
+                                       (300007, "ties", 1e-3)])
+def test_multi_group_chunks(orc, bbx, n, kind, xi):
+    pts = gen(kind, n, seed=31)
+    ref = orc.compress(pts, xi, "rel", 32, want_perm=True)
+    for lb in (1, 3, 16, 64):
+        for stage in (1, 2):
+            _say(f"{kind} n={n} level_blocks={lb} scatter_stage={stage}")
+            check_parity(orc, bbx, pts, xi, "rel", 32, scatter_stage=stage, level_blocks=lb,
+                         want_perm=(lb != 3), ref=ref)
+

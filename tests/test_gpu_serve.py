@@ -114,3 +114,38 @@ def test_server_rejects_job_larger_than_budget(bbx):
         srv.submit_compress(x, 1e-3)
     assert e.value.name == "ENOMEM"
     srv.close()
+
+
+def test_launches_overlap_on_the_device(bbx):
+    """Continuous batching keeps several launches in flight: jobs submitted
+    while earlier ones still run start on free streams at once, and a later
+    launch starts before an earlier one has finished."""
+    xs = [torch.from_numpy(cosmology(1 << 21, seed=40 + i)).cuda() for i in range(3)]
+    alone = [bbx.compress(x, 1e-4, "rel", 32) for x in xs]
+    torch.cuda.synchronize()
+    srv = bbx.Server(4 << 30, max_jobs=8, max_batch=1, nstreams=3)
+    ids, inflight = [], 0
+    for x in xs:
+        ids.append(srv.submit_compress(x, 1e-4, "rel", 32))
+        srv.progress()
+        inflight = max(inflight, srv.counts()["inflight"])
+    done = {}
+    t0 = time.perf_counter()
+    while len(done) < len(ids):
+        srv.progress()
+        while True:
+            jid = srv.pop_done()
+            if not jid:
+                break
+            done[jid] = srv.info(jid)
+        assert time.perf_counter() - t0 < 30, "jobs did not finish"
+    _say(f"launches in flight after the submissions: {inflight}")
+    assert inflight >= 2, "no two launches were in flight together"
+    first = done[ids[0]]
+    assert any(done[j]["t_launch"] < first["t_done"] for j in ids[1:]), \
+        "no later launch started before the first one finished"
+    for jid, a in zip(ids, alone):
+        assert torch.equal(srv.result(jid), a)
+        srv.release(jid)
+    srv.close()
+

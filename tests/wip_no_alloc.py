@@ -1,0 +1,59 @@
+"""bbx_compress_static (the workspace in a static per-device array, for
+callers that cannot allocate) against bbx_compress (caller's workspace) and
+the oracle, byte for byte: two calls in a row, the second on a smaller set,
+so the second runs on the memory the first left behind; plus the size limit
+and an argument error reported before any launch."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import Oracle
+from synth import cosmology, uniform_cube
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def test_static_scratch_matches_workspace_path():
+    import paper_2404_02826_amd as bbx
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    orc = Oracle()
+    limit = bbx.compress_static_limit()
+    assert limit == 64 << 20
+    for n, gen, xi, seed in ((1_500_001, cosmology, 1e-4, 21), (70_001, uniform_cube, 1e-3, 22)):
+        _say(f"static-scratch compress of {n} particles")
+        assert bbx.compress_workspace_size(n) <= limit
+        pts = gen(n, seed=seed)
+        x = torch.from_numpy(pts).cuda()
+        out = torch.zeros(bbx.compress_bound(n), dtype=torch.uint8, device="cuda")
+        perm = torch.zeros(n, dtype=torch.int32, device="cuda")
+        size = bbx.compress_static(x, xi, out, perm=perm)
+        ref_s, ref_p = bbx.compress(x, xi, want_perm=True)
+        torch.cuda.synchronize()
+        assert size == ref_s.numel()
+        assert torch.equal(out[:size], ref_s), "static-scratch stream differs from bbx_compress"
+        assert torch.equal(perm, ref_p), "static-scratch perm differs from bbx_compress"
+        o_s, o_p = orc.compress(pts, xi, "rel", 32, want_perm=True)
+        assert out[:size].cpu().numpy().tobytes() == o_s
+        assert np.array_equal(perm.cpu().numpy().astype(np.uint32), o_p)
+
+
+def test_static_scratch_limit_and_errors():
+    import paper_2404_02826_amd as bbx
+    n = 2_500_000  # its workspace exceeds the 64 MiB scratch
+    x = torch.zeros((n, 3), dtype=torch.float32, device="cuda")
+    out = torch.zeros(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(bbx.BitboxError) as e:
+        bbx.compress_static(x, 1e-3, out)
+    assert e.value.name == "ENOMEM"
+    with pytest.raises(bbx.BitboxError) as e:
+        bbx.compress_static(x[:10], -1.0, out)
+    assert e.value.name == "EINVAL"
