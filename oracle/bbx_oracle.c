@@ -680,12 +680,270 @@ int bbxo_stages_ex(const void* pos, uint64_t n, uint32_t dims, int dtype, int la
   return BBXO_OK;
 }
 
+/* ------------------------------------------------------------------ bit box reduction */
+
+/* Sec. 4.1 "Bit box reduction and bit box intersection update", the while
+ * loop of Alg. 1, on the leaves (subregions) of the partition above:
+ *   - a leaf's bit box is its reference's codes c_d and widths m_d; in code
+ *     space it holds exactly the codes q with |q_d - c_d| <= R(m_d), R(m) =
+ *     2^(m-1) - 1 (R(0) = 0): the offsets its widths can encode (Eq. 1/3);
+ *   - repeatedly pop the remaining leaf with the smallest key (key_rule 0:
+ *     the sum of widths sum_d m_d, as the text says; key_rule 1: the sum of
+ *     box lengths sum_d (2^m_d - 1) in bins, as the figure caption says),
+ *     ties to the first leaf in depth-first order;
+ *   - its sequence holds the centre (its reference), its other remaining
+ *     members in ascending index, then the common particles: the remaining
+ *     members of every other remaining leaf whose bit box intersects the
+ *     popped one and that lie inside the popped box, leaf by leaf in
+ *     depth-first order, each leaf's in ascending index;
+ *   - every leaf that lost particles gets its bit box again from what it
+ *     keeps (AABB, member nearest the AABB centre, Eq. 2); a leaf left empty
+ *     vanishes without a sequence.
+ * The loop ends when no particle remains. */
+typedef struct {
+  uint32_t ref;  /* source index of the current reference */
+  uint32_t m[3];
+  uint32_t cnt;  /* remaining members */
+  int live;      /* not popped and not empty */
+} rbox_t;
+
+static uint32_t box_reach(uint32_t m) { return m ? ((1u << (m - 1)) - 1u) : 0u; }
+
+static uint64_t box_key(const rbox_t* b, uint32_t dims, int key_rule) {
+  uint64_t k = 0;
+  for (uint32_t d = 0; d < dims; d++) {
+#if MUT(21)
+    k += key_rule == 0 ? ((1ull << b->m[d]) - 1) : b->m[d];
+#else
+    k += key_rule == 0 ? b->m[d] : ((1ull << b->m[d]) - 1);
+#endif
+  }
+  return k;
+}
+
+static int boxes_meet(const uint32_t* q, uint64_t n, uint32_t dims, const rbox_t* a,
+                      const rbox_t* b) {
+  for (uint32_t d = 0; d < dims; d++) {
+    int64_t ca = q[(uint64_t)d * n + a->ref], cb = q[(uint64_t)d * n + b->ref];
+    int64_t gap = ca > cb ? ca - cb : cb - ca;
+    if (gap > (int64_t)box_reach(a->m[d]) + (int64_t)box_reach(b->m[d])) return 0;
+  }
+  return 1;
+}
+
+static int box_holds(const uint32_t* q, uint64_t n, uint32_t dims, const rbox_t* a, uint32_t i) {
+  for (uint32_t d = 0; d < dims; d++) {
+    int64_t o = (int64_t)q[(uint64_t)d * n + i] - (int64_t)q[(uint64_t)d * n + a->ref];
+    if ((o < 0 ? -o : o) > (int64_t)box_reach(a->m[d])) return 0;
+  }
+  return 1;
+}
+
+typedef struct {
+  uint64_t nseq;
+  uint32_t* seq_center; /* [nseq] source index */
+  uint32_t* seq_m;      /* [nseq][3] */
+  uint32_t* seq_count;  /* [nseq] particles besides the centre */
+  uint32_t* slot_src;   /* [n] source index per output slot */
+} reduced_t;
+
+static void reduced_free(reduced_t* r) {
+  free(r->seq_center);
+  free(r->seq_m);
+  free(r->seq_count);
+  free(r->slot_src);
+  memset(r, 0, sizeof(*r));
+}
+
+static int reduce_boxes(const core_t* c, int key_rule, reduced_t* out) {
+  const uint64_t n = c->p.n, nl = c->nleaves;
+  const uint32_t dims = c->p.dims;
+  memset(out, 0, sizeof(*out));
+  rbox_t* box = (rbox_t*)calloc((size_t)(nl ? nl : 1), sizeof(rbox_t));
+  uint8_t* taken = (uint8_t*)calloc((size_t)(n ? n : 1), 1);
+  uint32_t* mem = (uint32_t*)malloc((size_t)(c->p.r + 1) * sizeof(uint32_t));
+  out->seq_center = (uint32_t*)malloc((size_t)(nl ? nl : 1) * sizeof(uint32_t));
+  out->seq_m = (uint32_t*)malloc((size_t)(nl ? nl : 1) * 3 * sizeof(uint32_t));
+  out->seq_count = (uint32_t*)malloc((size_t)(nl ? nl : 1) * sizeof(uint32_t));
+  out->slot_src = (uint32_t*)malloc((size_t)(n ? n : 1) * sizeof(uint32_t));
+  if (!box || !taken || !mem || !out->seq_center || !out->seq_m || !out->seq_count ||
+      !out->slot_src) {
+    free(box), free(taken), free(mem);
+    reduced_free(out);
+    return BBXO_ENOMEM;
+  }
+  /* the bit boxes of the partition's leaves (Step 4) */
+  for (uint64_t b = 0; b < nl; b++) {
+    box[b].ref = c->order[c->leaf_start[b] + c->leaf_ref[b]];
+    for (int d = 0; d < 3; d++) box[b].m[d] = c->leaf_m[3 * b + d];
+    box[b].cnt = c->leaf_size[b];
+    box[b].live = 1;
+  }
+  uint64_t slot = 0, left = n;
+  while (left > 0) {
+    /* the remaining box with the smallest key, first in leaf order on ties */
+    uint64_t cur = nl;
+    uint64_t best = 0;
+    for (uint64_t b = 0; b < nl; b++) {
+      if (!box[b].live) continue;
+      uint64_t k = box_key(&box[b], dims, key_rule);
+#if MUT(22)
+      if (cur == nl || k <= best) cur = b, best = k;
+#else
+      if (cur == nl || k < best) cur = b, best = k;
+#endif
+    }
+    if (cur == nl) break; /* never: particles remain only in live boxes */
+    rbox_t* B = &box[cur];
+    uint64_t s = out->nseq++;
+    out->seq_center[s] = B->ref;
+    for (int d = 0; d < 3; d++) out->seq_m[3 * s + d] = B->m[d];
+    uint64_t first = slot;
+    out->slot_src[slot++] = B->ref;
+    taken[B->ref] = 1;
+    /* its other remaining members, ascending index */
+    const uint32_t* L = c->order + c->leaf_start[cur];
+    for (uint32_t j = 0; j < c->leaf_size[cur]; j++)
+      if (!taken[L[j]]) {
+        taken[L[j]] = 1;
+        out->slot_src[slot++] = L[j];
+      }
+    /* common particles of the intersecting boxes, leaf by leaf */
+#if MUT(25)
+    for (uint64_t bb = nl; bb-- > 0;) {
+      uint64_t b = bb;
+#else
+    for (uint64_t b = 0; b < nl; b++) {
+#endif
+      if (b == cur || !box[b].live || !boxes_meet(c->q, n, dims, B, &box[b])) continue;
+#if MUT(24)
+      continue;
+#endif
+      const uint32_t* M = c->order + c->leaf_start[b];
+      uint32_t lost = 0, kept = 0;
+      for (uint32_t j = 0; j < c->leaf_size[b]; j++) {
+        uint32_t i = M[j];
+        if (taken[i]) continue;
+        if (box_holds(c->q, n, dims, B, i)) {
+          taken[i] = 1;
+          out->slot_src[slot++] = i;
+          lost++;
+        } else {
+          mem[kept++] = i;
+        }
+      }
+      if (lost == 0) continue;
+      box[b].cnt = kept;
+      if (kept == 0) {
+        box[b].live = 0; /* empty: vanishes */
+        continue;
+      }
+#if !MUT(23)
+      uint32_t ref = 0, m[3];
+      bit_box(c->q, n, dims, mem, kept, 0, &ref, m);
+      box[b].ref = mem[ref];
+      for (int d = 0; d < 3; d++) box[b].m[d] = m[d];
+#endif
+    }
+    out->seq_count[s] = (uint32_t)(slot - first - 1);
+    left -= slot - first;
+    B->live = 0;
+    B->cnt = 0;
+  }
+  free(box), free(taken), free(mem);
+  if (slot != n) {
+    reduced_free(out);
+    return BBXO_ENOMEM; /* internal inconsistency: never expected */
+  }
+  return BBXO_OK;
+}
+
+/* Stream of the reduced sequences (version 2 of the format): the v1 header
+ * with version 2 and the sequence count in the last field; a meta record
+ * per sequence (widths m_d in mbits bits, the centre's codes in G_d bits,
+ * then the number of other particles in 32 bits: the end mark of Sec. 4.2
+ * turned into a count); the payload holds each sequence's particles in
+ * order, per axis q_d - c_d + 2^(m_d - 1) in m_d bits. */
+int bbxo_compress_reduced(const void* pos, uint64_t n, uint32_t dims, int dtype, int layout,
+                          double eb, int eb_mode, uint32_t r, int key_rule, uint8_t* out,
+                          uint64_t out_cap, uint64_t* out_size, uint32_t* perm) {
+  if (key_rule != 0 && key_rule != 1) return BBXO_EINVAL;
+  core_t c;
+  int st = core_run(&c, pos, n, dims, dtype, layout, eb, eb_mode, r, 0, 0);
+  if (st) {
+    core_free(&c);
+    return st;
+  }
+  reduced_t R;
+  memset(&R, 0, sizeof(R));
+  if (n > 0) {
+    st = reduce_boxes(&c, key_rule, &R);
+    if (st) {
+      core_free(&c);
+      return st;
+    }
+  }
+  const params_t* p = &c.p;
+  uint32_t sumG = 0;
+  for (uint32_t d = 0; d < dims; d++) sumG += p->G[d];
+  uint64_t meta_bits = R.nseq * (uint64_t)(dims * p->mbits + sumG + 32), payload_bits = 0;
+  for (uint64_t s = 0; s < R.nseq; s++) {
+    uint32_t sm = 0;
+    for (uint32_t d = 0; d < dims; d++) sm += R.seq_m[3 * s + d];
+    payload_bits += (uint64_t)R.seq_count[s] * sm;
+  }
+  uint64_t mb = words_bytes(meta_bits), pb = words_bytes(payload_bits);
+  uint64_t total = HEADER_BYTES + mb + pb;
+  if (out_size) *out_size = total;
+  if (total > out_cap) {
+    reduced_free(&R);
+    core_free(&c);
+    return BBXO_ENOSPC;
+  }
+  memset(out, 0, (size_t)total);
+  c.meta_bits = meta_bits;
+  c.payload_bits = payload_bits;
+  write_header(out, &c);
+  put_u16le(out + 4, 2);
+  put_u64le(out + 120, R.nseq);
+  uint8_t* meta = out + HEADER_BYTES;
+  uint8_t* pay = meta + mb;
+  uint64_t mpos = 0, ppos = 0, slot = 0;
+  for (uint64_t s = 0; s < R.nseq; s++) {
+    const uint32_t* m = R.seq_m + 3 * s;
+    uint32_t ctr = R.seq_center[s];
+    for (uint32_t d = 0; d < dims; d++) put_bits(meta, mpos, m[d], p->mbits), mpos += p->mbits;
+    for (uint32_t d = 0; d < dims; d++)
+      put_bits(meta, mpos, c.q[(uint64_t)d * n + ctr], p->G[d]), mpos += p->G[d];
+    put_bits(meta, mpos, R.seq_count[s], 32), mpos += 32;
+    slot++; /* the centre */
+    for (uint32_t j = 0; j < R.seq_count[s]; j++, slot++) {
+      uint32_t i = R.slot_src[slot];
+      for (uint32_t d = 0; d < dims; d++) {
+        if (m[d] == 0) continue;
+        int64_t o = (int64_t)c.q[(uint64_t)d * n + i] - (int64_t)c.q[(uint64_t)d * n + ctr];
+        put_bits(pay, ppos, (uint64_t)(o + ((int64_t)1 << (m[d] - 1))), m[d]);
+        ppos += m[d];
+      }
+    }
+  }
+  if (perm && n) memcpy(perm, R.slot_src, (size_t)n * sizeof(uint32_t));
+  reduced_free(&R);
+  core_free(&c);
+  return BBXO_OK;
+}
+
 /* ------------------------------------------------------------------ decompress */
+
+static int decompress_reduced(const uint8_t* s, uint64_t size, void* pos, uint64_t pos_cap_bytes,
+                              int layout);
 
 int bbxo_decompress(const uint8_t* s, uint64_t size, void* pos, uint64_t pos_cap_bytes,
                     int layout) {
   if (layout != 0 && layout != 1) return BBXO_EINVAL;
   if (!s || size < HEADER_BYTES) return BBXO_ECORRUPT;
+  if (get_u32le(s) == MAGIC && get_u16le(s + 4) == 2)
+    return decompress_reduced(s, size, pos, pos_cap_bytes, layout);
   if (get_u32le(s) != MAGIC || get_u16le(s + 4) != 1) return BBXO_ECORRUPT;
   int dtype = s[6];
   uint32_t dims = s[7];
@@ -829,6 +1087,93 @@ int bbxo_decompress(const uint8_t* s, uint64_t size, void* pos, uint64_t pos_cap
   free(sizes);
   free(codes);
   free(rraw);
+  return st;
+}
+
+/* Decoder of the reduced stream (version 2): sequences in stored order; in
+ * each the centre, then its other particles in stored order. */
+static int decompress_reduced(const uint8_t* s, uint64_t size, void* pos, uint64_t pos_cap_bytes,
+                              int layout) {
+  int dtype = s[6];
+  uint32_t dims = s[7];
+  uint64_t n = get_u64le(s + 8);
+  uint32_t r = get_u32le(s + 16);
+  uint32_t eb_mode = s[20], mbits = s[23];
+  if (dtype > 1 || (dims != 2 && dims != 3) || eb_mode > 1 || s[21] != 0 || s[22] != 0)
+    return BBXO_ECORRUPT;
+  if (mbits != (dtype == 0 ? 5u : 6u) || r == 0 || n >= ((uint64_t)1 << 32)) return BBXO_ECORRUPT;
+  double w = get_f64le(s + 48), inv_w = get_f64le(s + 56);
+  double origin[3];
+  uint32_t G[3], sumG = 0;
+  for (uint32_t d = 0; d < 3; d++) {
+    origin[d] = get_f64le(s + 64 + 8 * d);
+    G[d] = s[88 + d];
+    if (d >= dims && (G[d] != 0 || origin[d] != 0.0)) return BBXO_ECORRUPT;
+    if (G[d] > 30 || !isfinite(origin[d])) return BBXO_ECORRUPT;
+    sumG += G[d];
+  }
+  if (!isfinite(w) || w < 0.0 || !isfinite(inv_w) || inv_w < 0.0) return BBXO_ECORRUPT;
+  for (int k = 91; k < 96; k++)
+    if (s[k] != 0) return BBXO_ECORRUPT;
+  uint64_t nl = get_u64le(s + 96), meta_bits = get_u64le(s + 104), payload_bits = get_u64le(s + 112);
+  uint64_t nseq = get_u64le(s + 120);
+  if (nl != bbxo_leaf_count(n, r) || nseq > nl || (n > 0 && nseq == 0)) return BBXO_ECORRUPT;
+  if (meta_bits != nseq * (uint64_t)(dims * mbits + sumG + 32)) return BBXO_ECORRUPT;
+  if (payload_bits > n * (uint64_t)dims * 31u) return BBXO_ECORRUPT;
+  uint64_t mb = words_bytes(meta_bits), pb = words_bytes(payload_bits);
+  if (size < HEADER_BYTES + mb + pb) return BBXO_ECORRUPT;
+  uint64_t esz = dtype == 0 ? 4 : 8;
+  if (pos_cap_bytes < n * dims * esz) return BBXO_ENOSPC;
+  if (n == 0) return BBXO_OK;
+  const uint8_t* meta = s + HEADER_BYTES;
+  const uint8_t* pay = meta + mb;
+  uint32_t* codes = (uint32_t*)malloc((size_t)(n * dims) * sizeof(uint32_t));
+  if (!codes) return BBXO_ENOMEM;
+  int st = BBXO_OK;
+  uint64_t mpos = 0, ppos = 0, slot = 0;
+  for (uint64_t q = 0; q < nseq && st == BBXO_OK; q++) {
+    uint32_t m[3] = {0, 0, 0}, sm = 0;
+    int64_t ctr[3] = {0, 0, 0};
+    for (uint32_t d = 0; d < dims; d++) {
+      m[d] = (uint32_t)get_bits(meta, mpos, mbits);
+      mpos += mbits;
+      if (m[d] == 1 || m[d] > 31 || m[d] > G[d] + 1) st = BBXO_ECORRUPT;
+      sm += m[d];
+    }
+    for (uint32_t d = 0; d < dims; d++) ctr[d] = (int64_t)get_bits(meta, mpos, G[d]), mpos += G[d];
+    uint64_t cnt = get_bits(meta, mpos, 32);
+    mpos += 32;
+    if (st || slot + 1 + cnt > n || ppos + cnt * sm > payload_bits) {
+      st = BBXO_ECORRUPT;
+      break;
+    }
+    for (uint32_t d = 0; d < dims; d++) codes[slot * dims + d] = (uint32_t)ctr[d];
+    slot++;
+    for (uint64_t j = 0; j < cnt && st == BBXO_OK; j++, slot++)
+      for (uint32_t d = 0; d < dims; d++) {
+        int64_t qv = ctr[d];
+        if (m[d] > 0) {
+          uint64_t u = get_bits(pay, ppos, m[d]);
+          ppos += m[d];
+          if (u == 0) st = BBXO_ECORRUPT;
+          qv = ctr[d] + (int64_t)u - ((int64_t)1 << (m[d] - 1));
+        }
+        if (qv < 0 || qv >= ((int64_t)1 << G[d])) st = BBXO_ECORRUPT;
+        codes[slot * dims + d] = (uint32_t)qv;
+      }
+  }
+  if (st == BBXO_OK && (slot != n || ppos != payload_bits)) st = BBXO_ECORRUPT;
+  if (st == BBXO_OK)
+    for (uint64_t i = 0; i < n; i++)
+      for (uint32_t d = 0; d < dims; d++) {
+        double v = origin[d] + (double)codes[i * dims + d] * w;
+        uint64_t kk = (layout == 0) ? i * dims + d : (uint64_t)d * n + i;
+        if (dtype == 0)
+          ((float*)pos)[kk] = (float)v;
+        else
+          ((double*)pos)[kk] = v;
+      }
+  free(codes);
   return st;
 }
 

@@ -57,6 +57,18 @@ int bbxo_compress_ex(const void* pos, uint64_t n, uint32_t dims, int dtype, int 
                      double eb, int eb_mode, uint32_t r, int ref_rule, int ref_mode,
                      uint8_t* out, uint64_t out_cap, uint64_t* out_size, uint32_t* perm);
 
+/* The bit box reduction of Sec. 4.1 (the while loop of Alg. 1) after the
+ * partition and bit boxes above: repeatedly the remaining leaf with the
+ * smallest key (key_rule 0: sum of widths; 1: sum of box lengths), ties to
+ * the first leaf, emits a sequence of its centre, its other remaining
+ * members and every remaining particle of other leaves inside its bit box;
+ * leaves that lose particles get new bit boxes, empty ones vanish.  Writes
+ * a version-2 stream (one meta record per sequence with a 32-bit particle
+ * count); perm as for bbxo_compress.  Reference stored as its codes. */
+int bbxo_compress_reduced(const void* pos, uint64_t n, uint32_t dims, int dtype, int layout,
+                          double eb, int eb_mode, uint32_t r, int key_rule, uint8_t* out,
+                          uint64_t out_cap, uint64_t* out_size, uint32_t* perm);
+
 /* Decompress a stream into pos (n*dims values of the stream's dtype). */
 int bbxo_decompress(const uint8_t* stream, uint64_t size, void* pos, uint64_t pos_cap_bytes,
                     int layout);

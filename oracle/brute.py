@@ -243,6 +243,132 @@ def decompress(stream: bytes) -> np.ndarray:
     return out
 
 
+def compress_reduced(points: np.ndarray, eb: float, eb_mode: str = "rel", r: int = 32,
+                     key_rule: int = 0):
+    """The bit box reduction of Sec. 4.1 restated with Python sets: a box is
+    its reference and widths; the key is the sum of widths (key_rule 0) or
+    the sum of the Eq. 3 box lengths (key_rule 1); two boxes meet when their
+    Eq. 1 predictable ranges overlap (closed intervals, in bins of 2*eps); a
+    particle is inside a box when the box's widths can encode its offsets
+    (searched, as for the widths themselves).  Returns (stream, perm)."""
+    n, dims = points.shape
+    f32 = points.dtype == np.float32
+    mbits = 5 if f32 else 6
+    prm = bound_params(points, eb, eb_mode)
+    codes = quantize(points, prm)
+    leaves = kd_leaves(codes, r, dims)
+    G = prm["G"]
+    boxes = []
+    for members in leaves:
+        j, m = bit_box(codes, members, dims)
+        boxes.append({"left": set(members), "ref": members[j], "m": m, "order": list(members)})
+
+    def key(b):
+        if key_rule == 0:
+            return sum(b["m"])
+        return sum(Fraction(4) * (Fraction(2) ** (md - 1) - Fraction(1, 2)) for md in b["m"])
+
+    def half(md):  # Eq. 1 half-range in bins: 2^(m-1) - 1/2 (zero for m = 0)
+        return Fraction(2) ** (md - 1) - Fraction(1, 2)
+
+    def meet(a, b):
+        return all(abs(codes[a["ref"]][d] - codes[b["ref"]][d]) <= half(a["m"][d]) + half(b["m"][d])
+                   for d in range(dims))
+
+    def inside(b, i):
+        return all(minimal_bits([codes[i][d] - codes[b["ref"]][d]]) <= b["m"][d] for d in range(dims))
+
+    seqs = []
+    live = [k for k in range(len(boxes))]
+    while live:
+        cur = min(live, key=lambda k: (key(boxes[k]), k))
+        B = boxes[cur]
+        parts = [i for i in B["order"] if i in B["left"] and i != B["ref"]]
+        for k in sorted(live):
+            if k == cur or not meet(B, boxes[k]):
+                continue
+            other = boxes[k]
+            common = [i for i in other["order"] if i in other["left"] and inside(B, i)]
+            if not common:
+                continue
+            parts += common
+            other["left"] -= set(common)
+            if other["left"]:
+                rest = [i for i in other["order"] if i in other["left"]]
+                j, m = bit_box(codes, rest, dims)
+                other["ref"], other["m"] = rest[j], m
+        seqs.append((B["ref"], list(B["m"]), parts))
+        live = [k for k in live if k != cur and boxes[k]["left"]]
+    meta = mpos = pay = ppos = 0
+    perm = []
+    for ref, m, parts in seqs:
+        for d in range(dims):
+            meta |= m[d] << mpos
+            mpos += mbits
+        for d in range(dims):
+            meta |= codes[ref][d] << mpos
+            mpos += G[d]
+        meta |= len(parts) << mpos
+        mpos += 32
+        perm.append(ref)
+        for i in parts:
+            perm.append(i)
+            for d in range(dims):
+                if m[d]:
+                    pay |= (codes[i][d] - codes[ref][d] + (1 << (m[d] - 1))) << ppos
+                    ppos += m[d]
+    lo3 = list(prm["lo"]) + [0.0] * (3 - dims)
+    G3 = list(G) + [0] * (3 - dims)
+    header = struct.pack(
+        "<4sHBBQIBBBBddddd3d3B5xQQQQ", b"BBX1", 2, 0 if f32 else 1, dims, n, r,
+        0 if eb_mode == "rel" else 1, 0, 0, mbits, eb, prm["eb_abs"], prm["eb_eff"], prm["w"],
+        prm["inv_w"], *lo3, *G3, len(leaves), mpos, ppos, len(seqs))
+    stream = (header + meta.to_bytes(8 * ((mpos + 63) // 64), "little")
+              + pay.to_bytes(8 * ((ppos + 63) // 64), "little"))
+    return stream, np.array(perm, dtype=np.uint32)
+
+
+def decompress_reduced(stream: bytes) -> np.ndarray:
+    """Decoder of the reduced stream (version 2) with big integers."""
+    (magic, ver, dt, dims, n, _r, _mode, _s, _rm, mbits, _eu, _ea, _ee, w, _iw, o0, o1, o2, g0,
+     g1, g2, _nl, meta_bits, pay_bits, nseq) = struct.unpack("<4sHBBQIBBBBddddd3d3B5xQQQQ",
+                                                             stream[:128])
+    assert magic == b"BBX1" and ver == 2
+    origin = [o0, o1, o2][:dims]
+    G = [g0, g1, g2][:dims]
+    mbytes = 8 * ((meta_bits + 63) // 64)
+    meta = int.from_bytes(stream[128:128 + mbytes], "little")
+    pay = int.from_bytes(stream[128 + mbytes:], "little")
+    T = np.float32 if dt == 0 else np.float64
+    out = np.zeros((n, dims), dtype=T)
+    mpos = ppos = slot = 0
+    for _ in range(nseq):
+        m, ref = [], []
+        for d in range(dims):
+            m.append((meta >> mpos) & ((1 << mbits) - 1))
+            mpos += mbits
+        for d in range(dims):
+            ref.append((meta >> mpos) & ((1 << G[d]) - 1))
+            mpos += G[d]
+        cnt = (meta >> mpos) & 0xFFFFFFFF
+        mpos += 32
+        rows = [ref]
+        for _ in range(cnt):
+            q = []
+            for d in range(dims):
+                if m[d]:
+                    q.append(ref[d] + ((pay >> ppos) & ((1 << m[d]) - 1)) - (1 << (m[d] - 1)))
+                    ppos += m[d]
+                else:
+                    q.append(ref[d])
+            rows.append(q)
+        for q in rows:
+            out[slot] = [T(origin[d] + float(q[d]) * w) for d in range(dims)]
+            slot += 1
+    assert slot == n and ppos == pay_bits
+    return out
+
+
 def export_sequences(stream: bytes) -> bytes:
     """Sec. 4.2 sequence layout of a ref_mode 1 stream, rebuilt with big
     integers: per leaf the centre's coordinate bits, the widths, the member

@@ -67,6 +67,9 @@ class Oracle:
         lib.bbxo_leaf_count.argtypes = [u64, u32]
         lib.bbxo_bits_for_offset.restype = u32
         lib.bbxo_bits_for_offset.argtypes = [u64]
+        lib.bbxo_compress_reduced.restype = i32
+        lib.bbxo_compress_reduced.argtypes = [vp, u64, u32, i32, i32, dbl, i32, u32, i32, vp, u64,
+                                              C.POINTER(u64), vp]
         lib.bbxo_axis_order_by_entropy.restype = None
         lib.bbxo_axis_order_by_entropy.argtypes = [vp, u64, u32, vp]
         lib.bbxo_r_index.restype = u64
@@ -139,6 +142,24 @@ class Oracle:
         if want_perm:
             return stream, perm[:n].copy()
         return stream
+
+    def compress_reduced(self, pos: np.ndarray, eb: float, eb_mode: str = "rel", r: int = 32,
+                         layout: str = "aos", key_rule: int = 0, want_perm: bool = False):
+        """Partition, bit boxes, then the bit box reduction of Sec. 4.1
+        (version-2 stream: one record per sequence)."""
+        pos = np.ascontiguousarray(pos)
+        n, dims, lay = self._shape(pos, layout)
+        cap = self.compress_bound(n, dims, pos.dtype) + 4 * n + 16
+        out = np.zeros(max(cap, 1), dtype=np.uint8)
+        size = C.c_uint64(0)
+        perm = np.zeros(max(n, 1), dtype=np.uint32)
+        st = self.lib.bbxo_compress_reduced(pos.ctypes.data, n, dims, _dt(pos), lay, float(eb),
+                                            0 if eb_mode == "rel" else 1, r, int(key_rule),
+                                            out.ctypes.data, cap, C.byref(size), perm.ctypes.data)
+        if st:
+            raise OracleError(st)
+        stream = out[: size.value].tobytes()
+        return (stream, perm[:n].copy()) if want_perm else stream
 
     def decompress(self, stream: bytes, layout: str = "aos", pos_cap_bytes: int | None = None):
         buf = np.frombuffer(stream, dtype=np.uint8) if len(stream) else np.zeros(1, np.uint8)

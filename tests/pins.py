@@ -167,12 +167,87 @@ def pin_lossless_reference(orc, seed=13, count=30):
         assert np.array_equal(d1[~first], d0[~first]), "members differ from the code stream"
 
 
+def reduction_case():
+    with open(os.path.join(GOLDEN, "reduction_examples.json")) as f:
+        return json.load(f)
+
+
+def pin_reduction_examples(orc):
+    """Sec. 4.1 bit box reduction on the hand-worked examples: sequence order,
+    centres, widths, counts and payload size, for both keys of the second."""
+    g = reduction_case()
+    for ex in g["examples"]:
+        pts = np.array(ex["points"], dtype=np.float64)
+        rules = ex.get("by_key_rule") or {str(ex["key_rule"]): ex}
+        for kr, want in rules.items():
+            s, perm = orc.compress_reduced(pts, ex["eps_abs"], "abs", ex["r"], key_rule=int(kr),
+                                           want_perm=True)
+            assert perm.tolist() == want["perm"], (ex["name"], kr, perm.tolist())
+            seqs = props.reduced_sequences(s)
+            assert len(seqs) == len(want["sequences"])
+            slot = 0
+            for sq, w in zip(seqs, want["sequences"]):
+                assert int(perm[slot]) == w["centre"] and sq["m"] == w["m"] and sq["count"] == w["count"]
+                slot += 1 + sq["count"]
+            assert props.parse_header(s)["payload_bits"] == want["payload_bits"]
+            assert np.array_equal(np.rint(orc.decompress(s)), pts[perm])  # eps 0.5: own bins
+        if "payload_bits_without_reduction" in ex:
+            s0 = orc.compress(pts, ex["eps_abs"], "abs", ex["r"])
+            assert props.parse_header(s0)["payload_bits"] == ex["payload_bits_without_reduction"]
+
+
+def pin_reduction_brute(orc, seed=14, count=40):
+    """The reduction against its restatement with Python sets, exact Eq. 1
+    ranges and searched widths; and the reduced stream's properties."""
+    for pts, eb, mode, r in tiny_cases(seed, count):
+        for kr in (0, 1):
+            s1, p1 = orc.compress_reduced(pts, eb, mode, r, key_rule=kr, want_perm=True)
+            s2, p2 = brute.compress_reduced(pts, eb, mode, r, key_rule=kr)
+            assert s1 == s2 and np.array_equal(p1, p2), ("reduced stream differs", pts.shape, r, kr)
+            d1 = orc.decompress(s1)
+            assert np.array_equal(d1, brute.decompress_reduced(s2))
+            st = orc.stages(pts, eb, mode, r)
+            props.check_reduced(pts, s1, p1, d1, st["q"], st["n_leaves"])
+
+
+def pin_reduction_special(orc):
+    """Special cases of the reduction: one leaf (r >= n) gives the plain
+    stream's single leaf as its one sequence; leaves whose bit boxes are far
+    apart keep their particles, so the sequences are the plain leaves taken
+    in ascending key (sum of widths), ties in leaf order."""
+    rng = np.random.default_rng(15)
+    pts = (rng.random((40, 3)) * 100).astype(np.float32)
+    s, p = orc.compress_reduced(pts, 1e-3, "rel", 64, want_perm=True)
+    s0, p0 = orc.compress(pts, 1e-3, "rel", 64, want_perm=True)
+    assert np.array_equal(p, p0) and props.parse_header(s)["payload_bits"] == props.parse_header(s0)["payload_bits"]
+    # eight tight clusters of eight particles, 1000 bins apart
+    centres = np.array([[i, j, k] for i in (0, 1) for j in (0, 1) for k in (0, 1)], dtype=np.float64) * 1000
+    pts = np.concatenate([c + rng.random((8, 3)) * (1 + 3 * t) for t, c in enumerate(centres)])
+    pts = pts[rng.permutation(len(pts))]
+    s, p = orc.compress_reduced(pts, 0.5, "abs", 8, want_perm=True)
+    st = orc.stages(pts, 0.5, "abs", 8)
+    keys = [int(sum(m)) for m in st["leaf_m"]]
+    order = sorted(range(len(keys)), key=lambda i: (keys[i], i))
+    seqs = props.reduced_sequences(s)
+    assert len(seqs) == st["n_leaves"] == 8
+    slot = 0
+    for sq, leaf in zip(seqs, order):
+        mem = st["order"][st["leaf_start"][leaf]: st["leaf_start"][leaf] + st["leaf_size"][leaf]]
+        ref = mem[st["leaf_ref"][leaf]]
+        assert int(p[slot]) == int(ref) and sq["m"] == [int(v) for v in st["leaf_m"][leaf]]
+        assert p[slot + 1: slot + 1 + sq["count"]].tolist() == [int(i) for i in mem if i != ref]
+        slot += 1 + sq["count"]
+
+
 def run_battery(orc):
     """Returns the names of the pins that fail."""
     failed = []
     for name, fn in (("worked_example", pin_worked_example), ("guard_size", pin_guard_size),
                      ("r_index", pin_r_index), ("brute_force", pin_brute_force),
-                     ("properties", pin_properties), ("lossless_reference", pin_lossless_reference)):
+                     ("properties", pin_properties), ("lossless_reference", pin_lossless_reference),
+                     ("reduction_examples", pin_reduction_examples),
+                     ("reduction_brute", pin_reduction_brute),
+                     ("reduction_special", pin_reduction_special)):
         try:
             fn(orc)
         except Exception as e:  # noqa: BLE001 -- any failure counts as caught

@@ -181,3 +181,51 @@ def psnr(points: np.ndarray, decoded: np.ndarray, perm: np.ndarray) -> float:
     rng = (points.max(axis=0).astype(np.float64) - points.min(axis=0).astype(np.float64)).max()
     nrmse = np.sqrt(np.mean(((x - y) / rng) ** 2))
     return float(-20.0 * np.log10(nrmse))
+
+
+def reduced_sequences(stream: bytes) -> list:
+    """Meta records of a reduced (version 2) stream: per sequence its widths,
+    centre codes and particle count (besides the centre)."""
+    h = parse_header(stream)
+    dims, mbits, G = h["dims"], h["mbits"], h["G"][: h["dims"]]
+    mb = 8 * ((h["meta_bits"] + 63) // 64)
+    meta = int.from_bytes(bytes(stream[128:128 + mb]), "little")
+    out, at = [], 0
+    for _ in range(h["reserved"]):
+        m = []
+        for d in range(dims):
+            m.append((meta >> at) & ((1 << mbits) - 1))
+            at += mbits
+        c = []
+        for d in range(dims):
+            c.append((meta >> at) & ((1 << G[d]) - 1))
+            at += G[d]
+        cnt = (meta >> at) & 0xFFFFFFFF
+        at += 32
+        out.append(dict(m=m, centre=c, count=cnt))
+    return out
+
+
+def check_reduced(points: np.ndarray, stream: bytes, perm: np.ndarray, decoded: np.ndarray,
+                  codes: np.ndarray, n_leaves: int):
+    """A reduced stream by definitions: every particle once, within the bound,
+    every particle of a sequence inside its bit box (its offsets from the
+    centre fit the sequence's widths, Eq. 1), at most one sequence per leaf,
+    none empty."""
+    h = parse_header(stream)
+    n, dims = points.shape
+    check_permutation(perm, n)
+    check_bound(points, decoded, perm, h["eb_abs"])
+    seqs = reduced_sequences(stream)
+    assert 1 <= len(seqs) <= n_leaves if n else len(seqs) == 0
+    slot = 0
+    for sq in seqs:
+        ctr = perm[slot]
+        assert [int(codes[d][ctr]) for d in range(dims)] == sq["centre"], "centre code"
+        reach = [(1 << (m - 1)) - 1 if m else 0 for m in sq["m"]]
+        for i in perm[slot + 1: slot + 1 + sq["count"]]:
+            for d in range(dims):
+                assert abs(int(codes[d][i]) - sq["centre"][d]) <= reach[d], "particle outside its box"
+        slot += 1 + sq["count"]
+    assert slot == n
+

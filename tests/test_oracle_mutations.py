@@ -34,6 +34,11 @@ MUTANTS = {
     18: "rounding guard of a whole FP32 ulp instead of half of one",
     19: "R-index axes in descending instead of ascending entropy",
     20: "R-index with the first axis least significant",
+    21: "reduction key: sum of box lengths where the sum of widths is asked, and the reverse",
+    22: "reduction ties go to the last box",
+    23: "boxes that lose particles keep their old bit box",
+    24: "no common particles are absorbed",
+    25: "common particles gathered in reverse leaf order",
 }
 
 

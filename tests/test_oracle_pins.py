@@ -470,3 +470,33 @@ def test_sequence_reordering_matches_python_sorts(oracle):
     s = oracle.compress(pts, 1e-4, "rel", 32, ref_mode=1)
     got, order = oracle.export_sequences_reordered(s)
     assert (got, order) == brute.export_sequences_reordered(s)
+
+
+def test_reduction_worked_examples(oracle):
+    """Sec. 4.1 bit box reduction on hand-worked examples (both keys)."""
+    pins.pin_reduction_examples(oracle)
+
+
+def test_reduction_brute_force(oracle):
+    pins.pin_reduction_brute(oracle, seed=102, count=120)
+
+
+def test_reduction_special_cases(oracle):
+    pins.pin_reduction_special(oracle)
+
+
+@pytest.mark.parametrize("gen,n,r,xi", [(cosmology, 20000, 32, 1e-3), (fluid, 32768, 32, 1e-4),
+                                        (uniform_cube, 5000, 8, 1e-2)])
+def test_reduction_properties_moderate(oracle, gen, n, r, xi):
+    """At moderate sizes: every particle once, within the bound, inside its
+    sequence's bit box; at most one sequence per leaf."""
+    if gen is fluid:
+        from synth import fluid_lattice_dims
+        pts = fluid(*fluid_lattice_dims(n), seed=3)
+    else:
+        pts = gen(n, seed=3)
+    s, perm = oracle.compress_reduced(pts, xi, "rel", r, want_perm=True)
+    st = oracle.stages(pts, xi, "rel", r)
+    props.check_reduced(pts, s, perm, oracle.decompress(s), st["q"], st["n_leaves"])
+    h = props.parse_header(s)
+    assert h["version"] == 2 and h["reserved"] <= st["n_leaves"]
