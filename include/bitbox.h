@@ -102,7 +102,21 @@ typedef enum { BBX_AOS = 0, BBX_SOA = 1 } bbx_layout;         /* [n][dims] or [d
  * set's partition levels with global histograms is cut into (0 = the
  * library's choice: 4,096 for a set alone, the set's share by particle count
  * in a batch; otherwise 1..4096, the smaller of this and that choice); fewer
- * blocks mean longer chunks per block.  It never changes the stream. */
+ * blocks mean longer chunks per block.  It never changes the stream.
+ * reduce != 0 adds the bit box reduction of Sec. 4.1 (the while loop of
+ * Alg. 1) after the bit boxes: repeatedly the remaining box with the
+ * smallest key (reduce 1: the sum of its widths, as the text says; 2: the
+ * sum of its box lengths, Eq. 3, as the figure caption says), ties to the
+ * first leaf in depth-first order, becomes a sequence of its reference, its
+ * other remaining members (ascending index) and every remaining particle of
+ * other boxes that lies inside its bit box (box by box in leaf order); boxes
+ * that lose particles get new bit boxes, empty ones vanish.  The stream is
+ * then version 2: the header's last field holds the sequence count, a meta
+ * record per sequence holds the widths, the reference's codes and a 32-bit
+ * count of the other particles, the payload their codes in sequence order;
+ * decompression writes the sequences in order, reference first.  Needs
+ * ref_mode 0 and fewer than 2^31 leaves; its loop runs one workgroup per
+ * set (a set's pops are sequential), so it suits batches of moderate sets. */
 typedef struct {
   uint32_t leaf_size;     /* r >= 1 */
   uint32_t eb_mode;       /* bbx_eb_mode */
@@ -112,6 +126,7 @@ typedef struct {
   uint32_t ref_mode;      /* 0 (reference code) or 1 (reference coordinates) */
   uint32_t scatter_stage; /* 0 (by chunk size), 1 (always) or 2 (never) */
   uint32_t level_blocks;  /* 0 (library's choice) or 1..4096 */
+  uint32_t reduce;        /* bit box reduction: 0 none, 1 (key: sum of widths), 2 (key: sum of lengths) */
 } bbx_params;
 
 /* Worst-case stream size in bytes for n particles of the given type, with
@@ -119,6 +134,10 @@ typedef struct {
  * 0 for a ref_mode other than 0 or 1). */
 size_t bbx_compress_bound(uint64_t n, uint32_t dims, bbx_dtype dtype);
 size_t bbx_compress_bound_mode(uint64_t n, uint32_t dims, bbx_dtype dtype, uint32_t ref_mode);
+/* The same for any parameters (the bit box reduction adds a 32-bit count
+ * per sequence, at most one sequence per leaf); 0 for invalid parameters. */
+size_t bbx_compress_bound_params(uint64_t n, uint32_t dims, bbx_dtype dtype,
+                                 const bbx_params* params);
 
 /* Device workspace bytes needed by bbx_compress for these arguments
  * (0 on invalid arguments; bbx_last_error() says why). */

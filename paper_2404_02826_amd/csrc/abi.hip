@@ -139,8 +139,12 @@ static bbx_status check_compress_args(uint64_t n, uint32_t dims, bbx_dtype dtype
   if (prm->ref_mode > 1) return fail(BBX_EINVAL, "ref_mode must be 0 or 1");
   if (prm->scatter_stage > 2) return fail(BBX_EINVAL, "scatter_stage must be 0, 1 or 2");
   if (prm->level_blocks > kLevelBlocks) return fail(BBX_EINVAL, "level_blocks must be 0..4096");
+  if (prm->reduce > 2) return fail(BBX_EINVAL, "reduce must be 0, 1 or 2");
+  if (prm->reduce && prm->ref_mode) return fail(BBX_EUNSUPPORTED, "the bit box reduction stores references as codes (ref_mode 0)");
   if (dims != 2 && dims != 3) return fail(BBX_EUNSUPPORTED, "dims must be 2 or 3");
   if (n >= (1ull << 32)) return fail(BBX_EUNSUPPORTED, "n must be below 2^32");
+  if (prm->reduce && n > 0 && make_geom(n, prm->leaf_size).L[0][0] >= (1ull << 31))
+    return fail(BBX_EUNSUPPORTED, "the bit box reduction needs fewer than 2^31 leaves");
   return BBX_OK;
 }
 
@@ -156,7 +160,8 @@ static bbx_status check_set(const SetIn& in) {
 // Byte offsets of the batch workspace regions.
 struct WsLayout {
   size_t params, sets, pre, partials, keys[2], idx[2], hist, sel, rows, cb, leaves, bits, spart,
-      stotal, pneed, defer, total;
+      stotal, pneed, defer, red_tq, red_taken, red_slot, red_perm, red_key, red_box, red_hits,
+      red_seq, total;
 };
 
 struct Carve {
@@ -190,6 +195,7 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
     return cap ? std::min(b, cap) : b;
   };
   std::vector<uint64_t> mm(nsets), qz(nsets), tl(nsets), bg(nsets), pm(nsets), pp(nsets);
+  std::vector<uint64_t> rp(nsets, 0), rl(nsets, 0), rw(nsets, 0);
   std::vector<uint8_t> stage_seen(kMaxDepth, 0);  // a set with global level k seen
   std::vector<std::vector<uint64_t>> lv(nsets), nd(nsets);
   for (uint32_t s = 0; s < nsets; ++s) {
@@ -211,7 +217,11 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
     D.r = I.prm.leaf_size;
     D.ref_rule = I.prm.ref_rule;
     D.ref_mode = I.prm.ref_mode;
-    D.track = (I.d_perm != nullptr || I.prm.ref_mode == 1) ? 1u : 0u;
+    D.reduce = I.prm.reduce;
+    D.user_perm = D.reduce ? I.d_perm : nullptr;
+    // a reduce set carries source indices; its leaf stage writes them to the
+    // workspace (batch_upload points perm there), the caller's perm comes last
+    D.track = (I.d_perm != nullptr || I.prm.ref_mode == 1 || D.reduce) ? 1u : 0u;
     D.eb_mode = I.prm.eb_mode;
     D.mbits = I.dtype == BBX_F32 ? 5u : 6u;
     const uint64_t n = I.n;
@@ -243,6 +253,13 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
       pm[s] = std::max<uint64_t>(1, std::min<uint64_t>((mw + kBlock - 1) / kBlock, 1024));
       const uint64_t lpb = leaves_per_block(D.r);
       pp[s] = (D.n_leaves + lpb - 1) / lpb;
+      if (D.reduce) {  // its own packing kernels; the leaf ones skip it
+        pm[s] = pp[s] = 0;
+        rp[s] = (D.n_leaves + kBlock - 1) / kBlock;
+        rl[s] = 1;
+        rw[s] = std::max<uint64_t>(1, std::min<uint64_t>((n + 2047) / 2048, 1024));
+        bp->reduce = 1;
+      }
       uint64_t max_nodes = 0, max_blocks = 0, bin_nodes = 0;
       for (uint32_t k = 0; k < D.gl; ++k) {
         const LevelShape sh = level_shape(n, k, D.level_blocks);
@@ -286,6 +303,7 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
       D.kst = (n + 63) & ~63ull;
       key_bytes += align_up((uint64_t)D.dims * D.kst * 4);
       if (I.need_idx || D.track) idx_n += (n + 63) & ~63ull;
+      if (D.reduce && !(I.need_idx || D.track)) idx_n += (n + 63) & ~63ull;
       hist_n += 2 * bin_nodes * kHistBins;
       sel_n += max_nodes;
       rows_n += max_blocks;
@@ -315,6 +333,9 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
   bp->o_big = add(bg, &bp->g_big);
   bp->o_pm = add(pm, &bp->g_pm);
   bp->o_pp = add(pp, &bp->g_pp);
+  bp->o_rp = add(rp, &bp->g_rp);
+  bp->o_rl = add(rl, &bp->g_rl);
+  bp->o_rw = add(rw, &bp->g_rw);
   for (uint32_t k = 0; k < bp->max_gl; ++k) {
     std::vector<uint64_t> a(nsets), b(nsets);
     for (uint32_t s = 0; s < nsets; ++s) {
@@ -344,6 +365,15 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
   lay->stotal = c.take(8);
   lay->pneed = c.take(4 * 4 * kMaxDepth);
   lay->defer = c.take(4 * (bp->g_tile + 1));
+  const uint64_t rn = bp->reduce ? idx_n : 0, rlv = bp->reduce ? leaves_n : 0;
+  lay->red_tq = c.take(16 * rn);
+  lay->red_taken = c.take(rn);
+  lay->red_slot = c.take(4 * rn);
+  lay->red_perm = c.take(4 * rn);
+  lay->red_key = c.take(8 * rlv);
+  lay->red_box = c.take(8 * rlv);
+  lay->red_hits = c.take(4 * rlv);
+  lay->red_seq = c.take(16 * rlv);
   lay->total = c.off;
 }
 
@@ -367,6 +397,13 @@ static Ws carve_ws(const WsLayout& L, uint8_t* base) {
   w.scan_total = (uint64_t*)(base + L.stotal);
   w.pass_need = (uint32_t*)(base + L.pneed);
   w.tile_defer = (uint32_t*)(base + L.defer);
+  w.red_tq = (uint4*)(base + L.red_tq);
+  w.red_taken = base + L.red_taken;
+  w.red_slot = (uint32_t*)(base + L.red_slot);
+  w.red_key = (uint64_t*)(base + L.red_key);
+  w.red_box = (uint2*)(base + L.red_box);
+  w.red_hits = (uint32_t*)(base + L.red_hits);
+  w.red_seq = (uint4*)(base + L.red_seq);
   return w;
 }
 
@@ -481,6 +518,9 @@ static bbx_status batch_upload(const SetIn* in, uint32_t nsets, void* d_ws, size
   plan_batch(in, nsets, &bp, &descs, &pre, &lay);
   if (!d_ws || ((uintptr_t)d_ws & 255)) return fail(BBX_EINVAL, "workspace must be 256-byte aligned");
   if (ws_size < lay.total) return fail(BBX_ENOMEM, "workspace too small: need " + std::to_string(lay.total));
+  for (uint32_t s = 0; s < nsets; ++s)
+    if (descs[s].reduce && descs[s].n > 0)
+      descs[s].perm = (uint32_t*)((uint8_t*)d_ws + lay.red_perm) + descs[s].idx_off;
   std::vector<uint8_t> blob(lay.pre + 8 * pre.size() - lay.sets);
   memcpy(blob.data(), descs.data(), sizeof(SetDesc) * nsets);
   memcpy(blob.data() + (lay.pre - lay.sets), pre.data(), 8 * pre.size());
@@ -514,6 +554,7 @@ static bbx_status batch_launch(const SetIn* in, uint32_t nsets, void* d_ws, size
   hipError_t e = launch_range(bp, w, stream);
   if (e == hipSuccess) e = launch_levels(bp, w, stream);
   if (e == hipSuccess) e = launch_leaves(bp, w, stream);
+  if (e == hipSuccess) e = launch_reduce(bp, w, stream);
   if (e == hipSuccess) e = launch_pack(bp, w, stream);
   if (e != hipSuccess) return fail(BBX_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
   return BBX_OK;
@@ -522,6 +563,8 @@ static bbx_status batch_launch(const SetIn* in, uint32_t nsets, void* d_ws, size
 // ---------------------------------------------------------------- stream header
 
 struct HostHeader {
+  uint32_t version;
+  uint64_t n_seq;
   uint64_t n, n_leaves, meta_bits, payload_bits;
   uint32_t dims, dtype, r, eb_mode, mbits, ref_mode;
   uint32_t G[3];
@@ -545,7 +588,8 @@ static bbx_status parse_header(const uint8_t* h, size_t bytes, HostHeader* o) {
   memcpy(&magic, h, 4);
   uint16_t ver;
   memcpy(&ver, h + 4, 2);
-  if (magic != kMagic || ver != 1) return fail(BBX_ECORRUPT, "bad magic or version");
+  if (magic != kMagic || (ver != 1 && ver != 2)) return fail(BBX_ECORRUPT, "bad magic or version");
+  o->version = ver;
   o->dtype = h[6];
   o->dims = h[7];
   o->n = rd64(h + 8);
@@ -577,9 +621,18 @@ static bbx_status parse_header(const uint8_t* h, size_t bytes, HostHeader* o) {
   o->n_leaves = rd64(h + 96);
   o->meta_bits = rd64(h + 104);
   o->payload_bits = rd64(h + 112);
-  if (rd64(h + 120) != 0) return fail(BBX_ECORRUPT, "reserved field not zero");
   const uint64_t nl = o->n ? make_geom(o->n, o->r).L[0][0] : 0;
   if (o->n_leaves != nl) return fail(BBX_ECORRUPT, "leaf count does not match (n, r)");
+  o->n_seq = rd64(h + 120);
+  if (o->version == 2) {  // sequences of the bit box reduction
+    if (o->ref_mode != 0) return fail(BBX_ECORRUPT, "reduced stream with stored coordinates");
+    if (o->n_seq > nl || (o->n > 0 && o->n_seq == 0)) return fail(BBX_ECORRUPT, "sequence count out of range");
+    if (o->meta_bits != o->n_seq * (uint64_t)(o->dims * o->mbits + sumG + 32))
+      return fail(BBX_ECORRUPT, "meta size mismatch");
+    if (o->payload_bits > o->n * (uint64_t)o->dims * 31u) return fail(BBX_ECORRUPT, "payload size out of range");
+    return BBX_OK;
+  }
+  if (o->n_seq != 0) return fail(BBX_ECORRUPT, "reserved field not zero");
   const uint32_t ref_bits = o->ref_mode ? o->dims * (o->dtype == 0 ? 32u : 64u) : sumG;
   if (o->meta_bits != nl * (uint64_t)(o->dims * o->mbits + ref_bits))
     return fail(BBX_ECORRUPT, "meta size mismatch");
@@ -597,7 +650,9 @@ static size_t carve_decompress(const HostHeader& h, uint8_t* base, DecompressWs*
   const size_t o_leaves = c.take(h.n_leaves * sizeof(LeafRec));
   const size_t o_bits = c.take(h.n_leaves * 8);
   const size_t o_sp = c.take((scan_blocks(h.n_leaves) + 1) * 8);
+  const size_t o_ss = c.take(h.version == 2 ? h.n_seq * 8 : 0);
   if (w && base) {
+    w->slot_start = (uint64_t*)(base + o_ss);
     w->params = (DevParams*)(base + o_params);
     w->leaves = (LeafRec*)(base + o_leaves);
     w->leaf_bits = (uint64_t*)(base + o_bits);
@@ -610,6 +665,8 @@ static DecompressPlan plan_of(const HostHeader& h, const void* raw, uint32_t lay
   DecompressPlan p;
   memset(&p, 0, sizeof(p));
   memcpy(p.header.w, raw, kHeaderBytes);
+  p.version = h.version;
+  p.n_seq = h.n_seq;
   p.n = h.n;
   p.n_leaves = h.n_leaves;
   p.meta_bits = h.meta_bits;
@@ -654,6 +711,15 @@ size_t bbx_compress_bound_mode(uint64_t n, uint32_t dims, bbx_dtype dtype, uint3
   const uint64_t mbits = dtype == BBX_F64 ? 6 : 5;
   const uint64_t ref = ref_mode ? (dtype == BBX_F64 ? 64 : 32) : 30;
   return kHeaderBytes + 16 + ((n * dims * (mbits + ref) + 63) / 64) * 8;
+}
+
+size_t bbx_compress_bound_params(uint64_t n, uint32_t dims, bbx_dtype dtype,
+                                 const bbx_params* params) {
+  if (!params || params->ref_mode > 1 || params->leaf_size == 0) return 0;
+  size_t b = bbx_compress_bound_mode(n, dims, dtype, params->ref_mode);
+  // the bit box reduction: a 32-bit count per sequence, at most one per leaf
+  if (params->reduce && n > 0) b += 4 * (size_t)make_geom(n, params->leaf_size).L[0][0] + 8;
+  return b;
 }
 
 size_t bbx_compress_workspace_size(uint64_t n, uint32_t dims, bbx_dtype dtype,

@@ -39,7 +39,8 @@ struct DevParams {
   uint32_t diag;        // first internal consistency check that failed (Check), 0 if none
   uint64_t meta_bits, payload_bits, total_bytes;
   uint64_t payload_base;  // global payload-bit offset of the set's first leaf
-  uint64_t pad1[3];
+  uint64_t nseq;          // sequences of the bit box reduction (reduce sets)
+  uint64_t pad1[2];
 };
 
 // Shape of the k-d tree, which depends on (n, r) only: at depth k every node
@@ -93,6 +94,8 @@ struct SetDesc {
   uint32_t track;         // source indices follow the codes (perm output or ref_mode 1)
   uint32_t fuse_depth;    // depth k whose levels k, k + 1 run fused in place, a wavefront per node (kNoFuse: none)
   uint32_t fuse_depth4;   // the same with a block per node (nodes of at most 4 kFuseNode)
+  uint32_t reduce;        // bit box reduction: 0 none, 1 key sum of widths, 2 key sum of lengths
+  uint32_t* user_perm;    // the caller's perm output of a reduce set (perm then points into the workspace)
   uint64_t n_leaves;
   uint64_t key_off;       // byte offset into each key buffer (capacity dims*n*4)
   uint64_t idx_off;       // u32 offset into each index buffer
@@ -124,6 +127,14 @@ struct Ws {
   const uint64_t* pre;  // block-count prefix arrays (see BatchPlan)
   uint32_t* pass_need;  // [kMaxDepth][4]: some set runs mid pass p at depth k
   uint32_t* tile_defer; // [0] = count, then global tile indices left to the 32-bit tile pass
+  // bit box reduction (sets with reduce != 0), particle arrays at idx_off, leaf arrays at leaf_off
+  uint4* red_tq;
+  uint8_t* red_taken;
+  uint32_t* red_slot;
+  uint64_t* red_key;
+  uint2* red_box;
+  uint32_t* red_hits;
+  uint4* red_seq;
 };
 
 // ---------------------------------------------------------------- device helpers
@@ -144,6 +155,7 @@ enum Check : uint32_t {
   kChkFusedPart = 9,
   kChkTileLeaves = 10,  // leaf count of a tile differs from the tree geometry
   kChkTileRange = 11,
+  kChkReduce = 12,      // the reduction did not place every particle
 };
 __device__ inline void check_failed(DevParams* P, uint32_t which) {
   atomicCAS(&P->diag, 0u, which);
@@ -417,6 +429,9 @@ struct BatchPlan {
   uint8_t lv_wave[kMaxDepth];    // some set handles level k one wavefront per node
   uint8_t lv_fused[kMaxDepth];   // some set handles levels k, k + 1 fused, a wavefront per node
   uint8_t lv_fused4[kMaxDepth];  // some set handles levels k, k + 1 fused, a block per node
+  uint32_t reduce;               // some set runs the bit box reduction
+  uint64_t g_rp, g_rl, g_rw;     // reduction: preparation, loop and packing blocks
+  uint64_t o_rp, o_rl, o_rw;
   uint64_t pre_entries;       // total u64 entries of the prefix buffer
 };
 
@@ -429,6 +444,8 @@ struct HeaderCopy {
 
 struct DecompressPlan {
   HeaderCopy header;
+  uint32_t version;  // 1: one record per leaf; 2: one per sequence of the bit box reduction
+  uint64_t n_seq;
   uint64_t n, n_leaves, meta_bits, payload_bits;
   uint32_t dims, dtype, r, mbits, layout, ref_mode;
   uint32_t G[3];
@@ -442,6 +459,7 @@ struct DecompressWs {
   LeafRec* leaves;
   uint64_t* leaf_bits;
   uint64_t* scan_part;
+  uint64_t* slot_start;  // version 2: first output slot of each sequence
 };
 
 uint64_t scan_blocks(uint64_t count);
@@ -460,5 +478,9 @@ hipError_t launch_export(const DecompressPlan& p, const DecompressWs& w, const u
                          void* out, uint32_t* d_status, hipStream_t s);
 hipError_t launch_dec_scan(uint64_t count, uint64_t* bits, uint64_t* part, DevParams* params,
                            uint64_t expect_payload, hipStream_t s);
+hipError_t launch_reduce(const BatchPlan& bp, const Ws& w, hipStream_t s);
+hipError_t launch_reduce_pack(const BatchPlan& bp, const Ws& w, hipStream_t s);
+hipError_t launch_decompress2(const DecompressPlan& p, const DecompressWs& w, const uint8_t* stream,
+                              void* pos, hipStream_t s);
 
 }  // namespace bbx

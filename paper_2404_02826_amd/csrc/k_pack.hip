@@ -135,7 +135,10 @@ __global__ void k_set_sizes(uint32_t nsets, const SetDesc* sets, DevParams* para
   const uint64_t endv = S.n_leaves ? (e < total_leaves ? off[e] : *total) : 0;
   uint32_t sumG = 0;  // reference field: codes, or original coordinates with ref_mode 1
   for (uint32_t d = 0; d < S.dims; ++d) sumG += S.ref_mode ? coord_bits(S.dtype) : P->G[d];
-  const uint64_t meta = S.n_leaves * (uint64_t)(S.dims * S.mbits + sumG);
+  // one record per leaf; with the bit box reduction one per sequence, with
+  // a 32-bit particle count
+  const uint64_t meta = S.reduce ? P->nseq * (uint64_t)(S.dims * S.mbits + sumG + 32)
+                                 : S.n_leaves * (uint64_t)(S.dims * S.mbits + sumG);
   P->payload_base = base;
   P->meta_bits = meta;
   P->payload_bits = endv - base;
@@ -480,7 +483,8 @@ __global__ void k_header(const SetDesc* sets, const DevParams* params) {
   const uint32_t dims = S.dims;
   uint64_t h[16];
   for (int k = 0; k < 16; ++k) h[k] = 0;
-  h[0] = (uint64_t)kMagic | ((uint64_t)1 << 32) | ((uint64_t)S.dtype << 48) | ((uint64_t)dims << 56);
+  h[0] = (uint64_t)kMagic | ((uint64_t)(S.reduce ? 2 : 1) << 32) | ((uint64_t)S.dtype << 48) |
+         ((uint64_t)dims << 56);
   h[1] = S.n;
   h[2] = (uint64_t)S.r | ((uint64_t)S.eb_mode << 32) | ((uint64_t)S.ref_mode << 48) |
          ((uint64_t)S.mbits << 56);
@@ -495,7 +499,7 @@ __global__ void k_header(const SetDesc* sets, const DevParams* params) {
   h[12] = S.n_leaves;
   h[13] = P->meta_bits;
   h[14] = P->payload_bits;
-  h[15] = 0;
+  h[15] = S.reduce ? P->nseq : 0;  // version 2: the sequence count
   uint64_t* o = (uint64_t*)S.out;
   for (int k = 0; k < 16; ++k) o[k] = h[k];
 }
@@ -521,6 +525,8 @@ hipError_t launch_pack(const BatchPlan& bp, const Ws& w, hipStream_t s) {
   if (bp.g_pp > 0)
     BBX_LAUNCH("pack_payload", k_pack_payload, bp.g_pp, kBlock, 0, s, bp.nsets, w.pre + bp.o_pp,
                w.sets, w.params, w.leaves, w.leaf_bits, w.keys[0], w.keys[1]);
+  e = launch_reduce_pack(bp, w, s);
+  if (e != hipSuccess) return e;
   BBX_LAUNCH("header", k_header, bp.nsets, 64, 0, s, w.sets, w.params);
   BBX_LAUNCH("finish", k_finish, g, kBlock, 0, s, bp.nsets, w.sets, w.params);
   return hipGetLastError();

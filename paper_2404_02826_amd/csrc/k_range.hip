@@ -167,7 +167,8 @@ __global__ void __launch_bounds__(kBlock) k_epilogue(const SetDesc* sets, const 
   p.status = BBX_OK;
   p.diag = 0;
   p.meta_bits = p.payload_bits = p.total_bytes = p.payload_base = 0;
-  for (int k = 0; k < 3; ++k) p.pad1[k] = 0;
+  p.nseq = 0;
+  for (int k = 0; k < 2; ++k) p.pad1[k] = 0;
   if (n == 0) {
     p.eb_abs = S.eb_mode == BBX_EB_ABS ? eb : 0.0;
     *P = p;

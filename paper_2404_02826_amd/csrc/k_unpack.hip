@@ -342,7 +342,10 @@ __global__ void __launch_bounds__(kBlock) k_dec_refs(uint64_t n, uint64_t n_leav
 hipError_t launch_decompress(const DecompressPlan& p, const DecompressWs& w, const uint8_t* stream,
                              void* pos, uint32_t* d_status, hipStream_t s) {
   BBX_LAUNCH("dec_init", k_dec_init, 1, 64, 0, s, w.params, stream, p.header);
-  if (p.n > 0) {
+  if (p.n > 0 && p.version == 2) {
+    hipError_t e = launch_decompress2(p, w, stream, pos, s);
+    if (e != hipSuccess) return e;
+  } else if (p.n > 0) {
     uint64_t g = (p.n_leaves + kBlock - 1) / kBlock;
     if (g > 65536) g = 65536;
     BBX_LAUNCH("dec_meta", k_dec_meta, g, kBlock, 0, s, p.n_leaves, p.dims, p.mbits, p.G[0],

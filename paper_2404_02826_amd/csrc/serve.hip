@@ -246,7 +246,7 @@ extern "C" bbx_status bbx_server_submit_compress(bbx_server* s, const void* d_po
   j.dtype = dtype;
   j.eb = eb;
   j.prm = p;
-  j.result_cap = round_up(bbx_compress_bound_mode(n, dims, dtype, p.ref_mode), 8);
+  j.result_cap = round_up(bbx_compress_bound_params(n, dims, dtype, &p), 8);
   j.res_bytes = kResultHead + j.result_cap;
   j.ws_need = ws;
   return enqueue(s, j, job);
