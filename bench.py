@@ -29,6 +29,9 @@ WORKLOADS = {
     "cosmology-2^24-f32-xi1e-4": ("cosmology", 1 << 24, "float32", 1e-4),
     "cosmology-2^24-f32-xi1e-3": ("cosmology", 1 << 24, "float32", 1e-3),
     "uniform-65536-f32-xi1e-3": ("uniform", 65536, "float32", 1e-3),
+    # moderate sets for the bit box reduction (one workgroup runs a set's pops)
+    "cosmology-2^18-f32-xi1e-4": ("cosmology", 1 << 18, "float32", 1e-4),
+    "fluid-2^18-f32-xi1e-4": ("fluid", 1 << 18, "float32", 1e-4),
     # fusion-shaped 2-D set of the size of the paper's XGC Poincare data
     "poincare-2d-13077313-f32": ("poincare", 13077313, "float32", 1e-4),
 }
@@ -504,6 +507,9 @@ def main():
                     help="leaf reference: 0 nearest the AABB centre (the paper's), 1 fewest bits")
     ap.add_argument("--ref-mode", type=int, default=0, choices=(0, 1),
                     help="reference stored as 0 its codes, 1 its original coordinates (lossless)")
+    ap.add_argument("--reduce", type=int, default=0, choices=(0, 1, 2),
+                    help="bit box reduction after the bit boxes: 1 key sum of widths, 2 key sum of "
+                         "box lengths (moderate sets: at most 65,536 leaves)")
     ap.add_argument("--scatter-stage", type=int, default=0, choices=(0, 1, 2),
                     help="global partition group stores: 0 by chunk size, 1 staged, 2 direct")
     ap.add_argument("--nsets", type=int, default=4096)
@@ -544,21 +550,32 @@ def main():
     B_in = x.numel() * x.element_size()
 
     dims = int(x.shape[1])
+    if args.reduce and n > 65536 * args.leaf_size:
+        print("the bit box reduction runs a set's pops in one workgroup: use a set of at most "
+              "65,536 leaves", file=sys.stderr)
+        sys.exit(2)
     comp = bbx.Compressor(n, dims, x.dtype, leaf_size=args.leaf_size, tile=args.tile,
                           ref_rule=args.ref_rule, ref_mode=args.ref_mode,
-                          scatter_stage=args.scatter_stage)
+                          scatter_stage=args.scatter_stage, reduce=args.reduce)
     s = comp(x, xi)
     S = s.numel()
+    S_plain = S
+    if args.reduce:  # the same input without the reduction: its stream size only
+        alt = bbx.Compressor(n, dims, x.dtype, leaf_size=args.leaf_size, tile=args.tile)
+        S_plain = alt(x, xi).numel()
+        del alt
     # the other leaf-reference rule, and the other reference storage, on the
     # same input: their stream sizes only
     alt = bbx.Compressor(n, dims, x.dtype, leaf_size=args.leaf_size, tile=args.tile,
                          ref_rule=1 - args.ref_rule, ref_mode=args.ref_mode)
     S_alt = alt(x, xi).numel()
     del alt
-    alt = bbx.Compressor(n, dims, x.dtype, leaf_size=args.leaf_size, tile=args.tile,
-                         ref_rule=args.ref_rule, ref_mode=1 - args.ref_mode)
-    S_alt_mode = alt(x, xi).numel()
-    del alt
+    S_alt_mode = None
+    if not args.reduce:
+        alt = bbx.Compressor(n, dims, x.dtype, leaf_size=args.leaf_size, tile=args.tile,
+                             ref_rule=args.ref_rule, ref_mode=1 - args.ref_mode)
+        S_alt_mode = alt(x, xi).numel()
+        del alt
     torch.cuda.empty_cache()
     header = s[:128].cpu().numpy().tobytes()
     info = bbx.stream_info(header)
@@ -621,7 +638,7 @@ def main():
     # ---- per-phase timing and latency distribution (HIP events, same stream)
     st = torch.cuda.current_stream()
     # (a small set is latency-bound: its p50 / p99 come from at least 1,000 runs)
-    lat_runs = args.steps if n > (1 << 20) else max(args.steps, 1000)
+    lat_runs = args.steps if n > (1 << 20) or args.reduce else max(args.steps, 1000)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
            torch.cuda.Event(enable_timing=True)) for _ in range(lat_runs)]
     for e0, e1, e2 in ev:
@@ -709,7 +726,8 @@ def main():
     perm_check = None
     try:
         pc = bbx.Compressor(n, dims, x.dtype, leaf_size=args.leaf_size, tile=args.tile,
-                            want_perm=True, ref_rule=args.ref_rule, ref_mode=args.ref_mode)
+                            want_perm=True, ref_rule=args.ref_rule, ref_mode=args.ref_mode,
+                            reduce=args.reduce)
         s2 = pc(x, xi)
         assert s2.numel() == S
         perm = pc.perm[:n].long()
@@ -730,8 +748,11 @@ def main():
         orc = Oracle()
         log(f"cpu oracle on {m} particles")
         t = time.perf_counter()
-        so = orc.compress(sample, xi, "rel", args.leaf_size, ref_rule=args.ref_rule,
-                          ref_mode=args.ref_mode)
+        if args.reduce:
+            so = orc.compress_reduced(sample, xi, "rel", args.leaf_size, key_rule=args.reduce - 1)
+        else:
+            so = orc.compress(sample, xi, "rel", args.leaf_size, ref_rule=args.ref_rule,
+                              ref_mode=args.ref_mode)
         t1 = time.perf_counter()
         orc.decompress(so)
         t2 = time.perf_counter()
@@ -752,7 +773,9 @@ def main():
                    "graph": bool(args.graph),
                    "stream_bytes": S, "cr": round(B_in / S, 4),
                    "cr_other_ref_rule": round(B_in / S_alt, 4),
-                   "cr_other_ref_mode": round(B_in / S_alt_mode, 4),
+                   "cr_other_ref_mode": round(B_in / S_alt_mode, 4) if S_alt_mode else None,
+                   "reduce": args.reduce,
+                   "cr_without_reduce": round(B_in / S_plain, 4),
                    "sequence_export": export,
                    "bpp": round(8 * S / n, 4),
                    "compress_gbps": round(B_in / (mc * 1e-3) / 1e9, 2),

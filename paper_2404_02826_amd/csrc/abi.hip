@@ -160,7 +160,7 @@ static bbx_status check_set(const SetIn& in) {
 // Byte offsets of the batch workspace regions.
 struct WsLayout {
   size_t params, sets, pre, partials, keys[2], idx[2], hist, sel, rows, cb, leaves, bits, spart,
-      stotal, pneed, defer, red_tq, red_taken, red_slot, red_perm, red_key, red_box, red_hits,
+      stotal, pneed, defer, red_tq, red_taken, red_slot, red_perm, red_key, red_ctr, red_ref, red_hits,
       red_seq, total;
 };
 
@@ -259,6 +259,10 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
         rl[s] = 1;
         rw[s] = std::max<uint64_t>(1, std::min<uint64_t>((n + 2047) / 2048, 1024));
         bp->reduce = 1;
+        if (D.n_leaves <= kRedLdsBoxes)
+          bp->red_lds_boxes = 1;
+        else
+          bp->red_global = 1;
       }
       uint64_t max_nodes = 0, max_blocks = 0, bin_nodes = 0;
       for (uint32_t k = 0; k < D.gl; ++k) {
@@ -371,7 +375,8 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
   lay->red_slot = c.take(4 * rn);
   lay->red_perm = c.take(4 * rn);
   lay->red_key = c.take(8 * rlv);
-  lay->red_box = c.take(8 * rlv);
+  lay->red_ctr = c.take(16 * rlv);
+  lay->red_ref = c.take(4 * rlv);
   lay->red_hits = c.take(4 * rlv);
   lay->red_seq = c.take(16 * rlv);
   lay->total = c.off;
@@ -401,7 +406,8 @@ static Ws carve_ws(const WsLayout& L, uint8_t* base) {
   w.red_taken = base + L.red_taken;
   w.red_slot = (uint32_t*)(base + L.red_slot);
   w.red_key = (uint64_t*)(base + L.red_key);
-  w.red_box = (uint2*)(base + L.red_box);
+  w.red_ctr = (uint4*)(base + L.red_ctr);
+  w.red_ref = (uint32_t*)(base + L.red_ref);
   w.red_hits = (uint32_t*)(base + L.red_hits);
   w.red_seq = (uint4*)(base + L.red_seq);
   return w;

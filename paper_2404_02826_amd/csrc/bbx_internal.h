@@ -25,6 +25,7 @@ constexpr int kGroup = kRows * kBlock;    // elements per streaming group
 constexpr uint64_t kLevelBlocks = 4096;   // blocks per global level of a set alone
 constexpr uint64_t kLocalBlocks = 4096;   // levels of at least this many nodes run block-local
 constexpr uint32_t kStageChunk = 16384;   // the global scatter stages groups from this chunk size
+constexpr uint32_t kRedLdsBoxes = 4096;   // bit box reduction: boxes kept in LDS (24 B each)
 // a block-local level is one chunk per node under every block target
 static_assert(kLevelBlocks <= kLocalBlocks, "block-local levels must have one chunk per node");
 
@@ -132,7 +133,8 @@ struct Ws {
   uint8_t* red_taken;
   uint32_t* red_slot;
   uint64_t* red_key;
-  uint2* red_box;
+  uint4* red_ctr;
+  uint32_t* red_ref;
   uint32_t* red_hits;
   uint4* red_seq;
 };
@@ -430,6 +432,8 @@ struct BatchPlan {
   uint8_t lv_fused[kMaxDepth];   // some set handles levels k, k + 1 fused, a wavefront per node
   uint8_t lv_fused4[kMaxDepth];  // some set handles levels k, k + 1 fused, a block per node
   uint32_t reduce;               // some set runs the bit box reduction
+  uint32_t red_lds_boxes;        // some reduce set keeps its boxes on chip (<= kRedLdsBoxes leaves)
+  uint32_t red_global;           // some reduce set keeps them in the workspace
   uint64_t g_rp, g_rl, g_rw;     // reduction: preparation, loop and packing blocks
   uint64_t o_rp, o_rl, o_rw;
   uint64_t pre_entries;       // total u64 entries of the prefix buffer

@@ -58,7 +58,8 @@ struct RedSet {
   uint8_t* taken;     // [n] 1 once a particle is in a sequence
   uint32_t* slot_pos; // [n] tq position of each output slot
   uint64_t* key;      // [n_leaves] key << 31 | leaf, or kDead
-  uint2* box;         // [n_leaves] reference position, packed widths
+  uint4* ctr;         // [n_leaves] the box: its reference's codes (x, y, z) and packed widths
+  uint32_t* ref;      // [n_leaves] tq position of the box's reference
   uint32_t* hits;     // [n_leaves] boxes meeting the popped one
   uint4* seq;         // [n_leaves] centre position, packed widths, count, first slot
 };
@@ -69,7 +70,8 @@ __device__ inline RedSet red_set(const SetDesc& S, const Ws& w) {
   r.taken = w.red_taken + S.idx_off;
   r.slot_pos = w.red_slot + S.idx_off;
   r.key = w.red_key + S.leaf_off;
-  r.box = w.red_box + S.leaf_off;
+  r.ctr = w.red_ctr + S.leaf_off;
+  r.ref = w.red_ref + S.leaf_off;
   r.hits = w.red_hits + S.leaf_off;
   r.seq = w.red_seq + S.leaf_off;
   return r;
@@ -96,7 +98,8 @@ __device__ void red_prep_leaf(const SetDesc& S, const RedSet& R, const KT* keys,
     R.tq[tp] = v;
     R.taken[tp] = 0;
   }
-  R.box[leaf] = make_uint2(st + rr, rec.m);
+  R.ref[leaf] = st + rr;
+  R.ctr[leaf] = make_uint4(rec.qref[0], rec.qref[1], rec.qref[2], rec.m);
   R.key[leaf] = red_key(rec.m, S.dims, S.reduce, leaf);
 }
 
@@ -142,6 +145,19 @@ __device__ inline bool red_inside(const uint4 q, const uint32_t c[3], const uint
   return in;
 }
 
+// Whether box b (reference codes and packed widths) meets the popped box:
+// the code intervals overlap on every axis.
+__device__ inline bool red_meet(const uint4 b, const uint32_t c[3], const uint32_t R[3],
+                                uint32_t dims) {
+  bool hit = true;
+  const uint32_t o[3] = {b.x, b.y, b.z};
+  for (uint32_t d = 0; d < dims; ++d) {
+    const uint64_t gap = o[d] > c[d] ? o[d] - c[d] : c[d] - o[d];
+    hit = hit && gap <= (uint64_t)R[d] + red_reach(red_m(b.w, d));
+  }
+  return hit;
+}
+
 // Bit box of the members of [st, st + sz) that stay: not taken before this
 // pop and not inside the popped box (c, Rr).  AABB, the member nearest the
 // AABB centre (squared distance in doubled code space, first position on
@@ -149,7 +165,7 @@ __device__ inline bool red_inside(const uint4 q, const uint32_t c[3], const uint
 // the popped box's catch afterwards).
 __device__ inline void red_refit(const RedSet& R, uint32_t st, uint32_t sz, uint32_t dims,
                                  const uint32_t c[3], const uint32_t Rr[3], uint32_t* ref_out,
-                                 uint32_t* m_out) {
+                                 uint4* box_out) {
   const uint32_t lane = threadIdx.x & 63;
   uint32_t mn[3] = {~0u, ~0u, ~0u}, mx[3] = {0, 0, 0};
   for (uint32_t k = lane; k < sz; k += 64) {
@@ -187,29 +203,61 @@ __device__ inline void red_refit(const RedSet& R, uint32_t st, uint32_t sz, uint
     mp |= red_width(D) << (8 * d);
   }
   *ref_out = st + bk;
-  *m_out = mp;
+  *box_out = make_uint4(v[0], v[1], v[2], mp);
 }
 
-__global__ void __launch_bounds__(kBlock) k_reduce(uint32_t nsets, const uint64_t* pre, Ws w) {
+// threads of the reduction loop: the pops' box scans and their catch are
+// spread over 16 wavefronts
+constexpr uint32_t kRedBlock = 1024;
+
+// Block-wide exclusive scan of one count per thread; *total gets the sum.
+__device__ inline uint32_t red_exscan(uint32_t v, uint32_t* wsum, uint32_t* total) {
+  const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const uint32_t incl = wave_incl(v);
+  if (lane == 63) wsum[wv] = incl;
+  __syncthreads();
+  uint32_t off = 0, tot = 0;
+  for (uint32_t k = 0; k < kRedBlock / 64; ++k) {
+    off += k < wv ? wsum[k] : 0u;
+    tot += wsum[k];
+  }
+  *total = tot;
+  return off + incl - v;
+}
+
+// The loop of one set.  LDS: the boxes' keys and records live in on-chip
+// memory for the whole loop (sets of at most kRedLdsBoxes leaves); else in
+// the workspace.  Each thread owns a contiguous range of boxes for the two
+// scans of every pop (smallest key; boxes that meet the popped one).
+template <bool LDS>
+__global__ void __launch_bounds__(kRedBlock) k_reduce(uint32_t nsets, const uint64_t* pre, Ws w) {
+  extern __shared__ __align__(16) uint8_t red_dyn[];
   const uint32_t s = find_set(pre, nsets, blockIdx.x);
   const SetDesc& S = w.sets[s];
   DevParams* P = w.params + s;
   if (P->status != BBX_OK || !S.reduce || S.n == 0) return;
+  if ((S.n_leaves <= kRedLdsBoxes) != LDS) return;
   const RedSet R = red_set(S, w);
   const LeafRec* leaves = w.leaves + S.leaf_off;
   const uint32_t B = (uint32_t)S.n_leaves, dims = S.dims;
   const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  constexpr uint32_t W = kBlock / 64;
+  constexpr uint32_t W = kRedBlock / 64;
+  uint64_t* K = LDS ? (uint64_t*)red_dyn : R.key;
+  uint4* C = LDS ? (uint4*)(red_dyn + 8 * (size_t)kRedLdsBoxes) : R.ctr;
   __shared__ uint64_t s_min[W];
-  __shared__ uint32_t s_cnt[W], s_keep[W];
-  __shared__ uint32_t s_slot, s_nseq, s_nh, s_first;
+  __shared__ uint32_t s_cnt[W], s_wsum[W];
+  __shared__ uint32_t s_slot, s_nseq, s_first;
+  if (LDS)
+    for (uint32_t b = threadIdx.x; b < B; b += kRedBlock) K[b] = R.key[b], C[b] = R.ctr[b];
   if (threadIdx.x == 0) s_slot = 0, s_nseq = 0;
   __syncthreads();
+  const uint32_t per = (B + kRedBlock - 1) / kRedBlock;
+  const uint32_t b_lo = umin32(threadIdx.x * per, B), b_hi = umin32(b_lo + per, B);
   for (;;) {
     // ---- the remaining box with the smallest (key, leaf)
     uint64_t best = kDead;
-    for (uint32_t b = threadIdx.x; b < B; b += kBlock) {
-      const uint64_t k = R.key[b];
+    for (uint32_t b = b_lo; b < b_hi; ++b) {
+      const uint64_t k = K[b];
       best = k < best ? k : best;
     }
     best = wave_min_u64(best);
@@ -219,19 +267,20 @@ __global__ void __launch_bounds__(kBlock) k_reduce(uint32_t nsets, const uint64_
     for (uint32_t k = 1; k < W; ++k) best = s_min[k] < best ? s_min[k] : best;
     if (best == kDead) break;  // uniform: every box popped or empty
     const uint32_t cur = (uint32_t)(best & 0x7fffffffu);
-    const uint2 cb = R.box[cur];
-    const uint4 cq = R.tq[cb.x];
-    const uint32_t c[3] = {cq.x, cq.y, cq.z};
-    const uint32_t Rr[3] = {red_reach(red_m(cb.y, 0)), red_reach(red_m(cb.y, 1)),
-                            red_reach(red_m(cb.y, 2))};
+    const uint4 cb = C[cur];
+    const uint32_t c[3] = {cb.x, cb.y, cb.z};
+    const uint32_t Rr[3] = {red_reach(red_m(cb.w, 0)), red_reach(red_m(cb.w, 1)),
+                            red_reach(red_m(cb.w, 2))};
     const uint32_t first = s_slot;
-    // ---- its centre, then its other remaining members in ascending index (wavefront 0)
+    // ---- its centre, then its other remaining members in ascending index
+    // (wavefront 0, while the others start the scan below; it skips cur)
     if (wv == 0) {
+      const uint32_t cref = R.ref[cur];
       const RedLeaf L = {leaves[cur].start, leaves[cur].size};
       uint32_t at = first + 1;
       for (uint32_t k0 = 0; k0 < L.sz; k0 += 64) {
         const uint32_t k = k0 + lane;
-        const bool mine = k < L.sz && L.st + k != cb.x && !R.taken[L.st + k];
+        const bool mine = k < L.sz && L.st + k != cref && !R.taken[L.st + k];
         const uint64_t bm = __ballot(mine);
         if (mine && at + lanes_below(bm) < S.n) {
           R.slot_pos[at + lanes_below(bm)] = L.st + k;
@@ -240,44 +289,21 @@ __global__ void __launch_bounds__(kBlock) k_reduce(uint32_t nsets, const uint64_
         at += (uint32_t)__popcll(bm);
       }
       if (lane == 0) {
-        if (first < S.n) R.slot_pos[first] = cb.x;
-        R.taken[cb.x] = 1;
-        R.key[cur] = kDead;
+        if (first < S.n) R.slot_pos[first] = cref;
+        R.taken[cref] = 1;
         s_first = at;
       }
     }
-    __syncthreads();
     // ---- every other remaining box that meets the popped one, in leaf order
-    if (threadIdx.x == 0) s_nh = 0;
+    uint32_t nhit = 0;
+    for (uint32_t b = b_lo; b < b_hi; ++b)
+      nhit += (b != cur && K[b] != kDead && red_meet(C[b], c, Rr, dims)) ? 1u : 0u;
+    uint32_t nh;
+    uint32_t at_h = red_exscan(nhit, s_wsum, &nh);
+    for (uint32_t b = b_lo; b < b_hi && nhit; ++b)
+      if (b != cur && K[b] != kDead && red_meet(C[b], c, Rr, dims)) R.hits[at_h++] = b;
     __syncthreads();
-    for (uint32_t b0 = 0; b0 < B; b0 += kBlock) {
-      const uint32_t b = b0 + threadIdx.x;
-      bool hit = false;
-      if (b < B && R.key[b] != kDead) {
-        const uint2 ob = R.box[b];
-        const uint4 oq = R.tq[ob.x];
-        const uint32_t o[3] = {oq.x, oq.y, oq.z};
-        hit = true;
-        for (uint32_t d = 0; d < dims; ++d) {
-          const uint64_t gap = o[d] > c[d] ? o[d] - c[d] : c[d] - o[d];
-          hit = hit && gap <= (uint64_t)Rr[d] + red_reach(red_m(ob.y, d));
-        }
-      }
-      const uint64_t bm = __ballot(hit);
-      if (lane == 0) s_cnt[wv] = (uint32_t)__popcll(bm);
-      __syncthreads();
-      uint32_t before = s_nh;
-      for (uint32_t k = 0; k < wv; ++k) before += s_cnt[k];
-      if (hit) R.hits[before + lanes_below(bm)] = b;
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        uint32_t t = 0;
-        for (uint32_t k = 0; k < W; ++k) t += s_cnt[k];
-        s_nh += t;
-      }
-      __syncthreads();
-    }
-    const uint32_t nh = s_nh;
+    if (threadIdx.x == 0) K[cur] = kDead;
     // ---- their common particles, W boxes at a time (one wavefront each)
     for (uint32_t h0 = 0; h0 < nh; h0 += W) {
       const uint32_t h = h0 + wv;
@@ -298,7 +324,7 @@ __global__ void __launch_bounds__(kBlock) k_reduce(uint32_t nsets, const uint64_
           keep += (uint32_t)__popcll(__ballot(alive && !in));
         }
       }
-      if (lane == 0) s_cnt[wv] = cnt, s_keep[wv] = keep;
+      if (lane == 0) s_cnt[wv] = cnt;
       __syncthreads();
       uint32_t at = s_first;
       for (uint32_t k = 0; k < wv; ++k) at += s_cnt[k];
@@ -312,8 +338,9 @@ __global__ void __launch_bounds__(kBlock) k_reduce(uint32_t nsets, const uint64_
           if (in && at + lanes_below(bm) < S.n) R.slot_pos[at + lanes_below(bm)] = L.st + k;
           at += (uint32_t)__popcll(bm);
         }
-        uint32_t ref = 0, mp = 0;
-        if (keep > 0) red_refit(R, L.st, L.sz, dims, c, Rr, &ref, &mp);
+        uint32_t ref = 0;
+        uint4 nb = make_uint4(0, 0, 0, 0);
+        if (keep > 0) red_refit(R, L.st, L.sz, dims, c, Rr, &ref, &nb);
         // every lane's reads of this box's flags are done (wavefront order)
         __builtin_amdgcn_wave_barrier();
         for (uint32_t k0 = 0; k0 < L.sz; k0 += 64) {
@@ -323,10 +350,11 @@ __global__ void __launch_bounds__(kBlock) k_reduce(uint32_t nsets, const uint64_
         }
         if (lane == 0) {
           if (keep == 0) {
-            R.key[b] = kDead;  // empty: vanishes
+            K[b] = kDead;  // empty: vanishes
           } else {
-            R.box[b] = make_uint2(ref, mp);
-            R.key[b] = red_key(mp, dims, S.reduce, b);
+            R.ref[b] = ref;
+            C[b] = nb;
+            K[b] = red_key(nb.w, dims, S.reduce, b);
           }
         }
       }
@@ -340,7 +368,7 @@ __global__ void __launch_bounds__(kBlock) k_reduce(uint32_t nsets, const uint64_
     }
     // ---- the sequence record
     if (threadIdx.x == 0) {
-      R.seq[s_nseq] = make_uint4(cb.x, cb.y, s_first - first - 1, first);
+      R.seq[s_nseq] = make_uint4(R.ref[cur], cb.w, s_first - first - 1, first);
       s_nseq += 1;
       s_slot = s_first;
     }
@@ -354,7 +382,7 @@ __global__ void __launch_bounds__(kBlock) k_reduce(uint32_t nsets, const uint64_
   }
   // payload bits per sequence (zero past the last), for the offset scan
   uint64_t* bits = w.leaf_bits + S.leaf_off;
-  for (uint32_t i = threadIdx.x; i < B; i += kBlock) {
+  for (uint32_t i = threadIdx.x; i < B; i += kRedBlock) {
     uint64_t v = 0;
     if (i < nseq) {
       const uint4 q = R.seq[i];
@@ -482,8 +510,19 @@ __global__ void __launch_bounds__(kBlock) k_red_perm(uint32_t nsets, const uint6
 
 hipError_t launch_reduce(const BatchPlan& bp, const Ws& w, hipStream_t s) {
   if (!bp.reduce) return hipGetLastError();
+  // the on-chip variant keeps 24 bytes per box: above the default 64 KB of
+  // dynamic LDS, so its limit is raised once (gfx950 has 160 KB per CU)
+  static hipError_t lds_set = hipFuncSetAttribute(
+      (const void*)k_reduce<true>, hipFuncAttributeMaxDynamicSharedMemorySize, 24 * kRedLdsBoxes);
+  if (lds_set != hipSuccess) return lds_set;
   if (bp.g_rp > 0) BBX_LAUNCH("reduce_prep", k_red_prep, bp.g_rp, kBlock, 0, s, bp.nsets, w.pre + bp.o_rp, w);
-  if (bp.g_rl > 0) BBX_LAUNCH("reduce", k_reduce, bp.g_rl, kBlock, 0, s, bp.nsets, w.pre + bp.o_rl, w);
+  if (bp.g_rl > 0) {
+    if (bp.red_lds_boxes)
+      BBX_LAUNCH("reduce", k_reduce<true>, bp.g_rl, kRedBlock, (size_t)24 * kRedLdsBoxes, s, bp.nsets,
+                 w.pre + bp.o_rl, w);
+    if (bp.red_global)
+      BBX_LAUNCH("reduce", k_reduce<false>, bp.g_rl, kRedBlock, 0, s, bp.nsets, w.pre + bp.o_rl, w);
+  }
   return hipGetLastError();
 }
 
