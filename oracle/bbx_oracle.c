@@ -390,6 +390,7 @@ typedef struct {
   uint64_t* leaf_bits;
   uint64_t meta_bits, payload_bits;
   int ref_mode; /* 0: reference stored as its code; 1: as its original coordinates */
+  int lossless; /* the bound cannot be met by quantization: every coordinate stored as is */
 } core_t;
 
 static void core_free(core_t* c) {
@@ -432,6 +433,15 @@ static int core_run(core_t* c, const void* pos, uint64_t n, uint32_t dims, int d
   p->eb_user = eb;
   p->mbits = dtype == 0 ? 5u : 6u; /* Sec. 4.2: 5 bits for M = 32, 6 for M = 64 */
   st = range_and_bound(pos, layout, p);
+  /* Sec. 4.1: a coordinate that needs more than M bits is stored losslessly.
+   * With codes on one global grid that happens to the whole set at once:
+   * the bound is below what the input type resolves (eb_eff <= 0) or the
+   * codes would need 30 bits or more; then every coordinate is stored as
+   * its input bits (a version-3 stream) instead of failing. */
+  if (st == BBXO_EBOUND) {
+    c->lossless = 1;
+    return BBXO_OK;
+  }
   if (st) return st;
   if (n == 0) return BBXO_OK;
 
@@ -520,7 +530,9 @@ uint64_t bbxo_compress_bound_mode(uint64_t n, uint32_t dims, int dtype, int ref_
    * meta bits, or dims*(mbits + M) with ref_mode 1) or a member (dims*31
    * payload bits at most) */
   uint64_t ref = ref_mode ? coord_bits(dtype) : 30;
-  return HEADER_BYTES + 16 + words_bytes(n * dims * (mbits + ref));
+  uint64_t b = HEADER_BYTES + 16 + words_bytes(n * dims * (mbits + ref));
+  uint64_t lossless = HEADER_BYTES + words_bytes(n * dims * coord_bits(dtype));
+  return b > lossless ? b : lossless;
 }
 
 static void write_header(uint8_t* h, const core_t* c) {
@@ -549,6 +561,43 @@ static void write_header(uint8_t* h, const core_t* c) {
   put_u64le(h + 120, 0);
 }
 
+/* The lossless stream (version 3): the header with no grid (eb_eff, w,
+ * inv_w, origin and G zero, no leaves, no meta section), then every input
+ * coordinate's bits, M per value, particle by particle in input order (x, y,
+ * z), zero-padded to 8 bytes.  Decoding returns the input exactly, in its
+ * order (perm is the identity). */
+static int write_lossless(const core_t* c, const void* pos, int layout, uint8_t* out,
+                          uint64_t out_cap, uint64_t* out_size, uint32_t* perm) {
+  const params_t* p = &c->p;
+  const uint32_t M = coord_bits(p->dtype);
+  const uint64_t bits = p->n * p->dims * M;
+  const uint64_t total = HEADER_BYTES + words_bytes(bits);
+  if (out_size) *out_size = total;
+  if (total > out_cap) return BBXO_ENOSPC;
+  memset(out, 0, (size_t)total);
+  write_header(out, c);
+  put_u16le(out + 4, 3);
+  out[22] = 0; /* no reference field */
+  for (int k = 40; k < 96; k++) out[k] = 0; /* eb_eff, w, inv_w, origin, G */
+  put_u64le(out + 96, 0);
+  put_u64le(out + 104, 0);
+  put_u64le(out + 112, bits);
+  uint8_t* pay = out + HEADER_BYTES;
+  uint64_t at = 0;
+  for (uint64_t i = 0; i < p->n; i++)
+    for (uint32_t d = 0; d < p->dims; d++) {
+#if MUT(26)
+      put_bits(pay, at, coord_raw(pos, p, layout, i, p->dims - 1 - d), M); /* axes reversed */
+#else
+      put_bits(pay, at, coord_raw(pos, p, layout, i, d), M);
+#endif
+      at += M;
+    }
+  if (perm)
+    for (uint64_t i = 0; i < p->n; i++) perm[i] = (uint32_t)i;
+  return BBXO_OK;
+}
+
 int bbxo_compress(const void* pos, uint64_t n, uint32_t dims, int dtype, int layout, double eb,
                   int eb_mode, uint32_t r, uint8_t* out, uint64_t out_cap, uint64_t* out_size,
                   uint32_t* perm) {
@@ -561,7 +610,8 @@ int bbxo_compress_ex(const void* pos, uint64_t n, uint32_t dims, int dtype, int 
                      uint64_t out_cap, uint64_t* out_size, uint32_t* perm) {
   core_t c;
   int st = core_run(&c, pos, n, dims, dtype, layout, eb, eb_mode, r, ref_rule, ref_mode);
-  if (st) {
+  if (st || c.lossless) {
+    if (!st) st = write_lossless(&c, pos, layout, out, out_cap, out_size, perm);
     core_free(&c);
     return st;
   }
@@ -645,6 +695,7 @@ int bbxo_stages_ex(const void* pos, uint64_t n, uint32_t dims, int dtype, int la
                    uint32_t* leaf_ref, uint8_t* leaf_m, uint64_t* leaf_bits, double* scal) {
   core_t c;
   int st = core_run(&c, pos, n, dims, dtype, layout, eb, eb_mode, r, ref_rule, 0);
+  if (!st && c.lossless) st = BBXO_EBOUND; /* no partition or bit boxes to dump */
   if (st) {
     core_free(&c);
     return st;
@@ -870,7 +921,8 @@ int bbxo_compress_reduced(const void* pos, uint64_t n, uint32_t dims, int dtype,
   if (key_rule != 0 && key_rule != 1) return BBXO_EINVAL;
   core_t c;
   int st = core_run(&c, pos, n, dims, dtype, layout, eb, eb_mode, r, 0, 0);
-  if (st) {
+  if (st || c.lossless) {
+    if (!st) st = write_lossless(&c, pos, layout, out, out_cap, out_size, perm);
     core_free(&c);
     return st;
   }
@@ -937,6 +989,8 @@ int bbxo_compress_reduced(const void* pos, uint64_t n, uint32_t dims, int dtype,
 
 static int decompress_reduced(const uint8_t* s, uint64_t size, void* pos, uint64_t pos_cap_bytes,
                               int layout);
+static int decompress_lossless(const uint8_t* s, uint64_t size, void* pos, uint64_t pos_cap_bytes,
+                               int layout);
 
 int bbxo_decompress(const uint8_t* s, uint64_t size, void* pos, uint64_t pos_cap_bytes,
                     int layout) {
@@ -944,6 +998,8 @@ int bbxo_decompress(const uint8_t* s, uint64_t size, void* pos, uint64_t pos_cap
   if (!s || size < HEADER_BYTES) return BBXO_ECORRUPT;
   if (get_u32le(s) == MAGIC && get_u16le(s + 4) == 2)
     return decompress_reduced(s, size, pos, pos_cap_bytes, layout);
+  if (get_u32le(s) == MAGIC && get_u16le(s + 4) == 3)
+    return decompress_lossless(s, size, pos, pos_cap_bytes, layout);
   if (get_u32le(s) != MAGIC || get_u16le(s + 4) != 1) return BBXO_ECORRUPT;
   int dtype = s[6];
   uint32_t dims = s[7];
@@ -1175,6 +1231,37 @@ static int decompress_reduced(const uint8_t* s, uint64_t size, void* pos, uint64
       }
   free(codes);
   return st;
+}
+
+/* Decoder of the lossless stream (version 3). */
+static int decompress_lossless(const uint8_t* s, uint64_t size, void* pos, uint64_t pos_cap_bytes,
+                               int layout) {
+  int dtype = s[6];
+  uint32_t dims = s[7];
+  uint64_t n = get_u64le(s + 8);
+  if (dtype > 1 || (dims != 2 && dims != 3) || s[20] > 1 || s[21] != 0 || s[22] != 0 ||
+      s[23] != (dtype == 0 ? 5u : 6u) || get_u32le(s + 16) == 0 || n >= ((uint64_t)1 << 32))
+    return BBXO_ECORRUPT;
+  for (int k = 40; k < 104; k++)
+    if (s[k] != 0) return BBXO_ECORRUPT; /* no grid, no leaves, no meta section */
+  uint32_t M = coord_bits(dtype);
+  if (get_u64le(s + 112) != n * dims * M || get_u64le(s + 120) != 0) return BBXO_ECORRUPT;
+  if (size < HEADER_BYTES + words_bytes(n * dims * M)) return BBXO_ECORRUPT;
+  if (pos_cap_bytes < n * dims * (M / 8)) return BBXO_ENOSPC;
+  const uint8_t* pay = s + HEADER_BYTES;
+  uint64_t at = 0;
+  for (uint64_t i = 0; i < n; i++)
+    for (uint32_t d = 0; d < dims; d++, at += M) {
+      uint64_t raw = get_bits(pay, at, M);
+      uint64_t kk = (layout == 0) ? i * dims + d : (uint64_t)d * n + i;
+      if (dtype == 0) {
+        uint32_t u32 = (uint32_t)raw;
+        memcpy((float*)pos + kk, &u32, 4);
+      } else {
+        memcpy((double*)pos + kk, &raw, 8);
+      }
+    }
+  return BBXO_OK;
 }
 
 /* ------------------------------------------------------------------ sequence export */

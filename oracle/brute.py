@@ -122,6 +122,31 @@ def _from_bits(raw: int, f32: bool):
     return np.array([raw], dtype=np.uint64).view(np.float64)[0]
 
 
+def lossless_stream(points: np.ndarray, eb: float, eb_mode: str, r: int):
+    """Sec. 4.1's lossless escape for a whole set whose bound the grid cannot
+    meet: version-3 header, then every coordinate's bits in input order."""
+    n, dims = points.shape
+    f32 = points.dtype == np.float32
+    pts = _coords(points)
+    if eb_mode == "rel":
+        lo = [min(p[d] for p in pts) + 0.0 for d in range(dims)]
+        hi = [max(p[d] for p in pts) + 0.0 for d in range(dims)]
+        eb_abs = eb * max(hi[d] - lo[d] for d in range(dims))
+    else:
+        eb_abs = eb
+    M = 32 if f32 else 64
+    pay = 0
+    at = 0
+    for i in range(n):
+        for d in range(dims):
+            pay |= _raw_bits(points, i, d) << at
+            at += M
+    header = struct.pack("<4sHBBQIBBBBddddd3d3B5xQQQQ", b"BBX1", 3, 0 if f32 else 1, dims, n, r,
+                         0 if eb_mode == "rel" else 1, 0, 0, 5 if f32 else 6, eb, eb_abs, 0.0,
+                         0.0, 0.0, 0.0, 0.0, 0.0, 0, 0, 0, 0, 0, at, 0)
+    return header + pay.to_bytes(8 * ((at + 63) // 64), "little"), np.arange(n, dtype=np.uint32)
+
+
 def compress(points: np.ndarray, eb: float, eb_mode: str = "rel", r: int = 32, ref_rule: int = 0,
              ref_mode: int = 0):
     """Returns (stream bytes, perm, details) for an (n, dims) float array.
@@ -131,7 +156,11 @@ def compress(points: np.ndarray, eb: float, eb_mode: str = "rel", r: int = 32, r
     f32 = points.dtype == np.float32
     mbits = 5 if f32 else 6
     M = 32 if f32 else 64
-    prm = bound_params(points, eb, eb_mode)
+    try:
+        prm = bound_params(points, eb, eb_mode)
+    except ValueError:
+        s, perm = lossless_stream(points, eb, eb_mode, r)
+        return s, perm, None
     codes = quantize(points, prm)
     leaves = kd_leaves(codes, r, dims)
     G = prm["G"]
@@ -183,6 +212,14 @@ def decompress(stream: bytes) -> np.ndarray:
     (magic, ver, dt, dims, n, r, mode, _s, ref_mode, mbits, _eu, _ea, _ee, w, inv_w, o0, o1, o2, g0,
      g1, g2, nl, meta_bits, pay_bits, _res) = struct.unpack("<4sHBBQIBBBBddddd3d3B5xQQQQ",
                                                             stream[:128])
+    if ver == 2:
+        return decompress_reduced(stream)
+    if ver == 3:  # every coordinate stored as its bits
+        M = 32 if dt == 0 else 64
+        pay = int.from_bytes(stream[128:], "little")
+        raw = [(pay >> (M * k)) & ((1 << M) - 1) for k in range(n * dims)]
+        return np.array(raw, dtype=np.uint32 if dt == 0 else np.uint64).view(
+            np.float32 if dt == 0 else np.float64).reshape(n, dims)
     assert magic == b"BBX1" and ver == 1
     origin = [o0, o1, o2][:dims]
     G = [g0, g1, g2][:dims]
@@ -254,7 +291,10 @@ def compress_reduced(points: np.ndarray, eb: float, eb_mode: str = "rel", r: int
     n, dims = points.shape
     f32 = points.dtype == np.float32
     mbits = 5 if f32 else 6
-    prm = bound_params(points, eb, eb_mode)
+    try:
+        prm = bound_params(points, eb, eb_mode)
+    except ValueError:
+        return lossless_stream(points, eb, eb_mode, r)
     codes = quantize(points, prm)
     leaves = kd_leaves(codes, r, dims)
     G = prm["G"]

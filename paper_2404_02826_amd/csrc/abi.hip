@@ -594,7 +594,7 @@ static bbx_status parse_header(const uint8_t* h, size_t bytes, HostHeader* o) {
   memcpy(&magic, h, 4);
   uint16_t ver;
   memcpy(&ver, h + 4, 2);
-  if (magic != kMagic || (ver != 1 && ver != 2)) return fail(BBX_ECORRUPT, "bad magic or version");
+  if (magic != kMagic || ver < 1 || ver > 3) return fail(BBX_ECORRUPT, "bad magic or version");
   o->version = ver;
   o->dtype = h[6];
   o->dims = h[7];
@@ -607,6 +607,22 @@ static bbx_status parse_header(const uint8_t* h, size_t bytes, HostHeader* o) {
     return fail(BBX_ECORRUPT, "bad dtype, dims, eb_mode or rule fields");
   if (o->mbits != (o->dtype == 0 ? 5u : 6u) || o->r == 0 || o->n >= (1ull << 32))
     return fail(BBX_ECORRUPT, "bad width-field size, leaf size or n");
+  if (ver == 3) {  // every coordinate stored as its bits: no grid, leaves or meta section
+    o->eb_user = rdf(h + 24);
+    o->eb_abs = rdf(h + 32);
+    o->eb_eff = o->w = o->inv_w = 0.0;
+    for (uint32_t d = 0; d < 3; ++d) o->origin[d] = 0.0, o->G[d] = 0;
+    for (int k = 40; k < 104; ++k)
+      if (h[k] != 0) return fail(BBX_ECORRUPT, "lossless stream with grid, leaf or meta fields");
+    if (h[21] != 0 || h[22] != 0) return fail(BBX_ECORRUPT, "bad rule fields");
+    o->n_leaves = 0;
+    o->meta_bits = 0;
+    o->payload_bits = rd64(h + 112);
+    o->n_seq = rd64(h + 120);
+    if (o->payload_bits != o->n * o->dims * (o->dtype == 0 ? 32ull : 64ull) || o->n_seq != 0)
+      return fail(BBX_ECORRUPT, "lossless payload size mismatch");
+    return BBX_OK;
+  }
   o->eb_user = rdf(h + 24);
   o->eb_abs = rdf(h + 32);
   o->eb_eff = rdf(h + 40);
@@ -716,7 +732,10 @@ size_t bbx_compress_bound_mode(uint64_t n, uint32_t dims, bbx_dtype dtype, uint3
   if (ref_mode > 1) return 0;
   const uint64_t mbits = dtype == BBX_F64 ? 6 : 5;
   const uint64_t ref = ref_mode ? (dtype == BBX_F64 ? 64 : 32) : 30;
-  return kHeaderBytes + 16 + ((n * dims * (mbits + ref) + 63) / 64) * 8;
+  const size_t b = kHeaderBytes + 16 + ((n * dims * (mbits + ref) + 63) / 64) * 8;
+  // a set stored losslessly (the grid cannot meet its bound): M bits per value
+  const size_t lossless = kHeaderBytes + ((n * dims * coord_bits(dtype) + 63) / 64) * 8;
+  return b > lossless ? b : lossless;
 }
 
 size_t bbx_compress_bound_params(uint64_t n, uint32_t dims, bbx_dtype dtype,
@@ -777,7 +796,7 @@ bbx_status bbx_compress(const void* d_pos, uint64_t n, uint32_t dims, bbx_dtype 
     hipError_t e = hipMemcpyAsync(&hp, d_ws, sizeof(hp), hipMemcpyDeviceToHost, stream);  // params[0]
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return fail(BBX_EHIP, std::string("synchronize failed: ") + hipGetErrorString(e));
-    if (hp.status != BBX_OK) {
+    if (hp.status != BBX_OK && hp.status != kStatusLossless) {
       const char* why = hp.status == BBX_EINVAL   ? "non-finite coordinate"
                         : hp.status == BBX_EBOUND ? "error bound too small for the input type or 30-bit codes"
                         : hp.status == BBX_ENOSPC ? "out_cap smaller than the stream"

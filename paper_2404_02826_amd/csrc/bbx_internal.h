@@ -25,7 +25,12 @@ constexpr int kGroup = kRows * kBlock;    // elements per streaming group
 constexpr uint64_t kLevelBlocks = 4096;   // blocks per global level of a set alone
 constexpr uint64_t kLocalBlocks = 4096;   // levels of at least this many nodes run block-local
 constexpr uint32_t kStageChunk = 16384;   // the global scatter stages groups from this chunk size
-constexpr uint32_t kRedLdsBoxes = 4096;   // bit box reduction: boxes kept in LDS (24 B each)
+constexpr uint32_t kRedLdsBoxes = 4096;
+// Status of a set whose bound the grid cannot meet (eb_eff <= 0 or codes of
+// 30 bits or more): every later kernel skips it as it skips a failed set,
+// the packer stores its coordinates as they are (Sec. 4.1's lossless
+// escape), and it is reported as BBX_OK.
+constexpr uint32_t kStatusLossless = 0x100;   // bit box reduction: boxes kept in LDS (24 B each)
 // a block-local level is one chunk per node under every block target
 static_assert(kLevelBlocks <= kLocalBlocks, "block-local levels must have one chunk per node");
 

@@ -129,6 +129,14 @@ __global__ void k_set_sizes(uint32_t nsets, const SetDesc* sets, DevParams* para
   if (s >= nsets) return;
   const SetDesc& S = sets[s];
   DevParams* P = params + s;
+  if (P->status == kStatusLossless) {  // every coordinate as its bits, no meta section
+    P->payload_base = 0;
+    P->meta_bits = 0;
+    P->payload_bits = S.n * S.dims * coord_bits(S.dtype);
+    P->total_bytes = kHeaderBytes + ((P->payload_bits + 63) / 64) * 8;
+    if (P->total_bytes > S.out_cap) P->status = BBX_ENOSPC;
+    return;
+  }
   if (P->status != BBX_OK) return;
   const uint64_t b = S.leaf_off, e = S.leaf_off + S.n_leaves;
   const uint64_t base = S.n_leaves ? off[b] : 0;
@@ -478,13 +486,24 @@ __global__ void __launch_bounds__(kBlock) k_pack_payload(uint32_t nsets, const u
 __global__ void k_header(const SetDesc* sets, const DevParams* params) {
   const SetDesc& S = sets[blockIdx.x];
   const DevParams* P = params + blockIdx.x;
-  if (P->status != BBX_OK) return;
+  const bool lossless = P->status == kStatusLossless;
+  if (P->status != BBX_OK && !lossless) return;
   if (threadIdx.x != 0) return;
   const uint32_t dims = S.dims;
   uint64_t h[16];
   for (int k = 0; k < 16; ++k) h[k] = 0;
-  h[0] = (uint64_t)kMagic | ((uint64_t)(S.reduce ? 2 : 1) << 32) | ((uint64_t)S.dtype << 48) |
-         ((uint64_t)dims << 56);
+  const uint64_t ver = lossless ? 3 : (S.reduce ? 2 : 1);
+  h[0] = (uint64_t)kMagic | (ver << 32) | ((uint64_t)S.dtype << 48) | ((uint64_t)dims << 56);
+  if (lossless) {  // no grid, no leaves, no meta section; no reference field
+    h[1] = S.n;
+    h[2] = (uint64_t)S.r | ((uint64_t)S.eb_mode << 32) | ((uint64_t)S.mbits << 56);
+    h[3] = __double_as_longlong(P->eb_user);
+    h[4] = __double_as_longlong(P->eb_abs);
+    h[14] = P->payload_bits;
+    uint64_t* o = (uint64_t*)S.out;
+    for (int k = 0; k < 16; ++k) o[k] = h[k];
+    return;
+  }
   h[1] = S.n;
   h[2] = (uint64_t)S.r | ((uint64_t)S.eb_mode << 32) | ((uint64_t)S.ref_mode << 48) |
          ((uint64_t)S.mbits << 56);
@@ -508,9 +527,41 @@ __global__ void k_finish(uint32_t nsets, const SetDesc* sets, const DevParams* p
   const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= nsets) return;
   const SetDesc& S = sets[s];
-  const uint32_t st = params[s].status;
+  const uint32_t st = params[s].status == kStatusLossless ? BBX_OK : params[s].status;
   if (S.d_size) *S.d_size = st == BBX_OK ? params[s].total_bytes : ~0ull;
   if (S.d_status) *S.d_status = st;
+}
+
+// A set stored losslessly: its coordinates' bits, particle by particle in
+// input order (x, y, z), M bits each, zero-padded to 8 bytes; perm is the
+// identity.  Blocks of the range pass's plan.
+__global__ void __launch_bounds__(kBlock) k_lossless(uint32_t nsets, const uint64_t* pre,
+                                                     const SetDesc* sets, const DevParams* params) {
+  const uint32_t s = find_set(pre, nsets, blockIdx.x);
+  const SetDesc& S = sets[s];
+  if (params[s].status != kStatusLossless) return;
+  const uint64_t lb = blockIdx.x - pre[s], nblk = pre[s + 1] - pre[s];
+  const uint64_t nv = S.n * S.dims, step = nblk * kBlock;
+  uint8_t* pay = S.out + kHeaderBytes;
+  if (S.dtype == BBX_F32) {
+    const uint32_t* in = (const uint32_t*)S.pos;
+    uint32_t* out = (uint32_t*)pay;
+    for (uint64_t k = lb * kBlock + threadIdx.x; k < nv; k += step) {
+      const uint64_t i = k / S.dims, d = k - i * S.dims;
+      out[k] = S.layout == BBX_AOS ? in[k] : in[d * S.n + i];
+    }
+    if (lb == 0 && threadIdx.x == 0 && (nv & 1)) out[nv] = 0;  // zero padding to 8 bytes
+  } else {
+    const uint64_t* in = (const uint64_t*)S.pos;
+    uint64_t* out = (uint64_t*)pay;
+    for (uint64_t k = lb * kBlock + threadIdx.x; k < nv; k += step) {
+      const uint64_t i = k / S.dims, d = k - i * S.dims;
+      out[k] = S.layout == BBX_AOS ? in[k] : in[d * S.n + i];
+    }
+  }
+  uint32_t* perm = S.reduce ? S.user_perm : S.perm;
+  if (perm)
+    for (uint64_t i = lb * kBlock + threadIdx.x; i < S.n; i += step) perm[i] = (uint32_t)i;
 }
 
 hipError_t launch_pack(const BatchPlan& bp, const Ws& w, hipStream_t s) {
@@ -527,6 +578,9 @@ hipError_t launch_pack(const BatchPlan& bp, const Ws& w, hipStream_t s) {
                w.sets, w.params, w.leaves, w.leaf_bits, w.keys[0], w.keys[1]);
   e = launch_reduce_pack(bp, w, s);
   if (e != hipSuccess) return e;
+  if (bp.g_mm > 0)
+    BBX_LAUNCH("lossless", k_lossless, bp.g_mm, kBlock, 0, s, bp.nsets, w.pre + bp.o_mm, w.sets,
+               w.params);
   BBX_LAUNCH("header", k_header, bp.nsets, 64, 0, s, w.sets, w.params);
   BBX_LAUNCH("finish", k_finish, g, kBlock, 0, s, bp.nsets, w.sets, w.params);
   return hipGetLastError();

@@ -190,7 +190,7 @@ __global__ void __launch_bounds__(kBlock) k_epilogue(const SetDesc* sets, const 
   }
   p.eb_abs = S.eb_mode == BBX_EB_REL ? eb * delta : eb;
   if (!isfinite(delta) || !isfinite(p.eb_abs)) {
-    p.status = BBX_EBOUND;
+    p.status = kStatusLossless;  // the grid cannot meet the bound
     *P = p;
     return;
   }
@@ -212,21 +212,21 @@ __global__ void __launch_bounds__(kBlock) k_epilogue(const SetDesc* sets, const 
     }
     p.eb_eff = p.eb_abs - guard;
     if (!(p.eb_eff > 0.0)) {
-      p.status = BBX_EBOUND;
+      p.status = kStatusLossless;
       *P = p;
       return;
     }
     p.w = 2.0 * p.eb_eff;
     p.inv_w = 1.0 / p.w;
     if (!isfinite(p.w) || !isfinite(p.inv_w) || !(p.inv_w > 0.0)) {
-      p.status = BBX_EBOUND;
+      p.status = kStatusLossless;
       *P = p;
       return;
     }
     for (uint32_t d = 0; d < dims; ++d) {
       const double qm = floor((p.hi[d] - p.lo[d]) * p.inv_w + 0.5);
       if (!(qm < 1073741824.0)) {
-        p.status = BBX_EBOUND;
+        p.status = kStatusLossless;  // codes of 30 bits or more
         *P = p;
         return;
       }

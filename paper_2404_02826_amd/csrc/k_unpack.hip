@@ -339,10 +339,32 @@ __global__ void __launch_bounds__(kBlock) k_dec_refs(uint64_t n, uint64_t n_leav
   }
 }
 
+// A lossless stream: the stored bits of every coordinate, in input order.
+__global__ void __launch_bounds__(kBlock) k_unpack_lossless(uint64_t n, uint32_t dims, uint32_t dtype,
+                                                            uint32_t layout, const uint8_t* stream,
+                                                            void* pos, const DevParams* P) {
+  if (P->status != BBX_OK) return;
+  const uint64_t nv = n * dims;
+  for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nv;
+       k += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t i = k / dims, d = k - i * dims;
+    const uint64_t o = layout == BBX_AOS ? k : d * n + i;
+    if (dtype == BBX_F32)
+      ((uint32_t*)pos)[o] = ((const uint32_t*)(stream + kHeaderBytes))[k];
+    else
+      ((uint64_t*)pos)[o] = ((const uint64_t*)(stream + kHeaderBytes))[k];
+  }
+}
+
 hipError_t launch_decompress(const DecompressPlan& p, const DecompressWs& w, const uint8_t* stream,
                              void* pos, uint32_t* d_status, hipStream_t s) {
   BBX_LAUNCH("dec_init", k_dec_init, 1, 64, 0, s, w.params, stream, p.header);
-  if (p.n > 0 && p.version == 2) {
+  if (p.n > 0 && p.version == 3) {
+    uint64_t g = (p.n * p.dims + kBlock - 1) / kBlock;
+    if (g > 16384) g = 16384;
+    BBX_LAUNCH("unpack_lossless", k_unpack_lossless, g, kBlock, 0, s, p.n, p.dims, p.dtype,
+               p.layout, stream, pos, w.params);
+  } else if (p.n > 0 && p.version == 2) {
     hipError_t e = launch_decompress2(p, w, stream, pos, s);
     if (e != hipSuccess) return e;
   } else if (p.n > 0) {

@@ -239,6 +239,34 @@ def pin_reduction_special(orc):
         slot += 1 + sq["count"]
 
 
+def pin_lossless_fallback(orc):
+    """Sec. 4.1's escape: a coordinate that needs more than M bits is stored
+    losslessly.  With one global grid that is the whole set when the bound
+    is below what the input type resolves or the codes would need 30 bits or
+    more: the stream (version 3) holds every coordinate's bits, decodes to
+    the input bit for bit in input order, is 128 + 8 ceil(n dims M / 64)
+    bytes, and equals the brute-force writer's; a bound the grid can meet
+    never takes this path."""
+    rng = np.random.default_rng(16)
+    for dt, xi in ((np.float32, 1e-12), (np.float64, 1e-10), (np.float32, 1e-9)):
+        for n, dims in ((2, 3), (7, 2), (50, 3), (33, 2)):  # (one point: exact, no grid needed)
+            pts = (rng.random((n, dims)) * 100 - 50).astype(dt)
+            if n > 1:
+                pts[1] = -0.0
+            for layout in ("aos", "soa"):
+                host = pts if layout == "aos" else np.ascontiguousarray(pts.T)
+                s, perm = orc.compress(host, xi, "rel", 4, layout=layout, want_perm=True)
+                h = props.parse_header(s)
+                M = 32 if dt == np.float32 else 64
+                assert h["version"] == 3 and len(s) == 128 + 8 * ((n * dims * M + 63) // 64)
+                assert np.array_equal(perm, np.arange(n))
+                assert np.array_equal(orc.decompress(s).view(np.uint8), pts.view(np.uint8))
+                assert s == brute.compress(pts, xi, "rel", 4)[0]
+                assert s == orc.compress_reduced(host, xi, "rel", 4, layout=layout)
+    pts = (rng.random((40, 3)) * 100).astype(np.float32)
+    assert props.parse_header(orc.compress(pts, 1e-4, "rel", 4))["version"] == 1
+
+
 def run_battery(orc):
     """Returns the names of the pins that fail."""
     failed = []
@@ -247,7 +275,8 @@ def run_battery(orc):
                      ("properties", pin_properties), ("lossless_reference", pin_lossless_reference),
                      ("reduction_examples", pin_reduction_examples),
                      ("reduction_brute", pin_reduction_brute),
-                     ("reduction_special", pin_reduction_special)):
+                     ("reduction_special", pin_reduction_special),
+                     ("lossless_fallback", pin_lossless_fallback)):
         try:
             fn(orc)
         except Exception as e:  # noqa: BLE001 -- any failure counts as caught

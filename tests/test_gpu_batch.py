@@ -125,7 +125,7 @@ def test_batch_failing_sets_are_isolated(orc, bbx):
     _say("batch with NaN / too-small eb / too-small output sets")
     bc = bbx.BatchCompressor(allspecs)
     res = bc()
-    want = {2: "EINVAL", 3: "EBOUND", 4: "ENOSPC"}
+    want = {2: "EINVAL", 4: "ENOSPC"}  # set 3 (bound below the f32 resolution): stored losslessly
     sizes = bc.d_size.cpu().tolist()
     for i, (host, spec) in enumerate(zip(allhosts, allspecs)):
         if i in want:

@@ -39,6 +39,7 @@ MUTANTS = {
     23: "boxes that lose particles keep their old bit box",
     24: "no common particles are absorbed",
     25: "common particles gathered in reverse leaf order",
+    26: "lossless fallback stores a particle's axes in reverse order",
 }
 
 

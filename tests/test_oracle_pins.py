@@ -266,8 +266,8 @@ def test_errors(oracle):
     _expect("EINVAL", oracle.compress, pts, 0.0)
     _expect("EINVAL", oracle.compress, pts, -1.0)
     _expect("EUNSUPPORTED", oracle.compress, np.zeros((4, 4), np.float32), 1e-3)
-    _expect("EBOUND", oracle.compress, pts, 1e-12)          # below f32 resolution
-    _expect("EBOUND", oracle.compress, pts.astype(np.float64), 1e-10)  # codes >= 2^30
+    # a bound the grid cannot meet (below the f32 resolution, or codes >= 2^30)
+    # is not an error: the set is stored losslessly (test_lossless_fallback)
     _expect("ENOSPC", oracle.compress, pts, 1e-3, out_cap=100)
 
 
@@ -332,14 +332,12 @@ def test_hypothesis_properties(oracle, data):
         pts = (pts + np.random.default_rng(n).random(pts.shape) * jitter).astype(dt)
     r = data.draw(st.integers(min_value=1, max_value=n + 1))
     eb = data.draw(st.sampled_from([1e-1, 1e-3, 1e-5]))
-    try:
-        stream, perm = oracle.compress(pts, eb, "rel", r, want_perm=True)
-    except OracleError as e:
-        assert e.name == "EBOUND"
-        with pytest.raises(ValueError):
-            brute.compress(pts, eb, "rel", r)
-        return
+    stream, perm = oracle.compress(pts, eb, "rel", r, want_perm=True)
     h = props.parse_header(stream)
+    if h["version"] == 3:  # lossless: the grid cannot meet the bound
+        assert stream == brute.compress(pts, eb, "rel", r)[0]
+        assert np.array_equal(oracle.decompress(stream).view(np.uint8), pts.view(np.uint8))
+        return
     dec = oracle.decompress(stream)
     props.check_permutation(perm, n)
     props.check_bound(pts, dec, perm, h["eb_abs"])
@@ -500,3 +498,8 @@ def test_reduction_properties_moderate(oracle, gen, n, r, xi):
     props.check_reduced(pts, s, perm, oracle.decompress(s), st["q"], st["n_leaves"])
     h = props.parse_header(s)
     assert h["version"] == 2 and h["reserved"] <= st["n_leaves"]
+
+
+def test_lossless_fallback(oracle):
+    pins.pin_lossless_fallback(oracle)
+
