@@ -160,7 +160,7 @@ static bbx_status check_set(const SetIn& in) {
 // Byte offsets of the batch workspace regions.
 struct WsLayout {
   size_t params, sets, pre, partials, keys[2], idx[2], hist, sel, rows, cb, leaves, bits, spart,
-      stotal, pneed, defer, red_tq, red_taken, red_slot, red_perm, red_key, red_ctr, red_ref, red_hits,
+      stotal, pneed, defer, lossless, red_tq, red_taken, red_slot, red_perm, red_key, red_ctr, red_ref, red_hits,
       red_seq, total;
 };
 
@@ -369,6 +369,7 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
   lay->stotal = c.take(8);
   lay->pneed = c.take(4 * 4 * kMaxDepth);
   lay->defer = c.take(4 * (bp->g_tile + 1));
+  lay->lossless = c.take(4 * (nsets + 1));
   const uint64_t rn = bp->reduce ? idx_n : 0, rlv = bp->reduce ? leaves_n : 0;
   lay->red_tq = c.take(16 * rn);
   lay->red_taken = c.take(rn);
@@ -402,6 +403,7 @@ static Ws carve_ws(const WsLayout& L, uint8_t* base) {
   w.scan_total = (uint64_t*)(base + L.stotal);
   w.pass_need = (uint32_t*)(base + L.pneed);
   w.tile_defer = (uint32_t*)(base + L.defer);
+  w.lossless = (uint32_t*)(base + L.lossless);
   w.red_tq = (uint4*)(base + L.red_tq);
   w.red_taken = base + L.red_taken;
   w.red_slot = (uint32_t*)(base + L.red_slot);

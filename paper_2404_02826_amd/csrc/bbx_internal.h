@@ -133,6 +133,7 @@ struct Ws {
   const uint64_t* pre;  // block-count prefix arrays (see BatchPlan)
   uint32_t* pass_need;  // [kMaxDepth][4]: some set runs mid pass p at depth k
   uint32_t* tile_defer; // [0] = count, then global tile indices left to the 32-bit tile pass
+  uint32_t* lossless;   // [0] = count, then the sets stored losslessly
   // bit box reduction (sets with reduce != 0), particle arrays at idx_off, leaf arrays at leaf_off
   uint4* red_tq;
   uint8_t* red_taken;

@@ -124,7 +124,8 @@ hipError_t launch_dec_scan(uint64_t count, uint64_t* bits, uint64_t* part, DevPa
 
 // per set: payload/meta bits, stream size, capacity check
 __global__ void k_set_sizes(uint32_t nsets, const SetDesc* sets, DevParams* params,
-                            const uint64_t* off, uint64_t total_leaves, const uint64_t* total) {
+                            const uint64_t* off, uint64_t total_leaves, const uint64_t* total,
+                            uint32_t* lossless) {
   const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= nsets) return;
   const SetDesc& S = sets[s];
@@ -134,7 +135,10 @@ __global__ void k_set_sizes(uint32_t nsets, const SetDesc* sets, DevParams* para
     P->meta_bits = 0;
     P->payload_bits = S.n * S.dims * coord_bits(S.dtype);
     P->total_bytes = kHeaderBytes + ((P->payload_bits + 63) / 64) * 8;
-    if (P->total_bytes > S.out_cap) P->status = BBX_ENOSPC;
+    if (P->total_bytes > S.out_cap)
+      P->status = BBX_ENOSPC;
+    else
+      lossless[1 + atomicAdd(lossless, 1u)] = s;  // for k_lossless
     return;
   }
   if (P->status != BBX_OK) return;
@@ -532,15 +536,7 @@ __global__ void k_finish(uint32_t nsets, const SetDesc* sets, const DevParams* p
   if (S.d_status) *S.d_status = st;
 }
 
-// A set stored losslessly: its coordinates' bits, particle by particle in
-// input order (x, y, z), M bits each, zero-padded to 8 bytes; perm is the
-// identity.  Blocks of the range pass's plan.
-__global__ void __launch_bounds__(kBlock) k_lossless(uint32_t nsets, const uint64_t* pre,
-                                                     const SetDesc* sets, const DevParams* params) {
-  const uint32_t s = find_set(pre, nsets, blockIdx.x);
-  const SetDesc& S = sets[s];
-  if (params[s].status != kStatusLossless) return;
-  const uint64_t lb = blockIdx.x - pre[s], nblk = pre[s + 1] - pre[s];
+__device__ void lossless_copy(const SetDesc& S, uint64_t lb, uint64_t nblk) {
   const uint64_t nv = S.n * S.dims, step = nblk * kBlock;
   uint8_t* pay = S.out + kHeaderBytes;
   if (S.dtype == BBX_F32) {
@@ -564,12 +560,25 @@ __global__ void __launch_bounds__(kBlock) k_lossless(uint32_t nsets, const uint6
     for (uint64_t i = lb * kBlock + threadIdx.x; i < S.n; i += step) perm[i] = (uint32_t)i;
 }
 
+// The sets stored losslessly (listed by k_set_sizes): their coordinates'
+// bits, particle by particle in input order (x, y, z), M bits each,
+// zero-padded to 8 bytes; perm is the identity.  A fixed grid shares each
+// listed set's copy; with no such set every block exits at once.
+constexpr uint32_t kLosslessBlocks = 256;
+__global__ void __launch_bounds__(kBlock) k_lossless(const SetDesc* sets, const uint32_t* list) {
+  const uint32_t count = list[0];
+  for (uint32_t li = 0; li < count; ++li) {
+    const SetDesc& S = sets[list[1 + li]];
+    lossless_copy(S, blockIdx.x, kLosslessBlocks);
+  }
+}
+
 hipError_t launch_pack(const BatchPlan& bp, const Ws& w, hipStream_t s) {
   hipError_t e = scan_launch(bp.total_leaves, w.leaf_bits, w.scan_part, w.scan_total, nullptr, 0, s);
   if (e != hipSuccess) return e;
   const uint32_t g = (bp.nsets + kBlock - 1) / kBlock;
   BBX_LAUNCH("set_sizes", k_set_sizes, g, kBlock, 0, s, bp.nsets, w.sets, w.params, w.leaf_bits,
-             bp.total_leaves, w.scan_total);
+             bp.total_leaves, w.scan_total, w.lossless);
   if (bp.g_pm > 0)
     BBX_LAUNCH("pack_meta", k_pack_meta, bp.g_pm, kBlock, 0, s, bp.nsets, w.pre + bp.o_pm, w.sets,
                w.params, w.leaves);
@@ -578,9 +587,7 @@ hipError_t launch_pack(const BatchPlan& bp, const Ws& w, hipStream_t s) {
                w.sets, w.params, w.leaves, w.leaf_bits, w.keys[0], w.keys[1]);
   e = launch_reduce_pack(bp, w, s);
   if (e != hipSuccess) return e;
-  if (bp.g_mm > 0)
-    BBX_LAUNCH("lossless", k_lossless, bp.g_mm, kBlock, 0, s, bp.nsets, w.pre + bp.o_mm, w.sets,
-               w.params);
+  BBX_LAUNCH("lossless", k_lossless, kLosslessBlocks, kBlock, 0, s, w.sets, w.lossless);
   BBX_LAUNCH("header", k_header, bp.nsets, 64, 0, s, w.sets, w.params);
   BBX_LAUNCH("finish", k_finish, g, kBlock, 0, s, bp.nsets, w.sets, w.params);
   return hipGetLastError();

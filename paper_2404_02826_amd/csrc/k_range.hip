@@ -366,6 +366,7 @@ hipError_t launch_range(const BatchPlan& bp, const Ws& w, hipStream_t s) {
   // every select kernel re-zeroes the bins it reads)
   if (bp.hist_entries > 0)
     BBX_LAUNCH("level_hist_zero", k_hist_zero, 1024, kBlock, 0, s, bp.hist_entries, w.hist);
+  BBX_LAUNCH("lossless_zero", k_hist_zero, 1, 64, 0, s, (uint64_t)1, w.lossless);  // list count
   if (bp.g_qz > 0)
     BBX_LAUNCH("quantize", k_quantize, bp.g_qz, kBlock, 0, s, bp.nsets, w.pre + bp.o_qz, w.sets,
                w.params, w.keys[0], w.idx[0], w.hist);
