@@ -242,7 +242,16 @@ typedef struct {
   uint32_t* leaf_size;
   uint64_t nleaves, cap;
   int fail;
+  int rule;         /* split rule, see kd_split */
+  uint64_t nb;      /* rule 2: leaves of the whole tree, ceil(n / r) */
 } tree_t;
+
+/* What a node knows besides its members: rule 2 the leaves [i0, i1) it will
+ * hold, rule 3 its cell, the codes lo[d] .. lo[d] + 2^lg[d] - 1 per axis. */
+typedef struct {
+  uint64_t i0, i1;
+  uint32_t lo[3], lg[3];
+} node_t;
 
 static int cmp_u64(const void* a, const void* b) {
   uint64_t x = *(const uint64_t*)a, y = *(const uint64_t*)b;
@@ -258,48 +267,159 @@ static uint64_t split_key(const tree_t* t, uint32_t i, uint32_t d) {
 #endif
 }
 
-/* Sec. 4.1: split the node order[start, start+s) at the median along one axis.
- * The element of rank floor(s/2) in (q_d, index) order and everything after
- * it form the right child ("median on the side with larger coordinates"); the
- * split is stable, so both children keep ascending original index. */
-static void kd_split(tree_t* t, uint64_t start, uint64_t s, uint32_t depth) {
-  uint32_t* S = t->order + start;
-#if MUT(12)
-  int leaf = (s < t->r) || s <= 1;
-#else
-  int leaf = (s <= t->r);
-#endif
-  if (leaf) {
-    if (t->nleaves >= t->cap) {
-      t->fail = 1;
-      return;
-    }
-    t->leaf_start[t->nleaves] = (uint32_t)start;
-    t->leaf_size[t->nleaves] = (uint32_t)s;
-    t->nleaves++;
+static void add_leaf(tree_t* t, uint64_t start, uint64_t s) {
+  if (t->nleaves >= t->cap) {
+    t->fail = 1;
     return;
+  }
+  t->leaf_start[t->nleaves] = (uint32_t)start;
+  t->leaf_size[t->nleaves] = (uint32_t)s;
+  t->nleaves++;
+}
+
+/* Stable split of S[0, s) along axis d at rank k: the member of rank k in
+ * (q_d, index) order and everything after it form the right child; both
+ * children keep ascending original index.  Returns the left size (k). */
+static uint64_t split_rank(tree_t* t, uint32_t* S, uint64_t s, uint32_t d, uint64_t k) {
+  for (uint64_t j = 0; j < s; j++) t->keys[j] = split_key(t, S[j], d);
+  qsort(t->keys, (size_t)s, sizeof(uint64_t), cmp_u64);
+#if MUT(1)
+  uint64_t med = k == s / 2 ? t->keys[(s - 1) / 2] + 1 : t->keys[k]; /* median joins the left */
+#else
+  uint64_t med = t->keys[k];
+#endif
+  uint64_t nl = 0;
+  for (uint64_t j = 0; j < s; j++)
+    if (split_key(t, S[j], d) < med) t->tmp[nl++] = S[j];
+  uint64_t m = nl;
+  for (uint64_t j = 0; j < s; j++)
+    if (!(split_key(t, S[j], d) < med)) t->tmp[m++] = S[j];
+  memcpy(S, t->tmp, (size_t)s * sizeof(uint32_t));
+  return nl;
+}
+
+/* Stable split of S[0, s) by value: codes q_d < mid go left. */
+static uint64_t split_value(tree_t* t, uint32_t* S, uint64_t s, uint32_t d, uint32_t mid) {
+  uint64_t nl = 0;
+  for (uint64_t j = 0; j < s; j++)
+#if MUT(29)
+    if (t->q[(uint64_t)d * t->n + S[j]] <= mid) t->tmp[nl++] = S[j];
+#else
+    if (t->q[(uint64_t)d * t->n + S[j]] < mid) t->tmp[nl++] = S[j];
+#endif
+  uint64_t m = nl;
+  for (uint64_t j = 0; j < s; j++)
+#if MUT(29)
+    if (!(t->q[(uint64_t)d * t->n + S[j]] <= mid)) t->tmp[m++] = S[j];
+#else
+    if (!(t->q[(uint64_t)d * t->n + S[j]] < mid)) t->tmp[m++] = S[j];
+#endif
+  memcpy(S, t->tmp, (size_t)s * sizeof(uint32_t));
+  return nl;
+}
+
+/* The axis along which the members' codes spread widest (max - min), the
+ * lowest axis on ties. */
+static uint32_t widest_axis(const tree_t* t, const uint32_t* S, uint64_t s) {
+  uint32_t best = 0;
+  uint64_t wbest = 0;
+  for (uint32_t d = 0; d < t->dims; d++) {
+    const uint32_t* qd = t->q + (uint64_t)d * t->n;
+    uint32_t lo = qd[S[0]], hi = qd[S[0]];
+    for (uint64_t j = 1; j < s; j++) {
+      if (qd[S[j]] < lo) lo = qd[S[j]];
+      if (qd[S[j]] > hi) hi = qd[S[j]];
+    }
+    uint64_t w = (uint64_t)(hi - lo);
+#if MUT(27)
+    if (d == 0 || w < wbest) best = d, wbest = w; /* the narrowest instead */
+#elif MUT(30)
+    if (d == 0 || w >= wbest) best = d, wbest = w; /* ties to the last axis */
+#else
+    if (d == 0 || w > wbest) best = d, wbest = w;
+#endif
+  }
+  return best;
+}
+
+/* Sec. 4.1 partition of the node order[start, start+s), depth-first, left
+ * child first.  The rule (header byte 21) picks how a node splits:
+ *   0  the paper's reading: halve until at most r particles, split at the
+ *      median along the axes in turn (depth mod dims); the member of rank
+ *      floor(s/2) in (q_d, index) order and everything after it form the
+ *      right child, the median on the side of larger coordinates;
+ *   1  as 0, along the axis of widest code extent among the node's members;
+ *   2  ceil(n / r) leaves of floor or ceil of n / ceil(n / r) particles: leaf
+ *      i holds the ranks floor(i n / b) .. floor((i + 1) n / b) - 1 of the
+ *      tree order, b = ceil(n / r); a node holding leaves [i0, i1) gives its
+ *      left child the first floor((i1 - i0) / 2) of them and splits at the
+ *      matching rank, along the axes in turn;
+ *   3  the midpoint (cell) split of the coders of Sec. 2.2: the root cell is
+ *      the whole code grid [0, 2^G_d) per axis, a node of more than r
+ *      particles halves its cell along the axes in turn, skipping axes whose
+ *      cell is one code wide (a node whose cell is a single code stays one
+ *      leaf), codes below the cell's midpoint go left, and an empty child
+ *      is no leaf.
+ * Every split is stable: both children keep ascending original index. */
+static void kd_split(tree_t* t, uint64_t start, uint64_t s, uint32_t depth, node_t nd) {
+  uint32_t* S = t->order + start;
+  int leaf;
+  if (t->rule == 2) {
+    leaf = nd.i1 - nd.i0 <= 1;
+  } else {
+#if MUT(12)
+    leaf = (s < t->r) || s <= 1;
+#else
+    leaf = (s <= t->r);
+#endif
   }
 #if MUT(3)
   uint32_t d = 0;
 #else
   uint32_t d = depth % t->dims; /* round-robin split axis */
 #endif
-  for (uint64_t j = 0; j < s; j++) t->keys[j] = split_key(t, S[j], d);
-  qsort(t->keys, (size_t)s, sizeof(uint64_t), cmp_u64);
-#if MUT(1)
-  uint64_t med = t->keys[(s - 1) / 2] + 1; /* median joins the left side */
-#else
-  uint64_t med = t->keys[s / 2];
+  if (!leaf && t->rule == 3) {
+    uint32_t k = 0;
+#if MUT(31)
+    if (nd.lg[d] == 0) k = t->dims; /* stops at the first one-code-wide axis */
 #endif
-  uint64_t nl = 0;
-  for (uint64_t j = 0; j < s; j++)
-    if (split_key(t, S[j], d) < med) t->tmp[nl++] = S[j];
-  uint64_t k = nl;
-  for (uint64_t j = 0; j < s; j++)
-    if (!(split_key(t, S[j], d) < med)) t->tmp[k++] = S[j];
-  memcpy(S, t->tmp, (size_t)s * sizeof(uint32_t));
-  kd_split(t, start, nl, depth + 1);
-  kd_split(t, start + nl, s - nl, depth + 1);
+    while (k < t->dims && nd.lg[(d + k) % t->dims] == 0) k++;
+    if (k == t->dims)
+      leaf = 1; /* a single code: nothing to split */
+    else
+      d = (d + k) % t->dims;
+  }
+  if (leaf) {
+    add_leaf(t, start, s);
+    return;
+  }
+  node_t L = nd, R = nd;
+  uint64_t nl;
+  if (t->rule == 3) {
+    uint32_t mid = nd.lo[d] + (1u << (nd.lg[d] - 1));
+    nl = split_value(t, S, s, d, mid);
+    L.lg[d] = R.lg[d] = nd.lg[d] - 1;
+    R.lo[d] = mid;
+    if (nl > 0) kd_split(t, start, nl, depth + 1, L);
+    if (s - nl > 0) kd_split(t, start + nl, s - nl, depth + 1, R);
+    return;
+  }
+  if (t->rule == 2) {
+#if MUT(28)
+    uint64_t im = nd.i0 + (nd.i1 - nd.i0 + 1) / 2; /* the left child takes the larger half */
+#else
+    uint64_t im = nd.i0 + (nd.i1 - nd.i0) / 2;
+#endif
+    uint64_t k = (im * t->n) / t->nb - (nd.i0 * t->n) / t->nb;
+    nl = split_rank(t, S, s, d, k);
+    L.i1 = im;
+    R.i0 = im;
+  } else {
+    if (t->rule == 1) d = widest_axis(t, S, s);
+    nl = split_rank(t, S, s, d, s / 2);
+  }
+  kd_split(t, start, nl, depth + 1, L);
+  kd_split(t, start + nl, s - nl, depth + 1, R);
 }
 
 /* The same recursion on sizes only (children floor(s/2), ceil(s/2)): the leaf
@@ -390,6 +510,7 @@ typedef struct {
   uint64_t* leaf_bits;
   uint64_t meta_bits, payload_bits;
   int ref_mode; /* 0: reference stored as its code; 1: as its original coordinates */
+  int split_rule; /* how nodes split (kd_split) */
   int lossless; /* the bound cannot be met by quantization: every coordinate stored as is */
 } core_t;
 
@@ -418,11 +539,22 @@ static int check_args(uint64_t n, uint32_t dims, int dtype, int layout, double e
   return BBXO_OK;
 }
 
+/* ceil(n / r): the leaves of split rule 2 */
+static uint64_t prop_leaf_count(uint64_t n, uint32_t r) {
+#if MUT(32)
+  return n / r ? n / r : 1;
+#else
+  return (n + r - 1) / r;
+#endif
+}
+
 static int core_run(core_t* c, const void* pos, uint64_t n, uint32_t dims, int dtype, int layout,
-                    double eb, int eb_mode, uint32_t r, int ref_rule, int ref_mode) {
+                    double eb, int eb_mode, uint32_t r, int ref_rule, int ref_mode, int split_rule) {
   memset(c, 0, sizeof(*c));
   int st = check_args(n, dims, dtype, layout, eb, eb_mode, r, ref_rule, ref_mode);
   if (st) return st;
+  if (split_rule < 0 || split_rule > 3) return BBXO_EINVAL;
+  c->split_rule = split_rule;
   c->ref_mode = ref_mode;
   params_t* p = &c->p;
   p->n = n;
@@ -445,7 +577,10 @@ static int core_run(core_t* c, const void* pos, uint64_t n, uint32_t dims, int d
   if (st) return st;
   if (n == 0) return BBXO_OK;
 
-  uint64_t nl = bbxo_leaf_count(n, r);
+  /* leaves at most: rules 0 and 1 the count of the size recursion, rule 2
+   * ceil(n / r), rule 3 one per particle (no leaf is empty) */
+  uint64_t nl = split_rule <= 1 ? bbxo_leaf_count(n, r)
+                                : (split_rule == 2 ? prop_leaf_count(n, r) : n);
   c->q = (uint32_t*)malloc((size_t)(n * dims) * sizeof(uint32_t));
   c->order = (uint32_t*)malloc((size_t)n * sizeof(uint32_t));
   c->leaf_start = (uint32_t*)malloc((size_t)nl * sizeof(uint32_t));
@@ -484,17 +619,29 @@ static int core_run(core_t* c, const void* pos, uint64_t n, uint32_t dims, int d
   t.leaf_start = c->leaf_start;
   t.leaf_size = c->leaf_size;
   t.cap = nl;
-  kd_split(&t, 0, n, 0);
+  t.rule = split_rule;
+  t.nb = prop_leaf_count(n, r);
+  node_t root;
+  memset(&root, 0, sizeof(root));
+  root.i1 = t.nb;
+  for (uint32_t d = 0; d < dims; d++) root.lg[d] = p->G[d];
+  kd_split(&t, 0, n, 0, root);
   c->nleaves = t.nleaves;
-  /* the partition must reproduce the size-only recursion exactly */
-  uint64_t k = 0;
-  size_leaves(n, r, sz, &k, nl);
-  int same = !t.fail && k == nl && t.nleaves == nl;
-  for (uint64_t i = 0; same && i < nl; i++) same = (sz[i] == c->leaf_size[i]);
+  int same = !t.fail;
+  if (split_rule <= 1) {
+    /* the partition must reproduce the size-only recursion exactly */
+    uint64_t k = 0;
+    size_leaves(n, r, sz, &k, nl);
+    same = same && k == nl && t.nleaves == nl;
+    for (uint64_t i = 0; same && i < nl; i++) same = (sz[i] == c->leaf_size[i]);
+  } else if (split_rule == 2) {
+    same = same && t.nleaves == nl;
+  }
   free(keys);
   free(tmp);
   free(sz);
   if (!same) return BBXO_ENOMEM; /* internal inconsistency: never expected */
+  nl = c->nleaves;
 
   /* Step 4: bit box of every leaf; Step 5: section sizes.  The reference
    * field of a meta record holds its code (G_d bits per axis), or with
@@ -545,7 +692,7 @@ static void write_header(uint8_t* h, const core_t* c) {
   put_u64le(h + 8, p->n);
   put_u32le(h + 16, p->r);
   h[20] = (uint8_t)p->eb_mode;
-  h[21] = 0; /* split rule: median, round-robin axis */
+  h[21] = (uint8_t)c->split_rule; /* how nodes split (kd_split); 0 in every version-1 stream */
   h[22] = (uint8_t)c->ref_mode; /* reference stored as its code (0) or coordinates (1) */
   h[23] = (uint8_t)p->mbits;
   put_f64le(h + 24, p->eb_user);
@@ -577,6 +724,7 @@ static int write_lossless(const core_t* c, const void* pos, int layout, uint8_t*
   memset(out, 0, (size_t)total);
   write_header(out, c);
   put_u16le(out + 4, 3);
+  out[21] = 0; /* no partition */
   out[22] = 0; /* no reference field */
   for (int k = 40; k < 96; k++) out[k] = 0; /* eb_eff, w, inv_w, origin, G */
   put_u64le(out + 96, 0);
@@ -609,7 +757,7 @@ int bbxo_compress_ex(const void* pos, uint64_t n, uint32_t dims, int dtype, int 
                      int eb_mode, uint32_t r, int ref_rule, int ref_mode, uint8_t* out,
                      uint64_t out_cap, uint64_t* out_size, uint32_t* perm) {
   core_t c;
-  int st = core_run(&c, pos, n, dims, dtype, layout, eb, eb_mode, r, ref_rule, ref_mode);
+  int st = core_run(&c, pos, n, dims, dtype, layout, eb, eb_mode, r, ref_rule, ref_mode, 0);
   if (st || c.lossless) {
     if (!st) st = write_lossless(&c, pos, layout, out, out_cap, out_size, perm);
     core_free(&c);
@@ -694,7 +842,7 @@ int bbxo_stages_ex(const void* pos, uint64_t n, uint32_t dims, int dtype, int la
                    uint64_t max_leaves, uint32_t* leaf_start, uint32_t* leaf_size,
                    uint32_t* leaf_ref, uint8_t* leaf_m, uint64_t* leaf_bits, double* scal) {
   core_t c;
-  int st = core_run(&c, pos, n, dims, dtype, layout, eb, eb_mode, r, ref_rule, 0);
+  int st = core_run(&c, pos, n, dims, dtype, layout, eb, eb_mode, r, ref_rule, 0, 0);
   if (!st && c.lossless) st = BBXO_EBOUND; /* no partition or bit boxes to dump */
   if (st) {
     core_free(&c);
@@ -812,7 +960,10 @@ static int reduce_boxes(const core_t* c, int key_rule, reduced_t* out) {
   memset(out, 0, sizeof(*out));
   rbox_t* box = (rbox_t*)calloc((size_t)(nl ? nl : 1), sizeof(rbox_t));
   uint8_t* taken = (uint8_t*)calloc((size_t)(n ? n : 1), 1);
-  uint32_t* mem = (uint32_t*)malloc((size_t)(c->p.r + 1) * sizeof(uint32_t));
+  uint64_t big = 1;
+  for (uint64_t b = 0; b < nl; b++)
+    if (c->leaf_size[b] > big) big = c->leaf_size[b];
+  uint32_t* mem = (uint32_t*)malloc((size_t)(big + 1) * sizeof(uint32_t));
   out->seq_center = (uint32_t*)malloc((size_t)(nl ? nl : 1) * sizeof(uint32_t));
   out->seq_m = (uint32_t*)malloc((size_t)(nl ? nl : 1) * 3 * sizeof(uint32_t));
   out->seq_count = (uint32_t*)malloc((size_t)(nl ? nl : 1) * sizeof(uint32_t));
@@ -909,18 +1060,99 @@ static int reduce_boxes(const core_t* c, int key_rule, reduced_t* out) {
   return BBXO_OK;
 }
 
-/* Stream of the reduced sequences (version 2 of the format): the v1 header
- * with version 2 and the sequence count in the last field; a meta record
- * per sequence (widths m_d in mbits bits, the centre's codes in G_d bits,
- * then the number of other particles in 32 bits: the end mark of Sec. 4.2
- * turned into a count); the payload holds each sequence's particles in
- * order, per axis q_d - c_d + 2^(m_d - 1) in m_d bits. */
-int bbxo_compress_reduced(const void* pos, uint64_t n, uint32_t dims, int dtype, int layout,
-                          double eb, int eb_mode, uint32_t r, int key_rule, uint8_t* out,
-                          uint64_t out_cap, uint64_t* out_size, uint32_t* perm) {
-  if (key_rule != 0 && key_rule != 1) return BBXO_EINVAL;
+/* Every leaf as one sequence, in leaf order: its reference, then its other
+ * members in ascending index (the stream of a partition without the
+ * reduction). */
+static int leaf_sequences(const core_t* c, reduced_t* out) {
+  const uint64_t n = c->p.n, nl = c->nleaves;
+  memset(out, 0, sizeof(*out));
+  out->seq_center = (uint32_t*)malloc((size_t)(nl ? nl : 1) * sizeof(uint32_t));
+  out->seq_m = (uint32_t*)malloc((size_t)(nl ? nl : 1) * 3 * sizeof(uint32_t));
+  out->seq_count = (uint32_t*)malloc((size_t)(nl ? nl : 1) * sizeof(uint32_t));
+  out->slot_src = (uint32_t*)malloc((size_t)(n ? n : 1) * sizeof(uint32_t));
+  if (!out->seq_center || !out->seq_m || !out->seq_count || !out->slot_src) {
+    reduced_free(out);
+    return BBXO_ENOMEM;
+  }
+  uint64_t slot = 0;
+  for (uint64_t b = 0; b < nl; b++) {
+    const uint32_t* L = c->order + c->leaf_start[b];
+    out->seq_center[b] = L[c->leaf_ref[b]];
+    for (int d = 0; d < 3; d++) out->seq_m[3 * b + d] = c->leaf_m[3 * b + d];
+    out->seq_count[b] = c->leaf_size[b] - 1;
+    out->slot_src[slot++] = L[c->leaf_ref[b]];
+    for (uint32_t j = 0; j < c->leaf_size[b]; j++)
+      if (j != c->leaf_ref[b]) out->slot_src[slot++] = L[j];
+  }
+  out->nseq = nl;
+  return BBXO_OK;
+}
+
+/* Stream of sequences (version 2 of the format): the v1 header with version
+ * 2, the split rule in byte 21, the partition's leaf count and the sequence
+ * count in the last field; a meta record per sequence (widths m_d in mbits
+ * bits, the centre's codes in G_d bits, then the number of other particles
+ * in 32 bits: the end mark of Sec. 4.2 turned into a count); the payload
+ * holds each sequence's particles in order, per axis q_d - c_d + 2^(m_d - 1)
+ * in m_d bits. */
+static int write_sequences(core_t* c, const reduced_t* R, uint8_t* out, uint64_t out_cap,
+                           uint64_t* out_size, uint32_t* perm) {
+  const params_t* p = &c->p;
+  const uint64_t n = p->n;
+  const uint32_t dims = p->dims;
+  uint32_t sumG = 0;
+  for (uint32_t d = 0; d < dims; d++) sumG += p->G[d];
+  uint64_t meta_bits = R->nseq * (uint64_t)(dims * p->mbits + sumG + 32), payload_bits = 0;
+  for (uint64_t s = 0; s < R->nseq; s++) {
+    uint32_t sm = 0;
+    for (uint32_t d = 0; d < dims; d++) sm += R->seq_m[3 * s + d];
+    payload_bits += (uint64_t)R->seq_count[s] * sm;
+  }
+  uint64_t mb = words_bytes(meta_bits), pb = words_bytes(payload_bits);
+  uint64_t total = HEADER_BYTES + mb + pb;
+  if (out_size) *out_size = total;
+  if (total > out_cap) return BBXO_ENOSPC;
+  memset(out, 0, (size_t)total);
+  c->meta_bits = meta_bits;
+  c->payload_bits = payload_bits;
+  write_header(out, c);
+  put_u16le(out + 4, 2);
+  put_u64le(out + 120, R->nseq);
+  uint8_t* meta = out + HEADER_BYTES;
+  uint8_t* pay = meta + mb;
+  uint64_t mpos = 0, ppos = 0, slot = 0;
+  for (uint64_t s = 0; s < R->nseq; s++) {
+    const uint32_t* m = R->seq_m + 3 * s;
+    uint32_t ctr = R->seq_center[s];
+    for (uint32_t d = 0; d < dims; d++) put_bits(meta, mpos, m[d], p->mbits), mpos += p->mbits;
+    for (uint32_t d = 0; d < dims; d++)
+      put_bits(meta, mpos, c->q[(uint64_t)d * n + ctr], p->G[d]), mpos += p->G[d];
+    put_bits(meta, mpos, R->seq_count[s], 32), mpos += 32;
+    slot++; /* the centre */
+    for (uint32_t j = 0; j < R->seq_count[s]; j++, slot++) {
+      uint32_t i = R->slot_src[slot];
+      for (uint32_t d = 0; d < dims; d++) {
+        if (m[d] == 0) continue;
+        int64_t o = (int64_t)c->q[(uint64_t)d * n + i] - (int64_t)c->q[(uint64_t)d * n + ctr];
+        put_bits(pay, ppos, (uint64_t)(o + ((int64_t)1 << (m[d] - 1))), m[d]);
+        ppos += m[d];
+      }
+    }
+  }
+  if (perm && n) memcpy(perm, R->slot_src, (size_t)n * sizeof(uint32_t));
+  return BBXO_OK;
+}
+
+int bbxo_compress_split(const void* pos, uint64_t n, uint32_t dims, int dtype, int layout,
+                        double eb, int eb_mode, uint32_t r, int split_rule, int ref_rule,
+                        int reduce, uint8_t* out, uint64_t out_cap, uint64_t* out_size,
+                        uint32_t* perm) {
+  if (reduce < 0 || reduce > 2 || split_rule < 0 || split_rule > 3) return BBXO_EINVAL;
+  if (split_rule == 0 && reduce == 0)
+    return bbxo_compress_ex(pos, n, dims, dtype, layout, eb, eb_mode, r, ref_rule, 0, out, out_cap,
+                            out_size, perm);
   core_t c;
-  int st = core_run(&c, pos, n, dims, dtype, layout, eb, eb_mode, r, 0, 0);
+  int st = core_run(&c, pos, n, dims, dtype, layout, eb, eb_mode, r, ref_rule, 0, split_rule);
   if (st || c.lossless) {
     if (!st) st = write_lossless(&c, pos, layout, out, out_cap, out_size, perm);
     core_free(&c);
@@ -929,60 +1161,24 @@ int bbxo_compress_reduced(const void* pos, uint64_t n, uint32_t dims, int dtype,
   reduced_t R;
   memset(&R, 0, sizeof(R));
   if (n > 0) {
-    st = reduce_boxes(&c, key_rule, &R);
+    st = reduce ? reduce_boxes(&c, reduce - 1, &R) : leaf_sequences(&c, &R);
     if (st) {
       core_free(&c);
       return st;
     }
   }
-  const params_t* p = &c.p;
-  uint32_t sumG = 0;
-  for (uint32_t d = 0; d < dims; d++) sumG += p->G[d];
-  uint64_t meta_bits = R.nseq * (uint64_t)(dims * p->mbits + sumG + 32), payload_bits = 0;
-  for (uint64_t s = 0; s < R.nseq; s++) {
-    uint32_t sm = 0;
-    for (uint32_t d = 0; d < dims; d++) sm += R.seq_m[3 * s + d];
-    payload_bits += (uint64_t)R.seq_count[s] * sm;
-  }
-  uint64_t mb = words_bytes(meta_bits), pb = words_bytes(payload_bits);
-  uint64_t total = HEADER_BYTES + mb + pb;
-  if (out_size) *out_size = total;
-  if (total > out_cap) {
-    reduced_free(&R);
-    core_free(&c);
-    return BBXO_ENOSPC;
-  }
-  memset(out, 0, (size_t)total);
-  c.meta_bits = meta_bits;
-  c.payload_bits = payload_bits;
-  write_header(out, &c);
-  put_u16le(out + 4, 2);
-  put_u64le(out + 120, R.nseq);
-  uint8_t* meta = out + HEADER_BYTES;
-  uint8_t* pay = meta + mb;
-  uint64_t mpos = 0, ppos = 0, slot = 0;
-  for (uint64_t s = 0; s < R.nseq; s++) {
-    const uint32_t* m = R.seq_m + 3 * s;
-    uint32_t ctr = R.seq_center[s];
-    for (uint32_t d = 0; d < dims; d++) put_bits(meta, mpos, m[d], p->mbits), mpos += p->mbits;
-    for (uint32_t d = 0; d < dims; d++)
-      put_bits(meta, mpos, c.q[(uint64_t)d * n + ctr], p->G[d]), mpos += p->G[d];
-    put_bits(meta, mpos, R.seq_count[s], 32), mpos += 32;
-    slot++; /* the centre */
-    for (uint32_t j = 0; j < R.seq_count[s]; j++, slot++) {
-      uint32_t i = R.slot_src[slot];
-      for (uint32_t d = 0; d < dims; d++) {
-        if (m[d] == 0) continue;
-        int64_t o = (int64_t)c.q[(uint64_t)d * n + i] - (int64_t)c.q[(uint64_t)d * n + ctr];
-        put_bits(pay, ppos, (uint64_t)(o + ((int64_t)1 << (m[d] - 1))), m[d]);
-        ppos += m[d];
-      }
-    }
-  }
-  if (perm && n) memcpy(perm, R.slot_src, (size_t)n * sizeof(uint32_t));
+  st = write_sequences(&c, &R, out, out_cap, out_size, perm);
   reduced_free(&R);
   core_free(&c);
-  return BBXO_OK;
+  return st;
+}
+
+int bbxo_compress_reduced(const void* pos, uint64_t n, uint32_t dims, int dtype, int layout,
+                          double eb, int eb_mode, uint32_t r, int key_rule, uint8_t* out,
+                          uint64_t out_cap, uint64_t* out_size, uint32_t* perm) {
+  if (key_rule != 0 && key_rule != 1) return BBXO_EINVAL;
+  return bbxo_compress_split(pos, n, dims, dtype, layout, eb, eb_mode, r, 0, 0, key_rule + 1, out,
+                             out_cap, out_size, perm);
 }
 
 /* ------------------------------------------------------------------ decompress */
@@ -1155,7 +1351,8 @@ static int decompress_reduced(const uint8_t* s, uint64_t size, void* pos, uint64
   uint64_t n = get_u64le(s + 8);
   uint32_t r = get_u32le(s + 16);
   uint32_t eb_mode = s[20], mbits = s[23];
-  if (dtype > 1 || (dims != 2 && dims != 3) || eb_mode > 1 || s[21] != 0 || s[22] != 0)
+  const uint32_t rule = s[21];
+  if (dtype > 1 || (dims != 2 && dims != 3) || eb_mode > 1 || rule > 3 || s[22] != 0)
     return BBXO_ECORRUPT;
   if (mbits != (dtype == 0 ? 5u : 6u) || r == 0 || n >= ((uint64_t)1 << 32)) return BBXO_ECORRUPT;
   double w = get_f64le(s + 48), inv_w = get_f64le(s + 56);
@@ -1173,7 +1370,11 @@ static int decompress_reduced(const uint8_t* s, uint64_t size, void* pos, uint64
     if (s[k] != 0) return BBXO_ECORRUPT;
   uint64_t nl = get_u64le(s + 96), meta_bits = get_u64le(s + 104), payload_bits = get_u64le(s + 112);
   uint64_t nseq = get_u64le(s + 120);
-  if (nl != bbxo_leaf_count(n, r) || nseq > nl || (n > 0 && nseq == 0)) return BBXO_ECORRUPT;
+  /* the partition's leaf count: fixed by (n, r) for rules 0 to 2, at most
+   * one per particle for rule 3 */
+  uint64_t want = rule <= 1 ? bbxo_leaf_count(n, r) : prop_leaf_count(n, r);
+  if (rule == 3 ? (nl > n || (n > 0 && nl == 0)) : nl != want) return BBXO_ECORRUPT;
+  if (nseq > nl || (n > 0 && nseq == 0)) return BBXO_ECORRUPT;
   if (meta_bits != nseq * (uint64_t)(dims * mbits + sumG + 32)) return BBXO_ECORRUPT;
   if (payload_bits > n * (uint64_t)dims * 31u) return BBXO_ECORRUPT;
   uint64_t mb = words_bytes(meta_bits), pb = words_bytes(payload_bits);

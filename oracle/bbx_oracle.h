@@ -69,6 +69,21 @@ int bbxo_compress_reduced(const void* pos, uint64_t n, uint32_t dims, int dtype,
                           double eb, int eb_mode, uint32_t r, int key_rule, uint8_t* out,
                           uint64_t out_cap, uint64_t* out_size, uint32_t* perm);
 
+/* The partition with a chosen split rule, as an ablation of the reading of
+ * Sec. 4.1: 0 = median along the axes in turn, halving until at most r
+ * particles (what bbxo_compress does); 1 = median along the axis of widest
+ * code extent; 2 = ceil(n / r) leaves of proportional sizes; 3 = midpoint
+ * (cell) split of the code grid (Sec. 2.2's coders), empty cells dropped.
+ * reduce: 0 none, 1 the reduction with key sum of widths, 2 with key sum of
+ * box lengths.  ref_rule as in bbxo_compress_ex (the reduction's re-fitted
+ * boxes always take rule 0).  With split_rule 0 and reduce 0 the stream is
+ * bbxo_compress_ex's (version 1); otherwise version 2, one sequence per leaf
+ * without the reduction, the split rule in header byte 21. */
+int bbxo_compress_split(const void* pos, uint64_t n, uint32_t dims, int dtype, int layout,
+                        double eb, int eb_mode, uint32_t r, int split_rule, int ref_rule,
+                        int reduce, uint8_t* out, uint64_t out_cap, uint64_t* out_size,
+                        uint32_t* perm);
+
 /* Decompress a stream into pos (n*dims values of the stream's dtype). */
 int bbxo_decompress(const uint8_t* stream, uint64_t size, void* pos, uint64_t pos_cap_bytes,
                     int layout);

@@ -64,24 +64,64 @@ def quantize(points: np.ndarray, prm: dict):
     return [[0] * points.shape[1] for _ in range(points.shape[0])]
 
 
-def kd_leaves(codes, r: int, dims: int):
-    """Leaves (lists of original indices, ascending) in depth-first order."""
-    leaves = []
+def kd_leaves(codes, r: int, dims: int, rule: int = 0, G=None):
+    """Leaves (lists of original indices, ascending) in depth-first order.
 
-    def split(members, depth):
+    rule 0: halve (floor(s/2) smallest (code, index) pairs go left) until at
+    most r, axes in turn; rule 1: the same along the axis whose codes spread
+    widest (lowest axis on ties); rule 2: ceil(n/r) leaves, leaf i holding
+    the ranks floor(i*n/b) .. floor((i+1)*n/b) - 1, every node giving its
+    left child the first half (rounded down) of its leaves; rule 3: cells of
+    the code grid [0, 2^G_d) halved at their midpoints, axes in turn with
+    one-code-wide axes skipped, empty halves dropped."""
+    leaves = []
+    n = len(codes)
+    b = -(-n // r) if n else 0
+
+    def by_rank(members, d, k):
+        ranked = sorted(members, key=lambda i: (codes[i][d], i))
+        left = set(ranked[:k])
+        return [i for i in members if i in left], [i for i in members if i not in left]
+
+    def split(members, depth, i0, i1, cell):
+        d = depth % dims
+        if rule == 2:
+            if i1 - i0 == 1:
+                leaves.append(members)
+                return
+            im = (i0 + i1) // 2
+            lo, hi = by_rank(members, d, im * n // b - i0 * n // b)
+            split(lo, depth + 1, i0, im, cell)
+            split(hi, depth + 1, im, i1, cell)
+            return
         if len(members) <= r:
             leaves.append(members)
             return
-        d = depth % dims
-        ranked = sorted(members, key=lambda i: (codes[i][d], i))
-        half = len(members) // 2
-        left = set(ranked[:half])
-        split([i for i in members if i in left], depth + 1)
-        split([i for i in members if i not in left], depth + 1)
+        if rule == 3:
+            axes = [(d + k) % dims for k in range(dims) if cell[(d + k) % dims][1] > 1]
+            if not axes:
+                leaves.append(members)
+                return
+            d = axes[0]
+            start, width = cell[d]
+            mid = start + width // 2
+            lo = [i for i in members if codes[i][d] < mid]
+            hi = [i for i in members if codes[i][d] >= mid]
+            for part, c in ((lo, (start, width // 2)), (hi, (mid, width // 2))):
+                if part:
+                    split(part, depth + 1, i0, i1, [c if a == d else cell[a] for a in range(dims)])
+            return
+        if rule == 1:
+            spread = [max(codes[i][a] for i in members) - min(codes[i][a] for i in members)
+                      for a in range(dims)]
+            d = max(range(dims), key=lambda a: (spread[a], -a))
+        lo, hi = by_rank(members, d, len(members) // 2)
+        split(lo, depth + 1, i0, i1, cell)
+        split(hi, depth + 1, i0, i1, cell)
 
-    n = len(codes)
     if n:
-        split(list(range(n)), 0)
+        cell = [(0, 1 << (G[a] if G else 0)) for a in range(dims)]
+        split(list(range(n)), 0, 0, b, cell)
     return leaves
 
 
@@ -280,11 +320,28 @@ def decompress(stream: bytes) -> np.ndarray:
     return out
 
 
+def compress_split(points: np.ndarray, eb: float, eb_mode: str = "rel", r: int = 32,
+                   split_rule: int = 0, ref_rule: int = 0, reduce: int = 0):
+    """The partition under a split rule (see kd_leaves), bit boxes, then
+    either one sequence per leaf (reduce 0) or the reduction below (reduce 1:
+    key sum of widths, 2: sum of box lengths).  Version-2 stream unless rule
+    0 without the reduction (then the version-1 stream of compress).
+    Returns (stream, perm)."""
+    if split_rule == 0 and reduce == 0:
+        s, perm, _ = compress(points, eb, eb_mode, r, ref_rule)
+        return s, perm
+    return _sequences(points, eb, eb_mode, r, split_rule, ref_rule, reduce)
+
+
 def compress_reduced(points: np.ndarray, eb: float, eb_mode: str = "rel", r: int = 32,
                      key_rule: int = 0):
+    return _sequences(points, eb, eb_mode, r, 0, 0, key_rule + 1)
+
+
+def _sequences(points, eb, eb_mode, r, split_rule, ref_rule, reduce):
     """The bit box reduction of Sec. 4.1 restated with Python sets: a box is
-    its reference and widths; the key is the sum of widths (key_rule 0) or
-    the sum of the Eq. 3 box lengths (key_rule 1); two boxes meet when their
+    its reference and widths; the key is the sum of widths (reduce 1) or
+    the sum of the Eq. 3 box lengths (reduce 2); two boxes meet when their
     Eq. 1 predictable ranges overlap (closed intervals, in bins of 2*eps); a
     particle is inside a box when the box's widths can encode its offsets
     (searched, as for the widths themselves).  Returns (stream, perm)."""
@@ -296,12 +353,13 @@ def compress_reduced(points: np.ndarray, eb: float, eb_mode: str = "rel", r: int
     except ValueError:
         return lossless_stream(points, eb, eb_mode, r)
     codes = quantize(points, prm)
-    leaves = kd_leaves(codes, r, dims)
     G = prm["G"]
+    leaves = kd_leaves(codes, r, dims, split_rule, G)
     boxes = []
     for members in leaves:
-        j, m = bit_box(codes, members, dims)
+        j, m = bit_box(codes, members, dims, ref_rule)
         boxes.append({"left": set(members), "ref": members[j], "m": m, "order": list(members)})
+    key_rule = reduce - 1
 
     def key(b):
         if key_rule == 0:
@@ -319,7 +377,9 @@ def compress_reduced(points: np.ndarray, eb: float, eb_mode: str = "rel", r: int
         return all(minimal_bits([codes[i][d] - codes[b["ref"]][d]]) <= b["m"][d] for d in range(dims))
 
     seqs = []
-    live = [k for k in range(len(boxes))]
+    live = [k for k in range(len(boxes))] if reduce else []
+    if not reduce:
+        seqs = [(B["ref"], list(B["m"]), [i for i in B["order"] if i != B["ref"]]) for B in boxes]
     while live:
         cur = min(live, key=lambda k: (key(boxes[k]), k))
         B = boxes[cur]
@@ -361,7 +421,7 @@ def compress_reduced(points: np.ndarray, eb: float, eb_mode: str = "rel", r: int
     G3 = list(G) + [0] * (3 - dims)
     header = struct.pack(
         "<4sHBBQIBBBBddddd3d3B5xQQQQ", b"BBX1", 2, 0 if f32 else 1, dims, n, r,
-        0 if eb_mode == "rel" else 1, 0, 0, mbits, eb, prm["eb_abs"], prm["eb_eff"], prm["w"],
+        0 if eb_mode == "rel" else 1, split_rule, 0, mbits, eb, prm["eb_abs"], prm["eb_eff"], prm["w"],
         prm["inv_w"], *lo3, *G3, len(leaves), mpos, ppos, len(seqs))
     stream = (header + meta.to_bytes(8 * ((mpos + 63) // 64), "little")
               + pay.to_bytes(8 * ((ppos + 63) // 64), "little"))

@@ -70,6 +70,9 @@ class Oracle:
         lib.bbxo_compress_reduced.restype = i32
         lib.bbxo_compress_reduced.argtypes = [vp, u64, u32, i32, i32, dbl, i32, u32, i32, vp, u64,
                                               C.POINTER(u64), vp]
+        lib.bbxo_compress_split.restype = i32
+        lib.bbxo_compress_split.argtypes = [vp, u64, u32, i32, i32, dbl, i32, u32, i32, i32, i32,
+                                            vp, u64, C.POINTER(u64), vp]
         lib.bbxo_axis_order_by_entropy.restype = None
         lib.bbxo_axis_order_by_entropy.argtypes = [vp, u64, u32, vp]
         lib.bbxo_r_index.restype = u64
@@ -142,6 +145,33 @@ class Oracle:
         if want_perm:
             return stream, perm[:n].copy()
         return stream
+
+    def compress_split(self, pos: np.ndarray, eb: float, eb_mode: str = "rel", r: int = 32,
+                       layout: str = "aos", split_rule: int = 0, ref_rule: int = 0,
+                       reduce: int = 0, want_perm: bool = False):
+        """The partition with split rule 0 (median, axes in turn), 1 (widest
+        axis), 2 (ceil(n/r) proportional leaves) or 3 (midpoint cells), then
+        bit boxes and, with reduce 1 or 2, the reduction of Sec. 4.1.  Rule 0
+        without the reduction gives the version-1 stream, anything else
+        version 2 (one record per sequence)."""
+        pos = np.ascontiguousarray(pos)
+        n, dims, lay = self._shape(pos, layout)
+        mbits = 5 if pos.dtype == np.float32 else 6
+        # version 2 at worst: a record per particle (widths, 30-bit codes,
+        # count), or the lossless stream
+        v2 = 128 + 8 * ((n * (dims * (mbits + 30 + 31) + 32) + 63) // 64)
+        cap = max(self.compress_bound(n, dims, pos.dtype), v2) + 16
+        out = np.zeros(max(cap, 1), dtype=np.uint8)
+        size = C.c_uint64(0)
+        perm = np.zeros(max(n, 1), dtype=np.uint32)
+        st = self.lib.bbxo_compress_split(pos.ctypes.data, n, dims, _dt(pos), lay, float(eb),
+                                          0 if eb_mode == "rel" else 1, r, int(split_rule),
+                                          int(ref_rule), int(reduce), out.ctypes.data, cap,
+                                          C.byref(size), perm.ctypes.data)
+        if st:
+            raise OracleError(st)
+        stream = out[: size.value].tobytes()
+        return (stream, perm[:n].copy()) if want_perm else stream
 
     def compress_reduced(self, pos: np.ndarray, eb: float, eb_mode: str = "rel", r: int = 32,
                          layout: str = "aos", key_rule: int = 0, want_perm: bool = False):

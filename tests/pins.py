@@ -267,6 +267,105 @@ def pin_lossless_fallback(orc):
     assert props.parse_header(orc.compress(pts, 1e-4, "rel", 4))["version"] == 1
 
 
+def split_case():
+    with open(os.path.join(GOLDEN, "split_examples.json")) as f:
+        return json.load(f)
+
+
+def split_leaves(orc, pts, eb, mode, r, rule):
+    """Member sets (ascending index) of the leaves, in leaf order, read from
+    the split stream (one sequence per leaf) and its perm."""
+    s, perm = orc.compress_split(pts, eb, mode, r, split_rule=rule, want_perm=True)
+    h = props.parse_header(s)
+    if rule == 0:
+        st = orc.stages(pts, eb, mode, r)
+        return s, [sorted(st["order"][a:a + z].tolist())
+                   for a, z in zip(st["leaf_start"], st["leaf_size"])]
+    assert h["version"] == 2 and s[21] == rule
+    out, at = [], 0
+    for sq in props.reduced_sequences(s):
+        out.append(sorted(perm[at:at + 1 + sq["count"]].tolist()))
+        at += 1 + sq["count"]
+    assert at == len(pts) and h["n_leaves"] == len(out)
+    return s, out
+
+
+def pin_split_examples(orc):
+    """The split rules on hand-worked examples (Sec. 4.1's single-axis median
+    split and its leaf count, Sec. 2.2's midpoint split): the leaves' member
+    sets in leaf order; each stream decodes within the bound."""
+    g = split_case()
+    for c in g["cases"]:
+        pts = np.array(c["points"], dtype=np.float64)
+        s, leaves = split_leaves(orc, pts, g["eb_abs"], "abs", c["r"], c["split_rule"])
+        assert leaves == c["leaves"], (c["name"], leaves)
+        if c["split_rule"]:
+            _, perm = orc.compress_split(pts, g["eb_abs"], "abs", c["r"], split_rule=c["split_rule"],
+                                         want_perm=True)
+            assert np.array_equal(np.rint(orc.decompress(s)), pts[perm])  # eps 0.5: own bins
+
+
+def pin_split_counts(orc):
+    """Leaf counts and sizes the rules fix: rule 2 makes ceil(n/r) leaves whose
+    rank boundaries are floor(i n / b) (262,144 particles at r = 131 give
+    2,002 leaves; the figure's 2,000 is r = 131.072, not an integer); rule 1
+    keeps rule 0's sizes (halving); rule 3 leaves hold at most r particles
+    unless all their codes are equal, none is empty, and each lies in one
+    cell of the grid halved along the axes."""
+    rng = np.random.default_rng(17)
+    for n, r in ((7, 2), (10, 3), (100, 7), (1000, 32), (999, 1), (5, 5), (5, 9)):
+        pts = rng.random((n, 3)).astype(np.float32)
+        s = orc.compress_split(pts, 1e-3, "rel", r, split_rule=2)
+        b = -(-n // r)
+        sizes = [1 + q["count"] for q in props.reduced_sequences(s)]
+        assert sizes == [(i + 1) * n // b - i * n // b for i in range(b)], (n, r)
+        assert props.parse_header(s)["n_leaves"] == b
+        s1, l1 = split_leaves(orc, pts, 1e-3, "rel", r, 1)
+        st = orc.stages(pts, 1e-3, "rel", r)
+        assert [len(x) for x in l1] == [int(z) for z in st["leaf_size"]]
+    pts = rng.random((262144, 3)).astype(np.float32)
+    s = orc.compress_split(pts, 5e-4, "rel", 131, split_rule=2)
+    assert props.parse_header(s)["n_leaves"] == 2002
+    # clusters and duplicates for the midpoint rule
+    pts = np.concatenate([rng.normal(size=(300, 3)) * 0.01, rng.random((300, 3)),
+                          np.full((20, 3), 0.5)]).astype(np.float32)
+    pts = pts[rng.permutation(len(pts))]
+    for r in (1, 4, 16):
+        st = orc.stages(pts, 1e-3, "rel", r)
+        q = np.asarray(st["q"]).reshape(3, -1).T  # [n][dims]
+        s, leaves = split_leaves(orc, pts, 1e-3, "rel", r, 3)
+        boxes = []
+        for mem in leaves:
+            assert len(mem) > 0
+            codes = q[mem]
+            if len(mem) > r:
+                assert (codes == codes[0]).all(), r
+            # the smallest aligned dyadic interval holding the leaf's codes,
+            # per axis: it lies inside the leaf's cell, and cells are disjoint
+            lo, hi = codes.min(axis=0).astype(np.int64), codes.max(axis=0).astype(np.int64)
+            k = np.array([int(a ^ b).bit_length() for a, b in zip(lo, hi)])
+            boxes.append(((lo >> k) << k, ((lo >> k) + 1) << k))
+        a = np.array([b[0] for b in boxes])
+        e = np.array([b[1] for b in boxes])
+        meet = ((a[:, None, :] < e[None, :, :]) & (a[None, :, :] < e[:, None, :])).all(axis=2)
+        assert meet.sum() == len(boxes), r  # each box meets only itself
+
+
+def pin_split_brute(orc, seed=18, count=30):
+    """The split rules (with and without the reduction) against the Python
+    restatement: every byte and the perm."""
+    for pts, eb, mode, r in tiny_cases(seed, count):
+        for rule in (1, 2, 3):
+            for red in (0, 1, 2):
+                rr = (rule + red) % 2
+                s1, p1 = orc.compress_split(pts, eb, mode, r, split_rule=rule, ref_rule=rr,
+                                            reduce=red, want_perm=True)
+                s2, p2 = brute.compress_split(pts, eb, mode, r, rule, rr, red)
+                assert s1 == s2 and np.array_equal(p1, p2), ("split stream differs", pts.shape,
+                                                             r, rule, red)
+                assert np.array_equal(orc.decompress(s1), brute.decompress(s2))
+
+
 def run_battery(orc):
     """Returns the names of the pins that fail."""
     failed = []
@@ -276,7 +375,9 @@ def run_battery(orc):
                      ("reduction_examples", pin_reduction_examples),
                      ("reduction_brute", pin_reduction_brute),
                      ("reduction_special", pin_reduction_special),
-                     ("lossless_fallback", pin_lossless_fallback)):
+                     ("lossless_fallback", pin_lossless_fallback),
+                     ("split_examples", pin_split_examples), ("split_counts", pin_split_counts),
+                     ("split_brute", pin_split_brute)):
         try:
             fn(orc)
         except Exception as e:  # noqa: BLE001 -- any failure counts as caught

@@ -40,6 +40,12 @@ MUTANTS = {
     24: "no common particles are absorbed",
     25: "common particles gathered in reverse leaf order",
     26: "lossless fallback stores a particle's axes in reverse order",
+    27: "split rule 1 takes the narrowest axis",
+    28: "split rule 2 gives the left child the larger half of the leaves",
+    29: "split rule 3 sends codes on the midpoint to the left",
+    30: "split rule 1 breaks extent ties towards the last axis",
+    31: "split rule 3 stops at a one-code-wide axis instead of trying the next",
+    32: "split rule 2 makes floor(n/r) leaves",
 }
 
 
