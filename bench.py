@@ -510,6 +510,10 @@ def main():
     ap.add_argument("--reduce", type=int, default=0, choices=(0, 1, 2),
                     help="bit box reduction after the bit boxes: 1 key sum of widths, 2 key sum of "
                          "box lengths (moderate sets: at most 65,536 leaves)")
+    ap.add_argument("--split-rule", type=int, default=0, choices=(0, 1, 2, 3),
+                    help="partition split rule: 0 median with axes in turn (the library's), "
+                         "1 widest axis, 2 ceil(n/r) proportional leaves, 3 midpoint cells "
+                         "(ablations, version-2 streams)")
     ap.add_argument("--scatter-stage", type=int, default=0, choices=(0, 1, 2),
                     help="global partition group stores: 0 by chunk size, 1 staged, 2 direct")
     ap.add_argument("--nsets", type=int, default=4096)
@@ -556,22 +560,24 @@ def main():
         sys.exit(2)
     comp = bbx.Compressor(n, dims, x.dtype, leaf_size=args.leaf_size, tile=args.tile,
                           ref_rule=args.ref_rule, ref_mode=args.ref_mode,
-                          scatter_stage=args.scatter_stage, reduce=args.reduce)
+                          scatter_stage=args.scatter_stage, reduce=args.reduce,
+                          split_rule=args.split_rule)
     s = comp(x, xi)
     S = s.numel()
     S_plain = S
-    if args.reduce:  # the same input without the reduction: its stream size only
+    if args.reduce or args.split_rule:  # the same input with the plain partition: its size only
         alt = bbx.Compressor(n, dims, x.dtype, leaf_size=args.leaf_size, tile=args.tile)
         S_plain = alt(x, xi).numel()
         del alt
     # the other leaf-reference rule, and the other reference storage, on the
     # same input: their stream sizes only
     alt = bbx.Compressor(n, dims, x.dtype, leaf_size=args.leaf_size, tile=args.tile,
-                         ref_rule=1 - args.ref_rule, ref_mode=args.ref_mode)
+                         ref_rule=1 - args.ref_rule, ref_mode=args.ref_mode,
+                         split_rule=args.split_rule)
     S_alt = alt(x, xi).numel()
     del alt
     S_alt_mode = None
-    if not args.reduce:
+    if not args.reduce and not args.split_rule:
         alt = bbx.Compressor(n, dims, x.dtype, leaf_size=args.leaf_size, tile=args.tile,
                              ref_rule=args.ref_rule, ref_mode=1 - args.ref_mode)
         S_alt_mode = alt(x, xi).numel()
@@ -694,7 +700,8 @@ def main():
     rt_ms = sum(a + b for a, b in zip(tc, td)) / len(tc)
     rt_achieved = algo_round_trip / (rt_ms * 1e-3) / 1e9
     traffic = measured_traffic(args.workload) if args.leaf_size == 32 and args.ref_mode == 0 \
-        and args.ref_rule == 0 and args.tile == 0 else None
+        and args.ref_rule == 0 and args.tile == 0 and not args.reduce and not args.split_rule \
+        else None
     roofline = {"bound": "hbm", "achieved": round(rt_achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(rt_achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "alg_bytes_per_step": int(algo_round_trip),
@@ -727,7 +734,7 @@ def main():
     try:
         pc = bbx.Compressor(n, dims, x.dtype, leaf_size=args.leaf_size, tile=args.tile,
                             want_perm=True, ref_rule=args.ref_rule, ref_mode=args.ref_mode,
-                            reduce=args.reduce)
+                            reduce=args.reduce, split_rule=args.split_rule)
         s2 = pc(x, xi)
         assert s2.numel() == S
         perm = pc.perm[:n].long()
@@ -748,8 +755,9 @@ def main():
         orc = Oracle()
         log(f"cpu oracle on {m} particles")
         t = time.perf_counter()
-        if args.reduce:
-            so = orc.compress_reduced(sample, xi, "rel", args.leaf_size, key_rule=args.reduce - 1)
+        if args.reduce or args.split_rule:
+            so = orc.compress_split(sample, xi, "rel", args.leaf_size, split_rule=args.split_rule,
+                                    ref_rule=args.ref_rule, reduce=args.reduce)
         else:
             so = orc.compress(sample, xi, "rel", args.leaf_size, ref_rule=args.ref_rule,
                               ref_mode=args.ref_mode)
@@ -774,7 +782,7 @@ def main():
                    "stream_bytes": S, "cr": round(B_in / S, 4),
                    "cr_other_ref_rule": round(B_in / S_alt, 4),
                    "cr_other_ref_mode": round(B_in / S_alt_mode, 4) if S_alt_mode else None,
-                   "reduce": args.reduce,
+                   "reduce": args.reduce, "split_rule": args.split_rule,
                    "cr_without_reduce": round(B_in / S_plain, 4),
                    "sequence_export": export,
                    "bpp": round(8 * S / n, 4),

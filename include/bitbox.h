@@ -116,7 +116,23 @@ typedef enum { BBX_AOS = 0, BBX_SOA = 1 } bbx_layout;         /* [n][dims] or [d
  * count of the other particles, the payload their codes in sequence order;
  * decompression writes the sequences in order, reference first.  Needs
  * ref_mode 0 and fewer than 2^31 leaves; its loop runs one workgroup per
- * set (a set's pops are sequential), so it suits batches of moderate sets. */
+ * set (a set's pops are sequential), so it suits batches of moderate sets.
+ * split_rule says how the partition splits a node (Sec. 4.1 fixes "along one
+ * dimension at the median" but not which dimension nor the leaf count):
+ * 0 = the median along the axes in turn, halving until at most r particles
+ * (the library's partition, stream version 1 unless reduce is set); 1 = the
+ * median along the axis whose codes spread widest in the node (lowest axis on
+ * ties); 2 = ceil(n / r) leaves of floor or ceil of n / ceil(n / r)
+ * particles, leaf i holding the tree-order ranks floor(i n / b) ..
+ * floor((i + 1) n / b) - 1 with b = ceil(n / r), axes in turn; 3 = the
+ * midpoint split of the coders Sec. 2.2 cites: cells of the code grid
+ * [0, 2^G_d) halved at their midpoints along the axes in turn (one-code-wide
+ * axes skipped; a cell of one code is one leaf, however many particles),
+ * until at most r particles, empty halves dropped.  Rules 1-3 write a
+ * version-2 stream (one sequence per leaf, or the reduction's sequences),
+ * header byte 21 holding the rule and the leaf-count field the partition's
+ * leaf count; they need ref_mode 0 and run a separate, untuned partition
+ * (an ablation of the reading, several times slower than rule 0). */
 typedef struct {
   uint32_t leaf_size;     /* r >= 1 */
   uint32_t eb_mode;       /* bbx_eb_mode */
@@ -127,6 +143,7 @@ typedef struct {
   uint32_t scatter_stage; /* 0 (by chunk size), 1 (always) or 2 (never) */
   uint32_t level_blocks;  /* 0 (library's choice) or 1..4096 */
   uint32_t reduce;        /* bit box reduction: 0 none, 1 (key: sum of widths), 2 (key: sum of lengths) */
+  uint32_t split_rule;    /* 0 (median, axes in turn), 1 (widest axis), 2 (ceil(n/r) leaves), 3 (midpoint cells) */
 } bbx_params;
 
 /* Worst-case stream size in bytes for n particles of the given type, with
@@ -135,7 +152,9 @@ typedef struct {
 size_t bbx_compress_bound(uint64_t n, uint32_t dims, bbx_dtype dtype);
 size_t bbx_compress_bound_mode(uint64_t n, uint32_t dims, bbx_dtype dtype, uint32_t ref_mode);
 /* The same for any parameters (the bit box reduction adds a 32-bit count
- * per sequence, at most one sequence per leaf); 0 for invalid parameters. */
+ * per sequence, at most one sequence per leaf; split rules 1-3 a record per
+ * leaf with its count, rule 3 at most a leaf per particle); 0 for invalid
+ * parameters. */
 size_t bbx_compress_bound_params(uint64_t n, uint32_t dims, bbx_dtype dtype,
                                  const bbx_params* params);
 

@@ -109,6 +109,36 @@ TreeGeom make_geom(uint64_t n, uint32_t r) {
 
 static size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
+// Leaves of a split-rule partition at most: rule 1 those of the halving
+// recursion, rule 2 ceil(n / r), rule 3 one per particle.
+static uint64_t split_leaf_cap(uint64_t n, uint32_t r, uint32_t rule) {
+  if (n == 0) return 0;
+  if (rule == 2) return (n + r - 1) / r;
+  if (rule == 3) return n;
+  return make_geom(n, r).L[0][0];
+}
+
+// Global levels a split-rule partition launches: until every node is a leaf
+// or holds at most kSpLocal particles (rule 1: nodes of depth k hold at most
+// ceil(n / 2^k); rule 2: at most ceil(b / 2^k) leaves of at most ceil(n / b)
+// particles; rule 3: every halving narrows one axis of a cell of at most 30
+// bits, so 30 dims levels leave single codes).
+static uint32_t split_levels(uint64_t n, uint32_t r, uint32_t rule, uint32_t dims) {
+  if (rule == 3) return 30 * dims;
+  uint32_t k = 0;
+  if (rule == 2) {
+    const uint64_t b = (n + r - 1) / r, lsz = b ? (n + b - 1) / b : 0;
+    while (true) {
+      const uint64_t lv = (b + (1ull << k) - 1) >> k;
+      if (lv <= 1 || lv * lsz <= kSpLocal) return k;
+      ++k;
+    }
+  }
+  const uint64_t cap = std::max<uint64_t>(kSpLocal, r);
+  while (((n + (1ull << k) - 1) >> k) > cap) ++k;
+  return k;
+}
+
 // One set of a compress request, as the ABI receives it.
 struct SetIn {
   const void* pos;
@@ -143,7 +173,10 @@ static bbx_status check_compress_args(uint64_t n, uint32_t dims, bbx_dtype dtype
   if (prm->reduce && prm->ref_mode) return fail(BBX_EUNSUPPORTED, "the bit box reduction stores references as codes (ref_mode 0)");
   if (dims != 2 && dims != 3) return fail(BBX_EUNSUPPORTED, "dims must be 2 or 3");
   if (n >= (1ull << 32)) return fail(BBX_EUNSUPPORTED, "n must be below 2^32");
-  if (prm->reduce && n > 0 && make_geom(n, prm->leaf_size).L[0][0] >= (1ull << 31))
+  if (prm->split_rule > 3) return fail(BBX_EINVAL, "split_rule must be 0, 1, 2 or 3");
+  if (prm->split_rule && prm->ref_mode)
+    return fail(BBX_EUNSUPPORTED, "split rules 1-3 store references as codes (ref_mode 0)");
+  if (prm->reduce && n > 0 && split_leaf_cap(n, prm->leaf_size, prm->split_rule) >= (1ull << 31))
     return fail(BBX_EUNSUPPORTED, "the bit box reduction needs fewer than 2^31 leaves");
   return BBX_OK;
 }
@@ -161,7 +194,7 @@ static bbx_status check_set(const SetIn& in) {
 struct WsLayout {
   size_t params, sets, pre, partials, keys[2], idx[2], hist, sel, rows, cb, leaves, bits, spart,
       stotal, pneed, defer, lossless, red_tq, red_taken, red_slot, red_perm, red_key, red_ctr, red_ref, red_hits,
-      red_seq, total;
+      red_seq, split, total;
 };
 
 struct Carve {
@@ -182,6 +215,7 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
   bp->tile = in[0].prm.tile_override ? in[0].prm.tile_override : 256;
   descs->assign(nsets, SetDesc());
   uint64_t key_bytes = 0, idx_n = 0, hist_n = 0, sel_n = 0, rows_n = 0, leaves_n = 0, parts = 0;
+  uint64_t split_bytes = 0;
   // block target of the global levels: kLevelBlocks for a set alone; in a
   // batch each set's share of 4 * kLevelBlocks by particle count
   uint64_t n_total = 0;
@@ -218,14 +252,43 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
     D.ref_rule = I.prm.ref_rule;
     D.ref_mode = I.prm.ref_mode;
     D.reduce = I.prm.reduce;
-    D.user_perm = D.reduce ? I.d_perm : nullptr;
+    D.split = I.prm.split_rule;
+    D.user_perm = seq_stream(D) ? I.d_perm : nullptr;
     // a reduce set carries source indices; its leaf stage writes them to the
     // workspace (batch_upload points perm there), the caller's perm comes last
-    D.track = (I.d_perm != nullptr || I.prm.ref_mode == 1 || D.reduce) ? 1u : 0u;
+    D.track = (I.d_perm != nullptr || I.prm.ref_mode == 1 || seq_stream(D)) ? 1u : 0u;
     D.eb_mode = I.prm.eb_mode;
     D.mbits = I.dtype == BBX_F32 ? 5u : 6u;
     const uint64_t n = I.n;
-    if (n > 0) {
+    if (n > 0 && D.split) {
+      // the split-rule partition (k_split.hip) makes the leaves and their
+      // boxes; the version-2 packer writes the stream
+      D.geom = make_geom(n, D.r);
+      D.n_leaves = split_leaf_cap(n, D.r, D.split);
+      D.sp_levels = split_levels(n, D.r, D.split, D.dims);
+      D.sp_off = split_bytes;
+      split_bytes += align_up(sp_layout(n, D.sp_levels).total);
+      mm[s] = std::min<uint64_t>((n + 2047) / 2048, kMaxMinMaxBlocks);
+      qz[s] = std::min<uint64_t>((n + 1023) / 1024, 16384);
+      rl[s] = D.reduce ? 1 : 0;
+      rw[s] = std::max<uint64_t>(1, std::min<uint64_t>((n + 2047) / 2048, 1024));
+      bp->reduce = 1;
+      bp->split = 1;
+      if (D.reduce) {
+        if (D.n_leaves <= kRedLdsBoxes || D.split == 3) bp->red_lds_boxes = 1;
+        if (D.n_leaves > kRedLdsBoxes) bp->red_global = 1;
+      }
+      D.mm_blocks = (uint32_t)mm[s];
+      D.key_off = key_bytes;
+      D.idx_off = idx_n;
+      D.leaf_off = leaves_n;
+      D.part_off = parts;
+      D.kst = (n + 63) & ~63ull;
+      key_bytes += align_up((uint64_t)D.dims * D.kst * 4);
+      idx_n += (n + 63) & ~63ull;
+      leaves_n += D.n_leaves;
+      parts += mm[s];
+    } else if (n > 0) {
       D.level_blocks = level_blocks(n, I.prm.level_blocks);
       D.geom = make_geom(n, D.r);
       D.n_leaves = D.geom.L[0][0];
@@ -380,6 +443,7 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
   lay->red_ref = c.take(4 * rlv);
   lay->red_hits = c.take(4 * rlv);
   lay->red_seq = c.take(16 * rlv);
+  lay->split = c.take(split_bytes);
   lay->total = c.off;
 }
 
@@ -412,6 +476,7 @@ static Ws carve_ws(const WsLayout& L, uint8_t* base) {
   w.red_ref = (uint32_t*)(base + L.red_ref);
   w.red_hits = (uint32_t*)(base + L.red_hits);
   w.red_seq = (uint4*)(base + L.red_seq);
+  w.split = base + L.split;
   return w;
 }
 
@@ -443,7 +508,7 @@ static std::string check_plan(const SetIn* in, uint32_t nsets) {
   for (uint32_t s = 0; s < nsets; ++s) {
     const SetDesc& D = descs[s];
     const uint64_t n = D.n;
-    if (n == 0) continue;
+    if (n == 0 || D.split) continue;  // a split-rule partition sizes its lists on the device
     if (D.level_blocks < 1 || D.level_blocks > kLevelBlocks) return where(s, 0) + "block target out of range";
     const uint64_t next_rows = s + 1 < nsets && descs[s + 1].n ? descs[s + 1].rows_off / kRowStride
                                                                : rows_total;
@@ -527,7 +592,7 @@ static bbx_status batch_upload(const SetIn* in, uint32_t nsets, void* d_ws, size
   if (!d_ws || ((uintptr_t)d_ws & 255)) return fail(BBX_EINVAL, "workspace must be 256-byte aligned");
   if (ws_size < lay.total) return fail(BBX_ENOMEM, "workspace too small: need " + std::to_string(lay.total));
   for (uint32_t s = 0; s < nsets; ++s)
-    if (descs[s].reduce && descs[s].n > 0)
+    if (seq_stream(descs[s]) && descs[s].n > 0)
       descs[s].perm = (uint32_t*)((uint8_t*)d_ws + lay.red_perm) + descs[s].idx_off;
   std::vector<uint8_t> blob(lay.pre + 8 * pre.size() - lay.sets);
   memcpy(blob.data(), descs.data(), sizeof(SetDesc) * nsets);
@@ -560,6 +625,7 @@ static bbx_status batch_launch(const SetIn* in, uint32_t nsets, void* d_ws, size
   if (ws_size < lay.total) return fail(BBX_ENOMEM, "workspace too small: need " + std::to_string(lay.total));
   const Ws w = carve_ws(lay, (uint8_t*)d_ws);
   hipError_t e = launch_range(bp, w, stream);
+  if (e == hipSuccess) e = launch_split(bp, descs.data(), w, stream);
   if (e == hipSuccess) e = launch_levels(bp, w, stream);
   if (e == hipSuccess) e = launch_leaves(bp, w, stream);
   if (e == hipSuccess) e = launch_reduce(bp, w, stream);
@@ -605,7 +671,9 @@ static bbx_status parse_header(const uint8_t* h, size_t bytes, HostHeader* o) {
   o->eb_mode = h[20];
   o->ref_mode = h[22];
   o->mbits = h[23];
-  if (o->dtype > 1 || (o->dims != 2 && o->dims != 3) || o->eb_mode > 1 || h[21] != 0 || h[22] > 1)
+  const uint32_t split = h[21];  // split rule: 1-3 only in version-2 streams
+  if (o->dtype > 1 || (o->dims != 2 && o->dims != 3) || o->eb_mode > 1 || split > 3 ||
+      (split && ver != 2) || h[22] > 1)
     return fail(BBX_ECORRUPT, "bad dtype, dims, eb_mode or rule fields");
   if (o->mbits != (o->dtype == 0 ? 5u : 6u) || o->r == 0 || o->n >= (1ull << 32))
     return fail(BBX_ECORRUPT, "bad width-field size, leaf size or n");
@@ -645,8 +713,12 @@ static bbx_status parse_header(const uint8_t* h, size_t bytes, HostHeader* o) {
   o->n_leaves = rd64(h + 96);
   o->meta_bits = rd64(h + 104);
   o->payload_bits = rd64(h + 112);
-  const uint64_t nl = o->n ? make_geom(o->n, o->r).L[0][0] : 0;
-  if (o->n_leaves != nl) return fail(BBX_ECORRUPT, "leaf count does not match (n, r)");
+  // the partition's leaf count: fixed by (n, r) and the split rule, except
+  // rule 3's (at most one leaf per particle)
+  const uint64_t nl = split == 3 ? o->n_leaves : (split ? split_leaf_cap(o->n, o->r, split)
+                                                        : (o->n ? make_geom(o->n, o->r).L[0][0] : 0));
+  if (o->n_leaves != nl || nl > o->n || (o->n > 0 && nl == 0))
+    return fail(BBX_ECORRUPT, "leaf count does not match (n, r)");
   o->n_seq = rd64(h + 120);
   if (o->version == 2) {  // sequences of the bit box reduction
     if (o->ref_mode != 0) return fail(BBX_ECORRUPT, "reduced stream with stored coordinates");
@@ -744,6 +816,16 @@ size_t bbx_compress_bound_params(uint64_t n, uint32_t dims, bbx_dtype dtype,
                                  const bbx_params* params) {
   if (!params || params->ref_mode > 1 || params->leaf_size == 0) return 0;
   size_t b = bbx_compress_bound_mode(n, dims, dtype, params->ref_mode);
+  if (params->split_rule > 3) return 0;
+  if (params->split_rule && n > 0) {
+    // version 2 with one record per leaf at most (widths, codes of up to 30
+    // bits, a 32-bit count), the payload's offsets at most 31 bits per axis
+    const uint64_t mbits = dtype == BBX_F64 ? 6 : 5;
+    const uint64_t nl = split_leaf_cap(n, params->leaf_size, params->split_rule);
+    const uint64_t meta = nl * (dims * (mbits + 30) + 32), pay = n * dims * 31ull;
+    const size_t v2 = kHeaderBytes + 16 + ((meta + 63) / 64) * 8 + ((pay + 63) / 64) * 8;
+    return b > v2 ? b : v2;
+  }
   // the bit box reduction: a 32-bit count per sequence, at most one per leaf
   if (params->reduce && n > 0) b += 4 * (size_t)make_geom(n, params->leaf_size).L[0][0] + 8;
   return b;

@@ -45,8 +45,9 @@ struct DevParams {
   uint32_t diag;        // first internal consistency check that failed (Check), 0 if none
   uint64_t meta_bits, payload_bits, total_bytes;
   uint64_t payload_base;  // global payload-bit offset of the set's first leaf
-  uint64_t nseq;          // sequences of the bit box reduction (reduce sets)
-  uint64_t pad1[2];
+  uint64_t nseq;          // sequences of the version-2 stream (reduce or split-rule sets)
+  uint64_t nleaves;       // leaves the partition made (split-rule sets; found on the device)
+  uint64_t pad1[1];
 };
 
 // Shape of the k-d tree, which depends on (n, r) only: at depth k every node
@@ -101,7 +102,10 @@ struct SetDesc {
   uint32_t fuse_depth;    // depth k whose levels k, k + 1 run fused in place, a wavefront per node (kNoFuse: none)
   uint32_t fuse_depth4;   // the same with a block per node (nodes of at most 4 kFuseNode)
   uint32_t reduce;        // bit box reduction: 0 none, 1 key sum of widths, 2 key sum of lengths
-  uint32_t* user_perm;    // the caller's perm output of a reduce set (perm then points into the workspace)
+  uint32_t* user_perm;    // the caller's perm output of a reduce or split-rule set (perm then points into the workspace)
+  uint32_t split;         // split rule: 0 the median partition above; 1-3 the ablations (k_split.hip)
+  uint32_t sp_levels;     // split-rule sets: global split levels launched
+  uint64_t sp_off;        // split-rule sets: byte offset of the set's region in Ws::split
   uint64_t n_leaves;
   uint64_t key_off;       // byte offset into each key buffer (capacity dims*n*4)
   uint64_t idx_off;       // u32 offset into each index buffer
@@ -143,7 +147,99 @@ struct Ws {
   uint32_t* red_ref;
   uint32_t* red_hits;
   uint4* red_seq;
+  uint8_t* split;       // partition state of the split-rule sets (SpLayout per set)
 };
+
+// A set's stream holds one record per sequence (version 2): the bit box
+// reduction, or a split rule other than 0 (one sequence per leaf).
+__host__ __device__ inline bool seq_stream(const SetDesc& S) { return S.reduce != 0 || S.split != 0; }
+
+// widths of a box packed m_x | m_y << 8 | m_z << 16
+__device__ inline uint32_t red_m(uint32_t mp, uint32_t d) { return (mp >> (8 * d)) & 0xffu; }
+
+// Reduction key of a box: (sum of widths, or with reduce = 2 the sum of
+// Eq. 3 box lengths in units of 2 eps) << 31 | leaf (leaf < 2^31), the order
+// of (key, leaf).
+__device__ inline uint64_t red_key(uint32_t mp, uint32_t dims, uint32_t rule, uint32_t leaf) {
+  uint64_t k = 0;
+  for (uint32_t d = 0; d < dims; ++d) {
+    const uint32_t m = red_m(mp, d);
+    k += rule == 2 ? ((1ull << m) - 1) : m;
+  }
+  return (k << 31) | leaf;
+}
+
+// Eq. 2 width of a largest offset D: bitlen(D) + 1, zero when D = 0.
+__device__ inline uint32_t red_width(uint32_t D) { return D ? 33u - (uint32_t)__builtin_clz(D) : 0u; }
+
+// ---------------------------------------------------------------- split rules 1-3
+
+constexpr uint32_t kSpTile = 2048;   // particles per tile of a global split level (256 threads x 8)
+constexpr uint32_t kSpLocal = 1024;  // nodes of at most this many particles finish in one block
+
+// A node of the split-rule partition (32 bytes): its particles are
+// positions [start, start + size) of the set's tree order.  Rule 2: the
+// leaves [i0, i1) it will hold.  Rule 3: its cell, codes lo[d] ..
+// lo[d] + 2^lg[d] - 1.  pk = lg[0] | lg[1] << 5 | lg[2] << 10 | buf << 16 |
+// leaf << 17 | depth << 24 (buf: which element buffer holds the particles).
+struct SpNode {
+  uint32_t start, size, i0, i1;
+  uint32_t lo[3];
+  uint32_t pk;
+};
+__host__ __device__ inline uint32_t sp_lg(uint32_t pk, uint32_t d) { return (pk >> (5 * d)) & 31u; }
+__host__ __device__ inline uint32_t sp_depth(uint32_t pk) { return pk >> 24; }
+
+// Per active node of a global split level: the split and the selection state.
+struct SpSel {
+  uint32_t axis, npass, prefix, rank;  // radix selection of the rank-k code (rules 1, 2)
+  uint32_t k;                          // rank of the split (rules 1, 2), midpoint code (rule 3)
+  uint32_t nl;                         // left child size
+  uint32_t tile0;                      // first tile of the node in the level's tile list
+  uint32_t base_lt, base_eq;           // the level-wide tile scan at the node's first tile
+  uint32_t ext[6];                     // rule 1: code min, max per axis
+  uint32_t pad;
+};
+
+// Control words of a set's split partition.
+enum { kSpNa0 = 0, kSpNa1 = 1, kSpTiles = 2, kSpDone = 3, kSpCovered = 4, kSpCtlWords = 16 };
+
+// Byte offsets inside one set's split region.  na: active nodes of a level
+// (each holds more than kSpLocal particles, disjoint); ta: tiles of a level;
+// dc: done nodes (children that are leaves or fit one block; disjoint and
+// non-empty, at most two per active node of each level).
+struct SpLayout {
+  uint64_t na, ta, dc, np;
+  uint64_t e[2], len, nodes[2], sel, hist, tcnt, toff, done, part, ctl, total;
+};
+__host__ __device__ inline SpLayout sp_layout(uint64_t n, uint32_t levels) {
+  SpLayout L;
+  L.na = n / (kSpLocal + 1) + 1;
+  L.ta = (n + kSpTile - 1) / kSpTile + L.na;
+  const uint64_t dc = 2 * (uint64_t)levels * L.na + 1;
+  L.dc = dc < n + 1 ? dc : n + 1;
+  L.np = (n + kSpTile - 1) / kSpTile + 1;
+  uint64_t off = 0;
+  auto take = [&](uint64_t bytes) {
+    const uint64_t o = off;
+    off = (off + bytes + 255) & ~(uint64_t)255;
+    return o;
+  };
+  L.e[0] = take(16 * n);
+  L.e[1] = take(16 * n);
+  L.len = take(4 * n);
+  L.nodes[0] = take(sizeof(SpNode) * L.na);
+  L.nodes[1] = take(sizeof(SpNode) * L.na);
+  L.sel = take(sizeof(SpSel) * L.na);
+  L.hist = take(4 * 256 * L.na);
+  L.tcnt = take(8 * L.ta);
+  L.toff = take(8 * L.ta);
+  L.done = take(sizeof(SpNode) * L.dc);
+  L.part = take(4 * L.np);
+  L.ctl = take(4 * kSpCtlWords);
+  L.total = off;
+  return L;
+}
 
 // ---------------------------------------------------------------- device helpers
 
@@ -164,6 +260,7 @@ enum Check : uint32_t {
   kChkTileLeaves = 10,  // leaf count of a tile differs from the tree geometry
   kChkTileRange = 11,
   kChkReduce = 12,      // the reduction did not place every particle
+  kChkSplit = 13,       // a split-rule partition overflowed its node lists or left particles out
 };
 __device__ inline void check_failed(DevParams* P, uint32_t which) {
   atomicCAS(&P->diag, 0u, which);
@@ -440,6 +537,7 @@ struct BatchPlan {
   uint32_t reduce;               // some set runs the bit box reduction
   uint32_t red_lds_boxes;        // some reduce set keeps its boxes on chip (<= kRedLdsBoxes leaves)
   uint32_t red_global;           // some reduce set keeps them in the workspace
+  uint32_t split;                // some set uses a split rule other than 0
   uint64_t g_rp, g_rl, g_rw;     // reduction: preparation, loop and packing blocks
   uint64_t o_rp, o_rl, o_rw;
   uint64_t pre_entries;       // total u64 entries of the prefix buffer
@@ -489,6 +587,7 @@ hipError_t launch_export(const DecompressPlan& p, const DecompressWs& w, const u
 hipError_t launch_dec_scan(uint64_t count, uint64_t* bits, uint64_t* part, DevParams* params,
                            uint64_t expect_payload, hipStream_t s);
 hipError_t launch_reduce(const BatchPlan& bp, const Ws& w, hipStream_t s);
+hipError_t launch_split(const BatchPlan& bp, const SetDesc* descs, const Ws& w, hipStream_t s);
 hipError_t launch_reduce_pack(const BatchPlan& bp, const Ws& w, hipStream_t s);
 hipError_t launch_decompress2(const DecompressPlan& p, const DecompressWs& w, const uint8_t* stream,
                               void* pos, hipStream_t s);

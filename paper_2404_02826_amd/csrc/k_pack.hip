@@ -149,7 +149,7 @@ __global__ void k_set_sizes(uint32_t nsets, const SetDesc* sets, DevParams* para
   for (uint32_t d = 0; d < S.dims; ++d) sumG += S.ref_mode ? coord_bits(S.dtype) : P->G[d];
   // one record per leaf; with the bit box reduction one per sequence, with
   // a 32-bit particle count
-  const uint64_t meta = S.reduce ? P->nseq * (uint64_t)(S.dims * S.mbits + sumG + 32)
+  const uint64_t meta = seq_stream(S) ? P->nseq * (uint64_t)(S.dims * S.mbits + sumG + 32)
                                  : S.n_leaves * (uint64_t)(S.dims * S.mbits + sumG);
   P->payload_base = base;
   P->meta_bits = meta;
@@ -496,7 +496,7 @@ __global__ void k_header(const SetDesc* sets, const DevParams* params) {
   const uint32_t dims = S.dims;
   uint64_t h[16];
   for (int k = 0; k < 16; ++k) h[k] = 0;
-  const uint64_t ver = lossless ? 3 : (S.reduce ? 2 : 1);
+  const uint64_t ver = lossless ? 3 : (seq_stream(S) ? 2 : 1);
   h[0] = (uint64_t)kMagic | (ver << 32) | ((uint64_t)S.dtype << 48) | ((uint64_t)dims << 56);
   if (lossless) {  // no grid, no leaves, no meta section; no reference field
     h[1] = S.n;
@@ -509,8 +509,8 @@ __global__ void k_header(const SetDesc* sets, const DevParams* params) {
     return;
   }
   h[1] = S.n;
-  h[2] = (uint64_t)S.r | ((uint64_t)S.eb_mode << 32) | ((uint64_t)S.ref_mode << 48) |
-         ((uint64_t)S.mbits << 56);
+  h[2] = (uint64_t)S.r | ((uint64_t)S.eb_mode << 32) | ((uint64_t)S.split << 40) |
+         ((uint64_t)S.ref_mode << 48) | ((uint64_t)S.mbits << 56);
   h[3] = __double_as_longlong(P->eb_user);
   h[4] = __double_as_longlong(P->eb_abs);
   h[5] = __double_as_longlong(P->eb_eff);
@@ -519,10 +519,10 @@ __global__ void k_header(const SetDesc* sets, const DevParams* params) {
   for (uint32_t d = 0; d < 3; ++d) h[8 + d] = d < dims ? __double_as_longlong(P->lo[d]) : 0;
   h[11] = (uint64_t)P->G[0] | ((uint64_t)(dims > 1 ? P->G[1] : 0) << 8) |
           ((uint64_t)(dims > 2 ? P->G[2] : 0) << 16);
-  h[12] = S.n_leaves;
+  h[12] = S.split ? P->nleaves : S.n_leaves;  // a split-rule partition's count is the device's
   h[13] = P->meta_bits;
   h[14] = P->payload_bits;
-  h[15] = S.reduce ? P->nseq : 0;  // version 2: the sequence count
+  h[15] = seq_stream(S) ? P->nseq : 0;  // version 2: the sequence count
   uint64_t* o = (uint64_t*)S.out;
   for (int k = 0; k < 16; ++k) o[k] = h[k];
 }
@@ -555,7 +555,7 @@ __device__ void lossless_copy(const SetDesc& S, uint64_t lb, uint64_t nblk) {
       out[k] = S.layout == BBX_AOS ? in[k] : in[d * S.n + i];
     }
   }
-  uint32_t* perm = S.reduce ? S.user_perm : S.perm;
+  uint32_t* perm = seq_stream(S) ? S.user_perm : S.perm;
   if (perm)
     for (uint64_t i = lb * kBlock + threadIdx.x; i < S.n; i += step) perm[i] = (uint32_t)i;
 }

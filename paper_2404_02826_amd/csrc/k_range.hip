@@ -168,7 +168,8 @@ __global__ void __launch_bounds__(kBlock) k_epilogue(const SetDesc* sets, const 
   p.diag = 0;
   p.meta_bits = p.payload_bits = p.total_bytes = p.payload_base = 0;
   p.nseq = 0;
-  for (int k = 0; k < 2; ++k) p.pad1[k] = 0;
+  p.nleaves = 0;
+  p.pad1[0] = 0;
   if (n == 0) {
     p.eb_abs = S.eb_mode == BBX_EB_ABS ? eb : 0.0;
     *P = p;
@@ -334,7 +335,7 @@ __global__ void __launch_bounds__(kBlock) k_quantize(uint32_t nsets, const uint6
   // with more than one digit pass (the same condition the level kernels use)
   __shared__ uint32_t lh[kHistBins];
   const DigitPlan pl = digit_plan(P->G[0]);
-  const bool root = !level_is_local(S.n, 0) && pl.npass >= 2 && S.n > S.r;
+  const bool root = !S.split && !level_is_local(S.n, 0) && pl.npass >= 2 && S.n > S.r;
   const uint32_t hsh = pl.shift[0], hmask = (1u << pl.width[0]) - 1;
   if (root) {
     lh[threadIdx.x] = 0;

@@ -38,19 +38,6 @@ typedef unsigned __int128 u128;
 constexpr uint64_t kDead = ~0ull;  // key of a popped or empty box
 
 __device__ inline uint32_t red_reach(uint32_t m) { return m ? (1u << (m - 1)) - 1u : 0u; }
-__device__ inline uint32_t red_m(uint32_t mp, uint32_t d) { return (mp >> (8 * d)) & 0xffu; }
-
-// key << 31 | leaf (leaf < 2^31): the order of (key, leaf)
-__device__ inline uint64_t red_key(uint32_t mp, uint32_t dims, uint32_t rule, uint32_t leaf) {
-  uint64_t k = 0;
-  for (uint32_t d = 0; d < dims; ++d) {
-    const uint32_t m = red_m(mp, d);
-    k += rule == 2 ? ((1ull << m) - 1) : m;
-  }
-  return (k << 31) | leaf;
-}
-
-__device__ inline uint32_t red_width(uint32_t D) { return D ? 33u - (uint32_t)__builtin_clz(D) : 0u; }
 
 // The reduction state of a set inside the batch workspace.
 struct RedSet {
@@ -236,10 +223,12 @@ __global__ void __launch_bounds__(kRedBlock) k_reduce(uint32_t nsets, const uint
   const SetDesc& S = w.sets[s];
   DevParams* P = w.params + s;
   if (P->status != BBX_OK || !S.reduce || S.n == 0) return;
-  if ((S.n_leaves <= kRedLdsBoxes) != LDS) return;
+  // a split-rule set's leaf count is found on the device
+  const uint64_t NL = S.split ? P->nleaves : S.n_leaves;
+  if ((NL <= kRedLdsBoxes) != LDS) return;
   const RedSet R = red_set(S, w);
   const LeafRec* leaves = w.leaves + S.leaf_off;
-  const uint32_t B = (uint32_t)S.n_leaves, dims = S.dims;
+  const uint32_t B = (uint32_t)NL, dims = S.dims;
   const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   constexpr uint32_t W = kRedBlock / 64;
   uint64_t* K = LDS ? (uint64_t*)red_dyn : R.key;
@@ -409,7 +398,7 @@ __global__ void __launch_bounds__(kBlock) k_red_meta(uint32_t nsets, const uint6
   const uint32_t s = find_set(pre, nsets, blockIdx.x);
   const SetDesc& S = w.sets[s];
   const DevParams* P = w.params + s;
-  if (P->status != BBX_OK || !S.reduce) return;
+  if (P->status != BBX_OK || !seq_stream(S)) return;
   const RedSet R = red_set(S, w);
   const uint64_t lb = blockIdx.x - pre[s], nblk = pre[s + 1] - pre[s];
   const uint32_t dims = S.dims, mbits = S.mbits;
@@ -456,7 +445,7 @@ __global__ void __launch_bounds__(kBlock) k_red_payload(uint32_t nsets, const ui
   const uint32_t s = find_set(pre, nsets, blockIdx.x);
   const SetDesc& S = w.sets[s];
   const DevParams* P = w.params + s;
-  if (P->status != BBX_OK || !S.reduce || P->payload_bits == 0) return;
+  if (P->status != BBX_OK || !seq_stream(S) || P->payload_bits == 0) return;
   const RedSet R = red_set(S, w);
   const uint64_t lb = blockIdx.x - pre[s], nblk = pre[s + 1] - pre[s];
   const uint64_t nseq = P->nseq, base = P->payload_base;
@@ -501,7 +490,7 @@ __global__ void __launch_bounds__(kBlock) k_red_perm(uint32_t nsets, const uint6
   const uint32_t s = find_set(pre, nsets, blockIdx.x);
   const SetDesc& S = w.sets[s];
   const DevParams* P = w.params + s;
-  if (P->status != BBX_OK || !S.reduce || !S.user_perm) return;
+  if (P->status != BBX_OK || !seq_stream(S) || !S.user_perm) return;
   const RedSet R = red_set(S, w);
   const uint64_t lb = blockIdx.x - pre[s], nblk = pre[s + 1] - pre[s];
   for (uint64_t i = lb * kBlock + threadIdx.x; i < S.n; i += nblk * kBlock)
