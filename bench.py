@@ -783,6 +783,8 @@ def main():
                    "cr_other_ref_rule": round(B_in / S_alt, 4),
                    "cr_other_ref_mode": round(B_in / S_alt_mode, 4) if S_alt_mode else None,
                    "reduce": args.reduce, "split_rule": args.split_rule,
+                   "n_leaves": info["n_leaves"],
+                   "n_seq": int(np.frombuffer(header[120:128], dtype="<u8")[0]),
                    "cr_without_reduce": round(B_in / S_plain, 4),
                    "sequence_export": export,
                    "bpp": round(8 * S / n, 4),
