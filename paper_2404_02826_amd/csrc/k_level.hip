@@ -524,6 +524,17 @@ __global__ void __launch_bounds__(kBlock) k_select_last_wide(uint32_t depth, uin
   }
 }
 
+// The next level's first-digit bins while a chunk is partitioned: kLhCopies
+// copies per child (lane mod kLhCopies picks one), each 257 words apart so
+// that equal bins of different copies sit in different LDS banks; few bins
+// (32 for 13-bit codes) are hit by many lanes at once, and one copy made the
+// atomics collide.
+constexpr uint32_t kLhCopies = 4, kLhStride = 257;
+constexpr uint32_t kLhWords = 2 * kLhCopies * kLhStride;
+__device__ __forceinline__ uint32_t lh_slot(bool left, uint32_t bin) {
+  return ((left ? 0u : kLhCopies) + (threadIdx.x & (kLhCopies - 1))) * kLhStride + bin;
+}
+
 // Stable partition of a chunk in streaming groups of kGroup elements:
 // wavefront w of the block takes the 512 consecutive elements
 // [g + 512 w, g + 512 w + 512) of a group as 8 rows of 64.  Codes are handled
@@ -609,8 +620,7 @@ __device__ __forceinline__ void scatter_store(uint32_t g, uint32_t end, const ui
       else if (!TRACK && is)
         id[dest] = is[p];
       if (left ? cl : cr)
-        atomicAdd(&lhist[(left ? 0u : (uint32_t)kBlock) + (((NA > 1 ? k[1][i] : k[0][i]) >> shn) & maskn)],
-                  1u);
+        atomicAdd(&lhist[lh_slot(left, (NA > 1 ? k[1][i] : k[0][i]) >> shn & maskn)], 1u);
     } else {
       check_failed(P, kChkScatterStore);
     }
@@ -649,8 +659,7 @@ __device__ __forceinline__ void scatter_stage(uint32_t g, uint32_t end, const ui
       if (NA > 2) stg[2 * kGroup + loc] = k[2][i];
       if (TRACK) stg[3 * kGroup + loc] = ki[i];  // (zero when the set carries none)
       if (left ? cl : cr)
-        atomicAdd(&lhist[(left ? 0u : (uint32_t)kBlock) + (((NA > 1 ? k[1][i] : k[0][i]) >> shn) & maskn)],
-                  1u);
+        atomicAdd(&lhist[lh_slot(left, (NA > 1 ? k[1][i] : k[0][i]) >> shn & maskn)], 1u);
     } else {
       check_failed(P, kChkScatterStage);
     }
@@ -792,7 +801,8 @@ __device__ void scatter_body(uint32_t depth, const SetDesc& S, DevParams* P, con
   const bool fuse = depth + 1 < S.gl && pn.npass >= 2 && level_kind(n, depth + 1) != kLevelWave;
   const uint32_t wn = pn.width[0], shn = pn.shift[0], maskn = (1u << wn) - 1;
   const bool cl = fuse && half > r, cr = fuse && (sz - half) > r;  // children that split again
-  if (fuse) lhist[threadIdx.x] = lhist[kBlock + threadIdx.x] = 0;
+  if (fuse)
+    for (uint32_t i = threadIdx.x; i < kLhWords; i += kBlock) lhist[i] = 0;
   // axis order: split axis, next axis, third axis
   const uint32_t a1 = dims > 1 ? dn : d, a2 = dims > 2 ? (d + 2) % dims : d;
   const KT* A0 = (const KT*)src + st + (uint64_t)d * kst;
@@ -810,7 +820,10 @@ __device__ void scatter_body(uint32_t depth, const SetDesc& S, DevParams* P, con
   if (fuse) {
     __syncthreads();
     for (uint32_t child = 0; child < 2; ++child) {
-      const uint32_t cnum = lhist[child * kBlock + threadIdx.x];
+      uint32_t cnum = 0;
+#pragma unroll
+      for (uint32_t cp = 0; cp < kLhCopies; ++cp)
+        cnum += lhist[(child * kLhCopies + cp) * kLhStride + threadIdx.x];
       if (cnum) atomicAdd(&hist_level(S, depth + 1, hist)[((2 * j + child) << 8) + threadIdx.x], cnum);
     }
   }
@@ -832,7 +845,7 @@ __global__ void __launch_bounds__(kBlock) k_scatter(uint32_t depth, uint32_t nse
   DevParams* P = params + c.s;
   if (P->status != BBX_OK) return;
   if (level_is_local(S.n, depth)) return;
-  __shared__ uint32_t lhist[2 * kBlock];
+  __shared__ uint32_t lhist[kLhWords];
   __shared__ uint32_t stg[STAGE ? (TRACK ? 4 : 3) * kGroup : 1];  // one staged group (codes, indices)
   const uint32_t* isrc = S.track ? isrc0 + S.idx_off : nullptr;
   uint32_t* idst = S.track ? idst0 + S.idx_off : nullptr;
@@ -936,7 +949,7 @@ __global__ void __launch_bounds__(kBlock) k_level_local(uint32_t depth, uint32_t
   DevParams* P = params + c.s;
   if (P->status != BBX_OK) return;
   if (level_kind(S.n, depth) != kLevelBlock) return;
-  __shared__ uint32_t lhist[2 * kBlock];
+  __shared__ uint32_t lhist[kLhWords];
   __shared__ uint32_t red[16];
   const uint32_t* isrc = S.track ? isrc0 + S.idx_off : nullptr;
   uint32_t* idst = S.track ? idst0 + S.idx_off : nullptr;
