@@ -1712,3 +1712,200 @@ int bbxo_export_sequences_reordered(const uint8_t* s, uint64_t size, uint8_t* ou
   free(plain), free(sizes), free(start), free(wid), free(seq), free(mem);
   return BBXO_OK;
 }
+
+/* ------------------------------------------------------------------ entropy coding */
+
+/* Huffman coding of a byte sequence (the encoding phase of Sec. 3, which the
+ * paper applies to its sequence layout, Sec. 4.2).  Symbols are bytes.  Code
+ * lengths come from Huffman's construction: repeatedly the two lightest
+ * nodes merge, weights compared first and the node created earlier (leaves
+ * first, in symbol order) preferred on ties; a tree deeper than HUF_MAXLEN
+ * is rebuilt from the weights halved (rounded up, so none vanishes) until
+ * it fits.  Codes are canonical: symbols in (length, symbol) order take
+ * consecutive codes, each shifted left when the length grows.  The input is
+ * cut into chunks of HUF_CHUNK bytes whose first bit offsets are stored, so
+ * chunks decode independently.
+ *
+ * Stream: [0,4) 'BBXH' | [4,6) version 1 | [6] HUF_MAXLEN | [7] 0 |
+ * [8,16) n bytes | [16,20) HUF_CHUNK | [20,24) 0 | [24,32) chunks |
+ * [32,40) payload bits | [40,48) 0 | [48,176) code lengths, a nibble per
+ * symbol (low nibble: even symbol) | chunk bit offsets (u64 each, from the
+ * payload start) | payload: codes in input order, each code's most
+ * significant bit first, bit i of the payload = bit i mod 64 of its u64 word
+ * i / 64, zero-padded to 8 bytes. */
+#define HUF_MAGIC 0x48584242u /* bytes 'B','B','X','H' */
+#define HUF_MAXLEN 12u
+#define HUF_CHUNK 16384u
+#define HUF_HEADER 176u
+
+void bbxo_huffman_lengths(const uint64_t* counts, uint32_t* len) {
+  uint64_t w[256];
+  for (int s = 0; s < 256; s++) w[s] = counts[s], len[s] = 0;
+  for (;;) {
+    uint32_t sym[256], k = 0;
+    for (uint32_t s = 0; s < 256; s++)
+      if (w[s]) sym[k++] = s;
+    if (k == 0) return;
+    if (k == 1) {
+      len[sym[0]] = 1;
+      return;
+    }
+    /* nodes 0..k-1 the leaves (symbol order), k.. the merged ones */
+    uint64_t weight[511];
+    int parent[511], alive[511];
+    for (uint32_t i = 0; i < k; i++) weight[i] = w[sym[i]], parent[i] = -1, alive[i] = 1;
+    uint32_t nn = k;
+    for (uint32_t m = 0; m + 1 < k; m++) {
+      int pick[2] = {-1, -1};
+      for (int t = 0; t < 2; t++)
+        for (uint32_t i = 0; i < nn; i++) {
+          if (!alive[i] || (int)i == pick[0]) continue;
+#if MUT(35)
+          if (pick[t] < 0 || weight[i] > weight[pick[t]]) pick[t] = (int)i; /* heaviest */
+#elif MUT(33)
+          if (pick[t] < 0 || weight[i] <= weight[pick[t]]) pick[t] = (int)i; /* later on ties */
+#else
+          if (pick[t] < 0 || weight[i] < weight[pick[t]]) pick[t] = (int)i;
+#endif
+        }
+      weight[nn] = weight[pick[0]] + weight[pick[1]];
+      parent[nn] = -1;
+      alive[nn] = 1;
+      alive[pick[0]] = alive[pick[1]] = 0;
+      parent[pick[0]] = parent[pick[1]] = (int)nn;
+      nn++;
+    }
+    uint32_t deepest = 0, d[256];
+    for (uint32_t i = 0; i < k; i++) {
+      uint32_t depth = 0;
+      for (int p = parent[i]; p >= 0; p = parent[p]) depth++;
+      d[i] = depth;
+      if (depth > deepest) deepest = depth;
+    }
+    if (deepest <= HUF_MAXLEN) {
+      for (uint32_t i = 0; i < k; i++) len[sym[i]] = d[i];
+      return;
+    }
+    for (int s = 0; s < 256; s++)
+      if (w[s]) w[s] = (w[s] + 1) / 2;
+  }
+}
+
+/* Canonical codes of the lengths. */
+static void huf_codes(const uint32_t* len, uint32_t* code) {
+  uint32_t c = 0, prev = 0;
+  int first = 1;
+  for (uint32_t L = 1; L <= HUF_MAXLEN; L++)
+#if MUT(34)
+    for (int s = 255; s >= 0; s--) {
+#else
+    for (int s = 0; s < 256; s++) {
+#endif
+      if (len[s] != L) continue;
+      if (!first) c = (c + 1) << (L - prev);
+      first = 0;
+      code[s] = c;
+      prev = L;
+    }
+}
+
+static void put_code(uint8_t* sec, uint64_t pos, uint32_t code, uint32_t L) {
+  for (uint32_t b = 0; b < L; b++) {
+#if MUT(37)
+    uint32_t bit = (code >> b) & 1u; /* least significant bit first */
+#else
+    uint32_t bit = (code >> (L - 1 - b)) & 1u;
+#endif
+    if (bit) sec[(pos + b) >> 3] |= (uint8_t)(1u << ((pos + b) & 7u));
+  }
+}
+
+uint64_t bbxo_huffman_bound(uint64_t n) {
+  return HUF_HEADER + 8 * ((n + HUF_CHUNK - 1) / HUF_CHUNK) + words_bytes(n * HUF_MAXLEN);
+}
+
+int bbxo_huffman_encode(const uint8_t* in, uint64_t n, uint8_t* out, uint64_t out_cap,
+                        uint64_t* out_size) {
+  uint64_t cnt[256];
+  uint32_t len[256], code[256];
+  memset(cnt, 0, sizeof(cnt));
+  for (uint64_t i = 0; i < n; i++) cnt[in[i]]++;
+  bbxo_huffman_lengths(cnt, len);
+  memset(code, 0, sizeof(code));
+  huf_codes(len, code);
+  uint64_t bits = 0;
+  for (int s = 0; s < 256; s++) bits += cnt[s] * len[s];
+  const uint64_t chunks = (n + HUF_CHUNK - 1) / HUF_CHUNK;
+  const uint64_t total = HUF_HEADER + 8 * chunks + words_bytes(bits);
+  if (out_size) *out_size = total;
+  if (total > out_cap) return BBXO_ENOSPC;
+  memset(out, 0, (size_t)total);
+  put_u32le(out, HUF_MAGIC);
+  put_u16le(out + 4, 1);
+  out[6] = (uint8_t)HUF_MAXLEN;
+  put_u64le(out + 8, n);
+  put_u32le(out + 16, HUF_CHUNK);
+  put_u64le(out + 24, chunks);
+  put_u64le(out + 32, bits);
+  for (int s = 0; s < 256; s++) out[48 + s / 2] |= (uint8_t)(len[s] << ((s & 1) ? 4 : 0));
+  uint8_t* offs = out + HUF_HEADER;
+  uint8_t* pay = offs + 8 * chunks;
+  uint64_t pos = 0;
+  for (uint64_t i = 0; i < n; i++) {
+    if (i % HUF_CHUNK == 0)
+#if MUT(36)
+      put_u64le(offs + 8 * (i / HUF_CHUNK), pos + (i ? 1 : 0));
+#else
+      put_u64le(offs + 8 * (i / HUF_CHUNK), pos);
+#endif
+    put_code(pay, pos, code[in[i]], len[in[i]]);
+    pos += len[in[i]];
+  }
+  return BBXO_OK;
+}
+
+int bbxo_huffman_decode(const uint8_t* s, uint64_t size, uint8_t* out, uint64_t out_cap,
+                        uint64_t* out_n) {
+  if (!s || size < HUF_HEADER || get_u32le(s) != HUF_MAGIC || get_u16le(s + 4) != 1 ||
+      s[6] != HUF_MAXLEN || s[7] != 0 || get_u32le(s + 16) != HUF_CHUNK || get_u32le(s + 20) != 0 ||
+      get_u64le(s + 40) != 0)
+    return BBXO_ECORRUPT;
+  const uint64_t n = get_u64le(s + 8), chunks = get_u64le(s + 24), bits = get_u64le(s + 32);
+  if (chunks != (n + HUF_CHUNK - 1) / HUF_CHUNK || bits > n * HUF_MAXLEN) return BBXO_ECORRUPT;
+  if (size < HUF_HEADER + 8 * chunks + words_bytes(bits)) return BBXO_ECORRUPT;
+  if (out_n) *out_n = n;
+  if (n > out_cap) return BBXO_ENOSPC;
+  uint32_t len[256], code[256];
+  uint64_t kraft = 0; /* in units of 2^-HUF_MAXLEN */
+  uint32_t used = 0;
+  for (int t = 0; t < 256; t++) {
+    len[t] = (s[48 + t / 2] >> ((t & 1) ? 4 : 0)) & 15u;
+    if (len[t] > HUF_MAXLEN) return BBXO_ECORRUPT;
+    if (len[t]) kraft += 1ull << (HUF_MAXLEN - len[t]), used++;
+  }
+  if (n > 0 && (used == 0 || kraft > (1ull << HUF_MAXLEN))) return BBXO_ECORRUPT;
+  memset(code, 0, sizeof(code));
+  huf_codes(len, code);
+  const uint8_t* offs = s + HUF_HEADER;
+  const uint8_t* pay = offs + 8 * chunks;
+  for (uint64_t c = 0; c < chunks; c++) {
+    uint64_t pos = get_u64le(offs + 8 * c);
+    const uint64_t end = c + 1 < chunks ? get_u64le(offs + 8 * (c + 1)) : bits;
+    if (pos > end || end > bits) return BBXO_ECORRUPT;
+    const uint64_t i0 = c * HUF_CHUNK, i1 = i0 + HUF_CHUNK < n ? i0 + HUF_CHUNK : n;
+    for (uint64_t i = i0; i < i1; i++) {
+      /* read bits until they spell a code of the table */
+      uint32_t v = 0, L = 0, sym = 256;
+      while (sym == 256) {
+        if (L == HUF_MAXLEN || pos >= end) return BBXO_ECORRUPT;
+        v = (v << 1) | (uint32_t)((pay[pos >> 3] >> (pos & 7u)) & 1u);
+        pos++, L++;
+        for (int t = 0; t < 256 && sym == 256; t++)
+          if (len[t] == L && code[t] == v) sym = (uint32_t)t;
+      }
+      out[i] = (uint8_t)sym;
+    }
+    if (pos != end) return BBXO_ECORRUPT;
+  }
+  return BBXO_OK;
+}

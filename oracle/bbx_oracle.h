@@ -135,6 +135,18 @@ void bbxo_axis_order_by_entropy(const uint32_t* widths, uint64_t nseq, uint32_t 
 uint64_t bbxo_r_index(const uint64_t* u, const uint32_t* m, uint32_t dims, const uint32_t* order,
                       uint64_t* hi);
 
+/* Huffman coding of bytes (the encoding phase of Sec. 3 applied to the
+ * sequence layout of Sec. 4.2): code lengths of Huffman's construction
+ * (ties: the earlier node; rebuilt from halved weights until no code is
+ * longer than 12 bits), canonical codes, chunks of 16,384 input bytes with
+ * their first bit offsets stored.  The stream layout is in bbx_oracle.c. */
+void bbxo_huffman_lengths(const uint64_t* counts, uint32_t* len);
+uint64_t bbxo_huffman_bound(uint64_t n);
+int bbxo_huffman_encode(const uint8_t* in, uint64_t n, uint8_t* out, uint64_t out_cap,
+                        uint64_t* out_size);
+int bbxo_huffman_decode(const uint8_t* stream, uint64_t size, uint8_t* out, uint64_t out_cap,
+                        uint64_t* out_n);
+
 /* Number of leaves of the size-only recursion for n particles, capacity r. */
 uint64_t bbxo_leaf_count(uint64_t n, uint32_t r);
 

@@ -567,3 +567,101 @@ def export_sequences_reordered(stream: bytes):
         out |= 0xFFFFFFFF << opos
         opos += 32
     return out.to_bytes(8 * ((opos + 63) // 64), "little"), order
+
+
+# ---------------------------------------------------------------- entropy coding
+
+HUF_MAXLEN, HUF_CHUNK = 12, 16384
+
+
+def huffman_lengths(counts):
+    """Huffman's construction restated with a priority queue: entries
+    (weight, creation number); leaves numbered first in symbol order, merged
+    nodes after them in creation order; depth of each leaf; rebuilt from the
+    halved weights (rounded up) while some depth exceeds HUF_MAXLEN."""
+    import heapq
+    w = [int(c) for c in counts]
+    while True:
+        syms = [s for s in range(256) if w[s] > 0]
+        if not syms:
+            return [0] * 256
+        if len(syms) == 1:
+            out = [0] * 256
+            out[syms[0]] = 1
+            return out
+        heap = [(w[s], i) for i, s in enumerate(syms)]
+        heapq.heapify(heap)
+        children = {}
+        nid = len(syms)
+        while len(heap) > 1:
+            a = heapq.heappop(heap)
+            b = heapq.heappop(heap)
+            children[nid] = (a[1], b[1])
+            heapq.heappush(heap, (a[0] + b[0], nid))
+            nid += 1
+        depth = {}
+        stack = [(heap[0][1], 0)]
+        while stack:
+            node, dpt = stack.pop()
+            if node in children:
+                for ch in children[node]:
+                    stack.append((ch, dpt + 1))
+            else:
+                depth[node] = dpt
+        lens = [0] * 256
+        for i, s in enumerate(syms):
+            lens[s] = depth[i]
+        if max(lens) <= HUF_MAXLEN:
+            return lens
+        w = [(x + 1) // 2 if x else 0 for x in w]
+
+
+def canonical_codes(lens):
+    """Codes in (length, symbol) order, consecutive, shifted at each longer length."""
+    order = sorted((L, s) for s, L in enumerate(lens) if L)
+    codes, c, prev = {}, 0, None
+    for L, s in order:
+        if prev is not None:
+            c = (c + 1) << (L - prev)
+        codes[s] = c
+        prev = L
+    return codes
+
+
+def huffman_encode(data: bytes) -> bytes:
+    n = len(data)
+    counts = [0] * 256
+    for b in data:
+        counts[b] += 1
+    lens = huffman_lengths(counts)
+    codes = canonical_codes(lens)
+    chunks = -(-n // HUF_CHUNK)
+    pay, pos, offs = 0, 0, []
+    for i, b in enumerate(data):
+        if i % HUF_CHUNK == 0:
+            offs.append(pos)
+        L = lens[b]
+        for k in range(L):  # most significant code bit first
+            pay |= ((codes[b] >> (L - 1 - k)) & 1) << pos
+            pos += 1
+    nib = bytearray(128)
+    for s in range(256):
+        nib[s // 2] |= lens[s] << (4 if s & 1 else 0)
+    head = struct.pack("<4sHBBQIIQQQ", b"BBXH", 1, HUF_MAXLEN, 0, n, HUF_CHUNK, 0, chunks, pos, 0)
+    return (head + bytes(nib) + b"".join(struct.pack("<Q", o) for o in offs)
+            + pay.to_bytes(8 * ((pos + 63) // 64), "little"))
+
+
+def huffman_optimal_cost(counts):
+    """Smallest sum of count x length over every length assignment with
+    Kraft sum <= 1 (exhaustive; tiny alphabets only)."""
+    import itertools
+    syms = [c for c in counts if c > 0]
+    if len(syms) <= 1:
+        return sum(syms)
+    best = None
+    for L in itertools.product(range(1, len(syms)), repeat=len(syms)):
+        if sum(Fraction(1, 2 ** x) for x in L) <= 1:
+            cost = sum(c * x for c, x in zip(syms, L))
+            best = cost if best is None else min(best, cost)
+    return best

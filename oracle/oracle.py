@@ -73,6 +73,14 @@ class Oracle:
         lib.bbxo_compress_split.restype = i32
         lib.bbxo_compress_split.argtypes = [vp, u64, u32, i32, i32, dbl, i32, u32, i32, i32, i32,
                                             vp, u64, C.POINTER(u64), vp]
+        lib.bbxo_huffman_lengths.restype = None
+        lib.bbxo_huffman_lengths.argtypes = [vp, vp]
+        lib.bbxo_huffman_bound.restype = u64
+        lib.bbxo_huffman_bound.argtypes = [u64]
+        lib.bbxo_huffman_encode.restype = i32
+        lib.bbxo_huffman_encode.argtypes = [vp, u64, vp, u64, C.POINTER(u64)]
+        lib.bbxo_huffman_decode.restype = i32
+        lib.bbxo_huffman_decode.argtypes = [vp, u64, vp, u64, C.POINTER(u64)]
         lib.bbxo_axis_order_by_entropy.restype = None
         lib.bbxo_axis_order_by_entropy.argtypes = [vp, u64, u32, vp]
         lib.bbxo_r_index.restype = u64
@@ -172,6 +180,39 @@ class Oracle:
             raise OracleError(st)
         stream = out[: size.value].tobytes()
         return (stream, perm[:n].copy()) if want_perm else stream
+
+    def huffman_lengths(self, counts) -> list:
+        c = np.ascontiguousarray(np.asarray(counts, dtype=np.uint64).reshape(256))
+        out = np.zeros(256, dtype=np.uint32)
+        self.lib.bbxo_huffman_lengths(c.ctypes.data, out.ctypes.data)
+        return out.tolist()
+
+    def huffman_encode(self, data: bytes) -> bytes:
+        """Huffman coding of bytes (canonical codes, 12-bit limit, chunks of
+        16,384 bytes)."""
+        a = np.frombuffer(bytes(data), dtype=np.uint8)
+        n = len(a)
+        cap = int(self.lib.bbxo_huffman_bound(n))
+        out = np.zeros(max(cap, 1), dtype=np.uint8)
+        size = C.c_uint64(0)
+        st = self.lib.bbxo_huffman_encode(a.ctypes.data if n else None, n, out.ctypes.data, cap,
+                                          C.byref(size))
+        if st:
+            raise OracleError(st)
+        return out[: size.value].tobytes()
+
+    def huffman_decode(self, stream: bytes) -> bytes:
+        b = np.frombuffer(bytes(stream), dtype=np.uint8)
+        n = C.c_uint64(0)
+        st = self.lib.bbxo_huffman_decode(b.ctypes.data, len(b), None, 0, C.byref(n))
+        if st not in (0, 2):
+            raise OracleError(st)
+        out = np.zeros(max(n.value, 1), dtype=np.uint8)
+        st = self.lib.bbxo_huffman_decode(b.ctypes.data, len(b), out.ctypes.data, n.value,
+                                          C.byref(n))
+        if st:
+            raise OracleError(st)
+        return out[: n.value].tobytes()
 
     def compress_reduced(self, pos: np.ndarray, eb: float, eb_mode: str = "rel", r: int = 32,
                          layout: str = "aos", key_rule: int = 0, want_perm: bool = False):

@@ -366,6 +366,70 @@ def pin_split_brute(orc, seed=18, count=30):
                 assert np.array_equal(orc.decompress(s1), brute.decompress(s2))
 
 
+def pin_huffman_example(orc):
+    """Huffman coding of the encoding phase (Sec. 3) on a hand-worked input:
+    lengths, canonical codes, the payload's bit order, the length nibbles and
+    the stream size; and the decode."""
+    with open(os.path.join(GOLDEN, "huffman_example.json")) as f:
+        g = json.load(f)
+    data = g["input_ascii"].encode()
+    counts = [0] * 256
+    for b in data:
+        counts[b] += 1
+    lens = orc.huffman_lengths(counts)
+    assert {str(s): L for s, L in enumerate(lens) if L} == g["lengths"], lens
+    s = orc.huffman_encode(data)
+    assert len(s) == g["stream_bytes"]
+    assert int.from_bytes(s[32:40], "little") == g["payload_bits"]
+    for k, v in g["length_bytes"].items():
+        assert s[int(k)] == v, (k, s[int(k)])
+    assert s[184:192].hex() == g["payload_hex"], s[184:192].hex()
+    codes = brute.canonical_codes(lens)
+    assert {str(k): format(v, "0%db" % lens[k]) for k, v in codes.items()} == g["codes"]
+    assert orc.huffman_decode(s) == data
+
+
+def pin_huffman_optimal(orc, seed=19, count=40):
+    """The lengths are optimal: their cost equals the least cost over every
+    length assignment that satisfies Kraft's inequality (exhaustive search,
+    alphabets of at most 6 symbols), and the Kraft sum is exactly 1."""
+    rng = np.random.default_rng(seed)
+    for _ in range(count):
+        k = int(rng.integers(2, 7))
+        counts = [0] * 256
+        for s_ in rng.choice(256, k, replace=False):
+            counts[int(s_)] = int(rng.integers(1, 30))
+        lens = orc.huffman_lengths(counts)
+        cost = sum(c * L for c, L in zip(counts, lens))
+        assert cost == brute.huffman_optimal_cost(counts), (counts, lens)
+        from fractions import Fraction
+        assert sum(Fraction(1, 2 ** L) for L in lens if L) == 1
+
+
+def pin_huffman_brute(orc, seed=20):
+    """Streams byte-equal to the priority-queue restatement, on inputs with
+    ties, skewed and uniform bytes, several chunks and a ragged tail; a
+    distribution that needs the 12-bit limit (Fibonacci counts); one
+    symbol; nothing; every stream decodes to its input."""
+    rng = np.random.default_rng(seed)
+    fib = [1, 1]
+    while len(fib) < 24:
+        fib.append(fib[-1] + fib[-2])
+    deep = b"".join(bytes([i]) * f for i, f in enumerate(fib))
+    cases = [b"", b"z", b"zzzz", b"abracadabra", deep,
+             bytes(rng.integers(0, 256, 3 * 16384 + 5, dtype=np.uint8)),
+             bytes(rng.geometric(0.2, 40000).clip(0, 255).astype(np.uint8)),
+             bytes(rng.integers(0, 3, 20000, dtype=np.uint8))]
+    for data in cases:
+        s = orc.huffman_encode(data)
+        assert s == brute.huffman_encode(data), len(data)
+        assert orc.huffman_decode(s) == data
+    counts = [0] * 256
+    for b in deep:
+        counts[b] += 1
+    assert max(orc.huffman_lengths(counts)) == 12  # unlimited, the tree would be 23 deep
+
+
 def run_battery(orc):
     """Returns the names of the pins that fail."""
     failed = []
@@ -377,7 +441,8 @@ def run_battery(orc):
                      ("reduction_special", pin_reduction_special),
                      ("lossless_fallback", pin_lossless_fallback),
                      ("split_examples", pin_split_examples), ("split_counts", pin_split_counts),
-                     ("split_brute", pin_split_brute)):
+                     ("split_brute", pin_split_brute), ("huffman_example", pin_huffman_example),
+                     ("huffman_optimal", pin_huffman_optimal), ("huffman_brute", pin_huffman_brute)):
         try:
             fn(orc)
         except Exception as e:  # noqa: BLE001 -- any failure counts as caught

@@ -46,6 +46,11 @@ MUTANTS = {
     30: "split rule 1 breaks extent ties towards the last axis",
     31: "split rule 3 stops at a one-code-wide axis instead of trying the next",
     32: "split rule 2 makes floor(n/r) leaves",
+    33: "Huffman merges prefer the later node on equal weights",
+    34: "canonical codes assigned in descending symbol order within a length",
+    35: "Huffman merges the heaviest nodes",
+    36: "chunk bit offsets one past the chunk's first code",
+    37: "codes written least significant bit first",
 }
 
 
