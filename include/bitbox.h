@@ -303,6 +303,68 @@ bbx_status bbx_export_sequences(const void* d_stream, size_t stream_size, const 
                                 void* d_out, size_t out_cap, uint32_t* d_status, void* d_ws,
                                 size_t ws_size, hipStream_t stream);
 
+/*
+ * The sequence layout after the two reorderings of Sec. 4.2 that lower its
+ * entropy before Huffman coding: sequences in ascending sum of widths (equal
+ * sums keep leaf order), and in each sequence the other members in
+ * ascending R-index, the members' codes concatenated with the axes in
+ * ascending entropy of their width distributions (the first axis most
+ * significant; axes with equal sums of c log2 c over their width counts c
+ * keep their order), equal R-indices in stored order.  Each member keeps its
+ * codes in axis order (x, y, z); each sequence keeps its centre, widths and
+ * end mark.  The same length as bbx_export_sequences, for the same streams
+ * (version 1, ref_mode 1).  h_header is required; h_axis_order (optional,
+ * dims entries) receives the axis order.  The call waits (the host derives
+ * the axis order from the device's width histograms); d_ws holds
+ * bbx_export_reordered_workspace_size bytes (0 for an unsuitable header).
+ */
+size_t bbx_export_reordered_workspace_size(const void* h_header, size_t header_bytes);
+bbx_status bbx_export_sequences_reordered(const void* d_stream, size_t stream_size,
+                                          const void* h_header, void* d_out, size_t out_cap,
+                                          uint32_t* h_axis_order, void* d_ws, size_t ws_size,
+                                          hipStream_t stream);
+
+/*
+ * Huffman coding of a byte buffer: the encoding phase of Sec. 3, which the
+ * paper applies to its sequence layout (Sec. 4.2; bbx_export_sequences and
+ * bbx_export_sequences_reordered write that layout).  Symbols are bytes;
+ * code lengths from Huffman's construction (the two lightest nodes merge
+ * first; on equal weights the node created earlier, leaves in symbol order
+ * before merged nodes in creation order), rebuilt from the weights halved
+ * (rounded up) while a code would exceed 12 bits; canonical codes in
+ * (length, symbol) order.  The input is cut into chunks of 16,384 bytes that
+ * decode independently.  Stream: a 176-byte header ('BBXH', version 1, the
+ * 12-bit limit, n, the chunk size, the chunk count, the payload bits, then
+ * the 256 code lengths, a nibble each, low nibble for the even symbol), the
+ * chunks' first bit offsets (u64 each), then the codes in input order, each
+ * code's most significant bit first, bit i of the payload = bit i mod 64 of
+ * its u64 word i / 64, zero-padded to 8 bytes.
+ *   bbx_huffman_bound           the largest stream for n input bytes
+ *   bbx_huffman_workspace_size  device workspace bytes of either call
+ *   bbx_huffman_encode          d_in: n bytes (16-byte aligned); d_out
+ *                               (8-byte aligned) receives the stream and
+ *                               *h_out_size its length; the call waits (the
+ *                               host builds the code from the device's byte
+ *                               histogram)
+ *   bbx_huffman_decode          h_header: a host copy of the stream's first
+ *                               176 bytes (it plans the launch; the device
+ *                               compares it with the stream, ECORRUPT on a
+ *                               difference); d_out receives n bytes (8-byte
+ *                               aligned); d_status as for bbx_decompress
+ *                               (NULL: the call waits and returns the
+ *                               device's verdict: lengths above 12 bits, a
+ *                               Kraft sum above 1, a bit that spells no code,
+ *                               or a chunk that does not end at the next one's
+ *                               offset are ECORRUPT)
+ */
+size_t bbx_huffman_bound(uint64_t n);
+size_t bbx_huffman_workspace_size(uint64_t n);
+bbx_status bbx_huffman_encode(const void* d_in, uint64_t n, void* d_out, size_t out_cap,
+                              size_t* h_out_size, void* d_ws, size_t ws_size, hipStream_t stream);
+bbx_status bbx_huffman_decode(const void* d_stream, size_t stream_size, const void* h_header,
+                              void* d_out, size_t out_cap, uint32_t* d_status, void* d_ws,
+                              size_t ws_size, hipStream_t stream);
+
 /* Short name of a status value, and the calling thread's last error message. */
 const char* bbx_status_str(bbx_status status);
 const char* bbx_last_error(void);

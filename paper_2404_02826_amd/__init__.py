@@ -26,6 +26,9 @@ from ._binding import (  # noqa: F401
     decompress,
     decompress_workspace_size,
     export_sequences,
+    export_sequences_reordered,
+    huffman_decode,
+    huffman_encode,
     lib_path,
     load,
     plan_check,

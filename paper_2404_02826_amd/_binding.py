@@ -128,6 +128,18 @@ def load():
     lib.bbx_decompress_workspace_size.argtypes = [vp, sz]
     lib.bbx_decompress.restype = i32
     lib.bbx_decompress.argtypes = [vp, sz, vp, vp, sz, i32, vp, vp, sz, vp]
+    lib.bbx_export_reordered_workspace_size.restype = sz
+    lib.bbx_export_reordered_workspace_size.argtypes = [vp, sz]
+    lib.bbx_export_sequences_reordered.restype = i32
+    lib.bbx_export_sequences_reordered.argtypes = [vp, sz, vp, vp, sz, vp, vp, sz, vp]
+    lib.bbx_huffman_bound.restype = sz
+    lib.bbx_huffman_bound.argtypes = [u64]
+    lib.bbx_huffman_workspace_size.restype = sz
+    lib.bbx_huffman_workspace_size.argtypes = [u64]
+    lib.bbx_huffman_encode.restype = i32
+    lib.bbx_huffman_encode.argtypes = [vp, u64, vp, sz, C.POINTER(sz), vp, sz, vp]
+    lib.bbx_huffman_decode.restype = i32
+    lib.bbx_huffman_decode.argtypes = [vp, sz, vp, vp, sz, vp, vp, sz, vp]
     lib.bbx_export_sequences_size.restype = sz
     lib.bbx_export_sequences_size.argtypes = [vp, sz]
     lib.bbx_export_sequences.restype = i32
@@ -655,6 +667,62 @@ def export_sequences(stream_t: torch.Tensor, stream=None) -> torch.Tensor:
         raise BitboxError(3, "stream shorter than its header")
     header = stream_t[:128].cpu().numpy().tobytes()
     return SequenceExporter(header, stream_t.device)(stream_t, stream).clone()
+
+
+def export_sequences_reordered(stream_t: torch.Tensor, stream=None):
+    """The Sec. 4.2 sequence layout after its two reorderings (sequences by
+    sum of widths, members by R-index with the axes in ascending entropy) of
+    a device uint8 stream compressed with ref_mode = 1; returns (layout as a
+    uint8 device tensor, axis order)."""
+    lib = load()
+    if stream_t.numel() < 128:
+        raise BitboxError(3, "stream shorter than its header")
+    header = stream_t[:128].cpu().numpy().tobytes()
+    size = int(lib.bbx_export_sequences_size(header, 128))
+    ws_size = int(lib.bbx_export_reordered_workspace_size(header, 128))
+    if ws_size == 0:
+        raise BitboxError(1, "the sequence layout needs references stored as coordinates (ref_mode 1)")
+    ws = torch.empty(ws_size, dtype=torch.uint8, device=stream_t.device)
+    out = torch.empty(max(size, 8), dtype=torch.uint8, device=stream_t.device)
+    order = (C.c_uint32 * 3)()
+    _check(lib.bbx_export_sequences_reordered(stream_t.data_ptr(), stream_t.numel(), header,
+                                              out.data_ptr(), out.numel(), order, ws.data_ptr(),
+                                              ws_size, _stream_ptr(stream)))
+    dims = stream_info(header)["dims"]
+    return out[:size].clone(), [int(order[d]) for d in range(dims)]
+
+
+def huffman_encode(data: torch.Tensor, stream=None) -> torch.Tensor:
+    """Huffman coding of a device uint8 tensor (the encoding phase of Sec. 3;
+    canonical codes of at most 12 bits, chunks of 16,384 bytes); returns the
+    stream as a uint8 device tensor."""
+    lib = load()
+    if data.dtype != torch.uint8 or not data.is_cuda or not data.is_contiguous():
+        raise ValueError("input must be a contiguous uint8 device tensor")
+    n = data.numel()
+    ws_size = int(lib.bbx_huffman_workspace_size(n))
+    ws = torch.empty(ws_size, dtype=torch.uint8, device=data.device)
+    cap = int(lib.bbx_huffman_bound(n))
+    out = torch.empty((cap + 7) // 8 * 8, dtype=torch.uint8, device=data.device)
+    size = C.c_size_t(0)
+    _check(lib.bbx_huffman_encode(data.data_ptr() if n else None, n, out.data_ptr(), out.numel(),
+                                  C.byref(size), ws.data_ptr(), ws_size, _stream_ptr(stream)))
+    return out[: size.value].clone()
+
+
+def huffman_decode(stream_t: torch.Tensor, stream=None) -> torch.Tensor:
+    """Decode a device uint8 Huffman stream (waits for the device's verdict)."""
+    lib = load()
+    if stream_t.numel() < 176:
+        raise BitboxError(3, "Huffman stream shorter than its header")
+    header = stream_t[:176].cpu().numpy().tobytes()
+    n = int.from_bytes(header[8:16], "little")
+    ws_size = int(lib.bbx_huffman_workspace_size(n))
+    ws = torch.empty(ws_size, dtype=torch.uint8, device=stream_t.device)
+    out = torch.empty(max((n + 7) // 8 * 8, 8), dtype=torch.uint8, device=stream_t.device)
+    _check(lib.bbx_huffman_decode(stream_t.data_ptr(), stream_t.numel(), header, out.data_ptr(),
+                                  out.numel(), None, ws.data_ptr(), ws_size, _stream_ptr(stream)))
+    return out[:n].clone()
 
 
 @contextmanager

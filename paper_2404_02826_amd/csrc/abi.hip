@@ -1069,6 +1069,92 @@ bbx_status bbx_export_sequences(const void* d_stream, size_t stream_size, const 
   return BBX_OK;
 }
 
+// The reordered export's workspace: the decompression workspace, the plain
+// layout, width histograms, per-leaf keys, (key, block) counts, the new
+// order and the placed payload bits.
+struct ReorderLayout {
+  size_t dec, plain, whist, key, bcount, order, sbits, total;
+};
+static ReorderLayout reorder_layout(const HostHeader& h) {
+  ReorderLayout L;
+  DecompressWs w;
+  Carve c;
+  L.dec = c.take(carve_decompress(h, nullptr, &w));
+  L.plain = c.take((size_t)export_bytes(h));
+  L.whist = c.take(3 * 64 * 4);
+  L.key = c.take((size_t)h.n_leaves);
+  L.bcount = c.take(4 * 94 * (size_t)((h.n_leaves + kBlock - 1) / kBlock));
+  L.order = c.take(4 * (size_t)h.n_leaves);
+  L.sbits = c.take(8 * (size_t)h.n_leaves);
+  L.total = c.off;
+  return L;
+}
+
+size_t bbx_export_reordered_workspace_size(const void* h_header, size_t header_bytes) {
+  HostHeader h;
+  if (parse_header((const uint8_t*)h_header, header_bytes, &h) != BBX_OK || h.ref_mode != 1 ||
+      h.version != 1)
+    return 0;
+  return reorder_layout(h).total;
+}
+
+bbx_status bbx_export_sequences_reordered(const void* d_stream, size_t stream_size,
+                                          const void* h_header, void* d_out, size_t out_cap,
+                                          uint32_t* h_axis_order, void* d_ws, size_t ws_size,
+                                          hipStream_t stream) {
+  if (!d_stream || ((uintptr_t)d_stream & 7)) return fail(BBX_EINVAL, "d_stream must be 8-byte aligned");
+  if (!h_header) return fail(BBX_EINVAL, "h_header is NULL");
+  HostHeader h;
+  bbx_status st = parse_header((const uint8_t*)h_header, kHeaderBytes, &h);
+  if (st != BBX_OK) return st;
+  if (h.ref_mode != 1 || h.version != 1)
+    return fail(BBX_EINVAL, "the sequence layout needs a version-1 stream with references stored as coordinates (ref_mode 1)");
+  if (stream_size < stream_bytes_of(h)) return fail(BBX_ECORRUPT, "stream shorter than its sections");
+  const uint64_t need_out = export_bytes(h);
+  if (out_cap < need_out) return fail(BBX_ENOSPC, "output buffer too small: need " + std::to_string(need_out));
+  if (need_out > 0 && (!d_out || ((uintptr_t)d_out & 7))) return fail(BBX_EINVAL, "d_out is NULL or not 8-byte aligned");
+  if (!d_ws || ((uintptr_t)d_ws & 255)) return fail(BBX_EINVAL, "d_ws must be 256-byte aligned");
+  const ReorderLayout L = reorder_layout(h);
+  if (ws_size < L.total) return fail(BBX_ENOMEM, "workspace too small: need " + std::to_string(L.total));
+  uint8_t* base = (uint8_t*)d_ws;
+  DecompressWs w;
+  memset(&w, 0, sizeof(w));
+  carve_decompress(h, base + L.dec, &w);
+  const DecompressPlan p = plan_of(h, h_header, BBX_AOS);
+  uint8_t* plain = base + L.plain;
+  uint32_t* whist = (uint32_t*)(base + L.whist);
+  hipError_t e = launch_export(p, w, (const uint8_t*)d_stream, plain, nullptr, stream);
+  if (e == hipSuccess) e = hipMemsetAsync(whist, 0, 3 * 64 * 4, stream);
+  if (e == hipSuccess)
+    e = launch_reorder_hist(h.n_leaves, h.dims, w, whist, base + L.key, (uint32_t*)(base + L.bcount), stream);
+  uint32_t hw[3 * 64];
+  DevParams hp;
+  if (e == hipSuccess) e = hipMemcpyAsync(hw, whist, sizeof(hw), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(&hp, w.params, sizeof(hp), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return fail(BBX_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+  if (hp.status != BBX_OK) return fail((bbx_status)hp.status, "stream fails validation");
+  // axes in ascending entropy of their widths' distribution: with the same
+  // number of sequences behind every axis, descending sum of c log2 c over
+  // the width counts c; equal sums keep the lower axis first
+  double sclog[3] = {0, 0, 0};
+  for (uint32_t d = 0; d < h.dims; ++d)
+    for (int b = 0; b < 64; ++b)
+      if (hw[d * 64 + b]) sclog[d] += (double)hw[d * 64 + b] * log2((double)hw[d * 64 + b]);
+  uint32_t ord[3] = {0, 1, 2};
+  std::stable_sort(ord, ord + h.dims, [&](uint32_t a, uint32_t b) { return sclog[a] > sclog[b]; });
+  if (h_axis_order)
+    for (uint32_t d = 0; d < h.dims; ++d) h_axis_order[d] = ord[d];
+  e = launch_reorder_write(p, w, ord, plain, (uint8_t*)d_out, need_out / 8, base + L.key,
+                           (uint32_t*)(base + L.bcount), (uint32_t*)(base + L.order),
+                           (uint64_t*)(base + L.sbits), stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(&hp, w.params, sizeof(hp), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return fail(BBX_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+  if (hp.status != BBX_OK) return fail((bbx_status)hp.status, "stream fails validation");
+  return BBX_OK;
+}
+
 const char* bbx_status_str(bbx_status s) {
   switch (s) {
     case BBX_OK: return "OK";

@@ -588,6 +588,11 @@ hipError_t launch_dec_scan(uint64_t count, uint64_t* bits, uint64_t* part, DevPa
                            uint64_t expect_payload, hipStream_t s);
 hipError_t launch_reduce(const BatchPlan& bp, const Ws& w, hipStream_t s);
 hipError_t launch_split(const BatchPlan& bp, const SetDesc* descs, const Ws& w, hipStream_t s);
+hipError_t launch_reorder_hist(uint64_t n_leaves, uint32_t dims, const DecompressWs& w,
+                               uint32_t* whist, uint8_t* key, uint32_t* bcount, hipStream_t s);
+hipError_t launch_reorder_write(const DecompressPlan& p, const DecompressWs& w, const uint32_t ord[3],
+                                const uint8_t* plain, uint8_t* out, uint64_t out_words, uint8_t* key,
+                                uint32_t* bcount, uint32_t* order, uint64_t* sbits, hipStream_t s);
 hipError_t launch_reduce_pack(const BatchPlan& bp, const Ws& w, hipStream_t s);
 hipError_t launch_decompress2(const DecompressPlan& p, const DecompressWs& w, const uint8_t* stream,
                               void* pos, hipStream_t s);
