@@ -100,6 +100,71 @@ def bench_copy(args):
                       "cpu_baseline": None}), flush=True)
 
 
+def bench_entropy(args):
+    """The entropy stage of Sec. 3 / 4.2 on a workload: the version-1 stream
+    with stored-coordinate references, its sequence layout, the layout after
+    the two reorderings, and Huffman coding (of the plain stream, the plain
+    layout and the reordered layout): sizes, compression ratios and device
+    throughput (each call waits; times over K calls after W warm-ups)."""
+    import numpy as np  # noqa: F401
+    import torch
+
+    import paper_2404_02826_amd as bbx
+
+    kind, n, dtype, xi = WORKLOADS[args.workload]
+    log(f"generating {args.workload} ({n} particles)")
+    pts = make_points(kind, n, dtype)
+    x = torch.from_numpy(pts).cuda()
+    B_in = x.numel() * x.element_size()
+    s0 = bbx.compress(x, xi, "rel", args.leaf_size)
+    s1 = bbx.compress(x, xi, "rel", args.leaf_size, ref_mode=1)
+    plain = bbx.export_sequences(s1)
+    del x
+    torch.cuda.empty_cache()
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            r = fn()
+        torch.cuda.synchronize()
+        return r, (time.perf_counter() - t) * 1e3 / args.steps
+
+    (ro, order), t_ro = timed(lambda: bbx.export_sequences_reordered(s1))
+    h_ro, t_enc = timed(lambda: bbx.huffman_encode(ro))
+    dec, t_dec = timed(lambda: bbx.huffman_decode(h_ro))
+    assert torch.equal(dec, ro)
+    h_plain = bbx.huffman_encode(plain)
+    h_s0 = bbx.huffman_encode(s0)
+    L = ro.numel()
+    gbps = L / ((t_ro + t_enc) * 1e-3) / 1e9
+    print(json.dumps({
+        "metric": "entropy stage GB/s (sequence layout bytes through reordering + Huffman coding)",
+        "value": round(gbps, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(t_ro + t_enc, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "leaf_size": args.leaf_size,
+                   "input_bytes": B_in, "stream_bytes": s0.numel(),
+                   "stream_ref_coords_bytes": s1.numel(), "layout_bytes": L,
+                   "huffman_of_stream_bytes": h_s0.numel(),
+                   "huffman_of_layout_bytes": h_plain.numel(),
+                   "huffman_of_reordered_layout_bytes": h_ro.numel(),
+                   "cr_stream": round(B_in / s0.numel(), 4),
+                   "cr_layout": round(B_in / L, 4),
+                   "cr_huffman_stream": round(B_in / h_s0.numel(), 4),
+                   "cr_huffman_layout": round(B_in / h_plain.numel(), 4),
+                   "cr_huffman_reordered_layout": round(B_in / h_ro.numel(), 4),
+                   "reordering_gain": round(h_plain.numel() / h_ro.numel(), 4),
+                   "axis_order": order,
+                   "reorder_ms": round(t_ro, 4), "huffman_encode_ms": round(t_enc, 4),
+                   "huffman_decode_ms": round(t_dec, 4),
+                   "huffman_encode_gbps": round(L / (t_enc * 1e-3) / 1e9, 2),
+                   "huffman_decode_gbps": round(L / (t_dec * 1e-3) / 1e9, 2)},
+        "roofline": None, "cpu_baseline": None}), flush=True)
+
+
 def _cpu_model():
     """The host CPU's model name (from /proc/cpuinfo), for the baseline record."""
     try:
@@ -521,6 +586,9 @@ def main():
     ap.add_argument("--qps", type=float, default=400.0, help="served workload: arrival rate")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 23)
+    ap.add_argument("--entropy", action="store_true",
+                    help="the entropy stage (sequence layout, reorderings, Huffman coding) on the "
+                         "workload instead of the compress + decompress step")
     ap.add_argument("--graph", type=int, default=0, choices=(0, 1),
                     help="single set: replay the compress + decompress step as one recorded HIP graph")
     args = ap.parse_args()
@@ -536,6 +604,9 @@ def main():
         return
     if args.workload == "copy-1GiB":
         bench_copy(args)
+        return
+    if args.entropy:
+        bench_entropy(args)
         return
 
     import numpy as np

@@ -332,7 +332,7 @@ bbx_status bbx_export_sequences_reordered(const void* d_stream, size_t stream_si
  * first; on equal weights the node created earlier, leaves in symbol order
  * before merged nodes in creation order), rebuilt from the weights halved
  * (rounded up) while a code would exceed 12 bits; canonical codes in
- * (length, symbol) order.  The input is cut into chunks of 16,384 bytes that
+ * (length, symbol) order.  The input is cut into chunks of 4,096 bytes that
  * decode independently.  Stream: a 176-byte header ('BBXH', version 1, the
  * 12-bit limit, n, the chunk size, the chunk count, the payload bits, then
  * the 256 code lengths, a nibble each, low nibble for the even symbol), the

@@ -1735,7 +1735,7 @@ int bbxo_export_sequences_reordered(const uint8_t* s, uint64_t size, uint8_t* ou
  * i / 64, zero-padded to 8 bytes. */
 #define HUF_MAGIC 0x48584242u /* bytes 'B','B','X','H' */
 #define HUF_MAXLEN 12u
-#define HUF_CHUNK 16384u
+#define HUF_CHUNK 4096u
 #define HUF_HEADER 176u
 
 void bbxo_huffman_lengths(const uint64_t* counts, uint32_t* len) {

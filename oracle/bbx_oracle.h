@@ -138,7 +138,7 @@ uint64_t bbxo_r_index(const uint64_t* u, const uint32_t* m, uint32_t dims, const
 /* Huffman coding of bytes (the encoding phase of Sec. 3 applied to the
  * sequence layout of Sec. 4.2): code lengths of Huffman's construction
  * (ties: the earlier node; rebuilt from halved weights until no code is
- * longer than 12 bits), canonical codes, chunks of 16,384 input bytes with
+ * longer than 12 bits), canonical codes, chunks of 4,096 input bytes with
  * their first bit offsets stored.  The stream layout is in bbx_oracle.c. */
 void bbxo_huffman_lengths(const uint64_t* counts, uint32_t* len);
 uint64_t bbxo_huffman_bound(uint64_t n);

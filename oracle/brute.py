@@ -571,7 +571,7 @@ def export_sequences_reordered(stream: bytes):
 
 # ---------------------------------------------------------------- entropy coding
 
-HUF_MAXLEN, HUF_CHUNK = 12, 16384
+HUF_MAXLEN, HUF_CHUNK = 12, 4096
 
 
 def huffman_lengths(counts):

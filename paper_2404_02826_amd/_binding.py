@@ -694,7 +694,7 @@ def export_sequences_reordered(stream_t: torch.Tensor, stream=None):
 
 def huffman_encode(data: torch.Tensor, stream=None) -> torch.Tensor:
     """Huffman coding of a device uint8 tensor (the encoding phase of Sec. 3;
-    canonical codes of at most 12 bits, chunks of 16,384 bytes); returns the
+    canonical codes of at most 12 bits, chunks of 4,096 bytes); returns the
     stream as a uint8 device tensor."""
     lib = load()
     if data.dtype != torch.uint8 or not data.is_cuda or not data.is_contiguous():

@@ -40,9 +40,11 @@
 
 namespace bbx {
 
+typedef unsigned __int128 u128;
+
 constexpr uint32_t kHufMagic = 0x48584242u;  // bytes 'B','B','X','H'
 constexpr uint32_t kHufMaxLen = 12;
-constexpr uint32_t kHufChunk = 16384;
+constexpr uint32_t kHufChunk = 4096;
 constexpr uint32_t kHufHeader = 176;
 constexpr uint32_t kHufPer = kHufChunk / kBlock;  // bytes per thread of a chunk block
 
@@ -333,19 +335,25 @@ __global__ void __launch_bounds__(kBlock) k_huf_decode(const uint8_t* s, uint64_
     return;
   }
   const uint64_t i0 = c * kHufChunk, i1 = i0 + kHufChunk < n ? i0 + kHufChunk : n;
-  // bit window: `buf` holds the stream's bits [pos, pos + have); reloaded
-  // from the payload whenever fewer than a longest code remain
-  uint64_t buf = 0;
-  uint32_t have = 0;
+  // bit reader: `acc` holds the stream's bits [pos, pos + have); the next
+  // word is loaded one refill ahead, so its latency overlaps the decoding of
+  // the bits before it
+  uint64_t wd = pos >> 6;
+  const uint32_t sh0 = (uint32_t)(pos & 63);
+  u128 acc = wd < nwords ? (u128)(pay[wd] >> sh0) : (u128)0;
+  uint32_t have = 64 - sh0;
+  ++wd;
+  uint64_t next = wd < nwords ? pay[wd] : 0ull;
+  ++wd;
   uint64_t pk = 0;  // eight decoded bytes, stored together
   for (uint64_t i = i0; i < i1; ++i) {
-    if (have < kHufMaxLen) {
-      const uint64_t wd = pos >> 6;
-      const uint32_t sh = (uint32_t)(pos & 63);
-      buf = wd < nwords ? pay[wd] >> sh : 0ull;
-      if (sh && wd + 1 < nwords) buf |= pay[wd + 1] << (64 - sh);
-      have = 64;
+    if (have < 64) {
+      acc |= (u128)next << have;
+      have += 64;
+      next = wd < nwords ? pay[wd] : 0ull;
+      ++wd;
     }
+    const uint64_t buf = (uint64_t)acc;
     const uint16_t e = table[buf & ((1u << kHufMaxLen) - 1)];
     const uint32_t L = e >> 8;
     if (L == 0 || pos + L > end) {
@@ -361,7 +369,7 @@ __global__ void __launch_bounds__(kBlock) k_huf_decode(const uint8_t* s, uint64_
         for (uint64_t t = b0; t <= i; ++t) out[t] = (uint8_t)(pk >> (8 * (t - b0)));
       pk = 0;
     }
-    buf >>= L;
+    acc >>= L;
     have -= L;
     pos += L;
   }

@@ -30,6 +30,7 @@ typedef unsigned __int128 u128;
 
 constexpr uint32_t kRoKeys = 94;        // sums of widths 0 .. 3 * 31
 constexpr uint32_t kRoLocal = 256;      // members ranked from LDS (more: from the layout)
+constexpr uint32_t kRoStage = 64;       // words of a sequence staged in LDS (longer: written in place)
 
 __device__ inline uint64_t ro_read(const uint64_t* sec, uint64_t nwords, uint64_t at, uint32_t len) {
   if (len == 0) return 0;
@@ -56,7 +57,9 @@ __global__ void __launch_bounds__(kBlock) k_ro_hist(uint64_t n_leaves, uint32_t 
                                                     const DevParams* P) {
   if (P->status != BBX_OK) return;
   __shared__ uint32_t kc[kRoKeys];
+  __shared__ uint32_t wh[3 * 64];  // the block's width counts, added to the device's once
   for (uint32_t k = threadIdx.x; k < kRoKeys; k += kBlock) kc[k] = 0;
+  for (uint32_t k = threadIdx.x; k < 3 * 64; k += kBlock) wh[k] = 0;
   __syncthreads();
   const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i < n_leaves) {
@@ -64,13 +67,15 @@ __global__ void __launch_bounds__(kBlock) k_ro_hist(uint64_t n_leaves, uint32_t 
     uint32_t sm = 0;
     for (uint32_t d = 0; d < dims; ++d) {
       const uint32_t md = (m >> (8 * d)) & 0xffu;
-      atomicAdd(&whist[d * 64 + (md & 63)], 1u);
+      atomicAdd(&wh[d * 64 + (md & 63)], 1u);
       sm += md;
     }
     key[i] = (uint8_t)sm;
     atomicAdd(&kc[sm < kRoKeys ? sm : kRoKeys - 1], 1u);
   }
   __syncthreads();
+  for (uint32_t k = threadIdx.x; k < 3 * 64; k += kBlock)
+    if (wh[k]) atomicAdd(&whist[k], wh[k]);
   const uint64_t nblk = gridDim.x;
   for (uint32_t k = threadIdx.x; k < kRoKeys; k += kBlock) bcount[(uint64_t)k * nblk + blockIdx.x] = kc[k];
 }
@@ -152,6 +157,7 @@ __global__ void __launch_bounds__(kBlock) k_ro_write(uint64_t n_leaves, uint32_t
                                                      unsigned long long* out, const DevParams* P) {
   if (P->status != BBX_OK) return;
   __shared__ u128 rk[kBlock / 64][kRoLocal];
+  __shared__ unsigned long long stg[kBlock / 64][kRoStage];
   const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const uint32_t ord[3] = {o0, o1, o2};
   const uint64_t F = (uint64_t)dims * (M + mbits) + 32;  // a sequence's bits besides its codes
@@ -162,15 +168,26 @@ __global__ void __launch_bounds__(kBlock) k_ro_write(uint64_t n_leaves, uint32_t
     const uint32_t i = order[q];
     const LeafRec L = leaves[i];
     const uint64_t in = (uint64_t)i * F + poff[i], op = q * F + soff[q];
-    // centre and widths, 32 bits per lane-step
-    for (uint32_t b = lane * 32; b < hdr; b += 64 * 32) {
-      const uint32_t c = hdr - b < 32 ? hdr - b : 32;
-      ro_write(out, op + b, ro_read(plain, plain_words, in + b, c), c);
-    }
     const uint32_t m[3] = {L.m & 0xffu, (L.m >> 8) & 0xffu, (L.m >> 16) & 0xffu};
     const uint32_t sm = m[0] + m[1] + m[2];
     const uint32_t cnt = L.size - 1;
-    const uint64_t cin = in + hdr, cout = op + hdr;
+    // the sequence's words: staged in LDS when few (then only the two
+    // boundary words, shared with the neighbours, need atomics), else ORed
+    // into the output in place
+    const uint64_t w0 = op >> 6, nwd = ((op + F + (uint64_t)cnt * sm - 1) >> 6) - w0 + 1;
+    const bool staged = nwd <= kRoStage;
+    unsigned long long* dst = staged ? stg[wv] : out;
+    const uint64_t dbase = staged ? w0 * 64 : 0;  // bit offset of dst[0] in the output
+    if (staged) {
+      for (uint32_t k = lane; k < kRoStage; k += 64) stg[wv][k] = 0;
+      wave_sync();
+    }
+    // centre and widths, 32 bits per lane-step
+    for (uint32_t b = lane * 32; b < hdr; b += 64 * 32) {
+      const uint32_t c = hdr - b < 32 ? hdr - b : 32;
+      ro_write(dst, op + b - dbase, ro_read(plain, plain_words, in + b, c), c);
+    }
+    const uint64_t cin = in + hdr, cout = op + hdr - dbase;
     if (sm > 0 && cnt > 0) {
       const bool local = cnt <= kRoLocal;
       if (local)
@@ -187,14 +204,25 @@ __global__ void __launch_bounds__(kBlock) k_ro_write(uint64_t n_leaves, uint32_t
         // the member's codes, in axis order, at its rank
         uint64_t p = cin + (uint64_t)j * sm, o = cout + (uint64_t)rank * sm;
         for (uint32_t d = 0; d < dims; ++d) {
-          ro_write(out, o, ro_read(plain, plain_words, p, m[d]), m[d]);
+          ro_write(dst, o, ro_read(plain, plain_words, p, m[d]), m[d]);
           p += m[d];
           o += m[d];
         }
       }
       wave_sync();  // rk is rewritten by the wavefront's next sequence
     }
-    if (lane == 0) ro_write(out, cout + (uint64_t)cnt * sm, 0xffffffffull, 32);  // end mark
+    if (lane == 0) ro_write(dst, cout + (uint64_t)cnt * sm, 0xffffffffull, 32);  // end mark
+    if (staged) {
+      wave_sync();
+      for (uint32_t k = lane; k < nwd; k += 64) {
+        const unsigned long long v = stg[wv][k];
+        if (k == 0 || k + 1 == nwd)
+          atomicOr(&out[w0 + k], v);
+        else
+          out[w0 + k] = v;
+      }
+      wave_sync();  // stg is rewritten by the wavefront's next sequence
+    }
   }
 }
 
