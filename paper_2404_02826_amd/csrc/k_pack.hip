@@ -11,10 +11,12 @@
 //   k_pack_payload  leaf-aligned blocks: each block owns the payload words
 //                   that start inside its leaves, ORs every member code
 //                   q - q_ref + 2^(m-1) into an LDS copy of those words (LDS
-//                   atomics; 8 consecutive members per thread), completes its
-//                   last word from the next leaves, then writes every owned
-//                   word once with a coalesced plain store (no global
-//                   atomics, no zeroing of the output)
+//                   atomics; 8 consecutive members per thread, assembled in
+//                   registers and ORed a word at a time when they share a
+//                   leaf), completes its last word from the next leaves (a
+//                   member per lane), then writes every owned word once with
+//                   a coalesced plain store (no global atomics, no zeroing of
+//                   the output)
 //   k_header        the 128-byte header
 //   k_finish        reports size and status
 #include "bbx_internal.h"
@@ -400,6 +402,46 @@ __device__ void pack_payload_body(const SetDesc& S, const DevParams* P, uint64_t
       else
         z = mid - 1;
     }
+    {
+      // the usual shape: all V slots inside leaf a, member codes of at most
+      // 32 bits.  The run's codes occupy consecutive bits, so they are
+      // assembled in registers and ORed into LDS one 64-bit word at a time.
+      const LeafRec ra = s_rec[a];
+      const uint32_t sma = sum_m(ra.m);
+      if (gs >= ra.start && gs + V <= (uint64_t)ra.start + ra.size && sma > 0 && sma <= 32) {
+        const uint32_t j0 = (uint32_t)(gs - ra.start);
+        uint32_t hm[3], sh3[3] = {0, 0, 0};
+#pragma unroll
+        for (uint32_t d = 0; d < 3; ++d) {
+          const uint32_t m = d < dims ? (ra.m >> (8 * d)) & 0xffu : 0u;
+          hm[d] = (uint32_t)((1ull << m) >> 1) - (d < dims ? ra.qref[d] : 0u);
+          if (d + 1 < 3) sh3[d + 1] = sh3[d] + m;
+        }
+        uint32_t at = (uint32_t)(s_off[a] - wlo * 64) + (j0 ? j0 - 1 : 0u) * sma;
+        uint32_t w = at >> 6, pos = at & 63;
+        uint64_t lo = 0, hi = 0;
+#pragma unroll
+        for (uint32_t k = 0; k < V; ++k) {
+          if (j0 + k == 0) continue;  // the reference carries no payload
+          uint64_t c = 0;
+#pragma unroll
+          for (uint32_t d = 0; d < 3; ++d)
+            if (d < dims) c |= (uint64_t)((uint32_t)kk[d].e[k] + hm[d]) << sh3[d];
+          lo |= c << pos;
+          hi |= pos ? c >> (64 - pos) : 0ull;
+          pos += sma;
+          if (pos >= 64) {
+            atomicOr(&s_w[w], (unsigned long long)lo);
+            ++w;
+            lo = hi;
+            hi = 0;
+            pos -= 64;
+          }
+        }
+        if (pos > 0) atomicOr(&s_w[w], (unsigned long long)lo);
+        continue;
+      }
+    }
 #pragma unroll
     for (uint32_t k = 0; k < V; ++k) {
       const uint64_t slot = gs + k;
@@ -440,23 +482,38 @@ __device__ void pack_payload_body(const SetDesc& S, const DevParams* P, uint64_t
     }
   }
   __syncthreads();
-  if (threadIdx.x == 0 && (bo1 & 63) != 0 && bo1 < pbits) {
+  if ((bo1 & 63) != 0 && bo1 < pbits && threadIdx.x < 64) {
     // bits [bo1, w_end * 64) of the last owned word come from the next leaves
-    const uint64_t b0 = (w_end - 1) * 64;
-    uint64_t word = s_w[w_end - 1 - wlo];
-    uint64_t i = Lend;
-    uint64_t at = bo1;
-    while (i < nl && at < w_end * 64) {
-      const LeafRec rec = leaves[i];
-      const uint32_t sm = sum_m(rec.m);
-      for (uint64_t jm = 0; sm > 0 && jm + 1 < rec.size && at < w_end * 64; ++jm) {
-        const u128 c = member_code(keys, kst, dims, rec, (uint64_t)rec.start + 1 + jm);
-        or_into(word, b0, c, at, sm);
-        at += sm;
+    // (bo1 < pbits: leaf Lend exists).  When leaf Lend alone holds them, the
+    // first wavefront adds one member per lane; otherwise one thread walks
+    // the following leaves.
+    const uint64_t b0 = (w_end - 1) * 64, need = w_end * 64 - bo1;
+    const LeafRec rn = leaves[Lend];
+    const uint32_t smn = sum_m(rn.m);
+    if (smn > 0 && (uint64_t)(rn.size - 1) * smn >= need) {
+      const uint32_t t = threadIdx.x;
+      const uint64_t at = bo1 + (uint64_t)t * smn;
+      if (t + 1 < rn.size && at < w_end * 64) {
+        uint64_t part = 0;
+        or_into(part, b0, member_code(keys, kst, dims, rn, (uint64_t)rn.start + 1 + t), at, smn);
+        atomicOr(&s_w[w_end - 1 - wlo], (unsigned long long)part);
       }
-      ++i;
+    } else if (threadIdx.x == 0) {
+      uint64_t word = s_w[w_end - 1 - wlo];
+      uint64_t i = Lend;
+      uint64_t at = bo1;
+      while (i < nl && at < w_end * 64) {
+        const LeafRec rec = leaves[i];
+        const uint32_t sm = sum_m(rec.m);
+        for (uint64_t jm = 0; sm > 0 && jm + 1 < rec.size && at < w_end * 64; ++jm) {
+          const u128 c = member_code(keys, kst, dims, rec, (uint64_t)rec.start + 1 + jm);
+          or_into(word, b0, c, at, sm);
+          at += sm;
+        }
+        ++i;
+      }
+      s_w[w_end - 1 - wlo] = word;
     }
-    s_w[w_end - 1 - wlo] = word;
   }
   __syncthreads();
   for (uint64_t w = w_first + threadIdx.x; w < w_end; w += kBlock) pay[w] = s_w[w - wlo];
