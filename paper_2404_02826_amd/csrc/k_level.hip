@@ -1242,19 +1242,24 @@ __device__ inline void fuse_bases(const uint32_t (&t)[K], uint32_t (&b)[K], uint
   __syncthreads();  // xs is reused by the next exchange
 }
 
-// Radix select over the node's codes held in registers: the member of rank
-// `rank` among the rows flagged in the lane's bit mask `m` (bit i = row i),
-// ordered by (code, member order); widest digit first, at most 8 bits per
-// pass, in the node's 256 bins.  Returns the code and how many members equal
-// to it precede it.
-template <int R, int W>
-__device__ void reg_select(const uint32_t (&q)[R], uint32_t m, uint32_t rank, uint32_t* bins,
-                           uint32_t* red, uint32_t* v_out, uint32_t* jeq_out) {
+// Radix select over the node's codes held in registers, for one or two
+// member groups at once: group g's member of rank rank[g] among the members
+// flagged in the lanes' bit masks m[g] (bit i: the lane's i-th member),
+// ordered by (code, member order).  Widest digit first, at most 8 bits per
+// pass, over the code range of all flagged members; group g counts into
+// bins [256 g, 256 g + 256).  Returns each group's code in v[g] and, in
+// rank[g], how many members equal to it precede it.  The bins are zero on
+// entry and on return (the scanning wavefront clears what it read).
+template <int R, int W, int NG, typename Q>
+__device__ void reg_select(const Q& q, const uint32_t (&m)[NG], uint32_t (&rank)[NG],
+                           uint32_t* bins, uint32_t* red, uint32_t (&v)[NG]) {
+  static_assert(NG == 1 || NG == 2, "one or two groups");
   const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const uint32_t all = NG == 1 ? m[0] : (m[0] | m[NG - 1]);
   uint32_t lo = 0xffffffffu, hi = 0;
 #pragma unroll
   for (int i = 0; i < R; ++i)
-    if ((m >> i) & 1u) lo = umin32(lo, q[i]), hi = umax32(hi, q[i]);
+    if ((all >> i) & 1u) lo = umin32(lo, q[i]), hi = umax32(hi, q[i]);
   uint32_t mn = wave_min_dpp(lo), mx = wave_max_dpp(hi);
   if (W > 1) {
     if (lane == 0) red[wv] = mn, red[W + wv] = mx;
@@ -1264,71 +1269,167 @@ __device__ void reg_select(const uint32_t (&q)[R], uint32_t m, uint32_t rank, ui
     for (int w = 1; w < W; ++w) mn = umin32(mn, red[w]), mx = umax32(mx, red[W + w]);
     __syncthreads();
   }
-  const uint32_t Gs = bitlen32(mx - mn);
-  uint32_t prefix = 0, used = 0;
+  const uint32_t Gs = mx > mn ? bitlen32(mx - mn) : 0u;
+  uint32_t prefix[NG];
+#pragma unroll
+  for (int g = 0; g < NG; ++g) prefix[g] = 0;
+  uint32_t used = 0;
   while (used < Gs) {
     const uint32_t w = Gs - used < 8 ? Gs - used : 8;
     const uint32_t hs = Gs - used;
     used += w;
     const uint32_t sh = Gs - used, mask = (1u << w) - 1;
-    if (W == 1) {
+    if (hs == Gs) {  // first pass: every flagged member is a candidate
 #pragma unroll
-      for (int k = 0; k < 4; ++k) bins[lane * 4 + k] = 0;
-    } else if (threadIdx.x < 256) {
-      bins[threadIdx.x] = 0;
-    }
-    fuse_sync<W>();
-#pragma unroll
-    for (int i = 0; i < R; ++i) {
-      const uint32_t k = q[i] - mn;
-      if (((m >> i) & 1u) && (k >> hs) == prefix) atomicAdd(&bins[(k >> sh) & mask], 1u);
-    }
-    fuse_sync<W>();
-    if (W == 1 || wv == 0) {  // the node's (first) wavefront finds the bin holding the rank
-      uint32_t c[4], mine = 0;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) c[k] = bins[lane * 4 + k], mine += c[k];
-      uint32_t cum = wave_incl(mine) - mine;
-      uint32_t fb = 0, fr = 0;
-      bool found = false;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        if (cum <= rank && rank < cum + c[k]) found = true, fb = lane * 4 + k, fr = rank - cum;
-        cum += c[k];
+      for (int i = 0; i < R; ++i) {
+        const uint32_t k = q[i] - mn;
+        const uint32_t g0 = NG == 2 && ((m[NG - 1] >> i) & 1u) ? 256u : 0u;
+        if ((all >> i) & 1u) atomicAdd(&bins[g0 + ((k >> sh) & mask)], 1u);
       }
-      const uint64_t fm = __ballot(found);
-      const int fl = fm ? __ffsll((unsigned long long)fm) - 1 : 0;
-      fb = (uint32_t)__builtin_amdgcn_readlane((int)fb, fl);
-      fr = (uint32_t)__builtin_amdgcn_readlane((int)fr, fl);
-      if (W == 1) {
-        prefix = (prefix << w) | fb;
-        rank = fr;
-      } else if (lane == 0) {
-        red[2 * W] = fb, red[2 * W + 1] = fr;
+    } else {
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        const uint32_t k = q[i] - mn;
+        const bool g1 = NG == 2 && ((m[NG - 1] >> i) & 1u);
+        const uint32_t pre = g1 ? prefix[NG - 1] : prefix[0];
+        if (((all >> i) & 1u) && (k >> hs) == pre)
+          atomicAdd(&bins[(g1 ? 256u : 0u) + ((k >> sh) & mask)], 1u);
+      }
+    }
+    fuse_sync<W>();
+    if (W == 1 || wv == 0) {  // the node's (first) wavefront finds the bin of each rank
+      uint32_t c[NG][4], mine = 0;
+#pragma unroll
+      for (int g = 0; g < NG; ++g)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          c[g][k] = bins[256 * g + lane * 4 + k];
+          mine += c[g][k] << (16 * g);  // a group's counts stay below 2^16
+        }
+#pragma unroll
+      for (int g = 0; g < NG; ++g)
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if (c[g][k]) bins[256 * g + lane * 4 + k] = 0;
+      const uint32_t cum = wave_incl(mine) - mine;
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        uint32_t cg = (cum >> (16 * g)) & 0xffffu, fb = 0, fr = 0;
+        bool found = false;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          if (cg <= rank[g] && rank[g] < cg + c[g][k]) found = true, fb = lane * 4 + k, fr = rank[g] - cg;
+          cg += c[g][k];
+        }
+        const uint64_t fm = __ballot(found);
+        const int fl = fm ? __ffsll((unsigned long long)fm) - 1 : 0;
+        fb = (uint32_t)__builtin_amdgcn_readlane((int)fb, fl);
+        fr = (uint32_t)__builtin_amdgcn_readlane((int)fr, fl);
+        if (W == 1) {
+          prefix[g] = (prefix[g] << w) | fb;
+          rank[g] = fr;
+        } else if (lane == 0) {
+          red[2 * W + 2 * g] = fb, red[2 * W + 2 * g + 1] = fr;
+        }
       }
     }
     if (W > 1) {
       __syncthreads();
-      prefix = (prefix << w) | red[2 * W];
-      rank = red[2 * W + 1];
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        prefix[g] = (prefix[g] << w) | red[2 * W + 2 * g];
+        rank[g] = red[2 * W + 2 * g + 1];
+      }
     }
-    fuse_sync<W>();  // the bins (and red) are rewritten by the next pass
+    fuse_sync<W>();  // bins cleared and red read before the next pass writes them
   }
-  *v_out = mn + prefix;
-  *jeq_out = rank;
+#pragma unroll
+  for (int g = 0; g < NG; ++g) v[g] = mn + prefix[g];
 }
 
-// Levels k and k + 1 of one node, in place: the node's codes (and source
-// indices) are loaded into registers, the node's median along axis d and
-// then each child's median along the next axis are selected there, and every
-// member is written once, to its grandchild's slot.  Equal to two stable
-// partitions: the children keep the node's member order, and the
-// grandchildren the children's.  All loads precede the first store, and no
-// other wavefront or block touches the node.
+// exclusive prefix over the wavefront; the wavefront total in *tot
+__device__ inline uint32_t wave_excl(uint32_t x, uint32_t* tot) {
+  const uint32_t incl = wave_incl(x);
+  *tot = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+  return incl - x;
+}
+
+// R consecutive elements [p0, p0 + R) of one array (those below s; 0
+// beyond) held by a lane, loaded with 16-byte loads when the array is
+// 16-byte aligned and the run is whole; 16-bit codes two to a register.
+template <typename T, int R>
+struct RegRun {
+  static constexpr int V = 16 / sizeof(T), PER = 4 / sizeof(T);
+  static_assert(R % V == 0, "whole vectors");
+  uint32_t w[R / PER];
+  __device__ __forceinline__ uint32_t operator[](int i) const {
+    return PER == 1 ? w[i] : ((i & 1) ? w[i >> 1] >> 16 : w[i >> 1] & 0xffffu);
+  }
+  __device__ __forceinline__ void load(const T* X, uint32_t p0, uint32_t s, bool vec) {
+    if (vec && p0 + R <= s) {
+#pragma unroll
+      for (int b = 0; b < R / V; ++b) {
+        const uint4 u = *(const uint4*)(X + p0 + b * V);
+        w[4 * b + 0] = u.x, w[4 * b + 1] = u.y, w[4 * b + 2] = u.z, w[4 * b + 3] = u.w;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < R / PER; ++k) {
+        uint32_t x = 0;
+#pragma unroll
+        for (int h = 0; h < PER; ++h) {
+          const uint32_t p = p0 + (uint32_t)(k * PER + h);
+          x |= (p < s ? (uint32_t)X[p] : 0u) << (16 * h);
+        }
+        w[k] = x;
+      }
+    }
+  }
+};
+
+// Stores E consecutive values [e0, e0 + E) (those below s) to X, with
+// 16-byte stores when X is 16-byte aligned and the run is whole; get(k)
+// gives the value of slot e0 + k.
+template <int E, typename T, typename F>
+__device__ inline void store_run(T* X, uint32_t e0, uint32_t s, bool vec, F&& get) {
+  constexpr int V = 16 / sizeof(T);
+  static_assert(E % V == 0, "whole vectors");
+  if (vec && e0 + E <= s) {
+#pragma unroll
+    for (int b = 0; b < E / V; ++b) {
+      union {
+        uint4 u;
+        T e[V];
+      } x;
+#pragma unroll
+      for (int k = 0; k < V; ++k) x.e[k] = (T)get((uint32_t)(b * V + k));
+      *(uint4*)(X + e0 + b * V) = x.u;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < E; ++k)
+      if (e0 + k < s) X[e0 + k] = (T)get((uint32_t)k);
+  }
+}
+
+// Levels k and k + 1 of one node, in place.  Each lane holds R consecutive
+// members (member order: wavefront, lane, row) with their codes (and source
+// indices) in registers.  The node's median along d is selected there, then
+// both children's medians along the next axis in one joint select.  Every
+// member's side, its side in its child and finally its slot come from
+// per-lane counts and one wavefront scan per phase (ties go left in member
+// order), and the node is permuted through LDS and written back with
+// coalesced stores.  Equal to two stable partitions: the children keep the
+// node's member order, and the grandchildren the children's.  Each array of
+// the node is read before the barrier that precedes the first store to it
+// (a value is consumed before the barrier, so its load has returned), and no
+// other wavefront or block touches the node.  `lds` holds the select bins,
+// then the staged node (8 bytes per member with 16-bit codes, else one
+// 32-bit array at a time).
 template <typename KT, bool TRACK, int W>
-__device__ void level_fused_body(uint32_t depth, const SetDesc& S, DevParams* P, uint64_t j,
-                                 uint8_t* keys, uint32_t* idx, uint32_t* bins, uint32_t* red,
-                                 uint32_t (*xs)[4]) {
+__device__ __forceinline__ void level_fused_body(uint32_t depth, const SetDesc& S, DevParams* P,
+                                                 uint64_t j, uint8_t* keys, uint32_t* idx,
+                                                 uint32_t* lds, uint32_t* red, uint32_t (*xs)[4]) {
   constexpr int R = kFuseRows;
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t wv = W == 1 ? 0u : (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -1346,97 +1447,166 @@ __device__ void level_fused_body(uint32_t depth, const SetDesc& S, DevParams* P,
   KT* X1 = (KT*)keys + st + (uint64_t)a1 * kst;
   KT* X2 = (KT*)keys + st + (uint64_t)a2 * kst;
   uint32_t* I = idx ? idx + st : nullptr;
-  const uint32_t p0 = wv * (uint32_t)kFuseNode + lane;  // the lane's member of row 0
-  uint32_t q0[R], q1[R], q2[R], ix[TRACK ? R : 1];
-  uint32_t act = 0;  // bit i: row i holds a member in this lane
-#pragma unroll
-  for (int i = 0; i < R; ++i) {
-    const uint32_t p = p0 + 64u * i;
-    const bool a = p < s;
-    act |= a ? (1u << i) : 0u;
-    q0[i] = a ? (uint32_t)X0[p] : 0u;
-    q1[i] = a ? (uint32_t)X1[p] : 0u;
-    q2[i] = a ? (uint32_t)X2[p] : 0u;
-    if (TRACK) ix[i] = (a && I) ? I[p] : 0u;
-  }
+  // the code arrays are 64-element aligned per axis, so one test covers all
+  const bool vk = (st % (16 / sizeof(KT))) == 0, vi = (st % 4) == 0;
+  const uint32_t p0 = wv * (uint32_t)kFuseNode + lane * R;  // the lane's first member
+  RegRun<KT, R> q0, q1;  // the split axis and the next one (the third axis, and
+                         // the source indices, are read when they are staged)
+  q0.load(X0, p0, s, vk);
+  q1.load(X1, p0, s, vk);
+  const uint32_t act = p0 >= s ? 0u : (p0 + R <= s ? (1u << R) - 1u : (1u << (s - p0)) - 1u);
+  for (uint32_t k = W == 1 ? lane : threadIdx.x; k < 512; k += 64u * W) lds[k] = 0;  // select bins
   // every load of the node has returned before any wavefront of the node
   // passes its first barrier (the stores come after it)
   __builtin_amdgcn_s_waitcnt(0);
-  // level k: the node's median along d, then each member's side (ties by
-  // member order: the lower wavefronts' equal members come first)
+  fuse_sync<W>();
+
+  // ---- level k: the node's median along d; each member's side (members
+  // equal to the median go left while fewer than jeq of them did)
   uint32_t v, jeq;
-  reg_select<R, W>(q0, act, s >> 1, bins, red, &v, &jeq);
-  uint32_t eqb = 0;  // bit i: row i's member equals the median
+  {
+    const uint32_t m1[1] = {act};
+    uint32_t rk[1] = {s >> 1}, vv[1];
+    reg_select<R, W, 1>(q0, m1, rk, lds, red, vv);
+    v = vv[0], jeq = rk[0];
+  }
+  uint32_t ne = 0;
 #pragma unroll
-  for (int i = 0; i < R; ++i) eqb |= q0[i] == v ? (1u << i) : 0u;
-  eqb &= act;
-  uint32_t t1[1] = {wave_sum(__popc(eqb))}, b1[1];
-  fuse_bases<W, 1>(t1, b1, xs);
-  uint32_t left = 0, erun = b1[0];
+  for (int i = 0; i < R; ++i) ne += (((act >> i) & 1u) && q0[i] == v) ? 1u : 0u;
+  uint32_t te[1], be[1];
+  uint32_t erun = wave_excl(ne, &te[0]);
+  fuse_bases<W, 1>(te, be, xs);
+  erun += be[0];
+  uint32_t left = 0;
 #pragma unroll
   for (int i = 0; i < R; ++i) {
-    const bool a = (act >> i) & 1u, eq = (eqb >> i) & 1u;
-    const uint64_t meq = __ballot(eq);
-    left |= (a && (q0[i] < v || (eq && erun + lanes_below(meq) < jeq))) ? (1u << i) : 0u;
-    erun += popc64(meq);
+    const bool a = (act >> i) & 1u, eq = a && q0[i] == v;
+    if ((a && q0[i] < v) || (eq && erun < jeq)) left |= 1u << i;
+    erun += eq ? 1u : 0u;
   }
   const uint32_t right = act & ~left;
-  // level k + 1: each child's median along the next axis
+
+  // ---- level k + 1: both children's medians along the next axis, then each
+  // member's side within its child (counts of the two children packed in
+  // the 16-bit halves of one word: they stay below 2^16)
   const uint32_t sL = s >> 1, sR = s - sL, hL = sL >> 1, hR = sR >> 1;
-  uint32_t vL, jL, vR, jR;
-  reg_select<R, W>(q1, left, hL, bins, red, &vL, &jL);
-  reg_select<R, W>(q1, right, hR, bins, red, &vR, &jR);
-  // each member's grandchild: first (lower) or second half of its child
-  uint32_t eqL = 0, ltL = 0, eqR = 0, ltR = 0;
-#pragma unroll
-  for (int i = 0; i < R; ++i) {
-    eqL |= q1[i] == vL ? (1u << i) : 0u;
-    ltL |= q1[i] < vL ? (1u << i) : 0u;
-    eqR |= q1[i] == vR ? (1u << i) : 0u;
-    ltR |= q1[i] < vR ? (1u << i) : 0u;
+  uint32_t vL, vR, jL, jR;
+  {
+    const uint32_t m2[2] = {left, right};
+    uint32_t rk[2] = {hL, hR}, vv[2];
+    reg_select<R, W, 2>(q1, m2, rk, lds, red, vv);
+    vL = vv[0], vR = vv[1], jL = rk[0], jR = rk[1];
   }
-  eqL &= left, ltL &= left, eqR &= right, ltR &= right;
-  uint32_t t2[2] = {wave_sum(__popc(eqL)), wave_sum(__popc(eqR))}, b2[2];
-  fuse_bases<W, 2>(t2, b2, xs);
-  uint32_t lo = 0;  // bit i: row i's member goes to its child's first half
-  uint32_t eL = b2[0], eR = b2[1];
+  uint32_t ne2 = 0;
 #pragma unroll
   for (int i = 0; i < R; ++i) {
-    const uint64_t bEL = __ballot((eqL >> i) & 1u), bER = __ballot((eqR >> i) & 1u);
-    const bool toL = ((ltL >> i) & 1u) || (((eqL >> i) & 1u) && eL + lanes_below(bEL) < jL);
-    const bool toR = ((ltR >> i) & 1u) || (((eqR >> i) & 1u) && eR + lanes_below(bER) < jR);
-    lo |= (toL || toR) ? (1u << i) : 0u;
-    eL += popc64(bEL);
-    eR += popc64(bER);
+    const bool l = (left >> i) & 1u;
+    if (((act >> i) & 1u) && q1[i] == (l ? vL : vR)) ne2 += l ? 1u : 0x10000u;
   }
-  // grandchildren: LL [0, hL), LR [hL, sL), RL [sL, sL + hR), RR [sL + hR, s)
-  const uint32_t mLL = left & lo, mLR = left & ~lo, mRL = right & lo, mRR = right & ~lo;
-  uint32_t t4[4] = {wave_sum(__popc(mLL)), wave_sum(__popc(mLR)), wave_sum(__popc(mRL)),
-                    wave_sum(__popc(mRR))}, b4[4];
-  fuse_bases<W, 4>(t4, b4, xs);
-  uint32_t cLL = b4[0], cLR = hL + b4[1], cRL = sL + b4[2], cRR = sL + hR + b4[3];
+  uint32_t t2, b2[2];
+  uint32_t run2 = wave_excl(ne2, &t2);
+  {
+    const uint32_t tt[2] = {t2 & 0xffffu, t2 >> 16};
+    fuse_bases<W, 2>(tt, b2, xs);
+  }
+  run2 += b2[0] | (b2[1] << 16);
+  uint32_t lo = 0;  // bit i: the member goes to its child's first half
 #pragma unroll
   for (int i = 0; i < R; ++i) {
-    const uint64_t bLL = __ballot((mLL >> i) & 1u), bLR = __ballot((mLR >> i) & 1u);
-    const uint64_t bRL = __ballot((mRL >> i) & 1u), bRR = __ballot((mRR >> i) & 1u);
-    const uint32_t dest = ((mLL >> i) & 1u)   ? cLL + lanes_below(bLL)
-                          : ((mLR >> i) & 1u) ? cLR + lanes_below(bLR)
-                          : ((mRL >> i) & 1u) ? cRL + lanes_below(bRL)
-                                              : cRR + lanes_below(bRR);
-    if ((act >> i) & 1u) {
-      if (dest < s) {
-        X0[dest] = (KT)q0[i];
-        X1[dest] = (KT)q1[i];
-        X2[dest] = (KT)q2[i];
-        if (TRACK && I) I[dest] = ix[i];
-      } else {
-        check_failed(P, kChkFusedPart);
-      }
+    const bool a = (act >> i) & 1u, l = (left >> i) & 1u;
+    const uint32_t vs = l ? vL : vR, js = l ? jL : jR;
+    const uint32_t run = l ? (run2 & 0xffffu) : (run2 >> 16);
+    const bool eq = a && q1[i] == vs;
+    if ((a && q1[i] < vs) || (eq && run < js)) lo |= 1u << i;
+    run2 += eq ? (l ? 1u : 0x10000u) : 0u;
+  }
+
+  // ---- slots: grandchildren LL [0, hL), LR [hL, sL), RL [sL, sL + hR),
+  // RR [sL + hR, s); counts of LL/LR and of RL/RR packed per word
+  uint32_t cA = 0, cB = 0;
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    if (!((act >> i) & 1u)) continue;
+    const uint32_t inc = ((lo >> i) & 1u) ? 1u : 0x10000u;
+    if ((left >> i) & 1u)
+      cA += inc;
+    else
+      cB += inc;
+  }
+  uint32_t tA, tB, b4[4];
+  uint32_t rA = wave_excl(cA, &tA), rB = wave_excl(cB, &tB);
+  {
+    const uint32_t tt[4] = {tA & 0xffffu, tA >> 16, tB & 0xffffu, tB >> 16};
+    fuse_bases<W, 4>(tt, b4, xs);
+  }
+  rA += b4[0] | (b4[1] << 16);
+  rB += b4[2] | (b4[3] << 16);
+  uint32_t dst[R];
+  bool bad = false;
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const bool a = (act >> i) & 1u, l = (left >> i) & 1u, f = (lo >> i) & 1u;
+    const uint32_t word = l ? rA : rB;
+    const uint32_t base = l ? (f ? 0u : hL) : (f ? sL : sL + hR);
+    dst[i] = base + (f ? (word & 0xffffu) : (word >> 16));
+    const uint32_t inc = a ? (f ? 1u : 0x10000u) : 0u;
+    rA += l ? inc : 0u;
+    rB += l ? 0u : inc;
+    bad |= a && dst[i] >= s;
+  }
+  if (bad) check_failed(P, kChkFusedPart);
+  // ---- the node permuted through LDS, then written back in slot order with
+  // 8 consecutive slots per thread and round
+  constexpr uint32_t T = 64u * W, E = 8;
+  const uint32_t tid = W == 1 ? lane : threadIdx.x;
+  if constexpr (sizeof(KT) == 2) {
+    RegRun<KT, R> q2;
+    q2.load(X2, p0, s, vk);  // no store to the node before the barrier below
+    uint64_t* stg = (uint64_t*)lds;
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+      if (((act >> i) & 1u) && dst[i] < s)
+        stg[dst[i]] = (uint64_t)q0[i] | ((uint64_t)q1[i] << 16) | ((uint64_t)q2[i] << 32);
+    fuse_sync<W>();
+    for (uint32_t e0 = tid * E; e0 < s; e0 += T * E) {
+      uint64_t e[E];
+#pragma unroll
+      for (uint32_t k = 0; k < E; ++k) e[k] = e0 + k < s ? stg[e0 + k] : 0ull;
+      store_run<E>(X0, e0, s, vk, [&](uint32_t k) { return (uint32_t)e[k] & 0xffffu; });
+      store_run<E>(X1, e0, s, vk, [&](uint32_t k) { return (uint32_t)(e[k] >> 16) & 0xffffu; });
+      if (dims > 2)
+        store_run<E>(X2, e0, s, vk, [&](uint32_t k) { return (uint32_t)(e[k] >> 32) & 0xffffu; });
     }
-    cLL += popc64(bLL);
-    cLR += popc64(bLR);
-    cRL += popc64(bRL);
-    cRR += popc64(bRR);
+  }
+  // 32-bit codes and source indices: one array at a time, each read from
+  // the node before any wavefront stores to it
+  uint32_t* stg32 = lds;
+  auto pass32 = [&](auto* X, const auto& val, bool vec) {
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+      if (((act >> i) & 1u) && dst[i] < s) stg32[dst[i]] = val[i];
+    fuse_sync<W>();
+    for (uint32_t e0 = tid * E; e0 < s; e0 += T * E)
+      store_run<E>(X, e0, s, vec, [&](uint32_t k) { return stg32[e0 + k]; });
+    fuse_sync<W>();  // the next array reuses the staging area
+  };
+  if constexpr (sizeof(KT) == 4) {
+    fuse_sync<W>();
+    pass32(X0, q0, vk);
+    pass32(X1, q1, vk);
+    if (dims > 2) {
+      RegRun<KT, R> q2;
+      q2.load(X2, p0, s, vk);
+      pass32(X2, q2, vk);
+    }
+  }
+  if constexpr (TRACK) {
+    if (I) {
+      fuse_sync<W>();
+      RegRun<uint32_t, R> ix;
+      ix.load(I, p0, s, vi);
+      pass32(I, ix, vi);
+    }
   }
 }
 
@@ -1449,8 +1619,9 @@ __global__ void __launch_bounds__(kBlock) k_level_fused(uint32_t depth, uint32_t
                                                         DevParams* params, uint8_t* keys0,
                                                         uint32_t* idx0) {
   static_assert(W == 1 || W == kBlock / 64, "a wavefront or a block per node");
-  __shared__ uint32_t bins[kBlock / 64][256];
-  __shared__ uint32_t red[2 * W + 2];
+  // per node (W = 1: per wavefront) the select bins, then the staged node
+  __shared__ uint64_t stage[(kBlock / 64) * kFuseNode];
+  __shared__ uint32_t red[2 * W + 4];
   __shared__ uint32_t xs[W][4];
   const uint32_t wv = threadIdx.x >> 6;
   const uint64_t gn = W == 1 ? (uint64_t)blockIdx.x * (kBlock / 64) + wv : blockIdx.x;
@@ -1462,7 +1633,7 @@ __global__ void __launch_bounds__(kBlock) k_level_fused(uint32_t depth, uint32_t
   if ((W == 1 ? S.fuse_depth : S.fuse_depth4) != depth) return;
   const uint64_t j = gn - pre[s];
   uint32_t* idx = S.track ? idx0 + S.idx_off : nullptr;
-  uint32_t* b = W == 1 ? bins[wv] : bins[0];
+  uint32_t* b = (uint32_t*)(stage + (W == 1 ? wv * kFuseNode : 0));
   if (P->key16)
     level_fused_body<uint16_t, TRACK, W>(depth, S, P, j, keys0 + S.key_off, idx, b, red, xs);
   else
