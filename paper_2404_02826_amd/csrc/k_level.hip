@@ -1256,10 +1256,8 @@ __device__ void reg_select(const Q& q, const uint32_t (&m)[NG], uint32_t (&rank)
   static_assert(NG == 1 || NG == 2, "one or two groups");
   const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const uint32_t all = NG == 1 ? m[0] : (m[0] | m[NG - 1]);
-  uint32_t lo = 0xffffffffu, hi = 0;
-#pragma unroll
-  for (int i = 0; i < R; ++i)
-    if ((all >> i) & 1u) lo = umin32(lo, q[i]), hi = umax32(hi, q[i]);
+  uint32_t lo, hi;
+  q.minmax(all, &lo, &hi);
   uint32_t mn = wave_min_dpp(lo), mx = wave_max_dpp(hi);
   if (W > 1) {
     if (lane == 0) red[wv] = mn, red[W + wv] = mx;
@@ -1364,6 +1362,29 @@ struct RegRun {
   uint32_t w[R / PER];
   __device__ __forceinline__ uint32_t operator[](int i) const {
     return PER == 1 ? w[i] : ((i & 1) ? w[i >> 1] >> 16 : w[i >> 1] & 0xffffu);
+  }
+  // smallest and largest of the elements flagged in m (bit i: element i);
+  // 16-bit codes of a lane whose every element is flagged go two at a time
+  __device__ __forceinline__ void minmax(uint32_t m, uint32_t* lo, uint32_t* hi) const {
+    uint32_t a = 0xffffffffu, b = 0;
+    if (PER == 2 && m == (1u << R) - 1u) {
+      typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+      u16x2 a2 = {0xffff, 0xffff}, b2 = {0, 0};
+#pragma unroll
+      for (int k = 0; k < R / PER; ++k) {
+        const u16x2 x = __builtin_bit_cast(u16x2, w[k]);
+        a2 = __builtin_elementwise_min(a2, x);
+        b2 = __builtin_elementwise_max(b2, x);
+      }
+      a = umin32(a2.x, a2.y);
+      b = umax32(b2.x, b2.y);
+    } else {
+#pragma unroll
+      for (int i = 0; i < R; ++i)
+        if ((m >> i) & 1u) a = umin32(a, (*this)[i]), b = umax32(b, (*this)[i]);
+    }
+    *lo = a;
+    *hi = b;
   }
   __device__ __forceinline__ void load(const T* X, uint32_t p0, uint32_t s, bool vec) {
     if (vec && p0 + R <= s) {
@@ -1510,48 +1531,44 @@ __device__ __forceinline__ void level_fused_body(uint32_t depth, const SetDesc& 
     fuse_bases<W, 2>(tt, b2, xs);
   }
   run2 += b2[0] | (b2[1] << 16);
-  uint32_t lo = 0;  // bit i: the member goes to its child's first half
+  // grandchild of each member: g = 0 LL [0, hL), 1 LR [hL, sL), 2 RL
+  // [sL, sL + hR), 3 RR [sL + hR, s), two bits per member in gm
+  uint32_t gm = 0;
 #pragma unroll
   for (int i = 0; i < R; ++i) {
     const bool a = (act >> i) & 1u, l = (left >> i) & 1u;
     const uint32_t vs = l ? vL : vR, js = l ? jL : jR;
     const uint32_t run = l ? (run2 & 0xffffu) : (run2 >> 16);
     const bool eq = a && q1[i] == vs;
-    if ((a && q1[i] < vs) || (eq && run < js)) lo |= 1u << i;
+    const bool f = (a && q1[i] < vs) || (eq && run < js);
+    gm |= ((l ? 0u : 2u) | (f ? 0u : 1u)) << (2 * i);
     run2 += eq ? (l ? 1u : 0x10000u) : 0u;
   }
 
-  // ---- slots: grandchildren LL [0, hL), LR [hL, sL), RL [sL, sL + hR),
-  // RR [sL + hR, s); counts of LL/LR and of RL/RR packed per word
-  uint32_t cA = 0, cB = 0;
+  // ---- slots: a lane's member counts per grandchild, 16 bits apiece in one
+  // 64-bit word (they stay below 2^16), one scan per 32-bit half; c holds
+  // each grandchild's next slot
+  uint64_t cnt = 0;
 #pragma unroll
-  for (int i = 0; i < R; ++i) {
-    if (!((act >> i) & 1u)) continue;
-    const uint32_t inc = ((lo >> i) & 1u) ? 1u : 0x10000u;
-    if ((left >> i) & 1u)
-      cA += inc;
-    else
-      cB += inc;
-  }
+  for (int i = 0; i < R; ++i)
+    if ((act >> i) & 1u) cnt += 1ull << (16 * ((gm >> (2 * i)) & 3u));
   uint32_t tA, tB, b4[4];
-  uint32_t rA = wave_excl(cA, &tA), rB = wave_excl(cB, &tB);
+  const uint32_t rA = wave_excl((uint32_t)cnt, &tA), rB = wave_excl((uint32_t)(cnt >> 32), &tB);
   {
     const uint32_t tt[4] = {tA & 0xffffu, tA >> 16, tB & 0xffffu, tB >> 16};
     fuse_bases<W, 4>(tt, b4, xs);
   }
-  rA += b4[0] | (b4[1] << 16);
-  rB += b4[2] | (b4[3] << 16);
+  uint64_t c = ((uint64_t)rB << 32 | rA) +
+               ((uint64_t)b4[0] | ((uint64_t)(hL + b4[1]) << 16) | ((uint64_t)(sL + b4[2]) << 32) |
+                ((uint64_t)(sL + hR + b4[3]) << 48));
   uint32_t dst[R];
   bool bad = false;
 #pragma unroll
   for (int i = 0; i < R; ++i) {
-    const bool a = (act >> i) & 1u, l = (left >> i) & 1u, f = (lo >> i) & 1u;
-    const uint32_t word = l ? rA : rB;
-    const uint32_t base = l ? (f ? 0u : hL) : (f ? sL : sL + hR);
-    dst[i] = base + (f ? (word & 0xffffu) : (word >> 16));
-    const uint32_t inc = a ? (f ? 1u : 0x10000u) : 0u;
-    rA += l ? inc : 0u;
-    rB += l ? 0u : inc;
+    const bool a = (act >> i) & 1u;
+    const uint32_t sh = 16 * ((gm >> (2 * i)) & 3u);
+    dst[i] = (uint32_t)(c >> sh) & 0xffffu;
+    c += a ? 1ull << sh : 0ull;
     bad |= a && dst[i] >= s;
   }
   if (bad) check_failed(P, kChkFusedPart);
