@@ -575,6 +575,8 @@ def main():
     ap.add_argument("--reduce", type=int, default=0, choices=(0, 1, 2),
                     help="bit box reduction after the bit boxes: 1 key sum of widths, 2 key sum of "
                          "box lengths (moderate sets: at most 65,536 leaves)")
+    ap.add_argument("--level-pairs", type=int, default=0, choices=(0, 1),
+                    help="1: two global partition levels per data movement (same stream)")
     ap.add_argument("--split-rule", type=int, default=0, choices=(0, 1, 2, 3),
                     help="partition split rule: 0 median with axes in turn (the library's), "
                          "1 widest axis, 2 ceil(n/r) proportional leaves, 3 midpoint cells "
@@ -632,7 +634,7 @@ def main():
     comp = bbx.Compressor(n, dims, x.dtype, leaf_size=args.leaf_size, tile=args.tile,
                           ref_rule=args.ref_rule, ref_mode=args.ref_mode,
                           scatter_stage=args.scatter_stage, reduce=args.reduce,
-                          split_rule=args.split_rule)
+                          split_rule=args.split_rule, level_pairs=args.level_pairs)
     s = comp(x, xi)
     S = s.numel()
     S_plain = S
@@ -772,7 +774,7 @@ def main():
     rt_achieved = algo_round_trip / (rt_ms * 1e-3) / 1e9
     traffic = measured_traffic(args.workload) if args.leaf_size == 32 and args.ref_mode == 0 \
         and args.ref_rule == 0 and args.tile == 0 and not args.reduce and not args.split_rule \
-        else None
+        and not args.level_pairs else None
     roofline = {"bound": "hbm", "achieved": round(rt_achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(rt_achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "alg_bytes_per_step": int(algo_round_trip),
@@ -849,6 +851,7 @@ def main():
         "config": {"workload": args.workload, "n": n, "dims": dims, "input": dtype, "eb_rel": xi,
                    "leaf_size": args.leaf_size, "ref_rule": args.ref_rule,
                    "ref_mode": args.ref_mode, "scatter_stage": args.scatter_stage,
+                   "level_pairs": args.level_pairs,
                    "graph": bool(args.graph),
                    "stream_bytes": S, "cr": round(B_in / S, 4),
                    "cr_other_ref_rule": round(B_in / S_alt, 4),

@@ -132,7 +132,13 @@ typedef enum { BBX_AOS = 0, BBX_SOA = 1 } bbx_layout;         /* [n][dims] or [d
  * version-2 stream (one sequence per leaf, or the reduction's sequences),
  * header byte 21 holding the rule and the leaf-count field the partition's
  * leaf count; they need ref_mode 0 and run a separate, untuned partition
- * (an ablation of the reading, several times slower than rule 0). */
+ * (an ablation of the reading, several times slower than rule 0).
+ * level_pairs says how the partition levels with global histograms move the
+ * codes: 0 = one pass per level; 1 = two levels per pass where both are
+ * such levels (the second level's medians are selected over side labels of
+ * the first, then one stable four-way partition moves every code to its
+ * grandchild: fewer bytes, but more passes over single axes and a heavier
+ * partition, slower on MI355X); it never changes the stream. */
 typedef struct {
   uint32_t leaf_size;     /* r >= 1 */
   uint32_t eb_mode;       /* bbx_eb_mode */
@@ -144,6 +150,7 @@ typedef struct {
   uint32_t level_blocks;  /* 0 (library's choice) or 1..4096 */
   uint32_t reduce;        /* bit box reduction: 0 none, 1 (key: sum of widths), 2 (key: sum of lengths) */
   uint32_t split_rule;    /* 0 (median, axes in turn), 1 (widest axis), 2 (ceil(n/r) leaves), 3 (midpoint cells) */
+  uint32_t level_pairs;   /* 0 (one global level per pass) or 1 (two per pass) */
 } bbx_params;
 
 /* Worst-case stream size in bytes for n particles of the given type, with

@@ -30,7 +30,7 @@ class _Params(C.Structure):
     _fields_ = [("leaf_size", C.c_uint32), ("eb_mode", C.c_uint32), ("layout", C.c_uint32),
                 ("tile_override", C.c_uint32), ("ref_rule", C.c_uint32), ("ref_mode", C.c_uint32),
                 ("scatter_stage", C.c_uint32), ("level_blocks", C.c_uint32),
-                ("reduce", C.c_uint32), ("split_rule", C.c_uint32)]
+                ("reduce", C.c_uint32), ("split_rule", C.c_uint32), ("level_pairs", C.c_uint32)]
 
 
 class _Set(C.Structure):
@@ -190,9 +190,9 @@ def _shape(pos: torch.Tensor, layout: str):
 
 def _params(leaf_size: int, eb_mode: str, layout: int, tile: int, ref_rule: int = 0,
             ref_mode: int = 0, scatter_stage: int = 0, level_blocks: int = 0,
-            reduce: int = 0, split_rule: int = 0) -> _Params:
+            reduce: int = 0, split_rule: int = 0, level_pairs: int = 0) -> _Params:
     return _Params(leaf_size, REL if eb_mode == "rel" else ABS, layout, tile, ref_rule, ref_mode,
-                   scatter_stage, level_blocks, reduce, split_rule)
+                   scatter_stage, level_blocks, reduce, split_rule, level_pairs)
 
 
 def compress_bound_params(n: int, dims: int, dtype, params: _Params) -> int:
@@ -210,9 +210,10 @@ def compress_bound(n: int, dims: int = 3, dtype=torch.float32, ref_mode: int = 0
 def compress_workspace_size(n: int, dims: int = 3, dtype=torch.float32, leaf_size: int = 32,
                             eb_mode: str = "rel", layout: str = "aos", tile: int = 0,
                             ref_rule: int = 0, ref_mode: int = 0, scatter_stage: int = 0,
-                            level_blocks: int = 0, reduce: int = 0, split_rule: int = 0) -> int:
+                            level_blocks: int = 0, reduce: int = 0, split_rule: int = 0,
+                            level_pairs: int = 0) -> int:
     p = _params(leaf_size, eb_mode, AOS if layout == "aos" else SOA, tile, ref_rule, ref_mode,
-                scatter_stage, level_blocks, reduce, split_rule)
+                scatter_stage, level_blocks, reduce, split_rule, level_pairs)
     code = F32 if dtype == torch.float32 else F64
     lib = load()
     v = int(lib.bbx_compress_workspace_size(n, dims, code, C.byref(p)))
@@ -235,15 +236,17 @@ class Compressor:
     def __init__(self, n: int, dims: int = 3, dtype=torch.float32, leaf_size: int = 32,
                  eb_mode: str = "rel", layout: str = "aos", tile: int = 0, want_perm: bool = False,
                  device="cuda", ref_rule: int = 0, ref_mode: int = 0, scatter_stage: int = 0,
-                 level_blocks: int = 0, reduce: int = 0, split_rule: int = 0):
+                 level_blocks: int = 0, reduce: int = 0, split_rule: int = 0,
+                 level_pairs: int = 0):
         self.n, self.dims, self.dtype = n, dims, dtype
         self.layout = layout
         self.params = _params(leaf_size, eb_mode, AOS if layout == "aos" else SOA, tile, ref_rule,
-                              ref_mode, scatter_stage, level_blocks, reduce, split_rule)
+                              ref_mode, scatter_stage, level_blocks, reduce, split_rule,
+                              level_pairs)
         lib = load()
         self.ws_size = compress_workspace_size(n, dims, dtype, leaf_size, eb_mode, layout, tile,
                                                ref_rule, ref_mode, scatter_stage, level_blocks,
-                                               reduce, split_rule)
+                                               reduce, split_rule, level_pairs)
         self.ws = torch.empty(self.ws_size, dtype=torch.uint8, device=device)
         self.cap = compress_bound_params(n, dims, dtype, self.params)
         self.out = torch.empty((self.cap + 7) // 8 * 8, dtype=torch.uint8, device=device)
@@ -358,7 +361,7 @@ class BatchCompressor:
             S.params = _params(spec.get("leaf_size", 32), spec.get("eb_mode", "rel"), lay, tile,
                                spec.get("ref_rule", 0), spec.get("ref_mode", 0), scatter_stage,
                                spec.get("level_blocks", 0), spec.get("reduce", 0),
-                               spec.get("split_rule", 0))
+                               spec.get("split_rule", 0), spec.get("level_pairs", 0))
             S.d_out = base + offs[i]
             S.out_cap = caps[i]
             S.d_size = self.d_size.data_ptr() + 8 * i
@@ -584,7 +587,8 @@ def plan_check(sets) -> None:
         S.params = _params(spec.get("leaf_size", 32), spec.get("eb_mode", "rel"), AOS,
                            spec.get("tile", 0), spec.get("ref_rule", 0), spec.get("ref_mode", 0),
                            spec.get("scatter_stage", 0), spec.get("level_blocks", 0),
-                           spec.get("reduce", 0), spec.get("split_rule", 0))
+                           spec.get("reduce", 0), spec.get("split_rule", 0),
+                           spec.get("level_pairs", 0))
         S.d_out, S.out_cap, S.d_size, S.d_status = None, 0, None, None
         S.d_perm = 8 if spec.get("want_perm") else None  # planned, never read
     _check(load().bbx_plan_check(arr, len(sets)))
@@ -597,7 +601,7 @@ def decompress_workspace_size(header: bytes) -> int:
 def compress(pos: torch.Tensor, eb: float, eb_mode: str = "rel", leaf_size: int = 32,
              layout: str = "aos", want_perm: bool = False, tile: int = 0, stream=None,
              ref_rule: int = 0, ref_mode: int = 0, scatter_stage: int = 0,
-             level_blocks: int = 0, reduce: int = 0, split_rule: int = 0):
+             level_blocks: int = 0, reduce: int = 0, split_rule: int = 0, level_pairs: int = 0):
     """One-shot compress of a device tensor; returns the stream as a uint8
     device tensor (and the int32 source index of every output slot).
     ref_rule: 0 = leaf reference nearest the AABB centre (the paper's rule),
@@ -610,10 +614,13 @@ def compress(pos: torch.Tensor, eb: float, eb_mode: str = "rel", leaf_size: int 
     widths, 2: key sum of box lengths), a version-2 stream.  split_rule: how
     the partition splits a node (0: median, axes in turn; 1: median along
     the widest axis; 2: ceil(n/r) proportional leaves; 3: midpoint cells);
-    1-3 give a version-2 stream."""
+    1-3 give a version-2 stream.  level_pairs: 0 = one data movement per
+    global partition level, 1 = two levels per movement; it never changes
+    the stream."""
     n, dims, _ = _shape(pos, layout)
     c = Compressor(n, dims, pos.dtype, leaf_size, eb_mode, layout, tile, want_perm, pos.device,
-                   ref_rule, ref_mode, scatter_stage, level_blocks, reduce, split_rule)
+                   ref_rule, ref_mode, scatter_stage, level_blocks, reduce, split_rule,
+                   level_pairs)
     s = c(pos.contiguous(), eb, stream).clone()
     if want_perm:
         return s, c.perm[:n].clone()

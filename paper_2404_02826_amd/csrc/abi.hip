@@ -169,6 +169,7 @@ static bbx_status check_compress_args(uint64_t n, uint32_t dims, bbx_dtype dtype
   if (prm->ref_mode > 1) return fail(BBX_EINVAL, "ref_mode must be 0 or 1");
   if (prm->scatter_stage > 2) return fail(BBX_EINVAL, "scatter_stage must be 0, 1 or 2");
   if (prm->level_blocks > kLevelBlocks) return fail(BBX_EINVAL, "level_blocks must be 0..4096");
+  if (prm->level_pairs > 1) return fail(BBX_EINVAL, "level_pairs must be 0 or 1");
   if (prm->reduce > 2) return fail(BBX_EINVAL, "reduce must be 0, 1 or 2");
   if (prm->reduce && prm->ref_mode) return fail(BBX_EUNSUPPORTED, "the bit box reduction stores references as codes (ref_mode 0)");
   if (dims != 2 && dims != 3) return fail(BBX_EUNSUPPORTED, "dims must be 2 or 3");
@@ -192,7 +193,7 @@ static bbx_status check_set(const SetIn& in) {
 
 // Byte offsets of the batch workspace regions.
 struct WsLayout {
-  size_t params, sets, pre, partials, keys[2], idx[2], hist, sel, rows, cb, leaves, bits, spart,
+  size_t params, sets, pre, partials, keys[2], idx[2], hist, sel, rows, cb, labels, leaves, bits, spart,
       stotal, pneed, defer, lossless, red_tq, red_taken, red_slot, red_perm, red_key, red_ctr, red_ref, red_hits,
       red_seq, split, total;
 };
@@ -215,6 +216,7 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
   bp->tile = in[0].prm.tile_override ? in[0].prm.tile_override : 256;
   descs->assign(nsets, SetDesc());
   uint64_t key_bytes = 0, idx_n = 0, hist_n = 0, sel_n = 0, rows_n = 0, leaves_n = 0, parts = 0;
+  uint64_t cb_n = 0, lab_n = 0;
   uint64_t split_bytes = 0;
   // block target of the global levels: kLevelBlocks for a set alone; in a
   // batch each set's share of 4 * kLevelBlocks by particle count
@@ -303,7 +305,13 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
         while ((n >> K) > D.r) ++K;
         D.gl = ((n + (1ull << K) - 1) >> K) <= D.r ? K : K + 1;
       }
-      D.final_buf = D.tile_mode ? (D.gl & 1) : ((D.gl & 1) ^ 1);
+      // paired global levels (k_pair.hip): depths 2p and 2p + 1 while both
+      // use global histograms and every node of the second still splits
+      if (I.prm.level_pairs == 1)
+        while (2 * D.npairs + 1 < D.gl && level_kind(n, 2 * D.npairs) == kLevelGlobal &&
+               level_kind(n, 2 * D.npairs + 1) == kLevelGlobal && (n >> (2 * D.npairs + 1)) > D.r)
+          ++D.npairs;
+      D.final_buf = D.tile_mode ? key_buf(D, D.gl) : (key_buf(D, D.gl) ^ 1);
       D.fuse_depth = fuse_depth_of(n, D.gl, D.tile_mode != 0, 2, kFuseNode);
       if (D.fuse_depth != kNoFuse)
         D.fuse_depth4 = fuse_depth_of(n, D.gl, D.tile_mode != 0, 4, 4 * kFuseNode);
@@ -327,7 +335,7 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
         else
           bp->red_global = 1;
       }
-      uint64_t max_nodes = 0, max_blocks = 0, bin_nodes = 0;
+      uint64_t max_nodes = 0, max_blocks = 0, bin_nodes = 0, max_lab = 0;
       for (uint32_t k = 0; k < D.gl; ++k) {
         const LevelShape sh = level_shape(n, k, D.level_blocks);
         const int kind = level_kind(n, k);
@@ -339,9 +347,14 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
           bp->lv_wave[k] = 1;
         else if (kind == 1)
           bp->lv_local[k] = 1;
-        else
-          bp->lv_global[k] = 1;
-        if (kind == kLevelGlobal && sh.chunks > 256) bp->sel_wide[k] = 1;
+        else if (pair_first(D, k))
+          bp->lv_global[k] = bp->lv_pair[k] = 1;
+        else if (!pair_second(D, k))
+          bp->lv_global[k] = bp->lv_single[k] = 1;
+        if (kind == kLevelGlobal && sh.chunks > 256) {
+          if (!pair_second(D, k)) bp->sel_wide[k] = 1;
+          if (pair_first(D, k)) bp->pair_wide[k] = 1;  // the second level's selects use these chunks
+        }
         if (kind == kLevelGlobal) {  // by default staged only when every set's chunks are large
           const uint32_t mode = in[0].prm.scatter_stage;
           if (!stage_seen[k]) bp->scat_stage[k] = mode != 2;
@@ -353,6 +366,7 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
         if (kind == kLevelGlobal) {  // only these use selections and rows
           max_nodes = std::max(max_nodes, sh.nodes);
           max_blocks = std::max(max_blocks, sh.nodes * sh.chunks);
+          max_lab = std::max(max_lab, sh.nodes * sh.chunks * (uint64_t)(sh.chunk_elems / 64));
         }
         if (kind != kLevelWave) bin_nodes = std::max(bin_nodes, sh.nodes);  // radix bins
       }
@@ -363,8 +377,11 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
       D.hist_off = hist_n;
       D.hist_half = bin_nodes * kHistBins;
       D.sel_off = sel_n;
+      D.sel_half = max_nodes;
       D.rows_off = rows_n * kRowStride;
-      D.cb_off = rows_n * 2;
+      D.cb_off = cb_n;
+      D.cb_half = 4 * max_blocks;  // a paired second level: two children per parent chunk
+      D.lab_off = lab_n;
       D.leaf_off = leaves_n;
       D.part_off = parts;
       D.kst = (n + 63) & ~63ull;
@@ -372,8 +389,10 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
       if (I.need_idx || D.track) idx_n += (n + 63) & ~63ull;
       if (D.reduce && !(I.need_idx || D.track)) idx_n += (n + 63) & ~63ull;
       hist_n += 2 * bin_nodes * kHistBins;
-      sel_n += max_nodes;
-      rows_n += max_blocks;
+      sel_n += 2 * max_nodes;
+      rows_n += 2 * max_blocks;
+      cb_n += 2 * D.cb_half;
+      lab_n += max_lab;
       leaves_n += D.n_leaves;
       parts += mm[s];
     }
@@ -425,7 +444,8 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
   lay->hist = c.take(4 * hist_n);
   lay->sel = c.take(sizeof(NodeSel) * sel_n);
   lay->rows = c.take(4 * kRowStride * rows_n);
-  lay->cb = c.take(8 * rows_n);
+  lay->cb = c.take(4 * cb_n);
+  lay->labels = c.take(8 * lab_n);
   lay->leaves = c.take(sizeof(LeafRec) * leaves_n);
   lay->bits = c.take(8 * leaves_n);
   lay->spart = c.take(8 * (scan_blocks(leaves_n) + 1));
@@ -461,6 +481,7 @@ static Ws carve_ws(const WsLayout& L, uint8_t* base) {
   w.sel = (NodeSel*)(base + L.sel);
   w.rows = (uint32_t*)(base + L.rows);
   w.chunk_base = (uint32_t*)(base + L.cb);
+  w.labels = (uint64_t*)(base + L.labels);
   w.leaves = (LeafRec*)(base + L.leaves);
   w.leaf_bits = (uint64_t*)(base + L.bits);
   w.scan_part = (uint64_t*)(base + L.spart);
@@ -551,7 +572,21 @@ static std::string check_plan(const SetIn* in, uint32_t nsets) {
       if (sh.nodes * sh.chunks > rows_cap) return where(s, k) + "chunk rows too few";
       if (bp.pre_entries == 0 || pre[bp.o_lv[k] + s + 1] - pre[bp.o_lv[k] + s] != sh.nodes * sh.chunks)
         return where(s, k) + "grid share differs from the level shape";
-      if (sh.chunks > 256 && !bp.sel_wide[k]) return where(s, k) + "wide select not launched";
+      if (sh.chunks > 256 && !pair_second(D, k) && !bp.sel_wide[k]) return where(s, k) + "wide select not launched";
+      if (pair_first(D, k)) {  // the pair's second level lives in this level's chunks
+        if (k + 1 >= D.gl || level_kind(n, k + 1) != kLevelGlobal) return where(s, k) + "pair without a second global level";
+        if ((n >> (k + 1)) <= D.r) return where(s, k) + "pair whose second level has leaves";
+        if (!bp.lv_pair[k]) return where(s, k) + "pair not launched";
+        if (sh.chunks > 256 && !bp.pair_wide[k]) return where(s, k) + "pair's wide select not launched";
+        if (2 * sh.nodes * sh.chunks > rows_cap) return where(s, k) + "pair rows too few";
+        if (4 * sh.nodes * sh.chunks > D.cb_half) return where(s, k) + "pair chunk bases too few";
+        const uint64_t next_lab = s + 1 < nsets && descs[s + 1].n ? descs[s + 1].lab_off
+                                                                  : (lay.leaves - lay.labels) / 8;
+        if (sh.nodes * sh.chunks * (uint64_t)(sh.chunk_elems / 64) > next_lab - D.lab_off)
+          return where(s, k) + "pair labels too few";
+      } else if (!pair_second(D, k) && !bp.lv_single[k]) {
+        return where(s, k) + "scatter not launched";
+      }
       if (bp.scat_stage[k] && in[0].prm.scatter_stage == 0 && sh.chunk_elems < kStageChunk)
         return where(s, k) + "staged scatter on short chunks";
       sel_need = std::max(sel_need, sh.nodes);

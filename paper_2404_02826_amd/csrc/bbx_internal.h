@@ -112,8 +112,13 @@ struct SetDesc {
   uint64_t hist_off;      // u32 offset into the histogram bins
   uint64_t hist_half;     // u32 entries of each of the set's two bin regions
   uint64_t sel_off;       // NodeSel offset
+  uint64_t sel_half;      // NodeSel entries of each of the set's two selection regions (by depth parity)
   uint64_t rows_off;      // u32 offset into the chunk rows
   uint64_t cb_off;        // u32 offset into the chunk bases
+  uint64_t cb_half;       // u32 entries of each of the set's two chunk-base regions (by depth parity)
+  uint64_t lab_off;       // u64 offset into the side labels of paired levels
+  uint32_t npairs;        // global levels 2p and 2p + 1 (p < npairs) run with one data movement
+  uint32_t pad_pairs;
   uint64_t leaf_off;      // first leaf of the set in the batch's leaf arrays
   uint64_t part_off;      // first block of the set's range partials
   TreeGeom geom;
@@ -130,6 +135,7 @@ struct Ws {
   NodeSel* sel;
   uint32_t* rows;
   uint32_t* chunk_base;
+  uint64_t* labels;     // side labels of a paired level's members, one bit each
   LeafRec* leaves;
   uint64_t* leaf_bits;
   uint64_t* scan_part;
@@ -153,6 +159,34 @@ struct Ws {
 // A set's stream holds one record per sequence (version 2): the bit box
 // reduction, or a split rule other than 0 (one sequence per leaf).
 __host__ __device__ inline bool seq_stream(const SetDesc& S) { return S.reduce != 0 || S.split != 0; }
+
+// Paired global levels: depths 2p and 2p + 1 (p < npairs) partition the
+// codes with one data movement (k_pair.hip), so the key buffer that holds a
+// level's codes is the depth minus the pairs before it, mod 2.
+__host__ __device__ inline bool pair_first(const SetDesc& S, uint32_t depth) {
+  return (depth & 1u) == 0 && depth / 2 < S.npairs;
+}
+__host__ __device__ inline bool pair_second(const SetDesc& S, uint32_t depth) {
+  return (depth & 1u) && depth / 2 < S.npairs;
+}
+__host__ __device__ inline uint32_t key_buf(const SetDesc& S, uint32_t depth) {
+  return (depth - (depth / 2 < S.npairs ? depth / 2 : S.npairs)) & 1u;
+}
+// the node selections and chunk bases of a global level: two regions by
+// depth parity (a paired level reads its first level's while it writes its
+// second's)
+__host__ __device__ inline NodeSel* sel_level(const SetDesc& S, uint32_t depth, NodeSel* sel0) {
+  return sel0 + S.sel_off + (depth & 1u) * S.sel_half;
+}
+__host__ __device__ inline const NodeSel* sel_level(const SetDesc& S, uint32_t depth, const NodeSel* sel0) {
+  return sel0 + S.sel_off + (depth & 1u) * S.sel_half;
+}
+__host__ __device__ inline uint32_t* cb_level(const SetDesc& S, uint32_t depth, uint32_t* cb0) {
+  return cb0 + S.cb_off + (depth & 1u) * S.cb_half;
+}
+__host__ __device__ inline const uint32_t* cb_level(const SetDesc& S, uint32_t depth, const uint32_t* cb0) {
+  return cb0 + S.cb_off + (depth & 1u) * S.cb_half;
+}
 
 // widths of a box packed m_x | m_y << 8 | m_z << 16
 __device__ inline uint32_t red_m(uint32_t mp, uint32_t d) { return (mp >> (8 * d)) & 0xffu; }
@@ -261,6 +295,8 @@ enum Check : uint32_t {
   kChkTileRange = 11,
   kChkReduce = 12,      // the reduction did not place every particle
   kChkSplit = 13,       // a split-rule partition overflowed its node lists or left particles out
+  kChkPairStage = 14,   // a paired level's member falls outside its group's staging
+  kChkPairStore = 15,   // a paired level's member falls outside its node
 };
 __device__ inline void check_failed(DevParams* P, uint32_t which) {
   atomicCAS(&P->diag, 0u, which);
@@ -534,6 +570,9 @@ struct BatchPlan {
   uint8_t lv_wave[kMaxDepth];    // some set handles level k one wavefront per node
   uint8_t lv_fused[kMaxDepth];   // some set handles levels k, k + 1 fused, a wavefront per node
   uint8_t lv_fused4[kMaxDepth];  // some set handles levels k, k + 1 fused, a block per node
+  uint8_t lv_single[kMaxDepth];  // some set partitions global level k alone (k_scatter)
+  uint8_t lv_pair[kMaxDepth];    // some set partitions global levels k, k + 1 together (k_pair.hip)
+  uint8_t pair_wide[kMaxDepth];  // some paired set's nodes have > 256 chunks at level k
   uint32_t reduce;               // some set runs the bit box reduction
   uint32_t red_lds_boxes;        // some reduce set keeps its boxes on chip (<= kRedLdsBoxes leaves)
   uint32_t red_global;           // some reduce set keeps them in the workspace
@@ -578,6 +617,7 @@ bbx_status set_error(bbx_status st, const char* msg);
 // launchers (one group per translation unit)
 hipError_t launch_range(const BatchPlan& bp, const Ws& w, hipStream_t s);
 hipError_t launch_levels(const BatchPlan& bp, const Ws& w, hipStream_t s);
+hipError_t launch_pair(const BatchPlan& bp, const Ws& w, uint32_t depth, hipStream_t s);
 hipError_t launch_leaves(const BatchPlan& bp, const Ws& w, hipStream_t s);
 hipError_t launch_pack(const BatchPlan& bp, const Ws& w, hipStream_t s);
 hipError_t launch_decompress(const DecompressPlan& p, const DecompressWs& w, const uint8_t* stream,

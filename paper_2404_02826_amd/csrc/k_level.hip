@@ -104,6 +104,21 @@ __device__ inline LevelCtx level_ctx(uint32_t nsets, const uint64_t* pre, const 
   return level_ctx(nsets, pre, sets, depth, blockIdx.x);
 }
 
+// The buffers a level of set S reads (a, ia) and writes (b, ib): the launch
+// passes buffer 0 then buffer 1, and paired levels before `depth` shift
+// which one holds the codes.
+__device__ inline void level_bufs(const SetDesc& S, uint32_t depth, uint8_t*& a, uint8_t*& b,
+                                  uint32_t*& ia, uint32_t*& ib) {
+  if (key_buf(S, depth)) {
+    uint8_t* t = a;
+    a = b;
+    b = t;
+    uint32_t* u = ia;
+    ia = ib;
+    ib = u;
+  }
+}
+
 // Calls f(code) for every code of axis[A, B) (absolute element indices) with
 // 16-byte loads, U of them in flight per thread.  The axis array is 16-byte
 // aligned and readable up to B rounded up to 16 bytes.
@@ -177,8 +192,8 @@ __device__ void hist_mid_body(uint32_t depth, uint32_t pass, const SetDesc& S, c
 __global__ void __launch_bounds__(kBlock) k_hist_mid(uint32_t depth, uint32_t pass, uint32_t nsets,
                                                      const uint64_t* pre, const SetDesc* sets,
                                                      const DevParams* params, uint8_t* keys0,
-                                                     const NodeSel* sel0, uint32_t* hist0,
-                                                     const uint32_t* pass_need) {
+                                                     uint8_t* keys1, const NodeSel* sel0,
+                                                     uint32_t* hist0, const uint32_t* pass_need) {
   if (!pass_need[depth * 4 + pass]) return;
   __shared__ uint32_t lh[kHistBins];
   const uint64_t total = pre[nsets];
@@ -187,20 +202,20 @@ __global__ void __launch_bounds__(kBlock) k_hist_mid(uint32_t depth, uint32_t pa
     const SetDesc& S = sets[c.s];
     const DevParams* P = params + c.s;
     if (P->status != BBX_OK) continue;
-    if (level_is_local(S.n, depth)) continue;
+    if (level_is_local(S.n, depth) || pair_second(S, depth)) continue;
     if (pass + 1 >= digit_plan(P->G[depth % S.dims]).npass) continue;
-    const uint8_t* keys = keys0 + S.key_off;
+    const uint8_t* keys = (key_buf(S, depth) ? keys1 : keys0) + S.key_off;
     if (P->key16)
-      hist_mid_body<uint16_t>(depth, pass, S, P, c, keys, sel0 + S.sel_off, hist0 + S.hist_off, lh);
+      hist_mid_body<uint16_t>(depth, pass, S, P, c, keys, sel_level(S, depth, sel0), hist0 + S.hist_off, lh);
     else
-      hist_mid_body<uint32_t>(depth, pass, S, P, c, keys, sel0 + S.sel_off, hist0 + S.hist_off, lh);
+      hist_mid_body<uint32_t>(depth, pass, S, P, c, keys, sel_level(S, depth, sel0), hist0 + S.hist_off, lh);
   }
 }
 
 // Per node: find the bin that holds the median's rank, then clear the bins.
 // One wavefront per node (4 bins per lane); the grid is capped and strides
 // over the level's nodes, so passes that a code does not need cost little.
-__global__ void __launch_bounds__(kBlock) k_select_mid(uint32_t depth, uint32_t pass,
+__global__ void __launch_bounds__(kBlock) k_select_mid(uint32_t depth, uint32_t pass, uint32_t virt,
                                                        uint32_t nsets, const uint64_t* pre,
                                                        const SetDesc* sets,
                                                        const DevParams* params, NodeSel* sel0,
@@ -216,13 +231,15 @@ __global__ void __launch_bounds__(kBlock) k_select_mid(uint32_t depth, uint32_t 
     const DevParams* P = params + s;
     if (P->status != BBX_OK) continue;
     if (level_is_local(S.n, depth)) continue;
+    // virt: the second level of a pair, selected before its data moves
+    if (virt ? !(depth > 0 && pair_first(S, depth - 1)) : pair_second(S, depth)) continue;
     const DigitPlan pl = digit_plan(P->G[depth % S.dims]);
     if (pass + 1 >= pl.npass) continue;
     const uint64_t j = gn - pre[s];
     uint64_t st, sz;
     node_span(S.n, depth, j, &st, &sz);
     if (sz <= S.r) continue;
-    NodeSel* sel = sel0 + S.sel_off;
+    NodeSel* sel = sel_level(S, depth, sel0);
     uint32_t* hist = hist0 + S.hist_off + (j << 8);
     const uint32_t w = dp_width(pl, pass);
     const uint32_t nb = 1u << w;
@@ -298,20 +315,20 @@ __device__ void hist_last_body(uint32_t depth, const SetDesc& S, const DevParams
 __global__ void __launch_bounds__(kBlock) k_hist_last(uint32_t depth, uint32_t nsets,
                                                       const uint64_t* pre, const SetDesc* sets,
                                                       const DevParams* params, uint8_t* keys0,
-                                                      const NodeSel* sel0, uint32_t* hist0,
-                                                      uint32_t* rows0) {
+                                                      uint8_t* keys1, const NodeSel* sel0,
+                                                      uint32_t* hist0, uint32_t* rows0) {
   const LevelCtx c = level_ctx(nsets, pre, sets, depth);
   const SetDesc& S = sets[c.s];
   const DevParams* P = params + c.s;
   if (P->status != BBX_OK) return;
-  if (level_is_local(S.n, depth)) return;
+  if (level_is_local(S.n, depth) || pair_second(S, depth)) return;
   __shared__ uint32_t lh[kBlock];
-  const uint8_t* keys = keys0 + S.key_off;
+  const uint8_t* keys = (key_buf(S, depth) ? keys1 : keys0) + S.key_off;
   if (P->key16)
-    hist_last_body<uint16_t>(depth, S, P, c, keys, sel0 + S.sel_off, hist0 + S.hist_off,
+    hist_last_body<uint16_t>(depth, S, P, c, keys, sel_level(S, depth, sel0), hist0 + S.hist_off,
                              rows0 + S.rows_off, lh);
   else
-    hist_last_body<uint32_t>(depth, S, P, c, keys, sel0 + S.sel_off, hist0 + S.hist_off,
+    hist_last_body<uint32_t>(depth, S, P, c, keys, sel_level(S, depth, sel0), hist0 + S.hist_off,
                              rows0 + S.rows_off, lh);
 }
 
@@ -355,14 +372,18 @@ struct LastSel {
   uint64_t j, chunks;
   uint32_t rank, prefix, w;
 };
-__device__ inline bool last_sel_node(uint32_t depth, uint32_t nsets, const uint64_t* pre,
-                                     const SetDesc* sets, const DevParams* params,
-                                     const NodeSel* sel0, uint64_t gn, LastSel* o) {
+// virt: the second level of a pair, whose nodes still lie inside their
+// parents (the parent level's chunks, one row per child and chunk)
+__device__ inline bool last_sel_node(uint32_t depth, uint32_t virt, uint32_t nsets,
+                                     const uint64_t* pre, const SetDesc* sets,
+                                     const DevParams* params, const NodeSel* sel0, uint64_t gn,
+                                     LastSel* o) {
   const uint32_t s = find_set(pre, nsets, gn);
   const SetDesc& S = sets[s];
   const DevParams* P = params + s;
   if (P->status != BBX_OK) return false;
   if (level_is_local(S.n, depth)) return false;
+  if (virt ? !(depth > 0 && pair_first(S, depth - 1)) : pair_second(S, depth)) return false;
   const DigitPlan pl = digit_plan(P->G[depth % S.dims]);
   const uint32_t pass = pl.npass - 1;
   const uint64_t j = gn - pre[s];
@@ -372,10 +393,10 @@ __device__ inline bool last_sel_node(uint32_t depth, uint32_t nsets, const uint6
   o->S = &S;
   o->P = (DevParams*)P;
   o->j = j;
-  o->chunks = level_shape(S.n, depth, S.level_blocks).chunks;
+  o->chunks = level_shape(S.n, virt ? depth - 1 : depth, S.level_blocks).chunks;
   o->w = dp_width(pl, pass);
-  o->rank = pass == 0 ? (uint32_t)(sz >> 1) : sel0[S.sel_off + j].rank;
-  o->prefix = pass == 0 ? 0u : sel0[S.sel_off + j].prefix;
+  o->rank = pass == 0 ? (uint32_t)(sz >> 1) : sel_level(S, depth, sel0)[j].rank;
+  o->prefix = pass == 0 ? 0u : sel_level(S, depth, sel0)[j].prefix;
   return true;
 }
 
@@ -383,7 +404,7 @@ __device__ inline bool last_sel_node(uint32_t depth, uint32_t nsets, const uint6
 // each chunk's (lt, eq) base by an exclusive scan over the node's chunks.
 // One wavefront per node, capped grid striding over the nodes (levels whose
 // nodes have few chunks).
-__global__ void __launch_bounds__(kBlock) k_select_last(uint32_t depth, uint32_t nsets,
+__global__ void __launch_bounds__(kBlock) k_select_last(uint32_t depth, uint32_t virt, uint32_t nsets,
                                                         const uint64_t* pre, const SetDesc* sets,
                                                         const DevParams* params, NodeSel* sel0,
                                                         uint32_t* hist0, const uint32_t* rows0,
@@ -394,12 +415,12 @@ __global__ void __launch_bounds__(kBlock) k_select_last(uint32_t depth, uint32_t
   for (uint64_t gn = (uint64_t)blockIdx.x * wpb + (threadIdx.x >> 6); gn < total;
        gn += (uint64_t)gridDim.x * wpb) {
     LastSel L;
-    if (!last_sel_node(depth, nsets, pre, sets, params, sel0, gn, &L)) continue;
+    if (!last_sel_node(depth, virt, nsets, pre, sets, params, sel0, gn, &L)) continue;
     const SetDesc& S = *L.S;
     const uint64_t j = L.j, chunks = L.chunks;
     uint32_t* hist = hist0 + S.hist_off + (j << 8);
     const uint32_t* rows = rows0 + S.rows_off + j * chunks * kRowStride;
-    uint32_t* chunk_base = cb0 + S.cb_off + j * chunks * 2;
+    uint32_t* chunk_base = cb_level(S, depth, cb0) + j * chunks * 2;
     uint32_t b, jeq;
     if (!last_digit_of(hist, 1u << L.w, L.rank, &b, &jeq)) {
       if (lane == 0) check_failed(L.P, kChkLastDigit);
@@ -411,7 +432,7 @@ __global__ void __launch_bounds__(kBlock) k_select_last(uint32_t depth, uint32_t
       ns.rank = L.rank;
       ns.v = (L.prefix << L.w) | b;
       ns.jeq = jeq;
-      sel0[S.sel_off + j] = ns;
+      sel_level(S, depth, sel0)[j] = ns;
     }
     // per-chunk counts of members below v (lt) and equal to v (eq), then an
     // exclusive scan over the node's chunks in rounds of 64 (chunk = round *
@@ -448,7 +469,7 @@ __global__ void __launch_bounds__(kBlock) k_select_last(uint32_t depth, uint32_t
 // As k_select_last for levels whose nodes have many chunks (the top levels
 // of a large set): one block per node, the chunk scan spread over the block
 // (16 consecutive chunks per thread, all their loads in flight).
-__global__ void __launch_bounds__(kBlock) k_select_last_wide(uint32_t depth, uint32_t nsets,
+__global__ void __launch_bounds__(kBlock) k_select_last_wide(uint32_t depth, uint32_t virt, uint32_t nsets,
                                                              const uint64_t* pre,
                                                              const SetDesc* sets,
                                                              const DevParams* params,
@@ -463,7 +484,7 @@ __global__ void __launch_bounds__(kBlock) k_select_last_wide(uint32_t depth, uin
     LastSel L;
     // every thread reads the set's status; a status set meanwhile by another
     // block must not split the block at the barriers below
-    const bool mine = last_sel_node(depth, nsets, pre, sets, params, sel0, gn, &L);
+    const bool mine = last_sel_node(depth, virt, nsets, pre, sets, params, sel0, gn, &L);
     if (!__syncthreads_and(mine ? 1 : 0)) continue;
     const SetDesc& S = *L.S;
     const uint64_t j = L.j, chunks = L.chunks;
@@ -477,7 +498,7 @@ __global__ void __launch_bounds__(kBlock) k_select_last_wide(uint32_t depth, uin
           ns.rank = L.rank;
           ns.v = (L.prefix << L.w) | b;
           ns.jeq = jeq;
-          sel0[S.sel_off + j] = ns;
+          sel_level(S, depth, sel0)[j] = ns;
         } else {
           check_failed(L.P, kChkLastDigitWide);
         }
@@ -491,7 +512,7 @@ __global__ void __launch_bounds__(kBlock) k_select_last_wide(uint32_t depth, uin
     __syncthreads();  // bx is rewritten by the next node
     if (!ok) continue;
     const uint32_t* rows = rows0 + S.rows_off + j * chunks * kRowStride;
-    uint32_t* chunk_base = cb0 + S.cb_off + j * chunks * 2;
+    uint32_t* chunk_base = cb_level(S, depth, cb0) + j * chunks * 2;
     uint64_t run = 0;  // (lt << 32) | eq before this round
     for (uint64_t r0 = 0; r0 < chunks; r0 += (uint64_t)kPer * kBlock) {
       const uint64_t c0 = r0 + (uint64_t)threadIdx.x * kPer;
@@ -844,13 +865,14 @@ __global__ void __launch_bounds__(kBlock) k_scatter(uint32_t depth, uint32_t nse
   const SetDesc& S = sets[c.s];
   DevParams* P = params + c.s;
   if (P->status != BBX_OK) return;
-  if (level_is_local(S.n, depth)) return;
+  if (level_is_local(S.n, depth) || pair_first(S, depth) || pair_second(S, depth)) return;
   __shared__ uint32_t lhist[kLhWords];
   __shared__ uint32_t stg[STAGE ? (TRACK ? 4 : 3) * kGroup : 1];  // one staged group (codes, indices)
+  level_bufs(S, depth, src0, dst0, isrc0, idst0);
   const uint32_t* isrc = S.track ? isrc0 + S.idx_off : nullptr;
   uint32_t* idst = S.track ? idst0 + S.idx_off : nullptr;
-  const NodeSel ns = (sel0 + S.sel_off)[c.lb / c.sh.chunks];
-  const uint32_t* cb = cb0 + S.cb_off + c.lb * 2;
+  const NodeSel ns = sel_level(S, depth, sel0)[c.lb / c.sh.chunks];
+  const uint32_t* cb = cb_level(S, depth, cb0) + c.lb * 2;
   if (P->key16)
     scatter_body<uint16_t, TRACK, STAGE>(depth, S, P, c, ns.v, ns.jeq, cb[0], cb[1], src0 + S.key_off,
                                         dst0 + S.key_off, isrc, idst, hist0 + S.hist_off, lhist, stg);
@@ -951,6 +973,7 @@ __global__ void __launch_bounds__(kBlock) k_level_local(uint32_t depth, uint32_t
   if (level_kind(S.n, depth) != kLevelBlock) return;
   __shared__ uint32_t lhist[kLhWords];
   __shared__ uint32_t red[16];
+  level_bufs(S, depth, src0, dst0, isrc0, idst0);
   const uint32_t* isrc = S.track ? isrc0 + S.idx_off : nullptr;
   uint32_t* idst = S.track ? idst0 + S.idx_off : nullptr;
   uint64_t st, sz;
@@ -1190,6 +1213,7 @@ __global__ void __launch_bounds__(kBlock) k_level_wave(uint32_t depth, uint32_t 
   if (P->status != BBX_OK) return;
   if (level_kind(S.n, depth) != kLevelWave) return;
   const uint64_t j = gn - pre[s];
+  level_bufs(S, depth, src0, dst0, isrc0, idst0);
   const uint32_t* isrc = S.track ? isrc0 + S.idx_off : nullptr;
   uint32_t* idst = S.track ? idst0 + S.idx_off : nullptr;
   if (P->key16)
@@ -1634,7 +1658,8 @@ template <bool TRACK, int W>
 __global__ void __launch_bounds__(kBlock) k_level_fused(uint32_t depth, uint32_t nsets,
                                                         const uint64_t* pre, const SetDesc* sets,
                                                         DevParams* params, uint8_t* keys0,
-                                                        uint32_t* idx0) {
+                                                        uint8_t* keys1, uint32_t* idx0,
+                                                        uint32_t* idx1) {
   static_assert(W == 1 || W == kBlock / 64, "a wavefront or a block per node");
   // per node (W = 1: per wavefront) the select bins, then the staged node
   __shared__ uint64_t stage[(kBlock / 64) * kFuseNode];
@@ -1649,6 +1674,7 @@ __global__ void __launch_bounds__(kBlock) k_level_fused(uint32_t depth, uint32_t
   if (P->status != BBX_OK) return;
   if ((W == 1 ? S.fuse_depth : S.fuse_depth4) != depth) return;
   const uint64_t j = gn - pre[s];
+  level_bufs(S, depth, keys0, keys1, idx0, idx1);  // in place: the buffer holding the codes
   uint32_t* idx = S.track ? idx0 + S.idx_off : nullptr;
   uint32_t* b = (uint32_t*)(stage + (W == 1 ? wv * kFuseNode : 0));
   if (P->key16)
@@ -1657,61 +1683,598 @@ __global__ void __launch_bounds__(kBlock) k_level_fused(uint32_t depth, uint32_t
     level_fused_body<uint32_t, TRACK, W>(depth, S, P, j, keys0 + S.key_off, idx, b, red, xs);
 }
 
+// ---------------------------------------------------------------- paired levels
+//
+// Global levels k (even) and k + 1 of a set with npairs > k / 2 move the codes
+// once.  After level k's selects (as for any global level):
+//   k_label          per chunk of level k: each member's side (left / right
+//                    child) as one bit, in the chunk's order, and the
+//                    children's first-digit bins of the next axis
+//   (selects)        level k + 1's radix select over its nodes, which still
+//                    lie inside their parents: k_lab_hist for further digits
+//                    and the last one (rows per child and parent chunk),
+//                    k_select_mid / k_select_last with virt = 1
+//   k_scatter4       per chunk of level k: both sides of every member, then
+//                    one stable four-way partition to the grandchildren, and
+//                    the first-digit bins of level k + 2
+// Equal to the two stable partitions: the members of each child keep their
+// order, those of each grandchild their child's order.
+
+// The side labels of a chunk: one 64-bit word per row of 64 members, at
+// (chunk's block) * chunk_elems / 64 + (row's first member - chunk start) / 64.
+__device__ inline uint64_t* chunk_labels(const SetDesc& S, const LevelCtx& c, uint64_t* lab0) {
+  return lab0 + S.lab_off + c.lb * (uint64_t)(c.sh.chunk_elems / 64);
+}
+
+// Level k's sides of one chunk, written as labels, and the children's
+// first-digit bins of the next axis when that code has more than one digit.
+template <typename KT>
+__device__ void label_body(uint32_t depth, const SetDesc& S, DevParams* P, const LevelCtx& c,
+                           uint32_t v, uint32_t jeq, uint32_t lt_run, uint32_t eq_run,
+                           const uint8_t* src, uint64_t* lab, uint32_t* hist, uint32_t* lhist) {
+  const uint64_t n = S.n;
+  const uint32_t dims = S.dims, d = depth % dims, dn = (depth + 1) % dims;
+  const uint64_t j = c.lb / c.sh.chunks, ch = c.lb % c.sh.chunks;
+  uint64_t st, sz64;
+  node_span(n, depth, j, &st, &sz64);
+  const uint64_t beg64 = ch * (uint64_t)c.sh.chunk_elems;
+  if (beg64 >= sz64) return;
+  const uint32_t beg = (uint32_t)beg64;
+  const uint32_t end = (uint32_t)(beg64 + c.sh.chunk_elems < sz64 ? beg64 + c.sh.chunk_elems : sz64);
+  const DigitPlan pn = digit_plan(P->G[dn]);
+  const bool fuse = pn.npass >= 2;  // both children split again (pairing asks for it)
+  const uint32_t shn = pn.shift[0], maskn = (1u << pn.width[0]) - 1;
+  if (fuse)
+    for (uint32_t i = threadIdx.x; i < kLhWords; i += kBlock) lhist[i] = 0;
+  const KT* A0 = (const KT*)src + st + (uint64_t)d * S.kst;
+  const KT* A1 = (const KT*)src + st + (uint64_t)dn * S.kst;
+  __shared__ __align__(16) uint32_t cnt[2][kBlock / 64][2];
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t wv = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  int buf = 0;
+  for (uint32_t g = beg; g < end; g += kGroup, buf ^= 1) {
+    const uint32_t base = g + wv * (kGroup / (kBlock / 64));
+    uint32_t k0[kRows], k1[kRows];
+#pragma unroll
+    for (int i = 0; i < kRows; ++i) {
+      const uint32_t p = base + 64u * i + lane;
+      k0[i] = p < end ? (uint32_t)A0[p] : 0u;
+      k1[i] = p < end ? (uint32_t)A1[p] : 0u;
+    }
+    uint32_t rr[kRows], wl = 0, we = 0;
+#pragma unroll
+    for (int i = 0; i < kRows; ++i) {
+      const bool act = base + 64u * i + lane < end;
+      const uint64_t mlt = __ballot(act && k0[i] < v);
+      const uint64_t meq = __ballot(act && k0[i] == v);
+      rr[i] = lanes_below(meq);
+      we += popc64(meq);
+      wl += popc64(mlt);
+    }
+    if (lane == 0) cnt[buf][wv][0] = wl, cnt[buf][wv][1] = we;
+    __syncthreads();
+    const uint4 X = *(const uint4*)&cnt[buf][0][0];
+    const uint4 Y = *(const uint4*)&cnt[buf][2][0];
+    uint32_t be = eq_run + (wv > 0 ? X.y : 0u) + (wv > 1 ? X.w : 0u) + (wv > 2 ? Y.y : 0u);
+    lt_run += X.x + X.z + Y.x + Y.z;
+    eq_run += X.y + X.w + Y.y + Y.w;
+#pragma unroll
+    for (int i = 0; i < kRows; ++i) {
+      const bool act = base + 64u * i + lane < end;
+      const bool eq = k0[i] == v;
+      const bool left = k0[i] < v || (eq && be + rr[i] < jeq);
+      const uint64_t mr = __ballot(act && !left);
+      be += popc64(__ballot(act && eq));
+      if (lane == 0) lab[(base - beg) / 64 + i] = mr;
+      if (fuse && act) atomicAdd(&lhist[lh_slot(left, (k1[i] >> shn) & maskn)], 1u);
+    }
+  }
+  if (fuse) {
+    __syncthreads();
+    for (uint32_t child = 0; child < 2; ++child) {
+      uint32_t cnum = 0;
+#pragma unroll
+      for (uint32_t cp = 0; cp < kLhCopies; ++cp)
+        cnum += lhist[(child * kLhCopies + cp) * kLhStride + threadIdx.x];
+      if (cnum) atomicAdd(&hist_level(S, depth + 1, hist)[((2 * j + child) << 8) + threadIdx.x], cnum);
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_label(uint32_t depth, uint32_t nsets,
+                                                  const uint64_t* pre, const SetDesc* sets,
+                                                  DevParams* params, const NodeSel* sel0,
+                                                  const uint32_t* cb0, uint8_t* keys0,
+                                                  uint8_t* keys1, uint64_t* lab0,
+                                                  uint32_t* hist0) {
+  const LevelCtx c = level_ctx(nsets, pre, sets, depth);
+  const SetDesc& S = sets[c.s];
+  DevParams* P = params + c.s;
+  if (P->status != BBX_OK || !pair_first(S, depth)) return;
+  __shared__ uint32_t lhist[kLhWords];
+  const uint8_t* src = (key_buf(S, depth) ? keys1 : keys0) + S.key_off;
+  const NodeSel ns = sel_level(S, depth, sel0)[c.lb / c.sh.chunks];
+  const uint32_t* cb = cb_level(S, depth, cb0) + c.lb * 2;
+  uint64_t* lab = chunk_labels(S, c, lab0);
+  if (P->key16)
+    label_body<uint16_t>(depth, S, P, c, ns.v, ns.jeq, cb[0], cb[1], src, lab, hist0 + S.hist_off, lhist);
+  else
+    label_body<uint32_t>(depth, S, P, c, ns.v, ns.jeq, cb[0], cb[1], src, lab, hist0 + S.hist_off, lhist);
+}
+
+// Level k + 1 (dv) of a pair, digit pass `pass` over one chunk of a level-k
+// node: each member's child from its label, candidates matching the child's
+// digits so far counted into the child's bins.  A mid pass adds the counts
+// to the children's node bins; the last pass also writes each child's row
+// for the chunk (prefix counts per bin, candidates, members below the
+// digits so far), at rows (child * chunks + chunk).
+template <typename KT, bool LAST>
+__device__ void lab_hist_body(uint32_t dv, uint32_t pass, const SetDesc& S, const DevParams* P,
+                              const LevelCtx& c, const uint8_t* src, const uint64_t* lab,
+                              const NodeSel* sel, uint32_t* hist, uint32_t* rows0,
+                              uint32_t* lh) {
+  const uint64_t n = S.n;
+  const uint32_t dn = dv % S.dims;
+  const DigitPlan pl = digit_plan(P->G[dn]);
+  const uint64_t j = c.lb / c.sh.chunks, ch = c.lb % c.sh.chunks;
+  uint64_t st, sz64;
+  node_span(n, dv - 1, j, &st, &sz64);
+  const uint32_t w = dp_width(pl, pass), sh = dp_shift(pl, pass), hs = sh + w;
+  const uint32_t pre0 = pass == 0 ? 0u : sel[2 * j].prefix;
+  const uint32_t pre1 = pass == 0 ? 0u : sel[2 * j + 1].prefix;
+  const uint32_t nb = 1u << w, mask = nb - 1;
+  lh[threadIdx.x] = 0;
+  lh[kBlock + threadIdx.x] = 0;
+  __syncthreads();
+  const uint64_t beg64 = ch * (uint64_t)c.sh.chunk_elems;
+  const uint32_t beg = (uint32_t)(beg64 < sz64 ? beg64 : sz64);
+  const uint32_t end = (uint32_t)(beg64 + c.sh.chunk_elems < sz64 ? beg64 + c.sh.chunk_elems : sz64);
+  const KT* A1 = (const KT*)src + st + (uint64_t)dn * S.kst;
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t wv = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  uint32_t below0 = 0, below1 = 0;
+  for (uint32_t g = beg; g < end; g += kGroup) {
+    const uint32_t base = g + wv * (kGroup / (kBlock / 64));
+    uint32_t k1[kRows];
+    uint64_t lw[kRows];
+#pragma unroll
+    for (int i = 0; i < kRows; ++i) {
+      const uint32_t p = base + 64u * i + lane;
+      k1[i] = p < end ? (uint32_t)A1[p] : 0u;
+      lw[i] = base + 64u * i < end ? lab[(base - beg) / 64 + i] : 0ull;
+    }
+#pragma unroll
+    for (int i = 0; i < kRows; ++i) {
+      const uint32_t p = base + 64u * i + lane;
+      if (p >= end) continue;
+      const bool right = (lw[i] >> lane) & 1u;
+      const uint32_t hi = k1[i] >> hs, pre = right ? pre1 : pre0;
+      if (LAST) {
+        if (hi < pre) {
+          if (right)
+            ++below1;
+          else
+            ++below0;
+        }
+      }
+      if (hi == pre) atomicAdd(&lh[(right ? kBlock : 0u) + ((k1[i] >> sh) & mask)], 1u);
+    }
+  }
+  __syncthreads();
+  for (uint32_t child = 0; child < 2; ++child) {
+    const uint32_t cnt = threadIdx.x < nb ? lh[child * kBlock + threadIdx.x] : 0u;
+    const uint64_t jc = 2 * j + child;
+    if (LAST) {
+      uint64_t tot;
+      const uint64_t ex = block_exscan_u64(((uint64_t)(child ? below1 : below0) << 32) | cnt, &tot);
+      uint32_t* row = rows0 + (jc * c.sh.chunks + ch) * kRowStride;
+      row[threadIdx.x] = (uint32_t)ex;
+      if (threadIdx.x == 0) {
+        row[256] = (uint32_t)tot;
+        row[257] = (uint32_t)(tot >> 32);
+      }
+    }
+    if (threadIdx.x < nb && cnt) atomicAdd(&hist[(jc << 8) + threadIdx.x], cnt);
+  }
+}
+
+// LAST = 0: a further digit pass (skipped by the sets that need none); 1: the last pass
+template <bool LAST>
+__global__ void __launch_bounds__(kBlock) k_lab_hist(uint32_t dv, uint32_t pass, uint32_t nsets,
+                                                     const uint64_t* pre, const SetDesc* sets,
+                                                     const DevParams* params, uint8_t* keys0,
+                                                     uint8_t* keys1, const uint64_t* lab0,
+                                                     const NodeSel* sel0, uint32_t* hist0,
+                                                     uint32_t* rows0, const uint32_t* pass_need) {
+  if (!LAST && !pass_need[dv * 4 + pass]) return;
+  __shared__ uint32_t lh[2 * kBlock];
+  const uint64_t total = pre[nsets];
+  for (uint64_t vb = blockIdx.x; vb < total; vb += gridDim.x) {  // block-uniform
+    const LevelCtx c = level_ctx(nsets, pre, sets, dv - 1, vb);
+    const SetDesc& S = sets[c.s];
+    const DevParams* P = params + c.s;
+    if (P->status != BBX_OK || !pair_first(S, dv - 1)) continue;
+    const uint32_t np = digit_plan(P->G[dv % S.dims]).npass;
+    const uint32_t ps = LAST ? np - 1 : pass;
+    if (!LAST && pass + 1 >= np) continue;
+    const uint8_t* src = (key_buf(S, dv - 1) ? keys1 : keys0) + S.key_off;
+    const uint64_t* lab = chunk_labels(S, c, (uint64_t*)lab0);
+    if (P->key16)
+      lab_hist_body<uint16_t, LAST>(dv, ps, S, P, c, src, lab, sel_level(S, dv, sel0),
+                                    hist0 + S.hist_off, rows0 + S.rows_off, lh);
+    else
+      lab_hist_body<uint32_t, LAST>(dv, ps, S, P, c, src, lab, sel_level(S, dv, sel0),
+                                    hist0 + S.hist_off, rows0 + S.rows_off, lh);
+    __syncthreads();  // lh is reused by the next block's chunk
+  }
+}
+
+// The four-way partition of one chunk of a level-k node.  Per group of
+// kGroup members: level k's ranks (below / equal to v) and one exchange of
+// wavefront counts give each member's side; the ranks of the members equal
+// to their child's median, and a second exchange, give its side in the
+// child; four ballots and a third exchange rank it among the members of
+// its grandchild.  The group is staged in LDS as four runs (one per
+// grandchild, each contiguous in the output) and written with coalesced
+// stores.
+constexpr uint32_t kLh4Copies = 2;
+constexpr uint32_t kLh4Words = 4 * kLh4Copies * kLhStride;
+
+template <typename KT, bool TRACK>
+__device__ void scatter4_body(uint32_t depth, const SetDesc& S, DevParams* P, const LevelCtx& c,
+                              const NodeSel* sel, const NodeSel* sel2, const uint32_t* cb,
+                              const uint32_t* cb2, const uint8_t* src, uint8_t* dst,
+                              const uint32_t* isrc, uint32_t* idst, uint32_t* hist,
+                              uint32_t* lhist, uint32_t* stg) {
+  static_assert(kBlock == 256, "four wavefronts per block");
+  const uint64_t n = S.n, kst = S.kst;
+  const uint32_t dims = S.dims, r = S.r;
+  const uint32_t d = depth % dims, dn = (depth + 1) % dims, d2 = (depth + 2) % dims;
+  const uint64_t j = c.lb / c.sh.chunks, ch = c.lb % c.sh.chunks;
+  uint64_t st, sz64;
+  node_span(n, depth, j, &st, &sz64);
+  const uint64_t beg64 = ch * (uint64_t)c.sh.chunk_elems;
+  if (beg64 >= sz64) return;
+  const uint32_t sz = (uint32_t)sz64, beg = (uint32_t)beg64;
+  const uint32_t end = (uint32_t)(beg64 + c.sh.chunk_elems < sz64 ? beg64 + c.sh.chunk_elems : sz64);
+  // level k: median, ties that go left, counts before the chunk
+  const uint32_t v = sel[j].v, jeq = sel[j].jeq;
+  uint32_t lt_run = cb[0], eq_run = cb[1];
+  // level k + 1: per child its median, ties that go left, and its members
+  // below / equal to the median before the chunk (rows of child * chunks + chunk)
+  uint32_t vc[2], jc[2], ltc[2], eqc[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    vc[q] = sel2[2 * j + q].v;
+    jc[q] = sel2[2 * j + q].jeq;
+    const uint32_t* b = cb2 + ((2 * j + q) * c.sh.chunks + ch) * 2;
+    ltc[q] = b[0];
+    eqc[q] = b[1];
+  }
+  const uint32_t sL = sz >> 1, sR = sz - sL, hL = sL >> 1, hR = sR >> 1;
+  // each grandchild's next slot (node-relative): LL, LR, RL, RR
+  const uint32_t nL = lt_run + umin32(eq_run, jeq), nR = beg - nL;
+  const uint32_t a0 = ltc[0] + umin32(eqc[0], jc[0]), a1 = ltc[1] + umin32(eqc[1], jc[1]);
+  uint32_t gb[4] = {a0, hL + (nL - a0), sL + a1, sL + hR + (nR - a1)};
+  const uint32_t gsz4[4] = {hL, sL - hL, hR, sR - hR};
+  // level k + 2's first-digit bins per grandchild (when it runs a mid pass)
+  const DigitPlan p2 = digit_plan(P->G[d2]);
+  const bool fuse = depth + 2 < S.gl && p2.npass >= 2 && level_kind(n, depth + 2) != kLevelWave;
+  const uint32_t sh2 = p2.shift[0], mask2 = (1u << p2.width[0]) - 1;
+  bool cg[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) cg[q] = fuse && gsz4[q] > r;
+  if (fuse)
+    for (uint32_t i = threadIdx.x; i < kLh4Words; i += kBlock) lhist[i] = 0;
+  const KT* A0 = (const KT*)src + st + (uint64_t)d * kst;
+  const KT* A1 = (const KT*)src + st + (uint64_t)dn * kst;
+  const KT* A2 = (const KT*)src + st + (uint64_t)d2 * kst;
+  KT* B0 = (KT*)dst + st + (uint64_t)d * kst;
+  KT* B1 = (KT*)dst + st + (uint64_t)dn * kst;
+  KT* B2 = (KT*)dst + st + (uint64_t)d2 * kst;
+  const uint32_t* is = isrc ? isrc + st : nullptr;
+  uint32_t* id = idst ? idst + st : nullptr;
+  // one exchange array per phase: a phase's counts are read before the
+  // barrier of the next phase, so each is free again by the next group
+  __shared__ __align__(16) uint32_t x1[kBlock / 64][2];
+  __shared__ uint32_t x2[kBlock / 64];
+  __shared__ __align__(16) uint32_t x3[kBlock / 64][4];
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t wv = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  uint32_t k[3][kRows], ki[TRACK ? kRows : 1];
+  auto load = [&](uint32_t g, uint32_t (&kk)[3][kRows], uint32_t (&kki)[TRACK ? kRows : 1]) {
+    const uint32_t base = g + wv * (kGroup / (kBlock / 64));
+#pragma unroll
+    for (int i = 0; i < kRows; ++i) {
+      const uint32_t p = base + 64u * i + lane;
+      const bool act = p < end;
+      kk[0][i] = act ? (uint32_t)A0[p] : 0u;
+      kk[1][i] = act ? (uint32_t)A1[p] : 0u;
+      kk[2][i] = act ? (uint32_t)A2[p] : 0u;
+      if (TRACK) kki[i] = (act && is) ? is[p] : 0u;
+    }
+  };
+  load(beg, k, ki);
+  for (uint32_t g = beg; g < end; g += kGroup) {
+    const uint32_t base = g + wv * (kGroup / (kBlock / 64));
+    const uint32_t gsz = end - g < (uint32_t)kGroup ? end - g : (uint32_t)kGroup;
+    // ---- level k: ranks among the members equal to v
+    uint32_t re[kRows], wl = 0, we = 0;
+    uint64_t am[kRows];  // lanes holding a member, per row
+#pragma unroll
+    for (int i = 0; i < kRows; ++i) {
+      const bool act = base + 64u * i + lane < end;
+      am[i] = __ballot(act);
+      const uint64_t mlt = __ballot(act && k[0][i] < v);
+      const uint64_t meq = __ballot(act && k[0][i] == v);
+      re[i] = we + lanes_below(meq);
+      wl += popc64(mlt);
+      we += popc64(meq);
+    }
+    // the next group's codes are in flight while this one is partitioned
+    uint32_t kn[3][kRows], kin[TRACK ? kRows : 1];
+    if (g + kGroup < end) load(g + kGroup, kn, kin);
+    if (lane == 0) x1[wv][0] = wl, x1[wv][1] = we;
+    __syncthreads();
+    uint32_t be = eq_run;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) {
+      be += (uint32_t)w < wv ? x1[w][1] : 0u;
+      lt_run += x1[w][0];
+      eq_run += x1[w][1];
+    }
+    // ---- level k + 1: each member's child, ranks among the child's members
+    // equal to its median (both children packed in 16-bit halves)
+    uint64_t rm[kRows];  // lanes whose member goes right at level k, per row
+    uint32_t re2[kRows], w2 = 0;
+#pragma unroll
+    for (int i = 0; i < kRows; ++i) {
+      const bool act = base + 64u * i + lane < end;
+      const bool right = !(k[0][i] < v || (k[0][i] == v && be + re[i] < jeq));
+      rm[i] = __ballot(act && right);
+      const uint32_t vq = right ? vc[1] : vc[0];
+      const uint64_t mq = __ballot(act && k[1][i] == vq);
+      const uint64_t m0 = mq & ~rm[i], m1 = mq & rm[i];
+      re2[i] = w2 + (lanes_below(m0) | (lanes_below(m1) << 16));
+      w2 += popc64(m0) | (popc64(m1) << 16);
+    }
+    if (lane == 0) x2[wv] = w2;
+    __syncthreads();
+    uint32_t e0 = eqc[0], e1 = eqc[1];
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) {
+      const uint32_t x = x2[w];
+      if ((uint32_t)w < wv) e0 += x & 0xffffu, e1 += x >> 16;
+      eqc[0] += x & 0xffffu;
+      eqc[1] += x >> 16;
+    }
+    // ---- grandchild of each member (0 LL, 1 LR, 2 RL, 3 RR) and its rank
+    // among the group's members of that grandchild: one ballot of the
+    // second-level side, the four masks from it and the first-level side
+    uint32_t gq = 0;  // two bits per row
+    uint32_t r4[kRows];
+    uint32_t c4[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < kRows; ++i) {
+      const bool right = (rm[i] >> lane) & 1u;
+      const uint32_t vq = right ? vc[1] : vc[0], jq = right ? jc[1] : jc[0];
+      const uint32_t eq2 = right ? e1 + (re2[i] >> 16) : e0 + (re2[i] & 0xffffu);
+      const bool first = k[1][i] < vq || (k[1][i] == vq && eq2 < jq);
+      const uint64_t ms = __ballot(!first) & am[i];  // second halves
+      const uint64_t M[4] = {am[i] & ~rm[i] & ~ms, ~rm[i] & ms, rm[i] & ~ms, rm[i] & ms};
+      const uint32_t q = (right ? 2u : 0u) | (first ? 0u : 1u);
+      gq |= q << (2 * i);
+      const uint64_t mine = q == 0 ? M[0] : q == 1 ? M[1] : q == 2 ? M[2] : M[3];
+      r4[i] = (q == 0 ? c4[0] : q == 1 ? c4[1] : q == 2 ? c4[2] : c4[3]) + lanes_below(mine);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) c4[t] += popc64(M[t]);
+    }
+    if (lane == 0) {
+      x3[wv][0] = c4[0];
+      x3[wv][1] = c4[1];
+      x3[wv][2] = c4[2];
+      x3[wv][3] = c4[3];
+    }
+    __syncthreads();
+    // group totals per grandchild, this wavefront's base within them, and
+    // the staging offset of each grandchild's run
+    uint32_t tq[4] = {0, 0, 0, 0}, wb[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint32_t x = x3[w][q];
+        if ((uint32_t)w < wv) wb[q] += x;
+        tq[q] += x;
+      }
+    const uint32_t ro[4] = {0, tq[0], tq[0] + tq[1], tq[0] + tq[1] + tq[2]};
+#pragma unroll
+    for (int i = 0; i < kRows; ++i) {
+      const uint32_t p = base + 64u * i + lane;
+      if (p >= end) continue;
+      const uint32_t q = (gq >> (2 * i)) & 3u;
+      const uint32_t loc = (q == 0 ? ro[0] + wb[0] : q == 1 ? ro[1] + wb[1] : q == 2 ? ro[2] + wb[2]
+                                                                                   : ro[3] + wb[3]) + r4[i];
+      if (loc < (uint32_t)kGroup) {
+        stg[loc] = k[0][i];
+        stg[kGroup + loc] = k[1][i];
+        stg[2 * kGroup + loc] = k[2][i];
+        if (TRACK) stg[3 * kGroup + loc] = ki[i];
+        if (q == 0 ? cg[0] : q == 1 ? cg[1] : q == 2 ? cg[2] : cg[3])
+          atomicAdd(&lhist[(q * kLh4Copies + (threadIdx.x & (kLh4Copies - 1))) * kLhStride +
+                           ((k[2][i] >> sh2) & mask2)], 1u);
+      } else {
+        check_failed(P, kChkPairStage);
+      }
+    }
+    __syncthreads();
+    // drain: output t of the group belongs to run q when ro[q] <= t < ro[q + 1]
+    // (the next group stages only after its first barrier, when this drain
+    // is done)
+#pragma unroll
+    for (int i = 0; i < kRows; ++i) {
+      const uint32_t t = threadIdx.x + (uint32_t)kBlock * i;
+      if (t >= gsz) break;
+      const uint32_t q = t >= ro[3] ? 3u : t >= ro[2] ? 2u : t >= ro[1] ? 1u : 0u;
+      const uint32_t dest = (q == 0 ? gb[0] : q == 1 ? gb[1] : q == 2 ? gb[2] : gb[3]) + t -
+                            (q == 0 ? 0u : q == 1 ? ro[1] : q == 2 ? ro[2] : ro[3]);
+      if (dest < sz) {
+        B0[dest] = (KT)stg[t];
+        B1[dest] = (KT)stg[kGroup + t];
+        if (dims > 2) B2[dest] = (KT)stg[2 * kGroup + t];
+        if (TRACK && id) id[dest] = stg[3 * kGroup + t];
+      } else {
+        check_failed(P, kChkPairStore);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) gb[q] += tq[q];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int i = 0; i < kRows; ++i) k[a][i] = kn[a][i];
+    if (TRACK)
+#pragma unroll
+      for (int i = 0; i < kRows; ++i) ki[i] = kin[i];
+  }
+  __syncthreads();  // every wavefront's bins are counted
+  if (fuse) {
+    for (uint32_t q = 0; q < 4; ++q) {
+      uint32_t cnum = 0;
+#pragma unroll
+      for (uint32_t cp = 0; cp < kLh4Copies; ++cp)
+        cnum += lhist[(q * kLh4Copies + cp) * kLhStride + threadIdx.x];
+      if (cnum) atomicAdd(&hist_level(S, depth + 2, hist)[((4 * j + q) << 8) + threadIdx.x], cnum);
+    }
+  }
+}
+
+template <bool TRACK>
+__global__ void __launch_bounds__(kBlock) k_scatter4(uint32_t depth, uint32_t nsets,
+                                                     const uint64_t* pre, const SetDesc* sets,
+                                                     DevParams* params, const NodeSel* sel0,
+                                                     const uint32_t* cb0, uint8_t* src0,
+                                                     uint8_t* dst0, uint32_t* isrc0,
+                                                     uint32_t* idst0, uint32_t* hist0) {
+  const LevelCtx c = level_ctx(nsets, pre, sets, depth);
+  const SetDesc& S = sets[c.s];
+  DevParams* P = params + c.s;
+  if (P->status != BBX_OK || !pair_first(S, depth)) return;
+  __shared__ uint32_t lhist[kLh4Words];
+  __shared__ uint32_t stg[(TRACK ? 4 : 3) * kGroup];
+  level_bufs(S, depth, src0, dst0, isrc0, idst0);
+  const uint32_t* isrc = S.track ? isrc0 + S.idx_off : nullptr;
+  uint32_t* idst = S.track ? idst0 + S.idx_off : nullptr;
+  if (!TRACK && isrc) {  // the launch carries indices for every set that has them
+    if (threadIdx.x == 0) check_failed(P, kChkStageIdx);
+    return;
+  }
+  const NodeSel* sel = sel_level(S, depth, sel0);
+  const NodeSel* sel2 = sel_level(S, depth + 1, sel0);
+  const uint32_t* cb = cb_level(S, depth, cb0) + c.lb * 2;
+  const uint32_t* cb2 = cb_level(S, depth + 1, cb0);
+  if (P->key16)
+    scatter4_body<uint16_t, TRACK>(depth, S, P, c, sel, sel2, cb, cb2, src0 + S.key_off,
+                                   dst0 + S.key_off, isrc, idst, hist0 + S.hist_off, lhist, stg);
+  else
+    scatter4_body<uint32_t, TRACK>(depth, S, P, c, sel, sel2, cb, cb2, src0 + S.key_off,
+                                   dst0 + S.key_off, isrc, idst, hist0 + S.hist_off, lhist, stg);
+}
+
 // blocks of a select launch: one wavefront per node up to 8192 blocks, then striding
 static uint64_t sel_grid(uint64_t nodes) {
   const uint64_t b = (nodes + kBlock / 64 - 1) / (kBlock / 64);
   return b < 8192 ? (b ? b : 1) : 8192;
 }
 
+// Levels k and k + 1 of the paired sets, after level k's selects.
+hipError_t launch_pair(const BatchPlan& bp, const Ws& w, uint32_t k, hipStream_t s) {
+  const uint64_t* plv = w.pre + bp.o_lv[k];
+  const uint64_t* pnd2 = w.pre + bp.o_nd[k + 1];
+  uint8_t* K0 = w.keys[0];
+  uint8_t* K1 = w.keys[1];
+  BBX_LAUNCH("pair_label", k_label, bp.g_lv[k], kBlock, 0, s, k, bp.nsets, plv, w.sets, w.params,
+             w.sel, w.chunk_base, K0, K1, w.labels, w.hist);
+  for (uint32_t pass = 0; pass < 3; ++pass) {
+    if (pass > 0)
+      BBX_LAUNCH("pair_hist_mid", k_lab_hist<false>, bp.g_lv[k] < 2048 ? bp.g_lv[k] : 2048, kBlock,
+                 0, s, k + 1, pass, bp.nsets, plv, w.sets, w.params, K0, K1, w.labels, w.sel,
+                 w.hist, w.rows, w.pass_need);
+    BBX_LAUNCH("pair_select_mid", k_select_mid, sel_grid(bp.g_nd[k + 1]), kBlock, 0, s, k + 1, pass,
+               1u, bp.nsets, pnd2, w.sets, w.params, w.sel, w.hist, w.pass_need);
+  }
+  BBX_LAUNCH("pair_hist_last", k_lab_hist<true>, bp.g_lv[k], kBlock, 0, s, k + 1, 0u, bp.nsets, plv,
+             w.sets, w.params, K0, K1, w.labels, w.sel, w.hist, w.rows, w.pass_need);
+  if (bp.pair_wide[k])
+    BBX_LAUNCH("pair_select_last", k_select_last_wide,
+               bp.g_nd[k + 1] < 8192 ? (bp.g_nd[k + 1] ? bp.g_nd[k + 1] : 1) : 8192, kBlock, 0, s,
+               k + 1, 1u, bp.nsets, pnd2, w.sets, w.params, w.sel, w.hist, w.rows, w.chunk_base);
+  else
+    BBX_LAUNCH("pair_select_last", k_select_last, sel_grid(bp.g_nd[k + 1]), kBlock, 0, s, k + 1, 1u,
+               bp.nsets, pnd2, w.sets, w.params, w.sel, w.hist, w.rows, w.chunk_base);
+  BBX_LAUNCH("pair_scatter", bp.track ? k_scatter4<true> : k_scatter4<false>, bp.g_lv[k], kBlock, 0,
+             s, k, bp.nsets, plv, w.sets, w.params, w.sel, w.chunk_base, K0, K1, w.idx[0], w.idx[1],
+             w.hist);
+  return hipGetLastError();
+}
+
 hipError_t launch_levels(const BatchPlan& bp, const Ws& w, hipStream_t s) {
   if (bp.max_gl == 0) return hipGetLastError();
   BBX_LAUNCH("level_pass_flags", k_pass_flags, 1, kBlock, 0, s, bp.nsets, w.sets, w.params,
              w.pass_need);
+  // every level kernel gets buffer 0 and buffer 1 and picks, per set, the
+  // one that holds the codes (paired levels shift it)
+  uint8_t* K0 = w.keys[0];
+  uint8_t* K1 = w.keys[1];
+  uint32_t* I0 = w.idx[0];
+  uint32_t* I1 = w.idx[1];
   for (uint32_t k = 0; k < bp.max_gl; ++k) {
     const uint64_t* plv = w.pre + bp.o_lv[k];
     const uint64_t* pnd = w.pre + bp.o_nd[k];
-    const int cur = k & 1;
     if (bp.lv_local[k])
       BBX_LAUNCH("level_local", k_level_local, bp.g_lv[k], kBlock, 0, s, k, bp.nsets, plv, w.sets,
-                 w.params, w.keys[cur], w.keys[cur ^ 1], w.idx[cur], w.idx[cur ^ 1], w.hist);
+                 w.params, K0, K1, I0, I1, w.hist);
     if (bp.lv_wave[k])
       BBX_LAUNCH("level_wave", bp.track ? k_level_wave<true> : k_level_wave<false>,
                  (bp.g_nd[k] + kBlock / 64 - 1) / (kBlock / 64), kBlock, 0, s, k, bp.nsets, pnd,
-                 w.sets, w.params, w.keys[cur], w.keys[cur ^ 1], w.idx[cur], w.idx[cur ^ 1]);
-    // levels k and k + 1 in place: depth k + 2 keeps buffer `cur`
+                 w.sets, w.params, K0, K1, I0, I1);
+    // levels k and k + 1 in place
     if (bp.lv_fused[k])
       BBX_LAUNCH("level_fused", (bp.track ? k_level_fused<true, 1> : k_level_fused<false, 1>),
                  (bp.g_nd[k] + kBlock / 64 - 1) / (kBlock / 64), kBlock, 0, s, k, bp.nsets, pnd,
-                 w.sets, w.params, w.keys[cur], w.idx[cur]);
+                 w.sets, w.params, K0, K1, I0, I1);
     if (bp.lv_fused4[k])
       BBX_LAUNCH("level_fused4", (bp.track ? k_level_fused<true, 4> : k_level_fused<false, 4>),
-                 bp.g_nd[k], kBlock, 0, s, k, bp.nsets, pnd, w.sets, w.params, w.keys[cur],
-                 w.idx[cur]);
+                 bp.g_nd[k], kBlock, 0, s, k, bp.nsets, pnd, w.sets, w.params, K0, K1, I0, I1);
     if (!bp.lv_global[k]) continue;
     // mid passes: pass 0 was built by the quantize pass (depth 0) or by the
     // previous scatter
     for (uint32_t pass = 0; pass < 3; ++pass) {
       if (pass > 0)
         BBX_LAUNCH("level_hist_mid", k_hist_mid, bp.g_lv[k] < 2048 ? bp.g_lv[k] : 2048, kBlock, 0, s,
-                   k, pass, bp.nsets, plv, w.sets, w.params, w.keys[cur], w.sel, w.hist,
-                   w.pass_need);
-      BBX_LAUNCH("level_select_mid", k_select_mid, sel_grid(bp.g_nd[k]), kBlock, 0, s, k, pass,
+                   k, pass, bp.nsets, plv, w.sets, w.params, K0, K1, w.sel, w.hist, w.pass_need);
+      BBX_LAUNCH("level_select_mid", k_select_mid, sel_grid(bp.g_nd[k]), kBlock, 0, s, k, pass, 0u,
                  bp.nsets, pnd, w.sets, w.params, w.sel, w.hist, w.pass_need);
     }
     BBX_LAUNCH("level_hist_last", k_hist_last, bp.g_lv[k], kBlock, 0, s, k, bp.nsets, plv, w.sets,
-               w.params, w.keys[cur], w.sel, w.hist, w.rows);
+               w.params, K0, K1, w.sel, w.hist, w.rows);
     if (bp.sel_wide[k])  // some set's nodes have many chunks at this level
       BBX_LAUNCH("level_select_last", k_select_last_wide,
-                 bp.g_nd[k] < 8192 ? (bp.g_nd[k] ? bp.g_nd[k] : 1) : 8192, kBlock, 0, s, k,
+                 bp.g_nd[k] < 8192 ? (bp.g_nd[k] ? bp.g_nd[k] : 1) : 8192, kBlock, 0, s, k, 0u,
                  bp.nsets, pnd, w.sets, w.params, w.sel, w.hist, w.rows, w.chunk_base);
     else
-      BBX_LAUNCH("level_select_last", k_select_last, sel_grid(bp.g_nd[k]), kBlock, 0, s, k,
+      BBX_LAUNCH("level_select_last", k_select_last, sel_grid(bp.g_nd[k]), kBlock, 0, s, k, 0u,
                  bp.nsets, pnd, w.sets, w.params, w.sel, w.hist, w.rows, w.chunk_base);
-    BBX_LAUNCH("level_scatter",
-               (bp.track ? (bp.scat_stage[k] ? k_scatter<true, true> : k_scatter<true, false>)
-                         : (bp.scat_stage[k] ? k_scatter<false, true> : k_scatter<false, false>)),
-               bp.g_lv[k], kBlock, 0, s, k, bp.nsets, plv, w.sets, w.params, w.sel, w.chunk_base,
-               w.keys[cur], w.keys[cur ^ 1], w.idx[cur], w.idx[cur ^ 1], w.hist);
+    if (bp.lv_single[k])
+      BBX_LAUNCH("level_scatter",
+                 (bp.track ? (bp.scat_stage[k] ? k_scatter<true, true> : k_scatter<true, false>)
+                           : (bp.scat_stage[k] ? k_scatter<false, true> : k_scatter<false, false>)),
+                 bp.g_lv[k], kBlock, 0, s, k, bp.nsets, plv, w.sets, w.params, w.sel, w.chunk_base,
+                 K0, K1, I0, I1, w.hist);
+    if (bp.lv_pair[k]) {
+      const hipError_t e = launch_pair(bp, w, k, s);
+      if (e != hipSuccess) return e;
+    }
   }
   return hipGetLastError();
 }

@@ -528,7 +528,7 @@ __device__ void tile_node(uint32_t nsets, const uint64_t* pre, const SetDesc* se
   DevParams* P = params + s;
   if (P->status != BBX_OK) return;
   const uint64_t j = gtile - pre[s];
-  const uint32_t buf = S.gl & 1;
+  const uint32_t buf = key_buf(S, S.gl);  // the buffer holding the codes at the leaf stage
   uint8_t* keys = (buf ? keys1 : keys0) + S.key_off;
   const uint32_t* idx = S.track ? (buf ? idx1 : idx0) + S.idx_off : nullptr;
   LeafRec* leaves = leaves0 + S.leaf_off;
@@ -680,7 +680,7 @@ __global__ void __launch_bounds__(kBlock) k_bigleaf(uint32_t nsets, const uint64
   const SetDesc& S = sets[s];
   DevParams* P = params + s;
   if (P->status != BBX_OK) return;
-  const uint32_t buf = S.gl & 1;
+  const uint32_t buf = key_buf(S, S.gl);  // the buffer holding the codes at the leaf stage
   const uint8_t* src = (buf ? keys1 : keys0) + S.key_off;
   uint8_t* dst = (buf ? keys0 : keys1) + S.key_off;
   const uint32_t* idx = S.track ? (buf ? idx1 : idx0) + S.idx_off : nullptr;

@@ -102,6 +102,22 @@ def test_batch_scatter_stage_invariance(orc, bbx, stage):
         _check_set(orc, host, spec, res[i], bc.perms[i], f"set {i} {MIX[i]} stage {stage}")
 
 
+def test_batch_level_pairs(orc, bbx):
+    """Sets with paired global levels (two levels per data movement) batched
+    with sets without: each set's key buffers follow its own pairs, and every
+    stream equals the oracle's."""
+    cases = MIX + [("cosmology", 400000, 3, np.float32, 1e-4, "rel", 32, "aos", False),
+                   ("uniform", 300001, 2, np.float32, 1e-3, "rel", 16, "soa", True)]
+    hosts, specs = _specs(cases, seed0=90)
+    for i, sp in enumerate(specs):
+        sp["level_pairs"] = i % 2
+    _say(f"batch of {len(specs)} sets, every other one with paired levels")
+    bc = bbx.BatchCompressor(specs)
+    res = bc()
+    for i, (host, spec) in enumerate(zip(hosts, specs)):
+        _check_set(orc, host, spec, res[i], bc.perms[i], f"set {i} {cases[i]} pairs {i % 2}")
+
+
 def test_batch_equals_single_calls(bbx):
     hosts, specs = _specs(MIX[3:8], seed0=40)
     res = bbx.BatchCompressor(specs)()

@@ -56,11 +56,12 @@ def gen(kind, n, dims=3, dtype=np.float32, seed=1):
 
 
 def gpu_roundtrip(bbx, pts, eb, mode, r, layout="aos", tile=0, ref_rule=0, ref_mode=0,
-                  want_perm=True, scatter_stage=0, level_blocks=0):
+                  want_perm=True, scatter_stage=0, level_blocks=0, level_pairs=0):
     host = pts if layout == "aos" else np.ascontiguousarray(pts.T)
     x = torch.from_numpy(host).cuda()
     out = bbx.compress(x, eb, mode, r, layout, want_perm=want_perm, tile=tile, ref_rule=ref_rule,
-                       ref_mode=ref_mode, scatter_stage=scatter_stage, level_blocks=level_blocks)
+                       ref_mode=ref_mode, scatter_stage=scatter_stage, level_blocks=level_blocks,
+                       level_pairs=level_pairs)
     s, perm = out if want_perm else (out, None)
     dec = bbx.decompress(s, layout)
     torch.cuda.synchronize()
@@ -76,12 +77,12 @@ def first_diff(a: bytes, b: bytes):
 
 
 def check_parity(orc, bbx, pts, eb, mode, r, layout="aos", tile=0, ref_rule=0, ref_mode=0,
-                 want_perm=True, scatter_stage=0, level_blocks=0, ref=None):
+                 want_perm=True, scatter_stage=0, level_blocks=0, ref=None, level_pairs=0):
     host = pts if layout == "aos" else np.ascontiguousarray(pts.T)
     ref_s, ref_p = ref if ref is not None else orc.compress(
         host, eb, mode, r, layout=layout, want_perm=True, ref_rule=ref_rule, ref_mode=ref_mode)
     got_s, got_p, got_d = gpu_roundtrip(bbx, pts, eb, mode, r, layout, tile, ref_rule, ref_mode,
-                                        want_perm, scatter_stage, level_blocks)
+                                        want_perm, scatter_stage, level_blocks, level_pairs)
     if got_s != ref_s:
         h = props.parse_header(ref_s)
         mb = 8 * ((h["meta_bits"] + 63) // 64)
@@ -134,6 +135,35 @@ def test_parity(orc, bbx, case):
     _say("case", case)
     pts = gen(kind, n, dims, dt, seed=n % 97 + 1)
     check_parity(orc, bbx, pts, eb, mode, r)
+
+
+# paired global levels (two levels per data movement): the sets with at
+# least two levels that use global histograms, with and without indices,
+# 16- and 32-bit codes, 2-D and 3-D, few and many chunks per node, and an
+# odd count of such levels (the last one alone)
+PAIR_CASES = [
+    ("cosmology", 300007, 3, np.float32, 1e-4, "rel", 32, True, 0),
+    ("ties", 300007, 3, np.float32, 1e-3, "rel", 32, False, 0),
+    ("cosmology", 150001, 3, np.float32, 1e-7, "rel", 32, True, 0),   # u32 codes (mid passes)
+    ("poincare", 300007, 2, np.float32, 1e-3, "rel", 16, True, 0),
+    ("uniform", 100003, 3, np.float64, 1e-5, "abs", 16, True, 0),
+    ("fluid", 1 << 20, 3, np.float32, 1e-4, "rel", 32, False, 0),
+    ("cosmology", 1 << 20, 3, np.float32, 1e-4, "rel", 32, True, 7),    # few blocks per level
+    ("uniform", (1 << 19) + 333, 3, np.float32, 1e-3, "rel", 8, True, 0),
+    ("cosmology", 700001, 3, np.float32, 1e-4, "rel", 1000, False, 0),  # leaves above a tile
+]
+
+
+@pytest.mark.parametrize("case", PAIR_CASES,
+                         ids=lambda c: f"{c[0]}-n{c[1]}-d{c[2]}-{np.dtype(c[3]).name}-r{c[6]}-perm{int(c[7])}-lb{c[8]}")
+def test_level_pairs_parity(orc, bbx, case):
+    kind, n, dims, dt, eb, mode, r, perm, lb = case
+    _say("pairs", case)
+    pts = gen(kind, n, dims, dt, seed=n % 89 + 3)
+    ref = check_parity(orc, bbx, pts, eb, mode, r, want_perm=perm, level_blocks=lb, level_pairs=1)
+    # and the same stream as one data movement per level
+    got, _, _ = gpu_roundtrip(bbx, pts, eb, mode, r, want_perm=False, level_blocks=lb)
+    assert got == ref
 
 
 @pytest.mark.parametrize("layout", ["aos", "soa"])

@@ -32,6 +32,8 @@ def test_plan_single_sets(tile):
                 bbx.plan_check([dict(n=n, leaf_size=r, tile=tile, level_blocks=lb)])
             bbx.plan_check([dict(n=n, leaf_size=r, tile=tile, want_perm=True)])
             bbx.plan_check([dict(n=n, leaf_size=r, tile=tile, dims=2, dtype=1, ref_mode=1)])
+            for lb in (1, 100, 4096):  # paired global levels
+                bbx.plan_check([dict(n=n, leaf_size=r, tile=tile, level_blocks=lb, level_pairs=1)])
 
 
 def test_plan_batches():
@@ -44,9 +46,12 @@ def test_plan_batches():
         k = int(rng.integers(2, 40))
         ns = np.exp(rng.uniform(np.log(1e3), np.log(1 << 26), k)).astype(np.int64)
         bbx.plan_check([dict(n=int(n), leaf_size=int(rng.choice([8, 16, 32, 64, 300])),
-                             want_perm=bool(rng.random() < 0.3)) for n in ns])
+                             want_perm=bool(rng.random() < 0.3),
+                             level_pairs=int(rng.random() < 0.5)) for n in ns])
 
 
 def test_plan_check_rejects_bad_arguments():
     with pytest.raises(bbx.BitboxError, match="level_blocks"):
         bbx.plan_check([dict(n=5000, level_blocks=5000)])
+    with pytest.raises(bbx.BitboxError, match="level_pairs"):
+        bbx.plan_check([dict(n=5000, level_pairs=2)])
