@@ -15,6 +15,8 @@
 // first in each leaf) with coalesced stores.
 //
 // k_bigleaf: one workgroup per leaf when leaves exceed the tile capacity.
+#include <type_traits>
+
 #include "bbx_internal.h"
 
 namespace bbx {
@@ -290,159 +292,199 @@ __device__ void tile_body(WaveTile<TILE, KL, TRACK>& sm, uint64_t j, uint32_t K0
   int last_l = -1;
   uint32_t lastN = 0;
   const uint32_t p0 = lane * E;
-  // the lane's E consecutive positions: node start and size at the current
-  // level, followed from level to level (a node's left child keeps the first
-  // floor(s/2) positions)
-  uint32_t nsr[E], nzz[E], ni[E];
+  // The levels.  POW2: a tile of exactly TILE members and r a power of two,
+  // so every node of level l holds TILE >> l members starting at a multiple
+  // of that: a position's node and its bounds are shifts, every node above
+  // the leaves splits, and a node's prefix at its start (a lane boundary
+  // while nodes hold >= E members) comes from the first lane of the node.
+  auto levels = [&](auto pow2_tag) __attribute__((always_inline)) {
+    constexpr bool POW2 = decltype(pow2_tag)::value;
+    constexpr uint32_t LT = TILE == 256 ? 8u : 9u;  // log2(TILE)
+    // the lane's E consecutive positions: node start and size at the current
+    // level, followed from level to level (a node's left child keeps the first
+    // floor(s/2) positions)
+    uint32_t nsr[E], nzz[E], ni[E];
 #pragma unroll
-  for (int k = 0; k < E; ++k) nsr[k] = 0, nzz[k] = s0, ni[k] = 0;
-  for (uint32_t l = 0;; ++l) {
-    const uint32_t N = 1u << l;
-    const uint32_t maxsz = (s0 + N - 1) >> l;
-    if (maxsz <= r) break;
-    const uint32_t d = (K0 + l) % dims;
-    const uint32_t G = d == 0 ? Gt[0] : (d == 1 ? Gt[1] : Gt[2]);
-    for (uint32_t i = lane; i < N; i += 64) {
-      uint64_t a, b;
-      node_span(s0, l, i, &a, &b);
-      sm.nst[i] = (uint16_t)a;
-      sm.nsz[i] = (uint16_t)b;
-      sm.npre[i] = 0;
-      sm.nrank[i] = (uint16_t)(b >> 1);
-    }
-    wave_sync();
-    uint32_t slot[E], q[E];
-    bool inner[E];
-#pragma unroll
-    for (int k = 0; k < E; ++k) {
-      const uint32_t p = p0 + k;
-      inner[k] = p < s0 && nzz[k] > r;
-      slot[k] = sm.Pm[cur][p & (TILE - 1)] & (TILE - 1);
-    }
-#pragma unroll
-    for (int k = 0; k < E; ++k) q[k] = sm.K[d][slot[k]];
-    // ---- radix select of each internal node's median code (N << w <= TILE bins);
-    // with all codes equal the median is that code and nothing is counted
-    if (G > 0) {
-      uint32_t Wl = 0;
-      while ((N << (Wl + 1)) <= (uint32_t)TILE && Wl < 8) ++Wl;
-      const uint32_t npass = (G + Wl - 1) / Wl;
-      const uint32_t firstw = G - (npass - 1) * Wl;
-      uint32_t used = 0;
-      for (uint32_t pass = 0; pass < npass; ++pass) {
-        const uint32_t w = pass == 0 ? firstw : Wl;
-        const uint32_t hs = G - used;
-        used += w;
-        const uint32_t sh = G - used;
-        const uint32_t nb = 1u << w, mask = nb - 1;
-        if (pass == 0) {
-#pragma unroll
-          for (int k = 0; k < E; ++k)
-            if (inner[k]) atomicAdd(&sm.H[(ni[k] << w) + ((q[k] >> sh) & mask)], 1u);
+    for (int k = 0; k < E; ++k) nsr[k] = 0, nzz[k] = s0, ni[k] = 0;
+    for (uint32_t l = 0;; ++l) {
+      const uint32_t N = 1u << l;
+      const uint32_t maxsz = POW2 ? (TILE >> l) : (s0 + N - 1) >> l;
+      if (maxsz <= r) break;
+      const uint32_t d = (K0 + l) % dims;
+      const uint32_t G = d == 0 ? Gt[0] : (d == 1 ? Gt[1] : Gt[2]);
+      for (uint32_t i = lane; i < N; i += 64) {
+        uint64_t a, b;
+        if (POW2) {
+          a = (uint64_t)i << (LT - l);
+          b = TILE >> l;
         } else {
-          uint32_t pre[E];
-#pragma unroll
-          for (int k = 0; k < E; ++k) pre[k] = sm.npre[ni[k]];
-#pragma unroll
-          for (int k = 0; k < E; ++k)
-            if (inner[k] && (q[k] >> hs) == pre[k])
-              atomicAdd(&sm.H[(ni[k] << w) + ((q[k] >> sh) & mask)], 1u);
+          node_span(s0, l, i, &a, &b);
         }
-        wave_sync();
-        if (N <= 8) {
-          // few nodes: every node's bins at once.  The N * 2^w bins are
-          // split evenly over the lanes, each lane's bins inside one node;
-          // a node's prefix is the wavefront prefix minus its value at the
-          // node's first lane.
-          const uint32_t T = N << w;
-          const uint32_t lp = T > 64 ? bitlen32(T) - 7 : 0u;  // T is a power of two
-          const uint32_t per = 1u << lp;                       // bins per lane, <= TILE / 64
-          const uint32_t b0 = lane << lp;
-          uint32_t c[TILE / 64];
-          uint32_t mine = 0;
+        sm.nst[i] = (uint16_t)a;
+        sm.nsz[i] = (uint16_t)b;
+        sm.npre[i] = 0;
+        sm.nrank[i] = (uint16_t)(b >> 1);
+      }
+      if (POW2) {
 #pragma unroll
-          for (int k = 0; k < TILE / 64; ++k) {
-            const uint32_t b = b0 + k;
-            c[k] = 0;
-            if ((uint32_t)k < per && b < T) {
-              c[k] = sm.H[b];
-              if (c[k]) sm.H[b] = 0;
-            }
-            mine += c[k];
+        for (int k = 0; k < E; ++k) {
+          ni[k] = (p0 + k) >> (LT - l);
+          nsr[k] = ni[k] << (LT - l);
+          nzz[k] = TILE >> l;
+        }
+      }
+      wave_sync();
+      uint32_t slot[E], q[E];
+      bool inner[E];
+#pragma unroll
+      for (int k = 0; k < E; ++k) {
+        const uint32_t p = p0 + k;
+        inner[k] = POW2 ? true : (p < s0 && nzz[k] > r);
+        slot[k] = sm.Pm[cur][p & (TILE - 1)] & (TILE - 1);
+      }
+#pragma unroll
+      for (int k = 0; k < E; ++k) q[k] = sm.K[d][slot[k]];
+      // ---- radix select of each internal node's median code (N << w <= TILE bins);
+      // with all codes equal the median is that code and nothing is counted
+      if (G > 0) {
+        uint32_t Wl = 0;
+        while ((N << (Wl + 1)) <= (uint32_t)TILE && Wl < 8) ++Wl;
+        const uint32_t npass = (G + Wl - 1) / Wl;
+        const uint32_t firstw = G - (npass - 1) * Wl;
+        uint32_t used = 0;
+        for (uint32_t pass = 0; pass < npass; ++pass) {
+          const uint32_t w = pass == 0 ? firstw : Wl;
+          const uint32_t hs = G - used;
+          used += w;
+          const uint32_t sh = G - used;
+          const uint32_t nb = 1u << w, mask = nb - 1;
+          if (pass == 0) {
+#pragma unroll
+            for (int k = 0; k < E; ++k)
+              if (inner[k]) atomicAdd(&sm.H[(ni[k] << w) + ((q[k] >> sh) & mask)], 1u);
+          } else {
+            uint32_t pre[E];
+#pragma unroll
+            for (int k = 0; k < E; ++k) pre[k] = sm.npre[ni[k]];
+#pragma unroll
+            for (int k = 0; k < E; ++k)
+              if (inner[k] && (q[k] >> hs) == pre[k])
+                atomicAdd(&sm.H[(ni[k] << w) + ((q[k] >> sh) & mask)], 1u);
           }
-          const uint32_t ex = wave_incl(mine) - mine;
-          const uint32_t i = b0 < T ? b0 >> w : 0u;
-          uint32_t cum = ex - (uint32_t)__shfl((int)ex, (int)((i << w) >> lp));
-          if (b0 < T && sm.nsz[i] > r) {
-            const uint32_t rank = sm.nrank[i];
-            const uint32_t pr = sm.npre[i];
+          wave_sync();
+          if (N <= 8) {
+            // few nodes: every node's bins at once.  The N * 2^w bins are
+            // split evenly over the lanes, each lane's bins inside one node;
+            // a node's prefix is the wavefront prefix minus its value at the
+            // node's first lane.
+            const uint32_t T = N << w;
+            const uint32_t lp = T > 64 ? bitlen32(T) - 7 : 0u;  // T is a power of two
+            const uint32_t per = 1u << lp;                       // bins per lane, <= TILE / 64
+            const uint32_t b0 = lane << lp;
+            uint32_t c[TILE / 64];
+            uint32_t mine = 0;
 #pragma unroll
             for (int k = 0; k < TILE / 64; ++k) {
-              if ((uint32_t)k < per && cum <= rank && rank < cum + c[k]) {
-                sm.npre[i] = (KL)((pr << w) | ((b0 + k) & (nb - 1)));
-                sm.nrank[i] = (uint16_t)(rank - cum);
+              const uint32_t b = b0 + k;
+              c[k] = 0;
+              if ((uint32_t)k < per && b < T) {
+                c[k] = sm.H[b];
+                if (c[k]) sm.H[b] = 0;
               }
-              cum += c[k];
+              mine += c[k];
+            }
+            const uint32_t ex = wave_incl(mine) - mine;
+            const uint32_t i = b0 < T ? b0 >> w : 0u;
+            uint32_t cum = ex - (uint32_t)__shfl((int)ex, (int)((i << w) >> lp));
+            if (b0 < T && sm.nsz[i] > r) {
+              const uint32_t rank = sm.nrank[i];
+              const uint32_t pr = sm.npre[i];
+#pragma unroll
+              for (int k = 0; k < TILE / 64; ++k) {
+                if ((uint32_t)k < per && cum <= rank && rank < cum + c[k]) {
+                  sm.npre[i] = (KL)((pr << w) | ((b0 + k) & (nb - 1)));
+                  sm.nrank[i] = (uint16_t)(rank - cum);
+                }
+                cum += c[k];
+              }
+            }
+          } else {  // many small nodes: one lane per node scans its few bins
+            for (uint32_t i = lane; i < N; i += 64) {
+              if (sm.nsz[i] <= r) continue;
+              const uint32_t rank = sm.nrank[i];
+              uint32_t cum = 0, found = 0xffffffffu, below = 0;
+              for (uint32_t b = 0; b < nb; ++b) {
+                const uint32_t c = sm.H[(i << w) + b];
+                if (c) sm.H[(i << w) + b] = 0;
+                if (found == 0xffffffffu && rank < cum + c) found = b, below = cum;
+                cum += c;
+              }
+              sm.npre[i] = (KL)(((uint32_t)sm.npre[i] << w) | found);
+              sm.nrank[i] = (uint16_t)(rank - below);
             }
           }
-        } else {  // many small nodes: one lane per node scans its few bins
-          for (uint32_t i = lane; i < N; i += 64) {
-            if (sm.nsz[i] <= r) continue;
-            const uint32_t rank = sm.nrank[i];
-            uint32_t cum = 0, found = 0xffffffffu, below = 0;
-            for (uint32_t b = 0; b < nb; ++b) {
-              const uint32_t c = sm.H[(i << w) + b];
-              if (c) sm.H[(i << w) + b] = 0;
-              if (found == 0xffffffffu && rank < cum + c) found = b, below = cum;
-              cum += c;
-            }
-            sm.npre[i] = (KL)(((uint32_t)sm.npre[i] << w) | found);
-            sm.nrank[i] = (uint16_t)(rank - below);
-          }
+          wave_sync();
+        }
+      }
+      // ---- stable partition: exclusive prefix of (lt | eq << 16) over the tile
+      uint32_t fl[E], jq[E];
+      uint32_t mine = 0;
+#pragma unroll
+      for (int k = 0; k < E; ++k) {
+        const uint32_t v = sm.npre[ni[k]];
+        jq[k] = sm.nrank[ni[k]];
+        fl[k] = inner[k] ? ((q[k] < v ? 1u : 0u) | (q[k] == v ? 0x10000u : 0u)) : 0u;
+        mine += fl[k];
+      }
+      uint32_t ex = wave_incl(mine) - mine;
+      // POW2 with nodes of >= E members: the prefix at the lane's node start
+      // is the exclusive prefix of the node's first lane
+      const bool lane_starts = POW2 && (TILE >> l) >= (uint32_t)E;
+      const uint32_t exs = lane_starts ? (uint32_t)__shfl((int)ex, (int)(nsr[0] / E)) : 0u;
+      if (!lane_starts) {
+        uint32_t e2 = ex;
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+          if (p0 + k < s0) sm.S[p0 + k] = e2;
+          e2 += fl[k];
         }
         wave_sync();
       }
-    }
-    // ---- stable partition: exclusive prefix of (lt | eq << 16) over the tile
-    uint32_t fl[E], jq[E];
-    uint32_t mine = 0;
 #pragma unroll
-    for (int k = 0; k < E; ++k) {
-      const uint32_t v = sm.npre[ni[k]];
-      jq[k] = sm.nrank[ni[k]];
-      fl[k] = inner[k] ? ((q[k] < v ? 1u : 0u) | (q[k] == v ? 0x10000u : 0u)) : 0u;
-      mine += fl[k];
+      for (int k = 0; k < E; ++k) {
+        const uint32_t p = p0 + k;
+        const uint32_t ns = nsr[k], nz = nzz[k];
+        const uint32_t X = lane_starts ? ex - exs : sm.S[p & (TILE - 1)] - sm.S[ns & (TILE - 1)];
+        const uint32_t L = X & 0xffffu, Eq = X >> 16;
+        const uint32_t jeq = jq[k];
+        const uint32_t lb = L + umin32(Eq, jeq);
+        const bool lt = fl[k] & 1u, eq = (fl[k] >> 16) & 1u;
+        const bool left = lt || (eq && Eq < jeq);
+        const uint32_t dest = inner[k] ? ns + (left ? lb : (nz >> 1) + (p - ns) - lb) : p;
+        if (p < s0 && dest < s0) sm.Pm[cur ^ 1][dest] = (uint16_t)slot[k];
+        ex += fl[k];
+        if (!POW2) {  // follow this position into its child of the next level
+          const uint32_t half = nz >> 1;
+          const bool right = p - ns >= half;
+          ni[k] = 2 * ni[k] + (right ? 1u : 0u);
+          nsr[k] = right ? ns + half : ns;
+          nzz[k] = right ? nz - half : half;
+        }
+      }
+      wave_sync();
+      cur ^= 1;
+      last_l = (int)l;
+      lastN = N;
     }
-    uint32_t ex = wave_incl(mine) - mine;
-#pragma unroll
-    for (int k = 0; k < E; ++k) {
-      if (p0 + k < s0) sm.S[p0 + k] = ex;
-      ex += fl[k];
-    }
-    wave_sync();
-#pragma unroll
-    for (int k = 0; k < E; ++k) {
-      const uint32_t p = p0 + k;
-      const uint32_t ns = nsr[k], nz = nzz[k];
-      const uint32_t X = sm.S[p & (TILE - 1)] - sm.S[ns & (TILE - 1)];
-      const uint32_t L = X & 0xffffu, Eq = X >> 16;
-      const uint32_t jeq = jq[k];
-      const uint32_t lb = L + umin32(Eq, jeq);
-      const bool lt = fl[k] & 1u, eq = (fl[k] >> 16) & 1u;
-      const bool left = lt || (eq && Eq < jeq);
-      const uint32_t dest = inner[k] ? ns + (left ? lb : (nz >> 1) + (p - ns) - lb) : p;
-      if (p < s0 && dest < s0) sm.Pm[cur ^ 1][dest] = (uint16_t)slot[k];
-      // follow this position into its child of the next level
-      const uint32_t half = nz >> 1;
-      const bool right = p - ns >= half;
-      ni[k] = 2 * ni[k] + (right ? 1u : 0u);
-      nsr[k] = right ? ns + half : ns;
-      nzz[k] = right ? nz - half : half;
-    }
-    wave_sync();
-    cur ^= 1;
-    last_l = (int)l;
-    lastN = N;
+
+  };
+  if constexpr (TILE == 256 && sizeof(KL) == 2) {  // the first pass at the default capacity
+    if (s0 == (uint32_t)TILE && (r & (r - 1)) == 0)
+      levels(std::true_type{});
+    else
+      levels(std::false_type{});
+  } else {
+    levels(std::false_type{});
   }
 
   // ---- leaf list (depth-first): nodes of the last level that were split give
