@@ -1471,7 +1471,7 @@ __device__ inline void store_run(T* X, uint32_t e0, uint32_t s, bool vec, F&& ge
 // other wavefront or block touches the node.  `lds` holds the select bins,
 // then the staged node (8 bytes per member with 16-bit codes, else one
 // 32-bit array at a time).
-template <typename KT, bool TRACK, int W>
+template <typename KT, bool TRACK, int W, bool FULL>
 __device__ __forceinline__ void level_fused_body(uint32_t depth, const SetDesc& S, DevParams* P,
                                                  uint64_t j, uint8_t* keys, uint32_t* idx,
                                                  uint32_t* lds, uint32_t* red, uint32_t (*xs)[4]) {
@@ -1499,7 +1499,9 @@ __device__ __forceinline__ void level_fused_body(uint32_t depth, const SetDesc& 
                          // the source indices, are read when they are staged)
   q0.load(X0, p0, s, vk);
   q1.load(X1, p0, s, vk);
-  const uint32_t act = p0 >= s ? 0u : (p0 + R <= s ? (1u << R) - 1u : (1u << (s - p0)) - 1u);
+  // FULL: the node holds W kFuseNode members, every lane all R of them
+  const uint32_t act = FULL ? (1u << R) - 1u
+                            : (p0 >= s ? 0u : (p0 + R <= s ? (1u << R) - 1u : (1u << (s - p0)) - 1u));
   for (uint32_t k = W == 1 ? lane : threadIdx.x; k < 512; k += 64u * W) lds[k] = 0;  // select bins
   // every load of the node has returned before any wavefront of the node
   // passes its first barrier (the stores come after it)
@@ -1655,7 +1657,7 @@ __device__ __forceinline__ void level_fused_body(uint32_t depth, const SetDesc& 
 // is k.  W = 1: one wavefront per node of depth k, four nodes per block;
 // W = 4: one block per node.
 template <bool TRACK, int W>
-__global__ void __launch_bounds__(kBlock) k_level_fused(uint32_t depth, uint32_t nsets,
+__global__ void __launch_bounds__(kBlock, W == 4 ? 4 : 1) k_level_fused(uint32_t depth, uint32_t nsets,
                                                         const uint64_t* pre, const SetDesc* sets,
                                                         DevParams* params, uint8_t* keys0,
                                                         uint8_t* keys1, uint32_t* idx0,
@@ -1678,9 +1680,16 @@ __global__ void __launch_bounds__(kBlock) k_level_fused(uint32_t depth, uint32_t
   uint32_t* idx = S.track ? idx0 + S.idx_off : nullptr;
   uint32_t* b = (uint32_t*)(stage + (W == 1 ? wv * kFuseNode : 0));
   if (P->key16)
-    level_fused_body<uint16_t, TRACK, W>(depth, S, P, j, keys0 + S.key_off, idx, b, red, xs);
+  {
+    uint64_t st, sz;
+    node_span(S.n, depth, j, &st, &sz);
+    if (W == 4 && sz == (uint64_t)W * kFuseNode)  // (a wavefront per node: no gain, more registers)
+      level_fused_body<uint16_t, TRACK, W, W == 4>(depth, S, P, j, keys0 + S.key_off, idx, b, red, xs);
+    else
+      level_fused_body<uint16_t, TRACK, W, false>(depth, S, P, j, keys0 + S.key_off, idx, b, red, xs);
+  }
   else
-    level_fused_body<uint32_t, TRACK, W>(depth, S, P, j, keys0 + S.key_off, idx, b, red, xs);
+    level_fused_body<uint32_t, TRACK, W, false>(depth, S, P, j, keys0 + S.key_off, idx, b, red, xs);
 }
 
 // ---------------------------------------------------------------- paired levels
