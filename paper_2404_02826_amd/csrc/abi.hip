@@ -234,6 +234,7 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
   std::vector<uint64_t> rp(nsets, 0), rl(nsets, 0), rw(nsets, 0);
   std::vector<uint8_t> stage_seen(kMaxDepth, 0);  // a set with global level k seen
   std::vector<std::vector<uint64_t>> lv(nsets), nd(nsets);
+  std::vector<std::vector<uint8_t>> lk(nsets);  // per depth: the kernel family that handles it
   for (uint32_t s = 0; s < nsets; ++s) {
     const SetIn& I = in[s];
     SetDesc& D = (*descs)[s];
@@ -339,18 +340,24 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
       for (uint32_t k = 0; k < D.gl; ++k) {
         const LevelShape sh = level_shape(n, k, D.level_blocks);
         const int kind = level_kind(n, k);
+        uint8_t fam = kFamGlobal;
         if (k - D.fuse_depth < 2u) {
+          fam = k == D.fuse_depth ? kFamFused : kFamNone;
           if (k == D.fuse_depth) bp->lv_fused[k] = 1;  // both levels in one pass
         } else if (k - D.fuse_depth4 < 2u) {
+          fam = k == D.fuse_depth4 ? kFamFused4 : kFamNone;
           if (k == D.fuse_depth4) bp->lv_fused4[k] = 1;
-        } else if (kind == 2)
+        } else if (kind == 2) {
+          fam = kFamWave;
           bp->lv_wave[k] = 1;
-        else if (kind == 1)
+        } else if (kind == 1) {
+          fam = kFamLocal;
           bp->lv_local[k] = 1;
-        else if (pair_first(D, k))
+        } else if (pair_first(D, k))
           bp->lv_global[k] = bp->lv_pair[k] = 1;
         else if (!pair_second(D, k))
           bp->lv_global[k] = bp->lv_single[k] = 1;
+        lk[s].push_back(fam);
         if (kind == kLevelGlobal && sh.chunks > 256) {
           if (!pair_second(D, k)) bp->sel_wide[k] = 1;
           if (pair_first(D, k)) bp->pair_wide[k] = 1;  // the second level's selects use these chunks
@@ -422,14 +429,27 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
   bp->o_rp = add(rp, &bp->g_rp);
   bp->o_rl = add(rl, &bp->g_rl);
   bp->o_rw = add(rw, &bp->g_rw);
+  // Per depth and kernel family, the blocks (or node wavefronts) of the sets
+  // that family handles there and none for the others, so that a launch spans
+  // only its own sets' nodes; a family no set uses at a depth gets no array.
   for (uint32_t k = 0; k < bp->max_gl; ++k) {
-    std::vector<uint64_t> a(nsets), b(nsets);
-    for (uint32_t s = 0; s < nsets; ++s) {
-      a[s] = k < lv[s].size() ? lv[s][k] : 0;
-      b[s] = k < nd[s].size() ? nd[s][k] : 0;
-    }
-    bp->o_lv[k] = add(a, &bp->g_lv[k]);
-    bp->o_nd[k] = add(b, &bp->g_nd[k]);
+    auto fam_add = [&](uint8_t fam, bool chunks, uint64_t* grid) -> uint64_t {
+      std::vector<uint64_t> a(nsets, 0);
+      bool any = false;
+      for (uint32_t s = 0; s < nsets; ++s)
+        if (k < lk[s].size() && lk[s][k] == fam) {
+          a[s] = chunks ? lv[s][k] : nd[s][k];
+          any = true;
+        }
+      *grid = 0;
+      return any ? add(a, grid) : 0;
+    };
+    bp->o_lv[k] = fam_add(kFamGlobal, true, &bp->g_lv[k]);
+    bp->o_nd[k] = fam_add(kFamGlobal, false, &bp->g_nd[k]);
+    bp->o_lc[k] = fam_add(kFamLocal, true, &bp->g_lc[k]);
+    bp->o_wv[k] = fam_add(kFamWave, false, &bp->g_wv[k]);
+    bp->o_fu[k] = fam_add(kFamFused, false, &bp->g_fu[k]);
+    bp->o_f4[k] = fam_add(kFamFused4, false, &bp->g_f4[k]);
   }
   bp->pre_entries = pre->size();
   Carve c;
@@ -537,6 +557,11 @@ static std::string check_plan(const SetIn* in, uint32_t nsets) {
     const uint64_t bin_nodes = D.hist_half / kHistBins;
     int prev_kind = kLevelGlobal;
     uint64_t sel_need = 0;
+    // set s's share of a family's grid at level k (the family's array must exist)
+    auto share = [&](uint64_t off, uint64_t grid) -> uint64_t {
+      if (bp.pre_entries == 0 || grid == 0) return 0;
+      return pre[off + s + 1] - pre[off + s];
+    };
     for (uint32_t k = 0; k < D.gl; ++k) {
       const int kind = level_kind(n, k);
       const LevelShape sh = level_shape(n, k, D.level_blocks);
@@ -553,10 +578,16 @@ static std::string check_plan(const SetIn* in, uint32_t nsets) {
         if (kind != kLevelWave) return where(s, k) + "fused level is not a wavefront level";
         if (D.fuse_depth != kNoFuse && D.fuse_depth4 != kNoFuse && D.fuse_depth4 + 2 > D.fuse_depth)
           return where(s, k) + "fused pairs overlap";
+        if (k == D.fuse_depth && (!bp.lv_fused[k] || share(bp.o_fu[k], bp.g_fu[k]) != sh.nodes))
+          return where(s, k) + "fused pair's grid share differs from its nodes";
+        if (k == D.fuse_depth4 && (!bp.lv_fused4[k] || share(bp.o_f4[k], bp.g_f4[k]) != sh.nodes))
+          return where(s, k) + "fused pair's grid share differs from its nodes";
         continue;
       }
       if (kind == kLevelWave) {
         if (maxsz > kWaveNode) return where(s, k) + "wavefront node above its capacity";
+        if (!bp.lv_wave[k] || share(bp.o_wv[k], bp.g_wv[k]) != sh.nodes)
+          return where(s, k) + "wavefront level's grid share differs from its nodes";
         continue;
       }
       // block-local and global levels count radix bins of their nodes
@@ -564,13 +595,15 @@ static std::string check_plan(const SetIn* in, uint32_t nsets) {
       if (kind == kLevelBlock) {
         if (sh.chunks != 1) return where(s, k) + "block-local level with more than one chunk per node";
         if (level_shape(n, k, kLocalBlocks).chunks != 1) return where(s, k) + "block-local kind";
+        if (!bp.lv_local[k] || share(bp.o_lc[k], bp.g_lc[k]) != sh.nodes)
+          return where(s, k) + "block-local level's grid share differs from its nodes";
         continue;
       }
       if (sh.chunk_elems == 0 || sh.chunk_elems % kGroup) return where(s, k) + "chunk not whole groups";
       if (sh.chunks * (uint64_t)sh.chunk_elems < maxsz) return where(s, k) + "chunks do not cover the node";
       if ((sh.chunks - 1) * (uint64_t)sh.chunk_elems >= maxsz) return where(s, k) + "empty chunk in the largest node";
       if (sh.nodes * sh.chunks > rows_cap) return where(s, k) + "chunk rows too few";
-      if (bp.pre_entries == 0 || pre[bp.o_lv[k] + s + 1] - pre[bp.o_lv[k] + s] != sh.nodes * sh.chunks)
+      if (share(bp.o_lv[k], bp.g_lv[k]) != sh.nodes * sh.chunks || share(bp.o_nd[k], bp.g_nd[k]) != sh.nodes)
         return where(s, k) + "grid share differs from the level shape";
       if (sh.chunks > 256 && !pair_second(D, k) && !bp.sel_wide[k]) return where(s, k) + "wide select not launched";
       if (pair_first(D, k)) {  // the pair's second level lives in this level's chunks

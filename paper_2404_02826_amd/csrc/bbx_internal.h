@@ -552,6 +552,14 @@ struct ProfScope {
 
 // Host-side launch plan of a batch: grid sizes and the offsets (in u64
 // entries) of each prefix array inside the uploaded plan buffer.
+// kernel families of a set's global level (which launch handles it)
+constexpr uint8_t kFamNone = 0;    // second level of a fused pair
+constexpr uint8_t kFamGlobal = 1;  // global histograms, single or paired
+constexpr uint8_t kFamLocal = 2;   // a block per node
+constexpr uint8_t kFamWave = 3;    // a wavefront per node
+constexpr uint8_t kFamFused = 4;   // two levels, a wavefront per node
+constexpr uint8_t kFamFused4 = 5;  // two levels, a block per node
+
 struct BatchPlan {
   uint32_t nsets;
   uint32_t max_gl;            // deepest global level count over the sets
@@ -561,8 +569,13 @@ struct BatchPlan {
   uint64_t hist_entries;      // u32 bins zeroed once per call
   uint64_t g_mm, g_qz, g_tile, g_big, g_pm, g_pp;
   uint64_t o_mm, o_qz, o_tile, o_big, o_pm, o_pp;
-  uint64_t g_lv[kMaxDepth], g_nd[kMaxDepth];
-  uint64_t o_lv[kMaxDepth], o_nd[kMaxDepth];
+  // per depth: global levels' chunk blocks and nodes, block-local levels'
+  // blocks, wavefront levels' nodes, fused pairs' nodes (a wavefront or a
+  // block each); each array counts only the sets of its family at that depth
+  uint64_t g_lv[kMaxDepth], g_nd[kMaxDepth], g_lc[kMaxDepth], g_wv[kMaxDepth];
+  uint64_t g_fu[kMaxDepth], g_f4[kMaxDepth];
+  uint64_t o_lv[kMaxDepth], o_nd[kMaxDepth], o_lc[kMaxDepth], o_wv[kMaxDepth];
+  uint64_t o_fu[kMaxDepth], o_f4[kMaxDepth];
   uint8_t lv_local[kMaxDepth];   // some set handles level k one block per node
   uint8_t lv_global[kMaxDepth];  // some set handles level k with global histograms
   uint8_t sel_wide[kMaxDepth];   // some set's nodes have > 256 chunks at global level k

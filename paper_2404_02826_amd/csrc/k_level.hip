@@ -2241,20 +2241,21 @@ hipError_t launch_levels(const BatchPlan& bp, const Ws& w, hipStream_t s) {
     const uint64_t* plv = w.pre + bp.o_lv[k];
     const uint64_t* pnd = w.pre + bp.o_nd[k];
     if (bp.lv_local[k])
-      BBX_LAUNCH("level_local", k_level_local, bp.g_lv[k], kBlock, 0, s, k, bp.nsets, plv, w.sets,
-                 w.params, K0, K1, I0, I1, w.hist);
+      BBX_LAUNCH("level_local", k_level_local, bp.g_lc[k], kBlock, 0, s, k, bp.nsets,
+                 w.pre + bp.o_lc[k], w.sets, w.params, K0, K1, I0, I1, w.hist);
     if (bp.lv_wave[k])
       BBX_LAUNCH("level_wave", bp.track ? k_level_wave<true> : k_level_wave<false>,
-                 (bp.g_nd[k] + kBlock / 64 - 1) / (kBlock / 64), kBlock, 0, s, k, bp.nsets, pnd,
-                 w.sets, w.params, K0, K1, I0, I1);
+                 (bp.g_wv[k] + kBlock / 64 - 1) / (kBlock / 64), kBlock, 0, s, k, bp.nsets,
+                 w.pre + bp.o_wv[k], w.sets, w.params, K0, K1, I0, I1);
     // levels k and k + 1 in place
     if (bp.lv_fused[k])
       BBX_LAUNCH("level_fused", (bp.track ? k_level_fused<true, 1> : k_level_fused<false, 1>),
-                 (bp.g_nd[k] + kBlock / 64 - 1) / (kBlock / 64), kBlock, 0, s, k, bp.nsets, pnd,
-                 w.sets, w.params, K0, K1, I0, I1);
+                 (bp.g_fu[k] + kBlock / 64 - 1) / (kBlock / 64), kBlock, 0, s, k, bp.nsets,
+                 w.pre + bp.o_fu[k], w.sets, w.params, K0, K1, I0, I1);
     if (bp.lv_fused4[k])
       BBX_LAUNCH("level_fused4", (bp.track ? k_level_fused<true, 4> : k_level_fused<false, 4>),
-                 bp.g_nd[k], kBlock, 0, s, k, bp.nsets, pnd, w.sets, w.params, K0, K1, I0, I1);
+                 bp.g_f4[k], kBlock, 0, s, k, bp.nsets, w.pre + bp.o_f4[k], w.sets, w.params, K0,
+                 K1, I0, I1);
     if (!bp.lv_global[k]) continue;
     // mid passes: pass 0 was built by the quantize pass (depth 0) or by the
     // previous scatter
