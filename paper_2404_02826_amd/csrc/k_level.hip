@@ -1376,7 +1376,7 @@ __device__ inline uint32_t wave_excl(uint32_t x, uint32_t* tot) {
   return incl - x;
 }
 
-// R consecutive elements [p0, p0 + R) of one array (those below s; 0
+// R consecutive elements [p0, p0 + R) of one array (those below s; fill
 // beyond) held by a lane, loaded with 16-byte loads when the array is
 // 16-byte aligned and the run is whole; 16-bit codes two to a register.
 template <typename T, int R>
@@ -1410,7 +1410,7 @@ struct RegRun {
     *lo = a;
     *hi = b;
   }
-  __device__ __forceinline__ void load(const T* X, uint32_t p0, uint32_t s, bool vec) {
+  __device__ __forceinline__ void load(const T* X, uint32_t p0, uint32_t s, bool vec, T fill) {
     if (vec && p0 + R <= s) {
 #pragma unroll
       for (int b = 0; b < R / V; ++b) {
@@ -1424,7 +1424,7 @@ struct RegRun {
 #pragma unroll
         for (int h = 0; h < PER; ++h) {
           const uint32_t p = p0 + (uint32_t)(k * PER + h);
-          x |= (p < s ? (uint32_t)X[p] : 0u) << (16 * h);
+          x |= (uint32_t)(p < s ? X[p] : fill) << (16 * h);
         }
         w[k] = x;
       }
@@ -1457,6 +1457,18 @@ __device__ inline void store_run(T* X, uint32_t e0, uint32_t s, bool vec, F&& ge
   }
 }
 
+// Marks v as rewritten (no instruction), so that values derived from it
+// before this point are not kept live past it but derived again after it.
+template <typename T>
+__device__ __forceinline__ void reg_fence(T& v) {
+  asm volatile("" : "+v"(v));
+}
+template <typename T, int R>
+__device__ __forceinline__ void reg_fence(RegRun<T, R>& q) {
+#pragma unroll
+  for (int k = 0; k < R * (int)sizeof(T) / 4; ++k) reg_fence(q.w[k]);
+}
+
 // Levels k and k + 1 of one node, in place.  Each lane holds R consecutive
 // members (member order: wavefront, lane, row) with their codes (and source
 // indices) in registers.  The node's median along d is selected there, then
@@ -1469,9 +1481,13 @@ __device__ inline void store_run(T* X, uint32_t e0, uint32_t s, bool vec, F&& ge
 // the node is read before the barrier that precedes the first store to it
 // (a value is consumed before the barrier, so its load has returned), and no
 // other wavefront or block touches the node.  `lds` holds the select bins,
-// then the staged node (8 bytes per member with 16-bit codes, else one
-// 32-bit array at a time).
-template <typename KT, bool TRACK, int W, bool FULL>
+// then the staged node (three 16-bit arrays with 16-bit codes, else one
+// 32-bit array at a time).  Every lane holds R members: those past the
+// node's end read as the top code of their axis, so they order after every
+// member of the node (a code as large or larger, a later member) and leave
+// each median, side and slot of the node's members as it is; they all fall
+// in the last grandchild, at slots s and up, which are never written back.
+template <typename KT, bool TRACK, int W>
 __device__ __forceinline__ void level_fused_body(uint32_t depth, const SetDesc& S, DevParams* P,
                                                  uint64_t j, uint8_t* keys, uint32_t* idx,
                                                  uint32_t* lds, uint32_t* red, uint32_t (*xs)[4]) {
@@ -1497,11 +1513,13 @@ __device__ __forceinline__ void level_fused_body(uint32_t depth, const SetDesc& 
   const uint32_t p0 = wv * (uint32_t)kFuseNode + lane * R;  // the lane's first member
   RegRun<KT, R> q0, q1;  // the split axis and the next one (the third axis, and
                          // the source indices, are read when they are staged)
-  q0.load(X0, p0, s, vk);
-  q1.load(X1, p0, s, vk);
-  // FULL: the node holds W kFuseNode members, every lane all R of them
-  const uint32_t act = FULL ? (1u << R) - 1u
-                            : (p0 >= s ? 0u : (p0 + R <= s ? (1u << R) - 1u : (1u << (s - p0)) - 1u));
+  auto top = [](uint32_t g) { return (KT)(g >= 32 ? 0xffffffffu : (1u << g) - 1u); };
+  q0.load(X0, p0, s, vk, top(P->G[d]));
+  q1.load(X1, p0, s, vk, top(P->G[a1]));
+  constexpr uint32_t all = (1u << R) - 1u;  // member flags: every member of the lane
+  // between phases: the codes are taken up again from their packed
+  // registers instead of holding unpacked copies across the phases
+  auto fence = [&]() { reg_fence(q0), reg_fence(q1); };
   for (uint32_t k = W == 1 ? lane : threadIdx.x; k < 512; k += 64u * W) lds[k] = 0;  // select bins
   // every load of the node has returned before any wavefront of the node
   // passes its first barrier (the stores come after it)
@@ -1512,14 +1530,15 @@ __device__ __forceinline__ void level_fused_body(uint32_t depth, const SetDesc& 
   // equal to the median go left while fewer than jeq of them did)
   uint32_t v, jeq;
   {
-    const uint32_t m1[1] = {act};
+    const uint32_t m1[1] = {all};
     uint32_t rk[1] = {s >> 1}, vv[1];
     reg_select<R, W, 1>(q0, m1, rk, lds, red, vv);
     v = vv[0], jeq = rk[0];
   }
+  fence();
   uint32_t ne = 0;
 #pragma unroll
-  for (int i = 0; i < R; ++i) ne += (((act >> i) & 1u) && q0[i] == v) ? 1u : 0u;
+  for (int i = 0; i < R; ++i) ne += q0[i] == v ? 1u : 0u;
   uint32_t te[1], be[1];
   uint32_t erun = wave_excl(ne, &te[0]);
   fuse_bases<W, 1>(te, be, xs);
@@ -1527,11 +1546,12 @@ __device__ __forceinline__ void level_fused_body(uint32_t depth, const SetDesc& 
   uint32_t left = 0;
 #pragma unroll
   for (int i = 0; i < R; ++i) {
-    const bool a = (act >> i) & 1u, eq = a && q0[i] == v;
-    if ((a && q0[i] < v) || (eq && erun < jeq)) left |= 1u << i;
+    const bool eq = q0[i] == v;
+    if (q0[i] < v || (eq && erun < jeq)) left |= 1u << i;
     erun += eq ? 1u : 0u;
   }
-  const uint32_t right = act & ~left;
+  const uint32_t right = all & ~left;
+  fence();
 
   // ---- level k + 1: both children's medians along the next axis, then each
   // member's side within its child (counts of the two children packed in
@@ -1544,11 +1564,12 @@ __device__ __forceinline__ void level_fused_body(uint32_t depth, const SetDesc& 
     reg_select<R, W, 2>(q1, m2, rk, lds, red, vv);
     vL = vv[0], vR = vv[1], jL = rk[0], jR = rk[1];
   }
+  fence();
   uint32_t ne2 = 0;
 #pragma unroll
   for (int i = 0; i < R; ++i) {
     const bool l = (left >> i) & 1u;
-    if (((act >> i) & 1u) && q1[i] == (l ? vL : vR)) ne2 += l ? 1u : 0x10000u;
+    if (q1[i] == (l ? vL : vR)) ne2 += l ? 1u : 0x10000u;
   }
   uint32_t t2, b2[2];
   uint32_t run2 = wave_excl(ne2, &t2);
@@ -1562,11 +1583,11 @@ __device__ __forceinline__ void level_fused_body(uint32_t depth, const SetDesc& 
   uint32_t gm = 0;
 #pragma unroll
   for (int i = 0; i < R; ++i) {
-    const bool a = (act >> i) & 1u, l = (left >> i) & 1u;
+    const bool l = (left >> i) & 1u;
     const uint32_t vs = l ? vL : vR, js = l ? jL : jR;
     const uint32_t run = l ? (run2 & 0xffffu) : (run2 >> 16);
-    const bool eq = a && q1[i] == vs;
-    const bool f = (a && q1[i] < vs) || (eq && run < js);
+    const bool eq = q1[i] == vs;
+    const bool f = q1[i] < vs || (eq && run < js);
     gm |= ((l ? 0u : 2u) | (f ? 0u : 1u)) << (2 * i);
     run2 += eq ? (l ? 1u : 0x10000u) : 0u;
   }
@@ -1574,51 +1595,68 @@ __device__ __forceinline__ void level_fused_body(uint32_t depth, const SetDesc& 
   // ---- slots: a lane's member counts per grandchild, 16 bits apiece in one
   // 64-bit word (they stay below 2^16), one scan per 32-bit half; c holds
   // each grandchild's next slot
+  fence();
   uint64_t cnt = 0;
 #pragma unroll
-  for (int i = 0; i < R; ++i)
-    if ((act >> i) & 1u) cnt += 1ull << (16 * ((gm >> (2 * i)) & 3u));
+  for (int i = 0; i < R; ++i) cnt += 1ull << (16 * ((gm >> (2 * i)) & 3u));
   uint32_t tA, tB, b4[4];
   const uint32_t rA = wave_excl((uint32_t)cnt, &tA), rB = wave_excl((uint32_t)(cnt >> 32), &tB);
   {
     const uint32_t tt[4] = {tA & 0xffffu, tA >> 16, tB & 0xffffu, tB >> 16};
     fuse_bases<W, 4>(tt, b4, xs);
   }
+  // C member slots: every grandchild must count its own size (the last also
+  // the members past the node's end), then each member's slot lies inside
+  // its grandchild (the last wavefront sees the node totals)
+  constexpr uint32_t C = W * kFuseNode;
+  if (wv == W - 1) {
+    const uint32_t tt[4] = {tA & 0xffffu, tA >> 16, tB & 0xffffu, tB >> 16};
+    const uint32_t gs[4] = {hL, sL - hL, hR, sR - hR + (C - s)};
+    bool bad = false;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) bad |= b4[g] + tt[g] != gs[g];
+    if (bad && lane == 0) check_failed(P, kChkFusedPart);
+  }
   uint64_t c = ((uint64_t)rB << 32 | rA) +
                ((uint64_t)b4[0] | ((uint64_t)(hL + b4[1]) << 16) | ((uint64_t)(sL + b4[2]) << 32) |
                 ((uint64_t)(sL + hR + b4[3]) << 48));
+  // the mask keeps even a failed count's slots inside LDS
   uint32_t dst[R];
-  bool bad = false;
 #pragma unroll
   for (int i = 0; i < R; ++i) {
-    const bool a = (act >> i) & 1u;
     const uint32_t sh = 16 * ((gm >> (2 * i)) & 3u);
-    dst[i] = (uint32_t)(c >> sh) & 0xffffu;
-    c += a ? 1ull << sh : 0ull;
-    bad |= a && dst[i] >= s;
+    dst[i] = (uint32_t)(c >> sh) & (C - 1);
+    c += 1ull << sh;
   }
-  if (bad) check_failed(P, kChkFusedPart);
   // ---- the node permuted through LDS, then written back in slot order with
   // 8 consecutive slots per thread and round
   constexpr uint32_t T = 64u * W, E = 8;
   const uint32_t tid = W == 1 ? lane : threadIdx.x;
   if constexpr (sizeof(KT) == 2) {
     RegRun<KT, R> q2;
-    q2.load(X2, p0, s, vk);  // no store to the node before the barrier below
-    uint64_t* stg = (uint64_t*)lds;
+    q2.load(X2, p0, s, vk, 0);  // no store to the node before the barrier below
+    // one array of C 16-bit slots per axis, copied out 16 bytes at a time
+    uint16_t* sg = (uint16_t*)lds;
 #pragma unroll
-    for (int i = 0; i < R; ++i)
-      if (((act >> i) & 1u) && dst[i] < s)
-        stg[dst[i]] = (uint64_t)q0[i] | ((uint64_t)q1[i] << 16) | ((uint64_t)q2[i] << 32);
+    for (int i = 0; i < R; ++i) {
+      sg[dst[i]] = (uint16_t)q0[i];
+      sg[C + dst[i]] = (uint16_t)q1[i];
+      if (dims > 2) sg[2 * C + dst[i]] = (uint16_t)q2[i];
+    }
     fuse_sync<W>();
-    for (uint32_t e0 = tid * E; e0 < s; e0 += T * E) {
-      uint64_t e[E];
+    auto out = [&](KT* X, const uint16_t* g, uint32_t e0) {
+      if (vk && e0 + E <= s) {
+        *(uint4*)(X + e0) = *(const uint4*)(g + e0);
+      } else {
 #pragma unroll
-      for (uint32_t k = 0; k < E; ++k) e[k] = e0 + k < s ? stg[e0 + k] : 0ull;
-      store_run<E>(X0, e0, s, vk, [&](uint32_t k) { return (uint32_t)e[k] & 0xffffu; });
-      store_run<E>(X1, e0, s, vk, [&](uint32_t k) { return (uint32_t)(e[k] >> 16) & 0xffffu; });
-      if (dims > 2)
-        store_run<E>(X2, e0, s, vk, [&](uint32_t k) { return (uint32_t)(e[k] >> 32) & 0xffffu; });
+        for (uint32_t k = 0; k < E; ++k)
+          if (e0 + k < s) X[e0 + k] = g[e0 + k];
+      }
+    };
+    for (uint32_t e0 = tid * E; e0 < s; e0 += T * E) {
+      out(X0, sg, e0);
+      out(X1, sg + C, e0);
+      if (dims > 2) out(X2, sg + 2 * C, e0);
     }
   }
   // 32-bit codes and source indices: one array at a time, each read from
@@ -1626,8 +1664,7 @@ __device__ __forceinline__ void level_fused_body(uint32_t depth, const SetDesc& 
   uint32_t* stg32 = lds;
   auto pass32 = [&](auto* X, const auto& val, bool vec) {
 #pragma unroll
-    for (int i = 0; i < R; ++i)
-      if (((act >> i) & 1u) && dst[i] < s) stg32[dst[i]] = val[i];
+    for (int i = 0; i < R; ++i) stg32[dst[i]] = val[i];
     fuse_sync<W>();
     for (uint32_t e0 = tid * E; e0 < s; e0 += T * E)
       store_run<E>(X, e0, s, vec, [&](uint32_t k) { return stg32[e0 + k]; });
@@ -1639,7 +1676,7 @@ __device__ __forceinline__ void level_fused_body(uint32_t depth, const SetDesc& 
     pass32(X1, q1, vk);
     if (dims > 2) {
       RegRun<KT, R> q2;
-      q2.load(X2, p0, s, vk);
+      q2.load(X2, p0, s, vk, 0);
       pass32(X2, q2, vk);
     }
   }
@@ -1647,7 +1684,7 @@ __device__ __forceinline__ void level_fused_body(uint32_t depth, const SetDesc& 
     if (I) {
       fuse_sync<W>();
       RegRun<uint32_t, R> ix;
-      ix.load(I, p0, s, vi);
+      ix.load(I, p0, s, vi, 0);
       pass32(I, ix, vi);
     }
   }
@@ -1664,7 +1701,7 @@ __global__ void __launch_bounds__(kBlock, W == 4 ? 4 : 1) k_level_fused(uint32_t
                                                         uint32_t* idx1) {
   static_assert(W == 1 || W == kBlock / 64, "a wavefront or a block per node");
   // per node (W = 1: per wavefront) the select bins, then the staged node
-  __shared__ uint64_t stage[(kBlock / 64) * kFuseNode];
+  __shared__ __align__(16) uint64_t stage[(kBlock / 64) * kFuseNode];
   __shared__ uint32_t red[2 * W + 4];
   __shared__ uint32_t xs[W][4];
   const uint32_t wv = threadIdx.x >> 6;
@@ -1680,16 +1717,9 @@ __global__ void __launch_bounds__(kBlock, W == 4 ? 4 : 1) k_level_fused(uint32_t
   uint32_t* idx = S.track ? idx0 + S.idx_off : nullptr;
   uint32_t* b = (uint32_t*)(stage + (W == 1 ? wv * kFuseNode : 0));
   if (P->key16)
-  {
-    uint64_t st, sz;
-    node_span(S.n, depth, j, &st, &sz);
-    if (W == 4 && sz == (uint64_t)W * kFuseNode)  // (a wavefront per node: no gain, more registers)
-      level_fused_body<uint16_t, TRACK, W, W == 4>(depth, S, P, j, keys0 + S.key_off, idx, b, red, xs);
-    else
-      level_fused_body<uint16_t, TRACK, W, false>(depth, S, P, j, keys0 + S.key_off, idx, b, red, xs);
-  }
+    level_fused_body<uint16_t, TRACK, W>(depth, S, P, j, keys0 + S.key_off, idx, b, red, xs);
   else
-    level_fused_body<uint32_t, TRACK, W, false>(depth, S, P, j, keys0 + S.key_off, idx, b, red, xs);
+    level_fused_body<uint32_t, TRACK, W>(depth, S, P, j, keys0 + S.key_off, idx, b, red, xs);
 }
 
 // ---------------------------------------------------------------- paired levels
