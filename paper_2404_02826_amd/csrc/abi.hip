@@ -239,7 +239,7 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
     const SetIn& I = in[s];
     SetDesc& D = (*descs)[s];
     memset(&D, 0, sizeof(D));
-    D.fuse_depth = D.fuse_depth4 = kNoFuse;
+    D.fuse_depth = D.fuse_depth4 = D.fuse_depth16 = kNoFuse;
     D.pos = I.pos;
     D.out = (uint8_t*)I.out;
     D.perm = I.d_perm;
@@ -316,6 +316,10 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
       D.fuse_depth = fuse_depth_of(n, D.gl, D.tile_mode != 0, 2, kFuseNode);
       if (D.fuse_depth != kNoFuse)
         D.fuse_depth4 = fuse_depth_of(n, D.gl, D.tile_mode != 0, 4, 4 * kFuseNode);
+      if (D.fuse_depth4 != kNoFuse) {  // below the paired global levels only
+        const uint32_t f = fuse_depth_of(n, D.gl, D.tile_mode != 0, 6, 16 * kFuseNode);
+        if (f != kNoFuse && f >= 2 * D.npairs) D.fuse_depth16 = f;
+      }
       mm[s] = std::min<uint64_t>((n + 2047) / 2048, kMaxMinMaxBlocks);
       qz[s] = std::min<uint64_t>((n + 1023) / 1024, 16384);
       tl[s] = D.tile_mode ? (1ull << D.gl) : 0;
@@ -347,6 +351,9 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
         } else if (k - D.fuse_depth4 < 2u) {
           fam = k == D.fuse_depth4 ? kFamFused4 : kFamNone;
           if (k == D.fuse_depth4) bp->lv_fused4[k] = 1;
+        } else if (k - D.fuse_depth16 < 2u) {
+          fam = k == D.fuse_depth16 ? kFamFused16 : kFamNone;
+          if (k == D.fuse_depth16) bp->lv_fused16[k] = 1;
         } else if (kind == 2) {
           fam = kFamWave;
           bp->lv_wave[k] = 1;
@@ -358,11 +365,11 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
         else if (!pair_second(D, k))
           bp->lv_global[k] = bp->lv_single[k] = 1;
         lk[s].push_back(fam);
-        if (kind == kLevelGlobal && sh.chunks > 256) {
+        if (fam == kFamGlobal && sh.chunks > 256) {
           if (!pair_second(D, k)) bp->sel_wide[k] = 1;
           if (pair_first(D, k)) bp->pair_wide[k] = 1;  // the second level's selects use these chunks
         }
-        if (kind == kLevelGlobal) {  // by default staged only when every set's chunks are large
+        if (fam == kFamGlobal) {  // by default staged only when every set's chunks are large
           const uint32_t mode = in[0].prm.scatter_stage;
           if (!stage_seen[k]) bp->scat_stage[k] = mode != 2;
           stage_seen[k] = 1;
@@ -450,6 +457,7 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
     bp->o_wv[k] = fam_add(kFamWave, false, &bp->g_wv[k]);
     bp->o_fu[k] = fam_add(kFamFused, false, &bp->g_fu[k]);
     bp->o_f4[k] = fam_add(kFamFused4, false, &bp->g_f4[k]);
+    bp->o_f16[k] = fam_add(kFamFused16, false, &bp->g_f16[k]);
   }
   bp->pre_entries = pre->size();
   Carve c;
@@ -569,18 +577,25 @@ static std::string check_plan(const SetIn* in, uint32_t nsets) {
       if (kind < prev_kind) return where(s, k) + "level kinds are not global, then block, then wavefront";
       prev_kind = kind;
       if (sh.nodes != (1ull << k)) return where(s, k) + "node count";
-      const bool fused = k - D.fuse_depth < 2u || k - D.fuse_depth4 < 2u;
-      if (fused) {
-        const uint32_t f = k - D.fuse_depth < 2u ? D.fuse_depth : D.fuse_depth4;
-        const uint64_t cap = f == D.fuse_depth ? kFuseNode : 4 * kFuseNode;
+      if (level_fused(D, k)) {
+        const uint32_t f = k - D.fuse_depth < 2u    ? D.fuse_depth
+                           : k - D.fuse_depth4 < 2u ? D.fuse_depth4
+                                                    : D.fuse_depth16;
+        const uint64_t cap = f == D.fuse_depth ? kFuseNode : f == D.fuse_depth4 ? 4 * kFuseNode : 16 * kFuseNode;
         if (f + 1 >= D.gl) return where(s, k) + "fused pair reaches the leaf stage";
         if (((n + (1ull << f) - 1) >> f) > cap) return where(s, k) + "fused node above its capacity";
-        if (kind != kLevelWave) return where(s, k) + "fused level is not a wavefront level";
+        if (f != D.fuse_depth16 && kind != kLevelWave) return where(s, k) + "fused level is not a wavefront level";
+        if (f == D.fuse_depth16 && (D.fuse_depth4 == kNoFuse || f < 2 * D.npairs))
+          return where(s, k) + "16-wavefront pair without a block pair below it or among paired levels";
         if (D.fuse_depth != kNoFuse && D.fuse_depth4 != kNoFuse && D.fuse_depth4 + 2 > D.fuse_depth)
+          return where(s, k) + "fused pairs overlap";
+        if (D.fuse_depth4 != kNoFuse && D.fuse_depth16 != kNoFuse && D.fuse_depth16 + 2 > D.fuse_depth4)
           return where(s, k) + "fused pairs overlap";
         if (k == D.fuse_depth && (!bp.lv_fused[k] || share(bp.o_fu[k], bp.g_fu[k]) != sh.nodes))
           return where(s, k) + "fused pair's grid share differs from its nodes";
         if (k == D.fuse_depth4 && (!bp.lv_fused4[k] || share(bp.o_f4[k], bp.g_f4[k]) != sh.nodes))
+          return where(s, k) + "fused pair's grid share differs from its nodes";
+        if (k == D.fuse_depth16 && (!bp.lv_fused16[k] || share(bp.o_f16[k], bp.g_f16[k]) != sh.nodes))
           return where(s, k) + "fused pair's grid share differs from its nodes";
         continue;
       }

@@ -118,7 +118,7 @@ struct SetDesc {
   uint64_t cb_half;       // u32 entries of each of the set's two chunk-base regions (by depth parity)
   uint64_t lab_off;       // u64 offset into the side labels of paired levels
   uint32_t npairs;        // global levels 2p and 2p + 1 (p < npairs) run with one data movement
-  uint32_t pad_pairs;
+  uint32_t fuse_depth16;  // the pair of fuse_depth4 with a block of 16 wavefronts per node (at most 16 kFuseNode)
   uint64_t leaf_off;      // first leaf of the set in the batch's leaf arrays
   uint64_t part_off;      // first block of the set's range partials
   TreeGeom geom;
@@ -446,10 +446,13 @@ __device__ inline uint32_t* hist_level(const SetDesc& S, uint32_t depth, uint32_
 
 // The last levels above the tile stage of a set with a tile stage run in
 // in-place pairs with the node in registers: depths gl - 2 and gl - 1 when
-// their nodes have at most kFuseNode members (a wavefront per node), and
-// depths gl - 4 and gl - 3 when theirs have at most 4 kFuseNode (a block of
-// four wavefronts per node).  Each pair leaves the data of depth k + 2 in
-// the buffer of depth k, which has its parity.
+// their nodes have at most kFuseNode members (a wavefront per node), depths
+// gl - 4 and gl - 3 when theirs have at most 4 kFuseNode (a block of four
+// wavefronts per node), and depths gl - 6 and gl - 5 when theirs have at
+// most 16 kFuseNode (a block of 16 wavefronts per node; only below the
+// paired global levels, and whatever kind the two levels have otherwise).
+// Each pair leaves the data of depth k + 2 in the buffer of depth k, which
+// has its parity.
 constexpr uint64_t kFuseNode = 1024;
 constexpr uint32_t kNoFuse = 0x80000000u;  // depth - kNoFuse >= 2 for every depth (unsigned)
 __host__ __device__ inline uint32_t fuse_depth_of(uint64_t n, uint32_t gl, bool tile_mode,
@@ -457,6 +460,10 @@ __host__ __device__ inline uint32_t fuse_depth_of(uint64_t n, uint32_t gl, bool 
   if (!tile_mode || gl < back) return kNoFuse;
   const uint32_t k = gl - back;
   return ((n + (1ull << k) - 1) >> k) <= max_node ? k : kNoFuse;
+}
+// depth is a level of one of the set's fused pairs
+__host__ __device__ inline bool level_fused(const SetDesc& S, uint32_t depth) {
+  return depth - S.fuse_depth < 2u || depth - S.fuse_depth4 < 2u || depth - S.fuse_depth16 < 2u;
 }
 
 // Leaves per block of the leaf-aligned packing and unpacking kernels: at most
@@ -559,6 +566,7 @@ constexpr uint8_t kFamLocal = 2;   // a block per node
 constexpr uint8_t kFamWave = 3;    // a wavefront per node
 constexpr uint8_t kFamFused = 4;   // two levels, a wavefront per node
 constexpr uint8_t kFamFused4 = 5;  // two levels, a block per node
+constexpr uint8_t kFamFused16 = 6; // two levels, a block of 16 wavefronts per node
 
 struct BatchPlan {
   uint32_t nsets;
@@ -573,9 +581,9 @@ struct BatchPlan {
   // blocks, wavefront levels' nodes, fused pairs' nodes (a wavefront or a
   // block each); each array counts only the sets of its family at that depth
   uint64_t g_lv[kMaxDepth], g_nd[kMaxDepth], g_lc[kMaxDepth], g_wv[kMaxDepth];
-  uint64_t g_fu[kMaxDepth], g_f4[kMaxDepth];
+  uint64_t g_fu[kMaxDepth], g_f4[kMaxDepth], g_f16[kMaxDepth];
   uint64_t o_lv[kMaxDepth], o_nd[kMaxDepth], o_lc[kMaxDepth], o_wv[kMaxDepth];
-  uint64_t o_fu[kMaxDepth], o_f4[kMaxDepth];
+  uint64_t o_fu[kMaxDepth], o_f4[kMaxDepth], o_f16[kMaxDepth];
   uint8_t lv_local[kMaxDepth];   // some set handles level k one block per node
   uint8_t lv_global[kMaxDepth];  // some set handles level k with global histograms
   uint8_t sel_wide[kMaxDepth];   // some set's nodes have > 256 chunks at global level k
@@ -583,6 +591,7 @@ struct BatchPlan {
   uint8_t lv_wave[kMaxDepth];    // some set handles level k one wavefront per node
   uint8_t lv_fused[kMaxDepth];   // some set handles levels k, k + 1 fused, a wavefront per node
   uint8_t lv_fused4[kMaxDepth];  // some set handles levels k, k + 1 fused, a block per node
+  uint8_t lv_fused16[kMaxDepth]; // the same with a block of 16 wavefronts per node
   uint8_t lv_single[kMaxDepth];  // some set partitions global level k alone (k_scatter)
   uint8_t lv_pair[kMaxDepth];    // some set partitions global levels k, k + 1 together (k_pair.hip)
   uint8_t pair_wide[kMaxDepth];  // some paired set's nodes have > 256 chunks at level k

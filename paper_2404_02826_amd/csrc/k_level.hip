@@ -77,6 +77,7 @@ __global__ void __launch_bounds__(kBlock) k_pass_flags(uint32_t nsets, const Set
     if (P.status != BBX_OK) continue;
     for (uint32_t k = 0; k < S.gl && k < (uint32_t)kMaxDepth; ++k) {
       if (level_is_local(S.n, k)) break;  // local levels form a suffix
+      if (level_fused(S, k)) continue;
       const uint32_t np = digit_plan(P.G[k % S.dims]).npass;
       for (uint32_t p = 0; p + 1 < np && p < 4; ++p) atomicOr(&pass_need[k * 4 + p], 1u);
     }
@@ -819,7 +820,8 @@ __device__ void scatter_body(uint32_t depth, const SetDesc& S, DevParams* P, con
   const DigitPlan pn = digit_plan(P->G[dn]);
   // (not for wavefront levels, whose medians work on registers or on codes
   // minus the node minimum)
-  const bool fuse = depth + 1 < S.gl && pn.npass >= 2 && level_kind(n, depth + 1) != kLevelWave;
+  const bool fuse = depth + 1 < S.gl && pn.npass >= 2 && level_kind(n, depth + 1) != kLevelWave &&
+                    !level_fused(S, depth + 1);
   const uint32_t wn = pn.width[0], shn = pn.shift[0], maskn = (1u << wn) - 1;
   const bool cl = fuse && half > r, cr = fuse && (sz - half) > r;  // children that split again
   if (fuse)
@@ -970,7 +972,7 @@ __global__ void __launch_bounds__(kBlock) k_level_local(uint32_t depth, uint32_t
   const SetDesc& S = sets[c.s];
   DevParams* P = params + c.s;
   if (P->status != BBX_OK) return;
-  if (level_kind(S.n, depth) != kLevelBlock) return;
+  if (level_kind(S.n, depth) != kLevelBlock || level_fused(S, depth)) return;
   __shared__ uint32_t lhist[kLhWords];
   __shared__ uint32_t red[16];
   level_bufs(S, depth, src0, dst0, isrc0, idst0);
@@ -1180,7 +1182,7 @@ __device__ void level_wave_body(uint32_t depth, const SetDesc& S, DevParams* P, 
   KT* d0 = (KT*)dst + st;
   const uint32_t* is = isrc ? isrc + st : nullptr;
   uint32_t* id = idst ? idst + st : nullptr;
-  if (depth - S.fuse_depth < 2u || depth - S.fuse_depth4 < 2u) return;  // levels of k_level_fused
+  if (level_fused(S, depth)) return;  // levels of k_level_fused
   if (sz <= S.r) {  // leaf: copy through
     for (uint32_t p = threadIdx.x & 63; p < sz; p += 64) {
       d0[p] = s0[p];
@@ -1692,16 +1694,21 @@ __device__ __forceinline__ void level_fused_body(uint32_t depth, const SetDesc& 
 
 // Levels k and k + 1 of the sets whose fused depth for W wavefronts per node
 // is k.  W = 1: one wavefront per node of depth k, four nodes per block;
-// W = 4: one block per node.
+// W = 4 or 16: one block of W wavefronts per node.
+template <int W>
+constexpr int fused_threads() { return W == 1 ? kBlock : 64 * W; }
 template <bool TRACK, int W>
-__global__ void __launch_bounds__(kBlock, W == 4 ? 4 : 1) k_level_fused(uint32_t depth, uint32_t nsets,
+__global__ void __launch_bounds__(fused_threads<W>(), W == 4 ? 4 : 1) k_level_fused(uint32_t depth, uint32_t nsets,
                                                         const uint64_t* pre, const SetDesc* sets,
                                                         DevParams* params, uint8_t* keys0,
                                                         uint8_t* keys1, uint32_t* idx0,
                                                         uint32_t* idx1) {
-  static_assert(W == 1 || W == kBlock / 64, "a wavefront or a block per node");
-  // per node (W = 1: per wavefront) the select bins, then the staged node
-  __shared__ __align__(16) uint64_t stage[(kBlock / 64) * kFuseNode];
+  static_assert(W == 1 || W == 4 || W == 16, "a wavefront or a block of 4 or 16 per node");
+  // per node (W = 1: per wavefront) the select bins, then the staged node:
+  // three 16-bit arrays of W kFuseNode members (3/4 of a u64 per member)
+  constexpr uint32_t kNodeWords = 3 * W * (uint32_t)kFuseNode / 4;
+  constexpr uint32_t kNodes = W == 1 ? kBlock / 64 : 1;
+  __shared__ __align__(16) uint64_t stage[kNodes * kNodeWords];
   __shared__ uint32_t red[2 * W + 4];
   __shared__ uint32_t xs[W][4];
   const uint32_t wv = threadIdx.x >> 6;
@@ -1711,11 +1718,11 @@ __global__ void __launch_bounds__(kBlock, W == 4 ? 4 : 1) k_level_fused(uint32_t
   const SetDesc& S = sets[s];
   DevParams* P = params + s;
   if (P->status != BBX_OK) return;
-  if ((W == 1 ? S.fuse_depth : S.fuse_depth4) != depth) return;
+  if ((W == 1 ? S.fuse_depth : W == 4 ? S.fuse_depth4 : S.fuse_depth16) != depth) return;
   const uint64_t j = gn - pre[s];
   level_bufs(S, depth, keys0, keys1, idx0, idx1);  // in place: the buffer holding the codes
   uint32_t* idx = S.track ? idx0 + S.idx_off : nullptr;
-  uint32_t* b = (uint32_t*)(stage + (W == 1 ? wv * kFuseNode : 0));
+  uint32_t* b = (uint32_t*)(stage + (W == 1 ? wv * kNodeWords : 0));
   if (P->key16)
     level_fused_body<uint16_t, TRACK, W>(depth, S, P, j, keys0 + S.key_off, idx, b, red, xs);
   else
@@ -1998,7 +2005,8 @@ __device__ void scatter4_body(uint32_t depth, const SetDesc& S, DevParams* P, co
   const uint32_t gsz4[4] = {hL, sL - hL, hR, sR - hR};
   // level k + 2's first-digit bins per grandchild (when it runs a mid pass)
   const DigitPlan p2 = digit_plan(P->G[d2]);
-  const bool fuse = depth + 2 < S.gl && p2.npass >= 2 && level_kind(n, depth + 2) != kLevelWave;
+  const bool fuse = depth + 2 < S.gl && p2.npass >= 2 && level_kind(n, depth + 2) != kLevelWave &&
+                    !level_fused(S, depth + 2);
   const uint32_t sh2 = p2.shift[0], mask2 = (1u << p2.width[0]) - 1;
   bool cg[4];
 #pragma unroll
@@ -2286,6 +2294,10 @@ hipError_t launch_levels(const BatchPlan& bp, const Ws& w, hipStream_t s) {
       BBX_LAUNCH("level_fused4", (bp.track ? k_level_fused<true, 4> : k_level_fused<false, 4>),
                  bp.g_f4[k], kBlock, 0, s, k, bp.nsets, w.pre + bp.o_f4[k], w.sets, w.params, K0,
                  K1, I0, I1);
+    if (bp.lv_fused16[k])
+      BBX_LAUNCH("level_fused16", (bp.track ? k_level_fused<true, 16> : k_level_fused<false, 16>),
+                 bp.g_f16[k], fused_threads<16>(), 0, s, k, bp.nsets, w.pre + bp.o_f16[k], w.sets,
+                 w.params, K0, K1, I0, I1);
     if (!bp.lv_global[k]) continue;
     // mid passes: pass 0 was built by the quantize pass (depth 0) or by the
     // previous scatter

@@ -335,7 +335,7 @@ __global__ void __launch_bounds__(kBlock) k_quantize(uint32_t nsets, const uint6
   // with more than one digit pass (the same condition the level kernels use)
   __shared__ uint32_t lh[kHistBins];
   const DigitPlan pl = digit_plan(P->G[0]);
-  const bool root = !S.split && !level_is_local(S.n, 0) && pl.npass >= 2 && S.n > S.r;
+  const bool root = !S.split && !level_is_local(S.n, 0) && !level_fused(S, 0) && pl.npass >= 2 && S.n > S.r;
   const uint32_t hsh = pl.shift[0], hmask = (1u << pl.width[0]) - 1;
   if (root) {
     lh[threadIdx.x] = 0;
