@@ -1249,7 +1249,8 @@ __device__ inline void fuse_sync() {
 }
 
 // Per-wavefront totals t[0..K) (uniform within each wavefront) -> the sum
-// over the node's lower wavefronts (member order is wavefront-major).
+// over the node's lower wavefronts (member order is wavefront-major).  Each
+// exchange of a node has an xs array of its own (nothing is reused).
 template <int W, int K>
 __device__ inline void fuse_bases(const uint32_t (&t)[K], uint32_t (&b)[K], uint32_t (*xs)[4]) {
   static_assert(K <= 4, "four totals per exchange");
@@ -1265,17 +1266,21 @@ __device__ inline void fuse_bases(const uint32_t (&t)[K], uint32_t (&b)[K], uint
   for (int w = 0; w < W; ++w)
 #pragma unroll
     for (int k = 0; k < K; ++k) b[k] += (uint32_t)w < wv ? xs[w][k] : 0u;
-  __syncthreads();  // xs is reused by the next exchange
 }
 
 // Radix select over the node's codes held in registers, for one or two
 // member groups at once: group g's member of rank rank[g] among the members
 // flagged in the lanes' bit masks m[g] (bit i: the lane's i-th member),
 // ordered by (code, member order).  Widest digit first, at most 8 bits per
-// pass, over the code range of all flagged members; group g counts into
-// bins [256 g, 256 g + 256).  Returns each group's code in v[g] and, in
-// rank[g], how many members equal to it precede it.  The bins are zero on
-// entry and on return (the scanning wavefront clears what it read).
+// pass, over the code range of all flagged members; pass p counts group g
+// into bins [512 (p & 1) + 256 g, ... + 256) and the scanning wavefront
+// posts its finds in red[2 W + 4 (p & 1) ...], so that a pass needs no
+// barrier after its reads: the next pass uses the other half, and the one
+// after it comes after the next pass's barriers.  Returns each group's code
+// in v[g] and, in rank[g], how many members equal to it precede it.  The
+// bins are zero on entry and on return (the scanning wavefront clears what
+// it read); red[0, 2 W) (the code range) is rewritten only after a later
+// barrier of the caller.
 template <int R, int W, int NG, typename Q>
 __device__ void reg_select(const Q& q, const uint32_t (&m)[NG], uint32_t (&rank)[NG],
                            uint32_t* bins, uint32_t* red, uint32_t (&v)[NG]) {
@@ -1291,24 +1296,26 @@ __device__ void reg_select(const Q& q, const uint32_t (&m)[NG], uint32_t (&rank)
     mn = red[0], mx = red[W];
 #pragma unroll
     for (int w = 1; w < W; ++w) mn = umin32(mn, red[w]), mx = umax32(mx, red[W + w]);
-    __syncthreads();
   }
   const uint32_t Gs = mx > mn ? bitlen32(mx - mn) : 0u;
   uint32_t prefix[NG];
 #pragma unroll
   for (int g = 0; g < NG; ++g) prefix[g] = 0;
-  uint32_t used = 0;
+  uint32_t used = 0, half = 0;
   while (used < Gs) {
     const uint32_t w = Gs - used < 8 ? Gs - used : 8;
     const uint32_t hs = Gs - used;
     used += w;
+    uint32_t* const bn = bins + 512 * half;
+    uint32_t* const rd = red + 2 * W + 4 * half;
+    half ^= 1;
     const uint32_t sh = Gs - used, mask = (1u << w) - 1;
     if (hs == Gs) {  // first pass: every flagged member is a candidate
 #pragma unroll
       for (int i = 0; i < R; ++i) {
         const uint32_t k = q[i] - mn;
         const uint32_t g0 = NG == 2 && ((m[NG - 1] >> i) & 1u) ? 256u : 0u;
-        if ((all >> i) & 1u) atomicAdd(&bins[g0 + ((k >> sh) & mask)], 1u);
+        if ((all >> i) & 1u) atomicAdd(&bn[g0 + ((k >> sh) & mask)], 1u);
       }
     } else {
 #pragma unroll
@@ -1317,7 +1324,7 @@ __device__ void reg_select(const Q& q, const uint32_t (&m)[NG], uint32_t (&rank)
         const bool g1 = NG == 2 && ((m[NG - 1] >> i) & 1u);
         const uint32_t pre = g1 ? prefix[NG - 1] : prefix[0];
         if (((all >> i) & 1u) && (k >> hs) == pre)
-          atomicAdd(&bins[(g1 ? 256u : 0u) + ((k >> sh) & mask)], 1u);
+          atomicAdd(&bn[(g1 ? 256u : 0u) + ((k >> sh) & mask)], 1u);
       }
     }
     fuse_sync<W>();
@@ -1327,14 +1334,14 @@ __device__ void reg_select(const Q& q, const uint32_t (&m)[NG], uint32_t (&rank)
       for (int g = 0; g < NG; ++g)
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-          c[g][k] = bins[256 * g + lane * 4 + k];
+          c[g][k] = bn[256 * g + lane * 4 + k];
           mine += c[g][k] << (16 * g);  // a group's counts stay below 2^16
         }
 #pragma unroll
       for (int g = 0; g < NG; ++g)
 #pragma unroll
         for (int k = 0; k < 4; ++k)
-          if (c[g][k]) bins[256 * g + lane * 4 + k] = 0;
+          if (c[g][k]) bn[256 * g + lane * 4 + k] = 0;
       const uint32_t cum = wave_incl(mine) - mine;
 #pragma unroll
       for (int g = 0; g < NG; ++g) {
@@ -1353,7 +1360,7 @@ __device__ void reg_select(const Q& q, const uint32_t (&m)[NG], uint32_t (&rank)
           prefix[g] = (prefix[g] << w) | fb;
           rank[g] = fr;
         } else if (lane == 0) {
-          red[2 * W + 2 * g] = fb, red[2 * W + 2 * g + 1] = fr;
+          rd[2 * g] = fb, rd[2 * g + 1] = fr;
         }
       }
     }
@@ -1361,11 +1368,10 @@ __device__ void reg_select(const Q& q, const uint32_t (&m)[NG], uint32_t (&rank)
       __syncthreads();
 #pragma unroll
       for (int g = 0; g < NG; ++g) {
-        prefix[g] = (prefix[g] << w) | red[2 * W + 2 * g];
-        rank[g] = red[2 * W + 2 * g + 1];
+        prefix[g] = (prefix[g] << w) | rd[2 * g];
+        rank[g] = rd[2 * g + 1];
       }
     }
-    fuse_sync<W>();  // bins cleared and red read before the next pass writes them
   }
 #pragma unroll
   for (int g = 0; g < NG; ++g) v[g] = mn + prefix[g];
@@ -1492,7 +1498,7 @@ __device__ __forceinline__ void reg_fence(RegRun<T, R>& q) {
 template <typename KT, bool TRACK, int W>
 __device__ __forceinline__ void level_fused_body(uint32_t depth, const SetDesc& S, DevParams* P,
                                                  uint64_t j, uint8_t* keys, uint32_t* idx,
-                                                 uint32_t* lds, uint32_t* red, uint32_t (*xs)[4]) {
+                                                 uint32_t* lds, uint32_t* red, uint32_t (*xs)[W][4]) {
   constexpr int R = kFuseRows;
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t wv = W == 1 ? 0u : (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -1522,7 +1528,7 @@ __device__ __forceinline__ void level_fused_body(uint32_t depth, const SetDesc& 
   // between phases: the codes are taken up again from their packed
   // registers instead of holding unpacked copies across the phases
   auto fence = [&]() { reg_fence(q0), reg_fence(q1); };
-  for (uint32_t k = W == 1 ? lane : threadIdx.x; k < 512; k += 64u * W) lds[k] = 0;  // select bins
+  for (uint32_t k = W == 1 ? lane : threadIdx.x; k < 1024; k += 64u * W) lds[k] = 0;  // select bins
   // every load of the node has returned before any wavefront of the node
   // passes its first barrier (the stores come after it)
   __builtin_amdgcn_s_waitcnt(0);
@@ -1543,7 +1549,7 @@ __device__ __forceinline__ void level_fused_body(uint32_t depth, const SetDesc& 
   for (int i = 0; i < R; ++i) ne += q0[i] == v ? 1u : 0u;
   uint32_t te[1], be[1];
   uint32_t erun = wave_excl(ne, &te[0]);
-  fuse_bases<W, 1>(te, be, xs);
+  fuse_bases<W, 1>(te, be, xs[0]);
   erun += be[0];
   uint32_t left = 0;
 #pragma unroll
@@ -1577,7 +1583,7 @@ __device__ __forceinline__ void level_fused_body(uint32_t depth, const SetDesc& 
   uint32_t run2 = wave_excl(ne2, &t2);
   {
     const uint32_t tt[2] = {t2 & 0xffffu, t2 >> 16};
-    fuse_bases<W, 2>(tt, b2, xs);
+    fuse_bases<W, 2>(tt, b2, xs[1]);
   }
   run2 += b2[0] | (b2[1] << 16);
   // grandchild of each member: g = 0 LL [0, hL), 1 LR [hL, sL), 2 RL
@@ -1605,7 +1611,7 @@ __device__ __forceinline__ void level_fused_body(uint32_t depth, const SetDesc& 
   const uint32_t rA = wave_excl((uint32_t)cnt, &tA), rB = wave_excl((uint32_t)(cnt >> 32), &tB);
   {
     const uint32_t tt[4] = {tA & 0xffffu, tA >> 16, tB & 0xffffu, tB >> 16};
-    fuse_bases<W, 4>(tt, b4, xs);
+    fuse_bases<W, 4>(tt, b4, xs[2]);
   }
   // C member slots: every grandchild must count its own size (the last also
   // the members past the node's end), then each member's slot lies inside
@@ -1709,8 +1715,8 @@ __global__ void __launch_bounds__(fused_threads<W>(), W == 4 ? 4 : 1) k_level_fu
   constexpr uint32_t kNodeWords = 3 * W * (uint32_t)kFuseNode / 4;
   constexpr uint32_t kNodes = W == 1 ? kBlock / 64 : 1;
   __shared__ __align__(16) uint64_t stage[kNodes * kNodeWords];
-  __shared__ uint32_t red[2 * W + 4];
-  __shared__ uint32_t xs[W][4];
+  __shared__ uint32_t red[2 * W + 8];
+  __shared__ uint32_t xs[3][W][4];
   const uint32_t wv = threadIdx.x >> 6;
   const uint64_t gn = W == 1 ? (uint64_t)blockIdx.x * (kBlock / 64) + wv : blockIdx.x;
   if (gn >= pre[nsets]) return;  // whole wavefront (W = 1) or block
