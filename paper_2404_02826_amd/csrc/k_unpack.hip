@@ -102,6 +102,7 @@ __global__ void __launch_bounds__(kBlock) k_dec_meta(uint64_t n_leaves, uint32_t
 
 constexpr uint32_t kLeafStage = 256;     // leaves per block (leaves_per_block)
 constexpr uint32_t kUnpackWords = 1534;  // staged payload words per block (+2 zero words: 12 KB)
+constexpr uint32_t kMapGroups = 520;     // 4-slot groups of a block's leaf map (2,048 slots and the ends)
 
 // Leaf-aligned decoding: a block takes leaves_per_block(r) consecutive
 // leaves, stages their records, bit offsets and payload words with coalesced
@@ -121,7 +122,7 @@ __device__ void unpack_body(uint64_t n, uint32_t layout, uint32_t r, double w,
                             const double* origin, const uint32_t* G, uint64_t nl,
                             const LeafRec* leaves, const uint64_t* off, const uint64_t* pay,
                             uint64_t pay_words, uint64_t pbits, T* out, DevParams* P,
-                            LeafRec* s_rec, uint64_t* s_off, uint64_t* s_pay) {
+                            LeafRec* s_rec, uint64_t* s_off, uint64_t* s_pay, uint16_t* s_map) {
   constexpr uint32_t dims = DIMS;
   const uint32_t lpb = leaves_per_block(r);
   const uint64_t L0 = (uint64_t)blockIdx.x * lpb;
@@ -133,6 +134,17 @@ __device__ void unpack_body(uint64_t n, uint32_t layout, uint32_t r, double w,
   }
   const uint64_t bo1 = L0 + nlb < nl ? off[L0 + nlb] : pbits;
   __syncthreads();
+  // leaf map: the leaf holding the first slot of each 4-aligned group of
+  // slots (each leaf writes the groups that start inside it), when the
+  // block's slots fit the map
+  const uint64_t mbase = (uint64_t)s_rec[0].start & ~3ull;
+  const uint64_t mend = (uint64_t)s_rec[nlb - 1].start + s_rec[nlb - 1].size;
+  const bool mapped = mend - mbase <= 4ull * kMapGroups;
+  if (mapped)
+    for (uint32_t t = threadIdx.x; t < nlb; t += kBlock) {
+      const uint64_t st = s_rec[t].start - mbase, en = st + s_rec[t].size;
+      for (uint64_t g = (st + 3) >> 2; 4 * g < en; ++g) s_map[g] = (uint16_t)t;
+    }
   const uint64_t bo0 = s_off[0];
   const uint64_t w0 = bo0 / 64, w1 = bo1 > bo0 ? (bo1 + 63) / 64 : w0;
   const bool staged = w1 - w0 <= kUnpackWords;
@@ -163,12 +175,16 @@ __device__ void unpack_body(uint64_t n, uint32_t layout, uint32_t r, double w,
     } o;
     if (simple && full) {
       uint32_t a = 0, z = nlb - 1;  // last staged leaf starting at or before gs
-      while (a < z) {
-        const uint32_t mid = (a + z + 1) >> 1;
-        if (s_rec[mid].start <= gs)
-          a = mid;
-        else
-          z = mid - 1;
+      if (mapped) {
+        a = s_map[(gs - mbase) >> 2];
+      } else {
+        while (a < z) {
+          const uint32_t mid = (a + z + 1) >> 1;
+          if (s_rec[mid].start <= gs)
+            a = mid;
+          else
+            z = mid - 1;
+        }
       }
 #pragma unroll
       for (uint32_t k = 0; k < 4; ++k) {
@@ -288,15 +304,16 @@ __global__ void __launch_bounds__(kBlock) k_unpack(uint64_t n, uint32_t dims, ui
   __shared__ LeafRec s_rec[kLeafStage];
   __shared__ uint64_t s_off[kLeafStage];
   __shared__ uint64_t s_pay[kUnpackWords + 2];
+  __shared__ uint16_t s_map[kMapGroups];
   const double origin[3] = {o0, o1, o2};
   const uint32_t G[3] = {G0, G1, G2};
   const uint64_t* pay = (const uint64_t*)(stream + kHeaderBytes + ((meta_bits + 63) / 64) * 8);
   if (dims == 3)
     unpack_body<T, 3>(n, layout, r, w, origin, G, n_leaves, leaves, off, pay, (pay_bits + 63) / 64,
-                      pay_bits, out, P, s_rec, s_off, s_pay);
+                      pay_bits, out, P, s_rec, s_off, s_pay, s_map);
   else
     unpack_body<T, 2>(n, layout, r, w, origin, G, n_leaves, leaves, off, pay, (pay_bits + 63) / 64,
-                      pay_bits, out, P, s_rec, s_off, s_pay);
+                      pay_bits, out, P, s_rec, s_off, s_pay, s_map);
 }
 
 // Starts a decode: clears the status and checks that the stream's own
