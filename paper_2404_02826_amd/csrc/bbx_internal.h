@@ -449,8 +449,9 @@ __device__ inline uint32_t* hist_level(const SetDesc& S, uint32_t depth, uint32_
 // their nodes have at most kFuseNode members (a wavefront per node), depths
 // gl - 4 and gl - 3 when theirs have at most 4 kFuseNode (a block of four
 // wavefronts per node), and depths gl - 6 and gl - 5 when theirs have at
-// most 16 kFuseNode (a block of 16 wavefronts per node; only below the
-// paired global levels, and whatever kind the two levels have otherwise).
+// most 16 kFuseNode and both would otherwise run block-local (a block of 16
+// wavefronts per node: one per CU, which pays off over the block-local
+// levels of large sets but not over the global levels of small ones).
 // Each pair leaves the data of depth k + 2 in the buffer of depth k, which
 // has its parity.
 constexpr uint64_t kFuseNode = 1024;

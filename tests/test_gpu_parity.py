@@ -438,6 +438,20 @@ def test_full_size_cosmology_1_in_4_oracle(orc, bbx):
     check_parity(orc, bbx, pts, 1e-4, "rel", 32, want_perm=False, scatter_stage=1)
 
 
+# Sets just above 2^25 particles: depths 12 and 13 (block-local kind) run as
+# one 16-wavefront fused pair over nodes of about 8,200 members, half the
+# pair's capacity, so every wavefront's lanes past its node's end hold the
+# top code of their axis; 16-bit codes with source indices, then 32-bit
+# codes (G = 20).  Byte parity with the oracle.
+@pytest.mark.timeout(1200)
+@pytest.mark.parametrize("kind,xi,seed", [("cosmology", 1e-4, 5), ("uniform", 1e-6, 6)])
+def test_fused16_ragged_nodes(orc, bbx, kind, xi, seed):
+    n = (1 << 25) + 12345
+    _say(f"{kind} n={n} xi={xi}: oracle")
+    pts = gen(kind, n, seed=seed)
+    check_parity(orc, bbx, pts, xi, "rel", 32)
+
+
 # Few blocks per global level: every block's chunk spans many 2048-member
 # groups (up to the whole node at level_blocks = 1), with a partial last
 # group, so the multi-group loop of the global partition (next-group
