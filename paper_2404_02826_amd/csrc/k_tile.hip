@@ -368,8 +368,8 @@ __device__ void tile_body(WaveTile<TILE, KL, TRACK>& sm, uint64_t j, uint32_t K0
             for (int k = 0; k < E; ++k) pre[k] = sm.npre[ni[k]];
 #pragma unroll
             for (int k = 0; k < E; ++k)
-              if (inner[k] && (q[k] >> hs) == pre[k])
-                atomicAdd(&sm.H[(ni[k] << w) + ((q[k] >> sh) & mask)], 1u);
+              atomicAdd(&sm.H[(ni[k] << w) + ((q[k] >> sh) & mask)],
+                        inner[k] && (q[k] >> hs) == pre[k] ? 1u : 0u);  // no branch: + 0
           }
           wave_sync();
           if (N <= 8) {
@@ -461,7 +461,10 @@ __device__ void tile_body(WaveTile<TILE, KL, TRACK>& sm, uint64_t j, uint32_t K0
         const bool lt = fl[k] & 1u, eq = (fl[k] >> 16) & 1u;
         const bool left = lt || (eq && Eq < jeq);
         const uint32_t dest = inner[k] ? ns + (left ? lb : (nz >> 1) + (p - ns) - lb) : p;
-        if (p < s0 && dest < s0) sm.Pm[cur ^ 1][dest] = (uint16_t)slot[k];
+        // every position stores, without a branch: a position past the
+        // node's end (or in a leaf) to itself, a member of a split node to
+        // its slot, which is below s0 when the counts are right
+        sm.Pm[cur ^ 1][dest & (TILE - 1)] = (uint16_t)slot[k];
         ex += fl[k];
         if (!POW2) {  // follow this position into its child of the next level
           const uint32_t half = nz >> 1;
