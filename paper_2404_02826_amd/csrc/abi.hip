@@ -316,11 +316,9 @@ static void plan_batch(const SetIn* in, uint32_t nsets, BatchPlan* bp, std::vect
       D.fuse_depth = fuse_depth_of(n, D.gl, D.tile_mode != 0, 2, kFuseNode);
       if (D.fuse_depth != kNoFuse)
         D.fuse_depth4 = fuse_depth_of(n, D.gl, D.tile_mode != 0, 4, 4 * kFuseNode);
-      if (D.fuse_depth4 != kNoFuse) {  // in place of two block-local levels only
+      if (D.fuse_depth4 != kNoFuse) {  // only over levels of many nodes
         const uint32_t f = fuse_depth_of(n, D.gl, D.tile_mode != 0, 6, 16 * kFuseNode);
-        if (f != kNoFuse && f >= 2 * D.npairs && level_kind(n, f) == kLevelBlock &&
-            level_kind(n, f + 1) == kLevelBlock)
-          D.fuse_depth16 = f;
+        if (f != kNoFuse && f >= 2 * D.npairs && (1ull << f) >= kFuse16Nodes) D.fuse_depth16 = f;
       }
       mm[s] = std::min<uint64_t>((n + 2047) / 2048, kMaxMinMaxBlocks);
       qz[s] = std::min<uint64_t>((n + 1023) / 1024, 16384);
@@ -587,7 +585,7 @@ static std::string check_plan(const SetIn* in, uint32_t nsets) {
         if (f + 1 >= D.gl) return where(s, k) + "fused pair reaches the leaf stage";
         if (((n + (1ull << f) - 1) >> f) > cap) return where(s, k) + "fused node above its capacity";
         if (f != D.fuse_depth16 && kind != kLevelWave) return where(s, k) + "fused level is not a wavefront level";
-        if (f == D.fuse_depth16 && kind != kLevelBlock) return where(s, k) + "16-wavefront pair on a level that is not block-local";
+        if (f == D.fuse_depth16 && (1ull << f) < kFuse16Nodes) return where(s, k) + "16-wavefront pair over too few nodes";
         if (f == D.fuse_depth16 && (D.fuse_depth4 == kNoFuse || f < 2 * D.npairs))
           return where(s, k) + "16-wavefront pair without a block pair below it or among paired levels";
         if (D.fuse_depth != kNoFuse && D.fuse_depth4 != kNoFuse && D.fuse_depth4 + 2 > D.fuse_depth)

@@ -449,13 +449,14 @@ __device__ inline uint32_t* hist_level(const SetDesc& S, uint32_t depth, uint32_
 // their nodes have at most kFuseNode members (a wavefront per node), depths
 // gl - 4 and gl - 3 when theirs have at most 4 kFuseNode (a block of four
 // wavefronts per node), and depths gl - 6 and gl - 5 when theirs have at
-// most 16 kFuseNode and both would otherwise run block-local (a block of 16
-// wavefronts per node: one per CU, which pays off over the block-local
-// levels of large sets but not over the global levels of small ones).
+// most 16 kFuseNode and there are at least kFuse16Nodes of them (a block of
+// 16 wavefronts per node, one per CU: it pays off over the levels of large
+// sets, not over the few ragged nodes of small ones).
 // Each pair leaves the data of depth k + 2 in the buffer of depth k, which
 // has its parity.
 constexpr uint64_t kFuseNode = 1024;
 constexpr uint32_t kNoFuse = 0x80000000u;  // depth - kNoFuse >= 2 for every depth (unsigned)
+constexpr uint64_t kFuse16Nodes = 1024;     // fewest nodes of a 16-wavefront pair's first level
 __host__ __device__ inline uint32_t fuse_depth_of(uint64_t n, uint32_t gl, bool tile_mode,
                                                   uint32_t back, uint64_t max_node) {
   if (!tile_mode || gl < back) return kNoFuse;
