@@ -360,8 +360,8 @@ __device__ void tile_body(WaveTile<TILE, KL, TRACK>& sm, uint64_t j, uint32_t K0
           const uint32_t nb = 1u << w, mask = nb - 1;
           if (pass == 0) {
 #pragma unroll
-            for (int k = 0; k < E; ++k)
-              if (inner[k]) atomicAdd(&sm.H[(ni[k] << w) + ((q[k] >> sh) & mask)], 1u);
+            for (int k = 0; k < E; ++k)  // no branch: + 0 outside split nodes
+              atomicAdd(&sm.H[(ni[k] << w) + ((q[k] >> sh) & mask)], inner[k] ? 1u : 0u);
           } else {
             uint32_t pre[E];
 #pragma unroll
@@ -381,32 +381,36 @@ __device__ void tile_body(WaveTile<TILE, KL, TRACK>& sm, uint64_t j, uint32_t K0
             const uint32_t lp = T > 64 ? bitlen32(T) - 7 : 0u;  // T is a power of two
             const uint32_t per = 1u << lp;                       // bins per lane, <= TILE / 64
             const uint32_t b0 = lane << lp;
+            // (b < 64 per <= TILE; bins at or past T were never counted,
+            // and leaves' bins only ever got zeros, so every lane reads and
+            // clears its bins and at most one lane per node finds the rank,
+            // without per-lane branches)
             uint32_t c[TILE / 64];
             uint32_t mine = 0;
 #pragma unroll
             for (int k = 0; k < TILE / 64; ++k) {
               const uint32_t b = b0 + k;
-              c[k] = 0;
-              if ((uint32_t)k < per && b < T) {
-                c[k] = sm.H[b];
-                if (c[k]) sm.H[b] = 0;
-              }
+              c[k] = (uint32_t)k < per ? sm.H[b] : 0u;
+              if ((uint32_t)k < per) sm.H[b] = 0;
               mine += c[k];
             }
             const uint32_t ex = wave_incl(mine) - mine;
             const uint32_t i = b0 < T ? b0 >> w : 0u;
             uint32_t cum = ex - (uint32_t)__shfl((int)ex, (int)((i << w) >> lp));
-            if (b0 < T && sm.nsz[i] > r) {
-              const uint32_t rank = sm.nrank[i];
-              const uint32_t pr = sm.npre[i];
+            const uint32_t rank = sm.nrank[i];
+            bool hit = false;
+            uint32_t fb = 0, fr = 0;
 #pragma unroll
-              for (int k = 0; k < TILE / 64; ++k) {
-                if ((uint32_t)k < per && cum <= rank && rank < cum + c[k]) {
-                  sm.npre[i] = (KL)((pr << w) | ((b0 + k) & (nb - 1)));
-                  sm.nrank[i] = (uint16_t)(rank - cum);
-                }
-                cum += c[k];
-              }
+            for (int k = 0; k < TILE / 64; ++k) {
+              const bool h = (uint32_t)k < per && cum <= rank && rank < cum + c[k];
+              fb = h ? b0 + k : fb;
+              fr = h ? rank - cum : fr;
+              hit |= h;
+              cum += c[k];
+            }
+            if (hit) {
+              sm.npre[i] = (KL)(((uint32_t)sm.npre[i] << w) | (fb & (nb - 1)));
+              sm.nrank[i] = (uint16_t)fr;
             }
           } else {  // many small nodes: one lane per node scans its few bins
             for (uint32_t i = lane; i < N; i += 64) {
