@@ -44,6 +44,16 @@ __device__ inline void gargmin(uint64_t& dist, uint32_t& pos, uint32_t gs) {
     if (d2 < dist || (d2 == dist && p2 < pos)) dist = d2, pos = p2;
   }
 }
+// the same over aligned groups of 8 lanes by DPP moves: neighbours, then
+// pairs within the quad, then the group's other quad through the half-row
+// mirror (lane i of a half-row reads lane 7 - i)
+template <typename F>
+__device__ __forceinline__ uint32_t g8_reduce(uint32_t v, F&& op) {
+  v = op(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0xB1, 0xf, 0xf, false));   // quad_perm 1,0,3,2
+  v = op(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x4E, 0xf, 0xf, false));   // quad_perm 2,3,0,1
+  v = op(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x141, 0xf, 0xf, false));  // row_half_mirror
+  return v;
+}
 __device__ inline uint32_t wmin_u32(uint32_t v) { return gmin_u32(v, 64); }
 __device__ inline uint32_t wmax_u32(uint32_t v) { return gmax_u32(v, 64); }
 __device__ inline void wargmin(uint64_t& dist, uint32_t& pos) { gargmin(dist, pos, 64); }
@@ -83,12 +93,14 @@ __device__ inline uint32_t leaf_fold(uint32_t s, uint32_t r) { return s <= r ? s
 // when every code span is below 2^14).  With M > 0 every leaf has at most
 // M * gs members: each lane reads its members' codes once into registers
 // (fixed trip counts); M = 0 walks the members from LDS in each pass.
-template <int TILE, typename KL, bool TRACK, typename DT, int M>
-__device__ void tile_bitboxes(WaveTile<TILE, KL, TRACK>& sm, int cur, uint32_t nl, uint32_t gs, uint32_t dims,
+template <int TILE, typename KL, bool TRACK, typename DT, int M, int GS = 0>
+__device__ void tile_bitboxes(WaveTile<TILE, KL, TRACK>& sm, int cur, uint32_t nl, uint32_t gs_rt, uint32_t dims,
                               uint32_t t0, uint32_t t1, uint32_t t2, uint64_t tst, uint64_t first_leaf,
                               uint64_t n_leaves, DevParams* P, LeafRec* leaves,
                               uint64_t* leaf_bits, uint32_t rule) {
   constexpr int MR = M > 0 ? M : 1;
+  static_assert(GS == 0 || GS == 8, "groups of 8 lanes or of a run-time size");
+  const uint32_t gs = GS ? (uint32_t)GS : gs_rt;  // GS: the group size, fixed at compile time
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t lpw = 64 / gs;
   const uint32_t sub = lane & (gs - 1);
@@ -128,8 +140,13 @@ __device__ void tile_bitboxes(WaveTile<TILE, KL, TRACK>& sm, int cur, uint32_t n
 #pragma unroll
     for (uint32_t d = 0; d < 3; ++d) {
       if (d >= dims) break;
-      mn[d] = gmin_u32(mn[d], gs);
-      mx[d] = gmax_u32(mx[d], gs);
+      if constexpr (GS == 8) {
+        mn[d] = g8_reduce(mn[d], [](uint32_t a, uint32_t b) { return umin32(a, b); });
+        mx[d] = g8_reduce(mx[d], [](uint32_t a, uint32_t b) { return umax32(a, b); });
+      } else {
+        mn[d] = gmin_u32(mn[d], gs);
+        mx[d] = gmax_u32(mx[d], gs);
+      }
       C[d] = (DT)mn[d] + (DT)mx[d];
     }
     DT best = (DT)~(DT)0;
@@ -175,14 +192,34 @@ __device__ void tile_bitboxes(WaveTile<TILE, KL, TRACK>& sm, int cur, uint32_t n
         if (dist < best) best = dist, bpos = t;  // t increases: ties keep the first
       }
     }
-    for (uint32_t o = gs >> 1; o > 0; o >>= 1) {
-      const DT d2 = __shfl_xor(best, (int)o);
-      const uint32_t p2 = __shfl_xor(bpos, (int)o);
-      if (d2 < best || (d2 == best && p2 < bpos)) best = d2, bpos = p2;
+    if constexpr (GS == 8 && sizeof(DT) == 4) {
+      auto take = [&](auto ctrl_tag) __attribute__((always_inline)) {
+        constexpr int ctrl = decltype(ctrl_tag)::value;
+        const DT d2 = (DT)__builtin_amdgcn_update_dpp((int)best, (int)best, ctrl, 0xf, 0xf, false);
+        const uint32_t p2 = (uint32_t)__builtin_amdgcn_update_dpp((int)bpos, (int)bpos, ctrl, 0xf, 0xf, false);
+        if (d2 < best || (d2 == best && p2 < bpos)) best = d2, bpos = p2;
+      };
+      take(std::integral_constant<int, 0xB1>{});   // quad_perm 1,0,3,2
+      take(std::integral_constant<int, 0x4E>{});   // quad_perm 2,3,0,1
+      take(std::integral_constant<int, 0x141>{});  // row_half_mirror
+    } else {
+      for (uint32_t o = gs >> 1; o > 0; o >>= 1) {
+        const DT d2 = __shfl_xor(best, (int)o);
+        const uint32_t p2 = __shfl_xor(bpos, (int)o);
+        if (d2 < best || (d2 == best && p2 < bpos)) best = d2, bpos = p2;
+      }
     }
     if (!act) continue;
     const uint32_t ref = bpos;
-    for (uint32_t t = sub; t < lz; t += gs) sm.S[ls + t] = L;  // position -> leaf
+    if constexpr (GS > 0 && M > 0) {
+#pragma unroll
+      for (int m = 0; m < M; ++m) {  // position -> leaf
+        const uint32_t t = sub + GS * (uint32_t)m;
+        if (t < lz) sm.S[ls + t] = L;
+      }
+    } else {
+      for (uint32_t t = sub; t < lz; t += gs) sm.S[ls + t] = L;  // position -> leaf
+    }
     if (sub == 0) {
       const uint32_t rslot = sm.Pm[cur][ls + ref];
       const uint32_t tmin[3] = {t0, t1, t2};
@@ -538,7 +575,11 @@ __device__ void tile_body(WaveTile<TILE, KL, TRACK>& sm, uint64_t j, uint32_t K0
   }
   while (gs > 1 && gs / 2 >= maxleaf) gs >>= 1;
   const uint32_t span = umax32(Gt[0], umax32(Gt[1], Gt[2]));
-  if (TILE == 256 && span <= 14 && maxleaf <= 4 * gs)  // the common shape: members in registers
+  if (TILE == 256 && span <= 14 && maxleaf <= 4 * gs && gs == 8)  // the common shape
+    tile_bitboxes<TILE, KL, TRACK, uint32_t, 4, 8>(sm, cur, nl, gs, dims, tmin[0], tmin[1], tmin[2],
+                                                   tst, first_leaf, n_leaves, P, leaves, leaf_bits,
+                                                   rule);
+  else if (TILE == 256 && span <= 14 && maxleaf <= 4 * gs)  // members in registers
     tile_bitboxes<TILE, KL, TRACK, uint32_t, 4>(sm, cur, nl, gs, dims, tmin[0], tmin[1], tmin[2],
                                                 tst, first_leaf, n_leaves, P, leaves, leaf_bits,
                                                 rule);
