@@ -384,9 +384,10 @@ __device__ void tile_body(WaveTile<TILE, KL, TRACK>& sm, uint64_t j, uint32_t K0
       // ---- radix select of each internal node's median code (N << w <= TILE bins);
       // with all codes equal the median is that code and nothing is counted
       if (G > 0) {
-        uint32_t Wl = 0;
-        while ((N << (Wl + 1)) <= (uint32_t)TILE && Wl < 8) ++Wl;
-        const uint32_t npass = (G + Wl - 1) / Wl;
+        // widest digit with N << w <= TILE bins, at most 8 bits: l + w <=
+        // log2(TILE); nodes still split here (two members or more), so l < log2(TILE)
+        const uint32_t Wl = umin32(8u, LT - l);
+        const uint32_t npass = G <= Wl ? 1u : (G <= 2 * Wl ? 2u : (G + Wl - 1) / Wl);
         const uint32_t firstw = G - (npass - 1) * Wl;
         uint32_t used = 0;
         for (uint32_t pass = 0; pass < npass; ++pass) {
