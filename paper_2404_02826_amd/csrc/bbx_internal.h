@@ -311,6 +311,11 @@ __host__ __device__ inline uint32_t coord_bits(uint32_t dtype) { return dtype ==
 // Node j of depth k: walk the path bits from the root (left child floor(s/2)).
 __host__ __device__ inline void node_span(uint64_t n, uint32_t k, uint64_t j, uint64_t* start,
                                           uint64_t* size) {
+  if ((n & ((1ull << k) - 1)) == 0) {  // 2^k divides n: every node of depth k holds n / 2^k
+    *size = n >> k;
+    *start = j * (n >> k);
+    return;
+  }
   uint64_t s = n, st = 0;
   for (int b = (int)k - 1; b >= 0; --b) {
     uint64_t half = s >> 1;
