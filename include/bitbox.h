@@ -100,8 +100,9 @@ typedef enum { BBX_AOS = 0, BBX_SOA = 1 } bbx_layout;         /* [n][dims] or [d
  * block); like tile_override it never changes the stream, and all sets of a
  * batch share it.  level_blocks caps the number of blocks that each of the
  * set's partition levels with global histograms is cut into (0 = the
- * library's choice: 4,096 for a set alone, the set's share by particle count
- * in a batch; otherwise 1..4096, the smaller of this and that choice); fewer
+ * library's choice: 1,024 for a set alone, the set's share of 16,384 by
+ * particle count in a batch, at most 4,096; otherwise 1..4096, the smaller of
+ * this and that choice); fewer
  * blocks mean longer chunks per block.  It never changes the stream.
  * reduce != 0 adds the bit box reduction of Sec. 4.1 (the while loop of
  * Alg. 1) after the bit boxes: repeatedly the remaining box with the

@@ -22,7 +22,8 @@ constexpr int kHistBins = 256;            // per-node bins of the global radix s
 constexpr int kRowStride = 258;           // per-chunk row: 257 prefix counts + below count
 constexpr int kRows = 8;                  // rows of kBlock elements per streaming group
 constexpr int kGroup = kRows * kBlock;    // elements per streaming group
-constexpr uint64_t kLevelBlocks = 4096;   // blocks per global level of a set alone
+constexpr uint64_t kLevelBlocks = 4096;   // most blocks per global level (cap of a target or share)
+constexpr uint64_t kSoloLevelBlocks = 1024;  // block target of a global level of a set alone
 constexpr uint64_t kLocalBlocks = 4096;   // levels of at least this many nodes run block-local
 constexpr uint32_t kStageChunk = 16384;   // the global scatter stages groups from this chunk size
 constexpr uint32_t kRedLdsBoxes = 4096;
@@ -399,8 +400,8 @@ __host__ __device__ inline uint32_t dp_shift(const DigitPlan& p, uint32_t i) {
 
 // Blocks of one global level of one set: nodes x chunks, each chunk a whole
 // number of streaming groups, about target_blocks blocks per level.  A set
-// alone targets kLevelBlocks; in a batch each set targets its share of that
-// (by particle count, at least 1), so that a batch of many small sets does
+// alone targets kSoloLevelBlocks; in a batch each set targets its share of
+// 4 kLevelBlocks (by particle count, at least 1), so that a batch of many small sets does
 // not launch a block per 2048 codes.  Which levels are global does not depend
 // on the target (level_kind below asks for kLocalBlocks).
 struct LevelShape {
