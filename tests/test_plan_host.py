@@ -2,8 +2,9 @@
 only, no GPU): bbx_plan_check plans a batch exactly as a compress call would
 and checks level kinds, chunk shapes, buffer capacities, fused pairs and the
 leaf stage.  Swept over set sizes from 10^3 to 2^27 and every block target a
-set can get (alone: 4096; in a batch: its share by particle count, 1..4096,
-reproduced here with the level_blocks cap)."""
+set can get (alone: 1024, or less with the level_blocks cap; in a batch: its
+share of 16384 by particle count, 1..4096, reproduced with the cap and, above
+1024, with a second set sized to give the first that share)."""
 from __future__ import annotations
 
 import numpy as np
@@ -34,6 +35,16 @@ def test_plan_single_sets(tile):
             bbx.plan_check([dict(n=n, leaf_size=r, tile=tile, dims=2, dtype=1, ref_mode=1)])
             for lb in (1, 100, 4096):  # paired global levels
                 bbx.plan_check([dict(n=n, leaf_size=r, tile=tile, level_blocks=lb, level_pairs=1)])
+
+
+def test_plan_batch_shares_above_solo_target():
+    # a set of n beside one of m particles gets round(16384 n / (n + m)) blocks
+    # per global level, capped at 4096: the shapes above a set alone's 1024
+    for n in _sizes()[::3]:
+        for share in (1025, 1500, 2048, 3000, 4095, 4096):
+            m = max(1, round(n * (16384 / share - 1)))
+            bbx.plan_check([dict(n=n, leaf_size=32), dict(n=m, leaf_size=32)])
+            bbx.plan_check([dict(n=n, leaf_size=8, want_perm=True), dict(n=m, leaf_size=300)])
 
 
 def test_plan_batches():
